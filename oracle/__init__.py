@@ -1,0 +1,23 @@
+"""CPU FP64 oracle for the Laplace-transform shifted-system path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+link anything here: only the test suite, the smoke check and the benchmark's
+CPU-baseline leg use it.  It shares no code with the HIP library: it
+assembles its own finite-volume operator, computes its own Talbot contour
+and solves every shifted system with a sparse direct factorisation, which
+is the plain definition of what the flexible Krylov method approximates.
+
+Modules
+-------
+fv        cell-centred finite-volume K, lumped M, point-source weights
+contour   optimised Talbot nodes and trapezoid weights (Section 2.2)
+heads     heads at receivers by one direct solve per shift (eqn:half)
+jacobian  sensitivities to ln(kappa), ln(S) by the discrete adjoint (Section 5.2)
+"""
+from .fv import assemble, point_weights
+from .contour import talbot_nodes, talbot_full
+from .heads import heads, shifted_fields
+from .jacobian import jacobian
+
+__all__ = ["assemble", "point_weights", "talbot_nodes", "talbot_full", "heads",
+           "shifted_fields", "jacobian"]
