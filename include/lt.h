@@ -1,0 +1,202 @@
+/*
+ * lt.h -- C ABI of the Laplace-transform shifted-system solver for MI355X.
+ *
+ * The library computes heads of the groundwater equation
+ *     S dphi/dt - div(kappa grad phi) = q delta(x - x_s),  phi(0) = 0
+ * (eqn:timedomain, Section 2.1) at receiver points and measurement times by
+ * the inverse Laplace transform on the optimised Talbot contour (eq:talbot,
+ * eqn:quadrature, eqn:half, Section 2.2).  Each time needs the shifted
+ * systems (K + z_k M) x_k = b for N_z/2 contour nodes z_k (eqn:multipleshifted,
+ * Section 3); one flexible Arnoldi basis per right-hand side serves all of
+ * them (eqn:shiftedarnoldimod, Algorithm "Flexible FOM/GMRES for shifted
+ * systems").  The preconditioner (K + tau_j M)^{-1} is applied by a
+ * geometric-multigrid V-cycle refined to a relaxed tolerance.
+ *
+ * Discretisation: cell-centred finite volumes on a regular grid, face
+ * transmissibility = harmonic mean of kappa, zero-Dirichlet walls with the
+ * boundary value at h/2, lumped storage m_i = S_i V_i.  Cells are numbered
+ * with x fastest: (ix, iy, iz) -> ix + nx (iy + ny iz).
+ *
+ * Conventions for every entry point
+ *   - "device" pointers are HIP device memory on the handle's device; "host"
+ *     pointers are ordinary host memory.  All arrays are owned by the caller
+ *     and only read or written during the call.
+ *   - Complex device vectors are stored as two real planes per vector
+ *     (all real parts, then all imaginary parts): [nvec][2][N].
+ *   - All work is enqueued on the stream given to lt_setup; entry points that
+ *     return results in host memory synchronise that stream before returning.
+ *   - Return value: 0 = success, negative = error (nothing useful written),
+ *     positive = warning (outputs hold the best estimate).  No exception or
+ *     abort crosses this boundary.  lt_strerror() names every code.
+ *   - A handle is used by one thread at a time.
+ */
+#ifndef LT_H
+#define LT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LT_OK = 0,
+    LT_EINVAL = -1,       /* an argument is out of range or inconsistent      */
+    LT_EHIP = -2,         /* a HIP runtime call failed                         */
+    LT_ENOMEM = -3,       /* device or host allocation failed                  */
+    LT_EUNSUPPORTED = -4, /* valid request this build does not implement       */
+    LT_WNOTCONV = 1       /* maxit reached before every shift met the tolerance */
+};
+
+enum { LT_BC_DIRICHLET0 = 0, LT_BC_NEUMANN0 = 1 };
+enum { LT_PREC_FP64 = 0, LT_PREC_MIXED = 1 };   /* V-cycle in FP64 or FP32   */
+
+typedef struct lt_handle lt_handle;
+
+/* Regular grid: ndim in {2, 3}; n[a] cells and spacing h[a] per axis
+ * (unused axes: n = 1, h = 1).  In 2D the depth is 1, so kappa is a
+ * transmissivity and S a storativity. */
+typedef struct {
+    int ndim;
+    int n[3];
+    double h[3];
+} lt_grid;
+
+/* Boundary condition per wall, order -x, +x, -y, +y, -z, +z. */
+typedef struct {
+    int face[6];
+} lt_bc;
+
+/* n points (wells); host array xyz[3 n] of coordinates in the domain
+ * [0, n_a h_a].  Each point is spread on the surrounding cell centres with
+ * bilinear (trilinear) weights; a point within h/2 of a wall uses the
+ * nearest cell along that axis.  Sources and receivers use the same rule,
+ * so B_r (K + zM)^{-1} B_s^T is symmetric (reciprocity, Section 5.2). */
+typedef struct {
+    int n;
+    const double* xyz;
+} lt_points;
+
+/* Talbot contour with nz nodes on the full contour per time (nz even);
+ * nz/2 shifted systems are solved per time (eqn:half). */
+typedef struct {
+    int nz;
+} lt_contour;
+
+/* Solver options.  Zero-initialise and set what you need; lt_opts_default()
+ * fills the defaults.
+ *   tol        weighted per-shift tolerance: shift k of time t is converged
+ *              when |w_k qhat_k| ||r_k|| <= tol * max_{k' at t} |w_k' qhat_k'| ||b||
+ *              (weights from eqn:half; residual bound of Proposition 1).
+ *   maxit      maximum outer (Arnoldi) iterations per right-hand side.
+ *   precision  LT_PREC_FP64 or LT_PREC_MIXED (V-cycle in FP32; Arnoldi,
+ *              least squares, residuals and the contour sum stay FP64).
+ *   n_tau      number of preconditioner shifts chosen from the contour nodes
+ *              (1: the node of smallest non-negative real part; 2: that node
+ *              three times, then the node of largest real part twice, repeated
+ *              (the rule of Section 3); 3: smallest, median-|z| and largest
+ *              real part in turn).  Ignored when tau_reim is given.
+ *   tau_reim   optional host array [2 n_tau] of explicit shifts (re, im),
+ *              used cyclically.
+ *   nu1, nu2   red-black Gauss-Seidel sweeps before / after coarse correction.
+ *   inner_max  maximum V-cycles per outer iteration (iterative refinement).
+ *   relax      inner tolerance factor: the refinement stops when
+ *              ||v - (K + tau M) u|| <= relax * tol / (worst weighted residual).
+ *   true_residual  1: compute the FP64 true residual of every (rhs, shift)
+ *              at exit (reported in lt_stats). */
+typedef struct {
+    double tol;
+    int maxit;
+    int precision;
+    int n_tau;
+    const double* tau_reim;
+    int nu1, nu2;
+    int inner_max;
+    double relax;
+    int true_residual;
+} lt_opts;
+
+/* Statistics of the last call.  Pointer members are optional host arrays the
+ * caller provides (NULL to skip). */
+typedef struct {
+    int n_rhs;            /* right-hand sides solved                          */
+    int n_shifts;         /* solved shifts per right-hand side                */
+    int iters_max;        /* outer iterations of the slowest right-hand side  */
+    int vcycles;          /* V-cycles applied, summed over right-hand sides   */
+    int levels;           /* multigrid levels                                  */
+    double true_relres_max;      /* max over (rhs, shift) of weighted true residual / tol-scale */
+    double seconds;              /* wall time of the call                    */
+    int* iters_per_rhs;          /* [n_rhs] or NULL                          */
+    double* true_relres;         /* [n_rhs][n_shifts] ||b - (K+zM)x|| / ||b|| or NULL */
+} lt_stats;
+
+void lt_opts_default(lt_opts* o);
+
+/* Build the operator for conductivity kappa and storage S (device arrays of
+ * grid cells, float64, x fastest; both strictly positive) and the multigrid
+ * hierarchy.  hip_stream is a hipStream_t (NULL = the default stream); all
+ * later work of the handle goes to it.  The handle copies what it needs, so
+ * kappa and S may be freed after the call.  Section 2.1 (semi-discrete
+ * system); the finite-volume form is stated at the top of this file. */
+int lt_setup(const lt_grid* grid, const double* kappa, const double* S, const lt_bc* bc,
+             void* hip_stream, lt_handle** out);
+
+/* Heads phi[s][r][t] at receivers r and times t (host array times[ntimes],
+ * strictly positive) for unit-location sources s pumping at constant rate q
+ * from t = 0 (qhat(z) = q / z): the contour sum of eqn:half over the
+ * solutions of eqn:multipleshifted, computed with the flexible shifted
+ * Krylov method of Section 3.  phi_out: device float64 [ns][nr][ntimes].
+ * Returns LT_WNOTCONV if some shift missed the tolerance after maxit
+ * outer iterations (phi_out then holds the best estimate). */
+int lt_solve(lt_handle* h, const lt_points* sources, double q, const double* times, int ntimes,
+             const lt_contour* contour, const lt_points* receivers, const lt_opts* opts,
+             double* phi_out, lt_stats* stats);
+
+/* Sensitivities of phi[s][r][t] to ln kappa and ln S of every cell
+ * (Section 5.2, adjoint state through the Laplace transform), for sources
+ * pumping at rate q: forward fields for every source and adjoint fields for
+ * every receiver (complex symmetric operator: no conjugation), contracted
+ * cell by cell and summed over the contour.  dlnK, dlnS: device float64
+ * [ns][nr][ntimes][N]; either may be NULL. */
+int lt_adjoint(lt_handle* h, const lt_points* sources, double q, const lt_points* receivers,
+               const double* times, int ntimes, const lt_contour* contour, const lt_opts* opts,
+               double* dlnK, double* dlnS, lt_stats* stats);
+
+/* Talbot nodes and weights for one time (host arrays of nz/2 complex values
+ * as (re, im) pairs, nodes with Im z > 0 in increasing theta):
+ * phi(t) ~ 2 Re sum_k w_k F(z_k).  eq:talbot, eqn:quadrature, eqn:half. */
+int lt_talbot(int nz, double t, double* z_reim, double* w_reim);
+
+/* y = (K + tau M) x on multigrid level `level` (0 = the fine grid) for nvec
+ * complex device vectors [nvec][2][N_level], float64.  Test and diagnostic
+ * entry point for the stencil (Section 2.1 operator). */
+int lt_apply_operator(lt_handle* h, int level, double tau_re, double tau_im,
+                      const double* x, double* y, int nvec);
+
+/* x = one V-cycle for (K + tau M) x = b from x = 0 on the fine grid, nvec
+ * complex device vectors [nvec][2][N] float64; precision as in lt_opts
+ * (FP32 cycles convert on entry and exit).  Test entry point for the
+ * preconditioner of Section 3 (here a multigrid approximation of the
+ * shift-and-invert solve). */
+int lt_vcycle(lt_handle* h, double tau_re, double tau_im, int precision, int nu1, int nu2,
+              const double* b, double* x, int nvec);
+
+/* Number of cells per axis of multigrid level `level` (n_out[3]); returns
+ * the number of levels, or a negative error code. */
+int lt_level_shape(lt_handle* h, int level, int* n_out);
+
+/* Name of a return code. */
+const char* lt_strerror(int code);
+
+/* Text describing the last error raised on the calling thread ("" if none). */
+const char* lt_last_error(void);
+
+/* Release the handle and everything it owns (NULL is accepted). */
+void lt_destroy(lt_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LT_H */

@@ -1,0 +1,279 @@
+"""Thin ctypes binding of the C ABI declared in include/lt.h.
+
+Argument marshalling only: device arrays are torch tensors on the GPU (their
+data pointers are passed through), host arrays are numpy arrays, and every
+step of the computation runs inside the HIP library.  Importing this module
+loads the built library and fails loudly if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblt.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"HIP library not built: {LIB_PATH} is missing (run paper_1409_2556_amd/build.py)")
+_lib = C.CDLL(LIB_PATH)
+
+LT_OK, LT_EINVAL, LT_EHIP, LT_ENOMEM, LT_EUNSUPPORTED, LT_WNOTCONV = 0, -1, -2, -3, -4, 1
+LT_BC_DIRICHLET0, LT_BC_NEUMANN0 = 0, 1
+LT_PREC_FP64, LT_PREC_MIXED = 0, 1
+
+
+class lt_grid(C.Structure):
+    _fields_ = [("ndim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double * 3)]
+
+
+class lt_bc(C.Structure):
+    _fields_ = [("face", C.c_int * 6)]
+
+
+class lt_points(C.Structure):
+    _fields_ = [("n", C.c_int), ("xyz", C.POINTER(C.c_double))]
+
+
+class lt_contour(C.Structure):
+    _fields_ = [("nz", C.c_int)]
+
+
+class lt_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("precision", C.c_int), ("n_tau", C.c_int),
+                ("tau_reim", C.POINTER(C.c_double)), ("nu1", C.c_int), ("nu2", C.c_int),
+                ("inner_max", C.c_int), ("relax", C.c_double), ("true_residual", C.c_int)]
+
+
+class lt_stats(C.Structure):
+    _fields_ = [("n_rhs", C.c_int), ("n_shifts", C.c_int), ("iters_max", C.c_int), ("vcycles", C.c_int),
+                ("levels", C.c_int), ("true_relres_max", C.c_double), ("seconds", C.c_double),
+                ("iters_per_rhs", C.POINTER(C.c_int)), ("true_relres", C.POINTER(C.c_double))]
+
+
+_vp = C.c_void_p
+_dp = C.POINTER(C.c_double)
+_h = C.c_void_p
+
+_lib.lt_opts_default.argtypes = [C.POINTER(lt_opts)]
+_lib.lt_opts_default.restype = None
+_lib.lt_setup.argtypes = [C.POINTER(lt_grid), _vp, _vp, C.POINTER(lt_bc), _vp, C.POINTER(_h)]
+_lib.lt_setup.restype = C.c_int
+_lib.lt_solve.argtypes = [_h, C.POINTER(lt_points), C.c_double, _dp, C.c_int, C.POINTER(lt_contour),
+                          C.POINTER(lt_points), C.POINTER(lt_opts), _vp, C.POINTER(lt_stats)]
+_lib.lt_solve.restype = C.c_int
+_lib.lt_adjoint.argtypes = [_h, C.POINTER(lt_points), C.c_double, C.POINTER(lt_points), _dp, C.c_int,
+                            C.POINTER(lt_contour), C.POINTER(lt_opts), _vp, _vp, C.POINTER(lt_stats)]
+_lib.lt_adjoint.restype = C.c_int
+_lib.lt_talbot.argtypes = [C.c_int, C.c_double, _dp, _dp]
+_lib.lt_talbot.restype = C.c_int
+_lib.lt_apply_operator.argtypes = [_h, C.c_int, C.c_double, C.c_double, _vp, _vp, C.c_int]
+_lib.lt_apply_operator.restype = C.c_int
+_lib.lt_vcycle.argtypes = [_h, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int]
+_lib.lt_vcycle.restype = C.c_int
+_lib.lt_level_shape.argtypes = [_h, C.c_int, C.POINTER(C.c_int)]
+_lib.lt_level_shape.restype = C.c_int
+_lib.lt_strerror.argtypes = [C.c_int]
+_lib.lt_strerror.restype = C.c_char_p
+_lib.lt_last_error.argtypes = []
+_lib.lt_last_error.restype = C.c_char_p
+_lib.lt_destroy.argtypes = [_h]
+_lib.lt_destroy.restype = None
+
+
+class LTError(RuntimeError):
+    def __init__(self, code):
+        self.code = code
+        super().__init__(f"{lt_strerror(code)} ({_lib.lt_last_error().decode()})")
+
+
+def _check(rc):
+    if rc < 0:
+        raise LTError(rc)
+    return rc
+
+
+def lt_strerror(code: int) -> str:
+    return _lib.lt_strerror(code).decode()
+
+
+def lt_last_error() -> str:
+    return _lib.lt_last_error().decode()
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _points(xyz):
+    a = np.ascontiguousarray(np.atleast_2d(np.asarray(xyz, dtype=np.float64)))
+    if a.shape[1] != 3:
+        raise ValueError("points must have shape [n, 3]")
+    return lt_points(a.shape[0], a.ctypes.data_as(_dp)), a
+
+
+def lt_opts_default() -> lt_opts:
+    o = lt_opts()
+    _lib.lt_opts_default(C.byref(o))
+    return o
+
+
+def make_opts(**kw) -> lt_opts:
+    """lt_opts with defaults overridden by keyword (tau may be a list of complex)."""
+    o = lt_opts_default()
+    tau = kw.pop("tau", None)
+    for k, v in kw.items():
+        setattr(o, k, v)
+    if tau is not None:
+        arr = np.ascontiguousarray(np.array([[complex(t).real, complex(t).imag] for t in tau]).ravel())
+        o.tau_reim = arr.ctypes.data_as(_dp)
+        o.n_tau = len(tau)
+        o._keep = arr
+    return o
+
+
+class Handle:
+    """Owns an lt_handle; lt_destroy on close or garbage collection."""
+
+    def __init__(self, ptr, grid, stream):
+        self.ptr = ptr
+        self.grid = grid
+        self.stream = stream
+
+    @property
+    def N(self):
+        return self.grid.n[0] * self.grid.n[1] * self.grid.n[2]
+
+    def close(self):
+        if self.ptr:
+            _lib.lt_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lt_setup(ndim, n, h, kappa, S, bc=(0, 0, 0, 0, 0, 0), stream=None) -> Handle:
+    g = lt_grid(int(ndim), (C.c_int * 3)(*[int(a) for a in n]), (C.c_double * 3)(*[float(a) for a in h]))
+    b = lt_bc((C.c_int * 6)(*[int(a) for a in bc]))
+    out = _h()
+    sp = _stream_ptr(stream)
+    _check(_lib.lt_setup(C.byref(g), _dev_f64(kappa, "kappa"), _dev_f64(S, "S"), C.byref(b), sp, C.byref(out)))
+    return Handle(out, g, sp)
+
+
+def _stats(nrhs, nshift):
+    st = lt_stats()
+    it = np.zeros(nrhs, dtype=np.int32)
+    tr = np.zeros(nrhs * nshift, dtype=np.float64)
+    st.iters_per_rhs = it.ctypes.data_as(C.POINTER(C.c_int))
+    st.true_relres = tr.ctypes.data_as(_dp)
+    return st, it, tr
+
+
+def _stats_dict(st, it, tr, rc, nrhs, nshift):
+    return {"rc": rc, "n_rhs": st.n_rhs, "n_shifts": st.n_shifts, "iters_max": st.iters_max,
+            "vcycles": st.vcycles, "levels": st.levels, "true_relres_max": st.true_relres_max,
+            "seconds": st.seconds, "iters_per_rhs": it.copy(), "true_relres": tr.reshape(nrhs, nshift).copy()}
+
+
+def lt_solve(handle: Handle, sources, q, times, nz, receivers, opts: lt_opts | None = None, phi_out=None):
+    """Heads [ns, nr, nt] as a float64 CUDA tensor, plus a stats dict."""
+    import torch
+    sp, sa = _points(sources)
+    rp, ra = _points(receivers)
+    t = np.ascontiguousarray(np.asarray(times, dtype=np.float64).ravel())
+    ns, nr, nt = sa.shape[0], ra.shape[0], t.size
+    if phi_out is None:
+        phi_out = torch.empty((ns, nr, nt), dtype=torch.float64, device="cuda")
+    con = lt_contour(int(nz))
+    o = opts if opts is not None else lt_opts_default()
+    st, it, tr = _stats(ns, nt * (int(nz) // 2))
+    rc = _check(_lib.lt_solve(handle.ptr, C.byref(sp), float(q), t.ctypes.data_as(_dp), nt, C.byref(con),
+                              C.byref(rp), C.byref(o), _dev_f64(phi_out, "phi_out"), C.byref(st)))
+    return phi_out, _stats_dict(st, it, tr, rc, ns, nt * (int(nz) // 2))
+
+
+def lt_adjoint(handle: Handle, sources, q, receivers, times, nz, opts: lt_opts | None = None,
+               dlnK=None, dlnS=None):
+    """Sensitivities [ns, nr, nt, N] to ln kappa and ln S (float64 CUDA tensors) and stats."""
+    import torch
+    sp, sa = _points(sources)
+    rp, ra = _points(receivers)
+    t = np.ascontiguousarray(np.asarray(times, dtype=np.float64).ravel())
+    ns, nr, nt = sa.shape[0], ra.shape[0], t.size
+    shape = (ns, nr, nt, handle.N)
+    if dlnK is None:
+        dlnK = torch.empty(shape, dtype=torch.float64, device="cuda")
+    if dlnS is None:
+        dlnS = torch.empty(shape, dtype=torch.float64, device="cuda")
+    con = lt_contour(int(nz))
+    o = opts if opts is not None else lt_opts_default()
+    st, it, tr = _stats(ns + nr, nt * (int(nz) // 2))
+    rc = _check(_lib.lt_adjoint(handle.ptr, C.byref(sp), float(q), C.byref(rp), t.ctypes.data_as(_dp), nt,
+                                C.byref(con), C.byref(o), _dev_f64(dlnK, "dlnK"), _dev_f64(dlnS, "dlnS"),
+                                C.byref(st)))
+    return dlnK, dlnS, _stats_dict(st, it, tr, rc, ns + nr, nt * (int(nz) // 2))
+
+
+def lt_talbot(nz, t):
+    """Upper-half Talbot nodes and weights (complex numpy arrays) computed by the library."""
+    z = np.zeros(nz, dtype=np.float64)
+    w = np.zeros(nz, dtype=np.float64)
+    _check(_lib.lt_talbot(int(nz), float(t), z.ctypes.data_as(_dp), w.ctypes.data_as(_dp)))
+    return z[0::2] + 1j * z[1::2], w[0::2] + 1j * w[1::2]
+
+
+def lt_apply_operator(handle: Handle, level, tau, x, y, nvec):
+    tau = complex(tau)
+    return _check(_lib.lt_apply_operator(handle.ptr, int(level), tau.real, tau.imag, _dev_f64(x, "x"),
+                                         _dev_f64(y, "y"), int(nvec)))
+
+
+def lt_vcycle(handle: Handle, tau, precision, nu1, nu2, b, x, nvec):
+    tau = complex(tau)
+    return _check(_lib.lt_vcycle(handle.ptr, tau.real, tau.imag, int(precision), int(nu1), int(nu2),
+                                 _dev_f64(b, "b"), _dev_f64(x, "x"), int(nvec)))
+
+
+def lt_level_shape(handle: Handle, level):
+    n = (C.c_int * 3)()
+    nl = _check(_lib.lt_level_shape(handle.ptr, int(level), n))
+    return nl, tuple(n)
+
+
+def lt_destroy(handle: Handle):
+    handle.close()
+
+
+def exported_symbols():
+    """Names the library exports among those of include/lt.h (no GPU needed)."""
+    return [name for name in _ABI_NAMES if hasattr(_lib, name)]
+
+
+_ABI_NAMES = ["lt_opts_default", "lt_setup", "lt_solve", "lt_adjoint", "lt_talbot", "lt_apply_operator",
+              "lt_vcycle", "lt_level_shape", "lt_strerror", "lt_last_error", "lt_destroy"]
+
+
+# ---------------------------------------------------------------- complex SoA helpers
+def to_planes(zc):
+    """complex torch tensor [..., N] -> float64 planes [..., 2, N] (contiguous)."""
+    import torch
+    return torch.stack([zc.real, zc.imag], dim=-2).to(torch.float64).contiguous()
+
+
+def from_planes(p):
+    return p[..., 0, :] + 1j * p[..., 1, :]

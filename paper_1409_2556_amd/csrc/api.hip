@@ -1,0 +1,511 @@
+// C ABI entry points and the batched flexible shifted Krylov driver.
+//
+// Method (Section 3): for each right-hand side b one flexible Arnoldi basis
+// V_{m+1} and preconditioned vectors U_m are built with preconditioner shifts
+// tau_j, and every contour shift z_k solves the small least-squares problem
+// min || beta e_1 - Hbar(z_k; T_m) y ||, Hbar(z; T) = [I; 0] + Hbar (z I - T)
+// (eqn:shiftedarnoldimod), x_k = U_m y_k.  The relation needs
+// (K + tau_j M) u_j = v_j; the multigrid preconditioner is therefore refined
+// (u_j += V-cycle(rho), rho = v_j - (K + tau_j M) u_j, in FP64) until
+// ||rho|| <= relax * tol / (largest weighted shift residual so far): the
+// residual gap this leaves is bounded by sum_j |y_j| ||rho_j|| and the
+// relaxation keeps it below the tolerance (inexact Krylov).  The FP64 true
+// residual of every (rhs, shift) is computed at exit.
+#include <chrono>
+#include <cstring>
+#include <mutex>
+
+#include "krylov.h"
+#include "lt_internal.h"
+
+namespace lt {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& s) { g_last_error = s; }
+
+}  // namespace lt
+
+using namespace lt;
+
+lt_handle::~lt_handle() {
+    for (Level& L : levels) {
+        L.c64.release();
+        L.c32.release();
+    }
+    for (CoarseInverse& c : coarse_cache) {
+        c.inv64.release();
+        c.inv32.release();
+    }
+    for (auto& kv : ws) kv.second.release();
+    if (pinned) (void)hipHostFree(pinned);
+}
+
+namespace {
+
+struct DevPoints {
+    int n = 0;
+    int* off = nullptr;
+    int* cell = nullptr;
+    double* wt = nullptr;
+};
+
+int upload_points(lt_handle* h, const PointsCSR& c, const char* tag, DevPoints* d) {
+    int rc = 0;
+    d->n = (int)c.off.size() - 1;
+    std::string t(tag);
+    d->off = wsp<int>(h, (t + "_off").c_str(), c.off.size(), &rc);
+    if (!d->off) return rc;
+    size_t nn = std::max<size_t>(c.cell.size(), 1);
+    d->cell = wsp<int>(h, (t + "_cell").c_str(), nn, &rc);
+    if (!d->cell) return rc;
+    d->wt = wsp<double>(h, (t + "_wt").c_str(), nn, &rc);
+    if (!d->wt) return rc;
+    LT_HIP(hipMemcpyAsync(d->off, c.off.data(), c.off.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+    if (!c.cell.empty()) {
+        LT_HIP(hipMemcpyAsync(d->cell, c.cell.data(), c.cell.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+        LT_HIP(hipMemcpyAsync(d->wt, c.wt.data(), c.wt.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    }
+    return 0;
+}
+
+int validate_opts(const lt_opts* o) {
+    if (!o) return 0;
+    if (!(o->tol > 0.0) || o->maxit < 1 || o->maxit > 2000 || o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 ||
+        o->inner_max < 1 || !(o->relax > 0.0) ||
+        (o->precision != LT_PREC_FP64 && o->precision != LT_PREC_MIXED)) {
+        set_last_error("invalid lt_opts");
+        return LT_EINVAL;
+    }
+    return 0;
+}
+
+// Everything the Krylov loop leaves on the device for the epilogues.
+struct KrylovOut {
+    int R = 0, Ks = 0, jmax = 0;
+    double* U = nullptr;      // [R][jmax][2][N]
+    size_t ustride = 0;
+    double* Y = nullptr;      // [R][jmax][Ks] complex
+    double* G = nullptr;      // [R][jmax][np] complex (receiver gathers of u_j)
+    int* mcols = nullptr;     // [R]
+    double* beta = nullptr;   // [R]
+    double* b = nullptr;      // [R][2][N]
+    double* zs = nullptr;     // [Ks] complex
+    double* omega = nullptr;  // [Ks]
+    double* wq = nullptr;     // [Ks] complex
+    int iters_max = 0, vcycles = 0;
+    bool converged = true;
+};
+
+// Batched flexible shifted GMRES for R right-hand sides b (device [R][2][N], already
+// filled).  Gathers B_rec u_j for `rec` if given.
+int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const DevPoints* rec, KrylovOut* out) {
+    hipStream_t st = h->stream;
+    const int N = h->N;
+    const int jmax = o.maxit;
+    const int Ks = plan.ntimes * plan.nk;
+    const size_t N2 = 2 * (size_t)N;
+    int rc = 0;
+    out->R = R;
+    out->Ks = Ks;
+    out->jmax = jmax;
+    const size_t qstride = (size_t)(jmax + 1) * N2, ustride = (size_t)jmax * N2;
+    double* Q = wsp<double>(h, "Q", (size_t)R * qstride, &rc);
+    if (!Q) return rc;
+    double* U = wsp<double>(h, "U", (size_t)R * ustride, &rc);
+    if (!U) return rc;
+    double* rho = wsp<double>(h, "rho", R * N2, &rc);
+    if (!rho) return rc;
+    const bool mixed = o.precision == LT_PREC_MIXED;
+    float* lo32 = nullptr;
+    float* e32 = nullptr;
+    double* e64 = nullptr;
+    if (mixed) {
+        lo32 = wsp<float>(h, "lo32", R * N2, &rc);
+        if (!lo32) return rc;
+        e32 = wsp<float>(h, "e32", R * N2, &rc);
+        if (!e32) return rc;
+    } else {
+        e64 = wsp<double>(h, "e64", R * N2, &rc);
+        if (!e64) return rc;
+    }
+    const int hstride = 2 * (jmax + 2);
+    const size_t hrstride = (size_t)jmax * hstride;
+    double* H = wsp<double>(h, "H", (size_t)R * hrstride, &rc);
+    if (!H) return rc;
+    const int cstride = 2 * (jmax + 2);
+    double* c1 = wsp<double>(h, "c1", (size_t)R * cstride, &rc);
+    double* c2 = wsp<double>(h, "c2", (size_t)R * cstride, &rc);
+    if (!c1 || !c2) return rc;
+    const int nb = reduce_blocks(N, R);
+    const int pstride = 2 * (jmax + 2);
+    double* part = wsp<double>(h, "part", (size_t)R * nb * pstride, &rc);
+    if (!part) return rc;
+    double* small = wsp<double>(h, "small", 4 * (size_t)R, &rc);
+    if (!small) return rc;
+    double* scale = small;
+    double* beta = small + R;
+    double* worst = small + 2 * R;
+    int* ints = wsp<int>(h, "ints", 4 * (size_t)R + 4, &rc);
+    if (!ints) return rc;
+    int* active = ints;
+    int* inner_active = ints + R;
+    int* mcols = ints + 2 * R;
+    int* vcyc = ints + 3 * R;
+    int* count = ints + 4 * R;
+    const size_t P = (size_t)R * Ks;
+    LSState ls;
+    ls.Rm = wsp<double>(h, "Rm", 2 * P * ((size_t)jmax * (jmax + 1) / 2), &rc);
+    ls.cs = wsp<double>(h, "cs", P * jmax, &rc);
+    ls.sn = wsp<double>(h, "sn", 2 * P * jmax, &rc);
+    ls.g = wsp<double>(h, "g", 2 * P * (jmax + 1), &rc);
+    ls.res = wsp<double>(h, "res", P, &rc);
+    int* conv = wsp<int>(h, "conv", P, &rc);
+    double* Y = wsp<double>(h, "Y", (size_t)R * jmax * 2 * Ks, &rc);
+    double* tabs = wsp<double>(h, "tabs", 5 * (size_t)Ks, &rc);
+    if (!ls.Rm || !ls.cs || !ls.sn || !ls.g || !ls.res || !conv || !Y || !tabs) return rc;
+    double* G = nullptr;
+    int np = rec ? rec->n : 0;
+    if (np > 0) {
+        G = wsp<double>(h, "G", (size_t)R * jmax * 2 * np, &rc);
+        if (!G) return rc;
+    }
+    double* zs = tabs;
+    double* wq = tabs + 2 * Ks;
+    double* omega = tabs + 4 * Ks;
+    {
+        std::vector<double> t(5 * (size_t)Ks);
+        for (int k = 0; k < Ks; ++k) {
+            t[2 * k] = plan.z[k].real();
+            t[2 * k + 1] = plan.z[k].imag();
+            t[2 * Ks + 2 * k] = plan.wq[k].real();
+            t[2 * Ks + 2 * k + 1] = plan.wq[k].imag();
+            t[4 * Ks + k] = plan.omega[k];
+        }
+        LT_HIP(hipMemcpyAsync(tabs, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    if (!h->pinned) LT_HIP(hipHostMalloc(&h->pinned, 4096, hipHostMallocDefault));
+    int* hflag = static_cast<int*>(h->pinned);
+    int* hact = hflag + 16;
+    if (R > 1000) {
+        set_last_error("at most 1000 right-hand sides per batch");
+        return LT_EINVAL;
+    }
+    double* b = out->b;
+    // beta, v_1 = b / beta, masks
+    LT_TRY(launch_norms(st, N, R, N2, b, part, beta, nullptr));
+    LT_TRY(launch_scale_into(st, N, R, N2, qstride, b, beta, Q));
+    {
+        std::vector<double> init(4 * (size_t)R, 0.0);
+        for (int r = 0; r < R; ++r) init[2 * R + r] = 1.0;  // worst
+        // scale, beta are device-computed; upload only worst (keep beta)
+        LT_HIP(hipMemcpyAsync(worst, init.data() + 2 * R, R * sizeof(double), hipMemcpyHostToDevice, st));
+        std::vector<double> hb(R);
+        LT_HIP(hipMemcpyAsync(hb.data(), beta, R * sizeof(double), hipMemcpyDeviceToHost, st));
+        LT_HIP(hipStreamSynchronize(st));
+        std::vector<int> ii(4 * (size_t)R + 4, 0);
+        for (int r = 0; r < R; ++r) ii[r] = hb[r] > 0.0 ? 1 : 0;
+        LT_HIP(hipMemcpyAsync(ints, ii.data(), ii.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    }
+    const LevelView<double> L0 = h->levels[0].v64();
+    const double* m = L0.m;
+    int n_active = R;
+    int j = 0;
+    out->converged = false;
+    for (j = 0; j < jmax; ++j) {
+        cdouble tau = plan.tau_sched[j % plan.tau_sched.size()];
+        // inner refinement of u_j ~ (K + tau M)^{-1} v_j
+        LT_HIP(hipMemcpyAsync(inner_active, active, R * sizeof(int), hipMemcpyDeviceToDevice, st));
+        double* uj = U + (size_t)j * N2;
+        const double* vj = Q + (size_t)j * N2;
+        if (mixed)
+            LT_TRY(launch_inner_init<float>(st, N, R, qstride, vj, uj, ustride, rho, lo32, active));
+        else
+            LT_TRY(launch_inner_init<double>(st, N, R, qstride, vj, uj, ustride, rho, (double*)nullptr, active));
+        for (int step = 0; step < o.inner_max; ++step) {
+            if (mixed) {
+                LT_TRY(mg_vcycle<float>(h, tau, o.nu1, o.nu2, R, inner_active, e32, lo32));
+                LT_TRY(launch_inner_update<float>(st, L0, tau, R, e32, uj, ustride, rho, lo32, part, inner_active));
+            } else {
+                LT_TRY(mg_vcycle<double>(h, tau, o.nu1, o.nu2, R, inner_active, e64, rho));
+                LT_TRY(launch_inner_update<double>(st, L0, tau, R, e64, uj, ustride, rho, (double*)nullptr, part,
+                                                   inner_active));
+            }
+            LT_TRY(launch_inner_finalize(st, N, R, part, active, worst, o.relax * o.tol, o.tol, step, o.inner_max,
+                                         inner_active, vcyc, count));
+            LT_HIP(hipMemcpyAsync(hflag, count, sizeof(int), hipMemcpyDeviceToHost, st));
+            LT_HIP(hipStreamSynchronize(st));
+            if (*hflag == 0) break;
+        }
+        // Arnoldi: v_{j+1} from M u_j by classical Gram-Schmidt with reorthogonalisation
+        LT_TRY(launch_cgs2(st, N, R, j, m, U, ustride, Q, qstride, H, hstride, hrstride, part, pstride, c1, c2,
+                           cstride, scale, active));
+        if (np > 0) LT_TRY(launch_gather(st, R, N, np, rec->off, rec->cell, rec->wt, U, ustride, j, G, jmax, active));
+        LT_TRY(launch_ls_update(st, R, Ks, j, tau, zs, omega, o.tol, H, hstride, hrstride, beta, ls, active, mcols,
+                                worst, conv));
+        LT_HIP(hipMemcpyAsync(hact, active, R * sizeof(int), hipMemcpyDeviceToHost, st));
+        LT_HIP(hipStreamSynchronize(st));
+        n_active = 0;
+        for (int r = 0; r < R; ++r) n_active += hact[r];
+        if (n_active == 0) {
+            out->converged = true;
+            break;
+        }
+    }
+    LT_TRY(launch_backsolve(st, R, Ks, mcols, ls, Y, jmax));
+    std::vector<int> hm(R), hv(R);
+    LT_HIP(hipMemcpyAsync(hm.data(), mcols, R * sizeof(int), hipMemcpyDeviceToHost, st));
+    LT_HIP(hipMemcpyAsync(hv.data(), vcyc, R * sizeof(int), hipMemcpyDeviceToHost, st));
+    LT_HIP(hipStreamSynchronize(st));
+    out->iters_max = 0;
+    out->vcycles = 0;
+    for (int r = 0; r < R; ++r) {
+        out->iters_max = std::max(out->iters_max, hm[r]);
+        out->vcycles += hv[r];
+    }
+    out->U = U;
+    out->ustride = ustride;
+    out->Y = Y;
+    out->G = G;
+    out->mcols = mcols;
+    out->beta = beta;
+    out->zs = zs;
+    out->omega = omega;
+    out->wq = wq;
+    return 0;
+}
+
+int true_residuals(lt_handle* h, const KrylovOut& k, const Plan& plan, lt_stats* stats) {
+    hipStream_t st = h->stream;
+    const int N = h->N, R = k.R, Ks = k.Ks;
+    int rc = 0;
+    const int nc = std::min(Ks, 16);
+    double* X = wsp<double>(h, "X", (size_t)R * nc * 2 * N, &rc);
+    if (!X) return rc;
+    const int nb = reduce_blocks(N, R);
+    double* part = wsp<double>(h, "tpart", (size_t)R * nc * nb, &rc);
+    double* tr = wsp<double>(h, "trel", (size_t)R * Ks, &rc);
+    if (!part || !tr) return rc;
+    for (int k0 = 0; k0 < Ks; k0 += nc) {
+        int c = std::min(nc, Ks - k0);
+        LT_TRY(launch_form_x(st, N, R, c, k0, Ks, k.U, k.ustride, k.Y, k.jmax, k.mcols, X));
+        LT_TRY(launch_true_residual(st, h->levels[0].v64(), R, c, k0, Ks, k.zs, X, k.b, k.beta, part, tr));
+    }
+    std::vector<double> ht((size_t)R * Ks);
+    LT_HIP(hipMemcpyAsync(ht.data(), tr, ht.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    LT_HIP(hipStreamSynchronize(st));
+    double mx = 0.0;
+    for (int r = 0; r < R; ++r)
+        for (int kk = 0; kk < Ks; ++kk) mx = std::max(mx, plan.omega[kk] * ht[(size_t)r * Ks + kk]);
+    if (stats) {
+        stats->true_relres_max = mx;
+        if (stats->true_relres) std::memcpy(stats->true_relres, ht.data(), ht.size() * sizeof(double));
+    }
+    return 0;
+}
+
+void fill_stats(lt_stats* s, const KrylovOut& k, int nlev, double secs) {
+    if (!s) return;
+    s->n_rhs = k.R;
+    s->n_shifts = k.Ks;
+    s->iters_max = k.iters_max;
+    s->vcycles = k.vcycles;
+    s->levels = nlev;
+    s->seconds = secs;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lt_opts_default(lt_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-10;
+    o->maxit = 200;
+    o->precision = LT_PREC_FP64;
+    o->n_tau = 1;
+    o->tau_reim = nullptr;
+    o->nu1 = 2;
+    o->nu2 = 2;
+    o->inner_max = 30;
+    o->relax = 1.0;
+    o->true_residual = 1;
+}
+
+const char* lt_strerror(int code) {
+    switch (code) {
+        case LT_OK: return "LT_OK";
+        case LT_EINVAL: return "LT_EINVAL: invalid argument";
+        case LT_EHIP: return "LT_EHIP: HIP runtime error";
+        case LT_ENOMEM: return "LT_ENOMEM: out of memory";
+        case LT_EUNSUPPORTED: return "LT_EUNSUPPORTED: not supported";
+        case LT_WNOTCONV: return "LT_WNOTCONV: not converged within maxit";
+        default: return "unknown lt status";
+    }
+}
+
+const char* lt_last_error(void) { return lt::g_last_error.c_str(); }
+
+int lt_setup(const lt_grid* grid, const double* kappa, const double* S, const lt_bc* bc, void* hip_stream,
+             lt_handle** out) {
+    if (!grid || !kappa || !S || !out) {
+        set_last_error("lt_setup: NULL argument");
+        return LT_EINVAL;
+    }
+    *out = nullptr;
+    if (grid->ndim < 2 || grid->ndim > 3) {
+        set_last_error("lt_setup: ndim must be 2 or 3");
+        return LT_EINVAL;
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (grid->n[a] < 1 || !(grid->h[a] > 0.0) || (a >= grid->ndim && grid->n[a] != 1)) {
+            set_last_error("lt_setup: bad grid shape or spacing");
+            return LT_EINVAL;
+        }
+    }
+    long long Nll = (long long)grid->n[0] * grid->n[1] * grid->n[2];
+    if (Nll < 2 || Nll > (1LL << 30)) {
+        set_last_error("lt_setup: grid too small or too large");
+        return LT_EINVAL;
+    }
+    lt_handle* h = new (std::nothrow) lt_handle();
+    if (!h) return LT_ENOMEM;
+    h->grid = *grid;
+    if (bc)
+        h->bc = *bc;
+    else
+        std::memset(&h->bc, 0, sizeof(h->bc));
+    for (int f = 0; f < 6; ++f) {
+        if (h->bc.face[f] != LT_BC_DIRICHLET0 && h->bc.face[f] != LT_BC_NEUMANN0) {
+            delete h;
+            set_last_error("lt_setup: unknown boundary condition");
+            return LT_EINVAL;
+        }
+    }
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    h->N = (int)Nll;
+    int rc = mg_build(h, kappa, S);
+    if (rc < 0) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return LT_OK;
+}
+
+void lt_destroy(lt_handle* h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+}
+
+int lt_level_shape(lt_handle* h, int level, int* n_out) {
+    if (!h) return LT_EINVAL;
+    int nl = (int)h->levels.size();
+    if (level < 0 || level >= nl) return LT_EINVAL;
+    if (n_out)
+        for (int a = 0; a < 3; ++a) n_out[a] = h->levels[level].n[a];
+    return nl;
+}
+
+int lt_talbot(int nz, double t, double* z_reim, double* w_reim) {
+    if (!z_reim || !w_reim) return LT_EINVAL;
+    std::vector<cdouble> z(nz / 2 > 0 ? nz / 2 : 1), w(z.size());
+    int rc = talbot(nz, t, z.data(), w.data());
+    if (rc < 0) return rc;
+    for (int k = 0; k < nz / 2; ++k) {
+        z_reim[2 * k] = z[k].real();
+        z_reim[2 * k + 1] = z[k].imag();
+        w_reim[2 * k] = w[k].real();
+        w_reim[2 * k + 1] = w[k].imag();
+    }
+    return 0;
+}
+
+int lt_apply_operator(lt_handle* h, int level, double tau_re, double tau_im, const double* x, double* y, int nvec) {
+    if (!h || !x || !y || nvec < 1 || level < 0 || level >= (int)h->levels.size()) return LT_EINVAL;
+    return apply_operator<double>(h, level, cdouble(tau_re, tau_im), x, y, nvec, nullptr);
+}
+
+int lt_vcycle(lt_handle* h, double tau_re, double tau_im, int precision, int nu1, int nu2, const double* b,
+              double* x, int nvec) {
+    if (!h || !b || !x || nvec < 1 || nu1 < 0 || nu2 < 0 || nu1 + nu2 < 1) return LT_EINVAL;
+    const size_t per = 2 * (size_t)h->N * nvec;
+    cdouble tau(tau_re, tau_im);
+    int rc = 0;
+    if (precision == LT_PREC_FP64) {
+        return mg_vcycle<double>(h, tau, nu1, nu2, nvec, nullptr, x, b);
+    } else if (precision == LT_PREC_MIXED) {
+        float* bf = wsp<float>(h, "vc_b32", per, &rc);
+        float* xf = wsp<float>(h, "vc_x32", per, &rc);
+        if (!bf || !xf) return rc;
+        LT_TRY(convert_vectors<double, float>(h->stream, b, bf, per));
+        LT_TRY(mg_vcycle<float>(h, tau, nu1, nu2, nvec, nullptr, xf, bf));
+        return convert_vectors<float, double>(h->stream, xf, x, per);
+    }
+    return LT_EINVAL;
+}
+
+int lt_solve(lt_handle* h, const lt_points* sources, double q, const double* times, int ntimes,
+             const lt_contour* contour, const lt_points* receivers, const lt_opts* opts, double* phi_out,
+             lt_stats* stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!h || !sources || sources->n < 1 || !times || ntimes < 1 || !contour || !receivers || receivers->n < 1 ||
+        !phi_out || !std::isfinite(q)) {
+        set_last_error("lt_solve: bad argument");
+        return LT_EINVAL;
+    }
+    for (int t = 0; t < ntimes; ++t)
+        if (!(times[t] > 0.0) || !std::isfinite(times[t])) {
+            set_last_error("lt_solve: times must be positive");
+            return LT_EINVAL;
+        }
+    lt_opts o;
+    if (opts) {
+        LT_TRY(validate_opts(opts));
+        o = *opts;
+    } else {
+        lt_opts_default(&o);
+    }
+    if (contour->nz < 2 || contour->nz % 2 || contour->nz > 512) {
+        set_last_error("lt_solve: contour nz must be even, 2..512");
+        return LT_EINVAL;
+    }
+    Plan plan;
+    LT_TRY(make_plan(times, ntimes, contour->nz, q, &o, &plan));
+    PointsCSR sc, rcsr;
+    LT_TRY(points_csr(h->grid, sources, &sc));
+    LT_TRY(points_csr(h->grid, receivers, &rcsr));
+    DevPoints ds, dr;
+    LT_TRY(upload_points(h, sc, "src", &ds));
+    LT_TRY(upload_points(h, rcsr, "rec", &dr));
+    const int R = sources->n;
+    const size_t N2 = 2 * (size_t)h->N;
+    int rc = 0;
+    double* b = wsp<double>(h, "b", R * N2, &rc);
+    if (!b) return rc;
+    LT_HIP(hipMemsetAsync(b, 0, R * N2 * sizeof(double), h->stream));
+    LT_TRY(launch_scatter_points(h->stream, R, h->N, ds.off, ds.cell, ds.wt, b));
+    KrylovOut k;
+    k.b = b;
+    LT_TRY(run_krylov(h, plan, o, R, &dr, &k));
+    LT_TRY(launch_heads(h->stream, R, dr.n, ntimes, plan.nk, k.wq, k.G, k.Y, k.mcols, k.jmax, phi_out));
+    if (o.true_residual) LT_TRY(true_residuals(h, k, plan, stats));
+    LT_HIP(hipStreamSynchronize(h->stream));
+    if (stats && stats->iters_per_rhs)
+        LT_HIP(hipMemcpy(stats->iters_per_rhs, k.mcols, R * sizeof(int), hipMemcpyDeviceToHost));
+    double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_stats(stats, k, (int)h->levels.size(), secs);
+    return k.converged ? LT_OK : LT_WNOTCONV;
+}
+
+int lt_adjoint(lt_handle* h, const lt_points* sources, double q, const lt_points* receivers, const double* times,
+               int ntimes, const lt_contour* contour, const lt_opts* opts, double* dlnK, double* dlnS,
+               lt_stats* stats) {
+    (void)h; (void)sources; (void)q; (void)receivers; (void)times; (void)ntimes; (void)contour; (void)opts;
+    (void)dlnK; (void)dlnS; (void)stats;
+    set_last_error("lt_adjoint: not built yet");
+    return LT_EUNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+// Launchers of the FP64 flexible shifted Arnoldi kernels (krylov.hip).
+#pragma once
+
+#include "lt_internal.h"
+
+namespace lt {
+
+// Per-(rhs, shift) Givens least-squares state, pair index p = r * Ks + k, P = R * Ks pairs:
+//   Rm[(col*(col+1)/2 + row) * P + p]  complex  upper-triangular factor, packed by column
+//   cs[col * P + p]                    real     rotation cosines
+//   sn[col * P + p]                    complex  rotation sines
+//   g[row * P + p]                     complex  rotated right-hand side beta e_1
+//   res[p]                             real     current relative residual
+struct LSState {
+    double* Rm;
+    double* cs;
+    double* sn;
+    double* g;
+    double* res;
+};
+
+int reduce_blocks(int N, int R);
+int launch_scatter_points(hipStream_t st, int R, int N, const int* off, const int* cell, const double* wt,
+                          double* b);
+int launch_norms(hipStream_t st, int N, int R, size_t vstride, const double* x, double* part, double* out,
+                 const int* active);
+int launch_scale_into(hipStream_t st, int N, int R, size_t instride, size_t outstride, const double* in,
+                      const double* nrm, double* out);
+template <typename T>
+int launch_inner_init(hipStream_t st, int N, int R, size_t qstride, const double* v, double* u, size_t ustride,
+                      double* rho, T* lo, const int* active);
+template <typename T>
+int launch_inner_update(hipStream_t st, LevelView<double> L, cdouble tau, int R, const T* e, double* u,
+                        size_t ustride, double* rho, T* lo, double* part, const int* inner_active);
+int launch_inner_finalize(hipStream_t st, int N, int R, const double* part, const int* active, const double* worst,
+                          double relax_tol, double tol, int step, int inner_max, int* inner_active, int* vcycles,
+                          int* count);
+int launch_cgs2(hipStream_t st, int N, int R, int j, const double* m, const double* U, size_t ustride, double* Q,
+                size_t qstride, double* H, int hstride, size_t hrstride, double* part, int pstride, double* c1,
+                double* c2, int cstride, double* scale, const int* active);
+int launch_ls_update(hipStream_t st, int R, int Ks, int j, cdouble tau, const double* zs, const double* omega,
+                     double tol, const double* H, int hstride, size_t hrstride, const double* beta,
+                     const LSState& s, int* active, int* mcols, double* worst, int* conv);
+int launch_gather(hipStream_t st, int R, int N, int np, const int* off, const int* cell, const double* wt,
+                  const double* U, size_t ustride, int j, double* G, int jmax, const int* active);
+int launch_backsolve(hipStream_t st, int R, int Ks, const int* mcols, const LSState& s, double* Y, int jmax);
+int launch_heads(hipStream_t st, int R, int np, int ntimes, int nk, const double* wq, const double* G,
+                 const double* Y, const int* mcols, int jmax, double* phi);
+int launch_form_x(hipStream_t st, int N, int R, int nc, int k0, int Ks, const double* U, size_t ustride,
+                  const double* Y, int jmax, const int* mcols, double* X);
+int launch_true_residual(hipStream_t st, LevelView<double> L, int R, int nc, int k0, int Ks, const double* zs,
+                         const double* X, const double* b, const double* beta, double* part, double* out);
+
+}  // namespace lt

@@ -1,0 +1,728 @@
+// FP64 kernels of the flexible shifted Arnoldi method (Section 3, Algorithm
+// "Flexible FOM/GMRES for shifted systems"), batched over right-hand sides.
+//
+// Vectors of one right-hand side are complex SoA planes [2][N]; a batch is
+// [R][2][N]; the basis is Q[R][jmax+1][2][N] and the preconditioned vectors
+// U[R][jmax][2][N].  Reductions are two-stage with a fixed order, so results
+// are deterministic.  Every kernel takes a per-RHS mask and skips converged
+// right-hand sides.
+#include "krylov.h"
+
+#include <cmath>
+
+namespace lt {
+
+static constexpr int kB = 256;
+static constexpr int kGroup = 8;  // basis columns reduced together
+
+struct c64 {
+    double re, im;
+};
+__device__ __forceinline__ c64 cm(c64 a, c64 b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ c64 cmc(c64 a, c64 b) {  // conj(a) * b
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+__device__ __forceinline__ c64 cd(c64 a, c64 b) {
+    double d = b.re * b.re + b.im * b.im;
+    return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+
+// Sum of v over the block (all threads get the result in lane 0 of wave 0; returned to thread 0).
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Reduce `n` doubles per thread across the block; result written to out[0..n) by thread 0.
+template <int NV>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], double* out) {
+    __shared__ double sh[kB / 64][NV];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[w][k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0;
+            for (int q = 0; q < kB / 64; ++q) s += sh[q][k];
+            out[k] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- RHS and norms
+__global__ void k_scatter_points(int R, int N, const int* __restrict__ off, const int* __restrict__ cell,
+                                 const double* __restrict__ wt, double* __restrict__ b) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    for (int p = off[r]; p < off[r + 1]; ++p) b[(size_t)2 * N * r + cell[p]] += wt[p];
+}
+
+// partial[r][blk] = sum |x|^2 over the block's cells of vector r (stride between vectors: vstride)
+__global__ void k_norm2_partial(int N, size_t vstride, const double* __restrict__ x, double* __restrict__ part,
+                                const int* __restrict__ active) {
+    int r = blockIdx.y;
+    if (active && !active[r]) return;
+    const double* xr = x + vstride * r;
+    const double* xi = xr + N;
+    double v[1] = {0};
+    for (int i = blockIdx.x * kB + threadIdx.x; i < N; i += gridDim.x * kB) v[0] += xr[i] * xr[i] + xi[i] * xi[i];
+    double o[1];
+    block_reduce<1>(v, o);
+    if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = o[0];
+}
+
+// beta[r] = ||b_r||, Q0 = b / beta
+__global__ void k_norm_finalize(int R, int nb, const double* __restrict__ part, double* __restrict__ out) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    double s = 0;
+    for (int q = 0; q < nb; ++q) s += part[(size_t)r * nb + q];
+    out[r] = sqrt(s);
+}
+
+__global__ void k_scale_into(int N, size_t instride, size_t outstride, const double* __restrict__ in,
+                             const double* __restrict__ nrm, double* __restrict__ out) {
+    int r = blockIdx.y;
+    size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
+    if (i >= 2 * (size_t)N) return;
+    double s = nrm[r] > 0 ? 1.0 / nrm[r] : 0.0;
+    out[outstride * r + i] = in[instride * r + i] * s;
+}
+
+// ---------------------------------------------------------------- inner refinement
+// u <- 0, rho <- v = Q[:, j]; lo <- (T) rho
+template <typename T>
+__global__ void k_inner_init(int N, size_t qstride, const double* __restrict__ v, double* __restrict__ u,
+                             size_t ustride, double* __restrict__ rho, T* __restrict__ lo,
+                             const int* __restrict__ active) {
+    int r = blockIdx.y;
+    if (active && !active[r]) return;
+    size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
+    if (i >= 2 * (size_t)N) return;
+    double x = v[qstride * r + i];
+    u[ustride * r + i] = 0.0;
+    rho[2 * (size_t)N * r + i] = x;
+    if (lo) lo[2 * (size_t)N * r + i] = (T)x;
+}
+
+// u += e; rho -= (K + tau M) e; lo = (T) rho; partial ||rho||^2
+template <typename T>
+__global__ void k_inner_update(LevelView<double> L, double tr, double ti, const T* __restrict__ e,
+                               double* __restrict__ u, size_t ustride, double* __restrict__ rho,
+                               T* __restrict__ lo, double* __restrict__ part, const int* __restrict__ active) {
+    int r = blockIdx.y;
+    if (active && !active[r]) return;
+    const size_t N = L.N;
+    const T* er = e + 2 * N * r;
+    const T* ei = er + N;
+    double* ur = u + ustride * r;
+    double* rr = rho + 2 * N * r;
+    double v[1] = {0};
+    for (int i = blockIdx.x * kB + threadIdx.x; i < L.N; i += gridDim.x * kB) {
+        int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+        double sre = 0, sim = 0;
+        if (x + 1 < L.nx) { double t = L.Tx[i]; sre += t * (double)er[i + 1]; sim += t * (double)ei[i + 1]; }
+        if (x > 0) { double t = L.Tx[i - 1]; sre += t * (double)er[i - 1]; sim += t * (double)ei[i - 1]; }
+        const int sy = L.nx, sz = L.nx * L.ny;
+        if (y + 1 < L.ny) { double t = L.Ty[i]; sre += t * (double)er[i + sy]; sim += t * (double)ei[i + sy]; }
+        if (y > 0) { double t = L.Ty[i - sy]; sre += t * (double)er[i - sy]; sim += t * (double)ei[i - sy]; }
+        if (z + 1 < L.nz) { double t = L.Tz[i]; sre += t * (double)er[i + sz]; sim += t * (double)ei[i + sz]; }
+        if (z > 0) { double t = L.Tz[i - sz]; sre += t * (double)er[i - sz]; sim += t * (double)ei[i - sz]; }
+        double dre = L.D[i] + tr * L.m[i], dim = ti * L.m[i];
+        double xre = (double)er[i], xim = (double)ei[i];
+        double are = dre * xre - dim * xim - sre;
+        double aim = dre * xim + dim * xre - sim;
+        ur[i] += xre;
+        ur[i + N] += xim;
+        double nre = rr[i] - are, nim = rr[i + N] - aim;
+        rr[i] = nre;
+        rr[i + N] = nim;
+        if (lo) {
+            lo[2 * N * r + i] = (T)nre;
+            lo[2 * N * r + N + i] = (T)nim;
+        }
+        v[0] += nre * nre + nim * nim;
+    }
+    double o[1];
+    block_reduce<1>(v, o);
+    if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = o[0];
+}
+
+// inner_active[r] = active[r] && ||rho_r|| > eta_r && step + 1 < inner_max; counts vcycles.
+__global__ void k_inner_finalize(int R, int nb, const double* __restrict__ part, const int* __restrict__ active,
+                                 const double* __restrict__ worst, double relax_tol, double tol, int step,
+                                 int inner_max, int* __restrict__ inner_active, int* __restrict__ vcycles,
+                                 int* __restrict__ count) {
+    int r = threadIdx.x;
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (; r < R; r += blockDim.x) {
+        int a = inner_active[r];
+        if (!a) continue;
+        double s = 0;
+        for (int q = 0; q < nb; ++q) s += part[(size_t)r * nb + q];
+        double eta = relax_tol / fmax(worst[r], tol);
+        eta = fmin(eta, 0.5);
+        vcycles[r] += 1;
+        int again = (sqrt(s) > eta) && (step + 1 < inner_max) && active[r];
+        inner_active[r] = again;
+        if (again) atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *count = cnt;
+}
+
+// ---------------------------------------------------------------- classical Gram-Schmidt (twice)
+// Source vector: if `u` is given, s = m .* u (lumped mass, M u_j of the algorithm); else s = svec.
+__device__ __forceinline__ c64 load_s(const double* __restrict__ m, const double* __restrict__ u,
+                                      const double* __restrict__ s, size_t N, int i) {
+    if (u) return {m[i] * u[i], m[i] * u[i + N]};
+    return {s[i], s[i + N]};
+}
+
+// part[r][blk][c] = sum_i conj(Q_c(i)) s(i),  c < ncols; plus part[...][ncols] = ||s||^2 (real part)
+__global__ void k_mdot(int N, int ncols, const double* __restrict__ Q, size_t qstride,
+                       const double* __restrict__ m, const double* __restrict__ u, size_t ustride,
+                       const double* __restrict__ s, size_t sstride, double* __restrict__ part, int pstride,
+                       const int* __restrict__ active) {
+    int r = blockIdx.y;
+    if (active && !active[r]) return;
+    const double* Qr = Q + qstride * r;
+    const double* ur = u ? u + ustride * r : nullptr;
+    const double* sr = s ? s + sstride * r : nullptr;
+    double* pr = part + ((size_t)r * gridDim.x + blockIdx.x) * pstride;
+    const size_t NN = N;
+    // norm of s
+    {
+        double v[1] = {0};
+        for (int i = blockIdx.x * kB + threadIdx.x; i < N; i += gridDim.x * kB) {
+            c64 sv = load_s(m, ur, sr, NN, i);
+            v[0] += sv.re * sv.re + sv.im * sv.im;
+        }
+        double o[1];
+        block_reduce<1>(v, o);
+        if (threadIdx.x == 0) {
+            pr[2 * ncols] = o[0];
+            pr[2 * ncols + 1] = 0;
+        }
+    }
+    for (int c0 = 0; c0 < ncols; c0 += kGroup) {
+        double v[2 * kGroup];
+#pragma unroll
+        for (int k = 0; k < 2 * kGroup; ++k) v[k] = 0;
+        for (int i = blockIdx.x * kB + threadIdx.x; i < N; i += gridDim.x * kB) {
+            c64 sv = load_s(m, ur, sr, NN, i);
+#pragma unroll
+            for (int k = 0; k < kGroup; ++k) {
+                int c = c0 + k;
+                if (c < ncols) {
+                    const double* q = Qr + 2 * NN * c;
+                    c64 p = cmc({q[i], q[i + NN]}, sv);
+                    v[2 * k] += p.re;
+                    v[2 * k + 1] += p.im;
+                }
+            }
+        }
+        double o[2 * kGroup];
+        block_reduce<2 * kGroup>(v, o);
+        if (threadIdx.x == 0) {
+            for (int k = 0; k < kGroup && c0 + k < ncols; ++k) {
+                pr[2 * (c0 + k)] = o[2 * k];
+                pr[2 * (c0 + k) + 1] = o[2 * k + 1];
+            }
+        }
+    }
+}
+
+// coef[r][c] = sum over blocks of part  (c < ncols + 1: the last entry is ||s||^2)
+__global__ void k_mdot_finalize(int nb, int ncols, const double* __restrict__ part, int pstride,
+                                double* __restrict__ coef, int cstride, const int* __restrict__ active) {
+    int r = blockIdx.x;
+    if (active && !active[r]) return;
+    for (int c = threadIdx.x; c <= ncols; c += blockDim.x) {
+        double re = 0, im = 0;
+        for (int q = 0; q < nb; ++q) {
+            const double* p = part + ((size_t)r * nb + q) * pstride;
+            re += p[2 * c];
+            im += p[2 * c + 1];
+        }
+        coef[(size_t)r * cstride + 2 * c] = re;
+        coef[(size_t)r * cstride + 2 * c + 1] = im;
+    }
+}
+
+// out = s - sum_c Q_c coef_c; optional partial ||out||^2 into part[r][blk]
+__global__ void k_update(int N, int ncols, const double* __restrict__ Q, size_t qstride,
+                         const double* __restrict__ m, const double* __restrict__ u, size_t ustride,
+                         const double* __restrict__ s, size_t sstride, const double* __restrict__ coef,
+                         int cstride, double* __restrict__ out, size_t ostride, double* __restrict__ part,
+                         const int* __restrict__ active) {
+    int r = blockIdx.y;
+    if (active && !active[r]) return;
+    const double* Qr = Q + qstride * r;
+    const double* ur = u ? u + ustride * r : nullptr;
+    const double* sr = s ? s + sstride * r : nullptr;
+    const double* cr = coef + (size_t)r * cstride;
+    double* orr = out + ostride * r;
+    const size_t NN = N;
+    double v[1] = {0};
+    for (int i = blockIdx.x * kB + threadIdx.x; i < N; i += gridDim.x * kB) {
+        c64 sv = load_s(m, ur, sr, NN, i);
+        for (int c = 0; c < ncols; ++c) {
+            const double* q = Qr + 2 * NN * c;
+            c64 p = cm({q[i], q[i + NN]}, {cr[2 * c], cr[2 * c + 1]});
+            sv.re -= p.re;
+            sv.im -= p.im;
+        }
+        orr[i] = sv.re;
+        orr[i + NN] = sv.im;
+        v[0] += sv.re * sv.re + sv.im * sv.im;
+    }
+    if (part) {
+        double o[1];
+        block_reduce<1>(v, o);
+        if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = o[0];
+    }
+}
+
+// Hbar column j: h = h1 + h2, h_{j+1,j} = ||s||; scale for the new basis vector;
+// breakdown (||s|| <= 1e-14 ||M u||) gives h_{j+1,j} = 0 and a zero vector.
+__global__ void k_hcol_finalize(int R, int j, int nb, const double* __restrict__ c1, const double* __restrict__ c2,
+                                int cstride, const double* __restrict__ part, double* __restrict__ H,
+                                int hstride, size_t hrstride, double* __restrict__ scale,
+                                const int* __restrict__ active) {
+    int r = blockIdx.x;
+    if (active && !active[r]) return;
+    double* Hc = H + hrstride * r + (size_t)hstride * j;
+    const double* a = c1 + (size_t)r * cstride;
+    const double* b = c2 + (size_t)r * cstride;
+    for (int c = threadIdx.x; c <= j; c += blockDim.x) {
+        Hc[2 * c] = a[2 * c] + b[2 * c];
+        Hc[2 * c + 1] = a[2 * c + 1] + b[2 * c + 1];
+    }
+    if (threadIdx.x == 0) {
+        double s = 0;
+        for (int q = 0; q < nb; ++q) s += part[(size_t)r * nb + q];
+        double nrm = sqrt(s);
+        double nrm0 = sqrt(a[2 * (j + 1)]);  // ||M u_j|| from the first pass
+        bool breakdown = !(nrm > 1e-14 * nrm0);
+        Hc[2 * (j + 1)] = breakdown ? 0.0 : nrm;
+        Hc[2 * (j + 1) + 1] = 0.0;
+        scale[r] = breakdown ? 0.0 : 1.0 / nrm;
+    }
+}
+
+__global__ void k_scale_inplace(int N, double* __restrict__ x, size_t stride, const double* __restrict__ scale,
+                                const int* __restrict__ active) {
+    int r = blockIdx.y;
+    if (active && !active[r]) return;
+    size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
+    if (i >= 2 * (size_t)N) return;
+    x[stride * r + i] *= scale[r];
+}
+
+// ---------------------------------------------------------------- per-shift least squares
+// One block per right-hand side, one thread per shift.  The Hessenberg matrix of shift z is
+// Hbar(z; T) = [I; 0] + Hbar (z I - T) (eqn:shiftedarnoldimod): column j is e_j + (z - tau_j) h_j.
+// Its QR factorisation is extended by one Givens rotation per column; |g_{j+1}| is the
+// GMRES residual norm of the shift.
+__global__ void k_ls_update(int R, int Ks, int j, double tau_re, double tau_im, const double* __restrict__ zs,
+                            const double* __restrict__ omega, double tol, const double* __restrict__ H,
+                            int hstride, size_t hrstride, const double* __restrict__ beta, LSState st,
+                            int* __restrict__ active, int* __restrict__ mcols, double* __restrict__ worst,
+                            int* __restrict__ conv_flags) {
+    int r = blockIdx.x;
+    if (!active[r]) return;
+    extern __shared__ double sh[];  // h column, 2 (j + 2) doubles
+    const double* Hc = H + hrstride * r + (size_t)hstride * j;
+    for (int c = threadIdx.x; c < 2 * (j + 2); c += blockDim.x) sh[c] = Hc[c];
+    __shared__ int notconv;
+    __shared__ double wmax[kB / 64];
+    if (threadIdx.x == 0) notconv = 0;
+    __syncthreads();
+    double myw = 0;
+    for (int k = threadIdx.x; k < Ks; k += blockDim.x) {
+        c64 dz = {zs[2 * k] - tau_re, zs[2 * k + 1] - tau_im};
+        const size_t base = (size_t)r * Ks + k;  // pair index
+        const size_t P = (size_t)R * Ks;
+        // column entries col_i = delta_ij + dz * h_i, streamed through the previous rotations
+        c64 cur = cm(dz, {sh[0], sh[1]});
+        if (j == 0) cur.re += 1.0;
+        for (int i = 0; i < j; ++i) {
+            c64 nxt = cm(dz, {sh[2 * (i + 1)], sh[2 * (i + 1) + 1]});
+            if (i + 1 == j) nxt.re += 1.0;
+            double c = st.cs[(size_t)i * P + base];
+            c64 s = {st.sn[2 * ((size_t)i * P + base)], st.sn[2 * ((size_t)i * P + base) + 1]};
+            // [c s; -conj(s) c] [cur; nxt]
+            c64 top = {c * cur.re + (s.re * nxt.re - s.im * nxt.im), c * cur.im + (s.re * nxt.im + s.im * nxt.re)};
+            c64 bot = {-(s.re * cur.re + s.im * cur.im) + c * nxt.re, -(s.re * cur.im - s.im * cur.re) + c * nxt.im};
+            size_t ri = (size_t)(j * (j + 1) / 2 + i) * P + base;
+            st.Rm[2 * ri] = top.re;
+            st.Rm[2 * ri + 1] = top.im;
+            cur = bot;
+        }
+        c64 sub = cm(dz, {sh[2 * (j + 1)], sh[2 * (j + 1) + 1]});
+        // new rotation zeroing `sub` into `cur`
+        double na = hypot(cur.re, cur.im), nb = hypot(sub.re, sub.im);
+        double c;
+        c64 s, rr;
+        if (nb == 0.0) {
+            c = 1.0;
+            s = {0.0, 0.0};
+            rr = cur;
+        } else if (na == 0.0) {
+            c = 0.0;
+            s = {sub.re / nb, -sub.im / nb};  // conj(sub)/|sub|
+            rr = {nb, 0.0};
+        } else {
+            double nu = hypot(na, nb);
+            c = na / nu;
+            c64 ph = {cur.re / na, cur.im / na};                 // a / |a|
+            c64 cb = {sub.re / nu, -sub.im / nu};                // conj(b) / nu
+            s = cm(ph, cb);
+            rr = {ph.re * nu, ph.im * nu};
+        }
+        size_t rj = (size_t)(j * (j + 1) / 2 + j) * P + base;
+        st.Rm[2 * rj] = rr.re;
+        st.Rm[2 * rj + 1] = rr.im;
+        st.cs[(size_t)j * P + base] = c;
+        st.sn[2 * ((size_t)j * P + base)] = s.re;
+        st.sn[2 * ((size_t)j * P + base) + 1] = s.im;
+        // g: g_j <- c g_j ; g_{j+1} = -conj(s) g_j
+        c64 gj;
+        if (j == 0) {
+            gj = {beta[r], 0.0};
+        } else {
+            gj = {st.g[2 * ((size_t)j * P + base)], st.g[2 * ((size_t)j * P + base) + 1]};
+        }
+        c64 gt = {c * gj.re, c * gj.im};
+        c64 gn = {-(s.re * gj.re + s.im * gj.im), -(s.re * gj.im - s.im * gj.re)};
+        st.g[2 * ((size_t)j * P + base)] = gt.re;
+        st.g[2 * ((size_t)j * P + base) + 1] = gt.im;
+        st.g[2 * ((size_t)(j + 1) * P + base)] = gn.re;
+        st.g[2 * ((size_t)(j + 1) * P + base) + 1] = gn.im;
+        double res = hypot(gn.re, gn.im) / beta[r];
+        double wres = omega[k] * res;
+        st.res[base] = res;
+        myw = fmax(myw, wres);
+        int ok = wres <= tol;
+        conv_flags[base] = ok;
+        if (!ok) atomicOr(&notconv, 1);
+    }
+    myw = fmax(myw, __shfl_xor(myw, 32, 64));
+    myw = fmax(myw, __shfl_xor(myw, 16, 64));
+    myw = fmax(myw, __shfl_xor(myw, 8, 64));
+    myw = fmax(myw, __shfl_xor(myw, 4, 64));
+    myw = fmax(myw, __shfl_xor(myw, 2, 64));
+    myw = fmax(myw, __shfl_xor(myw, 1, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = myw;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double w = 0;
+        for (int q = 0; q < (int)(blockDim.x + 63) / 64; ++q) w = fmax(w, wmax[q]);
+        worst[r] = w;
+        mcols[r] = j + 1;
+        // a breakdown (h_{j+1,j} = 0) leaves every residual at zero: converged
+        if (!notconv) active[r] = 0;
+    }
+}
+
+// y = R^{-1} g for each pair, m = mcols[r] columns.  Y[r][j][k].
+__global__ void k_backsolve(int R, int Ks, const int* __restrict__ mcols, LSState st, double* __restrict__ Y,
+                            int jmax) {
+    int r = blockIdx.y;
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Ks) return;
+    const int m = mcols[r];
+    const size_t P = (size_t)R * Ks;
+    const size_t base = (size_t)r * Ks + k;
+    double* Yr = Y + (size_t)r * jmax * 2 * Ks;
+    for (int j = m - 1; j >= 0; --j) {
+        c64 acc = {st.g[2 * ((size_t)j * P + base)], st.g[2 * ((size_t)j * P + base) + 1]};
+        for (int i = j + 1; i < m; ++i) {
+            size_t ri = (size_t)(i * (i + 1) / 2 + j) * P + base;
+            c64 Rji = {st.Rm[2 * ri], st.Rm[2 * ri + 1]};
+            c64 yi = {Yr[(size_t)i * 2 * Ks + 2 * k], Yr[(size_t)i * 2 * Ks + 2 * k + 1]};
+            c64 p = cm(Rji, yi);
+            acc.re -= p.re;
+            acc.im -= p.im;
+        }
+        size_t rj = (size_t)(j * (j + 1) / 2 + j) * P + base;
+        c64 y = cd(acc, {st.Rm[2 * rj], st.Rm[2 * rj + 1]});
+        Yr[(size_t)j * 2 * Ks + 2 * k] = y.re;
+        Yr[(size_t)j * 2 * Ks + 2 * k + 1] = y.im;
+    }
+}
+
+// ---------------------------------------------------------------- receivers and the contour sum
+// G[r][j][p] = sum_w w u_j(cell) for receiver p (B_r u_j).
+__global__ void k_gather(int R, int N, int np, const int* __restrict__ off, const int* __restrict__ cell,
+                         const double* __restrict__ wt, const double* __restrict__ U, size_t ustride, int j,
+                         double* __restrict__ G, int jmax, const int* __restrict__ active) {
+    int r = blockIdx.y;
+    if (active && !active[r]) return;
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const double* u = U + ustride * r + (size_t)2 * N * j;
+    double re = 0, im = 0;
+    for (int q = off[p]; q < off[p + 1]; ++q) {
+        re += wt[q] * u[cell[q]];
+        im += wt[q] * u[(size_t)N + cell[q]];
+    }
+    double* g = G + ((size_t)r * jmax + j) * 2 * np;
+    g[2 * p] = re;
+    g[2 * p + 1] = im;
+}
+
+// phi[r][p][t] = 2 Re sum_{k in t} wq_k sum_j G[r][j][p] Y[r][j][k]
+__global__ void k_heads(int R, int np, int ntimes, int nk, const double* __restrict__ wq,
+                        const double* __restrict__ G, const double* __restrict__ Y, const int* __restrict__ mcols,
+                        int jmax, double* __restrict__ phi) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= R * np * ntimes) return;
+    int t = idx % ntimes, p = (idx / ntimes) % np, r = idx / (ntimes * np);
+    const int Ks = ntimes * nk;
+    const int m = mcols[r];
+    double acc = 0;
+    for (int kk = 0; kk < nk; ++kk) {
+        int k = t * nk + kk;
+        c64 s = {0, 0};
+        for (int j = 0; j < m; ++j) {
+            const double* g = G + ((size_t)r * jmax + j) * 2 * np + 2 * p;
+            const double* y = Y + ((size_t)r * jmax + j) * 2 * Ks + 2 * k;
+            c64 pr = cm({g[0], g[1]}, {y[0], y[1]});
+            s.re += pr.re;
+            s.im += pr.im;
+        }
+        c64 w = {wq[2 * k], wq[2 * k + 1]};
+        acc += w.re * s.re - w.im * s.im;
+    }
+    phi[idx] = 2.0 * acc;
+}
+
+// ---------------------------------------------------------------- true residual
+// X[r][c][2][N] = sum_j U[r][j] Y[r][j][k0 + c], c < nc
+__global__ void k_form_x(int N, int nc, int k0, int Ks, const double* __restrict__ U, size_t ustride,
+                         const double* __restrict__ Y, int jmax, const int* __restrict__ mcols,
+                         double* __restrict__ X) {
+    constexpr int CMAX = 8;
+    int r = blockIdx.y;
+    int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= N) return;
+    const int m = mcols[r];
+    const size_t NN = N;
+    for (int c0 = 0; c0 < nc; c0 += CMAX) {
+        double are[CMAX], aim[CMAX];
+        for (int c = 0; c < CMAX; ++c) are[c] = aim[c] = 0;
+        for (int j = 0; j < m; ++j) {
+            const double* u = U + ustride * r + 2 * NN * j;
+            double ur = u[i], ui = u[i + NN];
+            const double* y = Y + ((size_t)r * jmax + j) * 2 * Ks + 2 * (k0 + c0);
+            for (int c = 0; c < CMAX && c0 + c < nc; ++c) {
+                are[c] += ur * y[2 * c] - ui * y[2 * c + 1];
+                aim[c] += ur * y[2 * c + 1] + ui * y[2 * c];
+            }
+        }
+        for (int c = 0; c < CMAX && c0 + c < nc; ++c) {
+            double* x = X + ((size_t)r * nc + c0 + c) * 2 * NN;
+            x[i] = are[c];
+            x[i + NN] = aim[c];
+        }
+    }
+}
+
+// part[(r*nc + c)][blk] = || b_r - (K + z_{k0+c} M) X[r][c] ||^2 over the block
+__global__ void k_true_res(LevelView<double> L, int nc, int k0, const double* __restrict__ zs,
+                           const double* __restrict__ X, const double* __restrict__ b, double* __restrict__ part) {
+    int rc = blockIdx.y;
+    int r = rc / nc, c = rc % nc;
+    const size_t N = L.N;
+    const double* xr = X + (size_t)rc * 2 * N;
+    const double* xi = xr + N;
+    const double* br = b + (size_t)r * 2 * N;
+    double zr = zs[2 * (k0 + c)], zi = zs[2 * (k0 + c) + 1];
+    double v[1] = {0};
+    for (int i = blockIdx.x * kB + threadIdx.x; i < L.N; i += gridDim.x * kB) {
+        int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+        double sre = 0, sim = 0;
+        const int sy = L.nx, sz = L.nx * L.ny;
+        if (x + 1 < L.nx) { double t = L.Tx[i]; sre += t * xr[i + 1]; sim += t * xi[i + 1]; }
+        if (x > 0) { double t = L.Tx[i - 1]; sre += t * xr[i - 1]; sim += t * xi[i - 1]; }
+        if (y + 1 < L.ny) { double t = L.Ty[i]; sre += t * xr[i + sy]; sim += t * xi[i + sy]; }
+        if (y > 0) { double t = L.Ty[i - sy]; sre += t * xr[i - sy]; sim += t * xi[i - sy]; }
+        if (z + 1 < L.nz) { double t = L.Tz[i]; sre += t * xr[i + sz]; sim += t * xi[i + sz]; }
+        if (z > 0) { double t = L.Tz[i - sz]; sre += t * xr[i - sz]; sim += t * xi[i - sz]; }
+        double dre = L.D[i] + zr * L.m[i], dim = zi * L.m[i];
+        double are = dre * xr[i] - dim * xi[i] - sre;
+        double aim = dre * xi[i] + dim * xr[i] - sim;
+        double rre = br[i] - are, rim = br[i + N] - aim;
+        v[0] += rre * rre + rim * rim;
+    }
+    double o[1];
+    block_reduce<1>(v, o);
+    if (threadIdx.x == 0) part[(size_t)rc * gridDim.x + blockIdx.x] = o[0];
+}
+
+__global__ void k_true_res_finalize(int R, int nc, int k0, int Ks, int nb, const double* __restrict__ part,
+                                    const double* __restrict__ beta, double* __restrict__ out) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= R * nc) return;
+    int r = idx / nc, c = idx % nc;
+    double s = 0;
+    for (int q = 0; q < nb; ++q) s += part[(size_t)idx * nb + q];
+    out[(size_t)r * Ks + k0 + c] = sqrt(s) / beta[r];
+}
+
+// ---------------------------------------------------------------- launchers
+static inline unsigned nb_for(size_t n) { return (unsigned)((n + kB - 1) / kB); }
+
+int launch_scatter_points(hipStream_t st, int R, int N, const int* off, const int* cell, const double* wt,
+                          double* b) {
+    k_scatter_points<<<nb_for(R), kB, 0, st>>>(R, N, off, cell, wt, b);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
+int reduce_blocks(int N, int R) {
+    // about 4 cells per thread and at least a few hundred blocks overall
+    int nb = (N + 4 * kB - 1) / (4 * kB);
+    if (nb < 1) nb = 1;
+    if (nb > 1024) nb = 1024;
+    return nb;
+}
+
+int launch_norms(hipStream_t st, int N, int R, size_t vstride, const double* x, double* part, double* out,
+                 const int* active) {
+    int nb = reduce_blocks(N, R);
+    k_norm2_partial<<<dim3(nb, R), kB, 0, st>>>(N, vstride, x, part, active);
+    k_norm_finalize<<<nb_for(R), kB, 0, st>>>(R, nb, part, out);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_scale_into(hipStream_t st, int N, int R, size_t instride, size_t outstride, const double* in,
+                      const double* nrm, double* out) {
+    k_scale_into<<<dim3(nb_for(2 * (size_t)N), R), kB, 0, st>>>(N, instride, outstride, in, nrm, out);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
+template <typename T>
+int launch_inner_init(hipStream_t st, int N, int R, size_t qstride, const double* v, double* u, size_t ustride,
+                      double* rho, T* lo, const int* active) {
+    k_inner_init<T><<<dim3(nb_for(2 * (size_t)N), R), kB, 0, st>>>(N, qstride, v, u, ustride, rho, lo, active);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+template int launch_inner_init<double>(hipStream_t, int, int, size_t, const double*, double*, size_t, double*,
+                                       double*, const int*);
+template int launch_inner_init<float>(hipStream_t, int, int, size_t, const double*, double*, size_t, double*,
+                                      float*, const int*);
+
+template <typename T>
+int launch_inner_update(hipStream_t st, LevelView<double> L, cdouble tau, int R, const T* e, double* u,
+                        size_t ustride, double* rho, T* lo, double* part, const int* inner_active) {
+    int nb = reduce_blocks(L.N, R);
+    k_inner_update<T><<<dim3(nb, R), kB, 0, st>>>(L, tau.real(), tau.imag(), e, u, ustride, rho, lo, part,
+                                                  inner_active);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+template int launch_inner_update<double>(hipStream_t, LevelView<double>, cdouble, int, const double*, double*,
+                                         size_t, double*, double*, double*, const int*);
+template int launch_inner_update<float>(hipStream_t, LevelView<double>, cdouble, int, const float*, double*,
+                                        size_t, double*, float*, double*, const int*);
+
+int launch_inner_finalize(hipStream_t st, int N, int R, const double* part, const int* active, const double* worst,
+                          double relax_tol, double tol, int step, int inner_max, int* inner_active, int* vcycles,
+                          int* count) {
+    int nb = reduce_blocks(N, R);
+    k_inner_finalize<<<1, 1024, 0, st>>>(R, nb, part, active, worst, relax_tol, tol, step, inner_max, inner_active,
+                                         vcycles, count);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
+// One CGS2 step for column j: Q[:, j+1] = normalised (I - Q Q^*)^2 (M u_j); Hbar column j.
+int launch_cgs2(hipStream_t st, int N, int R, int j, const double* m, const double* U, size_t ustride, double* Q,
+                size_t qstride, double* H, int hstride, size_t hrstride, double* part, int pstride, double* c1,
+                double* c2, int cstride, double* scale, const int* active) {
+    int nb = reduce_blocks(N, R);
+    int ncols = j + 1;
+    const double* u = U + 2 * (size_t)N * j;
+    double* qn = Q + 2 * (size_t)N * (j + 1);
+    dim3 g(nb, R);
+    k_mdot<<<g, kB, 0, st>>>(N, ncols, Q, qstride, m, u, ustride, nullptr, 0, part, pstride, active);
+    k_mdot_finalize<<<R, 256, 0, st>>>(nb, ncols, part, pstride, c1, cstride, active);
+    k_update<<<g, kB, 0, st>>>(N, ncols, Q, qstride, m, u, ustride, nullptr, 0, c1, cstride, qn, qstride, nullptr,
+                               active);
+    k_mdot<<<g, kB, 0, st>>>(N, ncols, Q, qstride, nullptr, nullptr, 0, qn, qstride, part, pstride, active);
+    k_mdot_finalize<<<R, 256, 0, st>>>(nb, ncols, part, pstride, c2, cstride, active);
+    k_update<<<g, kB, 0, st>>>(N, ncols, Q, qstride, nullptr, nullptr, 0, qn, qstride, c2, cstride, qn, qstride,
+                               part, active);
+    k_hcol_finalize<<<R, 256, 0, st>>>(R, j, nb, c1, c2, cstride, part, H, hstride, hrstride, scale, active);
+    k_scale_inplace<<<dim3(nb_for(2 * (size_t)N), R), kB, 0, st>>>(N, qn, qstride, scale, active);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_ls_update(hipStream_t st, int R, int Ks, int j, cdouble tau, const double* zs, const double* omega,
+                     double tol, const double* H, int hstride, size_t hrstride, const double* beta,
+                     const LSState& s, int* active, int* mcols, double* worst, int* conv) {
+    int threads = ((Ks + 63) / 64) * 64;
+    if (threads > kB) threads = kB;
+    size_t shm = sizeof(double) * 2 * (j + 2);
+    k_ls_update<<<R, threads, shm, st>>>(R, Ks, j, tau.real(), tau.imag(), zs, omega, tol, H, hstride, hrstride,
+                                         beta, s, active, mcols, worst, conv);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_gather(hipStream_t st, int R, int N, int np, const int* off, const int* cell, const double* wt,
+                  const double* U, size_t ustride, int j, double* G, int jmax, const int* active) {
+    if (np == 0) return 0;
+    k_gather<<<dim3(nb_for(np), R), kB, 0, st>>>(R, N, np, off, cell, wt, U, ustride, j, G, jmax, active);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_backsolve(hipStream_t st, int R, int Ks, const int* mcols, const LSState& s, double* Y, int jmax) {
+    k_backsolve<<<dim3(nb_for(Ks), R), kB, 0, st>>>(R, Ks, mcols, s, Y, jmax);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_heads(hipStream_t st, int R, int np, int ntimes, int nk, const double* wq, const double* G,
+                 const double* Y, const int* mcols, int jmax, double* phi) {
+    int tot = R * np * ntimes;
+    if (tot == 0) return 0;
+    k_heads<<<nb_for(tot), kB, 0, st>>>(R, np, ntimes, nk, wq, G, Y, mcols, jmax, phi);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_form_x(hipStream_t st, int N, int R, int nc, int k0, int Ks, const double* U, size_t ustride,
+                  const double* Y, int jmax, const int* mcols, double* X) {
+    k_form_x<<<dim3(nb_for(N), R), kB, 0, st>>>(N, nc, k0, Ks, U, ustride, Y, jmax, mcols, X);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_true_residual(hipStream_t st, LevelView<double> L, int R, int nc, int k0, int Ks, const double* zs,
+                         const double* X, const double* b, const double* beta, double* part, double* out) {
+    int nb = reduce_blocks(L.N, R);
+    k_true_res<<<dim3(nb, R * nc), kB, 0, st>>>(L, nc, k0, zs, X, b, part);
+    k_true_res_finalize<<<nb_for(R * nc), kB, 0, st>>>(R, nc, k0, Ks, nb, part, beta, out);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
+}  // namespace lt

@@ -1,0 +1,137 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <complex>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/lt.h"
+
+namespace lt {
+
+using cdouble = std::complex<double>;
+
+// ---------------------------------------------------------------- errors
+#define LT_HIP(...)                                                      \
+    do {                                                                 \
+        hipError_t e_ = (__VA_ARGS__);                                   \
+        if (e_ != hipSuccess) {                                          \
+            lt::set_last_error(std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_)); \
+            return LT_EHIP;                                              \
+        }                                                                \
+    } while (0)
+
+#define LT_TRY(...)                   \
+    do {                              \
+        int rc_ = (__VA_ARGS__);      \
+        if (rc_ < 0) return rc_;      \
+    } while (0)
+
+void set_last_error(const std::string& s);
+
+// ------------------------------------------------------------- device buffers
+// Grow-only device buffer: reallocates only when a larger size is requested.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    int reserve(size_t n);
+    void release();
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ------------------------------------------------------------- multigrid level
+// Cell-centred FV operator on one level: (A x)_i = (D_i + tau m_i) x_i
+//   - sum_a [ T_a[i] x_{i+e_a} + T_a[i-e_a] x_{i-e_a} ],
+// T_a[i] is the face to the +a neighbour (0 for the last cell along a);
+// D_i sums every face of the cell including walls; m_i is the lumped mass.
+template <typename T> struct LevelView {
+    int nx, ny, nz, N;
+    const T* Tx;
+    const T* Ty;
+    const T* Tz;
+    const T* D;
+    const T* m;
+};
+
+struct Level {
+    int n[3];
+    int N;
+    double h[3];
+    int coarsened_from_fine[3];  // axes halved when this level was built from the finer one
+    // coefficients: [5][N] = Tx, Ty, Tz, D, m
+    DevBuf c64, c32;
+    LevelView<double> v64() const;
+    LevelView<float> v32() const;
+};
+
+struct CoarseInverse {
+    cdouble tau;
+    DevBuf inv64, inv32;  // [N][N] complex (interleaved re, im), row-major
+};
+
+}  // namespace lt
+
+struct lt_handle {
+    lt_grid grid;
+    lt_bc bc;
+    hipStream_t stream;
+    int N;
+    std::vector<lt::Level> levels;
+    std::vector<lt::CoarseInverse> coarse_cache;
+    std::vector<double> coarse_host;  // coarsest level coefficients [5][Nc] on the host
+    // workspaces (grow-only, owned by the handle)
+    std::map<std::string, lt::DevBuf> ws;
+    void* pinned = nullptr;  // small pinned host area for flags
+    ~lt_handle();
+};
+
+namespace lt {
+
+// workspace helper
+template <typename T> T* wsp(lt_handle* h, const char* name, size_t count, int* rc) {
+    DevBuf& b = h->ws[name];
+    int r = b.reserve(count * sizeof(T));
+    if (r < 0) { *rc = r; return nullptr; }
+    return b.as<T>();
+}
+
+// ------------------------------------------------------------- host planner
+struct Plan {
+    int ntimes = 0, nz = 0, nk = 0;     // nk = nz/2 shifts per time
+    std::vector<cdouble> z;             // [ntimes * nk]
+    std::vector<cdouble> wq;            // w_k * qhat(z_k)  [ntimes * nk]
+    std::vector<double> omega;          // |wq| / max |wq| within the same time
+    std::vector<cdouble> tau_sched;     // cyclic preconditioner shifts
+};
+int talbot(int nz, double t, cdouble* z, cdouble* w);
+int make_plan(const double* times, int ntimes, int nz, double q, const lt_opts* o, Plan* p);
+
+// point weights as CSR (host)
+struct PointsCSR {
+    std::vector<int> off, cell;
+    std::vector<double> wt;
+};
+int points_csr(const lt_grid& g, const lt_points* pts, PointsCSR* out);
+
+// dense complex inverse (Gauss-Jordan with partial pivoting); returns 0 or LT_EINVAL if singular
+int dense_inverse(int n, std::vector<cdouble>& a, std::vector<cdouble>& inv);
+
+// ------------------------------------------------------------- multigrid
+int mg_build(lt_handle* h, const double* kappa, const double* S);
+const CoarseInverse* mg_coarse_inverse(lt_handle* h, cdouble tau, int* rc);
+// One V-cycle on level 0 for R complex vectors: b0, x0 in the level-0 work arrays of
+// precision T (x0 is overwritten).  active: device [R] mask or nullptr.
+template <typename T>
+int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* active,
+              T* x0, const T* b0);
+template <typename T>
+int apply_operator(lt_handle* h, int level, cdouble tau, const T* x, T* y, int R, const int* active);
+template <typename S, typename D>
+int convert_vectors(hipStream_t st, const S* in, D* out, size_t count);
+
+}  // namespace lt

@@ -1,0 +1,583 @@
+// Geometric multigrid for the complex-shifted cell-centred FV operator K + tau M.
+//
+// Levels are built by aggregating 2 cells per coarsened axis.  The coarse
+// transmissibility across an aggregate interface is the sum of the fine face
+// transmissibilities on that interface times h_a / H_a (1/2 on a halved
+// axis), which is exact for a homogeneous medium; walls scale the same way;
+// the lumped mass is summed.  Axes are halved only while their spacing is
+// within 1.5x of the finest spacing (semi-coarsening of anisotropic grids).
+// Restriction sums the fine residuals of an aggregate (the FV balance of the
+// coarse cell); prolongation is bilinear/trilinear in the cell centres with a
+// ghost value mirrored through the wall (odd for zero Dirichlet, even for zero
+// Neumann).  Smoothing is red-black Gauss-Seidel; the coarsest level is
+// solved exactly with a dense inverse per preconditioner shift.
+#include "lt_internal.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace lt {
+
+static constexpr int kBlock = 256;
+static constexpr int kMaxCoarseDense = 512;
+
+int DevBuf::reserve(size_t n) {
+    if (n <= bytes) return 0;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    if (hipMalloc(&p, n) != hipSuccess) {
+        p = nullptr;
+        set_last_error("hipMalloc failed");
+        return LT_ENOMEM;
+    }
+    bytes = n;
+    return 0;
+}
+void DevBuf::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+LevelView<double> Level::v64() const {
+    const double* b = c64.as<double>();
+    return {n[0], n[1], n[2], N, b, b + N, b + 2 * (size_t)N, b + 3 * (size_t)N, b + 4 * (size_t)N};
+}
+LevelView<float> Level::v32() const {
+    const float* b = c32.as<float>();
+    return {n[0], n[1], n[2], N, b, b + N, b + 2 * (size_t)N, b + 3 * (size_t)N, b + 4 * (size_t)N};
+}
+
+// ------------------------------------------------------------------ helpers
+template <typename T> struct cpx {
+    T re, im;
+};
+template <typename T> __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> __device__ __forceinline__ cpx<T> cdiv(cpx<T> a, cpx<T> b) {
+    T d = b.re * b.re + b.im * b.im;
+    return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+
+// Off-diagonal sum  sum_nbr T x_nbr  at cell i = (x, y, z) of plane pair (re, im).
+template <typename T>
+__device__ __forceinline__ cpx<T> offsum(const LevelView<T>& L, const T* xr, const T* xi, int i, int x,
+                                         int y, int z) {
+    cpx<T> s = {0, 0};
+    if (x + 1 < L.nx) { T t = L.Tx[i]; s.re += t * xr[i + 1]; s.im += t * xi[i + 1]; }
+    if (x > 0) { T t = L.Tx[i - 1]; s.re += t * xr[i - 1]; s.im += t * xi[i - 1]; }
+    const int sy = L.nx;
+    if (y + 1 < L.ny) { T t = L.Ty[i]; s.re += t * xr[i + sy]; s.im += t * xi[i + sy]; }
+    if (y > 0) { T t = L.Ty[i - sy]; s.re += t * xr[i - sy]; s.im += t * xi[i - sy]; }
+    const int sz = L.nx * L.ny;
+    if (z + 1 < L.nz) { T t = L.Tz[i]; s.re += t * xr[i + sz]; s.im += t * xi[i + sz]; }
+    if (z > 0) { T t = L.Tz[i - sz]; s.re += t * xr[i - sz]; s.im += t * xi[i - sz]; }
+    return s;
+}
+
+// ------------------------------------------------------------------ assembly
+// Fine-level coefficients from kappa and S.  out = [Tx, Ty, Tz, D(unused here), m],
+// walls = [Wx, Wy, Wz] (wall transmissibility per axis, summed over both walls).
+__global__ void k_fine_assemble(const double* __restrict__ kappa, const double* __restrict__ S, int nx,
+                                int ny, int nz, int ndim, double hx, double hy, double hz, int4 bclo,
+                                int4 bchi, double* __restrict__ out, double* __restrict__ walls) {
+    const int N = nx * ny * nz;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
+    double V = hx * hy * hz;
+    double h[3] = {hx, hy, hz};
+    int n[3] = {nx, ny, nz};
+    int c[3] = {x, y, z};
+    int stride[3] = {1, nx, nx * ny};
+    int lo[3] = {bclo.x, bclo.y, bclo.z};
+    int hi[3] = {bchi.x, bchi.y, bchi.z};
+    double ki = kappa[i];
+    for (int a = 0; a < 3; ++a) {
+        double T = 0.0, W = 0.0;
+        if (a < ndim) {
+            double area = V / h[a];
+            if (c[a] + 1 < n[a]) {
+                double kj = kappa[i + stride[a]];
+                T = 2.0 * ki * kj / (ki + kj) * area / h[a];
+            }
+            if (c[a] == 0 && lo[a] == LT_BC_DIRICHLET0) W += 2.0 * ki * area / h[a];
+            if (c[a] == n[a] - 1 && hi[a] == LT_BC_DIRICHLET0) W += 2.0 * ki * area / h[a];
+        }
+        out[(size_t)a * N + i] = T;
+        walls[(size_t)a * N + i] = W;
+    }
+    out[(size_t)4 * N + i] = S[i] * V;
+}
+
+// Aggregate a fine level into a coarse one (see the file comment).
+__global__ void k_coarsen(const double* __restrict__ fc, const double* __restrict__ fw, int fnx, int fny,
+                          int fnz, int cnx, int cny, int cnz, int cox, int coy, int coz,
+                          double* __restrict__ cc, double* __restrict__ cw) {
+    const int Nc = cnx * cny * cnz;
+    const int Nf = fnx * fny * fnz;
+    int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= Nc) return;
+    int X = I % cnx, Y = (I / cnx) % cny, Z = I / (cnx * cny);
+    int co[3] = {cox, coy, coz};
+    int C[3] = {X, Y, Z};
+    int k0[3], k1[3];
+    for (int a = 0; a < 3; ++a) {
+        k0[a] = co[a] ? 2 * C[a] : C[a];
+        k1[a] = co[a] ? 2 * C[a] + 1 : C[a];
+    }
+    double Tsum[3] = {0, 0, 0}, Wsum[3] = {0, 0, 0}, msum = 0.0;
+    for (int z = k0[2]; z <= k1[2]; ++z)
+        for (int y = k0[1]; y <= k1[1]; ++y)
+            for (int x = k0[0]; x <= k1[0]; ++x) {
+                int f = x + fnx * (y + fny * z);
+                int fc3[3] = {x, y, z};
+                msum += fc[(size_t)4 * Nf + f];
+                for (int a = 0; a < 3; ++a) {
+                    Wsum[a] += fw[(size_t)a * Nf + f];
+                    // only children on the +a interface of the aggregate carry the coarse face
+                    if (fc3[a] == k1[a]) Tsum[a] += fc[(size_t)a * Nf + f];
+                }
+            }
+    for (int a = 0; a < 3; ++a) {
+        double fa = co[a] ? 0.5 : 1.0;
+        cc[(size_t)a * Nc + I] = fa * Tsum[a];
+        cw[(size_t)a * Nc + I] = fa * Wsum[a];
+    }
+    cc[(size_t)4 * Nc + I] = msum;
+}
+
+// D_i = sum_a (W_a[i] + T_a[i] + T_a[i - e_a]).
+__global__ void k_finish_diag(double* __restrict__ c, const double* __restrict__ w, int nx, int ny, int nz) {
+    const int N = nx * ny * nz;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
+    double d = w[i] + w[(size_t)N + i] + w[(size_t)2 * N + i];
+    d += c[i] + (x > 0 ? c[i - 1] : 0.0);
+    d += c[(size_t)N + i] + (y > 0 ? c[(size_t)N + i - nx] : 0.0);
+    d += c[(size_t)2 * N + i] + (z > 0 ? c[(size_t)2 * N + i - nx * ny] : 0.0);
+    c[(size_t)3 * N + i] = d;
+}
+
+template <typename S, typename D>
+__global__ void k_convert(const S* __restrict__ in, D* __restrict__ out, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (D)in[i];
+}
+
+template <typename S, typename D>
+int convert_vectors(hipStream_t st, const S* in, D* out, size_t count) {
+    if (count == 0) return 0;
+    k_convert<S, D><<<(unsigned)((count + kBlock - 1) / kBlock), kBlock, 0, st>>>(in, out, count);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+template int convert_vectors<double, float>(hipStream_t, const double*, float*, size_t);
+template int convert_vectors<float, double>(hipStream_t, const float*, double*, size_t);
+template int convert_vectors<double, double>(hipStream_t, const double*, double*, size_t);
+
+// ------------------------------------------------------------------ smoothing and transfers
+// y = (K + tau M) x for R vectors [R][2][N].
+template <typename T>
+__global__ void k_apply(LevelView<T> L, T tr, T ti, const T* __restrict__ x, T* __restrict__ y,
+                        const int* __restrict__ active) {
+    int r = blockIdx.y;
+    if (active && !active[r]) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.N) return;
+    const size_t N = L.N;
+    const T* xr = x + 2 * N * r;
+    const T* xi = xr + N;
+    int X = i % L.nx, Y = (i / L.nx) % L.ny, Z = i / (L.nx * L.ny);
+    cpx<T> off = offsum(L, xr, xi, i, X, Y, Z);
+    cpx<T> d = {L.D[i] + tr * L.m[i], ti * L.m[i]};
+    cpx<T> xv = {xr[i], xi[i]};
+    cpx<T> dx = cmul(d, xv);
+    y[2 * N * r + i] = dx.re - off.re;
+    y[2 * N * r + N + i] = dx.im - off.im;
+}
+
+// One colour of red-black Gauss-Seidel (colour = parity of x + y + z).
+template <typename T>
+__global__ void k_gs_color(LevelView<T> L, T tr, T ti, int color, T* __restrict__ x,
+                           const T* __restrict__ b, const int* __restrict__ active) {
+    int r = blockIdx.y;
+    if (active && !active[r]) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.N) return;
+    int X = i % L.nx, Y = (i / L.nx) % L.ny, Z = i / (L.nx * L.ny);
+    if (((X + Y + Z) & 1) != color) return;
+    const size_t N = L.N;
+    T* xr = x + 2 * N * r;
+    T* xi = xr + N;
+    const T* br = b + 2 * N * r;
+    cpx<T> off = offsum(L, xr, xi, i, X, Y, Z);
+    cpx<T> num = {br[i] + off.re, br[i + N] + off.im};
+    cpx<T> d = {L.D[i] + tr * L.m[i], ti * L.m[i]};
+    cpx<T> v = cdiv(num, d);
+    xr[i] = v.re;
+    xi[i] = v.im;
+}
+
+// Coarse right-hand side = sum over the aggregate of the fine residual b - A x;
+// the coarse iterate is cleared.
+template <typename T>
+__global__ void k_resid_restrict(LevelView<T> F, int cnx, int cny, int cnz, int cox, int coy, int coz,
+                                 T tr, T ti, const T* __restrict__ xf, const T* __restrict__ bf,
+                                 T* __restrict__ bc, T* __restrict__ xc, const int* __restrict__ active) {
+    int r = blockIdx.y;
+    if (active && !active[r]) return;
+    const int Nc = cnx * cny * cnz;
+    int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= Nc) return;
+    int Xc = I % cnx, Yc = (I / cnx) % cny, Zc = I / (cnx * cny);
+    const size_t N = F.N;
+    const T* xr = xf + 2 * N * r;
+    const T* xi = xr + N;
+    const T* br = bf + 2 * N * r;
+    const T* bi = br + N;
+    int x0 = cox ? 2 * Xc : Xc, x1 = cox ? 2 * Xc + 1 : Xc;
+    int y0 = coy ? 2 * Yc : Yc, y1 = coy ? 2 * Yc + 1 : Yc;
+    int z0 = coz ? 2 * Zc : Zc, z1 = coz ? 2 * Zc + 1 : Zc;
+    cpx<T> acc = {0, 0};
+    for (int z = z0; z <= z1; ++z)
+        for (int y = y0; y <= y1; ++y)
+            for (int x = x0; x <= x1; ++x) {
+                int i = x + F.nx * (y + F.ny * z);
+                cpx<T> off = offsum(F, xr, xi, i, x, y, z);
+                cpx<T> d = {F.D[i] + tr * F.m[i], ti * F.m[i]};
+                cpx<T> ax = cmul(d, cpx<T>{xr[i], xi[i]});
+                acc.re += br[i] - (ax.re - off.re);
+                acc.im += bi[i] - (ax.im - off.im);
+            }
+    const size_t M = Nc;
+    bc[2 * M * r + I] = acc.re;
+    bc[2 * M * r + M + I] = acc.im;
+    xc[2 * M * r + I] = 0;
+    xc[2 * M * r + M + I] = 0;
+}
+
+// x_fine += P e_coarse with cell-centred linear interpolation per halved axis.
+template <typename T>
+__global__ void k_prolong(int fnx, int fny, int fnz, int cnx, int cny, int cnz, int cox, int coy, int coz,
+                          T glox, T ghix, T gloy, T ghiy, T gloz, T ghiz, const T* __restrict__ ec,
+                          T* __restrict__ xf, const int* __restrict__ active) {
+    int r = blockIdx.y;
+    if (active && !active[r]) return;
+    const int Nf = fnx * fny * fnz;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Nf) return;
+    int x = i % fnx, y = (i / fnx) % fny, z = i / (fnx * fny);
+    // per axis: up to two coarse indices and weights
+    int ia[3][2];
+    T wa[3][2];
+    int na[3];
+    const int c3[3] = {x, y, z};
+    const int co[3] = {cox, coy, coz};
+    const int cn[3] = {cnx, cny, cnz};
+    const T glo[3] = {glox, gloy, gloz};
+    const T ghi[3] = {ghix, ghiy, ghiz};
+    for (int a = 0; a < 3; ++a) {
+        if (!co[a]) {
+            ia[a][0] = c3[a];
+            wa[a][0] = 1;
+            na[a] = 1;
+            continue;
+        }
+        int I = c3[a] >> 1;
+        int J = (c3[a] & 1) ? I + 1 : I - 1;
+        if (J < 0) {
+            ia[a][0] = I;
+            wa[a][0] = T(0.75) + T(0.25) * glo[a];
+            na[a] = 1;
+        } else if (J >= cn[a]) {
+            ia[a][0] = I;
+            wa[a][0] = T(0.75) + T(0.25) * ghi[a];
+            na[a] = 1;
+        } else {
+            ia[a][0] = I;
+            wa[a][0] = T(0.75);
+            ia[a][1] = J;
+            wa[a][1] = T(0.25);
+            na[a] = 2;
+        }
+    }
+    const size_t Mc = (size_t)cnx * cny * cnz;
+    const T* er = ec + 2 * Mc * r;
+    const T* ei = er + Mc;
+    cpx<T> acc = {0, 0};
+    for (int c = 0; c < na[2]; ++c)
+        for (int b = 0; b < na[1]; ++b)
+            for (int a = 0; a < na[0]; ++a) {
+                T w = wa[0][a] * wa[1][b] * wa[2][c];
+                size_t J = ia[0][a] + (size_t)cnx * (ia[1][b] + (size_t)cny * ia[2][c]);
+                acc.re += w * er[J];
+                acc.im += w * ei[J];
+            }
+    const size_t Nfs = Nf;
+    xf[2 * Nfs * r + i] += acc.re;
+    xf[2 * Nfs * r + Nfs + i] += acc.im;
+}
+
+// x = Ainv b on the coarsest level (Ainv interleaved complex, row-major).
+template <typename T>
+__global__ void k_coarse_solve(int Nc, const T* __restrict__ inv, const T* __restrict__ b, T* __restrict__ x,
+                               const int* __restrict__ active) {
+    int r = blockIdx.y;
+    if (active && !active[r]) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Nc) return;
+    const T* br = b + (size_t)2 * Nc * r;
+    const T* bi = br + Nc;
+    cpx<T> acc = {0, 0};
+    const T* row = inv + (size_t)2 * Nc * i;
+    for (int j = 0; j < Nc; ++j) {
+        cpx<T> a = {row[2 * j], row[2 * j + 1]};
+        cpx<T> v = {br[j], bi[j]};
+        cpx<T> p = cmul(a, v);
+        acc.re += p.re;
+        acc.im += p.im;
+    }
+    x[(size_t)2 * Nc * r + i] = acc.re;
+    x[(size_t)2 * Nc * r + Nc + i] = acc.im;
+}
+
+template <typename T>
+__global__ void k_zero(T* __restrict__ x, size_t per, const int* __restrict__ active) {
+    int r = blockIdx.y;
+    if (active && !active[r]) return;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < per) x[per * r + i] = 0;
+}
+
+// ------------------------------------------------------------------ host side
+static inline unsigned nblk(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+int mg_build(lt_handle* h, const double* kappa, const double* S) {
+    const lt_grid& g = h->grid;
+    hipStream_t st = h->stream;
+    std::vector<Level>& lv = h->levels;
+    lv.clear();
+    Level f;
+    for (int a = 0; a < 3; ++a) {
+        f.n[a] = g.n[a];
+        f.h[a] = g.h[a];
+        f.coarsened_from_fine[a] = 0;
+    }
+    f.N = g.n[0] * g.n[1] * g.n[2];
+    lv.push_back(f);
+    DevBuf walls_f, walls_c;
+    LT_TRY(lv[0].c64.reserve(sizeof(double) * 5 * (size_t)f.N));
+    LT_TRY(walls_f.reserve(sizeof(double) * 3 * (size_t)f.N));
+    int4 lo = {h->bc.face[0], h->bc.face[2], h->bc.face[4], 0};
+    int4 hi = {h->bc.face[1], h->bc.face[3], h->bc.face[5], 0};
+    k_fine_assemble<<<nblk(f.N), kBlock, 0, st>>>(kappa, S, f.n[0], f.n[1], f.n[2], g.ndim, f.h[0], f.h[1],
+                                                   f.h[2], lo, hi, lv[0].c64.as<double>(),
+                                                   walls_f.as<double>());
+    LT_HIP(hipGetLastError());
+    k_finish_diag<<<nblk(f.N), kBlock, 0, st>>>(lv[0].c64.as<double>(), walls_f.as<double>(), f.n[0], f.n[1],
+                                                f.n[2]);
+    LT_HIP(hipGetLastError());
+    // coarsen while useful
+    while (true) {
+        const Level& L = lv.back();
+        if (L.N <= 64) break;
+        double hmin = 1e300;
+        for (int a = 0; a < g.ndim; ++a) hmin = std::min(hmin, L.h[a]);
+        int co[3] = {0, 0, 0};
+        bool any = false;
+        for (int a = 0; a < g.ndim; ++a) {
+            if (L.n[a] % 2 == 0 && L.n[a] > 2 && L.h[a] < 1.5 * hmin) {
+                co[a] = 1;
+                any = true;
+            }
+        }
+        if (!any) break;
+        Level C;
+        for (int a = 0; a < 3; ++a) {
+            C.n[a] = co[a] ? L.n[a] / 2 : L.n[a];
+            C.h[a] = co[a] ? L.h[a] * 2 : L.h[a];
+            C.coarsened_from_fine[a] = co[a];
+        }
+        C.N = C.n[0] * C.n[1] * C.n[2];
+        LT_TRY(C.c64.reserve(sizeof(double) * 5 * (size_t)C.N));
+        LT_TRY(walls_c.reserve(sizeof(double) * 3 * (size_t)C.N));
+        k_coarsen<<<nblk(C.N), kBlock, 0, st>>>(L.c64.as<double>(), walls_f.as<double>(), L.n[0], L.n[1],
+                                                L.n[2], C.n[0], C.n[1], C.n[2], co[0], co[1], co[2],
+                                                C.c64.as<double>(), walls_c.as<double>());
+        LT_HIP(hipGetLastError());
+        k_finish_diag<<<nblk(C.N), kBlock, 0, st>>>(C.c64.as<double>(), walls_c.as<double>(), C.n[0], C.n[1],
+                                                    C.n[2]);
+        LT_HIP(hipGetLastError());
+        std::swap(walls_f, walls_c);
+        lv.push_back(C);
+        // keep the DevBufs owned by the vector (C's buffer pointer moved by copy)
+        lv.back().c64 = C.c64;
+        C.c64.p = nullptr;
+    }
+    for (Level& L : lv) {
+        LT_TRY(L.c32.reserve(sizeof(float) * 5 * (size_t)L.N));
+        LT_TRY(convert_vectors<double, float>(st, L.c64.as<double>(), L.c32.as<float>(), 5 * (size_t)L.N));
+    }
+    // coarsest coefficients on the host for the dense coarse solve
+    const Level& Lc = lv.back();
+    h->coarse_host.resize(5 * (size_t)Lc.N);
+    LT_HIP(hipMemcpyAsync(h->coarse_host.data(), Lc.c64.p, sizeof(double) * 5 * Lc.N, hipMemcpyDeviceToHost, st));
+    LT_HIP(hipStreamSynchronize(st));
+    walls_f.release();
+    walls_c.release();
+    return 0;
+}
+
+const CoarseInverse* mg_coarse_inverse(lt_handle* h, cdouble tau, int* rc) {
+    *rc = 0;
+    for (const CoarseInverse& c : h->coarse_cache)
+        if (c.tau == tau) return &c;
+    const Level& L = h->levels.back();
+    const int n = L.N;
+    if (n > kMaxCoarseDense) { *rc = 0; return nullptr; }
+    const double* c = h->coarse_host.data();
+    const double *Tx = c, *Ty = c + n, *Tz = c + 2 * n, *D = c + 3 * n, *m = c + 4 * n;
+    std::vector<cdouble> A((size_t)n * n, 0.0), inv;
+    const int nx = L.n[0], ny = L.n[1];
+    for (int i = 0; i < n; ++i) {
+        int x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
+        A[(size_t)i * n + i] = D[i] + tau * m[i];
+        if (x + 1 < L.n[0]) A[(size_t)i * n + i + 1] = -Tx[i];
+        if (x > 0) A[(size_t)i * n + i - 1] = -Tx[i - 1];
+        if (y + 1 < L.n[1]) A[(size_t)i * n + i + nx] = -Ty[i];
+        if (y > 0) A[(size_t)i * n + i - nx] = -Ty[i - nx];
+        if (z + 1 < L.n[2]) A[(size_t)i * n + i + nx * ny] = -Tz[i];
+        if (z > 0) A[(size_t)i * n + i - nx * ny] = -Tz[i - nx * ny];
+    }
+    if (dense_inverse(n, A, inv) != 0) { *rc = LT_EINVAL; set_last_error("singular coarse operator"); return nullptr; }
+    if (h->coarse_cache.size() >= 16) {
+        h->coarse_cache.front().inv64.release();
+        h->coarse_cache.front().inv32.release();
+        h->coarse_cache.erase(h->coarse_cache.begin());
+    }
+    h->coarse_cache.emplace_back();
+    CoarseInverse& ci = h->coarse_cache.back();
+    ci.tau = tau;
+    std::vector<double> d64(2 * (size_t)n * n);
+    std::vector<float> d32(2 * (size_t)n * n);
+    for (size_t k = 0; k < (size_t)n * n; ++k) {
+        d64[2 * k] = inv[k].real();
+        d64[2 * k + 1] = inv[k].imag();
+        d32[2 * k] = (float)inv[k].real();
+        d32[2 * k + 1] = (float)inv[k].imag();
+    }
+    if ((*rc = ci.inv64.reserve(d64.size() * sizeof(double))) < 0) return nullptr;
+    if ((*rc = ci.inv32.reserve(d32.size() * sizeof(float))) < 0) return nullptr;
+    if (hipMemcpyAsync(ci.inv64.p, d64.data(), d64.size() * sizeof(double), hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(ci.inv32.p, d32.data(), d32.size() * sizeof(float), hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+        *rc = LT_EHIP;
+        set_last_error("coarse inverse upload failed");
+        return nullptr;
+    }
+    return &ci;
+}
+
+template <typename T> static LevelView<T> view(const Level& L);
+template <> LevelView<double> view<double>(const Level& L) { return L.v64(); }
+template <> LevelView<float> view<float>(const Level& L) { return L.v32(); }
+template <typename T> static const T* inv_ptr(const CoarseInverse* c);
+template <> const double* inv_ptr<double>(const CoarseInverse* c) { return c->inv64.as<double>(); }
+template <> const float* inv_ptr<float>(const CoarseInverse* c) { return c->inv32.as<float>(); }
+
+template <typename T>
+int apply_operator(lt_handle* h, int level, cdouble tau, const T* x, T* y, int R, const int* active) {
+    const Level& L = h->levels[level];
+    dim3 grid(nblk(L.N), R);
+    k_apply<T><<<grid, kBlock, 0, h->stream>>>(view<T>(L), (T)tau.real(), (T)tau.imag(), x, y, active);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+template int apply_operator<double>(lt_handle*, int, cdouble, const double*, double*, int, const int*);
+template int apply_operator<float>(lt_handle*, int, cdouble, const float*, float*, int, const int*);
+
+template <typename T>
+int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* active, T* x0, const T* b0) {
+    hipStream_t st = h->stream;
+    const int nl = (int)h->levels.size();
+    const T tr = (T)tau.real(), ti = (T)tau.imag();
+    // per-level work vectors x_l, b_l for l >= 1
+    std::vector<T*> xs(nl), bs(nl);
+    xs[0] = x0;
+    bs[0] = const_cast<T*>(b0);
+    int rc = 0;
+    for (int l = 1; l < nl; ++l) {
+        const size_t per = 2 * (size_t)h->levels[l].N;
+        std::string nx = std::string(sizeof(T) == 8 ? "mgx64_" : "mgx32_") + std::to_string(l);
+        std::string nb = std::string(sizeof(T) == 8 ? "mgb64_" : "mgb32_") + std::to_string(l);
+        xs[l] = wsp<T>(h, nx.c_str(), per * R, &rc);
+        if (!xs[l]) return rc;
+        bs[l] = wsp<T>(h, nb.c_str(), per * R, &rc);
+        if (!bs[l]) return rc;
+    }
+    const CoarseInverse* ci = mg_coarse_inverse(h, tau, &rc);
+    if (rc < 0) return rc;
+    {
+        const size_t per = 2 * (size_t)h->levels[0].N;
+        k_zero<T><<<dim3(nblk(per), R), kBlock, 0, st>>>(x0, per, active);
+        LT_HIP(hipGetLastError());
+    }
+    const T gsign[2] = {T(-1), T(1)};  // Dirichlet, Neumann ghost parity
+    auto g = [&](int face) { return gsign[h->bc.face[face] == LT_BC_NEUMANN0 ? 1 : 0]; };
+    // down
+    for (int l = 0; l < nl - 1; ++l) {
+        const Level& L = h->levels[l];
+        const Level& C = h->levels[l + 1];
+        LevelView<T> v = view<T>(L);
+        dim3 grid(nblk(L.N), R);
+        for (int s = 0; s < nu1; ++s)
+            for (int c = 0; c < 2; ++c) k_gs_color<T><<<grid, kBlock, 0, st>>>(v, tr, ti, c, xs[l], bs[l], active);
+        k_resid_restrict<T><<<dim3(nblk(C.N), R), kBlock, 0, st>>>(
+            v, C.n[0], C.n[1], C.n[2], C.coarsened_from_fine[0], C.coarsened_from_fine[1],
+            C.coarsened_from_fine[2], tr, ti, xs[l], bs[l], bs[l + 1], xs[l + 1], active);
+        LT_HIP(hipGetLastError());
+    }
+    // coarsest
+    {
+        const Level& L = h->levels[nl - 1];
+        dim3 grid(nblk(L.N), R);
+        if (ci) {
+            k_coarse_solve<T><<<grid, kBlock, 0, st>>>(L.N, inv_ptr<T>(ci), bs[nl - 1], xs[nl - 1], active);
+        } else {
+            LevelView<T> v = view<T>(L);
+            if (nl == 1) {
+                const size_t per = 2 * (size_t)L.N;
+                k_zero<T><<<dim3(nblk(per), R), kBlock, 0, st>>>(xs[0], per, active);
+            }
+            for (int s = 0; s < 64; ++s)
+                for (int c = 0; c < 2; ++c)
+                    k_gs_color<T><<<grid, kBlock, 0, st>>>(v, tr, ti, c, xs[nl - 1], bs[nl - 1], active);
+        }
+        LT_HIP(hipGetLastError());
+    }
+    // up
+    for (int l = nl - 2; l >= 0; --l) {
+        const Level& L = h->levels[l];
+        const Level& C = h->levels[l + 1];
+        dim3 grid(nblk(L.N), R);
+        k_prolong<T><<<grid, kBlock, 0, st>>>(L.n[0], L.n[1], L.n[2], C.n[0], C.n[1], C.n[2],
+                                              C.coarsened_from_fine[0], C.coarsened_from_fine[1],
+                                              C.coarsened_from_fine[2], g(0), g(1), g(2), g(3), g(4), g(5),
+                                              xs[l + 1], xs[l], active);
+        LevelView<T> v = view<T>(L);
+        for (int s = 0; s < nu2; ++s)
+            for (int c = 1; c >= 0; --c) k_gs_color<T><<<grid, kBlock, 0, st>>>(v, tr, ti, c, xs[l], bs[l], active);
+        LT_HIP(hipGetLastError());
+    }
+    return 0;
+}
+template int mg_vcycle<double>(lt_handle*, cdouble, int, int, int, const int*, double*, const double*);
+template int mg_vcycle<float>(lt_handle*, cdouble, int, int, int, const int*, float*, const float*);
+
+}  // namespace lt
