@@ -1,0 +1,147 @@
+"""Throughput of the Laplace-transform shifted-system solver on one MI355X.
+
+One step = one lt_solve of the 256x256 workload: ln(kappa) a Gaussian
+random field (exponential covariance, variance 1, correlation length 0.1),
+S = 1e-5, zero-Dirichlet walls, 8 pumping wells and 16 observation wells on
+a 4x4 pattern, 10 log-spaced times in [0.01, 10] diffusion times, a 20-node
+Talbot contour (10 solved shifts per time, 100 per right-hand side), one
+preconditioner shift; heads at every receiver and time, with the FP64 true
+residual of all 800 (rhs, shift) systems.  Inputs are resident on the GPU
+before the timed region.  Metric: shifted solves per second (rhs x shift
+pairs / wall time), counted only when the heads agree with the CPU oracle
+to 1e-5 relative.
+
+Two variants are timed: FP64 throughout, and the FP32 V-cycle inside the
+FP64 outer solve ("mixed", the headline value).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "C2"
+HBM_PEAK_GBS = 8000.0
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--tol-fp64", type=float, default=1e-8)
+    ap.add_argument("--tol-mixed", type=float, default=1e-7)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-times", type=int, default=4)
+    return ap.parse_args()
+
+
+def _run_variant(lt, h, p, opts, steps, warmup):
+    import torch
+    phi = torch.empty((len(p.sources), len(p.receivers), len(p.times)), dtype=torch.float64, device="cuda")
+    st = None
+    for _ in range(warmup):
+        _, st = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, opts, phi_out=phi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, st = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, opts, phi_out=phi)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return dt, st, phi.cpu().numpy()
+
+
+def _cpu_baseline(p, ntimes):
+    """The oracle as it stands, on a bounded sample: every source, the first
+    `ntimes` measurement times (ntimes * N_z/2 factorisations)."""
+    from oracle.heads import heads
+    workers = min(os.cpu_count() or 1, 16)
+    t0 = time.perf_counter()
+    ref = heads(p.n, p.h, p.kappa, p.S, p.sources, p.receivers, p.times[:ntimes], p.nz_contour,
+                q=p.q, bc=p.bc, workers=workers, ndim=p.ndim)
+    dt = time.perf_counter() - t0
+    pairs = len(p.sources) * ntimes * (p.nz_contour // 2)
+    return ref, {"value": pairs / dt, "unit": "shifted solves/s", "cores": workers, "kind": "oracle",
+                 "sample": f"{len(p.sources)} sources x first {ntimes} times x {p.nz_contour // 2} shifts "
+                           f"= {pairs} pairs of the same 256x256 workload, SuperLU per shift "
+                           f"({dt:.1f} s)"}
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import workloads as wl
+    p = wl.make_problem(WORKLOAD)
+    # the CPU oracle runs first, before this process touches the GPU
+    cpu, ref = None, None
+    nt = args.cpu_sample_times
+    if not args.no_cpu_baseline:
+        ref, cpu = _cpu_baseline(p, nt)
+        print(f"[bench] oracle sample: {cpu['value']:.2f} solves/s on {cpu['cores']} cores", file=sys.stderr,
+              flush=True)
+
+    import torch
+    from paper_1409_2556_amd import binding as lt
+
+    torch.cuda.set_device(0)
+    kap = torch.tensor(p.kappa, dtype=torch.float64, device="cuda")
+    S = torch.tensor(p.S, dtype=torch.float64, device="cuda")
+    h = lt.lt_setup(p.ndim, p.n, p.h, kap, S)
+    pairs = len(p.sources) * len(p.times) * (p.nz_contour // 2)
+    res = {}
+    for name, prec, tol in (("fp64", lt.LT_PREC_FP64, args.tol_fp64), ("mixed", lt.LT_PREC_MIXED, args.tol_mixed)):
+        opts = lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau)
+        dt, st, phi = _run_variant(lt, h, p, opts, args.steps, args.warmup)
+        res[name] = dict(dt=dt, st=st, phi=phi, tol=tol)
+        print(f"[bench] {name}: {dt * 1e3:.2f} ms/step, {pairs / dt:.0f} solves/s, iters {st['iters_max']}, "
+              f"vcycles {st['vcycles']}, true residual {st['true_relres_max']:.2e}", file=sys.stderr, flush=True)
+    errs = {}
+    if ref is not None:
+        for name in res:
+            got = res[name]["phi"][:, :, :nt]
+            e = np.linalg.norm((got - ref).reshape(len(p.sources), -1), axis=1) / \
+                np.linalg.norm(ref.reshape(len(p.sources), -1), axis=1)
+            errs[name] = float(e.max())
+        print(f"[bench] rel head err vs oracle sample: {errs}", file=sys.stderr, flush=True)
+    head = res["mixed"]
+    valid = (errs.get("mixed", 0.0) <= 1e-5)
+    out = {
+        "metric": "shifted solves/sec (RHS x shift, rel head err 1e-5)",
+        "value": pairs / head["dt"] if valid else 0.0,
+        "unit": "shifted solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["dt"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "2D 256x256 GRF aquifer (var 1, corr 0.1), 8 sources x 16 receivers, "
+                               "10 times, 20-node Talbot, 1 tau, GMG V(2,2) RB-GS",
+                   "rhs": len(p.sources), "shifts_per_rhs": len(p.times) * (p.nz_contour // 2),
+                   "pairs": pairs, "tol": head["tol"], "precision": "FP32 V-cycle, FP64 outer",
+                   "iters": head["st"]["iters_max"], "vcycles": head["st"]["vcycles"]},
+        "variants": {
+            name: {"solves_per_s": pairs / r["dt"], "ms_per_step": r["dt"] * 1e3, "tol": r["tol"],
+                   "iters": r["st"]["iters_max"], "vcycles": r["st"]["vcycles"],
+                   "true_relres_weighted_max": r["st"]["true_relres_max"],
+                   "rel_head_err_vs_oracle": errs.get(name)} for name, r in res.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
+if __name__ == "__main__":
+    main()

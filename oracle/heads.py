@@ -43,13 +43,24 @@ def _job(args):
     return X
 
 
+def _init_worker(K, m, rhs, Br):
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+    _G.update(K=K, m=m, rhs=rhs, Br=Br)
+
+
 def _map_shifts(K, m, rhs, shifts, take, Br=None, workers=1):
     _G.update(K=K, m=m, rhs=rhs, Br=Br)
     jobs = [(z, take) for z in shifts]
     if workers <= 1 or len(jobs) <= 1:
         return [_job(j) for j in jobs]
-    ctx = mp.get_context("fork")
-    with ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+    # fresh interpreters (spawn): safe even when the parent has initialised a GPU runtime
+    ctx = mp.get_context("spawn")
+    with ProcessPoolExecutor(max_workers=min(workers, len(jobs)), mp_context=ctx,
+                             initializer=_init_worker, initargs=(K, m, rhs, Br)) as ex:
         return list(ex.map(_job, jobs))
 
 
