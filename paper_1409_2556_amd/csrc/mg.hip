@@ -12,6 +12,7 @@
 // Neumann).  Smoothing is red-black Gauss-Seidel; the coarsest level is
 // solved exactly with a dense inverse per preconditioner shift.
 #include "lt_internal.h"
+#include "mg_fused.h"
 
 #include <algorithm>
 #include <cmath>
@@ -507,73 +508,122 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
     hipStream_t st = h->stream;
     const int nl = (int)h->levels.size();
     const T tr = (T)tau.real(), ti = (T)tau.imag();
-    // per-level work vectors x_l, b_l for l >= 1
-    std::vector<T*> xs(nl), bs(nl);
-    xs[0] = x0;
-    bs[0] = const_cast<T*>(b0);
     int rc = 0;
-    for (int l = 1; l < nl; ++l) {
-        const size_t per = 2 * (size_t)h->levels[l].N;
-        std::string nx = std::string(sizeof(T) == 8 ? "mgx64_" : "mgx32_") + std::to_string(l);
-        std::string nb = std::string(sizeof(T) == 8 ? "mgb64_" : "mgb32_") + std::to_string(l);
-        xs[l] = wsp<T>(h, nx.c_str(), per * R, &rc);
-        if (!xs[l]) return rc;
-        bs[l] = wsp<T>(h, nb.c_str(), per * R, &rc);
-        if (!bs[l]) return rc;
-    }
     const CoarseInverse* ci = mg_coarse_inverse(h, tau, &rc);
     if (rc < 0) return rc;
-    {
-        const size_t per = 2 * (size_t)h->levels[0].N;
-        k_zero<T><<<dim3(nblk(per), R), kBlock, 0, st>>>(x0, per, active);
-        LT_HIP(hipGetLastError());
+    // first level small enough for the single-workgroup kernel
+    int lc = nl;
+    for (int l = 0; l < nl; ++l)
+        if (h->levels[l].N <= kCoarseBlockCells) { lc = l; break; }
+    const bool cb = lc < nl && nl - lc <= kMaxCBLevels;
+    if (!cb) lc = nl - 1;  // generic path down to the coarsest level
+    const bool fused2d = h->grid.ndim == 2 && nu1 >= 1 && nu1 <= 3 && nu2 >= 1 && nu2 <= 3;
+    const char* tag = sizeof(T) == 8 ? "64_" : "32_";
+    std::vector<T*> xpre(nl + 1, nullptr), xpost(nl + 1, nullptr), bs(nl + 1, nullptr);
+    bs[0] = const_cast<T*>(b0);
+    for (int l = 0; l <= lc && l < nl; ++l) {
+        const size_t per = 2 * (size_t)h->levels[l].N * R;
+        if (l > 0) {
+            bs[l] = wsp<T>(h, (std::string("mgb") + tag + std::to_string(l)).c_str(), per, &rc);
+            if (!bs[l]) return rc;
+        }
+        if (l == 0 && (!fused2d || lc == 0)) {
+            xpre[0] = x0;
+        } else {
+            xpre[l] = wsp<T>(h, (std::string("mgx") + tag + std::to_string(l)).c_str(), per, &rc);
+            if (!xpre[l]) return rc;
+        }
+        xpost[l] = fused2d && l > 0 && l < lc
+                       ? wsp<T>(h, (std::string("mgy") + tag + std::to_string(l)).c_str(), per, &rc)
+                       : xpre[l];
+        if (!xpost[l]) return rc;
     }
+    xpost[0] = x0;
     const T gsign[2] = {T(-1), T(1)};  // Dirichlet, Neumann ghost parity
     auto g = [&](int face) { return gsign[h->bc.face[face] == LT_BC_NEUMANN0 ? 1 : 0]; };
-    // down
-    for (int l = 0; l < nl - 1; ++l) {
+    // ---- down
+    for (int l = 0; l < lc; ++l) {
         const Level& L = h->levels[l];
         const Level& C = h->levels[l + 1];
         LevelView<T> v = view<T>(L);
-        dim3 grid(nblk(L.N), R);
-        for (int s = 0; s < nu1; ++s)
-            for (int c = 0; c < 2; ++c) k_gs_color<T><<<grid, kBlock, 0, st>>>(v, tr, ti, c, xs[l], bs[l], active);
-        k_resid_restrict<T><<<dim3(nblk(C.N), R), kBlock, 0, st>>>(
-            v, C.n[0], C.n[1], C.n[2], C.coarsened_from_fine[0], C.coarsened_from_fine[1],
-            C.coarsened_from_fine[2], tr, ti, xs[l], bs[l], bs[l + 1], xs[l + 1], active);
-        LT_HIP(hipGetLastError());
+        if (fused2d) {
+            LT_TRY(launch_pre2d<T>(st, v, tr, ti, nu1, bs[l], xpre[l], C.n[0], C.n[1], C.coarsened_from_fine[0],
+                                   C.coarsened_from_fine[1], bs[l + 1], R, active));
+        } else {
+            const size_t per = 2 * (size_t)L.N;
+            dim3 grid(nblk(L.N), R);
+            if (l == 0) k_zero<T><<<dim3(nblk(per), R), kBlock, 0, st>>>(xpre[0], per, active);
+            for (int s = 0; s < nu1; ++s)
+                for (int c = 0; c < 2; ++c)
+                    k_gs_color<T><<<grid, kBlock, 0, st>>>(v, tr, ti, c, xpre[l], bs[l], active);
+            k_resid_restrict<T><<<dim3(nblk(C.N), R), kBlock, 0, st>>>(
+                v, C.n[0], C.n[1], C.n[2], C.coarsened_from_fine[0], C.coarsened_from_fine[1],
+                C.coarsened_from_fine[2], tr, ti, xpre[l], bs[l], bs[l + 1], xpre[l + 1], active);
+            LT_HIP(hipGetLastError());
+        }
     }
-    // coarsest
-    {
-        const Level& L = h->levels[nl - 1];
+    // ---- coarse levels
+    if (cb) {
+        CBMeta<T> M{};
+        M.nl = nl - lc;
+        int off = 0;
+        for (int l = lc; l < nl; ++l) {
+            const Level& L = h->levels[l];
+            LevelView<T> v = view<T>(L);
+            CBLevel<T>& c = M.L[l - lc];
+            c.nx = L.n[0]; c.ny = L.n[1]; c.nz = L.n[2]; c.N = L.N;
+            c.cox = L.coarsened_from_fine[0]; c.coy = L.coarsened_from_fine[1]; c.coz = L.coarsened_from_fine[2];
+            c.off = off;
+            off += L.N;
+            c.Tx = v.Tx; c.Ty = v.Ty; c.Tz = v.Tz; c.D = v.D; c.m = v.m;
+        }
+        for (int f = 0; f < 6; ++f) M.ghost[f] = g(f);
+        M.nu1 = nu1;
+        M.nu2 = nu2;
+        M.inv = ci ? inv_ptr<T>(ci) : nullptr;
+        M.coarse_sweeps = 64;
+        T* out = (lc == 0) ? x0 : xpre[lc];
+        LT_TRY(launch_coarse_block<T>(st, M, tr, ti, bs[lc], out, R, active));
+        xpost[lc] = out;
+    } else {
+        const Level& L = h->levels[lc];
         dim3 grid(nblk(L.N), R);
+        if (lc == 0) {
+            const size_t per = 2 * (size_t)L.N;
+            k_zero<T><<<dim3(nblk(per), R), kBlock, 0, st>>>(x0, per, active);
+        }
         if (ci) {
-            k_coarse_solve<T><<<grid, kBlock, 0, st>>>(L.N, inv_ptr<T>(ci), bs[nl - 1], xs[nl - 1], active);
+            k_coarse_solve<T><<<grid, kBlock, 0, st>>>(L.N, inv_ptr<T>(ci), bs[lc], xpre[lc], active);
         } else {
             LevelView<T> v = view<T>(L);
-            if (nl == 1) {
-                const size_t per = 2 * (size_t)L.N;
-                k_zero<T><<<dim3(nblk(per), R), kBlock, 0, st>>>(xs[0], per, active);
-            }
             for (int s = 0; s < 64; ++s)
                 for (int c = 0; c < 2; ++c)
-                    k_gs_color<T><<<grid, kBlock, 0, st>>>(v, tr, ti, c, xs[nl - 1], bs[nl - 1], active);
+                    k_gs_color<T><<<grid, kBlock, 0, st>>>(v, tr, ti, c, xpre[lc], bs[lc], active);
         }
         LT_HIP(hipGetLastError());
+        xpost[lc] = xpre[lc];
     }
-    // up
-    for (int l = nl - 2; l >= 0; --l) {
+    // ---- up
+    for (int l = lc - 1; l >= 0; --l) {
         const Level& L = h->levels[l];
         const Level& C = h->levels[l + 1];
-        dim3 grid(nblk(L.N), R);
-        k_prolong<T><<<grid, kBlock, 0, st>>>(L.n[0], L.n[1], L.n[2], C.n[0], C.n[1], C.n[2],
-                                              C.coarsened_from_fine[0], C.coarsened_from_fine[1],
-                                              C.coarsened_from_fine[2], g(0), g(1), g(2), g(3), g(4), g(5),
-                                              xs[l + 1], xs[l], active);
         LevelView<T> v = view<T>(L);
-        for (int s = 0; s < nu2; ++s)
-            for (int c = 1; c >= 0; --c) k_gs_color<T><<<grid, kBlock, 0, st>>>(v, tr, ti, c, xs[l], bs[l], active);
-        LT_HIP(hipGetLastError());
+        if (fused2d) {
+            T4 gh = {(double)g(0), (double)g(1), (double)g(2), (double)g(3)};
+            LT_TRY(launch_post2d<T>(st, v, tr, ti, nu2, bs[l], xpre[l], xpost[l + 1], C.n[0], C.n[1],
+                                    C.coarsened_from_fine[0], C.coarsened_from_fine[1], gh, xpost[l], R, active));
+        } else {
+            dim3 grid(nblk(L.N), R);
+            k_prolong<T><<<grid, kBlock, 0, st>>>(L.n[0], L.n[1], L.n[2], C.n[0], C.n[1], C.n[2],
+                                                  C.coarsened_from_fine[0], C.coarsened_from_fine[1],
+                                                  C.coarsened_from_fine[2], g(0), g(1), g(2), g(3), g(4), g(5),
+                                                  xpost[l + 1], xpre[l], active);
+            for (int s = 0; s < nu2; ++s)
+                for (int c = 1; c >= 0; --c)
+                    k_gs_color<T><<<grid, kBlock, 0, st>>>(v, tr, ti, c, xpre[l], bs[l], active);
+            LT_HIP(hipGetLastError());
+            xpost[l] = xpre[l];
+        }
     }
     return 0;
 }

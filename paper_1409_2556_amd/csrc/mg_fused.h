@@ -1,0 +1,47 @@
+// Fused multigrid kernels (mg_fused.hip).
+#pragma once
+
+#include "lt_internal.h"
+
+namespace lt {
+
+constexpr int kTileX = 32;
+constexpr int kTileY = 16;
+constexpr int kCoarseBlockCells = 1024;  // first level handled by the single-workgroup kernel
+constexpr int kMaxCBLevels = 10;
+
+struct T4 {
+    double x, y, z, w;  // ghost parity of the -x, +x, -y, +y walls
+};
+
+template <typename T> struct CBLevel {
+    int nx, ny, nz, N;
+    int cox, coy, coz;  // axes halved to make this level from the finer one
+    int off;            // cell offset of this level's vectors in LDS
+    const T* Tx;
+    const T* Ty;
+    const T* Tz;
+    const T* D;
+    const T* m;
+};
+
+template <typename T> struct CBMeta {
+    int nl;
+    CBLevel<T> L[kMaxCBLevels];
+    T ghost[6];
+    int nu1, nu2;
+    const T* inv;  // dense inverse of the coarsest level (interleaved complex) or nullptr
+    int coarse_sweeps;
+};
+
+template <typename T>
+int launch_pre2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, const T* b, T* x, int cnx, int cny,
+                 int cox, int coy, T* bc, int R, const int* active);
+template <typename T>
+int launch_post2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, const T* b, const T* xin,
+                  const T* ec, int cnx, int cny, int cox, int coy, T4 ghost, T* xout, int R, const int* active);
+template <typename T>
+int launch_coarse_block(hipStream_t st, const CBMeta<T>& M, T tr, T ti, const T* bin, T* xout, int R,
+                        const int* active);
+
+}  // namespace lt
