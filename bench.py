@@ -38,15 +38,21 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tol-fp64", type=float, default=1e-8)
     ap.add_argument("--tol-mixed", type=float, default=1e-7)
+    ap.add_argument("--relax", type=float, default=3.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-times", type=int, default=4)
     return ap.parse_args()
 
 
-def _run_variant(lt, h, p, opts, steps, warmup):
+def _run_variant(lt, h, p, opts, steps, warmup, profile=0):
+    """Warm up, then time `steps` solves.  With `profile`, the same `steps` solves
+    are run once more with the library timing every launch of the profiled
+    kernel with HIP events on its own stream and counting its algorithmic bytes
+    (kept out of the headline timing so the events do not slow it)."""
     import torch
     phi = torch.empty((len(p.sources), len(p.receivers), len(p.times)), dtype=torch.float64, device="cuda")
     st = None
+    opts.profile = 0
     for _ in range(warmup):
         _, st = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, opts, phi_out=phi)
     torch.cuda.synchronize()
@@ -55,7 +61,17 @@ def _run_variant(lt, h, p, opts, steps, warmup):
         _, st = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, opts, phi_out=phi)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
-    return dt, st, phi.cpu().numpy()
+    prof = {"launches": 0, "ms": 0.0, "bytes": 0.0}
+    if profile:
+        opts.profile = profile
+        for _ in range(steps):
+            _, stp = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, opts, phi_out=phi)
+            prof["launches"] += stp["prof_launches"]
+            prof["ms"] += stp["prof_ms"]
+            prof["bytes"] += stp["prof_bytes"]
+        torch.cuda.synchronize()
+        opts.profile = 0
+    return dt, st, phi.cpu().numpy(), prof
 
 
 def _cpu_baseline(p, ntimes):
@@ -99,9 +115,10 @@ def main():
     pairs = len(p.sources) * len(p.times) * (p.nz_contour // 2)
     res = {}
     for name, prec, tol in (("fp64", lt.LT_PREC_FP64, args.tol_fp64), ("mixed", lt.LT_PREC_MIXED, args.tol_mixed)):
-        opts = lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau)
-        dt, st, phi = _run_variant(lt, h, p, opts, args.steps, args.warmup)
-        res[name] = dict(dt=dt, st=st, phi=phi, tol=tol)
+        opts = lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau, relax=args.relax)
+        prof_kind = lt.LT_PROF_POST_FINE if name == "mixed" else 0
+        dt, st, phi, prof = _run_variant(lt, h, p, opts, args.steps, args.warmup, prof_kind)
+        res[name] = dict(dt=dt, st=st, phi=phi, tol=tol, prof=prof)
         print(f"[bench] {name}: {dt * 1e3:.2f} ms/step, {pairs / dt:.0f} solves/s, iters {st['iters_max']}, "
               f"vcycles {st['vcycles']}, true residual {st['true_relres_max']:.2e}", file=sys.stderr, flush=True)
     errs = {}
@@ -114,6 +131,18 @@ def main():
         print(f"[bench] rel head err vs oracle sample: {errs}", file=sys.stderr, flush=True)
     head = res["mixed"]
     valid = (errs.get("mixed", 0.0) <= 1e-5)
+    pr = head["prof"]
+    roofline = None
+    if pr["launches"] > 0 and pr["ms"] > 0:
+        avg_s = pr["ms"] * 1e-3 / pr["launches"]
+        bytes_per_launch = pr["bytes"] / pr["launches"]
+        achieved = bytes_per_launch / avg_s / 1e9
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "kernel": "k_post2d_refine<float,2> (fine-grid prolongation, 2 red-black sweeps, "
+                              "FP64 refinement update)",
+                    "avg_launch_us": avg_s * 1e6, "bytes_per_launch": bytes_per_launch,
+                    "launches": pr["launches"]}
     out = {
         "metric": "shifted solves/sec (RHS x shift, rel head err 1e-5)",
         "value": pairs / head["dt"] if valid else 0.0,
@@ -130,13 +159,15 @@ def main():
         "config": {"workload": "2D 256x256 GRF aquifer (var 1, corr 0.1), 8 sources x 16 receivers, "
                                "10 times, 20-node Talbot, 1 tau, GMG V(2,2) RB-GS",
                    "rhs": len(p.sources), "shifts_per_rhs": len(p.times) * (p.nz_contour // 2),
-                   "pairs": pairs, "tol": head["tol"], "precision": "FP32 V-cycle, FP64 outer",
+                   "pairs": pairs, "tol": head["tol"], "relax": args.relax,
+                   "precision": "FP32 V-cycle, FP64 outer",
                    "iters": head["st"]["iters_max"], "vcycles": head["st"]["vcycles"]},
         "variants": {
             name: {"solves_per_s": pairs / r["dt"], "ms_per_step": r["dt"] * 1e3, "tol": r["tol"],
                    "iters": r["st"]["iters_max"], "vcycles": r["st"]["vcycles"],
                    "true_relres_weighted_max": r["st"]["true_relres_max"],
                    "rel_head_err_vs_oracle": errs.get(name)} for name, r in res.items()},
+        "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

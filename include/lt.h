@@ -51,6 +51,7 @@ enum {
 
 enum { LT_BC_DIRICHLET0 = 0, LT_BC_NEUMANN0 = 1 };
 enum { LT_PREC_FP64 = 0, LT_PREC_MIXED = 1 };   /* V-cycle in FP64 or FP32   */
+enum { LT_PROF_OFF = 0, LT_PROF_PRE_FINE = 1, LT_PROF_POST_FINE = 2 };
 
 typedef struct lt_handle lt_handle;
 
@@ -104,7 +105,11 @@ typedef struct {
  *   relax      inner tolerance factor: the refinement stops when
  *              ||v - (K + tau M) u|| <= relax * tol / (worst weighted residual).
  *   true_residual  1: compute the FP64 true residual of every (rhs, shift)
- *              at exit (reported in lt_stats). */
+ *              at exit (reported in lt_stats).
+ *   profile    0: off.  LT_PROF_PRE_FINE / LT_PROF_POST_FINE: time every launch
+ *              of the fine-grid pre- / post-smoothing kernel with HIP events on
+ *              the handle's stream and count its algorithmic bytes (reported
+ *              in lt_stats.prof_*). */
 typedef struct {
     double tol;
     int maxit;
@@ -115,6 +120,7 @@ typedef struct {
     int inner_max;
     double relax;
     int true_residual;
+    int profile;
 } lt_opts;
 
 /* Statistics of the last call.  Pointer members are optional host arrays the
@@ -129,6 +135,9 @@ typedef struct {
     double seconds;              /* wall time of the call                    */
     int* iters_per_rhs;          /* [n_rhs] or NULL                          */
     double* true_relres;         /* [n_rhs][n_shifts] ||b - (K+zM)x|| / ||b|| or NULL */
+    int prof_launches;           /* profiled launches (opts.profile)          */
+    double prof_ms;              /* their summed device time, milliseconds    */
+    double prof_bytes;           /* their summed algorithmic bytes            */
 } lt_stats;
 
 void lt_opts_default(lt_opts* o);

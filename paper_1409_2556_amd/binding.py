@@ -22,6 +22,7 @@ _lib = C.CDLL(LIB_PATH)
 LT_OK, LT_EINVAL, LT_EHIP, LT_ENOMEM, LT_EUNSUPPORTED, LT_WNOTCONV = 0, -1, -2, -3, -4, 1
 LT_BC_DIRICHLET0, LT_BC_NEUMANN0 = 0, 1
 LT_PREC_FP64, LT_PREC_MIXED = 0, 1
+LT_PROF_OFF, LT_PROF_PRE_FINE, LT_PROF_POST_FINE = 0, 1, 2
 
 
 class lt_grid(C.Structure):
@@ -43,13 +44,15 @@ class lt_contour(C.Structure):
 class lt_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("precision", C.c_int), ("n_tau", C.c_int),
                 ("tau_reim", C.POINTER(C.c_double)), ("nu1", C.c_int), ("nu2", C.c_int),
-                ("inner_max", C.c_int), ("relax", C.c_double), ("true_residual", C.c_int)]
+                ("inner_max", C.c_int), ("relax", C.c_double), ("true_residual", C.c_int),
+                ("profile", C.c_int)]
 
 
 class lt_stats(C.Structure):
     _fields_ = [("n_rhs", C.c_int), ("n_shifts", C.c_int), ("iters_max", C.c_int), ("vcycles", C.c_int),
                 ("levels", C.c_int), ("true_relres_max", C.c_double), ("seconds", C.c_double),
-                ("iters_per_rhs", C.POINTER(C.c_int)), ("true_relres", C.POINTER(C.c_double))]
+                ("iters_per_rhs", C.POINTER(C.c_int)), ("true_relres", C.POINTER(C.c_double)),
+                ("prof_launches", C.c_int), ("prof_ms", C.c_double), ("prof_bytes", C.c_double)]
 
 
 _vp = C.c_void_p
@@ -187,7 +190,8 @@ def _stats(nrhs, nshift):
 def _stats_dict(st, it, tr, rc, nrhs, nshift):
     return {"rc": rc, "n_rhs": st.n_rhs, "n_shifts": st.n_shifts, "iters_max": st.iters_max,
             "vcycles": st.vcycles, "levels": st.levels, "true_relres_max": st.true_relres_max,
-            "seconds": st.seconds, "iters_per_rhs": it.copy(), "true_relres": tr.reshape(nrhs, nshift).copy()}
+            "seconds": st.seconds, "iters_per_rhs": it.copy(), "true_relres": tr.reshape(nrhs, nshift).copy(),
+            "prof_launches": st.prof_launches, "prof_ms": st.prof_ms, "prof_bytes": st.prof_bytes}
 
 
 def lt_solve(handle: Handle, sources, q, times, nz, receivers, opts: lt_opts | None = None, phi_out=None):

@@ -12,6 +12,8 @@
 // relaxation keeps it below the tolerance (inexact Krylov).  The FP64 true
 // residual of every (rhs, shift) is computed at exit.
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 
@@ -27,6 +29,31 @@ void set_last_error(const std::string& s) { g_last_error = s; }
 
 using namespace lt;
 
+namespace lt {
+
+int prof_begin(lt_handle* h, int family, unsigned long long** counter) {
+    (void)family;
+    if (h->prof_used + 2 > (int)h->prof_events.size()) {
+        for (int k = 0; k < 256; ++k) {
+            hipEvent_t e;
+            LT_HIP(hipEventCreate(&e));
+            h->prof_events.push_back(e);
+        }
+    }
+    LT_HIP(hipEventRecord(h->prof_events[h->prof_used], h->stream));
+    *counter = h->prof_counter;
+    return 0;
+}
+
+int prof_end(lt_handle* h, int family) {
+    (void)family;
+    LT_HIP(hipEventRecord(h->prof_events[h->prof_used + 1], h->stream));
+    h->prof_used += 2;
+    return 0;
+}
+
+}  // namespace lt
+
 lt_handle::~lt_handle() {
     for (Level& L : levels) {
         L.c64.release();
@@ -38,6 +65,7 @@ lt_handle::~lt_handle() {
     }
     for (auto& kv : ws) kv.second.release();
     if (pinned) (void)hipHostFree(pinned);
+    for (hipEvent_t e : prof_events) (void)hipEventDestroy(e);
 }
 
 namespace {
@@ -71,7 +99,7 @@ int upload_points(lt_handle* h, const PointsCSR& c, const char* tag, DevPoints* 
 int validate_opts(const lt_opts* o) {
     if (!o) return 0;
     if (!(o->tol > 0.0) || o->maxit < 1 || o->maxit > 2000 || o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 ||
-        o->inner_max < 1 || !(o->relax > 0.0) ||
+        o->inner_max < 1 || !(o->relax > 0.0) || o->profile < 0 || o->profile > LT_PROF_POST_FINE ||
         (o->precision != LT_PREC_FP64 && o->precision != LT_PREC_MIXED)) {
         set_last_error("invalid lt_opts");
         return LT_EINVAL;
@@ -119,9 +147,14 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     float* lo32 = nullptr;
     float* e32 = nullptr;
     double* e64 = nullptr;
+    double* rho_next = wsp<double>(h, "rho_next", R * N2, &rc);
+    if (!rho_next) return rc;
+    float* lo32_next = nullptr;
     if (mixed) {
         lo32 = wsp<float>(h, "lo32", R * N2, &rc);
         if (!lo32) return rc;
+        lo32_next = wsp<float>(h, "lo32_next", R * N2, &rc);
+        if (!lo32_next) return rc;
         e32 = wsp<float>(h, "e32", R * N2, &rc);
         if (!e32) return rc;
     } else {
@@ -138,14 +171,15 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     if (!c1 || !c2) return rc;
     const int nb = reduce_blocks(N, R);
     const int pstride = 2 * (jmax + 2);
-    double* part = wsp<double>(h, "part", (size_t)R * nb * pstride, &rc);
+    const size_t ntiles = ((size_t)h->grid.n[0] + 31) / 32 * (((size_t)h->grid.n[1] + 15) / 16) * h->grid.n[2];
+    double* part = wsp<double>(h, "part", (size_t)R * std::max((size_t)nb * pstride, ntiles), &rc);
     if (!part) return rc;
     double* small = wsp<double>(h, "small", 4 * (size_t)R, &rc);
     if (!small) return rc;
     double* scale = small;
     double* beta = small + R;
     double* worst = small + 2 * R;
-    int* ints = wsp<int>(h, "ints", 4 * (size_t)R + 4, &rc);
+    int* ints = wsp<int>(h, "ints", 4 * (size_t)R + 4, &rc);  // masks, counts, [count, steps needed]
     if (!ints) return rc;
     int* active = ints;
     int* inner_active = ints + R;
@@ -210,31 +244,73 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     const double* m = L0.m;
     int n_active = R;
     int j = 0;
+    int inner_guess = 2;
+    const bool debug = std::getenv("LT_DEBUG") != nullptr;
     out->converged = false;
     for (j = 0; j < jmax; ++j) {
         cdouble tau = plan.tau_sched[j % plan.tau_sched.size()];
         // inner refinement of u_j ~ (K + tau M)^{-1} v_j
         LT_HIP(hipMemcpyAsync(inner_active, active, R * sizeof(int), hipMemcpyDeviceToDevice, st));
+        LT_HIP(hipMemsetAsync(count + 1, 0, sizeof(int), st));
         double* uj = U + (size_t)j * N2;
         const double* vj = Q + (size_t)j * N2;
         if (mixed)
             LT_TRY(launch_inner_init<float>(st, N, R, qstride, vj, uj, ustride, rho, lo32, active));
         else
             LT_TRY(launch_inner_init<double>(st, N, R, qstride, vj, uj, ustride, rho, (double*)nullptr, active));
-        for (int step = 0; step < o.inner_max; ++step) {
-            if (mixed) {
-                LT_TRY(mg_vcycle<float>(h, tau, o.nu1, o.nu2, R, inner_active, e32, lo32));
-                LT_TRY(launch_inner_update<float>(st, L0, tau, R, e32, uj, ustride, rho, lo32, part, inner_active));
-            } else {
-                LT_TRY(mg_vcycle<double>(h, tau, o.nu1, o.nu2, R, inner_active, e64, rho));
-                LT_TRY(launch_inner_update<double>(st, L0, tau, R, e64, uj, ustride, rho, (double*)nullptr, part,
-                                                   inner_active));
+        // The refinement steps expected from the previous outer iteration are
+        // enqueued without waiting; finished right-hand sides are masked off on
+        // the device, and the host checks only after that batch.
+        int step = 0;
+        while (step < o.inner_max) {
+            const int batch = step == 0 ? std::min(inner_guess, o.inner_max) : 1;
+            for (int b2 = 0; b2 < batch; ++b2, ++step) {
+                // rho (FP64) and its FP32 copy are double-buffered so that halo loads of the
+                // next V-cycle input never race with the fused update
+                int nparts = -1;
+                if (mixed) {
+                    RefineArgs ra{uj, ustride, rho, rho, lo32_next, part, &nparts};
+                    LT_TRY(mg_vcycle<float>(h, tau, o.nu1, o.nu2, R, inner_active, e32, lo32, &ra));
+                    if (nparts < 0) {
+                        LT_TRY(launch_inner_update<float>(st, L0, tau, R, e32, uj, ustride, rho, lo32_next, part,
+                                                          inner_active));
+                        nparts = reduce_blocks(N, R);
+                    }
+                    std::swap(lo32, lo32_next);
+                } else {
+                    RefineArgs ra{uj, ustride, rho, rho_next, nullptr, part, &nparts};
+                    LT_TRY(mg_vcycle<double>(h, tau, o.nu1, o.nu2, R, inner_active, e64, rho, &ra));
+                    if (nparts < 0) {
+                        LT_TRY(launch_inner_update<double>(st, L0, tau, R, e64, uj, ustride, rho, (double*)nullptr,
+                                                           part, inner_active));
+                        nparts = reduce_blocks(N, R);
+                    } else {
+                        std::swap(rho, rho_next);
+                    }
+                }
+                LT_TRY(launch_inner_finalize(st, nparts, R, part, active, worst, o.relax * o.tol, o.tol, step,
+                                             o.inner_max, inner_active, vcyc, count));
             }
-            LT_TRY(launch_inner_finalize(st, N, R, part, active, worst, o.relax * o.tol, o.tol, step, o.inner_max,
-                                         inner_active, vcyc, count));
-            LT_HIP(hipMemcpyAsync(hflag, count, sizeof(int), hipMemcpyDeviceToHost, st));
+            LT_HIP(hipMemcpyAsync(hflag, count, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+            // convergence flags as left by the previous outer iteration's least squares
+            LT_HIP(hipMemcpyAsync(hact, active, R * sizeof(int), hipMemcpyDeviceToHost, st));
             LT_HIP(hipStreamSynchronize(st));
             if (*hflag == 0) break;
+        }
+        if (debug) {
+            std::vector<int> vc(R);
+            LT_HIP(hipMemcpy(vc.data(), vcyc, R * sizeof(int), hipMemcpyDeviceToHost));
+            std::fprintf(stderr, "[lt] j=%d tau=(%.3g,%.3g) inner launched=%d needed=%d guess=%d vcycles/rhs:", j,
+                         tau.real(), tau.imag(), step, hflag[1], inner_guess);
+            for (int r = 0; r < R; ++r) std::fprintf(stderr, " %d", vc[r]);
+            std::fprintf(stderr, "\n");
+        }
+        inner_guess = std::max(1, hflag[1]);
+        n_active = 0;
+        for (int r = 0; r < R; ++r) n_active += hact[r];
+        if (n_active == 0) {
+            out->converged = true;
+            break;
         }
         // Arnoldi: v_{j+1} from M u_j by classical Gram-Schmidt with reorthogonalisation
         LT_TRY(launch_cgs2(st, N, R, j, m, U, ustride, Q, qstride, H, hstride, hrstride, part, pstride, c1, c2,
@@ -242,14 +318,13 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
         if (np > 0) LT_TRY(launch_gather(st, R, N, np, rec->off, rec->cell, rec->wt, U, ustride, j, G, jmax, active));
         LT_TRY(launch_ls_update(st, R, Ks, j, tau, zs, omega, o.tol, H, hstride, hrstride, beta, ls, active, mcols,
                                 worst, conv));
+    }
+    if (!out->converged) {
         LT_HIP(hipMemcpyAsync(hact, active, R * sizeof(int), hipMemcpyDeviceToHost, st));
         LT_HIP(hipStreamSynchronize(st));
         n_active = 0;
         for (int r = 0; r < R; ++r) n_active += hact[r];
-        if (n_active == 0) {
-            out->converged = true;
-            break;
-        }
+        out->converged = n_active == 0;
     }
     LT_TRY(launch_backsolve(st, R, Ks, mcols, ls, Y, jmax));
     std::vector<int> hm(R), hv(R);
@@ -300,6 +375,40 @@ int true_residuals(lt_handle* h, const KrylovOut& k, const Plan& plan, lt_stats*
         stats->true_relres_max = mx;
         if (stats->true_relres) std::memcpy(stats->true_relres, ht.data(), ht.size() * sizeof(double));
     }
+    return 0;
+}
+
+int prof_start(lt_handle* h, int target) {
+    h->prof_target = target;
+    h->prof_used = 0;
+    if (!target) return 0;
+    int rc = 0;
+    h->prof_counter = wsp<unsigned long long>(h, "prof_counter", 1, &rc);
+    if (!h->prof_counter) return rc;
+    LT_HIP(hipMemsetAsync(h->prof_counter, 0, sizeof(unsigned long long), h->stream));
+    return 0;
+}
+
+int prof_finish(lt_handle* h, lt_stats* s) {
+    if (!h->prof_target) {
+        if (s) { s->prof_launches = 0; s->prof_ms = 0; s->prof_bytes = 0; }
+        return 0;
+    }
+    LT_HIP(hipStreamSynchronize(h->stream));
+    double ms = 0;
+    for (int k = 0; k + 1 < h->prof_used; k += 2) {
+        float e = 0;
+        LT_HIP(hipEventElapsedTime(&e, h->prof_events[k], h->prof_events[k + 1]));
+        ms += e;
+    }
+    unsigned long long bytes = 0;
+    LT_HIP(hipMemcpy(&bytes, h->prof_counter, sizeof(bytes), hipMemcpyDeviceToHost));
+    if (s) {
+        s->prof_launches = h->prof_used / 2;
+        s->prof_ms = ms;
+        s->prof_bytes = (double)bytes;
+    }
+    h->prof_target = 0;
     return 0;
 }
 
@@ -488,12 +597,14 @@ int lt_solve(lt_handle* h, const lt_points* sources, double q, const double* tim
     LT_TRY(launch_scatter_points(h->stream, R, h->N, ds.off, ds.cell, ds.wt, b));
     KrylovOut k;
     k.b = b;
+    LT_TRY(prof_start(h, o.profile));
     LT_TRY(run_krylov(h, plan, o, R, &dr, &k));
     LT_TRY(launch_heads(h->stream, R, dr.n, ntimes, plan.nk, k.wq, k.G, k.Y, k.mcols, k.jmax, phi_out));
     if (o.true_residual) LT_TRY(true_residuals(h, k, plan, stats));
     LT_HIP(hipStreamSynchronize(h->stream));
     if (stats && stats->iters_per_rhs)
         LT_HIP(hipMemcpy(stats->iters_per_rhs, k.mcols, R * sizeof(int), hipMemcpyDeviceToHost));
+    LT_TRY(prof_finish(h, stats));
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     fill_stats(stats, k, (int)h->levels.size(), secs);
     return k.converged ? LT_OK : LT_WNOTCONV;

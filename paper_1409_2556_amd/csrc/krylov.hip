@@ -156,17 +156,23 @@ __global__ void k_inner_update(LevelView<double> L, double tr, double ti, const 
 }
 
 // inner_active[r] = active[r] && ||rho_r|| > eta_r && step + 1 < inner_max; counts vcycles.
+// count[0] = right-hand sides still refining; count[1] = step + 1 if any right-hand
+// side was refined in this step (the number of steps this outer iteration needed).
 __global__ void k_inner_finalize(int R, int nb, const double* __restrict__ part, const int* __restrict__ active,
                                  const double* __restrict__ worst, double relax_tol, double tol, int step,
                                  int inner_max, int* __restrict__ inner_active, int* __restrict__ vcycles,
                                  int* __restrict__ count) {
     int r = threadIdx.x;
-    __shared__ int cnt;
-    if (threadIdx.x == 0) cnt = 0;
+    __shared__ int cnt, any;
+    if (threadIdx.x == 0) {
+        cnt = 0;
+        any = 0;
+    }
     __syncthreads();
     for (; r < R; r += blockDim.x) {
         int a = inner_active[r];
         if (!a) continue;
+        any = 1;
         double s = 0;
         for (int q = 0; q < nb; ++q) s += part[(size_t)r * nb + q];
         double eta = relax_tol / fmax(worst[r], tol);
@@ -177,7 +183,10 @@ __global__ void k_inner_finalize(int R, int nb, const double* __restrict__ part,
         if (again) atomicAdd(&cnt, 1);
     }
     __syncthreads();
-    if (threadIdx.x == 0) *count = cnt;
+    if (threadIdx.x == 0) {
+        count[0] = cnt;
+        if (any) count[1] = step + 1;
+    }
 }
 
 // ---------------------------------------------------------------- classical Gram-Schmidt (twice)
@@ -641,10 +650,9 @@ template int launch_inner_update<double>(hipStream_t, LevelView<double>, cdouble
 template int launch_inner_update<float>(hipStream_t, LevelView<double>, cdouble, int, const float*, double*,
                                         size_t, double*, float*, double*, const int*);
 
-int launch_inner_finalize(hipStream_t st, int N, int R, const double* part, const int* active, const double* worst,
+int launch_inner_finalize(hipStream_t st, int nb, int R, const double* part, const int* active, const double* worst,
                           double relax_tol, double tol, int step, int inner_max, int* inner_active, int* vcycles,
                           int* count) {
-    int nb = reduce_blocks(N, R);
     k_inner_finalize<<<1, 1024, 0, st>>>(R, nb, part, active, worst, relax_tol, tol, step, inner_max, inner_active,
                                          vcycles, count);
     LT_HIP(hipGetLastError());

@@ -87,10 +87,19 @@ struct lt_handle {
     // workspaces (grow-only, owned by the handle)
     std::map<std::string, lt::DevBuf> ws;
     void* pinned = nullptr;  // small pinned host area for flags
+    // profiling of one kernel family (opts.profile): event pairs and a byte counter
+    int prof_target = 0;
+    std::vector<hipEvent_t> prof_events;
+    int prof_used = 0;
+    unsigned long long* prof_counter = nullptr;  // device
     ~lt_handle();
 };
 
 namespace lt {
+
+// profiling helpers (api.hip)
+int prof_begin(lt_handle* h, int family, unsigned long long** counter);
+int prof_end(lt_handle* h, int family);
 
 // workspace helper
 template <typename T> T* wsp(lt_handle* h, const char* name, size_t count, int* rc) {
@@ -126,9 +135,22 @@ int mg_build(lt_handle* h, const double* kappa, const double* S);
 const CoarseInverse* mg_coarse_inverse(lt_handle* h, cdouble tau, int* rc);
 // One V-cycle on level 0 for R complex vectors: b0, x0 in the level-0 work arrays of
 // precision T (x0 is overwritten).  active: device [R] mask or nullptr.
+// Optional fusion of the fine-level post-smoother with one refinement step of the
+// preconditioner solve (2D fused path only): u += e, rho_out = rho_in - (K + tau M) e,
+// lo = (T) rho_out, part = per-tile ||rho_out||^2.  When applied, *nparts is set to
+// the number of partial sums per right-hand side and x0 is not written.
+struct RefineArgs {
+    double* u;
+    size_t ustride;
+    const double* rho_in;
+    double* rho_out;
+    void* lo;
+    double* part;
+    int* nparts;
+};
 template <typename T>
 int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* active,
-              T* x0, const T* b0);
+              T* x0, const T* b0, const RefineArgs* refine = nullptr);
 template <typename T>
 int apply_operator(lt_handle* h, int level, cdouble tau, const T* x, T* y, int R, const int* active);
 template <typename S, typename D>

@@ -504,7 +504,8 @@ template int apply_operator<double>(lt_handle*, int, cdouble, const double*, dou
 template int apply_operator<float>(lt_handle*, int, cdouble, const float*, float*, int, const int*);
 
 template <typename T>
-int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* active, T* x0, const T* b0) {
+int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* active, T* x0, const T* b0,
+              const RefineArgs* refine) {
     hipStream_t st = h->stream;
     const int nl = (int)h->levels.size();
     const T tr = (T)tau.real(), ti = (T)tau.imag();
@@ -547,8 +548,12 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
         const Level& C = h->levels[l + 1];
         LevelView<T> v = view<T>(L);
         if (fused2d) {
+            unsigned long long* pc = nullptr;
+            const bool prof = l == 0 && h->prof_target == LT_PROF_PRE_FINE;
+            if (prof) LT_TRY(prof_begin(h, LT_PROF_PRE_FINE, &pc));
             LT_TRY(launch_pre2d<T>(st, v, tr, ti, nu1, bs[l], xpre[l], C.n[0], C.n[1], C.coarsened_from_fine[0],
-                                   C.coarsened_from_fine[1], bs[l + 1], R, active));
+                                   C.coarsened_from_fine[1], bs[l + 1], R, active, pc));
+            if (prof) LT_TRY(prof_end(h, LT_PROF_PRE_FINE));
         } else {
             const size_t per = 2 * (size_t)L.N;
             dim3 grid(nblk(L.N), R);
@@ -610,8 +615,22 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
         LevelView<T> v = view<T>(L);
         if (fused2d) {
             T4 gh = {(double)g(0), (double)g(1), (double)g(2), (double)g(3)};
-            LT_TRY(launch_post2d<T>(st, v, tr, ti, nu2, bs[l], xpre[l], xpost[l + 1], C.n[0], C.n[1],
-                                    C.coarsened_from_fine[0], C.coarsened_from_fine[1], gh, xpost[l], R, active));
+            unsigned long long* pc = nullptr;
+            const bool prof = l == 0 && h->prof_target == LT_PROF_POST_FINE;
+            if (prof) LT_TRY(prof_begin(h, LT_PROF_POST_FINE, &pc));
+            if (l == 0 && refine) {
+                LT_TRY(launch_post2d_refine<T>(st, v, h->levels[0].v64(), tr, ti, tau.real(), tau.imag(), nu2, bs[0],
+                                               xpre[0], xpost[1], C.n[0], C.n[1], C.coarsened_from_fine[0],
+                                               C.coarsened_from_fine[1], gh, refine->u, refine->ustride,
+                                               refine->rho_in, refine->rho_out, static_cast<T*>(refine->lo),
+                                               refine->part, R, active, pc));
+                *refine->nparts = ((L.n[0] + kTileX - 1) / kTileX) * ((L.n[1] + kTileY - 1) / kTileY);
+            } else {
+                LT_TRY(launch_post2d<T>(st, v, tr, ti, nu2, bs[l], xpre[l], xpost[l + 1], C.n[0], C.n[1],
+                                        C.coarsened_from_fine[0], C.coarsened_from_fine[1], gh, xpost[l], R, active,
+                                        pc));
+            }
+            if (prof) LT_TRY(prof_end(h, LT_PROF_POST_FINE));
         } else {
             dim3 grid(nblk(L.N), R);
             k_prolong<T><<<grid, kBlock, 0, st>>>(L.n[0], L.n[1], L.n[2], C.n[0], C.n[1], C.n[2],
@@ -627,7 +646,8 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
     }
     return 0;
 }
-template int mg_vcycle<double>(lt_handle*, cdouble, int, int, int, const int*, double*, const double*);
-template int mg_vcycle<float>(lt_handle*, cdouble, int, int, int, const int*, float*, const float*);
+template int mg_vcycle<double>(lt_handle*, cdouble, int, int, int, const int*, double*, const double*,
+                               const RefineArgs*);
+template int mg_vcycle<float>(lt_handle*, cdouble, int, int, int, const int*, float*, const float*, const RefineArgs*);
 
 }  // namespace lt

@@ -8,7 +8,7 @@ namespace lt {
 constexpr int kTileX = 32;
 constexpr int kTileY = 16;
 constexpr int kCoarseBlockCells = 1024;  // first level handled by the single-workgroup kernel
-constexpr int kMaxCBLevels = 10;
+constexpr int kMaxCBLevels = 5;
 
 struct T4 {
     double x, y, z, w;  // ghost parity of the -x, +x, -y, +y walls
@@ -36,10 +36,16 @@ template <typename T> struct CBMeta {
 
 template <typename T>
 int launch_pre2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, const T* b, T* x, int cnx, int cny,
-                 int cox, int coy, T* bc, int R, const int* active);
+                 int cox, int coy, T* bc, int R, const int* active, unsigned long long* prof);
 template <typename T>
 int launch_post2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, const T* b, const T* xin,
-                  const T* ec, int cnx, int cny, int cox, int coy, T4 ghost, T* xout, int R, const int* active);
+                  const T* ec, int cnx, int cny, int cox, int coy, T4 ghost, T* xout, int R, const int* active,
+                  unsigned long long* prof);
+template <typename T>
+int launch_post2d_refine(hipStream_t st, const LevelView<T>& L, const LevelView<double>& L64, T tr, T ti,
+                         double tr64, double ti64, int nu, const T* b, const T* xin, const T* ec, int cnx, int cny,
+                         int cox, int coy, T4 ghost, double* u, size_t ustride, const double* rho_in,
+                         double* rho_out, T* lo, double* part, int R, const int* active, unsigned long long* prof);
 template <typename T>
 int launch_coarse_block(hipStream_t st, const CBMeta<T>& M, T tr, T ti, const T* bin, T* xout, int R,
                         const int* active);

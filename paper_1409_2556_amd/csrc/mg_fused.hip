@@ -92,7 +92,8 @@ __device__ __forceinline__ void tile_load_common(Tile2D<T, H>& s, const LevelVie
 template <typename T, int NU>
 __global__ __launch_bounds__(256) void k_pre2d(LevelView<T> L, T tr, T ti, const T* __restrict__ b,
                                                T* __restrict__ x, int cnx, int cny, int cox, int coy,
-                                               T* __restrict__ bc, const int* __restrict__ active) {
+                                               T* __restrict__ bc, const int* __restrict__ active,
+                                               unsigned long long* __restrict__ prof, int Rtot) {
     constexpr int H = 2 * NU + 1;
     constexpr int EX = Tile2D<T, H>::EX, EY = Tile2D<T, H>::EY;
     __shared__ Tile2D<T, H> s;
@@ -143,6 +144,16 @@ __global__ __launch_bounds__(256) void k_pre2d(LevelView<T> L, T tr, T ti, const
         bc[2 * Nc * r + I] = ar;
         bc[2 * Nc * r + Nc + I] = ai;
     }
+    if (prof && threadIdx.x == 0) {
+        // algorithmic bytes of this block: b in, x out (complex), the coefficient
+        // arrays Tx, Ty, D, m shared by the Rtot right-hand sides, coarse rhs out
+        const int nxi = min(kTileX, L.nx - blockIdx.x * kTileX), nyi = min(kTileY, L.ny - blockIdx.y * kTileY);
+        const int ncx = min(ctx, cnx - (int)blockIdx.x * ctx), ncy = min(cty, cny - (int)blockIdx.y * cty);
+        const double cell = 4.0 * sizeof(T) + 4.0 * sizeof(T) / Rtot;
+        const unsigned long long bytes =
+            (unsigned long long)(nxi * nyi * cell + (double)ncx * ncy * 2.0 * sizeof(T));
+        atomicAdd(prof, bytes);
+    }
 }
 
 // Cell-centred linear interpolation weights of one halved axis (ghost mirrored through the wall).
@@ -175,7 +186,8 @@ template <typename T, int NU>
 __global__ __launch_bounds__(256) void k_post2d(LevelView<T> L, T tr, T ti, const T* __restrict__ b,
                                                 const T* __restrict__ xin, const T* __restrict__ ec, int cnx,
                                                 int cny, int cox, int coy, T4 ghost, T* __restrict__ xout,
-                                                const int* __restrict__ active) {
+                                                const int* __restrict__ active, unsigned long long* __restrict__ prof,
+                                                int Rtot) {
     constexpr int H = 2 * NU;
     constexpr int EX = Tile2D<T, H>::EX, EY = Tile2D<T, H>::EY;
     __shared__ Tile2D<T, H> s;
@@ -226,163 +238,328 @@ __global__ __launch_bounds__(256) void k_post2d(LevelView<T> L, T tr, T ti, cons
             oxi[i] = s.xi[ly][lx];
         }
     }
-}
-
-// ------------------------------------------------------------------ coarse levels in one workgroup
-template <typename T>
-__device__ __forceinline__ void cb_gs(const CBLevel<T>& L, T tr, T ti, T* xr, T* xi, const T* br, const T* bi,
-                                      int color) {
-    const int sy = L.nx, sz = L.nx * L.ny;
-    for (int i = threadIdx.x; i < L.N; i += blockDim.x) {
-        const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / sz;
-        if (((x + y + z) & 1) != color) continue;
-        T ore = 0, oim = 0;
-        if (x + 1 < L.nx) { T t = L.Tx[i]; ore += t * xr[i + 1]; oim += t * xi[i + 1]; }
-        if (x > 0) { T t = L.Tx[i - 1]; ore += t * xr[i - 1]; oim += t * xi[i - 1]; }
-        if (y + 1 < L.ny) { T t = L.Ty[i]; ore += t * xr[i + sy]; oim += t * xi[i + sy]; }
-        if (y > 0) { T t = L.Ty[i - sy]; ore += t * xr[i - sy]; oim += t * xi[i - sy]; }
-        if (z + 1 < L.nz) { T t = L.Tz[i]; ore += t * xr[i + sz]; oim += t * xi[i + sz]; }
-        if (z > 0) { T t = L.Tz[i - sz]; ore += t * xr[i - sz]; oim += t * xi[i - sz]; }
-        T nr = br[i] + ore, ni = bi[i] + oim;
-        T dr = L.D[i] + tr * L.m[i], di = ti * L.m[i];
-        T dd = dr * dr + di * di;
-        xr[i] = (nr * dr + ni * di) / dd;
-        xi[i] = (ni * dr - nr * di) / dd;
+    if (prof && threadIdx.x == 0) {
+        // algorithmic bytes: x in, b in, x out (complex), shared coefficients, and the
+        // coarse correction (one coarse cell per aggregate of the fine cells)
+        const int nxi = min(kTileX, L.nx - blockIdx.x * kTileX), nyi = min(kTileY, L.ny - blockIdx.y * kTileY);
+        const double agg = (double)(1 << (cox + coy));
+        const double cell = 6.0 * sizeof(T) + 4.0 * sizeof(T) / Rtot + 2.0 * sizeof(T) / agg;
+        atomicAdd(prof, (unsigned long long)(nxi * nyi * cell));
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void cb_restrict(const CBLevel<T>& F, const CBLevel<T>& C, T tr, T ti, const T* xr,
-                                            const T* xi, const T* br, const T* bi, T* cbr, T* cbi, T* cxr,
-                                            T* cxi) {
-    const int sy = F.nx, sz = F.nx * F.ny;
-    for (int I = threadIdx.x; I < C.N; I += blockDim.x) {
-        const int X = I % C.nx, Y = (I / C.nx) % C.ny, Z = I / (C.nx * C.ny);
-        T ar = 0, ai = 0;
-        for (int z = Z << C.coz; z <= (Z << C.coz) + C.coz; ++z)
-            for (int y = Y << C.coy; y <= (Y << C.coy) + C.coy; ++y)
-                for (int x = X << C.cox; x <= (X << C.cox) + C.cox; ++x) {
-                    const int i = x + F.nx * (y + F.ny * z);
-                    T ore = 0, oim = 0;
-                    if (x + 1 < F.nx) { T t = F.Tx[i]; ore += t * xr[i + 1]; oim += t * xi[i + 1]; }
-                    if (x > 0) { T t = F.Tx[i - 1]; ore += t * xr[i - 1]; oim += t * xi[i - 1]; }
-                    if (y + 1 < F.ny) { T t = F.Ty[i]; ore += t * xr[i + sy]; oim += t * xi[i + sy]; }
-                    if (y > 0) { T t = F.Ty[i - sy]; ore += t * xr[i - sy]; oim += t * xi[i - sy]; }
-                    if (z + 1 < F.nz) { T t = F.Tz[i]; ore += t * xr[i + sz]; oim += t * xi[i + sz]; }
-                    if (z > 0) { T t = F.Tz[i - sz]; ore += t * xr[i - sz]; oim += t * xi[i - sz]; }
-                    T dr = F.D[i] + tr * F.m[i], di = ti * F.m[i];
-                    ar += br[i] - (dr * xr[i] - di * xi[i] - ore);
-                    ai += bi[i] - (dr * xi[i] + di * xr[i] - oim);
-                }
-        cbr[I] = ar;
-        cbi[I] = ai;
-        cxr[I] = 0;
-        cxi[I] = 0;
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void cb_prolong(const CBLevel<T>& F, const CBLevel<T>& C, const T* g, T* xr, T* xi,
-                                           const T* er, const T* ei) {
-    for (int i = threadIdx.x; i < F.N; i += blockDim.x) {
-        const int x = i % F.nx, y = (i / F.nx) % F.ny, z = i / (F.nx * F.ny);
-        int ix[2], iy[2], iz[2];
-        T wx[2], wy[2], wz[2];
-        const int nxp = prolong_axis<T>(x, C.nx, C.cox, g[0], g[1], ix, wx);
-        const int nyp = prolong_axis<T>(y, C.ny, C.coy, g[2], g[3], iy, wy);
-        const int nzp = prolong_axis<T>(z, C.nz, C.coz, g[4], g[5], iz, wz);
-        T pr = 0, pi = 0;
-        for (int c = 0; c < nzp; ++c)
-            for (int b = 0; b < nyp; ++b)
-                for (int a = 0; a < nxp; ++a) {
-                    const T w = wx[a] * wy[b] * wz[c];
-                    const int J = ix[a] + C.nx * (iy[b] + C.ny * iz[c]);
+// Fine-level post-smoothing fused with one step of the FP64 iterative
+// refinement of the preconditioner solve: with e the V-cycle output,
+//   u += e,  rho_out = rho_in - (K + tau M) e  (FP64 coefficients),
+//   lo = (T) rho_out,  part[r][block] = ||rho_out||^2 over the block.
+// One more halo ring than the plain post-smoother keeps e exact next to the
+// interior, so A e is exact there.  rho_in and the input b of the tile may be
+// the same buffer; rho_out and lo must not alias anything read here.
+template <typename T, int NU>
+__global__ __launch_bounds__(256) void k_post2d_refine(LevelView<T> L, LevelView<double> L64, T tr, T ti,
+                                                       double tr64, double ti64, const T* __restrict__ b,
+                                                       const T* __restrict__ xin, const T* __restrict__ ec,
+                                                       int cnx, int cny, int cox, int coy, T4 ghost,
+                                                       double* __restrict__ u, size_t ustride,
+                                                       const double* rho_in, double* rho_out,
+                                                       T* __restrict__ lo, double* __restrict__ part,
+                                                       const int* __restrict__ active,
+                                                       unsigned long long* __restrict__ prof, int Rtot) {
+    constexpr int H = 2 * NU + 1;
+    constexpr int EX = Tile2D<T, H>::EX, EY = Tile2D<T, H>::EY;
+    __shared__ Tile2D<T, H> s;
+    __shared__ double red[4];
+    const int r = blockIdx.z;
+    if (active && !active[r]) return;
+    const size_t N = L.N;
+    const size_t Nc = (size_t)cnx * cny;
+    const int gx0 = blockIdx.x * kTileX - H, gy0 = blockIdx.y * kTileY - H;
+    tile_load_common<T, H>(s, L, tr, ti, b + 2 * N * r, b + 2 * N * r + N, gx0, gy0);
+    const T* xr = xin + 2 * N * r;
+    const T* xi = xr + N;
+    const T* er = ec + 2 * Nc * r;
+    const T* ei = er + Nc;
+    for (int c = threadIdx.x; c < EX * EY; c += blockDim.x) {
+        const int lx = c % EX, ly = c / EX;
+        const int gx = gx0 + lx, gy = gy0 + ly;
+        T vr = 0, vi = 0;
+        if (gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
+            const int i = gx + L.nx * gy;
+            int ix[2], iy[2];
+            T wx[2], wy[2];
+            const int nxp = prolong_axis<T>(gx, cnx, cox, (T)ghost.x, (T)ghost.y, ix, wx);
+            const int nyp = prolong_axis<T>(gy, cny, coy, (T)ghost.z, (T)ghost.w, iy, wy);
+            T pr = 0, pi = 0;
+            for (int b2 = 0; b2 < nyp; ++b2)
+                for (int a2 = 0; a2 < nxp; ++a2) {
+                    const T w = wx[a2] * wy[b2];
+                    const size_t J = (size_t)ix[a2] + (size_t)cnx * iy[b2];
                     pr += w * er[J];
                     pi += w * ei[J];
                 }
-        xr[i] += pr;
-        xi[i] += pi;
+            vr = xr[i] + pr;
+            vi = xi[i] + pi;
+        }
+        s.xr[ly][lx] = vr;
+        s.xi[ly][lx] = vi;
+    }
+    __syncthreads();
+    tile_sweeps<T, H>(s, gx0, gy0, L.nx, L.ny, 2 * NU, 1);
+    double* ur = u + ustride * r;
+    const double* rin = rho_in + 2 * N * r;
+    double* rout = rho_out + 2 * N * r;
+    double acc = 0;
+    for (int c = threadIdx.x; c < kTileX * kTileY; c += blockDim.x) {
+        const int lx = H + c % kTileX, ly = H + c / kTileX;
+        const int gx = gx0 + lx, gy = gy0 + ly;
+        if (gx >= L.nx || gy >= L.ny) continue;
+        const int i = gx + L.nx * gy;
+        const double e0r = (double)s.xr[ly][lx], e0i = (double)s.xi[ly][lx];
+        // (K + tau M) e with the FP64 operator; walls are in D, out-of-grid neighbours hold 0
+        const double tE = L64.Tx[i], tW = gx > 0 ? L64.Tx[i - 1] : 0.0;
+        const double tN = L64.Ty[i], tS = gy > 0 ? L64.Ty[i - L.nx] : 0.0;
+        const double ore = tE * (double)s.xr[ly][lx + 1] + tW * (double)s.xr[ly][lx - 1] +
+                           tN * (double)s.xr[ly + 1][lx] + tS * (double)s.xr[ly - 1][lx];
+        const double oim = tE * (double)s.xi[ly][lx + 1] + tW * (double)s.xi[ly][lx - 1] +
+                           tN * (double)s.xi[ly + 1][lx] + tS * (double)s.xi[ly - 1][lx];
+        const double dre = L64.D[i] + tr64 * L64.m[i], dim = ti64 * L64.m[i];
+        const double are = dre * e0r - dim * e0i - ore;
+        const double aim = dre * e0i + dim * e0r - oim;
+        ur[i] += e0r;
+        ur[i + N] += e0i;
+        const double nre = rin[i] - are, nim = rin[i + N] - aim;
+        rout[i] = nre;
+        rout[i + N] = nim;
+        if (lo) {
+            lo[2 * N * r + i] = (T)nre;
+            lo[2 * N * r + N + i] = (T)nim;
+        }
+        acc += nre * nre + nim * nim;
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[(size_t)r * gridDim.x * gridDim.y + blockIdx.x + (size_t)gridDim.x * blockIdx.y] =
+            red[0] + red[1] + red[2] + red[3];
+        if (prof) {
+            const int nxi = min(kTileX, L.nx - blockIdx.x * kTileX), nyi = min(kTileY, L.ny - blockIdx.y * kTileY);
+            const double agg = (double)(1 << (cox + coy));
+            // x in, b in (T complex), shared T coefficients, coarse correction in,
+            // u in/out and rho in/out (FP64 complex), lo out (T complex), FP64 coefficients (shared)
+            const double cell = 4.0 * sizeof(T) + 4.0 * sizeof(T) / Rtot + 2.0 * sizeof(T) / agg + 64.0 +
+                                (lo ? 2.0 * sizeof(T) : 0.0) + 32.0 / Rtot;
+            atomicAdd(prof, (unsigned long long)(nxi * nyi * cell));
+        }
     }
 }
 
+// ------------------------------------------------------------------ coarse levels in one workgroup
+// Thread i owns cell i of every level (levels have at most blockDim cells): its
+// face transmissibilities, diagonal and right-hand side stay in registers,
+// iterates and residuals go through LDS.
+template <typename T> struct CBCell {
+    T tw, te, ts, tn, tb, tt;  // faces to the -x, +x, -y, +y, -z, +z neighbours
+    T dr, di;                  // D + tau m
+    T br, bi;                  // right-hand side of this level
+};
+
 template <typename T>
+__device__ __forceinline__ void cb_load_cell(const CBLevel<T>& L, T tr, T ti, int i, CBCell<T>& c) {
+    const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+    const int sy = L.nx, sz = L.nx * L.ny;
+    c.te = (x + 1 < L.nx) ? L.Tx[i] : T(0);
+    c.tw = (x > 0) ? L.Tx[i - 1] : T(0);
+    c.tn = (y + 1 < L.ny) ? L.Ty[i] : T(0);
+    c.ts = (y > 0) ? L.Ty[i - sy] : T(0);
+    c.tt = (z + 1 < L.nz) ? L.Tz[i] : T(0);
+    c.tb = (z > 0) ? L.Tz[i - sz] : T(0);
+    c.dr = L.D[i] + tr * L.m[i];
+    c.di = ti * L.m[i];
+}
+
+// off = sum of couplings times neighbour values (zero couplings at walls, so the
+// clamped neighbour index is never used with a non-zero weight)
+template <typename T>
+__device__ __forceinline__ void cb_off(const CBLevel<T>& L, const CBCell<T>& c, const T* xr, const T* xi, int i,
+                                       T& ore, T& oim) {
+    const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+    const int sy = L.nx, sz = L.nx * L.ny;
+    const int e = (x + 1 < L.nx) ? i + 1 : i, w = (x > 0) ? i - 1 : i;
+    const int n = (y + 1 < L.ny) ? i + sy : i, s = (y > 0) ? i - sy : i;
+    const int t = (z + 1 < L.nz) ? i + sz : i, b = (z > 0) ? i - sz : i;
+    ore = c.te * xr[e] + c.tw * xr[w] + c.tn * xr[n] + c.ts * xr[s] + c.tt * xr[t] + c.tb * xr[b];
+    oim = c.te * xi[e] + c.tw * xi[w] + c.tn * xi[n] + c.ts * xi[s] + c.tt * xi[t] + c.tb * xi[b];
+}
+
+template <typename T, int NLM>
 __global__ __launch_bounds__(1024) void k_coarse_block(CBMeta<T> M, T tr, T ti, const T* __restrict__ bin,
                                                        T* __restrict__ xout, const int* __restrict__ active) {
     const int r = blockIdx.x;
     if (active && !active[r]) return;
     extern __shared__ unsigned char smem_raw[];
-    T* sm = reinterpret_cast<T*>(smem_raw);
-    // per level: xr, xi, br, bi at offset 4 * off
-    auto X = [&](int l) { return sm + 4 * (size_t)M.L[l].off; };
-    const int n0 = M.L[0].N;
+    T* sm = reinterpret_cast<T*>(smem_raw);  // per level: xr, xi, rr, ri at 4 * off
+    const int i = threadIdx.x;
+    const int nl = M.nl;
+    CBCell<T> c[NLM];
+#pragma unroll
+    for (int l = 0; l < NLM; ++l)
+        if (l < nl && i < M.L[l].N) cb_load_cell<T>(M.L[l], tr, ti, i, c[l]);
     {
-        T* x = X(0);
-        const T* b = bin + 2 * (size_t)n0 * r;
-        for (int i = threadIdx.x; i < n0; i += blockDim.x) {
-            x[i] = 0;
-            x[n0 + i] = 0;
-            x[2 * n0 + i] = b[i];
-            x[3 * n0 + i] = b[n0 + i];
+        const int n0 = M.L[0].N;
+        if (i < n0) {
+            const T* b = bin + 2 * (size_t)n0 * r;
+            c[0].br = b[i];
+            c[0].bi = b[n0 + i];
+            T* p = sm + 4 * (size_t)M.L[0].off;
+            p[i] = 0;
+            p[n0 + i] = 0;
         }
     }
     __syncthreads();
-    const int nl = M.nl;
-    for (int l = 0; l < nl - 1; ++l) {
+    // down
+#pragma unroll
+    for (int l = 0; l < NLM - 1; ++l) {
+        if (l + 1 >= nl) break;
         const CBLevel<T>& L = M.L[l];
-        T* p = X(l);
-        for (int s = 0; s < M.nu1; ++s)
-            for (int c = 0; c < 2; ++c) {
-                cb_gs<T>(L, tr, ti, p, p + L.N, p + 2 * L.N, p + 3 * L.N, c);
+        T* xr = sm + 4 * (size_t)L.off;
+        T* xi = xr + L.N;
+        T* rr = xi + L.N;
+        T* ri = rr + L.N;
+        const bool own = i < L.N;
+        const int par = own ? ((i % L.nx) + ((i / L.nx) % L.ny) + i / (L.nx * L.ny)) & 1 : 0;
+        for (int sw = 0; sw < M.nu1; ++sw)
+            for (int col = 0; col < 2; ++col) {
+                if (own && par == col) {
+                    T ore, oim;
+                    cb_off<T>(L, c[l], xr, xi, i, ore, oim);
+                    const T nr = c[l].br + ore, ni = c[l].bi + oim;
+                    const T dd = c[l].dr * c[l].dr + c[l].di * c[l].di;
+                    xr[i] = (nr * c[l].dr + ni * c[l].di) / dd;
+                    xi[i] = (ni * c[l].dr - nr * c[l].di) / dd;
+                }
                 __syncthreads();
             }
-        T* q = X(l + 1);
-        const int nc = M.L[l + 1].N;
-        cb_restrict<T>(L, M.L[l + 1], tr, ti, p, p + L.N, p + 2 * L.N, p + 3 * L.N, q + 2 * nc, q + 3 * nc, q,
-                       q + nc);
+        if (own) {
+            T ore, oim;
+            cb_off<T>(L, c[l], xr, xi, i, ore, oim);
+            rr[i] = c[l].br - (c[l].dr * xr[i] - c[l].di * xi[i] - ore);
+            ri[i] = c[l].bi - (c[l].dr * xi[i] + c[l].di * xr[i] - oim);
+        }
+        __syncthreads();
+        const CBLevel<T>& C = M.L[l + 1];
+        if (i < C.N) {
+            const int X = i % C.nx, Y = (i / C.nx) % C.ny, Z = i / (C.nx * C.ny);
+            T ar = 0, ai = 0;
+            for (int z = Z << C.coz; z <= (Z << C.coz) + C.coz; ++z)
+                for (int y = Y << C.coy; y <= (Y << C.coy) + C.coy; ++y)
+                    for (int x = X << C.cox; x <= (X << C.cox) + C.cox; ++x) {
+                        const int f = x + L.nx * (y + L.ny * z);
+                        ar += rr[f];
+                        ai += ri[f];
+                    }
+            c[l + 1].br = ar;
+            c[l + 1].bi = ai;
+            T* q = sm + 4 * (size_t)C.off;
+            q[i] = 0;
+            q[C.N + i] = 0;
+        }
         __syncthreads();
     }
-    {
-        const CBLevel<T>& L = M.L[nl - 1];
-        T* p = X(nl - 1);
+    // coarsest level
+#pragma unroll
+    for (int l = 0; l < NLM; ++l) {
+        if (l != nl - 1) continue;
+        const CBLevel<T>& L = M.L[l];
+        T* xr = sm + 4 * (size_t)L.off;
+        T* xi = xr + L.N;
+        T* rr = xi + L.N;
+        T* ri = rr + L.N;
+        const bool own = i < L.N;
         if (M.inv) {
-            for (int i = threadIdx.x; i < L.N; i += blockDim.x) {
+            if (own) {
+                rr[i] = c[l].br;
+                ri[i] = c[l].bi;
+            }
+            __syncthreads();
+            if (own) {
                 const T* row = M.inv + 2 * (size_t)L.N * i;
                 T ar = 0, ai = 0;
                 for (int j = 0; j < L.N; ++j) {
                     const T a = row[2 * j], bb = row[2 * j + 1];
-                    const T vr = p[2 * L.N + j], vi = p[3 * L.N + j];
-                    ar += a * vr - bb * vi;
-                    ai += a * vi + bb * vr;
+                    ar += a * rr[j] - bb * ri[j];
+                    ai += a * ri[j] + bb * rr[j];
                 }
-                p[i] = ar;
-                p[L.N + i] = ai;
+                xr[i] = ar;
+                xi[i] = ai;
             }
             __syncthreads();
         } else {
-            for (int s = 0; s < M.coarse_sweeps; ++s)
-                for (int c = 0; c < 2; ++c) {
-                    cb_gs<T>(L, tr, ti, p, p + L.N, p + 2 * L.N, p + 3 * L.N, c);
+            const int par = own ? ((i % L.nx) + ((i / L.nx) % L.ny) + i / (L.nx * L.ny)) & 1 : 0;
+            for (int sw = 0; sw < M.coarse_sweeps; ++sw)
+                for (int col = 0; col < 2; ++col) {
+                    if (own && par == col) {
+                        T ore, oim;
+                        cb_off<T>(L, c[l], xr, xi, i, ore, oim);
+                        const T nr = c[l].br + ore, ni = c[l].bi + oim;
+                        const T dd = c[l].dr * c[l].dr + c[l].di * c[l].di;
+                        xr[i] = (nr * c[l].dr + ni * c[l].di) / dd;
+                        xi[i] = (ni * c[l].dr - nr * c[l].di) / dd;
+                    }
                     __syncthreads();
                 }
         }
     }
-    for (int l = nl - 2; l >= 0; --l) {
+    // up
+#pragma unroll
+    for (int l = NLM - 2; l >= 0; --l) {
+        if (l + 1 >= nl) continue;
         const CBLevel<T>& L = M.L[l];
-        T* p = X(l);
-        const T* q = X(l + 1);
-        const int nc = M.L[l + 1].N;
-        cb_prolong<T>(L, M.L[l + 1], M.ghost, p, p + L.N, q, q + nc);
+        const CBLevel<T>& C = M.L[l + 1];
+        T* xr = sm + 4 * (size_t)L.off;
+        T* xi = xr + L.N;
+        const T* er = sm + 4 * (size_t)C.off;
+        const T* ei = er + C.N;
+        const bool own = i < L.N;
+        if (own) {
+            const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+            int ix[2], iy[2], iz[2];
+            T wx[2], wy[2], wz[2];
+            const int nxp = prolong_axis<T>(x, C.nx, C.cox, M.ghost[0], M.ghost[1], ix, wx);
+            const int nyp = prolong_axis<T>(y, C.ny, C.coy, M.ghost[2], M.ghost[3], iy, wy);
+            const int nzp = prolong_axis<T>(z, C.nz, C.coz, M.ghost[4], M.ghost[5], iz, wz);
+            T pr = 0, pi = 0;
+            for (int cz = 0; cz < nzp; ++cz)
+                for (int cy = 0; cy < nyp; ++cy)
+                    for (int cxx = 0; cxx < nxp; ++cxx) {
+                        const T w = wx[cxx] * wy[cy] * wz[cz];
+                        const int J = ix[cxx] + C.nx * (iy[cy] + C.ny * iz[cz]);
+                        pr += w * er[J];
+                        pi += w * ei[J];
+                    }
+            xr[i] += pr;
+            xi[i] += pi;
+        }
         __syncthreads();
-        for (int s = 0; s < M.nu2; ++s)
-            for (int c = 1; c >= 0; --c) {
-                cb_gs<T>(L, tr, ti, p, p + L.N, p + 2 * L.N, p + 3 * L.N, c);
+        const int par = own ? ((i % L.nx) + ((i / L.nx) % L.ny) + i / (L.nx * L.ny)) & 1 : 0;
+        for (int sw = 0; sw < M.nu2; ++sw)
+            for (int col = 1; col >= 0; --col) {
+                if (own && par == col) {
+                    T ore, oim;
+                    cb_off<T>(L, c[l], xr, xi, i, ore, oim);
+                    const T nr = c[l].br + ore, ni = c[l].bi + oim;
+                    const T dd = c[l].dr * c[l].dr + c[l].di * c[l].di;
+                    xr[i] = (nr * c[l].dr + ni * c[l].di) / dd;
+                    xi[i] = (ni * c[l].dr - nr * c[l].di) / dd;
+                }
                 __syncthreads();
             }
     }
     {
-        const T* x = X(0);
-        T* o = xout + 2 * (size_t)n0 * r;
-        for (int i = threadIdx.x; i < n0; i += blockDim.x) {
+        const int n0 = M.L[0].N;
+        if (i < n0) {
+            const T* x = sm + 4 * (size_t)M.L[0].off;
+            T* o = xout + 2 * (size_t)n0 * r;
             o[i] = x[i];
             o[n0 + i] = x[n0 + i];
         }
@@ -392,12 +569,12 @@ __global__ __launch_bounds__(1024) void k_coarse_block(CBMeta<T> M, T tr, T ti, 
 // ------------------------------------------------------------------ launchers
 template <typename T>
 int launch_pre2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, const T* b, T* x, int cnx, int cny,
-                 int cox, int coy, T* bc, int R, const int* active) {
+                 int cox, int coy, T* bc, int R, const int* active, unsigned long long* prof) {
     dim3 grid((L.nx + kTileX - 1) / kTileX, (L.ny + kTileY - 1) / kTileY, R);
     switch (nu) {
-        case 1: k_pre2d<T, 1><<<grid, 256, 0, st>>>(L, tr, ti, b, x, cnx, cny, cox, coy, bc, active); break;
-        case 2: k_pre2d<T, 2><<<grid, 256, 0, st>>>(L, tr, ti, b, x, cnx, cny, cox, coy, bc, active); break;
-        case 3: k_pre2d<T, 3><<<grid, 256, 0, st>>>(L, tr, ti, b, x, cnx, cny, cox, coy, bc, active); break;
+        case 1: k_pre2d<T, 1><<<grid, 256, 0, st>>>(L, tr, ti, b, x, cnx, cny, cox, coy, bc, active, prof, R); break;
+        case 2: k_pre2d<T, 2><<<grid, 256, 0, st>>>(L, tr, ti, b, x, cnx, cny, cox, coy, bc, active, prof, R); break;
+        case 3: k_pre2d<T, 3><<<grid, 256, 0, st>>>(L, tr, ti, b, x, cnx, cny, cox, coy, bc, active, prof, R); break;
         default: set_last_error("fused smoother supports 1..3 sweeps"); return LT_EUNSUPPORTED;
     }
     LT_HIP(hipGetLastError());
@@ -406,14 +583,35 @@ int launch_pre2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, cons
 
 template <typename T>
 int launch_post2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, const T* b, const T* xin,
-                  const T* ec, int cnx, int cny, int cox, int coy, T4 ghost, T* xout, int R, const int* active) {
+                  const T* ec, int cnx, int cny, int cox, int coy, T4 ghost, T* xout, int R, const int* active,
+                  unsigned long long* prof) {
     dim3 grid((L.nx + kTileX - 1) / kTileX, (L.ny + kTileY - 1) / kTileY, R);
     switch (nu) {
-        case 1: k_post2d<T, 1><<<grid, 256, 0, st>>>(L, tr, ti, b, xin, ec, cnx, cny, cox, coy, ghost, xout, active); break;
-        case 2: k_post2d<T, 2><<<grid, 256, 0, st>>>(L, tr, ti, b, xin, ec, cnx, cny, cox, coy, ghost, xout, active); break;
-        case 3: k_post2d<T, 3><<<grid, 256, 0, st>>>(L, tr, ti, b, xin, ec, cnx, cny, cox, coy, ghost, xout, active); break;
+        case 1: k_post2d<T, 1><<<grid, 256, 0, st>>>(L, tr, ti, b, xin, ec, cnx, cny, cox, coy, ghost, xout, active, prof, R); break;
+        case 2: k_post2d<T, 2><<<grid, 256, 0, st>>>(L, tr, ti, b, xin, ec, cnx, cny, cox, coy, ghost, xout, active, prof, R); break;
+        case 3: k_post2d<T, 3><<<grid, 256, 0, st>>>(L, tr, ti, b, xin, ec, cnx, cny, cox, coy, ghost, xout, active, prof, R); break;
         default: set_last_error("fused smoother supports 1..3 sweeps"); return LT_EUNSUPPORTED;
     }
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
+template <typename T>
+int launch_post2d_refine(hipStream_t st, const LevelView<T>& L, const LevelView<double>& L64, T tr, T ti,
+                         double tr64, double ti64, int nu, const T* b, const T* xin, const T* ec, int cnx, int cny,
+                         int cox, int coy, T4 ghost, double* u, size_t ustride, const double* rho_in,
+                         double* rho_out, T* lo, double* part, int R, const int* active, unsigned long long* prof) {
+    dim3 grid((L.nx + kTileX - 1) / kTileX, (L.ny + kTileY - 1) / kTileY, R);
+#define LT_PR(NU)                                                                                              \
+    k_post2d_refine<T, NU><<<grid, 256, 0, st>>>(L, L64, tr, ti, tr64, ti64, b, xin, ec, cnx, cny, cox, coy,   \
+                                                 ghost, u, ustride, rho_in, rho_out, lo, part, active, prof, R)
+    switch (nu) {
+        case 1: LT_PR(1); break;
+        case 2: LT_PR(2); break;
+        case 3: LT_PR(3); break;
+        default: set_last_error("fused smoother supports 1..3 sweeps"); return LT_EUNSUPPORTED;
+    }
+#undef LT_PR
     LT_HIP(hipGetLastError());
     return 0;
 }
@@ -424,21 +622,38 @@ int launch_coarse_block(hipStream_t st, const CBMeta<T>& M, T tr, T ti, const T*
     size_t cells = 0;
     for (int l = 0; l < M.nl; ++l) cells += M.L[l].N;
     size_t shm = 4 * cells * sizeof(T);
-    int threads = M.L[0].N >= 1024 ? 1024 : ((M.L[0].N + 63) / 64) * 64;
+    if (M.nl > kMaxCBLevels || M.L[0].N > 1024) {
+        set_last_error("coarse block: too many levels or cells");
+        return LT_EUNSUPPORTED;
+    }
+    int threads = ((M.L[0].N + 63) / 64) * 64;
     if (threads < 64) threads = 64;
-    k_coarse_block<T><<<R, threads, shm, st>>>(M, tr, ti, bin, xout, active);
+    if (M.nl <= 3)
+        k_coarse_block<T, 3><<<R, threads, shm, st>>>(M, tr, ti, bin, xout, active);
+    else
+        k_coarse_block<T, kMaxCBLevels><<<R, threads, shm, st>>>(M, tr, ti, bin, xout, active);
     LT_HIP(hipGetLastError());
     return 0;
 }
 
 template int launch_pre2d<float>(hipStream_t, const LevelView<float>&, float, float, int, const float*, float*, int,
-                                 int, int, int, float*, int, const int*);
+                                 int, int, int, float*, int, const int*, unsigned long long*);
 template int launch_pre2d<double>(hipStream_t, const LevelView<double>&, double, double, int, const double*, double*,
-                                  int, int, int, int, double*, int, const int*);
+                                  int, int, int, int, double*, int, const int*, unsigned long long*);
 template int launch_post2d<float>(hipStream_t, const LevelView<float>&, float, float, int, const float*,
-                                  const float*, const float*, int, int, int, int, T4, float*, int, const int*);
+                                  const float*, const float*, int, int, int, int, T4, float*, int, const int*,
+                                  unsigned long long*);
 template int launch_post2d<double>(hipStream_t, const LevelView<double>&, double, double, int, const double*,
-                                   const double*, const double*, int, int, int, int, T4, double*, int, const int*);
+                                   const double*, const double*, int, int, int, int, T4, double*, int, const int*,
+                                   unsigned long long*);
+template int launch_post2d_refine<float>(hipStream_t, const LevelView<float>&, const LevelView<double>&, float, float,
+                                         double, double, int, const float*, const float*, const float*, int, int,
+                                         int, int, T4, double*, size_t, const double*, double*, float*, double*, int,
+                                         const int*, unsigned long long*);
+template int launch_post2d_refine<double>(hipStream_t, const LevelView<double>&, const LevelView<double>&, double,
+                                          double, double, double, int, const double*, const double*, const double*,
+                                          int, int, int, int, T4, double*, size_t, const double*, double*, double*,
+                                          double*, int, const int*, unsigned long long*);
 template int launch_coarse_block<float>(hipStream_t, const CBMeta<float>&, float, float, const float*, float*, int,
                                         const int*);
 template int launch_coarse_block<double>(hipStream_t, const CBMeta<double>&, double, double, const double*, double*,
