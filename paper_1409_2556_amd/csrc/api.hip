@@ -64,6 +64,7 @@ lt_handle::~lt_handle() {
         c.inv32.release();
     }
     for (auto& kv : ws) kv.second.release();
+    kappa.release();
     if (pinned) (void)hipHostFree(pinned);
     for (hipEvent_t e : prof_events) (void)hipEventDestroy(e);
 }
@@ -494,6 +495,12 @@ int lt_setup(const lt_grid* grid, const double* kappa, const double* S, const lt
     h->stream = static_cast<hipStream_t>(hip_stream);
     h->N = (int)Nll;
     int rc = mg_build(h, kappa, S);
+    if (rc >= 0) rc = h->kappa.reserve(sizeof(double) * (size_t)h->N);
+    if (rc >= 0 && hipMemcpyAsync(h->kappa.p, kappa, sizeof(double) * (size_t)h->N, hipMemcpyDeviceToDevice,
+                                  h->stream) != hipSuccess) {
+        set_last_error("lt_setup: copying kappa failed");
+        rc = LT_EHIP;
+    }
     if (rc < 0) {
         delete h;
         return rc;
@@ -613,10 +620,69 @@ int lt_solve(lt_handle* h, const lt_points* sources, double q, const double* tim
 int lt_adjoint(lt_handle* h, const lt_points* sources, double q, const lt_points* receivers, const double* times,
                int ntimes, const lt_contour* contour, const lt_opts* opts, double* dlnK, double* dlnS,
                lt_stats* stats) {
-    (void)h; (void)sources; (void)q; (void)receivers; (void)times; (void)ntimes; (void)contour; (void)opts;
-    (void)dlnK; (void)dlnS; (void)stats;
-    set_last_error("lt_adjoint: not built yet");
-    return LT_EUNSUPPORTED;
+    auto t0 = std::chrono::steady_clock::now();
+    if (!h || !sources || sources->n < 1 || !receivers || receivers->n < 1 || !times || ntimes < 1 || !contour ||
+        (!dlnK && !dlnS) || !std::isfinite(q)) {
+        set_last_error("lt_adjoint: bad argument");
+        return LT_EINVAL;
+    }
+    for (int t = 0; t < ntimes; ++t)
+        if (!(times[t] > 0.0) || !std::isfinite(times[t])) {
+            set_last_error("lt_adjoint: times must be positive");
+            return LT_EINVAL;
+        }
+    lt_opts o;
+    if (opts) {
+        LT_TRY(validate_opts(opts));
+        o = *opts;
+    } else {
+        lt_opts_default(&o);
+    }
+    if (contour->nz < 2 || contour->nz % 2 || contour->nz > 512) {
+        set_last_error("lt_adjoint: contour nz must be even, 2..512");
+        return LT_EINVAL;
+    }
+    Plan plan;
+    LT_TRY(make_plan(times, ntimes, contour->nz, q, &o, &plan));
+    // right-hand sides: every source's b, then every receiver's B_m^T (adjoint fields)
+    lt_points all;
+    std::vector<double> xyz(3 * (size_t)(sources->n + receivers->n));
+    std::memcpy(xyz.data(), sources->xyz, sizeof(double) * 3 * sources->n);
+    std::memcpy(xyz.data() + 3 * sources->n, receivers->xyz, sizeof(double) * 3 * receivers->n);
+    all.n = sources->n + receivers->n;
+    all.xyz = xyz.data();
+    PointsCSR ac;
+    LT_TRY(points_csr(h->grid, &all, &ac));
+    DevPoints da;
+    LT_TRY(upload_points(h, ac, "adj", &da));
+    const int ns = sources->n, nr = receivers->n, R = ns + nr;
+    const size_t N2 = 2 * (size_t)h->N;
+    int rc = 0;
+    double* b = wsp<double>(h, "b", R * N2, &rc);
+    if (!b) return rc;
+    LT_HIP(hipMemsetAsync(b, 0, R * N2 * sizeof(double), h->stream));
+    LT_TRY(launch_scatter_points(h->stream, R, h->N, da.off, da.cell, da.wt, b));
+    KrylovOut k;
+    k.b = b;
+    LT_TRY(prof_start(h, o.profile));
+    LT_TRY(run_krylov(h, plan, o, R, nullptr, &k));
+    // nodal fields of one time at a time, then the cell-wise contraction
+    const int nk = plan.nk;
+    double* X = wsp<double>(h, "Xadj", (size_t)R * nk * N2, &rc);
+    if (!X) return rc;
+    for (int t = 0; t < ntimes; ++t) {
+        LT_TRY(launch_form_x(h->stream, h->N, R, nk, t * nk, k.Ks, k.U, k.ustride, k.Y, k.jmax, k.mcols, X));
+        LT_TRY(launch_sens(h->stream, h->levels[0].v64(), h->kappa.as<double>(), ns, nr, nk, t, ntimes, X, k.zs,
+                           k.wq, dlnK, dlnS));
+    }
+    if (o.true_residual) LT_TRY(true_residuals(h, k, plan, stats));
+    LT_HIP(hipStreamSynchronize(h->stream));
+    if (stats && stats->iters_per_rhs)
+        LT_HIP(hipMemcpy(stats->iters_per_rhs, k.mcols, R * sizeof(int), hipMemcpyDeviceToHost));
+    LT_TRY(prof_finish(h, stats));
+    double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_stats(stats, k, (int)h->levels.size(), secs);
+    return k.converged ? LT_OK : LT_WNOTCONV;
 }
 
 }  // extern "C"

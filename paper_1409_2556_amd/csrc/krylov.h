@@ -51,4 +51,7 @@ int launch_form_x(hipStream_t st, int N, int R, int nc, int k0, int Ks, const do
 int launch_true_residual(hipStream_t st, LevelView<double> L, int R, int nc, int k0, int Ks, const double* zs,
                          const double* X, const double* b, const double* beta, double* part, double* out);
 
+int launch_sens(hipStream_t st, LevelView<double> L, const double* kappa, int ns, int nr, int nk, int t, int ntimes,
+                const double* X, const double* zs, const double* wq, double* JK, double* JS);
+
 }  // namespace lt

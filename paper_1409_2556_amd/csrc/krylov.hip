@@ -590,6 +590,94 @@ __global__ void k_true_res_finalize(int R, int nc, int k0, int Ks, int nb, const
     out[(size_t)r * Ks + k0 + c] = sqrt(s) / beta[r];
 }
 
+// ---------------------------------------------------------------- sensitivities
+// Discrete adjoint of the heads (Section 5.2): with phi = (K + zM)^{-1} b_s and
+// psi = (K + zM)^{-1} b_m (complex symmetric operator, no conjugation),
+//   d/dp B_m phi = - psi^T (dK/dp + z dM/dp) phi,
+// dT_f/dln k_c = T_f k_j / (k_c + k_j) for the face to neighbour j, dT_wall/dln k_c = T_wall,
+// dm_c/dln S_c = m_c; the time-domain sensitivity is 2 Re sum_k w_k qhat_k (.).
+// One thread per cell, one source and up to kSensM receivers per block.
+constexpr int kSensM = 8;
+__global__ void k_sens(LevelView<double> L, const double* __restrict__ kappa, int ns, int nr, int nk, int t,
+                       int ntimes, const double* __restrict__ X, const double* __restrict__ zs,
+                       const double* __restrict__ wq, double* __restrict__ JK, double* __restrict__ JS) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= L.N) return;
+    const int s = blockIdx.y;
+    const int m0 = blockIdx.z * kSensM;
+    const size_t N = L.N;
+    const int x = c % L.nx, y = (c / L.nx) % L.ny, z = c / (L.nx * L.ny);
+    const int sy = L.nx, sz = L.nx * L.ny;
+    // neighbours and face weights dT_f/dln k_c (zero where there is no face)
+    int nb[6];
+    double wf[6];
+    const double kc = kappa[c];
+    const int has[6] = {x > 0, x + 1 < L.nx, y > 0, y + 1 < L.ny, z > 0, z + 1 < L.nz};
+    const int off[6] = {-1, 1, -sy, sy, -sz, sz};
+    double tin = 0.0;
+    for (int f = 0; f < 6; ++f) {
+        nb[f] = has[f] ? c + off[f] : c;
+        double T = 0.0;
+        if (has[f]) {
+            if (f == 0) T = L.Tx[c - 1];
+            if (f == 1) T = L.Tx[c];
+            if (f == 2) T = L.Ty[c - sy];
+            if (f == 3) T = L.Ty[c];
+            if (f == 4) T = L.Tz[c - sz];
+            if (f == 5) T = L.Tz[c];
+        }
+        tin += T;
+        const double kj = kappa[nb[f]];
+        wf[f] = has[f] ? T * kj / (kc + kj) : 0.0;
+    }
+    const double wall = L.D[c] - tin;  // walls of this cell; their T is proportional to k_c
+    const double mc = L.m[c];
+    double aK[kSensM], aS[kSensM];
+    for (int q = 0; q < kSensM; ++q) aK[q] = aS[q] = 0.0;
+    for (int kk = 0; kk < nk; ++kk) {
+        const int k = t * nk + kk;
+        const c64 w = {wq[2 * k], wq[2 * k + 1]};
+        const c64 zw = cm(w, {zs[2 * k], zs[2 * k + 1]});
+        const double* ph = X + ((size_t)s * nk + kk) * 2 * N;
+        const c64 pc = {ph[c], ph[c + N]};
+        c64 dph[6];
+        for (int f = 0; f < 6; ++f) dph[f] = {pc.re - ph[nb[f]], pc.im - ph[nb[f] + N]};
+        for (int q = 0; q < kSensM; ++q) {
+            const int m = m0 + q;
+            if (m >= nr) break;
+            const double* ps = X + ((size_t)(ns + m) * nk + kk) * 2 * N;
+            const c64 qc = {ps[c], ps[c + N]};
+            c64 g = cm(pc, qc);
+            const c64 hs = {mc * g.re, mc * g.im};
+            g.re *= wall;
+            g.im *= wall;
+            for (int f = 0; f < 6; ++f) {
+                const c64 dq = {qc.re - ps[nb[f]], qc.im - ps[nb[f] + N]};
+                const c64 p = cm(dph[f], dq);
+                g.re += wf[f] * p.re;
+                g.im += wf[f] * p.im;
+            }
+            aK[q] += w.re * g.re - w.im * g.im;
+            aS[q] += zw.re * hs.re - zw.im * hs.im;
+        }
+    }
+    for (int q = 0; q < kSensM; ++q) {
+        const int m = m0 + q;
+        if (m >= nr) break;
+        const size_t o = (((size_t)s * nr + m) * ntimes + t) * N + c;
+        if (JK) JK[o] = -2.0 * aK[q];
+        if (JS) JS[o] = -2.0 * aS[q];
+    }
+}
+
+int launch_sens(hipStream_t st, LevelView<double> L, const double* kappa, int ns, int nr, int nk, int t, int ntimes,
+                const double* X, const double* zs, const double* wq, double* JK, double* JS) {
+    dim3 grid((unsigned)((L.N + kB - 1) / kB), ns, (nr + kSensM - 1) / kSensM);
+    k_sens<<<grid, kB, 0, st>>>(L, kappa, ns, nr, nk, t, ntimes, X, zs, wq, JK, JS);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
 // ---------------------------------------------------------------- launchers
 static inline unsigned nb_for(size_t n) { return (unsigned)((n + kB - 1) / kB); }
 

@@ -84,6 +84,7 @@ struct lt_handle {
     std::vector<lt::Level> levels;
     std::vector<lt::CoarseInverse> coarse_cache;
     std::vector<double> coarse_host;  // coarsest level coefficients [5][Nc] on the host
+    lt::DevBuf kappa;                 // copy of the fine-grid conductivity (sensitivities)
     // workspaces (grow-only, owned by the handle)
     std::map<std::string, lt::DevBuf> ws;
     void* pinned = nullptr;  // small pinned host area for flags
