@@ -52,6 +52,7 @@ enum {
 enum { LT_BC_DIRICHLET0 = 0, LT_BC_NEUMANN0 = 1 };
 enum { LT_PREC_FP64 = 0, LT_PREC_MIXED = 1 };   /* V-cycle in FP64 or FP32   */
 enum { LT_PROF_OFF = 0, LT_PROF_PRE_FINE = 1, LT_PROF_POST_FINE = 2 };
+enum { LT_PRECOND_GMG = 0, LT_PRECOND_UNET_GMG = 1 };
 
 typedef struct lt_handle lt_handle;
 
@@ -109,7 +110,14 @@ typedef struct {
  *   profile    0: off.  LT_PROF_PRE_FINE / LT_PROF_POST_FINE: time every launch
  *              of the fine-grid pre- / post-smoothing kernel with HIP events on
  *              the handle's stream and count its algorithmic bytes (reported
- *              in lt_stats.prof_*). */
+ *              in lt_stats.prof_*).
+ *   precond    LT_PRECOND_GMG: V-cycle refinement only.  LT_PRECOND_UNET_GMG:
+ *              every preconditioner solve starts from the attached network's
+ *              guess (lt_unet_attach, 2D grids whose nx is a multiple of 128 and
+ *              ny of 8); a guess that increases the residual is discarded, and
+ *              the V-cycle refinement then proceeds as usual, so the V-cycle
+ *              remains both the fallback and, through the true residual, the
+ *              judge. */
 typedef struct {
     double tol;
     int maxit;
@@ -121,6 +129,7 @@ typedef struct {
     double relax;
     int true_residual;
     int profile;
+    int precond;
 } lt_opts;
 
 /* Statistics of the last call.  Pointer members are optional host arrays the
@@ -135,6 +144,8 @@ typedef struct {
     double seconds;              /* wall time of the call                    */
     int* iters_per_rhs;          /* [n_rhs] or NULL                          */
     double* true_relres;         /* [n_rhs][n_shifts] ||b - (K+zM)x|| / ||b|| or NULL */
+    int net_applied;             /* network guesses applied (rhs x outer iterations) */
+    int net_rejected;            /* of which discarded by the residual guard      */
     int prof_launches;           /* profiled launches (opts.profile)          */
     double prof_ms;              /* their summed device time, milliseconds    */
     double prof_bytes;           /* their summed algorithmic bytes            */
@@ -190,6 +201,52 @@ int lt_apply_operator(lt_handle* h, int level, double tau_re, double tau_im,
  * shift-and-invert solve). */
 int lt_vcycle(lt_handle* h, double tau_re, double tau_im, int precision, int nu1, int nu2,
               const double* b, double* x, int nvec);
+
+/* ---- learned preconditioner -------------------------------------------
+ * A 2D convolutional U-Net (4 levels, 16/32/64/64 channels, 3x3 kernels,
+ * BF16 weights and activations, FP32 accumulation on the matrix cores) that
+ * maps a residual r to an approximation of (K + tau M)^{-1} r on the grid of
+ * a handle.  Its inputs per cell are r / rms(r), ln(D_i / mean D) and
+ * tau m_i / D_i (D_i the diagonal of K); it predicts e D_i / rms(r).  It is
+ * trained on the GPU with the library's own forward and backward kernels and
+ * Adam; FP32 master weights live on the device.  Grids: 2D, nx a multiple of
+ * 128, ny a multiple of 8.  Not part of the paper (which factorises
+ * K + tau M); the flexible method of Section 3 admits any preconditioner. */
+typedef struct lt_unet lt_unet;
+
+/* New network with He-normal weights from `seed`; work goes to hip_stream. */
+int lt_unet_create(unsigned long long seed, void* hip_stream, lt_unet** out);
+/* Number of FP32 parameters. */
+long long lt_unet_nparams(const lt_unet* u);
+/* Copy the parameters to / from a host array of lt_unet_nparams floats. */
+int lt_unet_get_params(lt_unet* u, float* host);
+int lt_unet_set_params(lt_unet* u, const float* host);
+/* e = network(r) for nvec complex device vectors [nvec][2][N] (float64) on the
+ * grid of h with preconditioner shift tau. */
+int lt_unet_apply(lt_unet* u, lt_handle* h, double tau_re, double tau_im, int nvec, const double* r, double* e);
+/* One training step on the pairs (r, e = (K + tau M)^{-1} r): loss = mean
+ * over vectors of the relative error left after the best complex multiple
+ * of the output, 1 - |<out, t>|^2 / (||out||^2 ||t||^2), t = e D / rms(r)
+ * (the solver applies the output with the residual-minimising multiple, so
+ * only its direction matters); Adam with learning rate lr (lr = 0: no update).
+ * loss: host float (mean loss before the update) or NULL. */
+int lt_unet_train_step(lt_unet* u, lt_handle* h, double tau_re, double tau_im, int nvec, const double* r,
+                       const double* e, float lr, float* loss);
+/* Gradient of that loss with respect to the parameters (host array of
+ * lt_unet_nparams floats); test entry point. */
+int lt_unet_grad(lt_unet* u, lt_handle* h, double tau_re, double tau_im, int nvec, const double* r, const double* e,
+                 float* grad_host);
+/* Use u in lt_solve / lt_adjoint of h when opts.precond = LT_PRECOND_UNET_GMG
+ * (NULL detaches).  The handle does not own the network. */
+int lt_unet_attach(lt_handle* h, lt_unet* u);
+void lt_unet_destroy(lt_unet* u);
+
+/* e = (K + tau M)^{-1} r to relative residual tol by FP64 V-cycle iteration
+ * (at most maxcycles), nvec complex device vectors [nvec][2][N]: accurate
+ * preconditioner solves, used as training targets.  Returns LT_WNOTCONV if
+ * tol is not reached. */
+int lt_precond_solve(lt_handle* h, double tau_re, double tau_im, int nvec, const double* r, double* e, double tol,
+                     int maxcycles);
 
 /* Number of cells per axis of multigrid level `level` (n_out[3]); returns
  * the number of levels, or a negative error code. */

@@ -23,6 +23,7 @@ LT_OK, LT_EINVAL, LT_EHIP, LT_ENOMEM, LT_EUNSUPPORTED, LT_WNOTCONV = 0, -1, -2, 
 LT_BC_DIRICHLET0, LT_BC_NEUMANN0 = 0, 1
 LT_PREC_FP64, LT_PREC_MIXED = 0, 1
 LT_PROF_OFF, LT_PROF_PRE_FINE, LT_PROF_POST_FINE = 0, 1, 2
+LT_PRECOND_GMG, LT_PRECOND_UNET_GMG = 0, 1
 
 
 class lt_grid(C.Structure):
@@ -45,13 +46,14 @@ class lt_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("precision", C.c_int), ("n_tau", C.c_int),
                 ("tau_reim", C.POINTER(C.c_double)), ("nu1", C.c_int), ("nu2", C.c_int),
                 ("inner_max", C.c_int), ("relax", C.c_double), ("true_residual", C.c_int),
-                ("profile", C.c_int)]
+                ("profile", C.c_int), ("precond", C.c_int)]
 
 
 class lt_stats(C.Structure):
     _fields_ = [("n_rhs", C.c_int), ("n_shifts", C.c_int), ("iters_max", C.c_int), ("vcycles", C.c_int),
                 ("levels", C.c_int), ("true_relres_max", C.c_double), ("seconds", C.c_double),
                 ("iters_per_rhs", C.POINTER(C.c_int)), ("true_relres", C.POINTER(C.c_double)),
+                ("net_applied", C.c_int), ("net_rejected", C.c_int),
                 ("prof_launches", C.c_int), ("prof_ms", C.c_double), ("prof_bytes", C.c_double)]
 
 
@@ -83,6 +85,27 @@ _lib.lt_last_error.argtypes = []
 _lib.lt_last_error.restype = C.c_char_p
 _lib.lt_destroy.argtypes = [_h]
 _lib.lt_destroy.restype = None
+_fp = C.POINTER(C.c_float)
+_lib.lt_unet_create.argtypes = [C.c_ulonglong, _vp, C.POINTER(_h)]
+_lib.lt_unet_create.restype = C.c_int
+_lib.lt_unet_nparams.argtypes = [_h]
+_lib.lt_unet_nparams.restype = C.c_longlong
+_lib.lt_unet_get_params.argtypes = [_h, _fp]
+_lib.lt_unet_get_params.restype = C.c_int
+_lib.lt_unet_set_params.argtypes = [_h, _fp]
+_lib.lt_unet_set_params.restype = C.c_int
+_lib.lt_unet_apply.argtypes = [_h, _h, C.c_double, C.c_double, C.c_int, _vp, _vp]
+_lib.lt_unet_apply.restype = C.c_int
+_lib.lt_unet_train_step.argtypes = [_h, _h, C.c_double, C.c_double, C.c_int, _vp, _vp, C.c_float, _fp]
+_lib.lt_unet_train_step.restype = C.c_int
+_lib.lt_unet_grad.argtypes = [_h, _h, C.c_double, C.c_double, C.c_int, _vp, _vp, _fp]
+_lib.lt_unet_grad.restype = C.c_int
+_lib.lt_unet_attach.argtypes = [_h, _h]
+_lib.lt_unet_attach.restype = C.c_int
+_lib.lt_unet_destroy.argtypes = [_h]
+_lib.lt_unet_destroy.restype = None
+_lib.lt_precond_solve.argtypes = [_h, C.c_double, C.c_double, C.c_int, _vp, _vp, C.c_double, C.c_int]
+_lib.lt_precond_solve.restype = C.c_int
 
 
 class LTError(RuntimeError):
@@ -191,6 +214,7 @@ def _stats_dict(st, it, tr, rc, nrhs, nshift):
     return {"rc": rc, "n_rhs": st.n_rhs, "n_shifts": st.n_shifts, "iters_max": st.iters_max,
             "vcycles": st.vcycles, "levels": st.levels, "true_relres_max": st.true_relres_max,
             "seconds": st.seconds, "iters_per_rhs": it.copy(), "true_relres": tr.reshape(nrhs, nshift).copy(),
+            "net_applied": st.net_applied, "net_rejected": st.net_rejected,
             "prof_launches": st.prof_launches, "prof_ms": st.prof_ms, "prof_bytes": st.prof_bytes}
 
 
@@ -269,7 +293,76 @@ def exported_symbols():
 
 
 _ABI_NAMES = ["lt_opts_default", "lt_setup", "lt_solve", "lt_adjoint", "lt_talbot", "lt_apply_operator",
-              "lt_vcycle", "lt_level_shape", "lt_strerror", "lt_last_error", "lt_destroy"]
+              "lt_vcycle", "lt_level_shape", "lt_strerror", "lt_last_error", "lt_destroy", "lt_unet_create",
+              "lt_unet_nparams", "lt_unet_get_params", "lt_unet_set_params", "lt_unet_apply",
+              "lt_unet_train_step", "lt_unet_grad", "lt_unet_attach", "lt_unet_destroy", "lt_precond_solve"]
+
+
+# ---------------------------------------------------------------- learned preconditioner
+class UNet:
+    """Owns an lt_unet (created on the current torch stream)."""
+
+    def __init__(self, seed=0, stream=None):
+        self.ptr = _h()
+        _check(_lib.lt_unet_create(int(seed), _stream_ptr(stream), C.byref(self.ptr)))
+
+    @property
+    def nparams(self):
+        return int(_lib.lt_unet_nparams(self.ptr))
+
+    def get_params(self):
+        p = np.zeros(self.nparams, dtype=np.float32)
+        _check(_lib.lt_unet_get_params(self.ptr, p.ctypes.data_as(_fp)))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.float32))
+        if p.size != self.nparams:
+            raise ValueError("wrong parameter count")
+        _check(_lib.lt_unet_set_params(self.ptr, p.ctypes.data_as(_fp)))
+
+    def close(self):
+        if self.ptr:
+            _lib.lt_unet_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lt_unet_apply(net: UNet, handle: Handle, tau, r, e, nvec):
+    tau = complex(tau)
+    return _check(_lib.lt_unet_apply(net.ptr, handle.ptr, tau.real, tau.imag, int(nvec), _dev_f64(r, "r"),
+                                     _dev_f64(e, "e")))
+
+
+def lt_unet_train_step(net: UNet, handle: Handle, tau, r, e, nvec, lr):
+    tau = complex(tau)
+    loss = C.c_float(0.0)
+    _check(_lib.lt_unet_train_step(net.ptr, handle.ptr, tau.real, tau.imag, int(nvec), _dev_f64(r, "r"),
+                                   _dev_f64(e, "e"), float(lr), C.byref(loss)))
+    return float(loss.value)
+
+
+def lt_unet_grad(net: UNet, handle: Handle, tau, r, e, nvec):
+    tau = complex(tau)
+    g = np.zeros(net.nparams, dtype=np.float32)
+    _check(_lib.lt_unet_grad(net.ptr, handle.ptr, tau.real, tau.imag, int(nvec), _dev_f64(r, "r"),
+                             _dev_f64(e, "e"), g.ctypes.data_as(_fp)))
+    return g
+
+
+def lt_unet_attach(handle: Handle, net):
+    return _check(_lib.lt_unet_attach(handle.ptr, net.ptr if net is not None else None))
+
+
+def lt_precond_solve(handle: Handle, tau, r, e, nvec, tol=1e-10, maxcycles=60):
+    tau = complex(tau)
+    return _check(_lib.lt_precond_solve(handle.ptr, tau.real, tau.imag, int(nvec), _dev_f64(r, "r"),
+                                        _dev_f64(e, "e"), float(tol), int(maxcycles)))
 
 
 # ---------------------------------------------------------------- complex SoA helpers

@@ -19,6 +19,7 @@
 
 #include "krylov.h"
 #include "lt_internal.h"
+#include "unet.h"
 
 namespace lt {
 
@@ -101,6 +102,7 @@ int validate_opts(const lt_opts* o) {
     if (!o) return 0;
     if (!(o->tol > 0.0) || o->maxit < 1 || o->maxit > 2000 || o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 ||
         o->inner_max < 1 || !(o->relax > 0.0) || o->profile < 0 || o->profile > LT_PROF_POST_FINE ||
+        (o->precond != LT_PRECOND_GMG && o->precond != LT_PRECOND_UNET_GMG) ||
         (o->precision != LT_PREC_FP64 && o->precision != LT_PREC_MIXED)) {
         set_last_error("invalid lt_opts");
         return LT_EINVAL;
@@ -122,6 +124,7 @@ struct KrylovOut {
     double* omega = nullptr;  // [Ks]
     double* wq = nullptr;     // [Ks] complex
     int iters_max = 0, vcycles = 0;
+    int net_applied = 0, net_rejected = 0;
     bool converged = true;
 };
 
@@ -180,13 +183,21 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     double* scale = small;
     double* beta = small + R;
     double* worst = small + 2 * R;
-    int* ints = wsp<int>(h, "ints", 4 * (size_t)R + 4, &rc);  // masks, counts, [count, steps needed]
+    int* ints = wsp<int>(h, "ints", 5 * (size_t)R + 8, &rc);  // masks, counts, [count, steps needed], net stats
     if (!ints) return rc;
     int* active = ints;
     int* inner_active = ints + R;
     int* mcols = ints + 2 * R;
     int* vcyc = ints + 3 * R;
     int* count = ints + 4 * R;
+    int* bad = ints + 4 * R + 4;      // [R] network guesses to discard
+    int* netc = ints + 5 * R + 4;     // [2] applied, rejected
+    const bool use_net = o.precond == LT_PRECOND_UNET_GMG && h->unet != nullptr;
+    if (o.precond == LT_PRECOND_UNET_GMG &&
+        (!h->unet || h->grid.ndim != 2 || h->grid.n[0] % 128 || h->grid.n[1] % 8)) {
+        set_last_error("LT_PRECOND_UNET_GMG needs an attached network and a 2D grid with nx % 128 == 0, ny % 8 == 0");
+        return LT_EINVAL;
+    }
     const size_t P = (size_t)R * Ks;
     LSState ls;
     ls.Rm = wsp<double>(h, "Rm", 2 * P * ((size_t)jmax * (jmax + 1) / 2), &rc);
@@ -237,7 +248,7 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
         std::vector<double> hb(R);
         LT_HIP(hipMemcpyAsync(hb.data(), beta, R * sizeof(double), hipMemcpyDeviceToHost, st));
         LT_HIP(hipStreamSynchronize(st));
-        std::vector<int> ii(4 * (size_t)R + 4, 0);
+        std::vector<int> ii(5 * (size_t)R + 8, 0);
         for (int r = 0; r < R; ++r) ii[r] = hb[r] > 0.0 ? 1 : 0;
         LT_HIP(hipMemcpyAsync(ints, ii.data(), ii.size() * sizeof(int), hipMemcpyHostToDevice, st));
     }
@@ -259,6 +270,26 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
             LT_TRY(launch_inner_init<float>(st, N, R, qstride, vj, uj, ustride, rho, lo32, active));
         else
             LT_TRY(launch_inner_init<double>(st, N, R, qstride, vj, uj, ustride, rho, (double*)nullptr, active));
+        if (use_net) {
+            // learned first guess u = alpha net(v), alpha minimising ||v - alpha (K + tau M) net(v)||;
+            // rho = v - (K + tau M) u; discarded where it is not finite or does not help
+            UNet* net = &h->unet->net;
+            const int nbr = reduce_blocks(N, R);
+            if (mixed) {
+                LT_TRY(unet_apply<float>(net, st, L0, h->lnDbar, tau, R, lo32, e32, active));
+                LT_TRY(launch_net_scale<float>(st, L0, tau, R, e32, rho, part, active));
+                LT_TRY(launch_inner_update<float>(st, L0, tau, R, e32, uj, ustride, rho, lo32, part, active));
+                LT_TRY(launch_net_guard(st, R, nbr, part, active, bad, netc));
+                LT_TRY(launch_inner_init<float>(st, N, R, qstride, vj, uj, ustride, rho, lo32, bad));
+            } else {
+                LT_TRY(unet_apply<double>(net, st, L0, h->lnDbar, tau, R, rho, e64, active));
+                LT_TRY(launch_net_scale<double>(st, L0, tau, R, e64, rho, part, active));
+                LT_TRY(launch_inner_update<double>(st, L0, tau, R, e64, uj, ustride, rho, (double*)nullptr, part,
+                                                   active));
+                LT_TRY(launch_net_guard(st, R, nbr, part, active, bad, netc));
+                LT_TRY(launch_inner_init<double>(st, N, R, qstride, vj, uj, ustride, rho, (double*)nullptr, bad));
+            }
+        }
         // The refinement steps expected from the previous outer iteration are
         // enqueued without waiting; finished right-hand sides are masked off on
         // the device, and the host checks only after that batch.
@@ -328,12 +359,15 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
         out->converged = n_active == 0;
     }
     LT_TRY(launch_backsolve(st, R, Ks, mcols, ls, Y, jmax));
-    std::vector<int> hm(R), hv(R);
+    std::vector<int> hm(R), hv(R), hn(2);
+    LT_HIP(hipMemcpyAsync(hn.data(), netc, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     LT_HIP(hipMemcpyAsync(hm.data(), mcols, R * sizeof(int), hipMemcpyDeviceToHost, st));
     LT_HIP(hipMemcpyAsync(hv.data(), vcyc, R * sizeof(int), hipMemcpyDeviceToHost, st));
     LT_HIP(hipStreamSynchronize(st));
     out->iters_max = 0;
     out->vcycles = 0;
+    out->net_applied = hn[0];
+    out->net_rejected = hn[1];
     for (int r = 0; r < R; ++r) {
         out->iters_max = std::max(out->iters_max, hm[r]);
         out->vcycles += hv[r];
@@ -419,6 +453,8 @@ void fill_stats(lt_stats* s, const KrylovOut& k, int nlev, double secs) {
     s->n_shifts = k.Ks;
     s->iters_max = k.iters_max;
     s->vcycles = k.vcycles;
+    s->net_applied = k.net_applied;
+    s->net_rejected = k.net_rejected;
     s->levels = nlev;
     s->seconds = secs;
 }
@@ -440,6 +476,7 @@ void lt_opts_default(lt_opts* o) {
     o->inner_max = 30;
     o->relax = 1.0;
     o->true_residual = 1;
+    o->precond = LT_PRECOND_GMG;
 }
 
 const char* lt_strerror(int code) {
@@ -684,5 +721,148 @@ int lt_adjoint(lt_handle* h, const lt_points* sources, double q, const lt_points
     fill_stats(stats, k, (int)h->levels.size(), secs);
     return k.converged ? LT_OK : LT_WNOTCONV;
 }
+
+// ---------------------------------------------------------------- learned preconditioner
+static int unet_check_grid(const lt_handle* h) {
+    if (h->grid.ndim != 2 || h->grid.n[0] % 128 || h->grid.n[1] % 8) {
+        set_last_error("the network needs a 2D grid with nx % 128 == 0 and ny % 8 == 0");
+        return LT_EUNSUPPORTED;
+    }
+    return 0;
+}
+
+int lt_unet_create(unsigned long long seed, void* hip_stream, lt_unet** out) {
+    if (!out) return LT_EINVAL;
+    *out = nullptr;
+    lt_unet* u = new (std::nothrow) lt_unet();
+    if (!u) return LT_ENOMEM;
+    u->net.stream = static_cast<hipStream_t>(hip_stream);
+    std::vector<float> p;
+    unet_init_params(&u->net, seed, p);
+    int rc = unet_upload(&u->net, u->net.stream, p.data());
+    if (rc >= 0 && hipStreamSynchronize(u->net.stream) != hipSuccess) rc = LT_EHIP;
+    if (rc < 0) {
+        delete u;
+        return rc;
+    }
+    *out = u;
+    return LT_OK;
+}
+
+long long lt_unet_nparams(const lt_unet* u) { return u ? (long long)u->net.nparams : LT_EINVAL; }
+
+int lt_unet_get_params(lt_unet* u, float* host) {
+    if (!u || !host) return LT_EINVAL;
+    LT_HIP(hipStreamSynchronize(u->net.stream));
+    LT_HIP(hipMemcpy(host, u->net.ws["params"].p, u->net.nparams * sizeof(float), hipMemcpyDeviceToHost));
+    return LT_OK;
+}
+
+int lt_unet_set_params(lt_unet* u, const float* host) {
+    if (!u || !host) return LT_EINVAL;
+    LT_TRY(unet_upload(&u->net, u->net.stream, host));
+    u->net.adam_t = 0;
+    LT_HIP(hipStreamSynchronize(u->net.stream));
+    return LT_OK;
+}
+
+int lt_unet_apply(lt_unet* u, lt_handle* h, double tau_re, double tau_im, int nvec, const double* r, double* e) {
+    if (!u || !h || !r || !e || nvec < 1) return LT_EINVAL;
+    LT_TRY(unet_check_grid(h));
+    LT_TRY(unet_apply<double>(&u->net, h->stream, h->levels[0].v64(), h->lnDbar, cdouble(tau_re, tau_im), nvec, r,
+                              e, nullptr));
+    LT_HIP(hipStreamSynchronize(h->stream));
+    return LT_OK;
+}
+
+static int unet_loss_grad(lt_unet* u, lt_handle* h, double tau_re, double tau_im, int nvec, const double* r,
+                          const double* e, float* loss) {
+    LT_TRY(unet_check_grid(h));
+    UNet* net = &u->net;
+    hipStream_t st = h->stream;
+    const LevelView<double> L0 = h->levels[0].v64();
+    LT_TRY(unet_features<double>(net, st, L0, h->lnDbar, cdouble(tau_re, tau_im), nvec, r));
+    LT_TRY(unet_forward(net, st, nvec, L0.ny, L0.nx));
+    DevBuf& lb = net->ws["loss"];
+    LT_TRY(lb.reserve(sizeof(float) * nvec));
+    LT_TRY(unet_loss_and_grad(net, st, L0, nvec, e, lb.as<float>()));
+    DevBuf& gb = net->ws["grad"];
+    LT_TRY(gb.reserve(sizeof(float) * net->nparams));
+    LT_HIP(hipMemsetAsync(gb.p, 0, sizeof(float) * net->nparams, st));
+    LT_TRY(unet_backward(net, st, nvec, L0.ny, L0.nx, nullptr));
+    if (loss) {
+        std::vector<float> l(nvec);
+        LT_HIP(hipMemcpyAsync(l.data(), lb.p, sizeof(float) * nvec, hipMemcpyDeviceToHost, st));
+        LT_HIP(hipStreamSynchronize(st));
+        double s = 0;
+        for (float v : l) s += v;
+        *loss = (float)(s / nvec);
+    }
+    return LT_OK;
+}
+
+int lt_unet_train_step(lt_unet* u, lt_handle* h, double tau_re, double tau_im, int nvec, const double* r,
+                       const double* e, float lr, float* loss) {
+    if (!u || !h || !r || !e || nvec < 1 || !(lr >= 0.0f)) return LT_EINVAL;
+    LT_TRY(unet_loss_grad(u, h, tau_re, tau_im, nvec, r, e, loss));
+    if (lr > 0.0f) LT_TRY(unet_adam(&u->net, h->stream, lr));
+    LT_HIP(hipStreamSynchronize(h->stream));
+    return LT_OK;
+}
+
+int lt_unet_grad(lt_unet* u, lt_handle* h, double tau_re, double tau_im, int nvec, const double* r, const double* e,
+                 float* grad_host) {
+    if (!u || !h || !r || !e || nvec < 1 || !grad_host) return LT_EINVAL;
+    LT_TRY(unet_loss_grad(u, h, tau_re, tau_im, nvec, r, e, nullptr));
+    LT_HIP(hipStreamSynchronize(h->stream));
+    LT_HIP(hipMemcpy(grad_host, u->net.ws["grad"].p, u->net.nparams * sizeof(float), hipMemcpyDeviceToHost));
+    return LT_OK;
+}
+
+int lt_unet_attach(lt_handle* h, lt_unet* u) {
+    if (!h) return LT_EINVAL;
+    if (u) LT_TRY(unet_check_grid(h));
+    h->unet = u;
+    return LT_OK;
+}
+
+void lt_unet_destroy(lt_unet* u) {
+    if (!u) return;
+    (void)hipStreamSynchronize(u->net.stream);
+    delete u;
+}
+
+int lt_precond_solve(lt_handle* h, double tau_re, double tau_im, int nvec, const double* r, double* e, double tol,
+                     int maxcycles) {
+    if (!h || !r || !e || nvec < 1 || !(tol > 0.0) || maxcycles < 1) return LT_EINVAL;
+    hipStream_t st = h->stream;
+    const int N = h->N;
+    const size_t N2 = 2 * (size_t)N;
+    int rc = 0;
+    double* rho = wsp<double>(h, "ps_rho", nvec * N2, &rc);
+    double* x = wsp<double>(h, "ps_x", nvec * N2, &rc);
+    const int nb = reduce_blocks(N, nvec);
+    double* part = wsp<double>(h, "ps_part", (size_t)nvec * nb, &rc);
+    double* nrm = wsp<double>(h, "ps_nrm", 2 * (size_t)nvec, &rc);
+    if (!rho || !x || !part || !nrm) return rc;
+    const cdouble tau(tau_re, tau_im);
+    const LevelView<double> L0 = h->levels[0].v64();
+    LT_HIP(hipMemcpyAsync(rho, r, nvec * N2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    LT_HIP(hipMemsetAsync(e, 0, nvec * N2 * sizeof(double), st));
+    LT_TRY(launch_norms(st, N, nvec, N2, r, part, nrm + nvec, nullptr));
+    std::vector<double> hn(2 * (size_t)nvec);
+    for (int c = 0; c < maxcycles; ++c) {
+        LT_TRY(mg_vcycle<double>(h, tau, 2, 2, nvec, nullptr, x, rho));
+        LT_TRY(launch_inner_update<double>(st, L0, tau, nvec, x, e, N2, rho, (double*)nullptr, part, nullptr));
+        LT_TRY(launch_norms(st, N, nvec, N2, rho, part, nrm, nullptr));
+        LT_HIP(hipMemcpyAsync(hn.data(), nrm, 2 * nvec * sizeof(double), hipMemcpyDeviceToHost, st));
+        LT_HIP(hipStreamSynchronize(st));
+        bool done = true;
+        for (int v = 0; v < nvec; ++v) done = done && hn[v] <= tol * hn[nvec + v];
+        if (done) return LT_OK;
+    }
+    return LT_WNOTCONV;
+}
+
 
 }  // extern "C"

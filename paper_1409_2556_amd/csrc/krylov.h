@@ -51,6 +51,10 @@ int launch_form_x(hipStream_t st, int N, int R, int nc, int k0, int Ks, const do
 int launch_true_residual(hipStream_t st, LevelView<double> L, int R, int nc, int k0, int Ks, const double* zs,
                          const double* X, const double* b, const double* beta, double* part, double* out);
 
+template <typename T>
+int launch_net_scale(hipStream_t st, LevelView<double> L, cdouble tau, int R, T* d, const double* v, double* part,
+                     const int* active);
+int launch_net_guard(hipStream_t st, int R, int nb, const double* part, const int* active, int* bad, int* counts);
 int launch_sens(hipStream_t st, LevelView<double> L, const double* kappa, int ns, int nr, int nk, int t, int ntimes,
                 const double* X, const double* zs, const double* wq, double* JK, double* JS);
 

@@ -189,6 +189,92 @@ __global__ void k_inner_finalize(int R, int nb, const double* __restrict__ part,
     }
 }
 
+// bad[r] = active[r] && ||rho_r||^2 > 1 (the network guess made the unit residual worse)
+__global__ void k_net_guard(int R, int nb, const double* __restrict__ part, const int* __restrict__ active,
+                            int* __restrict__ bad, int* __restrict__ counts) {
+    __shared__ int nbad, nact;
+    if (threadIdx.x == 0) { nbad = 0; nact = 0; }
+    __syncthreads();
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+        int b = 0;
+        if (active[r]) {
+            double s = 0;
+            for (int q = 0; q < nb; ++q) s += part[(size_t)r * nb + q];
+            b = !(s <= 1.0);
+            atomicAdd(&nact, 1);
+            if (b) atomicAdd(&nbad, 1);
+        }
+        bad[r] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        counts[0] += nact;
+        counts[1] += nbad;
+    }
+}
+
+// Residual-minimising multiple of the network's direction d for the residual v:
+// w = (K + tau M) d (FP64), alpha = <w, v> / <w, w>.  part[r][blk] = (Re <w,v>, Im <w,v>, <w,w>).
+template <typename T>
+__global__ void k_net_dots(LevelView<double> L, double tr, double ti, const T* __restrict__ d,
+                           const double* __restrict__ v, double* __restrict__ part, const int* __restrict__ active) {
+    const int r = blockIdx.y;
+    if (active && !active[r]) return;
+    const size_t N = L.N;
+    const T* dr = d + 2 * N * r;
+    const T* di = dr + N;
+    const double* vr = v + 2 * N * r;
+    double acc[3] = {0, 0, 0};
+    for (int i = blockIdx.x * kB + threadIdx.x; i < L.N; i += gridDim.x * kB) {
+        const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+        const int sy = L.nx, sz = L.nx * L.ny;
+        double sre = 0, sim = 0;
+        if (x + 1 < L.nx) { double t = L.Tx[i]; sre += t * (double)dr[i + 1]; sim += t * (double)di[i + 1]; }
+        if (x > 0) { double t = L.Tx[i - 1]; sre += t * (double)dr[i - 1]; sim += t * (double)di[i - 1]; }
+        if (y + 1 < L.ny) { double t = L.Ty[i]; sre += t * (double)dr[i + sy]; sim += t * (double)di[i + sy]; }
+        if (y > 0) { double t = L.Ty[i - sy]; sre += t * (double)dr[i - sy]; sim += t * (double)di[i - sy]; }
+        if (z + 1 < L.nz) { double t = L.Tz[i]; sre += t * (double)dr[i + sz]; sim += t * (double)di[i + sz]; }
+        if (z > 0) { double t = L.Tz[i - sz]; sre += t * (double)dr[i - sz]; sim += t * (double)di[i - sz]; }
+        const double dre = L.D[i] + tr * L.m[i], dim = ti * L.m[i];
+        const double wre = dre * (double)dr[i] - dim * (double)di[i] - sre;
+        const double wim = dre * (double)di[i] + dim * (double)dr[i] - sim;
+        const double xre = vr[i], xim = vr[i + N];
+        acc[0] += wre * xre + wim * xim;   // Re conj(w) v
+        acc[1] += wre * xim - wim * xre;   // Im conj(w) v
+        acc[2] += wre * wre + wim * wim;
+    }
+    double o[3];
+    block_reduce<3>(acc, o);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) part[((size_t)r * gridDim.x + blockIdx.x) * 3 + k] = o[k];
+}
+
+// d *= alpha_r (complex), alpha = <w, v> / <w, w> from the partial sums
+template <typename T>
+__global__ void k_net_scale(int N, int nb, const double* __restrict__ part, T* __restrict__ d,
+                            const int* __restrict__ active) {
+    const int r = blockIdx.y;
+    if (active && !active[r]) return;
+    __shared__ double al[2];
+    if (threadIdx.x == 0) {
+        double a = 0, b = 0, c = 0;
+        for (int q = 0; q < nb; ++q) {
+            a += part[((size_t)r * nb + q) * 3];
+            b += part[((size_t)r * nb + q) * 3 + 1];
+            c += part[((size_t)r * nb + q) * 3 + 2];
+        }
+        al[0] = c > 0 ? a / c : 0.0;
+        al[1] = c > 0 ? b / c : 0.0;
+    }
+    __syncthreads();
+    const size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
+    if (i >= (size_t)N) return;
+    T* dr = d + 2 * (size_t)N * r;
+    const double xr = (double)dr[i], xi = (double)dr[i + N];
+    dr[i] = (T)(al[0] * xr - al[1] * xi);
+    dr[i + N] = (T)(al[0] * xi + al[1] * xr);
+}
+
 // ---------------------------------------------------------------- classical Gram-Schmidt (twice)
 // Source vector: if `u` is given, s = m .* u (lumped mass, M u_j of the algorithm); else s = svec.
 __device__ __forceinline__ c64 load_s(const double* __restrict__ m, const double* __restrict__ u,
@@ -679,6 +765,26 @@ int launch_sens(hipStream_t st, LevelView<double> L, const double* kappa, int ns
 }
 
 // ---------------------------------------------------------------- launchers
+template <typename T>
+int launch_net_scale(hipStream_t st, LevelView<double> L, cdouble tau, int R, T* d, const double* v, double* part,
+                     const int* active) {
+    const int nb = reduce_blocks(L.N, R);
+    k_net_dots<T><<<dim3(nb, R), kB, 0, st>>>(L, tau.real(), tau.imag(), d, v, part, active);
+    k_net_scale<T><<<dim3((L.N + kB - 1) / kB, R), kB, 0, st>>>(L.N, nb, part, d, active);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+template int launch_net_scale<float>(hipStream_t, LevelView<double>, cdouble, int, float*, const double*, double*,
+                                     const int*);
+template int launch_net_scale<double>(hipStream_t, LevelView<double>, cdouble, int, double*, const double*, double*,
+                                      const int*);
+
+int launch_net_guard(hipStream_t st, int R, int nb, const double* part, const int* active, int* bad, int* counts) {
+    k_net_guard<<<1, 256, 0, st>>>(R, nb, part, active, bad, counts);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
 static inline unsigned nb_for(size_t n) { return (unsigned)((n + kB - 1) / kB); }
 
 int launch_scatter_points(hipStream_t st, int R, int N, const int* off, const int* cell, const double* wt,

@@ -85,6 +85,8 @@ struct lt_handle {
     std::vector<lt::CoarseInverse> coarse_cache;
     std::vector<double> coarse_host;  // coarsest level coefficients [5][Nc] on the host
     lt::DevBuf kappa;                 // copy of the fine-grid conductivity (sensitivities)
+    double lnDbar = 0.0;              // mean of ln D over the fine grid (network features)
+    struct lt_unet* unet = nullptr;   // attached learned preconditioner (not owned)
     // workspaces (grow-only, owned by the handle)
     std::map<std::string, lt::DevBuf> ws;
     void* pinned = nullptr;  // small pinned host area for flags

@@ -423,6 +423,16 @@ int mg_build(lt_handle* h, const double* kappa, const double* S) {
         LT_TRY(L.c32.reserve(sizeof(float) * 5 * (size_t)L.N));
         LT_TRY(convert_vectors<double, float>(st, L.c64.as<double>(), L.c32.as<float>(), 5 * (size_t)L.N));
     }
+    {
+        // mean of ln D on the fine grid (features of the learned preconditioner)
+        std::vector<double> D(f.N);
+        LT_HIP(hipMemcpyAsync(D.data(), lv[0].c64.as<double>() + 3 * (size_t)f.N, sizeof(double) * f.N,
+                              hipMemcpyDeviceToHost, st));
+        LT_HIP(hipStreamSynchronize(st));
+        double s = 0;
+        for (double d : D) s += std::log(d);
+        h->lnDbar = s / f.N;
+    }
     // coarsest coefficients on the host for the dense coarse solve
     const Level& Lc = lv.back();
     h->coarse_host.resize(5 * (size_t)Lc.N);
