@@ -11,8 +11,12 @@ before the timed region.  Metric: shifted solves per second (rhs x shift
 pairs / wall time), counted only when the heads agree with the CPU oracle
 to 1e-5 relative.
 
-Two variants are timed: FP64 throughout, and the FP32 V-cycle inside the
-FP64 outer solve ("mixed", the headline value).
+Three variants are timed: FP64 throughout ("fp64", the plain method), the
+FP32 V-cycle inside the FP64 outer solve ("mixed"), and "learned": mixed
+precision with the U-Net preconditioner giving each preconditioner solve its
+first guess (trained on the GPU just before, on 128x128 fields; training
+time reported separately), switched off by the solver once its guesses stop
+paying for themselves.  The headline value is the learned variant.
 """
 from __future__ import annotations
 
@@ -56,7 +60,8 @@ def _parse():
     ap.add_argument("--tol-fp64", type=float, default=1e-8)
     ap.add_argument("--tol-mixed", type=float, default=1e-7)
     ap.add_argument("--relax", type=float, default=3.0)
-    ap.add_argument("--variant", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--variant", choices=["all", "mixed", "fp64", "learned"], default="all")
+    ap.add_argument("--train-steps", type=int, default=400)
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="after the solves, copy a 512 MiB buffer once (a plain copy kernel of known "
                          "size, to scale hardware byte counters)")
@@ -135,16 +140,34 @@ def main():
     h = lt.lt_setup(p.ndim, p.n, p.h, kap, S)
     pairs = len(p.sources) * len(p.times) * (p.nz_contour // 2)
     res = {}
-    variants = [("fp64", lt.LT_PREC_FP64, args.tol_fp64), ("mixed", lt.LT_PREC_MIXED, args.tol_mixed)]
-    if args.variant != "both":
+    variants = [("fp64", lt.LT_PREC_FP64, args.tol_fp64), ("mixed", lt.LT_PREC_MIXED, args.tol_mixed),
+                ("learned", lt.LT_PREC_MIXED, args.tol_mixed)]
+    if args.variant != "all":
         variants = [v for v in variants if v[0] == args.variant]
+    training = None
+    net = None
+    if any(v[0] == "learned" for v in variants):
+        from paper_1409_2556_amd.train_unet import train
+        t0 = time.perf_counter()
+        net, hist = train(steps=args.train_steps, batch=8, lr=1e-3, verbose=False)
+        torch.cuda.synchronize()
+        training = {"steps": args.train_steps, "seconds": time.perf_counter() - t0,
+                    "final_loss_mean20": float(np.mean(hist[-20:])),
+                    "data": "128x128 GRF fields (seeds 10000-10007), point-source and smooth residuals, "
+                            "targets from lt_precond_solve"}
+        print(f"[bench] trained U-Net: {training['seconds']:.1f} s, loss {training['final_loss_mean20']:.3f}",
+              file=sys.stderr, flush=True)
+        lt.lt_unet_attach(h, net)
+    prof_name = "mixed" if any(v[0] == "mixed" for v in variants) else variants[0][0]
     for name, prec, tol in variants:
-        opts = lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau, relax=args.relax)
-        prof_kind = lt.LT_PROF_POST_FINE if name == ("mixed" if args.variant != "fp64" else "fp64") else 0
+        opts = lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau, relax=args.relax,
+                            precond=lt.LT_PRECOND_UNET_GMG if name == "learned" else lt.LT_PRECOND_GMG)
+        prof_kind = lt.LT_PROF_POST_FINE if name == prof_name else 0
         dt, st, phi, prof = _run_variant(lt, h, p, opts, args.steps, args.warmup, prof_kind)
         res[name] = dict(dt=dt, st=st, phi=phi, tol=tol, prof=prof)
         print(f"[bench] {name}: {dt * 1e3:.2f} ms/step, {pairs / dt:.0f} solves/s, iters {st['iters_max']}, "
-              f"vcycles {st['vcycles']}, true residual {st['true_relres_max']:.2e}", file=sys.stderr, flush=True)
+              f"vcycles {st['vcycles']}, true residual {st['true_relres_max']:.2e}, net applied "
+              f"{st['net_applied']} disabled after iteration {st['net_disabled_at']}", file=sys.stderr, flush=True)
     errs = {}
     if ref is not None:
         for name in res:
@@ -159,10 +182,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print("[bench] copy calibration: 536870912 bytes read and written", file=sys.stderr, flush=True)
-    hname = "mixed" if "mixed" in res else "fp64"
+    hname = "learned" if "learned" in res else ("mixed" if "mixed" in res else "fp64")
     head = res[hname]
+    pr_src = res[prof_name]
     valid = (errs.get(hname, 0.0) <= 1e-5)
-    pr = head["prof"]
+    pr = pr_src["prof"]
     roofline = None
     if pr["launches"] > 0 and pr["ms"] > 0:
         avg_s = pr["ms"] * 1e-3 / pr["launches"]
@@ -175,7 +199,7 @@ def main():
                     "avg_launch_us": avg_s * 1e6, "bytes_per_launch": bytes_per_launch,
                     "launches": pr["launches"]}
     out = {
-        "metric": "shifted solves/sec (RHS x shift, rel head err 1e-5)",
+        "metric": "shifted solves/sec (RHS\u00d7shift, rel head err 1e-5): learned+mixed vs plain FGMRES",
         "value": pairs / head["dt"] if valid else 0.0,
         "unit": "shifted solves/s",
         "n_gpus": 1,
@@ -190,18 +214,25 @@ def main():
         "config": {"workload": "2D 256x256 GRF aquifer (var 1, corr 0.1), 8 sources x 16 receivers, "
                                "10 times, 20-node Talbot, 1 tau, GMG V(2,2) RB-GS",
                    "rhs": len(p.sources), "shifts_per_rhs": len(p.times) * (p.nz_contour // 2),
-                   "pairs": pairs, "tol": head["tol"], "relax": args.relax,
+                   "pairs": pairs, "tol": head["tol"], "relax": args.relax, "variant": hname,
                    "precision": "FP32 V-cycle, FP64 outer",
                    "iters": head["st"]["iters_max"], "vcycles": head["st"]["vcycles"]},
         "variants": {
             name: {"solves_per_s": pairs / r["dt"], "ms_per_step": r["dt"] * 1e3, "tol": r["tol"],
                    "iters": r["st"]["iters_max"], "vcycles": r["st"]["vcycles"],
                    "true_relres_weighted_max": r["st"]["true_relres_max"],
+                   "net_applied": r["st"]["net_applied"], "net_disabled_after_iteration": r["st"]["net_disabled_at"],
                    "rel_head_err_vs_oracle": errs.get(name)} for name, r in res.items()},
+        "training": training,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if "fp64" in res:
+        out["vs_plain_fp64"] = (pairs / head["dt"]) / (pairs / res["fp64"]["dt"])
     print(json.dumps(out), flush=True)
+    if net is not None:
+        lt.lt_unet_attach(h, None)
+        net.close()
     h.close()
 
 

@@ -117,7 +117,11 @@ typedef struct {
  *              ny of 8); a guess that increases the residual is discarded, and
  *              the V-cycle refinement then proceeds as usual, so the V-cycle
  *              remains both the fallback and, through the true residual, the
- *              judge. */
+ *              judge.
+ *   net_keep   the network is switched off for the rest of the call after an
+ *              outer iteration in which its guess left more than this fraction
+ *              of some right-hand side's residual (default 0.05: it must do at
+ *              least the work of about two V-cycles to pay for itself). */
 typedef struct {
     double tol;
     int maxit;
@@ -130,6 +134,7 @@ typedef struct {
     int true_residual;
     int profile;
     int precond;
+    double net_keep;
 } lt_opts;
 
 /* Statistics of the last call.  Pointer members are optional host arrays the
@@ -146,6 +151,7 @@ typedef struct {
     double* true_relres;         /* [n_rhs][n_shifts] ||b - (K+zM)x|| / ||b|| or NULL */
     int net_applied;             /* network guesses applied (rhs x outer iterations) */
     int net_rejected;            /* of which discarded by the residual guard      */
+    int net_disabled_at;         /* outer iteration after which it was switched off (0: never) */
     int prof_launches;           /* profiled launches (opts.profile)          */
     double prof_ms;              /* their summed device time, milliseconds    */
     double prof_bytes;           /* their summed algorithmic bytes            */

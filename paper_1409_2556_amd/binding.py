@@ -46,14 +46,14 @@ class lt_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("precision", C.c_int), ("n_tau", C.c_int),
                 ("tau_reim", C.POINTER(C.c_double)), ("nu1", C.c_int), ("nu2", C.c_int),
                 ("inner_max", C.c_int), ("relax", C.c_double), ("true_residual", C.c_int),
-                ("profile", C.c_int), ("precond", C.c_int)]
+                ("profile", C.c_int), ("precond", C.c_int), ("net_keep", C.c_double)]
 
 
 class lt_stats(C.Structure):
     _fields_ = [("n_rhs", C.c_int), ("n_shifts", C.c_int), ("iters_max", C.c_int), ("vcycles", C.c_int),
                 ("levels", C.c_int), ("true_relres_max", C.c_double), ("seconds", C.c_double),
                 ("iters_per_rhs", C.POINTER(C.c_int)), ("true_relres", C.POINTER(C.c_double)),
-                ("net_applied", C.c_int), ("net_rejected", C.c_int),
+                ("net_applied", C.c_int), ("net_rejected", C.c_int), ("net_disabled_at", C.c_int),
                 ("prof_launches", C.c_int), ("prof_ms", C.c_double), ("prof_bytes", C.c_double)]
 
 
@@ -215,6 +215,7 @@ def _stats_dict(st, it, tr, rc, nrhs, nshift):
             "vcycles": st.vcycles, "levels": st.levels, "true_relres_max": st.true_relres_max,
             "seconds": st.seconds, "iters_per_rhs": it.copy(), "true_relres": tr.reshape(nrhs, nshift).copy(),
             "net_applied": st.net_applied, "net_rejected": st.net_rejected,
+            "net_disabled_at": st.net_disabled_at,
             "prof_launches": st.prof_launches, "prof_ms": st.prof_ms, "prof_bytes": st.prof_bytes}
 
 

@@ -102,7 +102,7 @@ int validate_opts(const lt_opts* o) {
     if (!o) return 0;
     if (!(o->tol > 0.0) || o->maxit < 1 || o->maxit > 2000 || o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 ||
         o->inner_max < 1 || !(o->relax > 0.0) || o->profile < 0 || o->profile > LT_PROF_POST_FINE ||
-        (o->precond != LT_PRECOND_GMG && o->precond != LT_PRECOND_UNET_GMG) ||
+        (o->precond != LT_PRECOND_GMG && o->precond != LT_PRECOND_UNET_GMG) || !(o->net_keep >= 0.0) ||
         (o->precision != LT_PREC_FP64 && o->precision != LT_PREC_MIXED)) {
         set_last_error("invalid lt_opts");
         return LT_EINVAL;
@@ -124,7 +124,7 @@ struct KrylovOut {
     double* omega = nullptr;  // [Ks]
     double* wq = nullptr;     // [Ks] complex
     int iters_max = 0, vcycles = 0;
-    int net_applied = 0, net_rejected = 0;
+    int net_applied = 0, net_rejected = 0, net_disabled_at = 0;
     bool converged = true;
 };
 
@@ -183,7 +183,7 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     double* scale = small;
     double* beta = small + R;
     double* worst = small + 2 * R;
-    int* ints = wsp<int>(h, "ints", 5 * (size_t)R + 8, &rc);  // masks, counts, [count, steps needed], net stats
+    int* ints = wsp<int>(h, "ints", 5 * (size_t)R + 8, &rc);  // netc has 3 entries at 5R + 4  // masks, counts, [count, steps needed], net stats
     if (!ints) return rc;
     int* active = ints;
     int* inner_active = ints + R;
@@ -191,8 +191,8 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     int* vcyc = ints + 3 * R;
     int* count = ints + 4 * R;
     int* bad = ints + 4 * R + 4;      // [R] network guesses to discard
-    int* netc = ints + 5 * R + 4;     // [2] applied, rejected
-    const bool use_net = o.precond == LT_PRECOND_UNET_GMG && h->unet != nullptr;
+    int* netc = ints + 5 * R + 4;     // [3] applied, rejected, worst residual ratio (float bits)
+    bool use_net = o.precond == LT_PRECOND_UNET_GMG && h->unet != nullptr;
     if (o.precond == LT_PRECOND_UNET_GMG &&
         (!h->unet || h->grid.ndim != 2 || h->grid.n[0] % 128 || h->grid.n[1] % 8)) {
         set_last_error("LT_PRECOND_UNET_GMG needs an attached network and a 2D grid with nx % 128 == 0, ny % 8 == 0");
@@ -326,8 +326,19 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
             LT_HIP(hipMemcpyAsync(hflag, count, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
             // convergence flags as left by the previous outer iteration's least squares
             LT_HIP(hipMemcpyAsync(hact, active, R * sizeof(int), hipMemcpyDeviceToHost, st));
+            if (use_net) LT_HIP(hipMemcpyAsync(hflag + 2, netc + 2, sizeof(int), hipMemcpyDeviceToHost, st));
             LT_HIP(hipStreamSynchronize(st));
             if (*hflag == 0) break;
+        }
+        if (use_net) {
+            // keep the network only while its guess removes at least the fraction 1 - net_keep
+            // of the residual; otherwise the V-cycle refinement alone continues
+            float worst_ratio;
+            std::memcpy(&worst_ratio, hflag + 2, sizeof(float));
+            if (!(worst_ratio <= o.net_keep)) {
+                use_net = false;
+                out->net_disabled_at = j + 1;
+            }
         }
         if (debug) {
             std::vector<int> vc(R);
@@ -455,6 +466,7 @@ void fill_stats(lt_stats* s, const KrylovOut& k, int nlev, double secs) {
     s->vcycles = k.vcycles;
     s->net_applied = k.net_applied;
     s->net_rejected = k.net_rejected;
+    s->net_disabled_at = k.net_disabled_at;
     s->levels = nlev;
     s->seconds = secs;
 }
@@ -477,6 +489,7 @@ void lt_opts_default(lt_opts* o) {
     o->relax = 1.0;
     o->true_residual = 1;
     o->precond = LT_PRECOND_GMG;
+    o->net_keep = 0.05;
 }
 
 const char* lt_strerror(int code) {

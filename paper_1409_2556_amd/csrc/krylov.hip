@@ -189,11 +189,15 @@ __global__ void k_inner_finalize(int R, int nb, const double* __restrict__ part,
     }
 }
 
-// bad[r] = active[r] && ||rho_r||^2 > 1 (the network guess made the unit residual worse)
+// bad[r] = active[r] && ||rho_r||^2 > 1 (the network guess made the unit residual worse);
+// counts[2] = bit pattern of the worst residual ratio over the active right-hand sides
 __global__ void k_net_guard(int R, int nb, const double* __restrict__ part, const int* __restrict__ active,
                             int* __restrict__ bad, int* __restrict__ counts) {
     __shared__ int nbad, nact;
     if (threadIdx.x == 0) { nbad = 0; nact = 0; }
+    __syncthreads();
+    __shared__ float worst;
+    if (threadIdx.x == 0) worst = 0.0f;
     __syncthreads();
     for (int r = threadIdx.x; r < R; r += blockDim.x) {
         int b = 0;
@@ -203,6 +207,9 @@ __global__ void k_net_guard(int R, int nb, const double* __restrict__ part, cons
             b = !(s <= 1.0);
             atomicAdd(&nact, 1);
             if (b) atomicAdd(&nbad, 1);
+            // residual ratio ||rho|| / ||v|| left by the guess (v has unit norm); 1 if discarded
+            const float ratio = b ? 1.0f : (float)sqrt(s);
+            atomicMax((int*)&worst, __float_as_int(ratio));  // non-negative floats order like ints
         }
         bad[r] = b;
     }
@@ -210,6 +217,7 @@ __global__ void k_net_guard(int R, int nb, const double* __restrict__ part, cons
     if (threadIdx.x == 0) {
         counts[0] += nact;
         counts[1] += nbad;
+        counts[2] = __float_as_int(worst);
     }
 }
 
