@@ -189,6 +189,57 @@ int lt_adjoint(lt_handle* h, const lt_points* sources, double q, const lt_points
                const double* times, int ntimes, const lt_contour* contour, const lt_opts* opts,
                double* dlnK, double* dlnS, lt_stats* stats);
 
+/* ---- batches of problems ----------------------------------------------
+ * Every shift of every right-hand side of several problems, possibly on
+ * grids of different shapes and dimensions, solved in one call: each item
+ * is the argument list of one lt_solve (or lt_adjoint) on its own handle.
+ * The shifted systems of all problems are independent (Section 3: one
+ * basis per right-hand side serves its shifts; nothing couples right-hand
+ * sides or problems), so the items run concurrently, one host thread per
+ * item driving its handle's stream; the GPU interleaves the workgroups of
+ * all streams.  Give every handle its own stream (lt_setup) for the items
+ * to overlap; handles sharing a stream still give correct results, one
+ * after another.  Every handle may appear once per call (handles are not
+ * thread-safe), and a network attached to a handle whose item selects
+ * LT_PRECOND_UNET_GMG may serve only that item.  Outputs and per-item
+ * return codes (status) are the same as lt_solve's / lt_adjoint's for the
+ * item alone: the kernels are deterministic, so results are bit-identical.
+ * Returns the first negative status in item order if any item failed,
+ * else LT_WNOTCONV if any item missed its tolerance, else LT_OK.
+ * LT_EINVAL for n < 1, n > 64, a NULL items or handle, or the sharing
+ * rules above (then no item runs). */
+typedef struct {
+    lt_handle* h;
+    const lt_points* sources;
+    double q;
+    const double* times;      /* host [ntimes] */
+    int ntimes;
+    const lt_contour* contour;
+    const lt_points* receivers;
+    const lt_opts* opts;      /* NULL: lt_opts_default */
+    double* phi_out;          /* device float64 [ns][nr][ntimes] */
+    lt_stats* stats;          /* or NULL */
+    int status;               /* out: the item's return code */
+} lt_solve_item;
+
+typedef struct {
+    lt_handle* h;
+    const lt_points* sources;
+    double q;
+    const lt_points* receivers;
+    const double* times;      /* host [ntimes] */
+    int ntimes;
+    const lt_contour* contour;
+    const lt_opts* opts;      /* NULL: lt_opts_default */
+    double* dlnK;             /* device float64 [ns][nr][ntimes][N] or NULL */
+    double* dlnS;             /* same shape or NULL (not both NULL) */
+    lt_stats* stats;          /* or NULL */
+    int status;               /* out */
+} lt_adjoint_item;
+
+int lt_solve_batch(lt_solve_item* items, int n);
+int lt_adjoint_batch(lt_adjoint_item* items, int n);
+
 /* Talbot nodes and weights for one time (host arrays of nz/2 complex values
  * as (re, im) pairs, nodes with Im z > 0 in increasing theta):
  * phi(t) ~ 2 Re sum_k w_k F(z_k).  eq:talbot, eqn:quadrature, eqn:half. */

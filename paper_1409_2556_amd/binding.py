@@ -61,6 +61,20 @@ _vp = C.c_void_p
 _dp = C.POINTER(C.c_double)
 _h = C.c_void_p
 
+
+class lt_solve_item(C.Structure):
+    _fields_ = [("h", _h), ("sources", C.POINTER(lt_points)), ("q", C.c_double), ("times", _dp),
+                ("ntimes", C.c_int), ("contour", C.POINTER(lt_contour)), ("receivers", C.POINTER(lt_points)),
+                ("opts", C.POINTER(lt_opts)), ("phi_out", _vp), ("stats", C.POINTER(lt_stats)),
+                ("status", C.c_int)]
+
+
+class lt_adjoint_item(C.Structure):
+    _fields_ = [("h", _h), ("sources", C.POINTER(lt_points)), ("q", C.c_double),
+                ("receivers", C.POINTER(lt_points)), ("times", _dp), ("ntimes", C.c_int),
+                ("contour", C.POINTER(lt_contour)), ("opts", C.POINTER(lt_opts)), ("dlnK", _vp), ("dlnS", _vp),
+                ("stats", C.POINTER(lt_stats)), ("status", C.c_int)]
+
 _lib.lt_opts_default.argtypes = [C.POINTER(lt_opts)]
 _lib.lt_opts_default.restype = None
 _lib.lt_setup.argtypes = [C.POINTER(lt_grid), _vp, _vp, C.POINTER(lt_bc), _vp, C.POINTER(_h)]
@@ -71,6 +85,10 @@ _lib.lt_solve.restype = C.c_int
 _lib.lt_adjoint.argtypes = [_h, C.POINTER(lt_points), C.c_double, C.POINTER(lt_points), _dp, C.c_int,
                             C.POINTER(lt_contour), C.POINTER(lt_opts), _vp, _vp, C.POINTER(lt_stats)]
 _lib.lt_adjoint.restype = C.c_int
+_lib.lt_solve_batch.argtypes = [C.POINTER(lt_solve_item), C.c_int]
+_lib.lt_solve_batch.restype = C.c_int
+_lib.lt_adjoint_batch.argtypes = [C.POINTER(lt_adjoint_item), C.c_int]
+_lib.lt_adjoint_batch.restype = C.c_int
 _lib.lt_talbot.argtypes = [C.c_int, C.c_double, _dp, _dp]
 _lib.lt_talbot.restype = C.c_int
 _lib.lt_apply_operator.argtypes = [_h, C.c_int, C.c_double, C.c_double, _vp, _vp, C.c_int]
@@ -258,6 +276,73 @@ def lt_adjoint(handle: Handle, sources, q, receivers, times, nz, opts: lt_opts |
     return dlnK, dlnS, _stats_dict(st, it, tr, rc, ns + nr, nt * (int(nz) // 2))
 
 
+def lt_solve_batch(problems):
+    """Solve several problems in one lt_solve_batch call.
+
+    ``problems``: sequence of dicts with keys handle, sources, q, times, nz,
+    receivers and optionally opts and phi_out (the arguments of lt_solve).
+    Returns (list of phi tensors, list of stats dicts, batch return code).
+    """
+    import torch
+    n = len(problems)
+    items = (lt_solve_item * n)()
+    keep, outs, meta = [], [], []
+    for i, pr in enumerate(problems):
+        sp, sa = _points(pr["sources"])
+        rp, ra = _points(pr["receivers"])
+        t = np.ascontiguousarray(np.asarray(pr["times"], dtype=np.float64).ravel())
+        ns, nr, nt = sa.shape[0], ra.shape[0], t.size
+        nz = int(pr["nz"])
+        phi = pr.get("phi_out")
+        if phi is None:
+            phi = torch.empty((ns, nr, nt), dtype=torch.float64, device="cuda")
+        con = lt_contour(nz)
+        o = pr.get("opts") or lt_opts_default()
+        st, it, tr = _stats(ns, nt * (nz // 2))
+        keep.append((sp, sa, rp, ra, t, con, o, st, it, tr))
+        items[i] = lt_solve_item(pr["handle"].ptr, C.pointer(sp), float(pr.get("q", 1.0)), t.ctypes.data_as(_dp),
+                                 nt, C.pointer(con), C.pointer(rp), C.pointer(o), _dev_f64(phi, "phi_out"),
+                                 C.pointer(st), 0)
+        outs.append(phi)
+        meta.append((ns, nt * (nz // 2)))
+    rc = _check(_lib.lt_solve_batch(items, n))
+    stats = [_stats_dict(k[7], k[8], k[9], items[i].status, *meta[i]) for i, k in enumerate(keep)]
+    return outs, stats, rc
+
+
+def lt_adjoint_batch(problems):
+    """Sensitivities of several problems in one lt_adjoint_batch call.
+
+    ``problems``: dicts with keys handle, sources, q, receivers, times, nz and
+    optionally opts.  Returns (list of (dlnK, dlnS), list of stats, code).
+    """
+    import torch
+    n = len(problems)
+    items = (lt_adjoint_item * n)()
+    keep, outs, meta = [], [], []
+    for i, pr in enumerate(problems):
+        sp, sa = _points(pr["sources"])
+        rp, ra = _points(pr["receivers"])
+        t = np.ascontiguousarray(np.asarray(pr["times"], dtype=np.float64).ravel())
+        ns, nr, nt = sa.shape[0], ra.shape[0], t.size
+        nz = int(pr["nz"])
+        shape = (ns, nr, nt, pr["handle"].N)
+        dK = torch.empty(shape, dtype=torch.float64, device="cuda")
+        dS = torch.empty(shape, dtype=torch.float64, device="cuda")
+        con = lt_contour(nz)
+        o = pr.get("opts") or lt_opts_default()
+        st, it, tr = _stats(ns + nr, nt * (nz // 2))
+        keep.append((sp, sa, rp, ra, t, con, o, st, it, tr))
+        items[i] = lt_adjoint_item(pr["handle"].ptr, C.pointer(sp), float(pr.get("q", 1.0)), C.pointer(rp),
+                                   t.ctypes.data_as(_dp), nt, C.pointer(con), C.pointer(o),
+                                   _dev_f64(dK, "dlnK"), _dev_f64(dS, "dlnS"), C.pointer(st), 0)
+        outs.append((dK, dS))
+        meta.append((ns + nr, nt * (nz // 2)))
+    rc = _check(_lib.lt_adjoint_batch(items, n))
+    stats = [_stats_dict(k[7], k[8], k[9], items[i].status, *meta[i]) for i, k in enumerate(keep)]
+    return outs, stats, rc
+
+
 def lt_talbot(nz, t):
     """Upper-half Talbot nodes and weights (complex numpy arrays) computed by the library."""
     z = np.zeros(nz, dtype=np.float64)
@@ -296,7 +381,8 @@ def exported_symbols():
 _ABI_NAMES = ["lt_opts_default", "lt_setup", "lt_solve", "lt_adjoint", "lt_talbot", "lt_apply_operator",
               "lt_vcycle", "lt_level_shape", "lt_strerror", "lt_last_error", "lt_destroy", "lt_unet_create",
               "lt_unet_nparams", "lt_unet_get_params", "lt_unet_set_params", "lt_unet_apply",
-              "lt_unet_train_step", "lt_unet_grad", "lt_unet_attach", "lt_unet_destroy", "lt_precond_solve"]
+              "lt_unet_train_step", "lt_unet_grad", "lt_unet_attach", "lt_unet_destroy", "lt_precond_solve",
+              "lt_solve_batch", "lt_adjoint_batch"]
 
 
 # ---------------------------------------------------------------- learned preconditioner

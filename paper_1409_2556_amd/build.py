@@ -9,12 +9,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblt.so")
 
-SOURCES = ["mg.hip", "mg_fused.hip", "krylov.hip", "unet.hip", "api.hip", "plan.cpp"]
+SOURCES = ["mg.hip", "mg_fused.hip", "krylov.hip", "unet.hip", "api.hip", "plan.cpp", "batch.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",
     # packed FP32 instructions are kept out of the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+    "-pthread", "-Wall", "-Wno-unused-function", "-Wno-unused-result",
 ]
 
 

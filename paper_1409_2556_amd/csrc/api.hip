@@ -543,6 +543,11 @@ int lt_setup(const lt_grid* grid, const double* kappa, const double* S, const lt
         }
     }
     h->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        set_last_error("lt_setup: no HIP device");
+        return LT_EHIP;
+    }
     h->N = (int)Nll;
     int rc = mg_build(h, kappa, S);
     if (rc >= 0) rc = h->kappa.reserve(sizeof(double) * (size_t)h->N);

@@ -80,6 +80,7 @@ struct lt_handle {
     lt_grid grid;
     lt_bc bc;
     hipStream_t stream;
+    int device = 0;  // HIP device current at setup
     int N;
     std::vector<lt::Level> levels;
     std::vector<lt::CoarseInverse> coarse_cache;

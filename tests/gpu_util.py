@@ -18,3 +18,15 @@ def rel_err_per_source(got, ref):
 
 def announce(*a):
     print("[case]", *a, flush=True)
+
+
+def device_problem_on_stream(lt, p):
+    """Handle on a new stream of its own (default priority), for concurrent batches."""
+    import torch
+    kap = torch.tensor(p.kappa, dtype=torch.float64, device="cuda")
+    S = torch.tensor(p.S, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    h = lt.lt_setup(p.ndim, p.n, p.h, kap, S, bc=p.bc, stream=s)
+    h._torch_stream = s
+    return h

@@ -51,3 +51,12 @@ def test_error_codes_without_gpu(lib):
     o = lib.lt_opts_default()
     assert o.tol == 1e-10 and o.nu1 == 2 and o.nu2 == 2 and o.precision == lib.LT_PREC_FP64
     so.lt_destroy(None)  # accepted
+    # batches are checked before any GPU work: no items, too many, a missing handle
+    items = (lib.lt_solve_item * 2)()
+    assert so.lt_solve_batch(None, 1) == lib.LT_EINVAL
+    assert so.lt_solve_batch(items, 0) == lib.LT_EINVAL
+    assert so.lt_solve_batch(items, 65) == lib.LT_EINVAL
+    assert so.lt_solve_batch(items, 2) == lib.LT_EINVAL
+    assert "no handle" in lib.lt_last_error()
+    adj = (lib.lt_adjoint_item * 1)()
+    assert so.lt_adjoint_batch(adj, 1) == lib.LT_EINVAL

@@ -8,6 +8,6 @@ the operator.  Both the CPU oracle and the GPU path read their inputs
 from here.
 """
 from .grf import gaussian_random_field
-from .configs import CONFIGS, T_D, make_problem, Problem
+from .configs import C5_BATCH, CONFIGS, T_D, make_batch, make_problem, Problem
 
-__all__ = ["gaussian_random_field", "CONFIGS", "T_D", "make_problem", "Problem"]
+__all__ = ["gaussian_random_field", "CONFIGS", "C5_BATCH", "T_D", "make_batch", "make_problem", "Problem"]

@@ -111,6 +111,13 @@ _C3_SOURCES = np.array([(x, y, 0.5) for y in np.linspace(0.2, 0.8, 5)
 _C3_RECEIVERS = np.array([(x, y, z) for z in (0.25, 0.5, 0.75)
                           for y in (0.2, 0.4, 0.6, 0.8) for x in (0.2, 0.4, 0.6, 0.8)])
 
+_C5_SOURCES_2D = _wells_2d([0.2, 0.4, 0.6, 0.8])
+_C5_RECEIVERS_2D = np.array([(x, y, 0.0) for y in (0.2, 0.4, 0.6, 0.8)
+                             for x in (0.1, 0.2, 0.3, 0.4, 0.6, 0.7, 0.8, 0.9)])
+_C5_SOURCES_3D = np.array([(x, y, 0.5) for y in (0.2, 0.4, 0.6, 0.8) for x in (0.2, 0.4, 0.6, 0.8)])
+_C5_RECEIVERS_3D = np.array([(x, y, z) for z in (0.25, 0.75)
+                             for y in (0.3, 0.5, 0.7, 0.9) for x in (0.3, 0.5, 0.7, 0.9)])
+
 CONFIGS = {
     # 2D 32x32, one central source, four receivers, 5 times, 16-node contour
     "C1": dict(n=(32, 32), var=1.0, ell=(0.2, 0.2, 0.2), seed=101, S=1e-5,
@@ -131,6 +138,31 @@ CONFIGS = {
                    sources=_C2_SOURCES, receivers=_C2_WELLS, times=[0.3], nz=40, n_tau=1),
     "C4_512": dict(n=(512, 512), var=1.0, ell=(0.1, 0.1, 0.1), seed=20001, S=1e-5,
                    sources=_C2_SOURCES, receivers=_C2_WELLS, times=[0.3], nz=40, n_tau=1),
+    # a batch of six problems on uneven grids (2D as the 256x256 workload, 3D as
+    # the 64x64x32 one): 16 sources and 32 receivers each, times {0.3, 1.2}, 24 nodes
+    "C5_128": dict(n=(128, 128), var=1.0, ell=(0.1, 0.1, 0.1), seed=501, S=1e-5,
+                   sources=_C5_SOURCES_2D, receivers=_C5_RECEIVERS_2D, times=[0.3, 1.2], nz=24, n_tau=1),
+    "C5_256": dict(n=(256, 256), var=1.0, ell=(0.1, 0.1, 0.1), seed=502, S=1e-5,
+                   sources=_C5_SOURCES_2D, receivers=_C5_RECEIVERS_2D, times=[0.3, 1.2], nz=24, n_tau=1),
+    "C5_512": dict(n=(512, 512), var=1.0, ell=(0.1, 0.1, 0.1), seed=503, S=1e-5,
+                   sources=_C5_SOURCES_2D, receivers=_C5_RECEIVERS_2D, times=[0.3, 1.2], nz=24, n_tau=1),
+    "C5_32c": dict(n=(32, 32, 32), var=2.0, ell=(0.2, 0.2, 0.05), seed=504,
+                   S_loguniform=(1e-6, 1e-4), S_seed=514,
+                   sources=_C5_SOURCES_3D, receivers=_C5_RECEIVERS_3D, times=[0.3, 1.2], nz=24, n_tau=3),
+    "C5_64c": dict(n=(64, 64, 64), var=2.0, ell=(0.2, 0.2, 0.05), seed=505,
+                   S_loguniform=(1e-6, 1e-4), S_seed=515,
+                   sources=_C5_SOURCES_3D, receivers=_C5_RECEIVERS_3D, times=[0.3, 1.2], nz=24, n_tau=3),
+    "C5_128x64": dict(n=(128, 128, 64), var=2.0, ell=(0.2, 0.2, 0.05), seed=506,
+                      S_loguniform=(1e-6, 1e-4), S_seed=516,
+                      sources=_C5_SOURCES_3D, receivers=_C5_RECEIVERS_3D, times=[0.3, 1.2], nz=24, n_tau=3),
     "C4_train": dict(n=(128, 128), var=1.0, ell=(0.1, 0.1, 0.1), seed=10000, S=1e-5,
                      sources=_C2_SOURCES, receivers=_C2_WELLS, times=[0.3], nz=40, n_tau=1),
 }
+
+
+C5_BATCH = ("C5_128", "C5_256", "C5_512", "C5_32c", "C5_64c", "C5_128x64")
+
+
+def make_batch(names=C5_BATCH, **kw):
+    """The problems of a batch workload (by default the six uneven grids)."""
+    return [make_problem(nm, **kw) for nm in names]

@@ -11,7 +11,19 @@ samples, of which the first is returned.
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
+
+# embeddings of at least this many points use the threaded FFT (same transform)
+_BIG = 1 << 22
+
+
+def _fftn(a):
+    if a.size >= _BIG:
+        import scipy.fft
+        return scipy.fft.fftn(a, workers=min(16, os.cpu_count() or 1))
+    return np.fft.fftn(a)
 
 
 def _embedding_eigs(n, h, ell, var, pad):
@@ -24,7 +36,7 @@ def _embedding_eigs(n, h, ell, var, pad):
     grids = np.meshgrid(*axes, indexing="ij")
     r = np.sqrt(sum(g * g for g in grids))
     c = var * np.exp(-r)
-    lam = np.fft.fftn(c).real
+    lam = _fftn(c).real
     return lam
 
 
@@ -47,6 +59,6 @@ def gaussian_random_field(n, h, ell, var, seed, mean=0.0):
     rng = np.random.default_rng(seed)
     shape = lam.shape
     xi = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
-    z = np.fft.fftn(np.sqrt(lam / lam.size) * xi)
+    z = _fftn(np.sqrt(lam / lam.size) * xi)
     field = z.real[tuple(slice(0, a) for a in n)]
     return mean + field
