@@ -121,7 +121,13 @@ typedef struct {
  *   net_keep   the network is switched off for the rest of the call after an
  *              outer iteration in which its guess left more than this fraction
  *              of some right-hand side's residual (default 0.05: it must do at
- *              least the work of about two V-cycles to pay for itself). */
+ *              least the work of about two V-cycles to pay for itself).
+ *   graph      1: each refinement step (V-cycle, FP64 update, stopping
+ *              test) is captured once as a HIP graph per shift, buffer set
+ *              and size, and replayed; 0 (default): launched kernel by
+ *              kernel.  Results are identical.  Needs a handle on a stream
+ *              of its own (the legacy default stream cannot be captured;
+ *              there, and when profiling, steps are launched directly). */
 typedef struct {
     double tol;
     int maxit;
@@ -135,6 +141,7 @@ typedef struct {
     int profile;
     int precond;
     double net_keep;
+    int graph;
 } lt_opts;
 
 /* Statistics of the last call.  Pointer members are optional host arrays the

@@ -46,7 +46,8 @@ class lt_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("precision", C.c_int), ("n_tau", C.c_int),
                 ("tau_reim", C.POINTER(C.c_double)), ("nu1", C.c_int), ("nu2", C.c_int),
                 ("inner_max", C.c_int), ("relax", C.c_double), ("true_residual", C.c_int),
-                ("profile", C.c_int), ("precond", C.c_int), ("net_keep", C.c_double)]
+                ("profile", C.c_int), ("precond", C.c_int), ("net_keep", C.c_double),
+                ("graph", C.c_int)]
 
 
 class lt_stats(C.Structure):

@@ -64,6 +64,8 @@ lt_handle::~lt_handle() {
         c.inv64.release();
         c.inv32.release();
     }
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second.first);
+    graphs.clear();
     for (auto& kv : ws) kv.second.release();
     kappa.release();
     if (pinned) (void)hipHostFree(pinned);
@@ -103,6 +105,7 @@ int validate_opts(const lt_opts* o) {
     if (!(o->tol > 0.0) || o->maxit < 1 || o->maxit > 2000 || o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 ||
         o->inner_max < 1 || !(o->relax > 0.0) || o->profile < 0 || o->profile > LT_PROF_POST_FINE ||
         (o->precond != LT_PRECOND_GMG && o->precond != LT_PRECOND_UNET_GMG) || !(o->net_keep >= 0.0) ||
+        (o->graph != 0 && o->graph != 1) ||
         (o->precision != LT_PREC_FP64 && o->precision != LT_PREC_MIXED)) {
         set_last_error("invalid lt_opts");
         return LT_EINVAL;
@@ -127,6 +130,106 @@ struct KrylovOut {
     int net_applied = 0, net_rejected = 0, net_disabled_at = 0;
     bool converged = true;
 };
+
+// One step of the iterative refinement of u_j ~ (K + tau M)^{-1} v_j for the
+// right-hand sides still marked in inner_active: a V-cycle on the current
+// residual, the FP64 update u_j += e, rho -= (K + tau M) e (fused into the
+// fine post-smoother where the level allows), and the stopping test.  Only
+// enqueues work; u_j is U advanced by the device column index jdev.
+// *swapped = 1 when the FP64 residual moved to rho_next.
+int refine_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, size_t ustride, const int* jdev,
+                float* e32, double* e64, float* lo32, float* lo32_next, double* rho, double* rho_next, double* part,
+                const int* active, int* inner_active, const double* worst, int* vcyc, int* count, int* swapped) {
+    hipStream_t st = h->stream;
+    const LevelView<double> L0 = h->levels[0].v64();
+    int nparts = -1;
+    *swapped = 0;
+    if (o.precision == LT_PREC_MIXED) {
+        // the FP32 copy of rho is double-buffered so that halo loads of this
+        // V-cycle's input never race with the fused update
+        RefineArgs ra{U, ustride, jdev, rho, rho, lo32_next, part, &nparts};
+        LT_TRY(mg_vcycle<float>(h, tau, o.nu1, o.nu2, R, inner_active, e32, lo32, &ra));
+        if (nparts < 0) {
+            LT_TRY(launch_inner_update<float>(st, L0, tau, R, e32, U, ustride, jdev, rho, lo32_next, part,
+                                              inner_active));
+            nparts = reduce_blocks(h->N, R);
+        }
+    } else {
+        RefineArgs ra{U, ustride, jdev, rho, rho_next, nullptr, part, &nparts};
+        LT_TRY(mg_vcycle<double>(h, tau, o.nu1, o.nu2, R, inner_active, e64, rho, &ra));
+        if (nparts < 0) {
+            LT_TRY(launch_inner_update<double>(st, L0, tau, R, e64, U, ustride, jdev, rho, (double*)nullptr, part,
+                                               inner_active));
+            nparts = reduce_blocks(h->N, R);
+        } else {
+            *swapped = 1;
+        }
+    }
+    return launch_inner_finalize(st, nparts, R, part, active, worst, o.relax * o.tol, o.tol, o.inner_max,
+                                 inner_active, vcyc, count);
+}
+
+// refine_step captured once as a HIP graph and replayed.  Everything a
+// captured step bakes in is part of the key: sizes, options, the shift, the
+// buffers, and the workspace generation (any reallocation retires all graphs).
+int graph_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, size_t ustride, const int* jdev,
+               float* e32, double* e64, float* lo32, float* lo32_next, double* rho, double* rho_next, double* part,
+               const int* active, int* inner_active, const double* worst, int* vcyc, int* count, int* swapped) {
+    hipStream_t st = h->stream;
+    int rc = 0;
+    // the coarse inverse for tau is built on the host and uploaded: do it before capturing
+    mg_coarse_inverse(h, tau, &rc);
+    if (rc < 0) return rc;
+    if (h->graphs_gen != h->ws_gen) {
+        for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second.first);
+        h->graphs.clear();
+        h->graphs_gen = h->ws_gen;
+    }
+    auto bits = [](double v) {
+        unsigned long long b;
+        std::memcpy(&b, &v, sizeof(b));
+        return b;
+    };
+    auto ptr = [](const void* p) { return (unsigned long long)(uintptr_t)p; };
+    std::vector<unsigned long long> key = {
+        (unsigned long long)o.precision, (unsigned long long)R, (unsigned long long)o.nu1, (unsigned long long)o.nu2,
+        bits(tau.real()), bits(tau.imag()), bits(o.relax * o.tol), bits(o.tol), (unsigned long long)o.inner_max,
+        ptr(U), ustride, ptr(jdev), ptr(e32), ptr(e64), ptr(lo32), ptr(lo32_next), ptr(rho), ptr(rho_next),
+        ptr(part), ptr(active), ptr(inner_active), ptr(worst), ptr(vcyc), ptr(count), h->ws_gen};
+    auto it = h->graphs.find(key);
+    if (it == h->graphs.end()) {
+        if (h->graphs.size() >= 64) {
+            for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second.first);
+            h->graphs.clear();
+        }
+        const unsigned long long gen = h->ws_gen;
+        LT_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        int sw = 0;
+        const int rcs = refine_step(h, o, R, tau, U, ustride, jdev, e32, e64, lo32, lo32_next, rho, rho_next, part,
+                                    active, inner_active, worst, vcyc, count, &sw);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(st, &g);
+        if (rcs < 0 || ec != hipSuccess || h->ws_gen != gen) {
+            if (g) (void)hipGraphDestroy(g);
+            if (rcs < 0) return rcs;
+            if (ec != hipSuccess) {
+                set_last_error(std::string("capturing a refinement step: ") + hipGetErrorString(ec));
+                return LT_EHIP;
+            }
+            // a workspace moved while capturing: launch this step directly
+            return refine_step(h, o, R, tau, U, ustride, jdev, e32, e64, lo32, lo32_next, rho, rho_next, part,
+                               active, inner_active, worst, vcyc, count, swapped);
+        }
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        LT_HIP(ei);
+        it = h->graphs.emplace(key, std::make_pair(ex, sw)).first;
+    }
+    *swapped = it->second.second;
+    LT_HIP(hipGraphLaunch(it->second.first, st));
+    return 0;
+}
 
 // Batched flexible shifted GMRES for R right-hand sides b (device [R][2][N], already
 // filled).  Gathers B_rec u_j for `rec` if given.
@@ -254,6 +357,9 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     }
     const LevelView<double> L0 = h->levels[0].v64();
     const double* m = L0.m;
+    int* jdev = count + 3;  // basis column the refinement steps update (device)
+    // captured steps need a stream of the handle's own (the legacy default stream cannot be captured)
+    const bool use_graphs = o.graph && !h->prof_target && st != nullptr;
     int n_active = R;
     int j = 0;
     int inner_guess = 2;
@@ -263,7 +369,8 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
         cdouble tau = plan.tau_sched[j % plan.tau_sched.size()];
         // inner refinement of u_j ~ (K + tau M)^{-1} v_j
         LT_HIP(hipMemcpyAsync(inner_active, active, R * sizeof(int), hipMemcpyDeviceToDevice, st));
-        LT_HIP(hipMemsetAsync(count + 1, 0, sizeof(int), st));
+        LT_HIP(hipMemsetAsync(count + 1, 0, 2 * sizeof(int), st));  // steps needed, steps taken
+        LT_TRY(launch_set_int(st, jdev, j));
         double* uj = U + (size_t)j * N2;
         const double* vj = Q + (size_t)j * N2;
         if (mixed)
@@ -278,13 +385,13 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
             if (mixed) {
                 LT_TRY(unet_apply<float>(net, st, L0, h->lnDbar, tau, R, lo32, e32, active));
                 LT_TRY(launch_net_scale<float>(st, L0, tau, R, e32, rho, part, active));
-                LT_TRY(launch_inner_update<float>(st, L0, tau, R, e32, uj, ustride, rho, lo32, part, active));
+                LT_TRY(launch_inner_update<float>(st, L0, tau, R, e32, uj, ustride, nullptr, rho, lo32, part, active));
                 LT_TRY(launch_net_guard(st, R, nbr, part, active, bad, netc));
                 LT_TRY(launch_inner_init<float>(st, N, R, qstride, vj, uj, ustride, rho, lo32, bad));
             } else {
                 LT_TRY(unet_apply<double>(net, st, L0, h->lnDbar, tau, R, rho, e64, active));
                 LT_TRY(launch_net_scale<double>(st, L0, tau, R, e64, rho, part, active));
-                LT_TRY(launch_inner_update<double>(st, L0, tau, R, e64, uj, ustride, rho, (double*)nullptr, part,
+                LT_TRY(launch_inner_update<double>(st, L0, tau, R, e64, uj, ustride, nullptr, rho, (double*)nullptr, part,
                                                    active));
                 LT_TRY(launch_net_guard(st, R, nbr, part, active, bad, netc));
                 LT_TRY(launch_inner_init<double>(st, N, R, qstride, vj, uj, ustride, rho, (double*)nullptr, bad));
@@ -297,31 +404,16 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
         while (step < o.inner_max) {
             const int batch = step == 0 ? std::min(inner_guess, o.inner_max) : 1;
             for (int b2 = 0; b2 < batch; ++b2, ++step) {
-                // rho (FP64) and its FP32 copy are double-buffered so that halo loads of the
-                // next V-cycle input never race with the fused update
-                int nparts = -1;
-                if (mixed) {
-                    RefineArgs ra{uj, ustride, rho, rho, lo32_next, part, &nparts};
-                    LT_TRY(mg_vcycle<float>(h, tau, o.nu1, o.nu2, R, inner_active, e32, lo32, &ra));
-                    if (nparts < 0) {
-                        LT_TRY(launch_inner_update<float>(st, L0, tau, R, e32, uj, ustride, rho, lo32_next, part,
-                                                          inner_active));
-                        nparts = reduce_blocks(N, R);
-                    }
-                    std::swap(lo32, lo32_next);
+                int swapped = 0;
+                if (use_graphs && j > 0) {
+                    LT_TRY(graph_step(h, o, R, tau, U, ustride, jdev, e32, e64, lo32, lo32_next, rho, rho_next, part,
+                                      active, inner_active, worst, vcyc, count, &swapped));
                 } else {
-                    RefineArgs ra{uj, ustride, rho, rho_next, nullptr, part, &nparts};
-                    LT_TRY(mg_vcycle<double>(h, tau, o.nu1, o.nu2, R, inner_active, e64, rho, &ra));
-                    if (nparts < 0) {
-                        LT_TRY(launch_inner_update<double>(st, L0, tau, R, e64, uj, ustride, rho, (double*)nullptr,
-                                                           part, inner_active));
-                        nparts = reduce_blocks(N, R);
-                    } else {
-                        std::swap(rho, rho_next);
-                    }
+                    LT_TRY(refine_step(h, o, R, tau, U, ustride, jdev, e32, e64, lo32, lo32_next, rho, rho_next, part,
+                                       active, inner_active, worst, vcyc, count, &swapped));
                 }
-                LT_TRY(launch_inner_finalize(st, nparts, R, part, active, worst, o.relax * o.tol, o.tol, step,
-                                             o.inner_max, inner_active, vcyc, count));
+                if (mixed) std::swap(lo32, lo32_next);
+                if (swapped) std::swap(rho, rho_next);
             }
             LT_HIP(hipMemcpyAsync(hflag, count, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
             // convergence flags as left by the previous outer iteration's least squares
@@ -490,6 +582,7 @@ void lt_opts_default(lt_opts* o) {
     o->true_residual = 1;
     o->precond = LT_PRECOND_GMG;
     o->net_keep = 0.05;
+    o->graph = 0;
 }
 
 const char* lt_strerror(int code) {
@@ -871,7 +964,7 @@ int lt_precond_solve(lt_handle* h, double tau_re, double tau_im, int nvec, const
     std::vector<double> hn(2 * (size_t)nvec);
     for (int c = 0; c < maxcycles; ++c) {
         LT_TRY(mg_vcycle<double>(h, tau, 2, 2, nvec, nullptr, x, rho));
-        LT_TRY(launch_inner_update<double>(st, L0, tau, nvec, x, e, N2, rho, (double*)nullptr, part, nullptr));
+        LT_TRY(launch_inner_update<double>(st, L0, tau, nvec, x, e, N2, nullptr, rho, (double*)nullptr, part, nullptr));
         LT_TRY(launch_norms(st, N, nvec, N2, rho, part, nrm, nullptr));
         LT_HIP(hipMemcpyAsync(hn.data(), nrm, 2 * nvec * sizeof(double), hipMemcpyDeviceToHost, st));
         LT_HIP(hipStreamSynchronize(st));

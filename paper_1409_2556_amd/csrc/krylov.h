@@ -31,9 +31,11 @@ int launch_inner_init(hipStream_t st, int N, int R, size_t qstride, const double
                       double* rho, T* lo, const int* active);
 template <typename T>
 int launch_inner_update(hipStream_t st, LevelView<double> L, cdouble tau, int R, const T* e, double* u,
-                        size_t ustride, double* rho, T* lo, double* part, const int* inner_active);
+                        size_t ustride, const int* jcol, double* rho, T* lo, double* part, const int* inner_active);
+// *p = v on the stream (device-side loop state outside captured graphs)
+int launch_set_int(hipStream_t st, int* p, int v);
 int launch_inner_finalize(hipStream_t st, int nb, int R, const double* part, const int* active, const double* worst,
-                          double relax_tol, double tol, int step, int inner_max, int* inner_active, int* vcycles,
+                          double relax_tol, double tol, int inner_max, int* inner_active, int* vcycles,
                           int* count);
 int launch_cgs2(hipStream_t st, int N, int R, int j, const double* m, const double* U, size_t ustride, double* Q,
                 size_t qstride, double* H, int hstride, size_t hrstride, double* part, int pstride, double* c1,

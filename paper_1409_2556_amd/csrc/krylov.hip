@@ -115,14 +115,15 @@ __global__ void k_inner_init(int N, size_t qstride, const double* __restrict__ v
 // u += e; rho -= (K + tau M) e; lo = (T) rho; partial ||rho||^2
 template <typename T>
 __global__ void k_inner_update(LevelView<double> L, double tr, double ti, const T* __restrict__ e,
-                               double* __restrict__ u, size_t ustride, double* __restrict__ rho,
-                               T* __restrict__ lo, double* __restrict__ part, const int* __restrict__ active) {
+                               double* __restrict__ u, size_t ustride, const int* __restrict__ jcol,
+                               double* __restrict__ rho, T* __restrict__ lo, double* __restrict__ part,
+                               const int* __restrict__ active) {
     int r = blockIdx.y;
     if (active && !active[r]) return;
     const size_t N = L.N;
     const T* er = e + 2 * N * r;
     const T* ei = er + N;
-    double* ur = u + ustride * r;
+    double* ur = u + ustride * r + (jcol ? 2 * N * (size_t)*jcol : 0);
     double* rr = rho + 2 * N * r;
     double v[1] = {0};
     for (int i = blockIdx.x * kB + threadIdx.x; i < L.N; i += gridDim.x * kB) {
@@ -159,33 +160,38 @@ __global__ void k_inner_update(LevelView<double> L, double tr, double ti, const 
 // count[0] = right-hand sides still refining; count[1] = step + 1 if any right-hand
 // side was refined in this step (the number of steps this outer iteration needed).
 __global__ void k_inner_finalize(int R, int nb, const double* __restrict__ part, const int* __restrict__ active,
-                                 const double* __restrict__ worst, double relax_tol, double tol, int step,
+                                 const double* __restrict__ worst, double relax_tol, double tol,
                                  int inner_max, int* __restrict__ inner_active, int* __restrict__ vcycles,
                                  int* __restrict__ count) {
-    int r = threadIdx.x;
     __shared__ int cnt, any;
+    const int step = count[2];  // refinement steps already taken in this outer iteration
     if (threadIdx.x == 0) {
         cnt = 0;
         any = 0;
     }
     __syncthreads();
-    for (; r < R; r += blockDim.x) {
-        int a = inner_active[r];
-        if (!a) continue;
-        any = 1;
+    // one wavefront per right-hand side sums its partial norms
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int r = threadIdx.x >> 6; r < R; r += nw) {
+        if (!inner_active[r]) continue;
         double s = 0;
-        for (int q = 0; q < nb; ++q) s += part[(size_t)r * nb + q];
-        double eta = relax_tol / fmax(worst[r], tol);
-        eta = fmin(eta, 0.5);
-        vcycles[r] += 1;
-        int again = (sqrt(s) > eta) && (step + 1 < inner_max) && active[r];
-        inner_active[r] = again;
-        if (again) atomicAdd(&cnt, 1);
+        for (int q = lane; q < nb; q += 64) s += part[(size_t)r * nb + q];
+        s = wave_sum(s);
+        if (lane == 0) {
+            any = 1;
+            double eta = relax_tol / fmax(worst[r], tol);
+            eta = fmin(eta, 0.5);
+            vcycles[r] += 1;
+            const int again = (sqrt(s) > eta) && (step + 1 < inner_max) && active[r];
+            inner_active[r] = again;
+            if (again) atomicAdd(&cnt, 1);
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         count[0] = cnt;
         if (any) count[1] = step + 1;
+        count[2] = step + 1;
     }
 }
 
@@ -350,15 +356,21 @@ __global__ void k_mdot_finalize(int nb, int ncols, const double* __restrict__ pa
                                 double* __restrict__ coef, int cstride, const int* __restrict__ active) {
     int r = blockIdx.x;
     if (active && !active[r]) return;
-    for (int c = threadIdx.x; c <= ncols; c += blockDim.x) {
+    // one wavefront per column: lanes stride over the partial sums, then a shuffle reduction
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int c = threadIdx.x >> 6; c <= ncols; c += nw) {
         double re = 0, im = 0;
-        for (int q = 0; q < nb; ++q) {
+        for (int q = lane; q < nb; q += 64) {
             const double* p = part + ((size_t)r * nb + q) * pstride;
             re += p[2 * c];
             im += p[2 * c + 1];
         }
-        coef[(size_t)r * cstride + 2 * c] = re;
-        coef[(size_t)r * cstride + 2 * c + 1] = im;
+        re = wave_sum(re);
+        im = wave_sum(im);
+        if (lane == 0) {
+            coef[(size_t)r * cstride + 2 * c] = re;
+            coef[(size_t)r * cstride + 2 * c + 1] = im;
+        }
     }
 }
 
@@ -840,23 +852,30 @@ template int launch_inner_init<float>(hipStream_t, int, int, size_t, const doubl
 
 template <typename T>
 int launch_inner_update(hipStream_t st, LevelView<double> L, cdouble tau, int R, const T* e, double* u,
-                        size_t ustride, double* rho, T* lo, double* part, const int* inner_active) {
+                        size_t ustride, const int* jcol, double* rho, T* lo, double* part, const int* inner_active) {
     int nb = reduce_blocks(L.N, R);
-    k_inner_update<T><<<dim3(nb, R), kB, 0, st>>>(L, tau.real(), tau.imag(), e, u, ustride, rho, lo, part,
+    k_inner_update<T><<<dim3(nb, R), kB, 0, st>>>(L, tau.real(), tau.imag(), e, u, ustride, jcol, rho, lo, part,
                                                   inner_active);
     LT_HIP(hipGetLastError());
     return 0;
 }
 template int launch_inner_update<double>(hipStream_t, LevelView<double>, cdouble, int, const double*, double*,
-                                         size_t, double*, double*, double*, const int*);
+                                         size_t, const int*, double*, double*, double*, const int*);
 template int launch_inner_update<float>(hipStream_t, LevelView<double>, cdouble, int, const float*, double*,
-                                        size_t, double*, float*, double*, const int*);
+                                        size_t, const int*, double*, float*, double*, const int*);
 
 int launch_inner_finalize(hipStream_t st, int nb, int R, const double* part, const int* active, const double* worst,
-                          double relax_tol, double tol, int step, int inner_max, int* inner_active, int* vcycles,
-                          int* count) {
-    k_inner_finalize<<<1, 1024, 0, st>>>(R, nb, part, active, worst, relax_tol, tol, step, inner_max, inner_active,
+                          double relax_tol, double tol, int inner_max, int* inner_active, int* vcycles, int* count) {
+    k_inner_finalize<<<1, 1024, 0, st>>>(R, nb, part, active, worst, relax_tol, tol, inner_max, inner_active,
                                          vcycles, count);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
+__global__ void k_set_int(int* __restrict__ p, int v) { *p = v; }
+
+int launch_set_int(hipStream_t st, int* p, int v) {
+    k_set_int<<<1, 1, 0, st>>>(p, v);
     LT_HIP(hipGetLastError());
     return 0;
 }

@@ -88,8 +88,14 @@ struct lt_handle {
     lt::DevBuf kappa;                 // copy of the fine-grid conductivity (sensitivities)
     double lnDbar = 0.0;              // mean of ln D over the fine grid (network features)
     struct lt_unet* unet = nullptr;   // attached learned preconditioner (not owned)
-    // workspaces (grow-only, owned by the handle)
+    // workspaces (grow-only, owned by the handle); ws_gen changes whenever a
+    // workspace or cached coarse inverse moves, which retires captured graphs
     std::map<std::string, lt::DevBuf> ws;
+    unsigned long long ws_gen = 0;
+    // captured refinement steps (hipGraphExec_t), keyed by everything they bake in
+    // (the int records whether the step swaps the FP64 residual buffers)
+    std::map<std::vector<unsigned long long>, std::pair<hipGraphExec_t, int>> graphs;
+    unsigned long long graphs_gen = 0;  // ws_gen the cached graphs were captured at
     void* pinned = nullptr;  // small pinned host area for flags
     // profiling of one kernel family (opts.profile): event pairs and a byte counter
     int prof_target = 0;
@@ -108,8 +114,10 @@ int prof_end(lt_handle* h, int family);
 // workspace helper
 template <typename T> T* wsp(lt_handle* h, const char* name, size_t count, int* rc) {
     DevBuf& b = h->ws[name];
+    void* before = b.p;
     int r = b.reserve(count * sizeof(T));
     if (r < 0) { *rc = r; return nullptr; }
+    if (b.p != before) ++h->ws_gen;
     return b.as<T>();
 }
 
@@ -141,11 +149,13 @@ const CoarseInverse* mg_coarse_inverse(lt_handle* h, cdouble tau, int* rc);
 // precision T (x0 is overwritten).  active: device [R] mask or nullptr.
 // Optional fusion of the fine-level post-smoother with one refinement step of the
 // preconditioner solve (2D fused path only): u += e, rho_out = rho_in - (K + tau M) e,
-// lo = (T) rho_out, part = per-tile ||rho_out||^2.  When applied, *nparts is set to
+// lo = (T) rho_out, part = per-tile ||rho_out||^2 (u of right-hand side r is
+// u + r * ustride + *jcol * 2N).  When applied, *nparts is set to
 // the number of partial sums per right-hand side and x0 is not written.
 struct RefineArgs {
     double* u;
     size_t ustride;
+    const int* jcol;  // device: u is advanced by jcol * 2N (nullptr: by 0)
     const double* rho_in;
     double* rho_out;
     void* lo;

@@ -466,6 +466,7 @@ const CoarseInverse* mg_coarse_inverse(lt_handle* h, cdouble tau, int* rc) {
     }
     if (dense_inverse(n, A, inv) != 0) { *rc = LT_EINVAL; set_last_error("singular coarse operator"); return nullptr; }
     if (h->coarse_cache.size() >= 16) {
+        ++h->ws_gen;
         h->coarse_cache.front().inv64.release();
         h->coarse_cache.front().inv32.release();
         h->coarse_cache.erase(h->coarse_cache.begin());
@@ -631,7 +632,7 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
             if (l == 0 && refine) {
                 LT_TRY(launch_post2d_refine<T>(st, v, h->levels[0].v64(), tr, ti, tau.real(), tau.imag(), nu2, bs[0],
                                                xpre[0], xpost[1], C.n[0], C.n[1], C.coarsened_from_fine[0],
-                                               C.coarsened_from_fine[1], gh, refine->u, refine->ustride,
+                                               C.coarsened_from_fine[1], gh, refine->u, refine->ustride, refine->jcol,
                                                refine->rho_in, refine->rho_out, static_cast<T*>(refine->lo),
                                                refine->part, R, active, pc));
                 *refine->nparts = ((L.n[0] + kTileX - 1) / kTileX) * ((L.n[1] + kTileY - 1) / kTileY);

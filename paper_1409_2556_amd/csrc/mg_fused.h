@@ -44,8 +44,9 @@ int launch_post2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, con
 template <typename T>
 int launch_post2d_refine(hipStream_t st, const LevelView<T>& L, const LevelView<double>& L64, T tr, T ti,
                          double tr64, double ti64, int nu, const T* b, const T* xin, const T* ec, int cnx, int cny,
-                         int cox, int coy, T4 ghost, double* u, size_t ustride, const double* rho_in,
-                         double* rho_out, T* lo, double* part, int R, const int* active, unsigned long long* prof);
+                         int cox, int coy, T4 ghost, double* u, size_t ustride, const int* jcol,
+                         const double* rho_in, double* rho_out, T* lo, double* part, int R, const int* active,
+                         unsigned long long* prof);
 template <typename T>
 int launch_coarse_block(hipStream_t st, const CBMeta<T>& M, T tr, T ti, const T* bin, T* xout, int R,
                         const int* active);

@@ -59,33 +59,145 @@ __device__ __forceinline__ void tile_sweeps(Tile2D<T, H>& s, int gx0, int gy0, i
     }
 }
 
+// Cell-centred linear interpolation weights of one halved axis (ghost mirrored through the wall).
+template <typename T>
+__device__ __forceinline__ int prolong_axis(int f, int nc, int halved, T glo, T ghi, int* idx, T* w) {
+    if (!halved) {
+        idx[0] = f;
+        w[0] = 1;
+        return 1;
+    }
+    const int I = f >> 1;
+    const int J = (f & 1) ? I + 1 : I - 1;
+    idx[0] = I;
+    if (J < 0) {
+        w[0] = T(0.75) + T(0.25) * glo;
+        return 1;
+    }
+    if (J >= nc) {
+        w[0] = T(0.75) + T(0.25) * ghi;
+        return 1;
+    }
+    w[0] = T(0.75);
+    idx[1] = J;
+    w[1] = T(0.25);
+    return 2;
+}
+
+constexpr int kThreads = 256;  // every fused 2D kernel runs 256 threads
+
 // Load coefficients and b of the extended tile; cells outside the grid get zero
-// couplings, zero b and a unit diagonal (they are never updated).
-template <typename T, int H>
-__device__ __forceinline__ void tile_load_common(Tile2D<T, H>& s, const LevelView<T>& L, T tr, T ti,
-                                                 const T* __restrict__ br, const T* __restrict__ bi, int gx0,
-                                                 int gy0) {
+// couplings, zero b and a unit diagonal (they are never updated).  Every
+// thread issues the loads of all its cells before any is used (addresses are
+// clamped into the grid, so no load depends on a branch), which keeps
+// several loads in flight per thread instead of one cell at a time.  With
+// PROLONG, x = xin + P e is formed from the coarse patch staged in pxr/pxi
+// (which the caller loads and which may alias s.xr/s.xi: a barrier separates
+// its last read from the first store here); otherwise x = 0.
+template <typename T, int H, bool PROLONG>
+__device__ __forceinline__ void tile_load(Tile2D<T, H>& s, const LevelView<T>& L, T tr, T ti,
+                                          const T* __restrict__ br, const T* __restrict__ bi,
+                                          const T* __restrict__ xr, const T* __restrict__ xi, int gx0, int gy0,
+                                          const T* pxr, const T* pxi, int px0, int py0, int pnx, int cnx, int cny,
+                                          int cox, int coy, T4 ghost) {
     constexpr int EX = Tile2D<T, H>::EX, EY = Tile2D<T, H>::EY;
-    for (int c = threadIdx.x; c < EX * EY; c += blockDim.x) {
+    constexpr int NC = EX * EY, NL = (NC + kThreads - 1) / kThreads;
+    T vtx[NL], vty[NL], vd[NL], vm[NL], vbr[NL], vbi[NL], vxr[NL], vxi[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int c = threadIdx.x + kThreads * k;
         const int lx = c % EX, ly = c / EX;
-        const int gx = gx0 + lx, gy = gy0 + ly;
-        if (gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
-            const int i = gx + L.nx * gy;
-            s.tx[ly][lx] = L.Tx[i];
-            s.ty[ly][lx] = L.Ty[i];
-            s.dr[ly][lx] = L.D[i] + tr * L.m[i];
-            s.di[ly][lx] = ti * L.m[i];
-            s.br[ly][lx] = br[i];
-            s.bi[ly][lx] = bi[i];
-        } else {
-            s.tx[ly][lx] = 0;
-            s.ty[ly][lx] = 0;
-            s.dr[ly][lx] = 1;
-            s.di[ly][lx] = 0;
-            s.br[ly][lx] = 0;
-            s.bi[ly][lx] = 0;
+        const int gx = min(max(gx0 + lx, 0), L.nx - 1), gy = min(max(gy0 + ly, 0), L.ny - 1);
+        const int i = gx + L.nx * gy;
+        vtx[k] = L.Tx[i];
+        vty[k] = L.Ty[i];
+        vd[k] = L.D[i];
+        vm[k] = L.m[i];
+        vbr[k] = br[i];
+        vbi[k] = bi[i];
+        if (PROLONG) {
+            vxr[k] = xr[i];
+            vxi[k] = xi[i];
         }
     }
+    if (PROLONG) {
+        // coarse correction, interpolated from the staged patch
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int c = threadIdx.x + kThreads * k;
+            const int gx = gx0 + c % EX, gy = gy0 + c / EX;
+            if (c < NC && gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
+                int ix[2], iy[2];
+                T wx[2], wy[2];
+                const int nxp = prolong_axis<T>(gx, cnx, cox, (T)ghost.x, (T)ghost.y, ix, wx);
+                const int nyp = prolong_axis<T>(gy, cny, coy, (T)ghost.z, (T)ghost.w, iy, wy);
+                T pr = 0, pi = 0;
+                for (int b2 = 0; b2 < nyp; ++b2)
+                    for (int a2 = 0; a2 < nxp; ++a2) {
+                        const T w = wx[a2] * wy[b2];
+                        const int J = (ix[a2] - px0) + pnx * (iy[b2] - py0);
+                        pr += w * pxr[J];
+                        pi += w * pxi[J];
+                    }
+                vxr[k] += pr;
+                vxi[k] += pi;
+            }
+        }
+        __syncthreads();  // the patch may alias s.xr / s.xi
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int c = threadIdx.x + kThreads * k;
+        if (c >= NC) continue;
+        const int lx = c % EX, ly = c / EX;
+        const int gx = gx0 + lx, gy = gy0 + ly;
+        const bool in = gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny;
+        s.tx[ly][lx] = in ? vtx[k] : T(0);
+        s.ty[ly][lx] = in ? vty[k] : T(0);
+        s.dr[ly][lx] = in ? vd[k] + tr * vm[k] : T(1);
+        s.di[ly][lx] = in ? ti * vm[k] : T(0);
+        s.br[ly][lx] = in ? vbr[k] : T(0);
+        s.bi[ly][lx] = in ? vbi[k] : T(0);
+        s.xr[ly][lx] = (PROLONG && in) ? vxr[k] : T(0);
+        s.xi[ly][lx] = (PROLONG && in) ? vxi[k] : T(0);
+    }
+}
+
+// Stage the coarse cells the tile's prolongation reads (a patch of at most
+// (EX/2 + 3) x EY or EX x (EY/2 + 3) cells) in pxr/pxi; returns its origin
+// and width.  Followed by a barrier.
+template <typename T, int H>
+__device__ __forceinline__ void stage_patch(const T* __restrict__ er, const T* __restrict__ ei, int gx0, int gy0,
+                                            int nx, int ny, int cnx, int cny, int cox, int coy, T* pxr, T* pxi,
+                                            int* px0, int* py0, int* pnx) {
+    constexpr int EX = Tile2D<T, H>::EX, EY = Tile2D<T, H>::EY;
+    const int fx0 = max(gx0, 0), fx1 = min(gx0 + EX - 1, nx - 1);
+    const int fy0 = max(gy0, 0), fy1 = min(gy0 + EY - 1, ny - 1);
+    const int x0 = cox ? max((fx0 >> 1) - 1, 0) : fx0, x1 = cox ? min((fx1 >> 1) + 1, cnx - 1) : fx1;
+    const int y0 = coy ? max((fy0 >> 1) - 1, 0) : fy0, y1 = coy ? min((fy1 >> 1) + 1, cny - 1) : fy1;
+    const int w = x1 - x0 + 1, hgt = y1 - y0 + 1;
+    constexpr int MAXP = (EX * (EY / 2 + 3) > (EX / 2 + 3) * EY) ? EX * (EY / 2 + 3) : (EX / 2 + 3) * EY;
+    constexpr int NP = (MAXP + kThreads - 1) / kThreads;
+    T vr[NP], vi[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int c = min((int)threadIdx.x + kThreads * k, w * hgt - 1);
+        const size_t J = (size_t)(x0 + c % w) + (size_t)cnx * (y0 + c / w);
+        vr[k] = er[J];
+        vi[k] = ei[J];
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int c = threadIdx.x + kThreads * k;
+        if (c < w * hgt) {
+            pxr[c] = vr[k];
+            pxi[c] = vi[k];
+        }
+    }
+    *px0 = x0;
+    *py0 = y0;
+    *pnx = w;
+    __syncthreads();
 }
 
 // Pre-smoothing from x = 0, then restriction of the residual.
@@ -95,18 +207,13 @@ __global__ __launch_bounds__(256) void k_pre2d(LevelView<T> L, T tr, T ti, const
                                                T* __restrict__ bc, const int* __restrict__ active,
                                                unsigned long long* __restrict__ prof, int Rtot) {
     constexpr int H = 2 * NU + 1;
-    constexpr int EX = Tile2D<T, H>::EX, EY = Tile2D<T, H>::EY;
     __shared__ Tile2D<T, H> s;
     const int r = blockIdx.z;
     if (active && !active[r]) return;
     const size_t N = L.N;
     const int gx0 = blockIdx.x * kTileX - H, gy0 = blockIdx.y * kTileY - H;
-    tile_load_common<T, H>(s, L, tr, ti, b + 2 * N * r, b + 2 * N * r + N, gx0, gy0);
-    for (int c = threadIdx.x; c < EX * EY; c += blockDim.x) {
-        const int lx = c % EX, ly = c / EX;
-        s.xr[ly][lx] = 0;
-        s.xi[ly][lx] = 0;
-    }
+    tile_load<T, H, false>(s, L, tr, ti, b + 2 * N * r, b + 2 * N * r + N, nullptr, nullptr, gx0, gy0, nullptr,
+                           nullptr, 0, 0, 0, cnx, cny, cox, coy, T4{});
     __syncthreads();
     tile_sweeps<T, H>(s, gx0, gy0, L.nx, L.ny, 2 * NU, 0);
     // interior -> x
@@ -156,31 +263,6 @@ __global__ __launch_bounds__(256) void k_pre2d(LevelView<T> L, T tr, T ti, const
     }
 }
 
-// Cell-centred linear interpolation weights of one halved axis (ghost mirrored through the wall).
-template <typename T>
-__device__ __forceinline__ int prolong_axis(int f, int nc, int halved, T glo, T ghi, int* idx, T* w) {
-    if (!halved) {
-        idx[0] = f;
-        w[0] = 1;
-        return 1;
-    }
-    const int I = f >> 1;
-    const int J = (f & 1) ? I + 1 : I - 1;
-    idx[0] = I;
-    if (J < 0) {
-        w[0] = T(0.75) + T(0.25) * glo;
-        return 1;
-    }
-    if (J >= nc) {
-        w[0] = T(0.75) + T(0.25) * ghi;
-        return 1;
-    }
-    w[0] = T(0.75);
-    idx[1] = J;
-    w[1] = T(0.25);
-    return 2;
-}
-
 // x_out = post-smooth( x_in + P e_coarse )
 template <typename T, int NU>
 __global__ __launch_bounds__(256) void k_post2d(LevelView<T> L, T tr, T ti, const T* __restrict__ b,
@@ -189,42 +271,18 @@ __global__ __launch_bounds__(256) void k_post2d(LevelView<T> L, T tr, T ti, cons
                                                 const int* __restrict__ active, unsigned long long* __restrict__ prof,
                                                 int Rtot) {
     constexpr int H = 2 * NU;
-    constexpr int EX = Tile2D<T, H>::EX, EY = Tile2D<T, H>::EY;
     __shared__ Tile2D<T, H> s;
     const int r = blockIdx.z;
     if (active && !active[r]) return;
     const size_t N = L.N;
     const size_t Nc = (size_t)cnx * cny;
     const int gx0 = blockIdx.x * kTileX - H, gy0 = blockIdx.y * kTileY - H;
-    tile_load_common<T, H>(s, L, tr, ti, b + 2 * N * r, b + 2 * N * r + N, gx0, gy0);
-    const T* xr = xin + 2 * N * r;
-    const T* xi = xr + N;
     const T* er = ec + 2 * Nc * r;
-    const T* ei = er + Nc;
-    for (int c = threadIdx.x; c < EX * EY; c += blockDim.x) {
-        const int lx = c % EX, ly = c / EX;
-        const int gx = gx0 + lx, gy = gy0 + ly;
-        T vr = 0, vi = 0;
-        if (gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
-            const int i = gx + L.nx * gy;
-            int ix[2], iy[2];
-            T wx[2], wy[2];
-            const int nxp = prolong_axis<T>(gx, cnx, cox, (T)ghost.x, (T)ghost.y, ix, wx);
-            const int nyp = prolong_axis<T>(gy, cny, coy, (T)ghost.z, (T)ghost.w, iy, wy);
-            T pr = 0, pi = 0;
-            for (int b2 = 0; b2 < nyp; ++b2)
-                for (int a2 = 0; a2 < nxp; ++a2) {
-                    const T w = wx[a2] * wy[b2];
-                    const size_t J = (size_t)ix[a2] + (size_t)cnx * iy[b2];
-                    pr += w * er[J];
-                    pi += w * ei[J];
-                }
-            vr = xr[i] + pr;
-            vi = xi[i] + pi;
-        }
-        s.xr[ly][lx] = vr;
-        s.xi[ly][lx] = vi;
-    }
+    int px0, py0, pnx;
+    stage_patch<T, H>(er, er + Nc, gx0, gy0, L.nx, L.ny, cnx, cny, cox, coy, &s.xr[0][0], &s.xi[0][0], &px0, &py0,
+                      &pnx);
+    tile_load<T, H, true>(s, L, tr, ti, b + 2 * N * r, b + 2 * N * r + N, xin + 2 * N * r, xin + 2 * N * r + N,
+                          gx0, gy0, &s.xr[0][0], &s.xi[0][0], px0, py0, pnx, cnx, cny, cox, coy, ghost);
     __syncthreads();
     tile_sweeps<T, H>(s, gx0, gy0, L.nx, L.ny, 2 * NU, 1);
     T* oxr = xout + 2 * N * r;
@@ -261,12 +319,12 @@ __global__ __launch_bounds__(256) void k_post2d_refine(LevelView<T> L, LevelView
                                                        const T* __restrict__ xin, const T* __restrict__ ec,
                                                        int cnx, int cny, int cox, int coy, T4 ghost,
                                                        double* __restrict__ u, size_t ustride,
+                                                       const int* __restrict__ jcol,
                                                        const double* rho_in, double* rho_out,
                                                        T* __restrict__ lo, double* __restrict__ part,
                                                        const int* __restrict__ active,
                                                        unsigned long long* __restrict__ prof, int Rtot) {
     constexpr int H = 2 * NU + 1;
-    constexpr int EX = Tile2D<T, H>::EX, EY = Tile2D<T, H>::EY;
     __shared__ Tile2D<T, H> s;
     __shared__ double red[4];
     const int r = blockIdx.z;
@@ -274,60 +332,59 @@ __global__ __launch_bounds__(256) void k_post2d_refine(LevelView<T> L, LevelView
     const size_t N = L.N;
     const size_t Nc = (size_t)cnx * cny;
     const int gx0 = blockIdx.x * kTileX - H, gy0 = blockIdx.y * kTileY - H;
-    tile_load_common<T, H>(s, L, tr, ti, b + 2 * N * r, b + 2 * N * r + N, gx0, gy0);
-    const T* xr = xin + 2 * N * r;
-    const T* xi = xr + N;
     const T* er = ec + 2 * Nc * r;
-    const T* ei = er + Nc;
-    for (int c = threadIdx.x; c < EX * EY; c += blockDim.x) {
-        const int lx = c % EX, ly = c / EX;
-        const int gx = gx0 + lx, gy = gy0 + ly;
-        T vr = 0, vi = 0;
-        if (gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
-            const int i = gx + L.nx * gy;
-            int ix[2], iy[2];
-            T wx[2], wy[2];
-            const int nxp = prolong_axis<T>(gx, cnx, cox, (T)ghost.x, (T)ghost.y, ix, wx);
-            const int nyp = prolong_axis<T>(gy, cny, coy, (T)ghost.z, (T)ghost.w, iy, wy);
-            T pr = 0, pi = 0;
-            for (int b2 = 0; b2 < nyp; ++b2)
-                for (int a2 = 0; a2 < nxp; ++a2) {
-                    const T w = wx[a2] * wy[b2];
-                    const size_t J = (size_t)ix[a2] + (size_t)cnx * iy[b2];
-                    pr += w * er[J];
-                    pi += w * ei[J];
-                }
-            vr = xr[i] + pr;
-            vi = xi[i] + pi;
-        }
-        s.xr[ly][lx] = vr;
-        s.xi[ly][lx] = vi;
-    }
+    int px0, py0, pnx;
+    stage_patch<T, H>(er, er + Nc, gx0, gy0, L.nx, L.ny, cnx, cny, cox, coy, &s.xr[0][0], &s.xi[0][0], &px0, &py0,
+                      &pnx);
+    tile_load<T, H, true>(s, L, tr, ti, b + 2 * N * r, b + 2 * N * r + N, xin + 2 * N * r, xin + 2 * N * r + N,
+                          gx0, gy0, &s.xr[0][0], &s.xi[0][0], px0, py0, pnx, cnx, cny, cox, coy, ghost);
     __syncthreads();
     tile_sweeps<T, H>(s, gx0, gy0, L.nx, L.ny, 2 * NU, 1);
-    double* ur = u + ustride * r;
+    double* ur = u + ustride * r + (jcol ? 2 * N * (size_t)*jcol : 0);
     const double* rin = rho_in + 2 * N * r;
     double* rout = rho_out + 2 * N * r;
+    // FP64 update of the interior: all global loads of a thread's cells first
+    constexpr int NI = kTileX * kTileY / kThreads;
+    static_assert(kTileX * kTileY % kThreads == 0, "interior cells per thread");
+    double vte[NI], vtw[NI], vtn[NI], vts[NI], vd[NI], vm[NI], vur[NI], vui[NI], vrr[NI], vri[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int c = threadIdx.x + kThreads * k;
+        const int gx = min(gx0 + H + c % kTileX, L.nx - 1), gy = min(gy0 + H + c / kTileX, L.ny - 1);
+        const int i = gx + L.nx * gy;
+        vte[k] = L64.Tx[i];
+        vtw[k] = L64.Tx[max(i - 1, 0)];
+        vtn[k] = L64.Ty[i];
+        vts[k] = L64.Ty[max(i - L.nx, 0)];
+        vd[k] = L64.D[i];
+        vm[k] = L64.m[i];
+        vur[k] = ur[i];
+        vui[k] = ur[i + N];
+        vrr[k] = rin[i];
+        vri[k] = rin[i + N];
+    }
     double acc = 0;
-    for (int c = threadIdx.x; c < kTileX * kTileY; c += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int c = threadIdx.x + kThreads * k;
         const int lx = H + c % kTileX, ly = H + c / kTileX;
         const int gx = gx0 + lx, gy = gy0 + ly;
         if (gx >= L.nx || gy >= L.ny) continue;
         const int i = gx + L.nx * gy;
         const double e0r = (double)s.xr[ly][lx], e0i = (double)s.xi[ly][lx];
         // (K + tau M) e with the FP64 operator; walls are in D, out-of-grid neighbours hold 0
-        const double tE = L64.Tx[i], tW = gx > 0 ? L64.Tx[i - 1] : 0.0;
-        const double tN = L64.Ty[i], tS = gy > 0 ? L64.Ty[i - L.nx] : 0.0;
+        const double tE = vte[k], tW = gx > 0 ? vtw[k] : 0.0;
+        const double tN = vtn[k], tS = gy > 0 ? vts[k] : 0.0;
         const double ore = tE * (double)s.xr[ly][lx + 1] + tW * (double)s.xr[ly][lx - 1] +
                            tN * (double)s.xr[ly + 1][lx] + tS * (double)s.xr[ly - 1][lx];
         const double oim = tE * (double)s.xi[ly][lx + 1] + tW * (double)s.xi[ly][lx - 1] +
                            tN * (double)s.xi[ly + 1][lx] + tS * (double)s.xi[ly - 1][lx];
-        const double dre = L64.D[i] + tr64 * L64.m[i], dim = ti64 * L64.m[i];
+        const double dre = vd[k] + tr64 * vm[k], dim = ti64 * vm[k];
         const double are = dre * e0r - dim * e0i - ore;
         const double aim = dre * e0i + dim * e0r - oim;
-        ur[i] += e0r;
-        ur[i + N] += e0i;
-        const double nre = rin[i] - are, nim = rin[i + N] - aim;
+        ur[i] = vur[k] + e0r;
+        ur[i + N] = vui[k] + e0i;
+        const double nre = vrr[k] - are, nim = vri[k] - aim;
         rout[i] = nre;
         rout[i + N] = nim;
         if (lo) {
@@ -599,12 +656,13 @@ int launch_post2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, con
 template <typename T>
 int launch_post2d_refine(hipStream_t st, const LevelView<T>& L, const LevelView<double>& L64, T tr, T ti,
                          double tr64, double ti64, int nu, const T* b, const T* xin, const T* ec, int cnx, int cny,
-                         int cox, int coy, T4 ghost, double* u, size_t ustride, const double* rho_in,
-                         double* rho_out, T* lo, double* part, int R, const int* active, unsigned long long* prof) {
+                         int cox, int coy, T4 ghost, double* u, size_t ustride, const int* jcol,
+                         const double* rho_in, double* rho_out, T* lo, double* part, int R, const int* active,
+                         unsigned long long* prof) {
     dim3 grid((L.nx + kTileX - 1) / kTileX, (L.ny + kTileY - 1) / kTileY, R);
 #define LT_PR(NU)                                                                                              \
     k_post2d_refine<T, NU><<<grid, 256, 0, st>>>(L, L64, tr, ti, tr64, ti64, b, xin, ec, cnx, cny, cox, coy,   \
-                                                 ghost, u, ustride, rho_in, rho_out, lo, part, active, prof, R)
+                                                 ghost, u, ustride, jcol, rho_in, rho_out, lo, part, active, prof, R)
     switch (nu) {
         case 1: LT_PR(1); break;
         case 2: LT_PR(2); break;
@@ -648,12 +706,12 @@ template int launch_post2d<double>(hipStream_t, const LevelView<double>&, double
                                    unsigned long long*);
 template int launch_post2d_refine<float>(hipStream_t, const LevelView<float>&, const LevelView<double>&, float, float,
                                          double, double, int, const float*, const float*, const float*, int, int,
-                                         int, int, T4, double*, size_t, const double*, double*, float*, double*, int,
-                                         const int*, unsigned long long*);
+                                         int, int, T4, double*, size_t, const int*, const double*, double*, float*,
+                                         double*, int, const int*, unsigned long long*);
 template int launch_post2d_refine<double>(hipStream_t, const LevelView<double>&, const LevelView<double>&, double,
                                           double, double, double, int, const double*, const double*, const double*,
-                                          int, int, int, int, T4, double*, size_t, const double*, double*, double*,
-                                          double*, int, const int*, unsigned long long*);
+                                          int, int, int, int, T4, double*, size_t, const int*, const double*, double*,
+                                          double*, double*, int, const int*, unsigned long long*);
 template int launch_coarse_block<float>(hipStream_t, const CBMeta<float>&, float, float, const float*, float*, int,
                                         const int*);
 template int launch_coarse_block<double>(hipStream_t, const CBMeta<double>&, double, double, const double*, double*,
