@@ -312,6 +312,28 @@ void lt_unet_destroy(lt_unet* u);
 int lt_precond_solve(lt_handle* h, double tau_re, double tau_im, int nvec, const double* r, double* e, double tol,
                      int maxcycles);
 
+/* ---- tile-shape autotuner ----------------------------------------------
+ * The fused 2D smoothing kernels (fine and intermediate multigrid levels of
+ * 2D grids) stage tiles of cells in LDS; the tile shape is chosen per level
+ * and precision.  lt_autotune times preconditioner steps for nvec
+ * right-hand sides on the handle's stream with every shape on one level at a
+ * time (finest first, the others kept) and keeps the fastest: the choice is
+ * stored in the handle and used by every later call.  tiles_out[n_out]
+ * receives the shape id per level (-1 past the tuned levels);
+ * *us_per_step the time of one step with the final choice (microseconds).
+ * Returns the number of tuned levels (0 for 3D grids or nu outside 1..3,
+ * which have no tile shapes), or a negative error code.  Results of later
+ * solves do not depend on the shapes (each cell's arithmetic is the same;
+ * only partial-sum order in residual norms differs).  A plain performance
+ * knob, not part of the paper's method. */
+int lt_autotune(lt_handle* h, int precision, int nu1, int nu2, int nvec, int* tiles_out, int n_out,
+                double* us_per_step);
+/* Set the tile shape ids per level (n <= 16; -1 or missing levels: shape 0),
+ * e.g. from a cache of earlier lt_autotune results. */
+int lt_set_tiles(lt_handle* h, int precision, const int* tiles, int n);
+/* Interior cells (tx, ty) of tile shape `id`; LT_EINVAL for an unknown id. */
+int lt_tile_shape(int id, int* tx, int* ty);
+
 /* Number of cells per axis of multigrid level `level` (n_out[3]); returns
  * the number of levels, or a negative error code. */
 int lt_level_shape(lt_handle* h, int level, int* n_out);

@@ -90,6 +90,12 @@ _lib.lt_solve_batch.argtypes = [C.POINTER(lt_solve_item), C.c_int]
 _lib.lt_solve_batch.restype = C.c_int
 _lib.lt_adjoint_batch.argtypes = [C.POINTER(lt_adjoint_item), C.c_int]
 _lib.lt_adjoint_batch.restype = C.c_int
+_lib.lt_autotune.argtypes = [_h, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.c_int, _dp]
+_lib.lt_autotune.restype = C.c_int
+_lib.lt_set_tiles.argtypes = [_h, C.c_int, C.POINTER(C.c_int), C.c_int]
+_lib.lt_set_tiles.restype = C.c_int
+_lib.lt_tile_shape.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+_lib.lt_tile_shape.restype = C.c_int
 _lib.lt_talbot.argtypes = [C.c_int, C.c_double, _dp, _dp]
 _lib.lt_talbot.restype = C.c_int
 _lib.lt_apply_operator.argtypes = [_h, C.c_int, C.c_double, C.c_double, _vp, _vp, C.c_int]
@@ -344,6 +350,25 @@ def lt_adjoint_batch(problems):
     return outs, stats, rc
 
 
+def lt_autotune(handle: Handle, precision, nu1=2, nu2=2, nvec=8):
+    """Tune the smoother tile shape per level; returns (shape ids of the tuned levels, us per step)."""
+    tiles = (C.c_int * 16)()
+    us = C.c_double()
+    n = _check(_lib.lt_autotune(handle.ptr, int(precision), int(nu1), int(nu2), int(nvec), tiles, 16, C.byref(us)))
+    return [tiles[i] for i in range(n)], us.value
+
+
+def lt_set_tiles(handle: Handle, precision, tiles):
+    arr = (C.c_int * max(1, len(tiles)))(*[int(t) for t in tiles])
+    return _check(_lib.lt_set_tiles(handle.ptr, int(precision), arr, len(tiles)))
+
+
+def lt_tile_shape(tile_id):
+    tx, ty = C.c_int(), C.c_int()
+    _check(_lib.lt_tile_shape(int(tile_id), C.byref(tx), C.byref(ty)))
+    return tx.value, ty.value
+
+
 def lt_talbot(nz, t):
     """Upper-half Talbot nodes and weights (complex numpy arrays) computed by the library."""
     z = np.zeros(nz, dtype=np.float64)
@@ -383,7 +408,7 @@ _ABI_NAMES = ["lt_opts_default", "lt_setup", "lt_solve", "lt_adjoint", "lt_talbo
               "lt_vcycle", "lt_level_shape", "lt_strerror", "lt_last_error", "lt_destroy", "lt_unet_create",
               "lt_unet_nparams", "lt_unet_get_params", "lt_unet_set_params", "lt_unet_apply",
               "lt_unet_train_step", "lt_unet_grad", "lt_unet_attach", "lt_unet_destroy", "lt_precond_solve",
-              "lt_solve_batch", "lt_adjoint_batch"]
+              "lt_solve_batch", "lt_adjoint_batch", "lt_autotune", "lt_set_tiles", "lt_tile_shape"]
 
 
 # ---------------------------------------------------------------- learned preconditioner

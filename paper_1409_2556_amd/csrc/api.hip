@@ -18,6 +18,7 @@
 #include <mutex>
 
 #include "krylov.h"
+#include "mg_fused.h"
 #include "lt_internal.h"
 #include "unet.h"
 
@@ -278,7 +279,9 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     if (!c1 || !c2) return rc;
     const int nb = reduce_blocks(N, R);
     const int pstride = 2 * (jmax + 2);
-    const size_t ntiles = ((size_t)h->grid.n[0] + 31) / 32 * (((size_t)h->grid.n[1] + 15) / 16) * h->grid.n[2];
+    // per-tile partial sums of the fused refinement (the smallest tile shape has the most)
+    const size_t ntiles = ((size_t)h->grid.n[0] + kMinTileX - 1) / kMinTileX *
+                          (((size_t)h->grid.n[1] + kMinTileY - 1) / kMinTileY) * h->grid.n[2];
     double* part = wsp<double>(h, "part", (size_t)R * std::max((size_t)nb * pstride, ntiles), &rc);
     if (!part) return rc;
     double* small = wsp<double>(h, "small", 4 * (size_t)R, &rc);

@@ -15,6 +15,7 @@
 namespace lt {
 
 using cdouble = std::complex<double>;
+constexpr int kMaxTunedLevels = 16;  // levels whose smoother tile shape can be tuned
 
 // ---------------------------------------------------------------- errors
 #define LT_HIP(...)                                                      \
@@ -86,6 +87,8 @@ struct lt_handle {
     std::vector<lt::CoarseInverse> coarse_cache;
     std::vector<double> coarse_host;  // coarsest level coefficients [5][Nc] on the host
     lt::DevBuf kappa;                 // copy of the fine-grid conductivity (sensitivities)
+    // tile shape id of the fused 2D smoothers per level, [0]: FP64, [1]: FP32 (lt_autotune)
+    int tiles[2][16] = {};
     double lnDbar = 0.0;              // mean of ln D over the fine grid (network features)
     struct lt_unet* unet = nullptr;   // attached learned preconditioner (not owned)
     // workspaces (grow-only, owned by the handle); ws_gen changes whenever a

@@ -530,6 +530,8 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
     const bool cb = lc < nl && nl - lc <= kMaxCBLevels;
     if (!cb) lc = nl - 1;  // generic path down to the coarsest level
     const bool fused2d = h->grid.ndim == 2 && nu1 >= 1 && nu1 <= 3 && nu2 >= 1 && nu2 <= 3;
+    const int* tiles = h->tiles[sizeof(T) == 4 ? 1 : 0];
+    auto tile_of = [&](int l) { return l < kMaxTunedLevels ? tiles[l] : 0; };
     const char* tag = sizeof(T) == 8 ? "64_" : "32_";
     std::vector<T*> xpre(nl + 1, nullptr), xpost(nl + 1, nullptr), bs(nl + 1, nullptr);
     bs[0] = const_cast<T*>(b0);
@@ -562,7 +564,7 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
             unsigned long long* pc = nullptr;
             const bool prof = l == 0 && h->prof_target == LT_PROF_PRE_FINE;
             if (prof) LT_TRY(prof_begin(h, LT_PROF_PRE_FINE, &pc));
-            LT_TRY(launch_pre2d<T>(st, v, tr, ti, nu1, bs[l], xpre[l], C.n[0], C.n[1], C.coarsened_from_fine[0],
+            LT_TRY(launch_pre2d<T>(st, v, tr, ti, nu1, tile_of(l), bs[l], xpre[l], C.n[0], C.n[1], C.coarsened_from_fine[0],
                                    C.coarsened_from_fine[1], bs[l + 1], R, active, pc));
             if (prof) LT_TRY(prof_end(h, LT_PROF_PRE_FINE));
         } else {
@@ -630,14 +632,14 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
             const bool prof = l == 0 && h->prof_target == LT_PROF_POST_FINE;
             if (prof) LT_TRY(prof_begin(h, LT_PROF_POST_FINE, &pc));
             if (l == 0 && refine) {
-                LT_TRY(launch_post2d_refine<T>(st, v, h->levels[0].v64(), tr, ti, tau.real(), tau.imag(), nu2, bs[0],
+                LT_TRY(launch_post2d_refine<T>(st, v, h->levels[0].v64(), tr, ti, tau.real(), tau.imag(), nu2,
+                                               tile_of(0), bs[0],
                                                xpre[0], xpost[1], C.n[0], C.n[1], C.coarsened_from_fine[0],
                                                C.coarsened_from_fine[1], gh, refine->u, refine->ustride, refine->jcol,
                                                refine->rho_in, refine->rho_out, static_cast<T*>(refine->lo),
-                                               refine->part, R, active, pc));
-                *refine->nparts = ((L.n[0] + kTileX - 1) / kTileX) * ((L.n[1] + kTileY - 1) / kTileY);
+                                               refine->part, R, active, pc, refine->nparts));
             } else {
-                LT_TRY(launch_post2d<T>(st, v, tr, ti, nu2, bs[l], xpre[l], xpost[l + 1], C.n[0], C.n[1],
+                LT_TRY(launch_post2d<T>(st, v, tr, ti, nu2, tile_of(l), bs[l], xpre[l], xpost[l + 1], C.n[0], C.n[1],
                                         C.coarsened_from_fine[0], C.coarsened_from_fine[1], gh, xpost[l], R, active,
                                         pc));
             }

@@ -5,8 +5,8 @@
 
 namespace lt {
 
-constexpr int kTileX = 32;
-constexpr int kTileY = 16;
+constexpr int kNumTiles = 4;               // tile shapes of the fused 2D kernels (tile_shape)
+constexpr int kMinTileX = 16, kMinTileY = 8;  // smallest of them (sizes per-tile partial sums)
 constexpr int kCoarseBlockCells = 1024;  // first level handled by the single-workgroup kernel
 constexpr int kMaxCBLevels = 5;
 
@@ -34,19 +34,22 @@ template <typename T> struct CBMeta {
     int coarse_sweeps;
 };
 
+// interior cells per workgroup of tile shape `id` (0..kNumTiles-1)
+int tile_shape(int id, int* tx, int* ty);
 template <typename T>
-int launch_pre2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, const T* b, T* x, int cnx, int cny,
-                 int cox, int coy, T* bc, int R, const int* active, unsigned long long* prof);
+int launch_pre2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, int tile, const T* b, T* x, int cnx,
+                 int cny, int cox, int coy, T* bc, int R, const int* active, unsigned long long* prof);
 template <typename T>
-int launch_post2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, const T* b, const T* xin,
+int launch_post2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, int tile, const T* b, const T* xin,
                   const T* ec, int cnx, int cny, int cox, int coy, T4 ghost, T* xout, int R, const int* active,
                   unsigned long long* prof);
+// *nparts = number of per-tile partial sums per right-hand side written to part
 template <typename T>
 int launch_post2d_refine(hipStream_t st, const LevelView<T>& L, const LevelView<double>& L64, T tr, T ti,
-                         double tr64, double ti64, int nu, const T* b, const T* xin, const T* ec, int cnx, int cny,
-                         int cox, int coy, T4 ghost, double* u, size_t ustride, const int* jcol,
+                         double tr64, double ti64, int nu, int tile, const T* b, const T* xin, const T* ec, int cnx,
+                         int cny, int cox, int coy, T4 ghost, double* u, size_t ustride, const int* jcol,
                          const double* rho_in, double* rho_out, T* lo, double* part, int R, const int* active,
-                         unsigned long long* prof);
+                         unsigned long long* prof, int* nparts);
 template <typename T>
 int launch_coarse_block(hipStream_t st, const CBMeta<T>& M, T tr, T ti, const T* bin, T* xout, int R,
                         const int* active);

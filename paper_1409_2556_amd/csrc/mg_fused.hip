@@ -23,19 +23,19 @@ template <typename T> struct cx {
 };
 
 // ------------------------------------------------------------------ 2D tiles
-template <typename T, int H> struct Tile2D {
-    static constexpr int EX = kTileX + 2 * H;
-    static constexpr int EY = kTileY + 2 * H;
+template <typename T, int H, int TX, int TY> struct Tile2D {
+    static constexpr int EX = TX + 2 * H;
+    static constexpr int EY = TY + 2 * H;
     T xr[EY][EX], xi[EY][EX];
     T br[EY][EX], bi[EY][EX];
     T tx[EY][EX], ty[EY][EX];
     T dr[EY][EX], di[EY][EX];
 };
 
-template <typename T, int H>
-__device__ __forceinline__ void tile_sweeps(Tile2D<T, H>& s, int gx0, int gy0, int nx, int ny, int nhalf,
+template <typename T, int H, int TX, int TY>
+__device__ __forceinline__ void tile_sweeps(Tile2D<T, H, TX, TY>& s, int gx0, int gy0, int nx, int ny, int nhalf,
                                             int first_color) {
-    constexpr int EX = Tile2D<T, H>::EX, EY = Tile2D<T, H>::EY;
+    constexpr int EX = Tile2D<T, H, TX, TY>::EX, EY = Tile2D<T, H, TX, TY>::EY;
     for (int hs = 0; hs < nhalf; ++hs) {
         const int color = (first_color + hs) & 1;
         const int sh = hs + 1;
@@ -94,13 +94,13 @@ constexpr int kThreads = 256;  // every fused 2D kernel runs 256 threads
 // PROLONG, x = xin + P e is formed from the coarse patch staged in pxr/pxi
 // (which the caller loads and which may alias s.xr/s.xi: a barrier separates
 // its last read from the first store here); otherwise x = 0.
-template <typename T, int H, bool PROLONG>
-__device__ __forceinline__ void tile_load(Tile2D<T, H>& s, const LevelView<T>& L, T tr, T ti,
+template <typename T, int H, int TX, int TY, bool PROLONG>
+__device__ __forceinline__ void tile_load(Tile2D<T, H, TX, TY>& s, const LevelView<T>& L, T tr, T ti,
                                           const T* __restrict__ br, const T* __restrict__ bi,
                                           const T* __restrict__ xr, const T* __restrict__ xi, int gx0, int gy0,
                                           const T* pxr, const T* pxi, int px0, int py0, int pnx, int cnx, int cny,
                                           int cox, int coy, T4 ghost) {
-    constexpr int EX = Tile2D<T, H>::EX, EY = Tile2D<T, H>::EY;
+    constexpr int EX = Tile2D<T, H, TX, TY>::EX, EY = Tile2D<T, H, TX, TY>::EY;
     constexpr int NC = EX * EY, NL = (NC + kThreads - 1) / kThreads;
     T vtx[NL], vty[NL], vd[NL], vm[NL], vbr[NL], vbi[NL], vxr[NL], vxi[NL];
 #pragma unroll
@@ -166,11 +166,11 @@ __device__ __forceinline__ void tile_load(Tile2D<T, H>& s, const LevelView<T>& L
 // Stage the coarse cells the tile's prolongation reads (a patch of at most
 // (EX/2 + 3) x EY or EX x (EY/2 + 3) cells) in pxr/pxi; returns its origin
 // and width.  Followed by a barrier.
-template <typename T, int H>
+template <typename T, int H, int TX, int TY>
 __device__ __forceinline__ void stage_patch(const T* __restrict__ er, const T* __restrict__ ei, int gx0, int gy0,
                                             int nx, int ny, int cnx, int cny, int cox, int coy, T* pxr, T* pxi,
                                             int* px0, int* py0, int* pnx) {
-    constexpr int EX = Tile2D<T, H>::EX, EY = Tile2D<T, H>::EY;
+    constexpr int EX = Tile2D<T, H, TX, TY>::EX, EY = Tile2D<T, H, TX, TY>::EY;
     const int fx0 = max(gx0, 0), fx1 = min(gx0 + EX - 1, nx - 1);
     const int fy0 = max(gy0, 0), fy1 = min(gy0 + EY - 1, ny - 1);
     const int x0 = cox ? max((fx0 >> 1) - 1, 0) : fx0, x1 = cox ? min((fx1 >> 1) + 1, cnx - 1) : fx1;
@@ -201,26 +201,26 @@ __device__ __forceinline__ void stage_patch(const T* __restrict__ er, const T* _
 }
 
 // Pre-smoothing from x = 0, then restriction of the residual.
-template <typename T, int NU>
+template <typename T, int NU, int TX, int TY>
 __global__ __launch_bounds__(256) void k_pre2d(LevelView<T> L, T tr, T ti, const T* __restrict__ b,
                                                T* __restrict__ x, int cnx, int cny, int cox, int coy,
                                                T* __restrict__ bc, const int* __restrict__ active,
                                                unsigned long long* __restrict__ prof, int Rtot) {
     constexpr int H = 2 * NU + 1;
-    __shared__ Tile2D<T, H> s;
+    __shared__ Tile2D<T, H, TX, TY> s;
     const int r = blockIdx.z;
     if (active && !active[r]) return;
     const size_t N = L.N;
-    const int gx0 = blockIdx.x * kTileX - H, gy0 = blockIdx.y * kTileY - H;
-    tile_load<T, H, false>(s, L, tr, ti, b + 2 * N * r, b + 2 * N * r + N, nullptr, nullptr, gx0, gy0, nullptr,
+    const int gx0 = blockIdx.x * TX - H, gy0 = blockIdx.y * TY - H;
+    tile_load<T, H, TX, TY, false>(s, L, tr, ti, b + 2 * N * r, b + 2 * N * r + N, nullptr, nullptr, gx0, gy0, nullptr,
                            nullptr, 0, 0, 0, cnx, cny, cox, coy, T4{});
     __syncthreads();
-    tile_sweeps<T, H>(s, gx0, gy0, L.nx, L.ny, 2 * NU, 0);
+    tile_sweeps<T, H, TX, TY>(s, gx0, gy0, L.nx, L.ny, 2 * NU, 0);
     // interior -> x
     T* xr = x + 2 * N * r;
     T* xi = xr + N;
-    for (int c = threadIdx.x; c < kTileX * kTileY; c += blockDim.x) {
-        const int lx = H + c % kTileX, ly = H + c / kTileX;
+    for (int c = threadIdx.x; c < TX * TY; c += blockDim.x) {
+        const int lx = H + c % TX, ly = H + c / TX;
         const int gx = gx0 + lx, gy = gy0 + ly;
         if (gx < L.nx && gy < L.ny) {
             const int i = gx + L.nx * gy;
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void k_pre2d(LevelView<T> L, T tr, T ti, const
         }
     }
     // residual of the interior, summed per aggregate
-    const int ctx = kTileX >> cox, cty = kTileY >> coy;
+    const int ctx = TX >> cox, cty = TY >> coy;
     const size_t Nc = (size_t)cnx * cny;
     for (int c = threadIdx.x; c < ctx * cty; c += blockDim.x) {
         const int X = blockIdx.x * ctx + c % ctx, Y = blockIdx.y * cty + c / ctx;
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void k_pre2d(LevelView<T> L, T tr, T ti, const
     if (prof && threadIdx.x == 0) {
         // algorithmic bytes of this block: b in, x out (complex), the coefficient
         // arrays Tx, Ty, D, m shared by the Rtot right-hand sides, coarse rhs out
-        const int nxi = min(kTileX, L.nx - blockIdx.x * kTileX), nyi = min(kTileY, L.ny - blockIdx.y * kTileY);
+        const int nxi = min(TX, L.nx - blockIdx.x * TX), nyi = min(TY, L.ny - blockIdx.y * TY);
         const int ncx = min(ctx, cnx - (int)blockIdx.x * ctx), ncy = min(cty, cny - (int)blockIdx.y * cty);
         const double cell = 4.0 * sizeof(T) + 4.0 * sizeof(T) / Rtot;
         const unsigned long long bytes =
@@ -264,31 +264,31 @@ __global__ __launch_bounds__(256) void k_pre2d(LevelView<T> L, T tr, T ti, const
 }
 
 // x_out = post-smooth( x_in + P e_coarse )
-template <typename T, int NU>
+template <typename T, int NU, int TX, int TY>
 __global__ __launch_bounds__(256) void k_post2d(LevelView<T> L, T tr, T ti, const T* __restrict__ b,
                                                 const T* __restrict__ xin, const T* __restrict__ ec, int cnx,
                                                 int cny, int cox, int coy, T4 ghost, T* __restrict__ xout,
                                                 const int* __restrict__ active, unsigned long long* __restrict__ prof,
                                                 int Rtot) {
     constexpr int H = 2 * NU;
-    __shared__ Tile2D<T, H> s;
+    __shared__ Tile2D<T, H, TX, TY> s;
     const int r = blockIdx.z;
     if (active && !active[r]) return;
     const size_t N = L.N;
     const size_t Nc = (size_t)cnx * cny;
-    const int gx0 = blockIdx.x * kTileX - H, gy0 = blockIdx.y * kTileY - H;
+    const int gx0 = blockIdx.x * TX - H, gy0 = blockIdx.y * TY - H;
     const T* er = ec + 2 * Nc * r;
     int px0, py0, pnx;
-    stage_patch<T, H>(er, er + Nc, gx0, gy0, L.nx, L.ny, cnx, cny, cox, coy, &s.xr[0][0], &s.xi[0][0], &px0, &py0,
+    stage_patch<T, H, TX, TY>(er, er + Nc, gx0, gy0, L.nx, L.ny, cnx, cny, cox, coy, &s.xr[0][0], &s.xi[0][0], &px0, &py0,
                       &pnx);
-    tile_load<T, H, true>(s, L, tr, ti, b + 2 * N * r, b + 2 * N * r + N, xin + 2 * N * r, xin + 2 * N * r + N,
+    tile_load<T, H, TX, TY, true>(s, L, tr, ti, b + 2 * N * r, b + 2 * N * r + N, xin + 2 * N * r, xin + 2 * N * r + N,
                           gx0, gy0, &s.xr[0][0], &s.xi[0][0], px0, py0, pnx, cnx, cny, cox, coy, ghost);
     __syncthreads();
-    tile_sweeps<T, H>(s, gx0, gy0, L.nx, L.ny, 2 * NU, 1);
+    tile_sweeps<T, H, TX, TY>(s, gx0, gy0, L.nx, L.ny, 2 * NU, 1);
     T* oxr = xout + 2 * N * r;
     T* oxi = oxr + N;
-    for (int c = threadIdx.x; c < kTileX * kTileY; c += blockDim.x) {
-        const int lx = H + c % kTileX, ly = H + c / kTileX;
+    for (int c = threadIdx.x; c < TX * TY; c += blockDim.x) {
+        const int lx = H + c % TX, ly = H + c / TX;
         const int gx = gx0 + lx, gy = gy0 + ly;
         if (gx < L.nx && gy < L.ny) {
             const int i = gx + L.nx * gy;
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) void k_post2d(LevelView<T> L, T tr, T ti, cons
     if (prof && threadIdx.x == 0) {
         // algorithmic bytes: x in, b in, x out (complex), shared coefficients, and the
         // coarse correction (one coarse cell per aggregate of the fine cells)
-        const int nxi = min(kTileX, L.nx - blockIdx.x * kTileX), nyi = min(kTileY, L.ny - blockIdx.y * kTileY);
+        const int nxi = min(TX, L.nx - blockIdx.x * TX), nyi = min(TY, L.ny - blockIdx.y * TY);
         const double agg = (double)(1 << (cox + coy));
         const double cell = 6.0 * sizeof(T) + 4.0 * sizeof(T) / Rtot + 2.0 * sizeof(T) / agg;
         atomicAdd(prof, (unsigned long long)(nxi * nyi * cell));
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(256) void k_post2d(LevelView<T> L, T tr, T ti, cons
 // One more halo ring than the plain post-smoother keeps e exact next to the
 // interior, so A e is exact there.  rho_in and the input b of the tile may be
 // the same buffer; rho_out and lo must not alias anything read here.
-template <typename T, int NU>
+template <typename T, int NU, int TX, int TY>
 __global__ __launch_bounds__(256) void k_post2d_refine(LevelView<T> L, LevelView<double> L64, T tr, T ti,
                                                        double tr64, double ti64, const T* __restrict__ b,
                                                        const T* __restrict__ xin, const T* __restrict__ ec,
@@ -325,32 +325,31 @@ __global__ __launch_bounds__(256) void k_post2d_refine(LevelView<T> L, LevelView
                                                        const int* __restrict__ active,
                                                        unsigned long long* __restrict__ prof, int Rtot) {
     constexpr int H = 2 * NU + 1;
-    __shared__ Tile2D<T, H> s;
+    __shared__ Tile2D<T, H, TX, TY> s;
     __shared__ double red[4];
     const int r = blockIdx.z;
     if (active && !active[r]) return;
     const size_t N = L.N;
     const size_t Nc = (size_t)cnx * cny;
-    const int gx0 = blockIdx.x * kTileX - H, gy0 = blockIdx.y * kTileY - H;
+    const int gx0 = blockIdx.x * TX - H, gy0 = blockIdx.y * TY - H;
     const T* er = ec + 2 * Nc * r;
     int px0, py0, pnx;
-    stage_patch<T, H>(er, er + Nc, gx0, gy0, L.nx, L.ny, cnx, cny, cox, coy, &s.xr[0][0], &s.xi[0][0], &px0, &py0,
+    stage_patch<T, H, TX, TY>(er, er + Nc, gx0, gy0, L.nx, L.ny, cnx, cny, cox, coy, &s.xr[0][0], &s.xi[0][0], &px0, &py0,
                       &pnx);
-    tile_load<T, H, true>(s, L, tr, ti, b + 2 * N * r, b + 2 * N * r + N, xin + 2 * N * r, xin + 2 * N * r + N,
+    tile_load<T, H, TX, TY, true>(s, L, tr, ti, b + 2 * N * r, b + 2 * N * r + N, xin + 2 * N * r, xin + 2 * N * r + N,
                           gx0, gy0, &s.xr[0][0], &s.xi[0][0], px0, py0, pnx, cnx, cny, cox, coy, ghost);
     __syncthreads();
-    tile_sweeps<T, H>(s, gx0, gy0, L.nx, L.ny, 2 * NU, 1);
+    tile_sweeps<T, H, TX, TY>(s, gx0, gy0, L.nx, L.ny, 2 * NU, 1);
     double* ur = u + ustride * r + (jcol ? 2 * N * (size_t)*jcol : 0);
     const double* rin = rho_in + 2 * N * r;
     double* rout = rho_out + 2 * N * r;
     // FP64 update of the interior: all global loads of a thread's cells first
-    constexpr int NI = kTileX * kTileY / kThreads;
-    static_assert(kTileX * kTileY % kThreads == 0, "interior cells per thread");
+    constexpr int NI = (TX * TY + kThreads - 1) / kThreads;
     double vte[NI], vtw[NI], vtn[NI], vts[NI], vd[NI], vm[NI], vur[NI], vui[NI], vrr[NI], vri[NI];
 #pragma unroll
     for (int k = 0; k < NI; ++k) {
-        const int c = threadIdx.x + kThreads * k;
-        const int gx = min(gx0 + H + c % kTileX, L.nx - 1), gy = min(gy0 + H + c / kTileX, L.ny - 1);
+        const int c = min((int)threadIdx.x + kThreads * k, TX * TY - 1);
+        const int gx = min(gx0 + H + c % TX, L.nx - 1), gy = min(gy0 + H + c / TX, L.ny - 1);
         const int i = gx + L.nx * gy;
         vte[k] = L64.Tx[i];
         vtw[k] = L64.Tx[max(i - 1, 0)];
@@ -367,9 +366,9 @@ __global__ __launch_bounds__(256) void k_post2d_refine(LevelView<T> L, LevelView
 #pragma unroll
     for (int k = 0; k < NI; ++k) {
         const int c = threadIdx.x + kThreads * k;
-        const int lx = H + c % kTileX, ly = H + c / kTileX;
+        const int lx = H + c % TX, ly = H + c / TX;
         const int gx = gx0 + lx, gy = gy0 + ly;
-        if (gx >= L.nx || gy >= L.ny) continue;
+        if (c >= TX * TY || gx >= L.nx || gy >= L.ny) continue;
         const int i = gx + L.nx * gy;
         const double e0r = (double)s.xr[ly][lx], e0i = (double)s.xi[ly][lx];
         // (K + tau M) e with the FP64 operator; walls are in D, out-of-grid neighbours hold 0
@@ -400,7 +399,7 @@ __global__ __launch_bounds__(256) void k_post2d_refine(LevelView<T> L, LevelView
         part[(size_t)r * gridDim.x * gridDim.y + blockIdx.x + (size_t)gridDim.x * blockIdx.y] =
             red[0] + red[1] + red[2] + red[3];
         if (prof) {
-            const int nxi = min(kTileX, L.nx - blockIdx.x * kTileX), nyi = min(kTileY, L.ny - blockIdx.y * kTileY);
+            const int nxi = min(TX, L.nx - blockIdx.x * TX), nyi = min(TY, L.ny - blockIdx.y * TY);
             const double agg = (double)(1 << (cox + coy));
             // x in, b in (T complex), shared T coefficients, coarse correction in,
             // u in/out and rho in/out (FP64 complex), lo out (T complex), FP64 coefficients (shared)
@@ -413,38 +412,43 @@ __global__ __launch_bounds__(256) void k_post2d_refine(LevelView<T> L, LevelView
 
 // ------------------------------------------------------------------ coarse levels in one workgroup
 // Thread i owns cell i of every level (levels have at most blockDim cells): its
-// face transmissibilities, diagonal and right-hand side stay in registers,
-// iterates and residuals go through LDS.
+// face transmissibilities, diagonal, right-hand side, neighbour indices and
+// colour stay in registers, iterates and residuals go through LDS.
 template <typename T> struct CBCell {
     T tw, te, ts, tn, tb, tt;  // faces to the -x, +x, -y, +y, -z, +z neighbours
     T dr, di;                  // D + tau m
     T br, bi;                  // right-hand side of this level
+    int flags;                 // bits 0-5: neighbour exists at +x, -x, +y, -y, +z, -z; bit 6: colour
 };
 
 template <typename T>
 __device__ __forceinline__ void cb_load_cell(const CBLevel<T>& L, T tr, T ti, int i, CBCell<T>& c) {
     const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
     const int sy = L.nx, sz = L.nx * L.ny;
-    c.te = (x + 1 < L.nx) ? L.Tx[i] : T(0);
-    c.tw = (x > 0) ? L.Tx[i - 1] : T(0);
-    c.tn = (y + 1 < L.ny) ? L.Ty[i] : T(0);
-    c.ts = (y > 0) ? L.Ty[i - sy] : T(0);
-    c.tt = (z + 1 < L.nz) ? L.Tz[i] : T(0);
-    c.tb = (z > 0) ? L.Tz[i - sz] : T(0);
-    c.dr = L.D[i] + tr * L.m[i];
-    c.di = ti * L.m[i];
+    c.flags = (x + 1 < L.nx) | ((x > 0) << 1) | ((y + 1 < L.ny) << 2) | ((y > 0) << 3) | ((z + 1 < L.nz) << 4) |
+              ((z > 0) << 5) | (((x + y + z) & 1) << 6);
+    // walls have zero couplings (and no neighbour load)
+    const T tx = L.Tx[i], txw = L.Tx[x > 0 ? i - 1 : i], ty = L.Ty[i], tys = L.Ty[y > 0 ? i - sy : i];
+    const T tz = L.Tz[i], tzb = L.Tz[z > 0 ? i - sz : i];
+    const T d = L.D[i], m = L.m[i];
+    c.te = (x + 1 < L.nx) ? tx : T(0);
+    c.tw = (x > 0) ? txw : T(0);
+    c.tn = (y + 1 < L.ny) ? ty : T(0);
+    c.ts = (y > 0) ? tys : T(0);
+    c.tt = (z + 1 < L.nz) ? tz : T(0);
+    c.tb = (z > 0) ? tzb : T(0);
+    c.dr = d + tr * m;
+    c.di = ti * m;
 }
 
-// off = sum of couplings times neighbour values (zero couplings at walls, so the
-// clamped neighbour index is never used with a non-zero weight)
+// off = sum of couplings times neighbour values (a missing neighbour reads the cell itself with weight 0)
 template <typename T>
 __device__ __forceinline__ void cb_off(const CBLevel<T>& L, const CBCell<T>& c, const T* xr, const T* xi, int i,
                                        T& ore, T& oim) {
-    const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
-    const int sy = L.nx, sz = L.nx * L.ny;
-    const int e = (x + 1 < L.nx) ? i + 1 : i, w = (x > 0) ? i - 1 : i;
-    const int n = (y + 1 < L.ny) ? i + sy : i, s = (y > 0) ? i - sy : i;
-    const int t = (z + 1 < L.nz) ? i + sz : i, b = (z > 0) ? i - sz : i;
+    const int sy = L.nx, sz = L.nx * L.ny, f = c.flags;
+    const int e = (f & 1) ? i + 1 : i, w = (f & 2) ? i - 1 : i;
+    const int n = (f & 4) ? i + sy : i, s = (f & 8) ? i - sy : i;
+    const int t = (f & 16) ? i + sz : i, b = (f & 32) ? i - sz : i;
     ore = c.te * xr[e] + c.tw * xr[w] + c.tn * xr[n] + c.ts * xr[s] + c.tt * xr[t] + c.tb * xr[b];
     oim = c.te * xi[e] + c.tw * xi[w] + c.tn * xi[n] + c.ts * xi[s] + c.tt * xi[t] + c.tb * xi[b];
 }
@@ -484,7 +488,7 @@ __global__ __launch_bounds__(1024) void k_coarse_block(CBMeta<T> M, T tr, T ti, 
         T* rr = xi + L.N;
         T* ri = rr + L.N;
         const bool own = i < L.N;
-        const int par = own ? ((i % L.nx) + ((i / L.nx) % L.ny) + i / (L.nx * L.ny)) & 1 : 0;
+        const int par = own ? (c[l].flags >> 6) & 1 : 0;
         for (int sw = 0; sw < M.nu1; ++sw)
             for (int col = 0; col < 2; ++col) {
                 if (own && par == col) {
@@ -552,7 +556,7 @@ __global__ __launch_bounds__(1024) void k_coarse_block(CBMeta<T> M, T tr, T ti, 
             }
             __syncthreads();
         } else {
-            const int par = own ? ((i % L.nx) + ((i / L.nx) % L.ny) + i / (L.nx * L.ny)) & 1 : 0;
+            const int par = own ? (c[l].flags >> 6) & 1 : 0;
             for (int sw = 0; sw < M.coarse_sweeps; ++sw)
                 for (int col = 0; col < 2; ++col) {
                     if (own && par == col) {
@@ -598,7 +602,7 @@ __global__ __launch_bounds__(1024) void k_coarse_block(CBMeta<T> M, T tr, T ti, 
             xi[i] += pi;
         }
         __syncthreads();
-        const int par = own ? ((i % L.nx) + ((i / L.nx) % L.ny) + i / (L.nx * L.ny)) & 1 : 0;
+        const int par = own ? (c[l].flags >> 6) & 1 : 0;
         for (int sw = 0; sw < M.nu2; ++sw)
             for (int col = 1; col >= 0; --col) {
                 if (own && par == col) {
@@ -624,52 +628,84 @@ __global__ __launch_bounds__(1024) void k_coarse_block(CBMeta<T> M, T tr, T ti, 
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename T>
-int launch_pre2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, const T* b, T* x, int cnx, int cny,
-                 int cox, int coy, T* bc, int R, const int* active, unsigned long long* prof) {
-    dim3 grid((L.nx + kTileX - 1) / kTileX, (L.ny + kTileY - 1) / kTileY, R);
-    switch (nu) {
-        case 1: k_pre2d<T, 1><<<grid, 256, 0, st>>>(L, tr, ti, b, x, cnx, cny, cox, coy, bc, active, prof, R); break;
-        case 2: k_pre2d<T, 2><<<grid, 256, 0, st>>>(L, tr, ti, b, x, cnx, cny, cox, coy, bc, active, prof, R); break;
-        case 3: k_pre2d<T, 3><<<grid, 256, 0, st>>>(L, tr, ti, b, x, cnx, cny, cox, coy, bc, active, prof, R); break;
-        default: set_last_error("fused smoother supports 1..3 sweeps"); return LT_EUNSUPPORTED;
+// Tile shapes (interior cells per workgroup); the id is what lt_autotune picks per level.
+int tile_shape(int id, int* tx, int* ty) {
+    static const int shapes[kNumTiles][2] = {{32, 16}, {64, 8}, {16, 16}, {16, 8}};
+    if (id < 0 || id >= kNumTiles) return LT_EINVAL;
+    *tx = shapes[id][0];
+    *ty = shapes[id][1];
+    return 0;
+}
+
+// expands F(TX, TY) for the tile id, F(NU) for the sweep count
+#define LT_TILE_SWITCH(id, F)                                                    \
+    switch (id) {                                                                \
+        case 0: F(32, 16); break;                                                \
+        case 1: F(64, 8); break;                                                 \
+        case 2: F(16, 16); break;                                                \
+        case 3: F(16, 8); break;                                                 \
+        default: set_last_error("unknown tile shape"); return LT_EINVAL;         \
     }
+
+template <typename T>
+int launch_pre2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, int tile, const T* b, T* x, int cnx,
+                 int cny, int cox, int coy, T* bc, int R, const int* active, unsigned long long* prof) {
+    if (nu < 1 || nu > 3) {
+        set_last_error("fused smoother supports 1..3 sweeps");
+        return LT_EUNSUPPORTED;
+    }
+#define LT_K(NU, X, Y) \
+    k_pre2d<T, NU, X, Y><<<dim3((L.nx + X - 1) / X, (L.ny + Y - 1) / Y, R), kThreads, 0, st>>>( \
+        L, tr, ti, b, x, cnx, cny, cox, coy, bc, active, prof, R)
+#define LT_T(X, Y) \
+    if (nu == 1) LT_K(1, X, Y); else if (nu == 2) LT_K(2, X, Y); else LT_K(3, X, Y)
+    LT_TILE_SWITCH(tile, LT_T)
+#undef LT_T
+#undef LT_K
     LT_HIP(hipGetLastError());
     return 0;
 }
 
 template <typename T>
-int launch_post2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, const T* b, const T* xin,
+int launch_post2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, int tile, const T* b, const T* xin,
                   const T* ec, int cnx, int cny, int cox, int coy, T4 ghost, T* xout, int R, const int* active,
                   unsigned long long* prof) {
-    dim3 grid((L.nx + kTileX - 1) / kTileX, (L.ny + kTileY - 1) / kTileY, R);
-    switch (nu) {
-        case 1: k_post2d<T, 1><<<grid, 256, 0, st>>>(L, tr, ti, b, xin, ec, cnx, cny, cox, coy, ghost, xout, active, prof, R); break;
-        case 2: k_post2d<T, 2><<<grid, 256, 0, st>>>(L, tr, ti, b, xin, ec, cnx, cny, cox, coy, ghost, xout, active, prof, R); break;
-        case 3: k_post2d<T, 3><<<grid, 256, 0, st>>>(L, tr, ti, b, xin, ec, cnx, cny, cox, coy, ghost, xout, active, prof, R); break;
-        default: set_last_error("fused smoother supports 1..3 sweeps"); return LT_EUNSUPPORTED;
+    if (nu < 1 || nu > 3) {
+        set_last_error("fused smoother supports 1..3 sweeps");
+        return LT_EUNSUPPORTED;
     }
+#define LT_K(NU, X, Y) \
+    k_post2d<T, NU, X, Y><<<dim3((L.nx + X - 1) / X, (L.ny + Y - 1) / Y, R), kThreads, 0, st>>>( \
+        L, tr, ti, b, xin, ec, cnx, cny, cox, coy, ghost, xout, active, prof, R)
+#define LT_T(X, Y) \
+    if (nu == 1) LT_K(1, X, Y); else if (nu == 2) LT_K(2, X, Y); else LT_K(3, X, Y)
+    LT_TILE_SWITCH(tile, LT_T)
+#undef LT_T
+#undef LT_K
     LT_HIP(hipGetLastError());
     return 0;
 }
 
 template <typename T>
 int launch_post2d_refine(hipStream_t st, const LevelView<T>& L, const LevelView<double>& L64, T tr, T ti,
-                         double tr64, double ti64, int nu, const T* b, const T* xin, const T* ec, int cnx, int cny,
-                         int cox, int coy, T4 ghost, double* u, size_t ustride, const int* jcol,
+                         double tr64, double ti64, int nu, int tile, const T* b, const T* xin, const T* ec, int cnx,
+                         int cny, int cox, int coy, T4 ghost, double* u, size_t ustride, const int* jcol,
                          const double* rho_in, double* rho_out, T* lo, double* part, int R, const int* active,
-                         unsigned long long* prof) {
-    dim3 grid((L.nx + kTileX - 1) / kTileX, (L.ny + kTileY - 1) / kTileY, R);
-#define LT_PR(NU)                                                                                              \
-    k_post2d_refine<T, NU><<<grid, 256, 0, st>>>(L, L64, tr, ti, tr64, ti64, b, xin, ec, cnx, cny, cox, coy,   \
-                                                 ghost, u, ustride, jcol, rho_in, rho_out, lo, part, active, prof, R)
-    switch (nu) {
-        case 1: LT_PR(1); break;
-        case 2: LT_PR(2); break;
-        case 3: LT_PR(3); break;
-        default: set_last_error("fused smoother supports 1..3 sweeps"); return LT_EUNSUPPORTED;
+                         unsigned long long* prof, int* nparts) {
+    if (nu < 1 || nu > 3) {
+        set_last_error("fused smoother supports 1..3 sweeps");
+        return LT_EUNSUPPORTED;
     }
-#undef LT_PR
+#define LT_K(NU, X, Y)                                                                                        \
+    k_post2d_refine<T, NU, X, Y><<<dim3((L.nx + X - 1) / X, (L.ny + Y - 1) / Y, R), kThreads, 0, st>>>(       \
+        L, L64, tr, ti, tr64, ti64, b, xin, ec, cnx, cny, cox, coy, ghost, u, ustride, jcol, rho_in, rho_out, lo, \
+        part, active, prof, R)
+#define LT_T(X, Y)                                                          \
+    *nparts = ((L.nx + X - 1) / X) * ((L.ny + Y - 1) / Y);                 \
+    if (nu == 1) LT_K(1, X, Y); else if (nu == 2) LT_K(2, X, Y); else LT_K(3, X, Y)
+    LT_TILE_SWITCH(tile, LT_T)
+#undef LT_T
+#undef LT_K
     LT_HIP(hipGetLastError());
     return 0;
 }
@@ -694,24 +730,25 @@ int launch_coarse_block(hipStream_t st, const CBMeta<T>& M, T tr, T ti, const T*
     return 0;
 }
 
-template int launch_pre2d<float>(hipStream_t, const LevelView<float>&, float, float, int, const float*, float*, int,
-                                 int, int, int, float*, int, const int*, unsigned long long*);
-template int launch_pre2d<double>(hipStream_t, const LevelView<double>&, double, double, int, const double*, double*,
-                                  int, int, int, int, double*, int, const int*, unsigned long long*);
-template int launch_post2d<float>(hipStream_t, const LevelView<float>&, float, float, int, const float*,
+template int launch_pre2d<float>(hipStream_t, const LevelView<float>&, float, float, int, int, const float*, float*,
+                                 int, int, int, int, float*, int, const int*, unsigned long long*);
+template int launch_pre2d<double>(hipStream_t, const LevelView<double>&, double, double, int, int, const double*,
+                                  double*, int, int, int, int, double*, int, const int*, unsigned long long*);
+template int launch_post2d<float>(hipStream_t, const LevelView<float>&, float, float, int, int, const float*,
                                   const float*, const float*, int, int, int, int, T4, float*, int, const int*,
                                   unsigned long long*);
-template int launch_post2d<double>(hipStream_t, const LevelView<double>&, double, double, int, const double*,
+template int launch_post2d<double>(hipStream_t, const LevelView<double>&, double, double, int, int, const double*,
                                    const double*, const double*, int, int, int, int, T4, double*, int, const int*,
                                    unsigned long long*);
 template int launch_post2d_refine<float>(hipStream_t, const LevelView<float>&, const LevelView<double>&, float, float,
-                                         double, double, int, const float*, const float*, const float*, int, int,
-                                         int, int, T4, double*, size_t, const int*, const double*, double*, float*,
-                                         double*, int, const int*, unsigned long long*);
+                                         double, double, int, int, const float*, const float*, const float*, int,
+                                         int, int, int, T4, double*, size_t, const int*, const double*, double*,
+                                         float*, double*, int, const int*, unsigned long long*, int*);
 template int launch_post2d_refine<double>(hipStream_t, const LevelView<double>&, const LevelView<double>&, double,
-                                          double, double, double, int, const double*, const double*, const double*,
-                                          int, int, int, int, T4, double*, size_t, const int*, const double*, double*,
-                                          double*, double*, int, const int*, unsigned long long*);
+                                          double, double, double, int, int, const double*, const double*,
+                                          const double*, int, int, int, int, T4, double*, size_t, const int*,
+                                          const double*, double*, double*, double*, int, const int*,
+                                          unsigned long long*, int*);
 template int launch_coarse_block<float>(hipStream_t, const CBMeta<float>&, float, float, const float*, float*, int,
                                         const int*);
 template int launch_coarse_block<double>(hipStream_t, const CBMeta<double>&, double, double, const double*, double*,

@@ -60,3 +60,9 @@ def test_error_codes_without_gpu(lib):
     assert "no handle" in lib.lt_last_error()
     adj = (lib.lt_adjoint_item * 1)()
     assert so.lt_adjoint_batch(adj, 1) == lib.LT_EINVAL
+    # tile shapes
+    assert [lib.lt_tile_shape(i) for i in range(4)] == [(32, 16), (64, 8), (16, 16), (16, 8)]
+    tx = lib.C.c_int()
+    assert so.lt_tile_shape(4, lib.C.byref(tx), lib.C.byref(tx)) == lib.LT_EINVAL
+    assert so.lt_autotune(None, 0, 2, 2, 1, None, 0, None) == lib.LT_EINVAL
+    assert so.lt_set_tiles(None, 0, None, 0) == lib.LT_EINVAL
