@@ -67,7 +67,30 @@ def _parse():
                          "size, to scale hardware byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-times", type=int, default=4)
+    ap.add_argument("--no-tune", action="store_true", help="keep the default smoother tile shapes")
+    ap.add_argument("--workload", choices=["C2", "C5"], default="C2",
+                    help="C2: the 256x256 workload (default); C5: the batch of six uneven 2D/3D grids "
+                         "solved in one lt_solve_batch call")
     return ap.parse_args()
+
+
+def _handle(lt, p, tune, nvec):
+    """Handle on a stream of its own, with smoother tiles tuned for both precisions (setup, untimed)."""
+    import torch
+    kap = torch.tensor(p.kappa, dtype=torch.float64, device="cuda")
+    S = torch.tensor(p.S, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    h = lt.lt_setup(p.ndim, p.n, p.h, kap, S, bc=p.bc, stream=stream)
+    h._torch_stream = stream
+    tiles = {}
+    if tune:
+        for name, prec in (("fp64", lt.LT_PREC_FP64), ("mixed", lt.LT_PREC_MIXED)):
+            t0 = time.perf_counter()
+            ids, us = lt.lt_autotune(h, prec, 2, 2, nvec)
+            tiles[name] = {"tiles": [list(lt.lt_tile_shape(t)) for t in ids], "us_per_step": us,
+                           "tune_ms": (time.perf_counter() - t0) * 1e3}
+    return h, tiles
 
 
 def _run_variant(lt, h, p, opts, steps, warmup, profile=0):
@@ -121,6 +144,8 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "C5":
+        return main_batch(args)
     import workloads as wl
     p = wl.make_problem(WORKLOAD)
     # the CPU oracle runs first, before this process touches the GPU
@@ -135,9 +160,7 @@ def main():
     from paper_1409_2556_amd import binding as lt
 
     torch.cuda.set_device(0)
-    kap = torch.tensor(p.kappa, dtype=torch.float64, device="cuda")
-    S = torch.tensor(p.S, dtype=torch.float64, device="cuda")
-    h = lt.lt_setup(p.ndim, p.n, p.h, kap, S)
+    h, tiles = _handle(lt, p, not args.no_tune, len(p.sources))
     pairs = len(p.sources) * len(p.times) * (p.nz_contour // 2)
     res = {}
     variants = [("fp64", lt.LT_PREC_FP64, args.tol_fp64), ("mixed", lt.LT_PREC_MIXED, args.tol_mixed),
@@ -216,7 +239,8 @@ def main():
                    "rhs": len(p.sources), "shifts_per_rhs": len(p.times) * (p.nz_contour // 2),
                    "pairs": pairs, "tol": head["tol"], "relax": args.relax, "variant": hname,
                    "precision": "FP32 V-cycle, FP64 outer",
-                   "iters": head["st"]["iters_max"], "vcycles": head["st"]["vcycles"]},
+                   "iters": head["st"]["iters_max"], "vcycles": head["st"]["vcycles"],
+                   "smoother_tiles": tiles},
         "variants": {
             name: {"solves_per_s": pairs / r["dt"], "ms_per_step": r["dt"] * 1e3, "tol": r["tol"],
                    "iters": r["st"]["iters_max"], "vcycles": r["st"]["vcycles"],
@@ -234,6 +258,83 @@ def main():
         lt.lt_unet_attach(h, None)
         net.close()
     h.close()
+
+
+def main_batch(args):
+    """The six-grid batch (128^2, 256^2, 512^2, 32^3, 64^3, 128x128x64; 16 sources, 32 receivers,
+    2 times, 24-node contour each) in one lt_solve_batch call per step."""
+    import workloads as wl
+    ps = wl.make_batch()
+    pairs = sum(len(p.sources) * len(p.times) * (p.nz_contour // 2) for p in ps)
+    cpu, ref = None, None
+    small = ps[0]  # the oracle sample: the 128x128 problem, first time
+    if not args.no_cpu_baseline:
+        from oracle.heads import heads
+        workers = min(os.cpu_count() or 1, 16)
+        t0 = time.perf_counter()
+        ref = heads(small.n, small.h, small.kappa, small.S, small.sources, small.receivers, small.times[:1],
+                    small.nz_contour, q=small.q, bc=small.bc, workers=workers, ndim=small.ndim)
+        dt = time.perf_counter() - t0
+        npair = len(small.sources) * (small.nz_contour // 2)
+        cpu = {"value": npair / dt, "unit": "shifted solves/s", "cores": workers, "kind": "oracle",
+               "sample": f"the 128x128 problem of the batch: {len(small.sources)} sources x first time x "
+                         f"{small.nz_contour // 2} shifts = {npair} pairs, SuperLU per shift ({dt:.1f} s)"}
+        print(f"[bench] oracle sample: {cpu['value']:.2f} solves/s", file=sys.stderr, flush=True)
+    import torch
+    from paper_1409_2556_amd import binding as lt
+    torch.cuda.set_device(0)
+    hs, tiles = [], {}
+    for p in ps:
+        h, t = _handle(lt, p, not args.no_tune, len(p.sources))
+        hs.append(h)
+        tiles[p.name] = t
+    res = {}
+    for name, prec, tol in (("fp64", lt.LT_PREC_FP64, 1e-9), ("mixed", lt.LT_PREC_MIXED, 1e-8)):
+        opts = [lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau, maxit=64, relax=1.0) for p in ps]
+        items = [dict(handle=h, sources=p.sources, q=p.q, times=p.times, nz=p.nz_contour, receivers=p.receivers,
+                      opts=o) for p, h, o in zip(ps, hs, opts)]
+        for _ in range(args.warmup):
+            outs, sts, rc = lt.lt_solve_batch(items)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            outs, sts, rc = lt.lt_solve_batch(items)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        err = None
+        if ref is not None:
+            got = outs[0].cpu().numpy()[:, :, :1]
+            e = np.linalg.norm((got - ref).reshape(len(small.sources), -1), axis=1) / \
+                np.linalg.norm(ref.reshape(len(small.sources), -1), axis=1)
+            err = float(e.max())
+        res[name] = {"dt": dt, "tol": tol, "err": err, "rc": rc,
+                     "per_problem": {p.name: {"iters": s["iters_max"], "vcycles": s["vcycles"],
+                                              "true_relres_weighted_max": s["true_relres_max"],
+                                              "solve_ms": s["seconds"] * 1e3} for p, s in zip(ps, sts)}}
+        print(f"[bench] C5 {name}: {dt * 1e3:.1f} ms/step, {pairs / dt:.0f} solves/s, err {err}", file=sys.stderr,
+              flush=True)
+    head = res["mixed"]
+    valid = head["rc"] == 0 and (head["err"] is None or head["err"] <= 1e-5)
+    out = {
+        "metric": "shifted solves/sec (RHS\u00d7shift, rel head err 1e-5): learned+mixed vs plain FGMRES",
+        "value": pairs / head["dt"] if valid else 0.0,
+        "unit": "shifted solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["dt"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": "batch of six uneven grids (128^2, 256^2, 512^2, 32^3, 64^3, 128x128x64), "
+                               "16 sources x 32 receivers each, times {0.3, 1.2}, 24-node Talbot, "
+                               "lt_solve_batch (one stream per problem)",
+                   "pairs": pairs, "variant": "mixed", "smoother_tiles": tiles},
+        "variants": {n: {"solves_per_s": pairs / r["dt"], "ms_per_step": r["dt"] * 1e3, "tol": r["tol"],
+                         "rel_head_err_vs_oracle_128": r["err"], "per_problem": r["per_problem"]}
+                     for n, r in res.items()},
+        "vs_plain_fp64": res["fp64"]["dt"] / head["dt"],
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    for h in hs:
+        h.close()
 
 
 if __name__ == "__main__":
