@@ -29,31 +29,37 @@ template <typename T, int H, int TX, int TY> struct Tile2D {
     T xr[EY][EX], xi[EY][EX];
     T br[EY][EX], bi[EY][EX];
     T tx[EY][EX], ty[EY][EX];
-    T dr[EY][EX], di[EY][EX];
+    T dr[EY][EX], di[EY][EX];  // inverse of the diagonal D + tau m
 };
 
+// nhalf half-sweeps of red-black Gauss-Seidel on the tile.  Threads walk the
+// cells of the colour being updated only (half the cells of each row), and
+// the tile holds the inverse of the complex diagonal, so an update is
+// x = (b + off) / d with no division.
 template <typename T, int H, int TX, int TY>
 __device__ __forceinline__ void tile_sweeps(Tile2D<T, H, TX, TY>& s, int gx0, int gy0, int nx, int ny, int nhalf,
                                             int first_color) {
     constexpr int EX = Tile2D<T, H, TX, TY>::EX, EY = Tile2D<T, H, TX, TY>::EY;
+    static_assert(EX % 2 == 0, "tile rows hold whole colour pairs");
+    constexpr int W = EX / 2;
     for (int hs = 0; hs < nhalf; ++hs) {
         const int color = (first_color + hs) & 1;
         const int sh = hs + 1;
-        for (int c = threadIdx.x; c < EX * EY; c += blockDim.x) {
-            const int lx = c % EX, ly = c / EX;
-            if (lx < sh || lx >= EX - sh || ly < sh || ly >= EY - sh) continue;
+        const int nrow = EY - 2 * sh;
+        for (int c = threadIdx.x; c < nrow * W; c += blockDim.x) {
+            const int ly = sh + c / W;
+            const int lx = 2 * (c % W) + ((color + gx0 + gy0 + ly) & 1);
+            if (lx < sh || lx >= EX - sh) continue;
             const int gx = gx0 + lx, gy = gy0 + ly;
             if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) continue;
-            if (((gx + gy) & 1) != color) continue;
-            T ore = s.tx[ly][lx] * s.xr[ly][lx + 1] + s.tx[ly][lx - 1] * s.xr[ly][lx - 1] +
-                    s.ty[ly][lx] * s.xr[ly + 1][lx] + s.ty[ly - 1][lx] * s.xr[ly - 1][lx];
-            T oim = s.tx[ly][lx] * s.xi[ly][lx + 1] + s.tx[ly][lx - 1] * s.xi[ly][lx - 1] +
-                    s.ty[ly][lx] * s.xi[ly + 1][lx] + s.ty[ly - 1][lx] * s.xi[ly - 1][lx];
-            T nr = s.br[ly][lx] + ore, ni = s.bi[ly][lx] + oim;
-            T dr = s.dr[ly][lx], di = s.di[ly][lx];
-            T dd = dr * dr + di * di;
-            s.xr[ly][lx] = (nr * dr + ni * di) / dd;
-            s.xi[ly][lx] = (ni * dr - nr * di) / dd;
+            const T ore = s.tx[ly][lx] * s.xr[ly][lx + 1] + s.tx[ly][lx - 1] * s.xr[ly][lx - 1] +
+                          s.ty[ly][lx] * s.xr[ly + 1][lx] + s.ty[ly - 1][lx] * s.xr[ly - 1][lx];
+            const T oim = s.tx[ly][lx] * s.xi[ly][lx + 1] + s.tx[ly][lx - 1] * s.xi[ly][lx - 1] +
+                          s.ty[ly][lx] * s.xi[ly + 1][lx] + s.ty[ly - 1][lx] * s.xi[ly - 1][lx];
+            const T nr = s.br[ly][lx] + ore, ni = s.bi[ly][lx] + oim;
+            const T ir = s.dr[ly][lx], ii = s.di[ly][lx];
+            s.xr[ly][lx] = nr * ir - ni * ii;
+            s.xi[ly][lx] = nr * ii + ni * ir;
         }
         __syncthreads();
     }
@@ -154,8 +160,11 @@ __device__ __forceinline__ void tile_load(Tile2D<T, H, TX, TY>& s, const LevelVi
         const bool in = gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny;
         s.tx[ly][lx] = in ? vtx[k] : T(0);
         s.ty[ly][lx] = in ? vty[k] : T(0);
-        s.dr[ly][lx] = in ? vd[k] + tr * vm[k] : T(1);
-        s.di[ly][lx] = in ? ti * vm[k] : T(0);
+        // inverse of the diagonal D + tau m (1 outside the grid)
+        const T dr = in ? vd[k] + tr * vm[k] : T(1), di = in ? ti * vm[k] : T(0);
+        const T dd = dr * dr + di * di;
+        s.dr[ly][lx] = dr / dd;
+        s.di[ly][lx] = -di / dd;
         s.br[ly][lx] = in ? vbr[k] : T(0);
         s.bi[ly][lx] = in ? vbi[k] : T(0);
         s.xr[ly][lx] = (PROLONG && in) ? vxr[k] : T(0);
@@ -242,8 +251,11 @@ __global__ __launch_bounds__(256) void k_pre2d(LevelView<T> L, T tr, T ti, const
                         s.ty[ly][lx] * s.xr[ly + 1][lx] + s.ty[ly - 1][lx] * s.xr[ly - 1][lx];
                 T oim = s.tx[ly][lx] * s.xi[ly][lx + 1] + s.tx[ly][lx - 1] * s.xi[ly][lx - 1] +
                         s.ty[ly][lx] * s.xi[ly + 1][lx] + s.ty[ly - 1][lx] * s.xi[ly - 1][lx];
-                T axr = s.dr[ly][lx] * s.xr[ly][lx] - s.di[ly][lx] * s.xi[ly][lx] - ore;
-                T axi = s.dr[ly][lx] * s.xi[ly][lx] + s.di[ly][lx] * s.xr[ly][lx] - oim;
+                // the tile holds the inverse diagonal: take D + tau m from the level arrays
+                const int fi = fx + L.nx * fy;
+                const T dm = L.m[fi], dre = L.D[fi] + tr * dm, dim = ti * dm;
+                T axr = dre * s.xr[ly][lx] - dim * s.xi[ly][lx] - ore;
+                T axi = dre * s.xi[ly][lx] + dim * s.xr[ly][lx] - oim;
                 ar += s.br[ly][lx] - axr;
                 ai += s.bi[ly][lx] - axi;
             }
