@@ -555,16 +555,29 @@ __global__ __launch_bounds__(1024) void k_coarse_block(CBMeta<T> M, T tr, T ti, 
                 ri[i] = c[l].bi;
             }
             __syncthreads();
-            if (own) {
-                const T* row = M.inv + 2 * (size_t)L.N * i;
-                T ar = 0, ai = 0;
-                for (int j = 0; j < L.N; ++j) {
-                    const T a = row[2 * j], bb = row[2 * j + 1];
+            // dense solve x = inv * r: P consecutive lanes share a row (P a power of two, at
+            // most 64, as many as the block allows), so every load of the inverse is in
+            // flight at once; the partial sums meet in a shuffle reduction
+            const int n = L.N;
+            int P = 1;
+            while (P < 64 && 2 * P * n <= (int)blockDim.x) P *= 2;
+            const int row = i / P, seg = i % P;
+            T ar = 0, ai = 0;
+            if (row < n) {
+                const T* rowp = M.inv + 2 * (size_t)n * row;
+                for (int j = seg; j < n; j += P) {
+                    const T a = rowp[2 * j], bb = rowp[2 * j + 1];
                     ar += a * rr[j] - bb * ri[j];
                     ai += a * ri[j] + bb * rr[j];
                 }
-                xr[i] = ar;
-                xi[i] = ai;
+            }
+            for (int o = P / 2; o > 0; o >>= 1) {
+                ar += __shfl_xor(ar, o, 64);
+                ai += __shfl_xor(ai, o, 64);
+            }
+            if (row < n && seg == 0) {
+                xr[row] = ar;
+                xi[row] = ai;
             }
             __syncthreads();
         } else {
