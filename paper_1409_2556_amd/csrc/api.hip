@@ -33,7 +33,10 @@ using namespace lt;
 
 namespace lt {
 
-int prof_begin(lt_handle* h, int family, unsigned long long** counter) {
+// Events for one profiled launch: the launcher passes them to hipExtLaunchKernel,
+// which records them at the start and end of that kernel's execution (no launch
+// gap inside the interval).
+int prof_begin(lt_handle* h, int family, unsigned long long** counter, hipEvent_t* ev0, hipEvent_t* ev1) {
     (void)family;
     if (h->prof_used + 2 > (int)h->prof_events.size()) {
         for (int k = 0; k < 256; ++k) {
@@ -42,14 +45,14 @@ int prof_begin(lt_handle* h, int family, unsigned long long** counter) {
             h->prof_events.push_back(e);
         }
     }
-    LT_HIP(hipEventRecord(h->prof_events[h->prof_used], h->stream));
+    *ev0 = h->prof_events[h->prof_used];
+    *ev1 = h->prof_events[h->prof_used + 1];
     *counter = h->prof_counter;
     return 0;
 }
 
 int prof_end(lt_handle* h, int family) {
     (void)family;
-    LT_HIP(hipEventRecord(h->prof_events[h->prof_used + 1], h->stream));
     h->prof_used += 2;
     return 0;
 }

@@ -111,7 +111,7 @@ struct lt_handle {
 namespace lt {
 
 // profiling helpers (api.hip)
-int prof_begin(lt_handle* h, int family, unsigned long long** counter);
+int prof_begin(lt_handle* h, int family, unsigned long long** counter, hipEvent_t* ev0, hipEvent_t* ev1);
 int prof_end(lt_handle* h, int family);
 
 // workspace helper

@@ -563,9 +563,10 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
         if (fused2d) {
             unsigned long long* pc = nullptr;
             const bool prof = l == 0 && h->prof_target == LT_PROF_PRE_FINE;
-            if (prof) LT_TRY(prof_begin(h, LT_PROF_PRE_FINE, &pc));
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (prof) LT_TRY(prof_begin(h, LT_PROF_PRE_FINE, &pc, &e0, &e1));
             LT_TRY(launch_pre2d<T>(st, v, tr, ti, nu1, tile_of(l), bs[l], xpre[l], C.n[0], C.n[1], C.coarsened_from_fine[0],
-                                   C.coarsened_from_fine[1], bs[l + 1], R, active, pc));
+                                   C.coarsened_from_fine[1], bs[l + 1], R, active, pc, e0, e1));
             if (prof) LT_TRY(prof_end(h, LT_PROF_PRE_FINE));
         } else {
             const size_t per = 2 * (size_t)L.N;
@@ -630,18 +631,19 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
             T4 gh = {(double)g(0), (double)g(1), (double)g(2), (double)g(3)};
             unsigned long long* pc = nullptr;
             const bool prof = l == 0 && h->prof_target == LT_PROF_POST_FINE;
-            if (prof) LT_TRY(prof_begin(h, LT_PROF_POST_FINE, &pc));
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (prof) LT_TRY(prof_begin(h, LT_PROF_POST_FINE, &pc, &e0, &e1));
             if (l == 0 && refine) {
                 LT_TRY(launch_post2d_refine<T>(st, v, h->levels[0].v64(), tr, ti, tau.real(), tau.imag(), nu2,
                                                tile_of(0), bs[0],
                                                xpre[0], xpost[1], C.n[0], C.n[1], C.coarsened_from_fine[0],
                                                C.coarsened_from_fine[1], gh, refine->u, refine->ustride, refine->jcol,
                                                refine->rho_in, refine->rho_out, static_cast<T*>(refine->lo),
-                                               refine->part, R, active, pc, refine->nparts));
+                                               refine->part, R, active, pc, refine->nparts, e0, e1));
             } else {
                 LT_TRY(launch_post2d<T>(st, v, tr, ti, nu2, tile_of(l), bs[l], xpre[l], xpost[l + 1], C.n[0], C.n[1],
                                         C.coarsened_from_fine[0], C.coarsened_from_fine[1], gh, xpost[l], R, active,
-                                        pc));
+                                        pc, e0, e1));
             }
             if (prof) LT_TRY(prof_end(h, LT_PROF_POST_FINE));
         } else {

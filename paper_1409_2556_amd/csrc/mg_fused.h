@@ -38,18 +38,21 @@ template <typename T> struct CBMeta {
 int tile_shape(int id, int* tx, int* ty);
 template <typename T>
 int launch_pre2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, int tile, const T* b, T* x, int cnx,
-                 int cny, int cox, int coy, T* bc, int R, const int* active, unsigned long long* prof);
+                 int cny, int cox, int coy, T* bc, int R, const int* active, unsigned long long* prof,
+                 hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename T>
 int launch_post2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, int tile, const T* b, const T* xin,
                   const T* ec, int cnx, int cny, int cox, int coy, T4 ghost, T* xout, int R, const int* active,
-                  unsigned long long* prof);
-// *nparts = number of per-tile partial sums per right-hand side written to part
+                  unsigned long long* prof, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// *nparts = number of per-tile partial sums per right-hand side written to part.
+// ev0/ev1 (optional): events recorded at the start and end of this launch.
 template <typename T>
 int launch_post2d_refine(hipStream_t st, const LevelView<T>& L, const LevelView<double>& L64, T tr, T ti,
                          double tr64, double ti64, int nu, int tile, const T* b, const T* xin, const T* ec, int cnx,
                          int cny, int cox, int coy, T4 ghost, double* u, size_t ustride, const int* jcol,
                          const double* rho_in, double* rho_out, T* lo, double* part, int R, const int* active,
-                         unsigned long long* prof, int* nparts);
+                         unsigned long long* prof, int* nparts, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);
 template <typename T>
 int launch_coarse_block(hipStream_t st, const CBMeta<T>& M, T tr, T ti, const T* bin, T* xout, int R,
                         const int* active);

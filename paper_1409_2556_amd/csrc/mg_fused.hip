@@ -16,6 +16,8 @@
 // V-cycle in LDS, including the dense solve on the coarsest level.
 #include "mg_fused.h"
 
+#include <hip/hip_ext.h>
+
 namespace lt {
 
 template <typename T> struct cx {
@@ -350,12 +352,11 @@ __global__ __launch_bounds__(256) void k_post2d_refine(LevelView<T> L, LevelView
                       &pnx);
     tile_load<T, H, TX, TY, true>(s, L, tr, ti, b + 2 * N * r, b + 2 * N * r + N, xin + 2 * N * r, xin + 2 * N * r + N,
                           gx0, gy0, &s.xr[0][0], &s.xi[0][0], px0, py0, pnx, cnx, cny, cox, coy, ghost);
-    __syncthreads();
-    tile_sweeps<T, H, TX, TY>(s, gx0, gy0, L.nx, L.ny, 2 * NU, 1);
+    // the FP64 operands of the update do not depend on the sweeps: load them first so
+    // their latency overlaps the LDS work
     double* ur = u + ustride * r + (jcol ? 2 * N * (size_t)*jcol : 0);
     const double* rin = rho_in + 2 * N * r;
     double* rout = rho_out + 2 * N * r;
-    // FP64 update of the interior: all global loads of a thread's cells first
     constexpr int NI = (TX * TY + kThreads - 1) / kThreads;
     double vte[NI], vtw[NI], vtn[NI], vts[NI], vd[NI], vm[NI], vur[NI], vui[NI], vrr[NI], vri[NI];
 #pragma unroll
@@ -374,6 +375,8 @@ __global__ __launch_bounds__(256) void k_post2d_refine(LevelView<T> L, LevelView
         vrr[k] = rin[i];
         vri[k] = rin[i + N];
     }
+    __syncthreads();
+    tile_sweeps<T, H, TX, TY>(s, gx0, gy0, L.nx, L.ny, 2 * NU, 1);
     double acc = 0;
 #pragma unroll
     for (int k = 0; k < NI; ++k) {
@@ -662,6 +665,16 @@ int tile_shape(int id, int* tx, int* ty) {
     return 0;
 }
 
+// Launch a kernel; with profiling events, through hipExtLaunchKernel so that the
+// events bracket exactly this kernel's execution.
+#define LT_LAUNCH(KERNEL, GRID, EV0, EV1, ...)                                              \
+    do {                                                                                    \
+        if (EV0)                                                                            \
+            hipExtLaunchKernelGGL(KERNEL, GRID, dim3(kThreads), 0, st, EV0, EV1, 0, __VA_ARGS__); \
+        else                                                                                \
+            KERNEL<<<GRID, kThreads, 0, st>>>(__VA_ARGS__);                                 \
+    } while (0)
+
 // expands F(TX, TY) for the tile id, F(NU) for the sweep count
 #define LT_TILE_SWITCH(id, F)                                                    \
     switch (id) {                                                                \
@@ -674,14 +687,15 @@ int tile_shape(int id, int* tx, int* ty) {
 
 template <typename T>
 int launch_pre2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, int tile, const T* b, T* x, int cnx,
-                 int cny, int cox, int coy, T* bc, int R, const int* active, unsigned long long* prof) {
+                 int cny, int cox, int coy, T* bc, int R, const int* active, unsigned long long* prof,
+                 hipEvent_t ev0, hipEvent_t ev1) {
     if (nu < 1 || nu > 3) {
         set_last_error("fused smoother supports 1..3 sweeps");
         return LT_EUNSUPPORTED;
     }
-#define LT_K(NU, X, Y) \
-    k_pre2d<T, NU, X, Y><<<dim3((L.nx + X - 1) / X, (L.ny + Y - 1) / Y, R), kThreads, 0, st>>>( \
-        L, tr, ti, b, x, cnx, cny, cox, coy, bc, active, prof, R)
+#define LT_K(NU, X, Y)                                                                                \
+    LT_LAUNCH((k_pre2d<T, NU, X, Y>), dim3((L.nx + X - 1) / X, (L.ny + Y - 1) / Y, R), ev0, ev1, L, tr, ti, b, \
+              x, cnx, cny, cox, coy, bc, active, prof, R)
 #define LT_T(X, Y) \
     if (nu == 1) LT_K(1, X, Y); else if (nu == 2) LT_K(2, X, Y); else LT_K(3, X, Y)
     LT_TILE_SWITCH(tile, LT_T)
@@ -694,14 +708,14 @@ int launch_pre2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, int 
 template <typename T>
 int launch_post2d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, int tile, const T* b, const T* xin,
                   const T* ec, int cnx, int cny, int cox, int coy, T4 ghost, T* xout, int R, const int* active,
-                  unsigned long long* prof) {
+                  unsigned long long* prof, hipEvent_t ev0, hipEvent_t ev1) {
     if (nu < 1 || nu > 3) {
         set_last_error("fused smoother supports 1..3 sweeps");
         return LT_EUNSUPPORTED;
     }
-#define LT_K(NU, X, Y) \
-    k_post2d<T, NU, X, Y><<<dim3((L.nx + X - 1) / X, (L.ny + Y - 1) / Y, R), kThreads, 0, st>>>( \
-        L, tr, ti, b, xin, ec, cnx, cny, cox, coy, ghost, xout, active, prof, R)
+#define LT_K(NU, X, Y)                                                                                 \
+    LT_LAUNCH((k_post2d<T, NU, X, Y>), dim3((L.nx + X - 1) / X, (L.ny + Y - 1) / Y, R), ev0, ev1, L, tr, ti, b, \
+              xin, ec, cnx, cny, cox, coy, ghost, xout, active, prof, R)
 #define LT_T(X, Y) \
     if (nu == 1) LT_K(1, X, Y); else if (nu == 2) LT_K(2, X, Y); else LT_K(3, X, Y)
     LT_TILE_SWITCH(tile, LT_T)
@@ -716,15 +730,15 @@ int launch_post2d_refine(hipStream_t st, const LevelView<T>& L, const LevelView<
                          double tr64, double ti64, int nu, int tile, const T* b, const T* xin, const T* ec, int cnx,
                          int cny, int cox, int coy, T4 ghost, double* u, size_t ustride, const int* jcol,
                          const double* rho_in, double* rho_out, T* lo, double* part, int R, const int* active,
-                         unsigned long long* prof, int* nparts) {
+                         unsigned long long* prof, int* nparts, hipEvent_t ev0, hipEvent_t ev1) {
     if (nu < 1 || nu > 3) {
         set_last_error("fused smoother supports 1..3 sweeps");
         return LT_EUNSUPPORTED;
     }
 #define LT_K(NU, X, Y)                                                                                        \
-    k_post2d_refine<T, NU, X, Y><<<dim3((L.nx + X - 1) / X, (L.ny + Y - 1) / Y, R), kThreads, 0, st>>>(       \
-        L, L64, tr, ti, tr64, ti64, b, xin, ec, cnx, cny, cox, coy, ghost, u, ustride, jcol, rho_in, rho_out, lo, \
-        part, active, prof, R)
+    LT_LAUNCH((k_post2d_refine<T, NU, X, Y>), dim3((L.nx + X - 1) / X, (L.ny + Y - 1) / Y, R), ev0, ev1, L, L64, \
+              tr, ti, tr64, ti64, b, xin, ec, cnx, cny, cox, coy, ghost, u, ustride, jcol, rho_in, rho_out, lo,   \
+              part, active, prof, R)
 #define LT_T(X, Y)                                                          \
     *nparts = ((L.nx + X - 1) / X) * ((L.ny + Y - 1) / Y);                 \
     if (nu == 1) LT_K(1, X, Y); else if (nu == 2) LT_K(2, X, Y); else LT_K(3, X, Y)
@@ -756,24 +770,27 @@ int launch_coarse_block(hipStream_t st, const CBMeta<T>& M, T tr, T ti, const T*
 }
 
 template int launch_pre2d<float>(hipStream_t, const LevelView<float>&, float, float, int, int, const float*, float*,
-                                 int, int, int, int, float*, int, const int*, unsigned long long*);
+                                 int, int, int, int, float*, int, const int*, unsigned long long*, hipEvent_t,
+                                 hipEvent_t);
 template int launch_pre2d<double>(hipStream_t, const LevelView<double>&, double, double, int, int, const double*,
-                                  double*, int, int, int, int, double*, int, const int*, unsigned long long*);
+                                  double*, int, int, int, int, double*, int, const int*, unsigned long long*,
+                                  hipEvent_t, hipEvent_t);
 template int launch_post2d<float>(hipStream_t, const LevelView<float>&, float, float, int, int, const float*,
                                   const float*, const float*, int, int, int, int, T4, float*, int, const int*,
-                                  unsigned long long*);
+                                  unsigned long long*, hipEvent_t, hipEvent_t);
 template int launch_post2d<double>(hipStream_t, const LevelView<double>&, double, double, int, int, const double*,
                                    const double*, const double*, int, int, int, int, T4, double*, int, const int*,
-                                   unsigned long long*);
+                                   unsigned long long*, hipEvent_t, hipEvent_t);
 template int launch_post2d_refine<float>(hipStream_t, const LevelView<float>&, const LevelView<double>&, float, float,
                                          double, double, int, int, const float*, const float*, const float*, int,
                                          int, int, int, T4, double*, size_t, const int*, const double*, double*,
-                                         float*, double*, int, const int*, unsigned long long*, int*);
+                                         float*, double*, int, const int*, unsigned long long*, int*, hipEvent_t,
+                                         hipEvent_t);
 template int launch_post2d_refine<double>(hipStream_t, const LevelView<double>&, const LevelView<double>&, double,
                                           double, double, double, int, int, const double*, const double*,
                                           const double*, int, int, int, int, T4, double*, size_t, const int*,
                                           const double*, double*, double*, double*, int, const int*,
-                                          unsigned long long*, int*);
+                                          unsigned long long*, int*, hipEvent_t, hipEvent_t);
 template int launch_coarse_block<float>(hipStream_t, const CBMeta<float>&, float, float, const float*, float*, int,
                                         const int*);
 template int launch_coarse_block<double>(hipStream_t, const CBMeta<double>&, double, double, const double*, double*,

@@ -89,20 +89,23 @@ int tune(lt_handle* h, int nu1, int nu2, int R, int* tiles_out, int n_out, doubl
     float best_ms = 0;
     int result = 0;
     const int reps = 10;
+    // three interleaved rounds over the shapes, keeping each shape's fastest round, so
+    // that a transient slowdown does not decide the choice
     for (int l = 0; l < nf && result == 0; ++l) {
-        int best = h->tiles[p][l];
-        float bms = 1e30f;
-        for (int t = 0; t < kNumTiles && result == 0; ++t) {
-            h->tiles[p][l] = t;
-            float ms = 0;
-            result = time_steps<T>(h, tau, nu1, nu2, R, e, b, &ra, ev0, ev1, reps, &ms);
-            if (result == 0 && ms < bms) {
-                bms = ms;
-                best = t;
+        float tms[kNumTiles];
+        for (int t = 0; t < kNumTiles; ++t) tms[t] = 1e30f;
+        for (int round = 0; round < 3 && result == 0; ++round)
+            for (int t = 0; t < kNumTiles && result == 0; ++t) {
+                h->tiles[p][l] = t;
+                float ms = 0;
+                result = time_steps<T>(h, tau, nu1, nu2, R, e, b, &ra, ev0, ev1, reps, &ms);
+                if (result == 0) tms[t] = std::min(tms[t], ms);
             }
-        }
+        int best = 0;
+        for (int t = 1; t < kNumTiles; ++t)
+            if (tms[t] < tms[best]) best = t;
         h->tiles[p][l] = best;
-        best_ms = bms;
+        best_ms = tms[best];
     }
     if (result == 0 && nf == 0) {
         float ms = 0;
