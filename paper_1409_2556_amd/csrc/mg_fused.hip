@@ -265,15 +265,12 @@ __global__ __launch_bounds__(256) void k_pre2d(LevelView<T> L, T tr, T ti, const
         bc[2 * Nc * r + I] = ar;
         bc[2 * Nc * r + Nc + I] = ai;
     }
-    if (prof && threadIdx.x == 0) {
-        // algorithmic bytes of this block: b in, x out (complex), the coefficient
-        // arrays Tx, Ty, D, m shared by the Rtot right-hand sides, coarse rhs out
-        const int nxi = min(TX, L.nx - blockIdx.x * TX), nyi = min(TY, L.ny - blockIdx.y * TY);
-        const int ncx = min(ctx, cnx - (int)blockIdx.x * ctx), ncy = min(cty, cny - (int)blockIdx.y * cty);
+    if (prof && threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0) {
+        // algorithmic bytes of this right-hand side over the level (one count per
+        // right-hand side and launch): b in, x out (complex), the coefficient arrays
+        // Tx, Ty, D, m shared by the Rtot right-hand sides, coarse rhs out
         const double cell = 4.0 * sizeof(T) + 4.0 * sizeof(T) / Rtot;
-        const unsigned long long bytes =
-            (unsigned long long)(nxi * nyi * cell + (double)ncx * ncy * 2.0 * sizeof(T));
-        atomicAdd(prof, bytes);
+        atomicAdd(prof, (unsigned long long)((double)L.N * cell + (double)Nc * 2.0 * sizeof(T)));
     }
 }
 
@@ -310,13 +307,11 @@ __global__ __launch_bounds__(256) void k_post2d(LevelView<T> L, T tr, T ti, cons
             oxi[i] = s.xi[ly][lx];
         }
     }
-    if (prof && threadIdx.x == 0) {
-        // algorithmic bytes: x in, b in, x out (complex), shared coefficients, and the
-        // coarse correction (one coarse cell per aggregate of the fine cells)
-        const int nxi = min(TX, L.nx - blockIdx.x * TX), nyi = min(TY, L.ny - blockIdx.y * TY);
-        const double agg = (double)(1 << (cox + coy));
-        const double cell = 6.0 * sizeof(T) + 4.0 * sizeof(T) / Rtot + 2.0 * sizeof(T) / agg;
-        atomicAdd(prof, (unsigned long long)(nxi * nyi * cell));
+    if (prof && threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0) {
+        // algorithmic bytes of this right-hand side over the level: x in, b in, x out
+        // (complex), shared coefficients, and the coarse correction in
+        const double cell = 6.0 * sizeof(T) + 4.0 * sizeof(T) / Rtot;
+        atomicAdd(prof, (unsigned long long)((double)L.N * cell + (double)Nc * 2.0 * sizeof(T)));
     }
 }
 
@@ -413,14 +408,13 @@ __global__ __launch_bounds__(256) void k_post2d_refine(LevelView<T> L, LevelView
     if (threadIdx.x == 0) {
         part[(size_t)r * gridDim.x * gridDim.y + blockIdx.x + (size_t)gridDim.x * blockIdx.y] =
             red[0] + red[1] + red[2] + red[3];
-        if (prof) {
-            const int nxi = min(TX, L.nx - blockIdx.x * TX), nyi = min(TY, L.ny - blockIdx.y * TY);
-            const double agg = (double)(1 << (cox + coy));
-            // x in, b in (T complex), shared T coefficients, coarse correction in,
-            // u in/out and rho in/out (FP64 complex), lo out (T complex), FP64 coefficients (shared)
-            const double cell = 4.0 * sizeof(T) + 4.0 * sizeof(T) / Rtot + 2.0 * sizeof(T) / agg + 64.0 +
-                                (lo ? 2.0 * sizeof(T) : 0.0) + 32.0 / Rtot;
-            atomicAdd(prof, (unsigned long long)(nxi * nyi * cell));
+        if (prof && blockIdx.x == 0 && blockIdx.y == 0) {
+            // algorithmic bytes of this right-hand side over the level: x in, b in
+            // (T complex), shared T coefficients, coarse correction in, u in/out and rho
+            // in/out (FP64 complex), lo out (T complex), FP64 coefficients (shared)
+            const double cell = 4.0 * sizeof(T) + 4.0 * sizeof(T) / Rtot + 64.0 + (lo ? 2.0 * sizeof(T) : 0.0) +
+                                32.0 / Rtot;
+            atomicAdd(prof, (unsigned long long)((double)L.N * cell + (double)Nc * 2.0 * sizeof(T)));
         }
     }
 }
