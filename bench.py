@@ -215,9 +215,13 @@ def main():
         avg_s = pr["ms"] * 1e-3 / pr["launches"]
         bytes_per_launch = pr["bytes"] / pr["launches"]
         achieved = bytes_per_launch / avg_s / 1e9
+        t0 = (tiles.get(prof_name) or {}).get("tiles") or [[32, 16]]
+        tx, ty = t0[0]
+        # the committed counter run used the 32x16 fine-level tile
+        traffic = _measured_traffic() if (tx, ty) == (32, 16) else None
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": _measured_traffic(),
-                    "kernel": "k_post2d_refine<float,2> (fine-grid prolongation, 2 red-black sweeps, "
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                    "kernel": f"k_post2d_refine<float,2,{tx},{ty}> (fine-grid prolongation, 2 red-black sweeps, "
                               "FP64 refinement update)",
                     "avg_launch_us": avg_s * 1e6, "bytes_per_launch": bytes_per_launch,
                     "launches": pr["launches"]}
