@@ -97,49 +97,64 @@ __global__ __launch_bounds__(256) void k_conv3(const unsigned short* __restrict_
     }
 }
 
-// dW[tap][co][ci] += sum_p dZ[p][co] X[p + off(tap)][ci]  (split-K over pixel chunks, FP32 atomics)
+// dW[tap][co][ci] += sum_p dZ[p][co] X[p + off(tap)][ci] and db[co] += sum_p dZ[p][co]
+// (split-K over pixel chunks along blockIdx.x, FP32 atomics).  Every wave takes one
+// (tap, ci-tile) combination (blockIdx.y selects a group of four) and all co-tiles; the
+// wave of combination 0 also forms the bias gradient as a product with a ones operand.
 template <int NT>
 __global__ __launch_bounds__(256) void k_wgrad3(const unsigned short* __restrict__ X, const unsigned short* __restrict__ dZ,
-                                                int B, int H, int W, int cin, int chunk, float* __restrict__ dW) {
+                                                int B, int H, int W, int cin, int chunk, float* __restrict__ dW,
+                                                float* __restrict__ db) {
     constexpr int cout = 16 * NT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long P = (long long)B * H * W;
     const long long pb = (long long)blockIdx.x * chunk;
     const long long pe = pb + chunk < P ? pb + chunk : P;
     const int nci = cin / 16;
-    const int ncombo = 9 * nci;  // (tap, ci-tile); every wave does all co-tiles of its combos
-    for (int cb = wave; cb < ncombo; cb += 4) {
+    const int ncombo = 9 * nci;
+    const int cb = blockIdx.y * 4 + wave;
+    if (cb < ncombo) {
         const int tap = cb / nci, ct = cb % nci;
+        const bool bias = db != nullptr && cb == 0;
+        const v4s ones = (v4s){(short)0x3f80, (short)0x3f80, (short)0x3f80, (short)0x3f80};  // bf16 1.0
+        v4f accb[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) accb[t] = (v4f){0, 0, 0, 0};
         const int dy = tap / 3 - 1, dx = tap % 3 - 1;
         v4f acc[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = (v4f){0, 0, 0, 0};
-        for (long long q0 = pb; q0 < pe; q0 += 16) {
+        // W is a multiple of 16 and so are pb and pe: a group of 16 pixels lies in one row,
+        // whose coordinates are found once per group (32-bit: P < 2^31)
+        for (int q0 = (int)pb; q0 < (int)pe; q0 += 16) {
+            const int row = q0 / W;  // b * H + h
+            const int w0 = q0 - row * W;
+            const int hh = row % H + dy;
+            const bool rowok = hh >= 0 && hh < H;
+            const unsigned short* xrow = X + (long long)(row + dy) * W * cin + 16 * ct + (lane & 15);
             // B operand: X at pixels q0 + 4 (lane/16) + i shifted by the tap, channel ci = 16 ct + lane%16
             v4s bx;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const long long p = q0 + 4 * (lane >> 4) + i;
-                unsigned short v = 0;
-                if (p < pe) {
-                    const int w = (int)(p % W);
-                    const long long r = p / W;
-                    const int hh = (int)(r % H) + dy, ww = w + dx;
-                    if (hh >= 0 && hh < H && ww >= 0 && ww < W)
-                        v = X[((r + dy) * W + ww) * (long long)cin + 16 * ct + (lane & 15)];
-                }
-                bx[i] = (short)v;
+                const int ww = w0 + 4 * (lane >> 4) + i + dx;
+                bx[i] = (short)((rowok && ww >= 0 && ww < W) ? xrow[(long long)ww * cin] : (unsigned short)0);
             }
+            const unsigned short* zp = dZ + (long long)(q0 + 4 * (lane >> 4)) * cout + (lane & 15);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 v4s az;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const long long p = q0 + 4 * (lane >> 4) + i;
-                    az[i] = (short)(p < pe ? dZ[p * cout + 16 * t + (lane & 15)] : (unsigned short)0);
-                }
+                for (int i = 0; i < 4; ++i) az[i] = (short)zp[i * cout + 16 * t];
                 acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(az, bx, acc[t], 0, 0, 0);
+                if (bias) accb[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(az, ones, accb[t], 0, 0, 0);
             }
+        }
+        // every column of accb holds the row sums: column 0 gives db
+        if (bias && (lane & 15) == 0) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) atomicAdd(&db[16 * t + 4 * (lane >> 4) + i], accb[t][i]);
         }
         // lane: column ci = 16 ct + lane%16, rows co = 16 t + 4 (lane/16) + i
 #pragma unroll
@@ -150,17 +165,6 @@ __global__ __launch_bounds__(256) void k_wgrad3(const unsigned short* __restrict
                 atomicAdd(&dW[((size_t)tap * cout + co) * cin + 16 * ct + (lane & 15)], acc[t][i]);
             }
     }
-}
-
-// db[c] += sum_p dZ[p][c]
-__global__ void k_bgrad(const unsigned short* __restrict__ dZ, long long P, int C, float* __restrict__ db) {
-    const int c = threadIdx.x % C;
-    const int lanes_per = blockDim.x / C;
-    const int sub = threadIdx.x / C;
-    float s = 0;
-    for (long long p = (long long)blockIdx.x * lanes_per + sub; p < P; p += (long long)gridDim.x * lanes_per)
-        s += bf2f(dZ[p * C + c]);
-    atomicAdd(&db[c], s);
 }
 
 // dZ = bf16(dY * (Y > 0))  (ReLU backward; Y is the post-activation output)
@@ -518,14 +522,19 @@ static int conv3(hipStream_t st, const unsigned short* X, const unsigned short* 
 }
 
 static int wgrad3(hipStream_t st, const unsigned short* X, const unsigned short* dZ, int B, int H, int W, int cin,
-                  int cout, float* dW) {
+                  int cout, float* dW, float* db) {
     const long long P = (long long)B * H * W;
-    const int chunk = 512;
-    const unsigned grid = (unsigned)((P + chunk - 1) / chunk);
+    if (W % 16 || P >= (1LL << 31)) {
+        set_last_error("unet: weight gradient needs a width that is a multiple of 16 and < 2^31 pixels");
+        return LT_EUNSUPPORTED;
+    }
+    // pixel chunks (multiples of 16) sized so the grid has a few hundred workgroups
+    const int chunk = P >= 65536 ? 512 : 256;
+    const dim3 grid((unsigned)((P + chunk - 1) / chunk), (unsigned)((9 * (cin / 16) + 3) / 4));
     switch (cout / 16) {
-        case 1: k_wgrad3<1><<<grid, 256, 0, st>>>(X, dZ, B, H, W, cin, chunk, dW); break;
-        case 2: k_wgrad3<2><<<grid, 256, 0, st>>>(X, dZ, B, H, W, cin, chunk, dW); break;
-        case 4: k_wgrad3<4><<<grid, 256, 0, st>>>(X, dZ, B, H, W, cin, chunk, dW); break;
+        case 1: k_wgrad3<1><<<grid, 256, 0, st>>>(X, dZ, B, H, W, cin, chunk, dW, db); break;
+        case 2: k_wgrad3<2><<<grid, 256, 0, st>>>(X, dZ, B, H, W, cin, chunk, dW, db); break;
+        case 4: k_wgrad3<4><<<grid, 256, 0, st>>>(X, dZ, B, H, W, cin, chunk, dW, db); break;
         default: set_last_error("unet: unsupported channel count"); return LT_EUNSUPPORTED;
     }
     LT_HIP(hipGetLastError());
@@ -652,8 +661,7 @@ int unet_backward(UNet* u, hipStream_t st, int B, int H, int W, float* dIn) {
         const int h = H >> L[l], w = W >> L[l];
         const int ci = kCin[l], co = kCout[l];
         k_relu_back<<<nb(P * co), 256, 0, st>>>(dy, a.y[l], P * co, dZ);
-        k_bgrad<<<256, 256, 0, st>>>(dZ, P, co, g + u->layers[l].b_off);
-        LT_TRY(wgrad3(st, lin[l], dZ, B, h, w, ci, co, g + u->layers[l].w_off));
+        LT_TRY(wgrad3(st, lin[l], dZ, B, h, w, ci, co, g + u->layers[l].w_off, g + u->layers[l].b_off));
         if (dx) LT_TRY(conv3(st, dZ, wb(l), nullptr, B, h, w, co, ci, 0, mode_dx, nullptr, dx));
         return 0;
     };
