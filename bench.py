@@ -68,9 +68,9 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-times", type=int, default=4)
     ap.add_argument("--no-tune", action="store_true", help="keep the default smoother tile shapes")
-    ap.add_argument("--workload", choices=["C2", "C5"], default="C2",
-                    help="C2: the 256x256 workload (default); C5: the batch of six uneven 2D/3D grids "
-                         "solved in one lt_solve_batch call")
+    ap.add_argument("--workload", choices=["C2", "C3", "C5"], default="C2",
+                    help="C2: the 256x256 workload (default); C3: sensitivities (lt_adjoint) of the "
+                         "64x64x32 workload; C5: the batch of six uneven 2D/3D grids in one lt_solve_batch call")
     return ap.parse_args()
 
 
@@ -146,6 +146,8 @@ def main():
         sys.exit(2)
     if args.workload == "C5":
         return main_batch(args)
+    if args.workload == "C3":
+        return main_adjoint(args)
     import workloads as wl
     p = wl.make_problem(WORKLOAD)
     # the CPU oracle runs first, before this process touches the GPU
@@ -261,6 +263,101 @@ def main():
     if net is not None:
         lt.lt_unet_attach(h, None)
         net.close()
+    h.close()
+
+
+def main_adjoint(args):
+    """Sensitivities of the 64x64x32 workload: 25 sources and 48 receivers give 73 right-hand
+    sides x 24 shifts = 1,752 shifted solves per lt_adjoint call, contracted to d phi / d ln kappa
+    and d phi / d ln S of every cell for 25 x 48 x 2 (source, receiver, time) triples."""
+    import workloads as wl
+    p = wl.make_problem("C3")
+    nrhs = len(p.sources) + len(p.receivers)
+    pairs = nrhs * len(p.times) * (p.nz_contour // 2)
+    cpu, ref = None, None
+    if not args.no_cpu_baseline:
+        # the oracle as it stands: the shifts of the first time (one factorisation each, all 73
+        # right-hand sides), in parallel; their heads also check the GPU setup at full size
+        from oracle.heads import heads
+        workers = min(os.cpu_count() or 1, 16)
+        t0 = time.perf_counter()
+        ref = heads(p.n, p.h, p.kappa, p.S, p.sources, p.receivers, p.times[:1], p.nz_contour, q=p.q, bc=p.bc,
+                    workers=workers, ndim=p.ndim)
+        dt = time.perf_counter() - t0
+        nshift = p.nz_contour // 2
+        cpu = {"value": nrhs * nshift / dt, "unit": "shifted solves/s", "cores": workers, "kind": "oracle",
+               "sample": f"64x64x32 workload, first time: {nshift} shifts x {nrhs} right-hand sides "
+                         f"(sources and receivers) = {nrhs * nshift} pairs, SuperLU per shift, "
+                         f"{min(workers, nshift)} processes ({dt:.1f} s); no contraction"}
+        print(f"[bench] oracle sample: {cpu['value']:.2f} solves/s ({dt:.1f} s)", file=sys.stderr, flush=True)
+    import torch
+    from paper_1409_2556_amd import binding as lt
+    torch.cuda.set_device(0)
+    h, tiles = _handle(lt, p, False, nrhs)
+    res = {}
+    for name, prec, tol in (("fp64", lt.LT_PREC_FP64, 1e-10), ("mixed", lt.LT_PREC_MIXED, 1e-9)):
+        o = lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau, maxit=64, relax=1.0)
+        out = None
+        for _ in range(args.warmup):
+            out = lt.lt_adjoint(h, p.sources, p.q, p.receivers, p.times, p.nz_contour, o)
+            del out
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = lt.lt_adjoint(h, p.sources, p.q, p.receivers, p.times, p.nz_contour, o)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        dK, dS, st = out
+        res[name] = {"dt": dt, "tol": tol, "st": st, "dK": dK, "dS": dS}
+        print(f"[bench] C3 adjoint {name}: {dt * 1e3:.1f} ms/step, {pairs / dt:.0f} solves/s, iters "
+              f"{st['iters_max']}, true residual {st['true_relres_max']:.2e}", file=sys.stderr, flush=True)
+    # mixed against FP64 sensitivities.  d/d ln kappa: per (source, receiver, time) field.  d/d ln S:
+    # relative to the largest storage field of the same (source, receiver) over the times; near
+    # steady state (the later time) the storage sensitivity is a vanishing difference of contour
+    # terms of the earlier size, resolved to the tolerance of that scale, not of its own norm
+    def rel(a, b, over_times=False):
+        d = torch.linalg.vector_norm(a - b, dim=-1)
+        n = torch.linalg.vector_norm(b, dim=-1)
+        if over_times:
+            n = n.max(dim=-1, keepdim=True).values
+        return float((d / n).max())
+    agree = {"dlnK": rel(res["mixed"]["dK"], res["fp64"]["dK"]),
+             "dlnS_vs_scale_over_times": rel(res["mixed"]["dS"], res["fp64"]["dS"], True),
+             "dlnS_per_field": rel(res["mixed"]["dS"], res["fp64"]["dS"])}
+    head_err = None
+    if ref is not None:
+        o = lt.make_opts(tol=1e-9, precision=lt.LT_PREC_FP64, n_tau=p.n_tau, maxit=64)
+        phi, _ = lt.lt_solve(h, p.sources, p.q, p.times[:1], p.nz_contour, p.receivers, o)
+        got = phi.cpu().numpy()
+        e = np.linalg.norm((got - ref).reshape(len(p.sources), -1), axis=1) / \
+            np.linalg.norm(ref.reshape(len(p.sources), -1), axis=1)
+        head_err = float(e.max())
+    print(f"[bench] C3 mixed vs fp64 sensitivities {agree}, FP64 heads vs oracle {head_err}", file=sys.stderr,
+          flush=True)
+    head = res["mixed"]
+    valid = (head["st"]["rc"] == 0 and agree["dlnK"] <= 1e-4 and agree["dlnS_vs_scale_over_times"] <= 1e-3
+             and (head_err is None or head_err <= 1e-6))
+    out = {
+        "metric": "shifted solves/sec (RHS\u00d7shift, rel head err 1e-5): learned+mixed vs plain FGMRES",
+        "value": pairs / head["dt"] if valid else 0.0,
+        "unit": "shifted solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["dt"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": "3D 64x64x32 GRF (var 2, corr 0.2/0.2/0.05), log-uniform S, 25 sources + 48 "
+                               "receivers (adjoint), times {0.3, 1.2}, 24-node Talbot, 3 tau, lt_adjoint "
+                               "(d phi / d ln kappa and d ln S of every cell)",
+                   "rhs": nrhs, "pairs": pairs, "variant": "mixed", "tol": head["tol"],
+                   "iters": head["st"]["iters_max"], "vcycles": head["st"]["vcycles"]},
+        "variants": {n: {"solves_per_s": pairs / r["dt"], "ms_per_step": r["dt"] * 1e3, "tol": r["tol"],
+                         "iters": r["st"]["iters_max"], "vcycles": r["st"]["vcycles"],
+                         "true_relres_weighted_max": r["st"]["true_relres_max"]} for n, r in res.items()},
+        "mixed_vs_fp64_sensitivity_rel_max": agree,
+        "fp64_heads_vs_oracle_first_time": head_err,
+        "vs_plain_fp64": res["fp64"]["dt"] / head["dt"],
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
     h.close()
 
 

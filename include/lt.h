@@ -191,7 +191,11 @@ int lt_solve(lt_handle* h, const lt_points* sources, double q, const double* tim
  * pumping at rate q: forward fields for every source and adjoint fields for
  * every receiver (complex symmetric operator: no conjugation), contracted
  * cell by cell and summed over the contour.  dlnK, dlnS: device float64
- * [ns][nr][ntimes][N]; either may be NULL. */
+ * [ns][nr][ntimes][N]; either may be NULL.  Every shift meets the stricter of
+ * the heads' weighting |w_k qhat_k| and the storage term's |w_k qhat_k z_k|
+ * in the convergence test.  Near steady state the storage sensitivity is a
+ * vanishing sum of contour terms of its early-time size, so its error is set
+ * by tol relative to that size, not to its own norm. */
 int lt_adjoint(lt_handle* h, const lt_points* sources, double q, const lt_points* receivers,
                const double* times, int ntimes, const lt_contour* contour, const lt_opts* opts,
                double* dlnK, double* dlnS, lt_stats* stats);

@@ -797,7 +797,7 @@ int lt_adjoint(lt_handle* h, const lt_points* sources, double q, const lt_points
         return LT_EINVAL;
     }
     Plan plan;
-    LT_TRY(make_plan(times, ntimes, contour->nz, q, &o, &plan));
+    LT_TRY(make_plan(times, ntimes, contour->nz, q, &o, &plan, true));
     // right-hand sides: every source's b, then every receiver's B_m^T (adjoint fields)
     lt_points all;
     std::vector<double> xyz(3 * (size_t)(sources->n + receivers->n));

@@ -133,7 +133,8 @@ struct Plan {
     std::vector<cdouble> tau_sched;     // cyclic preconditioner shifts
 };
 int talbot(int nz, double t, cdouble* z, cdouble* w);
-int make_plan(const double* times, int ntimes, int nz, double q, const lt_opts* o, Plan* p);
+// storage: convergence weights that also cover the storage-sensitivity contraction (lt_adjoint)
+int make_plan(const double* times, int ntimes, int nz, double q, const lt_opts* o, Plan* p, bool storage = false);
 
 // point weights as CSR (host)
 struct PointsCSR {

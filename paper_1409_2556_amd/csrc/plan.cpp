@@ -36,7 +36,7 @@ int talbot(int nz, double t, cdouble* z, cdouble* w) {
     return 0;
 }
 
-int make_plan(const double* times, int ntimes, int nz, double q, const lt_opts* o, Plan* p) {
+int make_plan(const double* times, int ntimes, int nz, double q, const lt_opts* o, Plan* p, bool storage) {
     if (ntimes < 1 || !times) {
         set_last_error("need at least one time");
         return LT_EINVAL;
@@ -50,16 +50,22 @@ int make_plan(const double* times, int ntimes, int nz, double q, const lt_opts* 
     std::vector<cdouble> w(p->nk);
     for (int t = 0; t < ntimes; ++t) {
         LT_TRY(talbot(nz, times[t], &p->z[(size_t)t * p->nk], w.data()));
-        double mx = 0.0;
+        double mx = 0.0, mz = 0.0;
         for (int k = 0; k < p->nk; ++k) {
             cdouble zk = p->z[(size_t)t * p->nk + k];
             cdouble v = w[k] * (q / zk);  // qhat(z) = q / z for a constant rate from t = 0
             p->wq[(size_t)t * p->nk + k] = v;
             mx = std::max(mx, std::abs(v));
+            mz = std::max(mz, std::abs(v * zk));
         }
+        // Heads weigh shift k by |w_k qhat_k|.  The storage sensitivity weighs the same
+        // fields by |w_k qhat_k z_k| (the z dM/dp term of Section 5.2), so for it each
+        // shift must meet the stricter of the two weightings.
         for (int k = 0; k < p->nk; ++k) {
-            double a = std::abs(p->wq[(size_t)t * p->nk + k]);
-            p->omega[(size_t)t * p->nk + k] = mx > 0 ? a / mx : 1.0;
+            const cdouble v = p->wq[(size_t)t * p->nk + k], zk = p->z[(size_t)t * p->nk + k];
+            double a = mx > 0 ? std::abs(v) / mx : 1.0;
+            if (storage && mz > 0) a = std::max(a, std::abs(v * zk) / mz);
+            p->omega[(size_t)t * p->nk + k] = a;
         }
     }
     p->tau_sched.clear();
