@@ -60,20 +60,30 @@ __global__ __launch_bounds__(256) void k_conv3(const unsigned short* __restrict_
     v4f acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = (v4f){0, 0, 0, 0};
-    for (int tap = 0; tap < 9; ++tap) {
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        const int hh = h + dy, ww = pw + dx;
-        const bool in = hh >= 0 && hh < H && ww >= 0 && ww < W;
-        const unsigned short* xp = X + ((rowi + dy) * W + ww) * (long long)cin;
-        const unsigned short* wp = Wt + (size_t)tap * cout * cin;
+    // one stencil row (three taps) at a time: all of its input and weight loads are issued
+    // before the first product (addresses clamped into the image, out-of-image inputs zeroed)
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int hh = h + dy;
+        const bool rin = hh >= 0 && hh < H;
+        const long long rowc = rin ? rowi + dy : rowi;
         for (int c0 = 0; c0 < cin; c0 += 16) {
-            v4s a = (v4s){0, 0, 0, 0};
-            if (in) a = *reinterpret_cast<const v4s*>(xp + c0 + kq);
+            v4s a[3], b[3][NT];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const v4s b = *reinterpret_cast<const v4s*>(wp + (size_t)(16 * t + (lane & 15)) * cin + c0 + kq);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+            for (int j = 0; j < 3; ++j) {
+                const int ww = pw + j - 1;
+                const bool in = rin && ww >= 0 && ww < W;
+                const int wc = min(max(ww, 0), W - 1);
+                const v4s v = *reinterpret_cast<const v4s*>(X + (rowc * W + wc) * (long long)cin + c0 + kq);
+                a[j] = in ? v : (v4s){0, 0, 0, 0};
+                const unsigned short* wp = Wt + (size_t)((dy + 1) * 3 + j) * cout * cin;
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    b[j][t] = *reinterpret_cast<const v4s*>(wp + (size_t)(16 * t + (lane & 15)) * cin + c0 + kq);
             }
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[j], b[j][t], acc[t], 0, 0, 0);
         }
     }
     // lane holds column co = 16 t + lane%16, rows (pixels) 4 (lane/16) + i
