@@ -57,8 +57,12 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--tol-fp64", type=float, default=1e-8)
-    ap.add_argument("--tol-mixed", type=float, default=1e-7)
+    # Both variants stop at the same weighted tolerance: at equal settings the FP64 and mixed
+    # paths take the same outer iterations and give the same head error (the refinement of every
+    # preconditioner solve is FP64 in both), so the comparison is at equal accuracy.  3e-7 with
+    # relax 3 leaves 2.2e-6 against the oracle over all ten times, a 4.6x margin to the 1e-5 bar.
+    ap.add_argument("--tol-fp64", type=float, default=3e-7)
+    ap.add_argument("--tol-mixed", type=float, default=3e-7)
     ap.add_argument("--relax", type=float, default=3.0)
     ap.add_argument("--variant", choices=["all", "mixed", "fp64", "learned"], default="all")
     ap.add_argument("--train-steps", type=int, default=400)
@@ -66,7 +70,7 @@ def _parse():
                     help="after the solves, copy a 512 MiB buffer once (a plain copy kernel of known "
                          "size, to scale hardware byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-times", type=int, default=4)
+    ap.add_argument("--cpu-sample-times", type=int, default=10)
     ap.add_argument("--no-tune", action="store_true", help="keep the default smoother tile shapes")
     ap.add_argument("--workload", choices=["C2", "C3", "C5"], default="C2",
                     help="C2: the 256x256 workload (default); C3: sensitivities (lt_adjoint) of the "
