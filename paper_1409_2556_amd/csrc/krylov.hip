@@ -704,9 +704,10 @@ __global__ void k_true_res_finalize(int R, int nc, int k0, int Ks, int nb, const
 // dm_c/dln S_c = m_c; the time-domain sensitivity is 2 Re sum_k w_k qhat_k (.).
 // One thread per cell, one source and up to kSensM receivers per block.
 constexpr int kSensM = 8;
-__global__ void k_sens(LevelView<double> L, const double* __restrict__ kappa, int ns, int nr, int nk, int t,
-                       int ntimes, const double* __restrict__ X, const double* __restrict__ zs,
-                       const double* __restrict__ wq, double* __restrict__ JK, double* __restrict__ JS) {
+__global__ __launch_bounds__(256) void k_sens(LevelView<double> L, const double* __restrict__ kappa, int ns, int nr,
+                                              int nk, int t, int ntimes, const double* __restrict__ X,
+                                              const double* __restrict__ zs, const double* __restrict__ wq,
+                                              double* __restrict__ JK, double* __restrict__ JS) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= L.N) return;
     const int s = blockIdx.y;
@@ -739,6 +740,7 @@ __global__ void k_sens(LevelView<double> L, const double* __restrict__ kappa, in
     const double wall = L.D[c] - tin;  // walls of this cell; their T is proportional to k_c
     const double mc = L.m[c];
     double aK[kSensM], aS[kSensM];
+#pragma unroll
     for (int q = 0; q < kSensM; ++q) aK[q] = aS[q] = 0.0;
     for (int kk = 0; kk < nk; ++kk) {
         const int k = t * nk + kk;
@@ -747,16 +749,20 @@ __global__ void k_sens(LevelView<double> L, const double* __restrict__ kappa, in
         const double* ph = X + ((size_t)s * nk + kk) * 2 * N;
         const c64 pc = {ph[c], ph[c + N]};
         c64 dph[6];
+#pragma unroll
         for (int f = 0; f < 6; ++f) dph[f] = {pc.re - ph[nb[f]], pc.im - ph[nb[f] + N]};
+        // receivers past nr read the last one (their results are not stored): no branch, so
+        // the loop unrolls and every receiver's loads are in flight together
+#pragma unroll
         for (int q = 0; q < kSensM; ++q) {
-            const int m = m0 + q;
-            if (m >= nr) break;
+            const int m = min(m0 + q, nr - 1);
             const double* ps = X + ((size_t)(ns + m) * nk + kk) * 2 * N;
             const c64 qc = {ps[c], ps[c + N]};
             c64 g = cm(pc, qc);
             const c64 hs = {mc * g.re, mc * g.im};
             g.re *= wall;
             g.im *= wall;
+#pragma unroll
             for (int f = 0; f < 6; ++f) {
                 const c64 dq = {qc.re - ps[nb[f]], qc.im - ps[nb[f] + N]};
                 const c64 p = cm(dph[f], dq);
@@ -767,9 +773,10 @@ __global__ void k_sens(LevelView<double> L, const double* __restrict__ kappa, in
             aS[q] += zw.re * hs.re - zw.im * hs.im;
         }
     }
+#pragma unroll
     for (int q = 0; q < kSensM; ++q) {
         const int m = m0 + q;
-        if (m >= nr) break;
+        if (m >= nr) continue;
         const size_t o = (((size_t)s * nr + m) * ntimes + t) * N + c;
         if (JK) JK[o] = -2.0 * aK[q];
         if (JS) JS[o] = -2.0 * aS[q];
