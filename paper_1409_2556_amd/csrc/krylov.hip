@@ -702,15 +702,19 @@ __global__ void k_true_res_finalize(int R, int nc, int k0, int Ks, int nb, const
 //   d/dp B_m phi = - psi^T (dK/dp + z dM/dp) phi,
 // dT_f/dln k_c = T_f k_j / (k_c + k_j) for the face to neighbour j, dT_wall/dln k_c = T_wall,
 // dm_c/dln S_c = m_c; the time-domain sensitivity is 2 Re sum_k w_k qhat_k (.).
-// One thread per cell, one source and up to kSensM receivers per block.
-constexpr int kSensM = 8;
+// One thread per cell and per block of kSensS sources x kSensM receivers: the
+// stencil of each field is loaded once per block and serves kSensS (or kSensM)
+// pairs.  Indices past ns / nr are clamped (their results are not stored), so
+// the loops unroll and all loads of a shift are in flight together.
+constexpr int kSensS = 1;
+constexpr int kSensM = 2;
 __global__ __launch_bounds__(256) void k_sens(LevelView<double> L, const double* __restrict__ kappa, int ns, int nr,
                                               int nk, int t, int ntimes, const double* __restrict__ X,
                                               const double* __restrict__ zs, const double* __restrict__ wq,
                                               double* __restrict__ JK, double* __restrict__ JS) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= L.N) return;
-    const int s = blockIdx.y;
+    const int s0 = blockIdx.y * kSensS;
     const int m0 = blockIdx.z * kSensM;
     const size_t N = L.N;
     const int x = c % L.nx, y = (c / L.nx) % L.ny, z = c / (L.nx * L.ny);
@@ -722,6 +726,7 @@ __global__ __launch_bounds__(256) void k_sens(LevelView<double> L, const double*
     const int has[6] = {x > 0, x + 1 < L.nx, y > 0, y + 1 < L.ny, z > 0, z + 1 < L.nz};
     const int off[6] = {-1, 1, -sy, sy, -sz, sz};
     double tin = 0.0;
+#pragma unroll
     for (int f = 0; f < 6; ++f) {
         nb[f] = has[f] ? c + off[f] : c;
         double T = 0.0;
@@ -739,53 +744,64 @@ __global__ __launch_bounds__(256) void k_sens(LevelView<double> L, const double*
     }
     const double wall = L.D[c] - tin;  // walls of this cell; their T is proportional to k_c
     const double mc = L.m[c];
-    double aK[kSensM], aS[kSensM];
+    double aK[kSensS][kSensM], aS[kSensS][kSensM];
 #pragma unroll
-    for (int q = 0; q < kSensM; ++q) aK[q] = aS[q] = 0.0;
+    for (int a = 0; a < kSensS; ++a)
+#pragma unroll
+        for (int q = 0; q < kSensM; ++q) aK[a][q] = aS[a][q] = 0.0;
     for (int kk = 0; kk < nk; ++kk) {
         const int k = t * nk + kk;
         const c64 w = {wq[2 * k], wq[2 * k + 1]};
         const c64 zw = cm(w, {zs[2 * k], zs[2 * k + 1]});
-        const double* ph = X + ((size_t)s * nk + kk) * 2 * N;
-        const c64 pc = {ph[c], ph[c + N]};
-        c64 dph[6];
+        c64 pc[kSensS], dph[kSensS][6];
 #pragma unroll
-        for (int f = 0; f < 6; ++f) dph[f] = {pc.re - ph[nb[f]], pc.im - ph[nb[f] + N]};
-        // receivers past nr read the last one (their results are not stored): no branch, so
-        // the loop unrolls and every receiver's loads are in flight together
+        for (int a = 0; a < kSensS; ++a) {
+            const int sa = min(s0 + a, ns - 1);
+            const double* ph = X + ((size_t)sa * nk + kk) * 2 * N;
+            pc[a] = {ph[c], ph[c + N]};
+#pragma unroll
+            for (int f = 0; f < 6; ++f) dph[a][f] = {pc[a].re - ph[nb[f]], pc[a].im - ph[nb[f] + N]};
+        }
 #pragma unroll
         for (int q = 0; q < kSensM; ++q) {
             const int m = min(m0 + q, nr - 1);
             const double* ps = X + ((size_t)(ns + m) * nk + kk) * 2 * N;
             const c64 qc = {ps[c], ps[c + N]};
-            c64 g = cm(pc, qc);
-            const c64 hs = {mc * g.re, mc * g.im};
-            g.re *= wall;
-            g.im *= wall;
+            c64 dq[6];
 #pragma unroll
-            for (int f = 0; f < 6; ++f) {
-                const c64 dq = {qc.re - ps[nb[f]], qc.im - ps[nb[f] + N]};
-                const c64 p = cm(dph[f], dq);
-                g.re += wf[f] * p.re;
-                g.im += wf[f] * p.im;
+            for (int f = 0; f < 6; ++f) dq[f] = {qc.re - ps[nb[f]], qc.im - ps[nb[f] + N]};
+#pragma unroll
+            for (int a = 0; a < kSensS; ++a) {
+                c64 g = cm(pc[a], qc);
+                const c64 hs = {mc * g.re, mc * g.im};
+                g.re *= wall;
+                g.im *= wall;
+#pragma unroll
+                for (int f = 0; f < 6; ++f) {
+                    const c64 p = cm(dph[a][f], dq[f]);
+                    g.re += wf[f] * p.re;
+                    g.im += wf[f] * p.im;
+                }
+                aK[a][q] += w.re * g.re - w.im * g.im;
+                aS[a][q] += zw.re * hs.re - zw.im * hs.im;
             }
-            aK[q] += w.re * g.re - w.im * g.im;
-            aS[q] += zw.re * hs.re - zw.im * hs.im;
         }
     }
 #pragma unroll
-    for (int q = 0; q < kSensM; ++q) {
-        const int m = m0 + q;
-        if (m >= nr) continue;
-        const size_t o = (((size_t)s * nr + m) * ntimes + t) * N + c;
-        if (JK) JK[o] = -2.0 * aK[q];
-        if (JS) JS[o] = -2.0 * aS[q];
-    }
+    for (int a = 0; a < kSensS; ++a)
+#pragma unroll
+        for (int q = 0; q < kSensM; ++q) {
+            const int sa = s0 + a, m = m0 + q;
+            if (sa >= ns || m >= nr) continue;
+            const size_t o = (((size_t)sa * nr + m) * ntimes + t) * N + c;
+            if (JK) JK[o] = -2.0 * aK[a][q];
+            if (JS) JS[o] = -2.0 * aS[a][q];
+        }
 }
 
 int launch_sens(hipStream_t st, LevelView<double> L, const double* kappa, int ns, int nr, int nk, int t, int ntimes,
                 const double* X, const double* zs, const double* wq, double* JK, double* JS) {
-    dim3 grid((unsigned)((L.N + kB - 1) / kB), ns, (nr + kSensM - 1) / kSensM);
+    dim3 grid((unsigned)((L.N + kB - 1) / kB), (ns + kSensS - 1) / kSensS, (nr + kSensM - 1) / kSensM);
     k_sens<<<grid, kB, 0, st>>>(L, kappa, ns, nr, nk, t, ntimes, X, zs, wq, JK, JS);
     LT_HIP(hipGetLastError());
     return 0;
