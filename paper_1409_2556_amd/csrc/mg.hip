@@ -179,6 +179,7 @@ int convert_vectors(hipStream_t st, const S* in, D* out, size_t count) {
 template int convert_vectors<double, float>(hipStream_t, const double*, float*, size_t);
 template int convert_vectors<float, double>(hipStream_t, const float*, double*, size_t);
 template int convert_vectors<double, double>(hipStream_t, const double*, double*, size_t);
+template int convert_vectors<float, float>(hipStream_t, const float*, float*, size_t);
 
 // ------------------------------------------------------------------ smoothing and transfers
 // y = (K + tau M) x for R vectors [R][2][N].
@@ -261,26 +262,19 @@ __global__ void k_resid_restrict(LevelView<T> F, int cnx, int cny, int cnz, int 
     xc[2 * M * r + M + I] = 0;
 }
 
-// x_fine += P e_coarse with cell-centred linear interpolation per halved axis.
+// Prolongation P e_coarse at fine cell (x, y, z): cell-centred linear interpolation
+// along every halved axis (the ghost beyond a wall mirrors the boundary cell with
+// parity g: -1 Dirichlet, +1 Neumann).
 template <typename T>
-__global__ void k_prolong(int fnx, int fny, int fnz, int cnx, int cny, int cnz, int cox, int coy, int coz,
-                          T glox, T ghix, T gloy, T ghiy, T gloz, T ghiz, const T* __restrict__ ec,
-                          T* __restrict__ xf, const int* __restrict__ active) {
-    int r = blockIdx.y;
-    if (active && !active[r]) return;
-    const int Nf = fnx * fny * fnz;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= Nf) return;
-    int x = i % fnx, y = (i / fnx) % fny, z = i / (fnx * fny);
-    // per axis: up to two coarse indices and weights
+__device__ __forceinline__ cpx<T> prolong_value(int x, int y, int z, int cnx, int cny, int cnz, int cox, int coy,
+                                                int coz, const T* glo, const T* ghi, const T* __restrict__ er,
+                                                const T* __restrict__ ei) {
     int ia[3][2];
     T wa[3][2];
     int na[3];
     const int c3[3] = {x, y, z};
     const int co[3] = {cox, coy, coz};
     const int cn[3] = {cnx, cny, cnz};
-    const T glo[3] = {glox, gloy, gloz};
-    const T ghi[3] = {ghix, ghiy, ghiz};
     for (int a = 0; a < 3; ++a) {
         if (!co[a]) {
             ia[a][0] = c3[a];
@@ -306,9 +300,6 @@ __global__ void k_prolong(int fnx, int fny, int fnz, int cnx, int cny, int cnz, 
             na[a] = 2;
         }
     }
-    const size_t Mc = (size_t)cnx * cny * cnz;
-    const T* er = ec + 2 * Mc * r;
-    const T* ei = er + Mc;
     cpx<T> acc = {0, 0};
     for (int c = 0; c < na[2]; ++c)
         for (int b = 0; b < na[1]; ++b)
@@ -318,9 +309,54 @@ __global__ void k_prolong(int fnx, int fny, int fnz, int cnx, int cny, int cnz, 
                 acc.re += w * er[J];
                 acc.im += w * ei[J];
             }
+    return acc;
+}
+
+// x_fine += P e_coarse with cell-centred linear interpolation per halved axis.
+template <typename T>
+__global__ void k_prolong(int fnx, int fny, int fnz, int cnx, int cny, int cnz, int cox, int coy, int coz,
+                          T glox, T ghix, T gloy, T ghiy, T gloz, T ghiz, const T* __restrict__ ec,
+                          T* __restrict__ xf, const int* __restrict__ active) {
+    int r = blockIdx.y;
+    if (active && !active[r]) return;
+    const int Nf = fnx * fny * fnz;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Nf) return;
+    int x = i % fnx, y = (i / fnx) % fny, z = i / (fnx * fny);
+    const T glo[3] = {glox, gloy, gloz};
+    const T ghi[3] = {ghix, ghiy, ghiz};
+    const size_t Mc = (size_t)cnx * cny * cnz;
+    const T* er = ec + 2 * Mc * r;
+    const cpx<T> acc = prolong_value<T>(x, y, z, cnx, cny, cnz, cox, coy, coz, glo, ghi, er, er + Mc);
     const size_t Nfs = Nf;
     xf[2 * Nfs * r + i] += acc.re;
     xf[2 * Nfs * r + Nfs + i] += acc.im;
+}
+
+// The first half-sweep of red-black Gauss-Seidel from x = 0: colour-0 cells see only
+// zero neighbours and take b / d, colour-1 cells stay 0.  Replaces clearing x and the
+// first sweep of colour 0.
+template <typename T>
+__global__ void k_gs_first(LevelView<T> L, T tr, T ti, T* __restrict__ x, const T* __restrict__ b,
+                           const int* __restrict__ active) {
+    int r = blockIdx.y;
+    if (active && !active[r]) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.N) return;
+    const int X = i % L.nx, Y = (i / L.nx) % L.ny, Z = i / (L.nx * L.ny);
+    const size_t N = L.N;
+    T* xr = x + 2 * N * r;
+    T* xi = xr + N;
+    if (((X + Y + Z) & 1) == 0) {
+        const T* br = b + 2 * N * r;
+        const cpx<T> d = {L.D[i] + tr * L.m[i], ti * L.m[i]};
+        const cpx<T> v = cdiv(cpx<T>{br[i], br[i + N]}, d);
+        xr[i] = v.re;
+        xi[i] = v.im;
+    } else {
+        xr[i] = 0;
+        xi[i] = 0;
+    }
 }
 
 // x = Ainv b on the coarsest level (Ainv interleaved complex, row-major).
@@ -571,8 +607,14 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
         } else {
             const size_t per = 2 * (size_t)L.N;
             dim3 grid(nblk(L.N), R);
-            if (l == 0) k_zero<T><<<dim3(nblk(per), R), kBlock, 0, st>>>(xpre[0], per, active);
-            for (int s = 0; s < nu1; ++s)
+            if (nu1 > 0) {
+                // from x = 0 (level 0 here; coarser levels are cleared by the restriction)
+                k_gs_first<T><<<grid, kBlock, 0, st>>>(v, tr, ti, xpre[l], bs[l], active);
+                k_gs_color<T><<<grid, kBlock, 0, st>>>(v, tr, ti, 1, xpre[l], bs[l], active);
+            } else if (l == 0) {
+                k_zero<T><<<dim3(nblk(per), R), kBlock, 0, st>>>(xpre[0], per, active);
+            }
+            for (int s = 1; s < nu1; ++s)
                 for (int c = 0; c < 2; ++c)
                     k_gs_color<T><<<grid, kBlock, 0, st>>>(v, tr, ti, c, xpre[l], bs[l], active);
             k_resid_restrict<T><<<dim3(nblk(C.N), R), kBlock, 0, st>>>(
@@ -655,8 +697,8 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
             for (int s = 0; s < nu2; ++s)
                 for (int c = 1; c >= 0; --c)
                     k_gs_color<T><<<grid, kBlock, 0, st>>>(v, tr, ti, c, xpre[l], bs[l], active);
-            LT_HIP(hipGetLastError());
             xpost[l] = xpre[l];
+            LT_HIP(hipGetLastError());
         }
     }
     return 0;

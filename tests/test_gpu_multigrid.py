@@ -17,6 +17,9 @@ pytestmark = pytest.mark.gpu
     ("C1", (32, 32), (0,) * 6, (2, 2)),
     ("C3", (32, 32, 16), (0,) * 6, (2, 2)),
     ("C3", (12, 20, 10), (1, 0, 0, 0, 0, 1), (2, 1)),
+    ("C3", (16, 12, 8), (0,) * 6, (2, 0)),
+    ("C3", (16, 12, 8), (0, 0, 1, 0, 0, 0), (0, 3)),
+    ("C3", (20, 20, 12), (0,) * 6, (1, 1)),
 ])
 def test_vcycle_matches_reference(lt, name, n, bc, nus):
     import torch
