@@ -224,6 +224,42 @@ __global__ void k_gs_color(LevelView<T> L, T tr, T ti, int color, T* __restrict_
     xi[i] = v.im;
 }
 
+// The same half-sweep with one thread per cell of the colour (nx even): thread k takes
+// the k-th cell of that colour in storage order, so no lane idles.
+template <typename T>
+__global__ void k_gs_color_half(LevelView<T> L, T tr, T ti, int color, T* __restrict__ x,
+                                const T* __restrict__ b, const int* __restrict__ active) {
+    int r = blockIdx.y;
+    if (active && !active[r]) return;
+    const int W = L.nx >> 1;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (L.N >> 1)) return;
+    const int row = k / W;  // y + ny z
+    const int Y = row % L.ny, Z = row / L.ny;
+    const int X = 2 * (k - row * W) + ((Y + Z + color) & 1);
+    const int i = X + L.nx * row;
+    const size_t N = L.N;
+    T* xr = x + 2 * N * r;
+    T* xi = xr + N;
+    const T* br = b + 2 * N * r;
+    cpx<T> off = offsum(L, xr, xi, i, X, Y, Z);
+    cpx<T> num = {br[i] + off.re, br[i + N] + off.im};
+    cpx<T> d = {L.D[i] + tr * L.m[i], ti * L.m[i]};
+    cpx<T> v = cdiv(num, d);
+    xr[i] = v.re;
+    xi[i] = v.im;
+}
+
+template <typename T>
+static void gs_half_sweep(hipStream_t st, const LevelView<T>& L, T tr, T ti, int color, T* x, const T* b, int R,
+                          const int* active) {
+    if ((L.nx & 1) == 0)
+        k_gs_color_half<T><<<dim3((unsigned)((L.N / 2 + 255) / 256), R), 256, 0, st>>>(L, tr, ti, color, x, b,
+                                                                                      active);
+    else
+        k_gs_color<T><<<dim3((unsigned)((L.N + 255) / 256), R), 256, 0, st>>>(L, tr, ti, color, x, b, active);
+}
+
 // Coarse right-hand side = sum over the aggregate of the fine residual b - A x;
 // the coarse iterate is cleared.
 template <typename T>
@@ -610,13 +646,13 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
             if (nu1 > 0) {
                 // from x = 0 (level 0 here; coarser levels are cleared by the restriction)
                 k_gs_first<T><<<grid, kBlock, 0, st>>>(v, tr, ti, xpre[l], bs[l], active);
-                k_gs_color<T><<<grid, kBlock, 0, st>>>(v, tr, ti, 1, xpre[l], bs[l], active);
+                gs_half_sweep<T>(st, v, tr, ti, 1, xpre[l], bs[l], R, active);
             } else if (l == 0) {
                 k_zero<T><<<dim3(nblk(per), R), kBlock, 0, st>>>(xpre[0], per, active);
             }
             for (int s = 1; s < nu1; ++s)
                 for (int c = 0; c < 2; ++c)
-                    k_gs_color<T><<<grid, kBlock, 0, st>>>(v, tr, ti, c, xpre[l], bs[l], active);
+                    gs_half_sweep<T>(st, v, tr, ti, c, xpre[l], bs[l], R, active);
             k_resid_restrict<T><<<dim3(nblk(C.N), R), kBlock, 0, st>>>(
                 v, C.n[0], C.n[1], C.n[2], C.coarsened_from_fine[0], C.coarsened_from_fine[1],
                 C.coarsened_from_fine[2], tr, ti, xpre[l], bs[l], bs[l + 1], xpre[l + 1], active);
@@ -659,7 +695,7 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
             LevelView<T> v = view<T>(L);
             for (int s = 0; s < 64; ++s)
                 for (int c = 0; c < 2; ++c)
-                    k_gs_color<T><<<grid, kBlock, 0, st>>>(v, tr, ti, c, xpre[lc], bs[lc], active);
+                    gs_half_sweep<T>(st, v, tr, ti, c, xpre[lc], bs[lc], R, active);
         }
         LT_HIP(hipGetLastError());
         xpost[lc] = xpre[lc];
@@ -696,7 +732,7 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
                                                   xpost[l + 1], xpre[l], active);
             for (int s = 0; s < nu2; ++s)
                 for (int c = 1; c >= 0; --c)
-                    k_gs_color<T><<<grid, kBlock, 0, st>>>(v, tr, ti, c, xpre[l], bs[l], active);
+                    gs_half_sweep<T>(st, v, tr, ti, c, xpre[l], bs[l], R, active);
             xpost[l] = xpre[l];
             LT_HIP(hipGetLastError());
         }
