@@ -497,18 +497,14 @@ int true_residuals(lt_handle* h, const KrylovOut& k, const Plan& plan, lt_stats*
     hipStream_t st = h->stream;
     const int N = h->N, R = k.R, Ks = k.Ks;
     int rc = 0;
-    const int nc = std::min(Ks, 16);
-    double* X = wsp<double>(h, "X", (size_t)R * nc * 2 * N, &rc);
-    if (!X) return rc;
+    const int mmax = k.iters_max;
+    double* KU = wsp<double>(h, "KU", (size_t)R * std::max(mmax, 1) * 2 * N, &rc);
     const int nb = reduce_blocks(N, R);
-    double* part = wsp<double>(h, "tpart", (size_t)R * nc * nb, &rc);
+    double* part = wsp<double>(h, "tpart", (size_t)R * Ks * nb, &rc);
     double* tr = wsp<double>(h, "trel", (size_t)R * Ks, &rc);
-    if (!part || !tr) return rc;
-    for (int k0 = 0; k0 < Ks; k0 += nc) {
-        int c = std::min(nc, Ks - k0);
-        LT_TRY(launch_form_x(st, N, R, c, k0, Ks, k.U, k.ustride, k.Y, k.jmax, k.mcols, X));
-        LT_TRY(launch_true_residual(st, h->levels[0].v64(), R, c, k0, Ks, k.zs, X, k.b, k.beta, part, tr));
-    }
+    if (!KU || !part || !tr) return rc;
+    LT_TRY(launch_true_residual_cols(st, h->levels[0].v64(), R, Ks, k.jmax, mmax, k.U, k.ustride, k.Y, k.mcols,
+                                     k.zs, k.b, k.beta, KU, part, tr));
     std::vector<double> ht((size_t)R * Ks);
     LT_HIP(hipMemcpyAsync(ht.data(), tr, ht.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     LT_HIP(hipStreamSynchronize(st));

@@ -34,6 +34,12 @@ int launch_inner_update(hipStream_t st, LevelView<double> L, cdouble tau, int R,
                         size_t ustride, const int* jcol, double* rho, T* lo, double* part, const int* inner_active);
 // *p = v on the stream (device-side loop state outside captured graphs)
 int launch_set_int(hipStream_t st, int* p, int v);
+// out[r][k] = ||b_r - (K + z_k M) U_r y_rk|| / beta_r for every right-hand side and shift,
+// from K applied once to each used basis column (KU: R * max(mmax, 1) * 2N doubles,
+// part: R * Ks * reduce_blocks(N, R) doubles).
+int launch_true_residual_cols(hipStream_t st, LevelView<double> L, int R, int Ks, int jmax, int mmax,
+                              const double* U, size_t ustride, const double* Y, const int* mcols, const double* zs,
+                              const double* b, const double* beta, double* KU, double* part, double* out);
 int launch_inner_finalize(hipStream_t st, int nb, int R, const double* part, const int* active, const double* worst,
                           double relax_tol, double tol, int inner_max, int* inner_active, int* vcycles,
                           int* count);

@@ -8,6 +8,8 @@
 // right-hand sides.
 #include "krylov.h"
 
+#include <algorithm>
+
 #include <cmath>
 
 namespace lt {
@@ -694,6 +696,141 @@ __global__ void k_true_res_finalize(int R, int nc, int k0, int Ks, int nb, const
     double s = 0;
     for (int q = 0; q < nb; ++q) s += part[(size_t)idx * nb + q];
     out[(size_t)r * Ks + k0 + c] = sqrt(s) / beta[r];
+}
+
+// ---------------------------------------------------------------- true residuals from the basis
+// With x_k = U y_k, the residual of shift k is b - sum_j y_jk (K u_j + z_k M u_j): the
+// stencil is applied once per basis column (KU) and every shift's residual is then
+// pointwise, so no solution vector is formed or re-read.
+__global__ void k_apply_cols(LevelView<double> L, const double* __restrict__ U, size_t ustride,
+                             const int* __restrict__ mcols, double* __restrict__ KU, size_t kstride) {
+    const int j = blockIdx.y, r = blockIdx.z;
+    if (j >= mcols[r]) return;
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= L.N) return;
+    const size_t N = L.N;
+    const double* xr = U + ustride * r + 2 * N * j;
+    const double* xi = xr + N;
+    const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+    const int sy = L.nx, sz = L.nx * L.ny;
+    double sre = 0, sim = 0;
+    if (x + 1 < L.nx) { const double t = L.Tx[i]; sre += t * xr[i + 1]; sim += t * xi[i + 1]; }
+    if (x > 0) { const double t = L.Tx[i - 1]; sre += t * xr[i - 1]; sim += t * xi[i - 1]; }
+    if (y + 1 < L.ny) { const double t = L.Ty[i]; sre += t * xr[i + sy]; sim += t * xi[i + sy]; }
+    if (y > 0) { const double t = L.Ty[i - sy]; sre += t * xr[i - sy]; sim += t * xi[i - sy]; }
+    if (z + 1 < L.nz) { const double t = L.Tz[i]; sre += t * xr[i + sz]; sim += t * xi[i + sz]; }
+    if (z > 0) { const double t = L.Tz[i - sz]; sre += t * xr[i - sz]; sim += t * xi[i - sz]; }
+    double* o = KU + kstride * r + 2 * N * j;
+    o[i] = L.D[i] * xr[i] - sre;
+    o[i + N] = L.D[i] * xi[i] - sim;
+}
+
+template <int kTrK>  // shifts per pass
+__global__ __launch_bounds__(256) void k_true_res_cols(LevelView<double> L, int Ks, int k0, int kc, int jmax,
+                                                       const double* __restrict__ U, size_t ustride,
+                                                       const double* __restrict__ KU, size_t kstride,
+                                                       const double* __restrict__ Y, const int* __restrict__ mcols,
+                                                       const double* __restrict__ zs, const double* __restrict__ b,
+                                                       double* __restrict__ part) {
+    const int r = blockIdx.y;
+    const int m = mcols[r];
+    const size_t N = L.N;
+    const double* br = b + 2 * N * r;
+    const double* Yr = Y + (size_t)r * jmax * 2 * Ks;
+    double v[kTrK];
+#pragma unroll
+    for (int c = 0; c < kTrK; ++c) v[c] = 0;
+    for (int i = blockIdx.x * kB + threadIdx.x; i < L.N; i += gridDim.x * kB) {
+        double ar[kTrK], ai[kTrK];
+        const double b0 = br[i], b1 = br[i + N];
+#pragma unroll
+        for (int c = 0; c < kTrK; ++c) {
+            ar[c] = b0;
+            ai[c] = b1;
+        }
+        const double mi = L.m[i];
+        for (int j = 0; j < m; ++j) {
+            const double* u = U + ustride * r + 2 * N * j;
+            const double* ku = KU + kstride * r + 2 * N * j;
+            const double ur = mi * u[i], ui = mi * u[i + N], kr = ku[i], ki = ku[i + N];  // m u, K u
+            const double* y = Yr + (size_t)j * 2 * Ks + 2 * k0;
+#pragma unroll
+            for (int c = 0; c < kTrK; ++c) {
+                const int cc = min(c, kc - 1);
+                const double zr = zs[2 * (k0 + cc)], zi = zs[2 * (k0 + cc) + 1];
+                // t = K u + z m u;  acc -= y t
+                const double tr = kr + (zr * ur - zi * ui), ti = ki + (zr * ui + zi * ur);
+                const double yr = y[2 * cc], yi = y[2 * cc + 1];
+                ar[c] -= yr * tr - yi * ti;
+                ai[c] -= yr * ti + yi * tr;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kTrK; ++c) v[c] += ar[c] * ar[c] + ai[c] * ai[c];
+    }
+    // block sums of the kc squared norms
+    __shared__ double sh[kB / 64][kTrK];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < kTrK; ++c) {
+        const double t = wave_sum(v[c]);
+        if (lane == 0) sh[w][c] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < kc) {
+        double t = 0;
+        for (int q = 0; q < kB / 64; ++q) t += sh[q][threadIdx.x];
+        part[((size_t)r * Ks + k0 + threadIdx.x) * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+__global__ void k_true_res_cols_finalize(int R, int Ks, int nb, const double* __restrict__ part,
+                                         const double* __restrict__ beta, double* __restrict__ out) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= R * Ks) return;
+    double s = 0;
+    for (int q = 0; q < nb; ++q) s += part[(size_t)idx * nb + q];
+    const double bt = beta[idx / Ks];
+    out[idx] = bt > 0 ? sqrt(s) / bt : 0.0;
+}
+
+int launch_true_residual_cols(hipStream_t st, LevelView<double> L, int R, int Ks, int jmax, int mmax,
+                              const double* U, size_t ustride, const double* Y, const int* mcols, const double* zs,
+                              const double* b, const double* beta, double* KU, double* part, double* out) {
+    const size_t kstride = (size_t)std::max(mmax, 1) * 2 * L.N;
+    if (mmax > 0) {
+        k_apply_cols<<<dim3((unsigned)((L.N + kB - 1) / kB), mmax, R), kB, 0, st>>>(L, U, ustride, mcols, KU, kstride);
+    }
+    const int nb = reduce_blocks(L.N, R);
+    // shifts per pass: a multiple of 4 up to 32 that covers Ks with the fewest computed lanes
+    int best = 32, cost = 1 << 30;
+    for (int w = 4; w <= 32; w += 4) {
+        const int c = (Ks + w - 1) / w * w + 8 * ((Ks + w - 1) / w);  // lanes plus a per-pass overhead
+        if (c < cost) {
+            cost = c;
+            best = w;
+        }
+    }
+    for (int k0 = 0; k0 < Ks; k0 += best) {
+        const int kc = std::min(best, Ks - k0);
+#define LT_TR(W)                                                                                                \
+    k_true_res_cols<W><<<dim3(nb, R), kB, 0, st>>>(L, Ks, k0, kc, jmax, U, ustride, KU, kstride, Y, mcols, zs, b, \
+                                                   part)
+        switch (best) {
+            case 4: LT_TR(4); break;
+            case 8: LT_TR(8); break;
+            case 12: LT_TR(12); break;
+            case 16: LT_TR(16); break;
+            case 20: LT_TR(20); break;
+            case 24: LT_TR(24); break;
+            case 28: LT_TR(28); break;
+            default: LT_TR(32); break;
+        }
+#undef LT_TR
+    }
+    k_true_res_cols_finalize<<<(unsigned)((R * Ks + kB - 1) / kB), kB, 0, st>>>(R, Ks, nb, part, beta, out);
+    LT_HIP(hipGetLastError());
+    return 0;
 }
 
 // ---------------------------------------------------------------- sensitivities
