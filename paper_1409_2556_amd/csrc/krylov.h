@@ -56,9 +56,6 @@ int launch_heads(hipStream_t st, int R, int np, int ntimes, int nk, const double
                  const double* Y, const int* mcols, int jmax, double* phi);
 int launch_form_x(hipStream_t st, int N, int R, int nc, int k0, int Ks, const double* U, size_t ustride,
                   const double* Y, int jmax, const int* mcols, double* X);
-int launch_true_residual(hipStream_t st, LevelView<double> L, int R, int nc, int k0, int Ks, const double* zs,
-                         const double* X, const double* b, const double* beta, double* part, double* out);
-
 template <typename T>
 int launch_net_scale(hipStream_t st, LevelView<double> L, cdouble tau, int R, T* d, const double* v, double* part,
                      const int* active);

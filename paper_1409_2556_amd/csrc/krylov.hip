@@ -657,46 +657,7 @@ __global__ void k_form_x(int N, int nc, int k0, int Ks, const double* __restrict
 }
 
 // part[(r*nc + c)][blk] = || b_r - (K + z_{k0+c} M) X[r][c] ||^2 over the block
-__global__ void k_true_res(LevelView<double> L, int nc, int k0, const double* __restrict__ zs,
-                           const double* __restrict__ X, const double* __restrict__ b, double* __restrict__ part) {
-    int rc = blockIdx.y;
-    int r = rc / nc, c = rc % nc;
-    const size_t N = L.N;
-    const double* xr = X + (size_t)rc * 2 * N;
-    const double* xi = xr + N;
-    const double* br = b + (size_t)r * 2 * N;
-    double zr = zs[2 * (k0 + c)], zi = zs[2 * (k0 + c) + 1];
-    double v[1] = {0};
-    for (int i = blockIdx.x * kB + threadIdx.x; i < L.N; i += gridDim.x * kB) {
-        int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
-        double sre = 0, sim = 0;
-        const int sy = L.nx, sz = L.nx * L.ny;
-        if (x + 1 < L.nx) { double t = L.Tx[i]; sre += t * xr[i + 1]; sim += t * xi[i + 1]; }
-        if (x > 0) { double t = L.Tx[i - 1]; sre += t * xr[i - 1]; sim += t * xi[i - 1]; }
-        if (y + 1 < L.ny) { double t = L.Ty[i]; sre += t * xr[i + sy]; sim += t * xi[i + sy]; }
-        if (y > 0) { double t = L.Ty[i - sy]; sre += t * xr[i - sy]; sim += t * xi[i - sy]; }
-        if (z + 1 < L.nz) { double t = L.Tz[i]; sre += t * xr[i + sz]; sim += t * xi[i + sz]; }
-        if (z > 0) { double t = L.Tz[i - sz]; sre += t * xr[i - sz]; sim += t * xi[i - sz]; }
-        double dre = L.D[i] + zr * L.m[i], dim = zi * L.m[i];
-        double are = dre * xr[i] - dim * xi[i] - sre;
-        double aim = dre * xi[i] + dim * xr[i] - sim;
-        double rre = br[i] - are, rim = br[i + N] - aim;
-        v[0] += rre * rre + rim * rim;
-    }
-    double o[1];
-    block_reduce<1>(v, o);
-    if (threadIdx.x == 0) part[(size_t)rc * gridDim.x + blockIdx.x] = o[0];
-}
 
-__global__ void k_true_res_finalize(int R, int nc, int k0, int Ks, int nb, const double* __restrict__ part,
-                                    const double* __restrict__ beta, double* __restrict__ out) {
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= R * nc) return;
-    int r = idx / nc, c = idx % nc;
-    double s = 0;
-    for (int q = 0; q < nb; ++q) s += part[(size_t)idx * nb + q];
-    out[(size_t)r * Ks + k0 + c] = sqrt(s) / beta[r];
-}
 
 // ---------------------------------------------------------------- true residuals from the basis
 // With x_k = U y_k, the residual of shift k is b - sum_j y_jk (K u_j + z_k M u_j): the
@@ -1105,13 +1066,5 @@ int launch_form_x(hipStream_t st, int N, int R, int nc, int k0, int Ks, const do
     return 0;
 }
 
-int launch_true_residual(hipStream_t st, LevelView<double> L, int R, int nc, int k0, int Ks, const double* zs,
-                         const double* X, const double* b, const double* beta, double* part, double* out) {
-    int nb = reduce_blocks(L.N, R);
-    k_true_res<<<dim3(nb, R * nc), kB, 0, st>>>(L, nc, k0, zs, X, b, part);
-    k_true_res_finalize<<<nb_for(R * nc), kB, 0, st>>>(R, nc, k0, Ks, nb, part, beta, out);
-    LT_HIP(hipGetLastError());
-    return 0;
-}
 
 }  // namespace lt
