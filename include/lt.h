@@ -112,12 +112,14 @@ typedef struct {
  *              the handle's stream and count its algorithmic bytes (reported
  *              in lt_stats.prof_*).
  *   precond    LT_PRECOND_GMG: V-cycle refinement only.  LT_PRECOND_UNET_GMG:
- *              every preconditioner solve starts from the attached network's
- *              guess (lt_unet_attach, 2D grids whose nx is a multiple of 128 and
- *              ny of 8); a guess that increases the residual is discarded, and
- *              the V-cycle refinement then proceeds as usual, so the V-cycle
- *              remains both the fallback and, through the true residual, the
- *              judge.
+ *              preconditioner solves start from the attached network's guess
+ *              (lt_unet_attach, 2D grids whose nx is a multiple of 128 and ny of
+ *              8).  The network is first tried on one right-hand side (a batch
+ *              of one); once its guess passes the net_keep test it serves every
+ *              right-hand side.  A guess that increases the residual is
+ *              discarded, and the V-cycle refinement then proceeds as usual, so
+ *              the V-cycle remains both the fallback and, through the true
+ *              residual, the judge.
  *   net_keep   the network is switched off for the rest of the call after an
  *              outer iteration in which its guess left more than this fraction
  *              of some right-hand side's residual (default 0.05: it must do at

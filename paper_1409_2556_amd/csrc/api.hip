@@ -292,7 +292,7 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     double* scale = small;
     double* beta = small + R;
     double* worst = small + 2 * R;
-    int* ints = wsp<int>(h, "ints", 5 * (size_t)R + 8, &rc);  // netc has 3 entries at 5R + 4  // masks, counts, [count, steps needed], net stats
+    int* ints = wsp<int>(h, "ints", 6 * (size_t)R + 8, &rc);  // netc has 3 entries at 5R + 4  // masks, counts, [count, steps needed], net stats
     if (!ints) return rc;
     int* active = ints;
     int* inner_active = ints + R;
@@ -301,6 +301,7 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     int* count = ints + 4 * R;
     int* bad = ints + 4 * R + 4;      // [R] network guesses to discard
     int* netc = ints + 5 * R + 4;     // [3] applied, rejected, worst residual ratio (float bits)
+    int* probe = ints + 5 * R + 8;    // [R] the one right-hand side the network is first tried on
     bool use_net = o.precond == LT_PRECOND_UNET_GMG && h->unet != nullptr;
     if (o.precond == LT_PRECOND_UNET_GMG &&
         (!h->unet || h->grid.ndim != 2 || h->grid.n[0] % 128 || h->grid.n[1] % 8)) {
@@ -346,6 +347,8 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
         return LT_EINVAL;
     }
     double* b = out->b;
+    int probe_rhs = -1;           // first right-hand side with a non-zero b
+    bool net_confirmed = false;   // the network's probe guess paid for itself
     // beta, v_1 = b / beta, masks
     LT_TRY(launch_norms(st, N, R, N2, b, part, beta, nullptr));
     LT_TRY(launch_scale_into(st, N, R, N2, qstride, b, beta, Q));
@@ -357,8 +360,12 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
         std::vector<double> hb(R);
         LT_HIP(hipMemcpyAsync(hb.data(), beta, R * sizeof(double), hipMemcpyDeviceToHost, st));
         LT_HIP(hipStreamSynchronize(st));
-        std::vector<int> ii(5 * (size_t)R + 8, 0);
+        std::vector<int> ii(6 * (size_t)R + 8, 0);
         for (int r = 0; r < R; ++r) ii[r] = hb[r] > 0.0 ? 1 : 0;
+        probe_rhs = -1;
+        for (int r = 0; r < R && probe_rhs < 0; ++r)
+            if (hb[r] > 0.0) probe_rhs = r;
+        if (probe_rhs >= 0) ii[5 * (size_t)R + 8 + probe_rhs] = 1;
         LT_HIP(hipMemcpyAsync(ints, ii.data(), ii.size() * sizeof(int), hipMemcpyHostToDevice, st));
     }
     const LevelView<double> L0 = h->levels[0].v64();
@@ -383,23 +390,29 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
             LT_TRY(launch_inner_init<float>(st, N, R, qstride, vj, uj, ustride, rho, lo32, active));
         else
             LT_TRY(launch_inner_init<double>(st, N, R, qstride, vj, uj, ustride, rho, (double*)nullptr, active));
-        if (use_net) {
+        if (use_net && probe_rhs >= 0) {
             // learned first guess u = alpha net(v), alpha minimising ||v - alpha (K + tau M) net(v)||;
-            // rho = v - (K + tau M) u; discarded where it is not finite or does not help
+            // rho = v - (K + tau M) u; discarded where it is not finite or does not help.  Until
+            // a guess has paid for itself the network runs on one right-hand side only (a batch
+            // of one), so a network that does not help costs one small application.
             UNet* net = &h->unet->net;
             const int nbr = reduce_blocks(N, R);
+            const int* mask = net_confirmed ? active : probe;
+            const int nb_net = net_confirmed ? R : 1;
+            const size_t o0 = net_confirmed ? 0 : 2 * (size_t)N * probe_rhs;
+            const int* amask = net_confirmed ? active : nullptr;
             if (mixed) {
-                LT_TRY(unet_apply<float>(net, st, L0, h->lnDbar, tau, R, lo32, e32, active));
-                LT_TRY(launch_net_scale<float>(st, L0, tau, R, e32, rho, part, active));
-                LT_TRY(launch_inner_update<float>(st, L0, tau, R, e32, uj, ustride, nullptr, rho, lo32, part, active));
-                LT_TRY(launch_net_guard(st, R, nbr, part, active, bad, netc));
+                LT_TRY(unet_apply<float>(net, st, L0, h->lnDbar, tau, nb_net, lo32 + o0, e32 + o0, amask));
+                LT_TRY(launch_net_scale<float>(st, L0, tau, R, e32, rho, part, mask));
+                LT_TRY(launch_inner_update<float>(st, L0, tau, R, e32, uj, ustride, nullptr, rho, lo32, part, mask));
+                LT_TRY(launch_net_guard(st, R, nbr, part, mask, bad, netc));
                 LT_TRY(launch_inner_init<float>(st, N, R, qstride, vj, uj, ustride, rho, lo32, bad));
             } else {
-                LT_TRY(unet_apply<double>(net, st, L0, h->lnDbar, tau, R, rho, e64, active));
-                LT_TRY(launch_net_scale<double>(st, L0, tau, R, e64, rho, part, active));
+                LT_TRY(unet_apply<double>(net, st, L0, h->lnDbar, tau, nb_net, rho + o0, e64 + o0, amask));
+                LT_TRY(launch_net_scale<double>(st, L0, tau, R, e64, rho, part, mask));
                 LT_TRY(launch_inner_update<double>(st, L0, tau, R, e64, uj, ustride, nullptr, rho, (double*)nullptr, part,
-                                                   active));
-                LT_TRY(launch_net_guard(st, R, nbr, part, active, bad, netc));
+                                                   mask));
+                LT_TRY(launch_net_guard(st, R, nbr, part, mask, bad, netc));
                 LT_TRY(launch_inner_init<double>(st, N, R, qstride, vj, uj, ustride, rho, (double*)nullptr, bad));
             }
         }
@@ -436,6 +449,8 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
             if (!(worst_ratio <= o.net_keep)) {
                 use_net = false;
                 out->net_disabled_at = j + 1;
+            } else {
+                net_confirmed = true;
             }
         }
         if (debug) {
