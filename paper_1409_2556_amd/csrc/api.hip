@@ -289,6 +289,8 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     if (!part) return rc;
     double* small = wsp<double>(h, "small", 4 * (size_t)R, &rc);
     if (!small) return rc;
+    double* partn = wsp<double>(h, "partn", (size_t)R * nb, &rc);  // norm partials of the Gram-Schmidt step
+    if (!partn) return rc;
     double* scale = small;
     double* beta = small + R;
     double* worst = small + 2 * R;
@@ -381,15 +383,15 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     for (j = 0; j < jmax; ++j) {
         cdouble tau = plan.tau_sched[j % plan.tau_sched.size()];
         // inner refinement of u_j ~ (K + tau M)^{-1} v_j
-        LT_HIP(hipMemcpyAsync(inner_active, active, R * sizeof(int), hipMemcpyDeviceToDevice, st));
-        LT_HIP(hipMemsetAsync(count + 1, 0, 2 * sizeof(int), st));  // steps needed, steps taken
-        LT_TRY(launch_set_int(st, jdev, j));
+        LT_TRY(launch_iter_begin(st, R, active, inner_active, count, j));  // jdev = count + 3
         double* uj = U + (size_t)j * N2;
-        const double* vj = Q + (size_t)j * N2;
+        double* vj = Q + (size_t)j * N2;
+        const double* vscale = j > 0 ? scale : nullptr;  // v_j is normalised by its first read
         if (mixed)
-            LT_TRY(launch_inner_init<float>(st, N, R, qstride, vj, uj, ustride, rho, lo32, active));
+            LT_TRY(launch_inner_init<float>(st, N, R, qstride, vj, uj, ustride, rho, lo32, active, vscale));
         else
-            LT_TRY(launch_inner_init<double>(st, N, R, qstride, vj, uj, ustride, rho, (double*)nullptr, active));
+            LT_TRY(launch_inner_init<double>(st, N, R, qstride, vj, uj, ustride, rho, (double*)nullptr, active,
+                                             vscale));
         if (use_net && probe_rhs >= 0) {
             // learned first guess u = alpha net(v), alpha minimising ||v - alpha (K + tau M) net(v)||;
             // rho = v - (K + tau M) u; discarded where it is not finite or does not help.  Until
@@ -470,7 +472,7 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
         }
         // Arnoldi: v_{j+1} from M u_j by classical Gram-Schmidt with reorthogonalisation
         LT_TRY(launch_cgs2(st, N, R, j, m, U, ustride, Q, qstride, H, hstride, hrstride, part, pstride, c1, c2,
-                           cstride, scale, active));
+                           cstride, scale, partn, active));
         if (np > 0) LT_TRY(launch_gather(st, R, N, np, rec->off, rec->cell, rec->wt, U, ustride, j, G, jmax, active));
         LT_TRY(launch_ls_update(st, R, Ks, j, tau, zs, omega, o.tol, H, hstride, hrstride, beta, ls, active, mcols,
                                 worst, conv));

@@ -27,13 +27,13 @@ int launch_norms(hipStream_t st, int N, int R, size_t vstride, const double* x, 
 int launch_scale_into(hipStream_t st, int N, int R, size_t instride, size_t outstride, const double* in,
                       const double* nrm, double* out);
 template <typename T>
-int launch_inner_init(hipStream_t st, int N, int R, size_t qstride, const double* v, double* u, size_t ustride,
-                      double* rho, T* lo, const int* active);
+int launch_inner_init(hipStream_t st, int N, int R, size_t qstride, double* v, double* u, size_t ustride,
+                      double* rho, T* lo, const int* active, const double* scale = nullptr);
+// inner_active = active; clear the refinement step counters; count[3] = j
+int launch_iter_begin(hipStream_t st, int R, const int* active, int* inner_active, int* count, int j);
 template <typename T>
 int launch_inner_update(hipStream_t st, LevelView<double> L, cdouble tau, int R, const T* e, double* u,
                         size_t ustride, const int* jcol, double* rho, T* lo, double* part, const int* inner_active);
-// *p = v on the stream (device-side loop state outside captured graphs)
-int launch_set_int(hipStream_t st, int* p, int v);
 // out[r][k] = ||b_r - (K + z_k M) U_r y_rk|| / beta_r for every right-hand side and shift,
 // from K applied once to each used basis column (KU: R * max(mmax, 1) * 2N doubles,
 // part: R * Ks * reduce_blocks(N, R) doubles).
@@ -43,9 +43,11 @@ int launch_true_residual_cols(hipStream_t st, LevelView<double> L, int R, int Ks
 int launch_inner_finalize(hipStream_t st, int nb, int R, const double* part, const int* active, const double* worst,
                           double relax_tol, double tol, int inner_max, int* inner_active, int* vcycles,
                           int* count);
+// One CGS2 step for column j: unnormalised q_{j+1} in column j + 1 of Q, Hbar column j, and
+// scale[r] = 1 / ||q_{j+1}|| (applied by the next launch_inner_init).  partn: R * nb doubles.
 int launch_cgs2(hipStream_t st, int N, int R, int j, const double* m, const double* U, size_t ustride, double* Q,
                 size_t qstride, double* H, int hstride, size_t hrstride, double* part, int pstride, double* c1,
-                double* c2, int cstride, double* scale, const int* active);
+                double* c2, int cstride, double* scale, double* partn, const int* active);
 int launch_ls_update(hipStream_t st, int R, int Ks, int j, cdouble tau, const double* zs, const double* omega,
                      double tol, const double* H, int hstride, size_t hrstride, const double* beta,
                      const LSState& s, int* active, int* mcols, double* worst, int* conv);

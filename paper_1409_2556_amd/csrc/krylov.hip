@@ -101,14 +101,19 @@ __global__ void k_scale_into(int N, size_t instride, size_t outstride, const dou
 // ---------------------------------------------------------------- inner refinement
 // u <- 0, rho <- v = Q[:, j]; lo <- (T) rho
 template <typename T>
-__global__ void k_inner_init(int N, size_t qstride, const double* __restrict__ v, double* __restrict__ u,
+__global__ void k_inner_init(int N, size_t qstride, double* __restrict__ v, double* __restrict__ u,
                              size_t ustride, double* __restrict__ rho, T* __restrict__ lo,
-                             const int* __restrict__ active) {
+                             const int* __restrict__ active, const double* __restrict__ scale) {
     int r = blockIdx.y;
     if (active && !active[r]) return;
     size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
     if (i >= 2 * (size_t)N) return;
     double x = v[qstride * r + i];
+    if (scale) {
+        // normalisation of the new basis vector, deferred from the Gram-Schmidt step
+        x *= scale[r];
+        v[qstride * r + i] = x;
+    }
     u[ustride * r + i] = 0.0;
     rho[2 * (size_t)N * r + i] = x;
     if (lo) lo[2 * (size_t)N * r + i] = (T)x;
@@ -354,61 +359,7 @@ __global__ void k_mdot(int N, int ncols, const double* __restrict__ Q, size_t qs
 }
 
 // coef[r][c] = sum over blocks of part  (c < ncols + 1: the last entry is ||s||^2)
-__global__ void k_mdot_finalize(int nb, int ncols, const double* __restrict__ part, int pstride,
-                                double* __restrict__ coef, int cstride, const int* __restrict__ active) {
-    int r = blockIdx.x;
-    if (active && !active[r]) return;
-    // one wavefront per column: lanes stride over the partial sums, then a shuffle reduction
-    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-    for (int c = threadIdx.x >> 6; c <= ncols; c += nw) {
-        double re = 0, im = 0;
-        for (int q = lane; q < nb; q += 64) {
-            const double* p = part + ((size_t)r * nb + q) * pstride;
-            re += p[2 * c];
-            im += p[2 * c + 1];
-        }
-        re = wave_sum(re);
-        im = wave_sum(im);
-        if (lane == 0) {
-            coef[(size_t)r * cstride + 2 * c] = re;
-            coef[(size_t)r * cstride + 2 * c + 1] = im;
-        }
-    }
-}
 
-// out = s - sum_c Q_c coef_c; optional partial ||out||^2 into part[r][blk]
-__global__ void k_update(int N, int ncols, const double* __restrict__ Q, size_t qstride,
-                         const double* __restrict__ m, const double* __restrict__ u, size_t ustride,
-                         const double* __restrict__ s, size_t sstride, const double* __restrict__ coef,
-                         int cstride, double* __restrict__ out, size_t ostride, double* __restrict__ part,
-                         const int* __restrict__ active) {
-    int r = blockIdx.y;
-    if (active && !active[r]) return;
-    const double* Qr = Q + qstride * r;
-    const double* ur = u ? u + ustride * r : nullptr;
-    const double* sr = s ? s + sstride * r : nullptr;
-    const double* cr = coef + (size_t)r * cstride;
-    double* orr = out + ostride * r;
-    const size_t NN = N;
-    double v[1] = {0};
-    for (int i = blockIdx.x * kB + threadIdx.x; i < N; i += gridDim.x * kB) {
-        c64 sv = load_s(m, ur, sr, NN, i);
-        for (int c = 0; c < ncols; ++c) {
-            const double* q = Qr + 2 * NN * c;
-            c64 p = cm({q[i], q[i + NN]}, {cr[2 * c], cr[2 * c + 1]});
-            sv.re -= p.re;
-            sv.im -= p.im;
-        }
-        orr[i] = sv.re;
-        orr[i + NN] = sv.im;
-        v[0] += sv.re * sv.re + sv.im * sv.im;
-    }
-    if (part) {
-        double o[1];
-        block_reduce<1>(v, o);
-        if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = o[0];
-    }
-}
 
 // Hbar column j: h = h1 + h2, h_{j+1,j} = ||s||; scale for the new basis vector;
 // breakdown (||s|| <= 1e-14 ||M u||) gives h_{j+1,j} = 0 and a zero vector.
@@ -437,14 +388,76 @@ __global__ void k_hcol_finalize(int R, int j, int nb, const double* __restrict__
     }
 }
 
-__global__ void k_scale_inplace(int N, double* __restrict__ x, size_t stride, const double* __restrict__ scale,
-                                const int* __restrict__ active) {
+// out = s - sum_c Q_c coef_c (optional partial ||out||^2 into part[r][blk]), with the
+// projection coefficients summed in the workgroup from the pass's partial dot products
+// (one wavefront per column, lanes striding over the partials: every workgroup forms the
+// same coefficients); workgroup 0 also stores them for the Hessenberg column.
+// Dynamic LDS: 2 (ncols + 1) doubles.
+__global__ void k_update_sum(int N, int ncols, const double* __restrict__ Q, size_t qstride,
+                             const double* __restrict__ m, const double* __restrict__ u, size_t ustride,
+                             const double* __restrict__ s, size_t sstride, const double* __restrict__ pin, int nbin,
+                             int pstride, double* __restrict__ coef, int cstride, double* __restrict__ out,
+                             size_t ostride, double* __restrict__ part, const int* __restrict__ active) {
     int r = blockIdx.y;
     if (active && !active[r]) return;
-    size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
-    if (i >= 2 * (size_t)N) return;
-    x[stride * r + i] *= scale[r];
+    extern __shared__ double cs[];
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int c = threadIdx.x >> 6; c <= ncols; c += nw) {
+        double re = 0, im = 0;
+        for (int q = lane; q < nbin; q += 64) {
+            const double* p = pin + ((size_t)r * nbin + q) * pstride;
+            re += p[2 * c];
+            im += p[2 * c + 1];
+        }
+        re = wave_sum(re);
+        im = wave_sum(im);
+        if (lane == 0) {
+            cs[2 * c] = re;
+            cs[2 * c + 1] = im;
+            if (blockIdx.x == 0) {
+                coef[(size_t)r * cstride + 2 * c] = re;
+                coef[(size_t)r * cstride + 2 * c + 1] = im;
+            }
+        }
+    }
+    __syncthreads();
+    const double* Qr = Q + qstride * r;
+    const double* ur = u ? u + ustride * r : nullptr;
+    const double* sr = s ? s + sstride * r : nullptr;
+    double* orr = out + ostride * r;
+    const size_t NN = N;
+    double v[1] = {0};
+    for (int i = blockIdx.x * kB + threadIdx.x; i < N; i += gridDim.x * kB) {
+        c64 sv = load_s(m, ur, sr, NN, i);
+        for (int c = 0; c < ncols; ++c) {
+            const double* q = Qr + 2 * NN * c;
+            c64 p = cm({q[i], q[i + NN]}, {cs[2 * c], cs[2 * c + 1]});
+            sv.re -= p.re;
+            sv.im -= p.im;
+        }
+        orr[i] = sv.re;
+        orr[i + NN] = sv.im;
+        v[0] += sv.re * sv.re + sv.im * sv.im;
+    }
+    if (part) {
+        double o[1];
+        block_reduce<1>(v, o);
+        if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = o[0];
+    }
 }
+
+// Start of an outer iteration: every active right-hand side refines, the step counters
+// are cleared and the basis column is set (one launch instead of a copy, a fill and a store).
+__global__ void k_iter_begin(int R, const int* __restrict__ active, int* __restrict__ inner_active,
+                             int* __restrict__ count, int j) {
+    for (int r = threadIdx.x; r < R; r += blockDim.x) inner_active[r] = active[r];
+    if (threadIdx.x == 0) {
+        count[1] = 0;
+        count[2] = 0;
+        count[3] = j;
+    }
+}
+
 
 // ---------------------------------------------------------------- per-shift least squares
 // One block per right-hand side, one thread per shift.  The Hessenberg matrix of shift z is
@@ -960,16 +973,23 @@ int launch_scale_into(hipStream_t st, int N, int R, size_t instride, size_t outs
 }
 
 template <typename T>
-int launch_inner_init(hipStream_t st, int N, int R, size_t qstride, const double* v, double* u, size_t ustride,
-                      double* rho, T* lo, const int* active) {
-    k_inner_init<T><<<dim3(nb_for(2 * (size_t)N), R), kB, 0, st>>>(N, qstride, v, u, ustride, rho, lo, active);
+int launch_inner_init(hipStream_t st, int N, int R, size_t qstride, double* v, double* u, size_t ustride,
+                      double* rho, T* lo, const int* active, const double* scale) {
+    k_inner_init<T><<<dim3(nb_for(2 * (size_t)N), R), kB, 0, st>>>(N, qstride, v, u, ustride, rho, lo, active,
+                                                                   scale);
     LT_HIP(hipGetLastError());
     return 0;
 }
-template int launch_inner_init<double>(hipStream_t, int, int, size_t, const double*, double*, size_t, double*,
-                                       double*, const int*);
-template int launch_inner_init<float>(hipStream_t, int, int, size_t, const double*, double*, size_t, double*,
-                                      float*, const int*);
+template int launch_inner_init<double>(hipStream_t, int, int, size_t, double*, double*, size_t, double*,
+                                       double*, const int*, const double*);
+template int launch_inner_init<float>(hipStream_t, int, int, size_t, double*, double*, size_t, double*,
+                                      float*, const int*, const double*);
+
+int launch_iter_begin(hipStream_t st, int R, const int* active, int* inner_active, int* count, int j) {
+    k_iter_begin<<<1, 256, 0, st>>>(R, active, inner_active, count, j);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
 
 template <typename T>
 int launch_inner_update(hipStream_t st, LevelView<double> L, cdouble tau, int R, const T* e, double* u,
@@ -993,33 +1013,26 @@ int launch_inner_finalize(hipStream_t st, int nb, int R, const double* part, con
     return 0;
 }
 
-__global__ void k_set_int(int* __restrict__ p, int v) { *p = v; }
-
-int launch_set_int(hipStream_t st, int* p, int v) {
-    k_set_int<<<1, 1, 0, st>>>(p, v);
-    LT_HIP(hipGetLastError());
-    return 0;
-}
 
 // One CGS2 step for column j: Q[:, j+1] = normalised (I - Q Q^*)^2 (M u_j); Hbar column j.
 int launch_cgs2(hipStream_t st, int N, int R, int j, const double* m, const double* U, size_t ustride, double* Q,
                 size_t qstride, double* H, int hstride, size_t hrstride, double* part, int pstride, double* c1,
-                double* c2, int cstride, double* scale, const int* active) {
+                double* c2, int cstride, double* scale, double* partn, const int* active) {
     int nb = reduce_blocks(N, R);
     int ncols = j + 1;
     const double* u = U + 2 * (size_t)N * j;
     double* qn = Q + 2 * (size_t)N * (j + 1);
     dim3 g(nb, R);
+    const size_t shm = sizeof(double) * 2 * (ncols + 1);
+    // first pass: coefficients of M u_j, then its projection; second pass on the result
     k_mdot<<<g, kB, 0, st>>>(N, ncols, Q, qstride, m, u, ustride, nullptr, 0, part, pstride, active);
-    k_mdot_finalize<<<R, 256, 0, st>>>(nb, ncols, part, pstride, c1, cstride, active);
-    k_update<<<g, kB, 0, st>>>(N, ncols, Q, qstride, m, u, ustride, nullptr, 0, c1, cstride, qn, qstride, nullptr,
-                               active);
+    k_update_sum<<<g, kB, shm, st>>>(N, ncols, Q, qstride, m, u, ustride, nullptr, 0, part, nb, pstride, c1, cstride,
+                                     qn, qstride, nullptr, active);
     k_mdot<<<g, kB, 0, st>>>(N, ncols, Q, qstride, nullptr, nullptr, 0, qn, qstride, part, pstride, active);
-    k_mdot_finalize<<<R, 256, 0, st>>>(nb, ncols, part, pstride, c2, cstride, active);
-    k_update<<<g, kB, 0, st>>>(N, ncols, Q, qstride, nullptr, nullptr, 0, qn, qstride, c2, cstride, qn, qstride,
-                               part, active);
-    k_hcol_finalize<<<R, 256, 0, st>>>(R, j, nb, c1, c2, cstride, part, H, hstride, hrstride, scale, active);
-    k_scale_inplace<<<dim3(nb_for(2 * (size_t)N), R), kB, 0, st>>>(N, qn, qstride, scale, active);
+    k_update_sum<<<g, kB, shm, st>>>(N, ncols, Q, qstride, nullptr, nullptr, 0, qn, qstride, part, nb, pstride, c2,
+                                     cstride, qn, qstride, partn, active);
+    // Hessenberg column and 1 / ||q_{j+1}||; the next iteration's first read applies the scale
+    k_hcol_finalize<<<R, 256, 0, st>>>(R, j, nb, c1, c2, cstride, partn, H, hstride, hrstride, scale, active);
     LT_HIP(hipGetLastError());
     return 0;
 }
