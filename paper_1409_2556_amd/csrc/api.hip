@@ -143,7 +143,8 @@ struct KrylovOut {
 // *swapped = 1 when the FP64 residual moved to rho_next.
 int refine_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, size_t ustride, const int* jdev,
                 float* e32, double* e64, float* lo32, float* lo32_next, double* rho, double* rho_next, double* part,
-                const int* active, int* inner_active, const double* worst, int* vcyc, int* count, int* swapped) {
+                const int* active, int* inner_active, const double* worst, int* vcyc, int* count, double* rprev,
+                int* est, int* swapped) {
     hipStream_t st = h->stream;
     const LevelView<double> L0 = h->levels[0].v64();
     int nparts = -1;
@@ -170,7 +171,7 @@ int refine_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, s
         }
     }
     return launch_inner_finalize(st, nparts, R, part, active, worst, o.relax * o.tol, o.tol, o.inner_max,
-                                 inner_active, vcyc, count);
+                                 inner_active, vcyc, count, rprev, est);
 }
 
 // refine_step captured once as a HIP graph and replayed.  Everything a
@@ -178,7 +179,8 @@ int refine_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, s
 // buffers, and the workspace generation (any reallocation retires all graphs).
 int graph_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, size_t ustride, const int* jdev,
                float* e32, double* e64, float* lo32, float* lo32_next, double* rho, double* rho_next, double* part,
-               const int* active, int* inner_active, const double* worst, int* vcyc, int* count, int* swapped) {
+               const int* active, int* inner_active, const double* worst, int* vcyc, int* count, double* rprev,
+               int* est, int* swapped) {
     hipStream_t st = h->stream;
     int rc = 0;
     // the coarse inverse for tau is built on the host and uploaded: do it before capturing
@@ -199,7 +201,8 @@ int graph_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, si
         (unsigned long long)o.precision, (unsigned long long)R, (unsigned long long)o.nu1, (unsigned long long)o.nu2,
         bits(tau.real()), bits(tau.imag()), bits(o.relax * o.tol), bits(o.tol), (unsigned long long)o.inner_max,
         ptr(U), ustride, ptr(jdev), ptr(e32), ptr(e64), ptr(lo32), ptr(lo32_next), ptr(rho), ptr(rho_next),
-        ptr(part), ptr(active), ptr(inner_active), ptr(worst), ptr(vcyc), ptr(count), h->ws_gen};
+        ptr(part), ptr(active), ptr(inner_active), ptr(worst), ptr(vcyc), ptr(count), ptr(rprev), ptr(est),
+        h->ws_gen};
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
         if (h->graphs.size() >= 64) {
@@ -210,7 +213,7 @@ int graph_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, si
         LT_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         int sw = 0;
         const int rcs = refine_step(h, o, R, tau, U, ustride, jdev, e32, e64, lo32, lo32_next, rho, rho_next, part,
-                                    active, inner_active, worst, vcyc, count, &sw);
+                                    active, inner_active, worst, vcyc, count, rprev, est, &sw);
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(st, &g);
         if (rcs < 0 || ec != hipSuccess || h->ws_gen != gen) {
@@ -222,7 +225,7 @@ int graph_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, si
             }
             // a workspace moved while capturing: launch this step directly
             return refine_step(h, o, R, tau, U, ustride, jdev, e32, e64, lo32, lo32_next, rho, rho_next, part,
-                               active, inner_active, worst, vcyc, count, swapped);
+                               active, inner_active, worst, vcyc, count, rprev, est, swapped);
         }
         hipGraphExec_t ex = nullptr;
         const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -294,7 +297,8 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     double* scale = small;
     double* beta = small + R;
     double* worst = small + 2 * R;
-    int* ints = wsp<int>(h, "ints", 6 * (size_t)R + 8, &rc);  // netc has 3 entries at 5R + 4  // masks, counts, [count, steps needed], net stats
+    double* rprev = small + 3 * R;  // residual norms before the last refinement step
+    int* ints = wsp<int>(h, "ints", 6 * (size_t)R + 12, &rc);  // netc has 3 entries at 5R + 4  // masks, counts, [count, steps needed], net stats
     if (!ints) return rc;
     int* active = ints;
     int* inner_active = ints + R;
@@ -304,6 +308,7 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     int* bad = ints + 4 * R + 4;      // [R] network guesses to discard
     int* netc = ints + 5 * R + 4;     // [3] applied, rejected, worst residual ratio (float bits)
     int* probe = ints + 5 * R + 8;    // [R] the one right-hand side the network is first tried on
+    int* est = ints + 6 * R + 8;      // [1] estimated refinement steps still needed
     bool use_net = o.precond == LT_PRECOND_UNET_GMG && h->unet != nullptr;
     if (o.precond == LT_PRECOND_UNET_GMG &&
         (!h->unet || h->grid.ndim != 2 || h->grid.n[0] % 128 || h->grid.n[1] % 8)) {
@@ -362,7 +367,7 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
         std::vector<double> hb(R);
         LT_HIP(hipMemcpyAsync(hb.data(), beta, R * sizeof(double), hipMemcpyDeviceToHost, st));
         LT_HIP(hipStreamSynchronize(st));
-        std::vector<int> ii(6 * (size_t)R + 8, 0);
+        std::vector<int> ii(6 * (size_t)R + 12, 0);
         for (int r = 0; r < R; ++r) ii[r] = hb[r] > 0.0 ? 1 : 0;
         probe_rhs = -1;
         for (int r = 0; r < R && probe_rhs < 0; ++r)
@@ -383,7 +388,7 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     for (j = 0; j < jmax; ++j) {
         cdouble tau = plan.tau_sched[j % plan.tau_sched.size()];
         // inner refinement of u_j ~ (K + tau M)^{-1} v_j
-        LT_TRY(launch_iter_begin(st, R, active, inner_active, count, j));  // jdev = count + 3
+        LT_TRY(launch_iter_begin(st, R, active, inner_active, count, j, rprev));  // jdev = count + 3
         double* uj = U + (size_t)j * N2;
         double* vj = Q + (size_t)j * N2;
         const double* vscale = j > 0 ? scale : nullptr;  // v_j is normalised by its first read
@@ -421,27 +426,33 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
         // The refinement steps expected from the previous outer iteration are
         // enqueued without waiting; finished right-hand sides are masked off on
         // the device, and the host checks only after that batch.
-        int step = 0;
+        // Later batches are sized by the finalize kernel's estimate of the steps still needed
+        // (from each residual's contraction in the last step), so a short first batch costs
+        // one more synchronisation rather than one per missing step.
+        int step = 0, checks = 0;
+        int batch = std::min(inner_guess, o.inner_max);
         while (step < o.inner_max) {
-            const int batch = step == 0 ? std::min(inner_guess, o.inner_max) : 1;
-            for (int b2 = 0; b2 < batch; ++b2, ++step) {
+            ++checks;
+            for (int b2 = 0; b2 < batch && step < o.inner_max; ++b2, ++step) {
                 int swapped = 0;
                 if (use_graphs && j > 0) {
                     LT_TRY(graph_step(h, o, R, tau, U, ustride, jdev, e32, e64, lo32, lo32_next, rho, rho_next, part,
-                                      active, inner_active, worst, vcyc, count, &swapped));
+                                      active, inner_active, worst, vcyc, count, rprev, est, &swapped));
                 } else {
                     LT_TRY(refine_step(h, o, R, tau, U, ustride, jdev, e32, e64, lo32, lo32_next, rho, rho_next, part,
-                                       active, inner_active, worst, vcyc, count, &swapped));
+                                       active, inner_active, worst, vcyc, count, rprev, est, &swapped));
                 }
                 if (mixed) std::swap(lo32, lo32_next);
                 if (swapped) std::swap(rho, rho_next);
             }
+            LT_HIP(hipMemcpyAsync(hflag + 3, est, sizeof(int), hipMemcpyDeviceToHost, st));
             LT_HIP(hipMemcpyAsync(hflag, count, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
             // convergence flags as left by the previous outer iteration's least squares
             LT_HIP(hipMemcpyAsync(hact, active, R * sizeof(int), hipMemcpyDeviceToHost, st));
             if (use_net) LT_HIP(hipMemcpyAsync(hflag + 2, netc + 2, sizeof(int), hipMemcpyDeviceToHost, st));
             LT_HIP(hipStreamSynchronize(st));
             if (*hflag == 0) break;
+            batch = std::max(1, hflag[3]);
         }
         if (use_net) {
             // keep the network only while its guess removes at least the fraction 1 - net_keep
@@ -458,8 +469,8 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
         if (debug) {
             std::vector<int> vc(R);
             LT_HIP(hipMemcpy(vc.data(), vcyc, R * sizeof(int), hipMemcpyDeviceToHost));
-            std::fprintf(stderr, "[lt] j=%d tau=(%.3g,%.3g) inner launched=%d needed=%d guess=%d vcycles/rhs:", j,
-                         tau.real(), tau.imag(), step, hflag[1], inner_guess);
+            std::fprintf(stderr, "[lt] j=%d tau=(%.3g,%.3g) inner launched=%d needed=%d guess=%d checks=%d vcycles/rhs:",
+                         j, tau.real(), tau.imag(), step, hflag[1], inner_guess, checks);
             for (int r = 0; r < R; ++r) std::fprintf(stderr, " %d", vc[r]);
             std::fprintf(stderr, "\n");
         }

@@ -29,8 +29,9 @@ int launch_scale_into(hipStream_t st, int N, int R, size_t instride, size_t outs
 template <typename T>
 int launch_inner_init(hipStream_t st, int N, int R, size_t qstride, double* v, double* u, size_t ustride,
                       double* rho, T* lo, const int* active, const double* scale = nullptr);
-// inner_active = active; clear the refinement step counters; count[3] = j
-int launch_iter_begin(hipStream_t st, int R, const int* active, int* inner_active, int* count, int j);
+// inner_active = active; clear the refinement step counters; count[3] = j; rprev = 1
+int launch_iter_begin(hipStream_t st, int R, const int* active, int* inner_active, int* count, int j,
+                      double* rprev);
 template <typename T>
 int launch_inner_update(hipStream_t st, LevelView<double> L, cdouble tau, int R, const T* e, double* u,
                         size_t ustride, const int* jcol, double* rho, T* lo, double* part, const int* inner_active);
@@ -40,9 +41,11 @@ int launch_inner_update(hipStream_t st, LevelView<double> L, cdouble tau, int R,
 int launch_true_residual_cols(hipStream_t st, LevelView<double> L, int R, int Ks, int jmax, int mmax,
                               const double* U, size_t ustride, const double* Y, const int* mcols, const double* zs,
                               const double* b, const double* beta, double* KU, double* part, double* out);
+// Stopping test after a refinement step; rprev [R] holds each residual norm before the
+// step, est[0] receives the largest estimate of steps still needed (0 when none refine).
 int launch_inner_finalize(hipStream_t st, int nb, int R, const double* part, const int* active, const double* worst,
-                          double relax_tol, double tol, int inner_max, int* inner_active, int* vcycles,
-                          int* count);
+                          double relax_tol, double tol, int inner_max, int* inner_active, int* vcycles, int* count,
+                          double* rprev, int* est);
 // One CGS2 step for column j: unnormalised q_{j+1} in column j + 1 of Q, Hbar column j, and
 // scale[r] = 1 / ||q_{j+1}|| (applied by the next launch_inner_init).  partn: R * nb doubles.
 int launch_cgs2(hipStream_t st, int N, int R, int j, const double* m, const double* U, size_t ustride, double* Q,

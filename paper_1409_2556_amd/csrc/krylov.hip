@@ -169,12 +169,13 @@ __global__ void k_inner_update(LevelView<double> L, double tr, double ti, const 
 __global__ void k_inner_finalize(int R, int nb, const double* __restrict__ part, const int* __restrict__ active,
                                  const double* __restrict__ worst, double relax_tol, double tol,
                                  int inner_max, int* __restrict__ inner_active, int* __restrict__ vcycles,
-                                 int* __restrict__ count) {
-    __shared__ int cnt, any;
+                                 int* __restrict__ count, double* __restrict__ rprev, int* __restrict__ est) {
+    __shared__ int cnt, any, more;
     const int step = count[2];  // refinement steps already taken in this outer iteration
     if (threadIdx.x == 0) {
         cnt = 0;
         any = 0;
+        more = 0;
     }
     __syncthreads();
     // one wavefront per right-hand side sums its partial norms
@@ -189,9 +190,20 @@ __global__ void k_inner_finalize(int R, int nb, const double* __restrict__ part,
             double eta = relax_tol / fmax(worst[r], tol);
             eta = fmin(eta, 0.5);
             vcycles[r] += 1;
-            const int again = (sqrt(s) > eta) && (step + 1 < inner_max) && active[r];
+            const double nrm = sqrt(s), prev = rprev[r];
+            rprev[r] = nrm;
+            const int again = (nrm > eta) && (step + 1 < inner_max) && active[r];
             inner_active[r] = again;
-            if (again) atomicAdd(&cnt, 1);
+            if (again) {
+                atomicAdd(&cnt, 1);
+                // steps still needed at the contraction this step showed (an estimate for
+                // sizing the next batch of launches; the test above decides)
+                const double q = prev > 0.0 ? nrm / prev : 1.0;
+                int n = 1;
+                if (q > 0.0 && q < 0.95) n = (int)ceil(log(eta / nrm) / log(q));
+                n = max(1, min(n, inner_max - step - 1));
+                atomicMax(&more, n);
+            }
         }
     }
     __syncthreads();
@@ -199,6 +211,7 @@ __global__ void k_inner_finalize(int R, int nb, const double* __restrict__ part,
         count[0] = cnt;
         if (any) count[1] = step + 1;
         count[2] = step + 1;
+        est[0] = more;
     }
 }
 
@@ -449,8 +462,11 @@ __global__ void k_update_sum(int N, int ncols, const double* __restrict__ Q, siz
 // Start of an outer iteration: every active right-hand side refines, the step counters
 // are cleared and the basis column is set (one launch instead of a copy, a fill and a store).
 __global__ void k_iter_begin(int R, const int* __restrict__ active, int* __restrict__ inner_active,
-                             int* __restrict__ count, int j) {
-    for (int r = threadIdx.x; r < R; r += blockDim.x) inner_active[r] = active[r];
+                             int* __restrict__ count, int j, double* __restrict__ rprev) {
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+        inner_active[r] = active[r];
+        rprev[r] = 1.0;  // ||v_j||: the residual before the first step
+    }
     if (threadIdx.x == 0) {
         count[1] = 0;
         count[2] = 0;
@@ -985,8 +1001,9 @@ template int launch_inner_init<double>(hipStream_t, int, int, size_t, double*, d
 template int launch_inner_init<float>(hipStream_t, int, int, size_t, double*, double*, size_t, double*,
                                       float*, const int*, const double*);
 
-int launch_iter_begin(hipStream_t st, int R, const int* active, int* inner_active, int* count, int j) {
-    k_iter_begin<<<1, 256, 0, st>>>(R, active, inner_active, count, j);
+int launch_iter_begin(hipStream_t st, int R, const int* active, int* inner_active, int* count, int j,
+                      double* rprev) {
+    k_iter_begin<<<1, 256, 0, st>>>(R, active, inner_active, count, j, rprev);
     LT_HIP(hipGetLastError());
     return 0;
 }
@@ -1006,9 +1023,10 @@ template int launch_inner_update<float>(hipStream_t, LevelView<double>, cdouble,
                                         size_t, const int*, double*, float*, double*, const int*);
 
 int launch_inner_finalize(hipStream_t st, int nb, int R, const double* part, const int* active, const double* worst,
-                          double relax_tol, double tol, int inner_max, int* inner_active, int* vcycles, int* count) {
+                          double relax_tol, double tol, int inner_max, int* inner_active, int* vcycles, int* count,
+                          double* rprev, int* est) {
     k_inner_finalize<<<1, 1024, 0, st>>>(R, nb, part, active, worst, relax_tol, tol, inner_max, inner_active,
-                                         vcycles, count);
+                                         vcycles, count, rprev, est);
     LT_HIP(hipGetLastError());
     return 0;
 }
