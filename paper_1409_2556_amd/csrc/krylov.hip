@@ -181,18 +181,22 @@ __global__ void k_inner_finalize(int R, int nb, const double* __restrict__ part,
     // one wavefront per right-hand side sums its partial norms
     const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     for (int r = threadIdx.x >> 6; r < R; r += nw) {
-        if (!inner_active[r]) continue;
+        // every load is issued before any of them is used (one memory latency, not three)
+        const int on = inner_active[r];
         double s = 0;
         for (int q = lane; q < nb; q += 64) s += part[(size_t)r * nb + q];
+        const double wr = worst[r], prev = rprev[r];
+        const int act = active[r], vc = vcycles[r];
         s = wave_sum(s);
+        if (!on) continue;
         if (lane == 0) {
             any = 1;
-            double eta = relax_tol / fmax(worst[r], tol);
+            double eta = relax_tol / fmax(wr, tol);
             eta = fmin(eta, 0.5);
-            vcycles[r] += 1;
-            const double nrm = sqrt(s), prev = rprev[r];
+            vcycles[r] = vc + 1;
+            const double nrm = sqrt(s);
             rprev[r] = nrm;
-            const int again = (nrm > eta) && (step + 1 < inner_max) && active[r];
+            const int again = (nrm > eta) && (step + 1 < inner_max) && act;
             inner_active[r] = again;
             if (again) {
                 atomicAdd(&cnt, 1);
@@ -322,51 +326,43 @@ __global__ void k_mdot(int N, int ncols, const double* __restrict__ Q, size_t qs
                        const double* __restrict__ m, const double* __restrict__ u, size_t ustride,
                        const double* __restrict__ s, size_t sstride, double* __restrict__ part, int pstride,
                        const int* __restrict__ active) {
-    int r = blockIdx.y;
+    // blockIdx.z picks a group of kGroup basis columns (groups run side by side rather than
+    // in turn); group 0 also accumulates ||s||^2
+    const int r = blockIdx.y;
     if (active && !active[r]) return;
+    const int c0 = blockIdx.z * kGroup;
     const double* Qr = Q + qstride * r;
     const double* ur = u ? u + ustride * r : nullptr;
     const double* sr = s ? s + sstride * r : nullptr;
     double* pr = part + ((size_t)r * gridDim.x + blockIdx.x) * pstride;
     const size_t NN = N;
-    // norm of s
-    {
-        double v[1] = {0};
-        for (int i = blockIdx.x * kB + threadIdx.x; i < N; i += gridDim.x * kB) {
-            c64 sv = load_s(m, ur, sr, NN, i);
-            v[0] += sv.re * sv.re + sv.im * sv.im;
-        }
-        double o[1];
-        block_reduce<1>(v, o);
-        if (threadIdx.x == 0) {
-            pr[2 * ncols] = o[0];
-            pr[2 * ncols + 1] = 0;
+    double v[2 * kGroup + 1];
+#pragma unroll
+    for (int k = 0; k < 2 * kGroup + 1; ++k) v[k] = 0;
+    for (int i = blockIdx.x * kB + threadIdx.x; i < N; i += gridDim.x * kB) {
+        c64 sv = load_s(m, ur, sr, NN, i);
+        v[2 * kGroup] += sv.re * sv.re + sv.im * sv.im;
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+            int c = c0 + k;
+            if (c < ncols) {
+                const double* q = Qr + 2 * NN * c;
+                c64 p = cmc({q[i], q[i + NN]}, sv);
+                v[2 * k] += p.re;
+                v[2 * k + 1] += p.im;
+            }
         }
     }
-    for (int c0 = 0; c0 < ncols; c0 += kGroup) {
-        double v[2 * kGroup];
-#pragma unroll
-        for (int k = 0; k < 2 * kGroup; ++k) v[k] = 0;
-        for (int i = blockIdx.x * kB + threadIdx.x; i < N; i += gridDim.x * kB) {
-            c64 sv = load_s(m, ur, sr, NN, i);
-#pragma unroll
-            for (int k = 0; k < kGroup; ++k) {
-                int c = c0 + k;
-                if (c < ncols) {
-                    const double* q = Qr + 2 * NN * c;
-                    c64 p = cmc({q[i], q[i + NN]}, sv);
-                    v[2 * k] += p.re;
-                    v[2 * k + 1] += p.im;
-                }
-            }
+    double o[2 * kGroup + 1];
+    block_reduce<2 * kGroup + 1>(v, o);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < kGroup && c0 + k < ncols; ++k) {
+            pr[2 * (c0 + k)] = o[2 * k];
+            pr[2 * (c0 + k) + 1] = o[2 * k + 1];
         }
-        double o[2 * kGroup];
-        block_reduce<2 * kGroup>(v, o);
-        if (threadIdx.x == 0) {
-            for (int k = 0; k < kGroup && c0 + k < ncols; ++k) {
-                pr[2 * (c0 + k)] = o[2 * k];
-                pr[2 * (c0 + k) + 1] = o[2 * k + 1];
-            }
+        if (blockIdx.z == 0) {
+            pr[2 * ncols] = o[2 * kGroup];
+            pr[2 * ncols + 1] = 0;
         }
     }
 }
@@ -727,9 +723,16 @@ __global__ __launch_bounds__(256) void k_true_res_cols(LevelView<double> L, int 
     const size_t N = L.N;
     const double* br = b + 2 * N * r;
     const double* Yr = Y + (size_t)r * jmax * 2 * Ks;
-    double v[kTrK];
+    double v[kTrK], zr[kTrK], zi[kTrK];
 #pragma unroll
-    for (int c = 0; c < kTrK; ++c) v[c] = 0;
+    for (int c = 0; c < kTrK; ++c) {
+        v[c] = 0;
+        const int cc = min(c, kc - 1);
+        zr[c] = zs[2 * (k0 + cc)];
+        zi[c] = zs[2 * (k0 + cc) + 1];
+    }
+    const double* Ur = U + ustride * r;
+    const double* KUr = KU + kstride * r;
     for (int i = blockIdx.x * kB + threadIdx.x; i < L.N; i += gridDim.x * kB) {
         double ar[kTrK], ai[kTrK];
         const double b0 = br[i], b1 = br[i + N];
@@ -739,17 +742,29 @@ __global__ __launch_bounds__(256) void k_true_res_cols(LevelView<double> L, int 
             ai[c] = b1;
         }
         const double mi = L.m[i];
+        // column j + 1 is loaded while column j is used
+        double nu0 = 0, nu1 = 0, nk0 = 0, nk1 = 0;
+        if (m > 0) {
+            nu0 = Ur[i];
+            nu1 = Ur[i + N];
+            nk0 = KUr[i];
+            nk1 = KUr[i + N];
+        }
         for (int j = 0; j < m; ++j) {
-            const double* u = U + ustride * r + 2 * N * j;
-            const double* ku = KU + kstride * r + 2 * N * j;
-            const double ur = mi * u[i], ui = mi * u[i + N], kr = ku[i], ki = ku[i + N];  // m u, K u
+            const double ur = mi * nu0, ui = mi * nu1, kr = nk0, ki = nk1;  // m u, K u
+            if (j + 1 < m) {
+                const size_t o = 2 * N * (j + 1) + i;
+                nu0 = Ur[o];
+                nu1 = Ur[o + N];
+                nk0 = KUr[o];
+                nk1 = KUr[o + N];
+            }
             const double* y = Yr + (size_t)j * 2 * Ks + 2 * k0;
 #pragma unroll
             for (int c = 0; c < kTrK; ++c) {
                 const int cc = min(c, kc - 1);
-                const double zr = zs[2 * (k0 + cc)], zi = zs[2 * (k0 + cc) + 1];
                 // t = K u + z m u;  acc -= y t
-                const double tr = kr + (zr * ur - zi * ui), ti = ki + (zr * ui + zi * ur);
+                const double tr = kr + (zr[c] * ur - zi[c] * ui), ti = ki + (zr[c] * ui + zi[c] * ur);
                 const double yr = y[2 * cc], yi = y[2 * cc + 1];
                 ar[c] -= yr * tr - yi * ti;
                 ai[c] -= yr * ti + yi * tr;
@@ -774,14 +789,18 @@ __global__ __launch_bounds__(256) void k_true_res_cols(LevelView<double> L, int 
     }
 }
 
+// one wavefront per (right-hand side, shift)
 __global__ void k_true_res_cols_finalize(int R, int Ks, int nb, const double* __restrict__ part,
                                          const double* __restrict__ beta, double* __restrict__ out) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int idx = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
     if (idx >= R * Ks) return;
     double s = 0;
-    for (int q = 0; q < nb; ++q) s += part[(size_t)idx * nb + q];
-    const double bt = beta[idx / Ks];
-    out[idx] = bt > 0 ? sqrt(s) / bt : 0.0;
+    for (int q = lane; q < nb; q += 64) s += part[(size_t)idx * nb + q];
+    s = wave_sum(s);
+    if (lane == 0) {
+        const double bt = beta[idx / Ks];
+        out[idx] = bt > 0 ? sqrt(s) / bt : 0.0;
+    }
 }
 
 int launch_true_residual_cols(hipStream_t st, LevelView<double> L, int R, int Ks, int jmax, int mmax,
@@ -791,7 +810,7 @@ int launch_true_residual_cols(hipStream_t st, LevelView<double> L, int R, int Ks
     if (mmax > 0) {
         k_apply_cols<<<dim3((unsigned)((L.N + kB - 1) / kB), mmax, R), kB, 0, st>>>(L, U, ustride, mcols, KU, kstride);
     }
-    const int nb = reduce_blocks(L.N, R);
+    const int nb = true_res_blocks(L.N);
     // shifts per pass: a multiple of 4 up to 32 that covers Ks with the fewest computed lanes
     int best = 32, cost = 1 << 30;
     for (int w = 4; w <= 32; w += 4) {
@@ -818,7 +837,8 @@ int launch_true_residual_cols(hipStream_t st, LevelView<double> L, int R, int Ks
         }
 #undef LT_TR
     }
-    k_true_res_cols_finalize<<<(unsigned)((R * Ks + kB - 1) / kB), kB, 0, st>>>(R, Ks, nb, part, beta, out);
+    k_true_res_cols_finalize<<<(unsigned)(((size_t)R * Ks * 64 + kB - 1) / kB), kB, 0, st>>>(R, Ks, nb, part, beta,
+                                                                                              out);
     LT_HIP(hipGetLastError());
     return 0;
 }
@@ -972,6 +992,12 @@ int reduce_blocks(int N, int R) {
     return nb;
 }
 
+int true_res_blocks(int N) {
+    // one cell per thread up to 1024 blocks per right-hand side: the column loop is
+    // latency-bound, so occupancy matters more than the number of partial sums
+    return std::max(1, std::min(1024, (N + kB - 1) / kB));
+}
+
 int launch_norms(hipStream_t st, int N, int R, size_t vstride, const double* x, double* part, double* out,
                  const int* active) {
     int nb = reduce_blocks(N, R);
@@ -1041,12 +1067,13 @@ int launch_cgs2(hipStream_t st, int N, int R, int j, const double* m, const doub
     const double* u = U + 2 * (size_t)N * j;
     double* qn = Q + 2 * (size_t)N * (j + 1);
     dim3 g(nb, R);
+    const dim3 gd(nb, R, (ncols + kGroup - 1) / kGroup);
     const size_t shm = sizeof(double) * 2 * (ncols + 1);
     // first pass: coefficients of M u_j, then its projection; second pass on the result
-    k_mdot<<<g, kB, 0, st>>>(N, ncols, Q, qstride, m, u, ustride, nullptr, 0, part, pstride, active);
+    k_mdot<<<gd, kB, 0, st>>>(N, ncols, Q, qstride, m, u, ustride, nullptr, 0, part, pstride, active);
     k_update_sum<<<g, kB, shm, st>>>(N, ncols, Q, qstride, m, u, ustride, nullptr, 0, part, nb, pstride, c1, cstride,
                                      qn, qstride, nullptr, active);
-    k_mdot<<<g, kB, 0, st>>>(N, ncols, Q, qstride, nullptr, nullptr, 0, qn, qstride, part, pstride, active);
+    k_mdot<<<gd, kB, 0, st>>>(N, ncols, Q, qstride, nullptr, nullptr, 0, qn, qstride, part, pstride, active);
     k_update_sum<<<g, kB, shm, st>>>(N, ncols, Q, qstride, nullptr, nullptr, 0, qn, qstride, part, nb, pstride, c2,
                                      cstride, qn, qstride, partn, active);
     // Hessenberg column and 1 / ||q_{j+1}||; the next iteration's first read applies the scale

@@ -426,43 +426,91 @@ __global__ __launch_bounds__(256) void k_post2d_refine(LevelView<T> L, LevelView
 template <typename T> struct CBCell {
     T tw, te, ts, tn, tb, tt;  // faces to the -x, +x, -y, +y, -z, +z neighbours
     T dr, di;                  // D + tau m
+    T ir, ii;                  // 1 / (D + tau m)
     T br, bi;                  // right-hand side of this level
+    int x, y, z;               // coordinates of the cell
     int flags;                 // bits 0-5: neighbour exists at +x, -x, +y, -y, +z, -z; bit 6: colour
 };
 
-template <typename T>
-__device__ __forceinline__ void cb_load_cell(const CBLevel<T>& L, T tr, T ti, int i, CBCell<T>& c) {
-    const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
-    const int sy = L.nx, sz = L.nx * L.ny;
+// Coefficients of cell i as loaded, before walls are applied.  Every address is valid
+// whatever the cell (clamped), so the loads of all levels are issued before any is used.
+template <typename T> struct CBRaw {
+    T tx, txw, ty, tys, tz, tzb, d, m;
+};
+
+// D3: the levels have more than one layer (2D grids skip every z term)
+template <typename T, bool D3>
+__device__ __forceinline__ void cb_load_raw(const CBLevel<T>& L, int i, CBRaw<T>& q) {
+    const int k = min(i, L.N - 1), sy = L.nx, sz = L.nx * L.ny;
+    q.tx = L.Tx[k];
+    q.txw = L.Tx[max(k - 1, 0)];
+    q.ty = L.Ty[k];
+    q.tys = L.Ty[max(k - sy, 0)];
+    if (D3) {
+        q.tz = L.Tz[k];
+        q.tzb = L.Tz[max(k - sz, 0)];
+    }
+    q.d = L.D[k];
+    q.m = L.m[k];
+}
+
+template <typename T, bool D3>
+__device__ __forceinline__ void cb_make_cell(const CBLevel<T>& L, const CBRaw<T>& q, T tr, T ti, int i,
+                                             CBCell<T>& c) {
+    const int x = i % L.nx, y = (i / L.nx) % L.ny, z = D3 ? i / (L.nx * L.ny) : 0;
+    c.x = x;
+    c.y = y;
+    c.z = z;
     c.flags = (x + 1 < L.nx) | ((x > 0) << 1) | ((y + 1 < L.ny) << 2) | ((y > 0) << 3) | ((z + 1 < L.nz) << 4) |
               ((z > 0) << 5) | (((x + y + z) & 1) << 6);
-    // walls have zero couplings (and no neighbour load)
-    const T tx = L.Tx[i], txw = L.Tx[x > 0 ? i - 1 : i], ty = L.Ty[i], tys = L.Ty[y > 0 ? i - sy : i];
-    const T tz = L.Tz[i], tzb = L.Tz[z > 0 ? i - sz : i];
-    const T d = L.D[i], m = L.m[i];
-    c.te = (x + 1 < L.nx) ? tx : T(0);
-    c.tw = (x > 0) ? txw : T(0);
-    c.tn = (y + 1 < L.ny) ? ty : T(0);
-    c.ts = (y > 0) ? tys : T(0);
-    c.tt = (z + 1 < L.nz) ? tz : T(0);
-    c.tb = (z > 0) ? tzb : T(0);
-    c.dr = d + tr * m;
-    c.di = ti * m;
+    // walls have zero couplings
+    c.te = (x + 1 < L.nx) ? q.tx : T(0);
+    c.tw = (x > 0) ? q.txw : T(0);
+    c.tn = (y + 1 < L.ny) ? q.ty : T(0);
+    c.ts = (y > 0) ? q.tys : T(0);
+    if (D3) {
+        c.tt = (z + 1 < L.nz) ? q.tz : T(0);
+        c.tb = (z > 0) ? q.tzb : T(0);
+    } else {
+        c.tt = c.tb = T(0);
+    }
+    c.dr = q.d + tr * q.m;
+    c.di = ti * q.m;
+    const T dd = c.dr * c.dr + c.di * c.di;
+    c.ir = c.dr / dd;
+    c.ii = -c.di / dd;
 }
 
 // off = sum of couplings times neighbour values (a missing neighbour reads the cell itself with weight 0)
-template <typename T>
+template <typename T, bool D3>
 __device__ __forceinline__ void cb_off(const CBLevel<T>& L, const CBCell<T>& c, const T* xr, const T* xi, int i,
                                        T& ore, T& oim) {
-    const int sy = L.nx, sz = L.nx * L.ny, f = c.flags;
+    const int sy = L.nx, f = c.flags;
     const int e = (f & 1) ? i + 1 : i, w = (f & 2) ? i - 1 : i;
     const int n = (f & 4) ? i + sy : i, s = (f & 8) ? i - sy : i;
-    const int t = (f & 16) ? i + sz : i, b = (f & 32) ? i - sz : i;
-    ore = c.te * xr[e] + c.tw * xr[w] + c.tn * xr[n] + c.ts * xr[s] + c.tt * xr[t] + c.tb * xr[b];
-    oim = c.te * xi[e] + c.tw * xi[w] + c.tn * xi[n] + c.ts * xi[s] + c.tt * xi[t] + c.tb * xi[b];
+    ore = c.te * xr[e] + c.tw * xr[w] + c.tn * xr[n] + c.ts * xr[s];
+    oim = c.te * xi[e] + c.tw * xi[w] + c.tn * xi[n] + c.ts * xi[s];
+    if (D3) {
+        const int sz = L.nx * L.ny;
+        const int t = (f & 16) ? i + sz : i, b = (f & 32) ? i - sz : i;
+        ore += c.tt * xr[t] + c.tb * xr[b];
+        oim += c.tt * xi[t] + c.tb * xi[b];
+    }
 }
 
-template <typename T, int NLM>
+// one Gauss-Seidel update of cell i: x = (b + off) / (D + tau m)
+template <typename T, bool D3>
+__device__ __forceinline__ void cb_relax(const CBLevel<T>& L, const CBCell<T>& c, T* xr, T* xi, int i) {
+    T ore, oim;
+    cb_off<T, D3>(L, c, xr, xi, i, ore, oim);
+    const T nr = c.br + ore, ni = c.bi + oim;
+    xr[i] = nr * c.ir - ni * c.ii;
+    xi[i] = nr * c.ii + ni * c.ir;
+}
+
+constexpr int kCBInvRegs = 8;  // inverse entries per lane held in registers from the kernel's start
+
+template <typename T, int NLM, bool D3>
 __global__ __launch_bounds__(1024) void k_coarse_block(CBMeta<T> M, T tr, T ti, const T* __restrict__ bin,
                                                        T* __restrict__ xout, const int* __restrict__ active) {
     const int r = blockIdx.x;
@@ -471,10 +519,39 @@ __global__ __launch_bounds__(1024) void k_coarse_block(CBMeta<T> M, T tr, T ti, 
     T* sm = reinterpret_cast<T*>(smem_raw);  // per level: xr, xi, rr, ri at 4 * off
     const int i = threadIdx.x;
     const int nl = M.nl;
+    // Dense solve of the coarsest level, x = inv * r: P consecutive lanes share a row (P a
+    // power of two, at most 64, as many as the block allows).  Each lane's entries of the
+    // inverse are loaded now, so their latency overlaps the descent.
+    int nc = 0;  // (compile-time indices only: a runtime index into the kernel argument
+                 // struct becomes a chain of dependent scalar loads)
+#pragma unroll
+    for (int l = 0; l < NLM; ++l)
+        if (l == nl - 1) nc = M.L[l].N;
+    int P = 1, lp = 0;
+    while (P < 64 && 2 * P * nc <= (int)blockDim.x) {
+        P *= 2;
+        ++lp;
+    }
+    const int row = i >> lp, seg = i & (P - 1);
+    const bool inv_regs = M.inv && (nc + P - 1) / P <= kCBInvRegs;
+    T ia[kCBInvRegs], ib[kCBInvRegs];
+    if (inv_regs && row < nc) {
+        const T* rowp = M.inv + 2 * (size_t)nc * row;
+#pragma unroll
+        for (int t = 0; t < kCBInvRegs; ++t) {
+            const int j = seg + t * P;
+            ia[t] = j < nc ? rowp[2 * j] : T(0);
+            ib[t] = j < nc ? rowp[2 * j + 1] : T(0);
+        }
+    }
+    CBRaw<T> raw[NLM];
+#pragma unroll
+    for (int l = 0; l < NLM; ++l)
+        if (l < nl) cb_load_raw<T, D3>(M.L[l], i, raw[l]);
     CBCell<T> c[NLM];
 #pragma unroll
     for (int l = 0; l < NLM; ++l)
-        if (l < nl && i < M.L[l].N) cb_load_cell<T>(M.L[l], tr, ti, i, c[l]);
+        if (l < nl && i < M.L[l].N) cb_make_cell<T, D3>(M.L[l], raw[l], tr, ti, i, c[l]);
     {
         const int n0 = M.L[0].N;
         if (i < n0) {
@@ -500,34 +577,33 @@ __global__ __launch_bounds__(1024) void k_coarse_block(CBMeta<T> M, T tr, T ti, 
         const int par = own ? (c[l].flags >> 6) & 1 : 0;
         for (int sw = 0; sw < M.nu1; ++sw)
             for (int col = 0; col < 2; ++col) {
-                if (own && par == col) {
-                    T ore, oim;
-                    cb_off<T>(L, c[l], xr, xi, i, ore, oim);
-                    const T nr = c[l].br + ore, ni = c[l].bi + oim;
-                    const T dd = c[l].dr * c[l].dr + c[l].di * c[l].di;
-                    xr[i] = (nr * c[l].dr + ni * c[l].di) / dd;
-                    xi[i] = (ni * c[l].dr - nr * c[l].di) / dd;
-                }
+                if (own && par == col) cb_relax<T, D3>(L, c[l], xr, xi, i);
                 __syncthreads();
             }
         if (own) {
             T ore, oim;
-            cb_off<T>(L, c[l], xr, xi, i, ore, oim);
+            cb_off<T, D3>(L, c[l], xr, xi, i, ore, oim);
             rr[i] = c[l].br - (c[l].dr * xr[i] - c[l].di * xi[i] - ore);
             ri[i] = c[l].bi - (c[l].dr * xi[i] + c[l].di * xr[i] - oim);
         }
         __syncthreads();
         const CBLevel<T>& C = M.L[l + 1];
         if (i < C.N) {
-            const int X = i % C.nx, Y = (i / C.nx) % C.ny, Z = i / (C.nx * C.ny);
+            // the aggregate of coarse cell i: up to two fine cells along each halved axis
+            const int f0 = (c[l + 1].x << C.cox) + L.nx * ((c[l + 1].y << C.coy) + L.ny * (c[l + 1].z << C.coz));
+            const int sy = L.nx, sz = L.nx * L.ny;
             T ar = 0, ai = 0;
-            for (int z = Z << C.coz; z <= (Z << C.coz) + C.coz; ++z)
-                for (int y = Y << C.coy; y <= (Y << C.coy) + C.coy; ++y)
-                    for (int x = X << C.cox; x <= (X << C.cox) + C.cox; ++x) {
-                        const int f = x + L.nx * (y + L.ny * z);
-                        ar += rr[f];
-                        ai += ri[f];
-                    }
+#pragma unroll
+            for (int dz = 0; dz < (D3 ? 2 : 1); ++dz)
+#pragma unroll
+                for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 2; ++dx)
+                        if (dz <= C.coz && dy <= C.coy && dx <= C.cox) {
+                            const int f = f0 + dx + sy * dy + sz * dz;
+                            ar += rr[f];
+                            ai += ri[f];
+                        }
             c[l + 1].br = ar;
             c[l + 1].bi = ai;
             T* q = sm + 4 * (size_t)C.off;
@@ -552,20 +628,26 @@ __global__ __launch_bounds__(1024) void k_coarse_block(CBMeta<T> M, T tr, T ti, 
                 ri[i] = c[l].bi;
             }
             __syncthreads();
-            // dense solve x = inv * r: P consecutive lanes share a row (P a power of two, at
-            // most 64, as many as the block allows), so every load of the inverse is in
-            // flight at once; the partial sums meet in a shuffle reduction
+            // the partial sums of a row's P lanes meet in a shuffle reduction
             const int n = L.N;
-            int P = 1;
-            while (P < 64 && 2 * P * n <= (int)blockDim.x) P *= 2;
-            const int row = i / P, seg = i % P;
             T ar = 0, ai = 0;
             if (row < n) {
-                const T* rowp = M.inv + 2 * (size_t)n * row;
-                for (int j = seg; j < n; j += P) {
-                    const T a = rowp[2 * j], bb = rowp[2 * j + 1];
-                    ar += a * rr[j] - bb * ri[j];
-                    ai += a * ri[j] + bb * rr[j];
+                if (inv_regs) {
+#pragma unroll
+                    for (int t = 0; t < kCBInvRegs; ++t) {
+                        const int j = seg + t * P;
+                        if (j < n) {
+                            ar += ia[t] * rr[j] - ib[t] * ri[j];
+                            ai += ia[t] * ri[j] + ib[t] * rr[j];
+                        }
+                    }
+                } else {
+                    const T* rowp = M.inv + 2 * (size_t)n * row;
+                    for (int j = seg; j < n; j += P) {
+                        const T a = rowp[2 * j], bb = rowp[2 * j + 1];
+                        ar += a * rr[j] - bb * ri[j];
+                        ai += a * ri[j] + bb * rr[j];
+                    }
                 }
             }
             for (int o = P / 2; o > 0; o >>= 1) {
@@ -581,14 +663,7 @@ __global__ __launch_bounds__(1024) void k_coarse_block(CBMeta<T> M, T tr, T ti, 
             const int par = own ? (c[l].flags >> 6) & 1 : 0;
             for (int sw = 0; sw < M.coarse_sweeps; ++sw)
                 for (int col = 0; col < 2; ++col) {
-                    if (own && par == col) {
-                        T ore, oim;
-                        cb_off<T>(L, c[l], xr, xi, i, ore, oim);
-                        const T nr = c[l].br + ore, ni = c[l].bi + oim;
-                        const T dd = c[l].dr * c[l].dr + c[l].di * c[l].di;
-                        xr[i] = (nr * c[l].dr + ni * c[l].di) / dd;
-                        xi[i] = (ni * c[l].dr - nr * c[l].di) / dd;
-                    }
+                    if (own && par == col) cb_relax<T, D3>(L, c[l], xr, xi, i);
                     __syncthreads();
                 }
         }
@@ -605,7 +680,7 @@ __global__ __launch_bounds__(1024) void k_coarse_block(CBMeta<T> M, T tr, T ti, 
         const T* ei = er + C.N;
         const bool own = i < L.N;
         if (own) {
-            const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+            const int x = c[l].x, y = c[l].y, z = c[l].z;
             int ix[2], iy[2], iz[2];
             T wx[2], wy[2], wz[2];
             const int nxp = prolong_axis<T>(x, C.nx, C.cox, M.ghost[0], M.ghost[1], ix, wx);
@@ -627,14 +702,7 @@ __global__ __launch_bounds__(1024) void k_coarse_block(CBMeta<T> M, T tr, T ti, 
         const int par = own ? (c[l].flags >> 6) & 1 : 0;
         for (int sw = 0; sw < M.nu2; ++sw)
             for (int col = 1; col >= 0; --col) {
-                if (own && par == col) {
-                    T ore, oim;
-                    cb_off<T>(L, c[l], xr, xi, i, ore, oim);
-                    const T nr = c[l].br + ore, ni = c[l].bi + oim;
-                    const T dd = c[l].dr * c[l].dr + c[l].di * c[l].di;
-                    xr[i] = (nr * c[l].dr + ni * c[l].di) / dd;
-                    xi[i] = (ni * c[l].dr - nr * c[l].di) / dd;
-                }
+                if (own && par == col) cb_relax<T, D3>(L, c[l], xr, xi, i);
                 __syncthreads();
             }
     }
@@ -755,10 +823,19 @@ int launch_coarse_block(hipStream_t st, const CBMeta<T>& M, T tr, T ti, const T*
     }
     int threads = ((M.L[0].N + 63) / 64) * 64;
     if (threads < 64) threads = 64;
-    if (M.nl <= 3)
-        k_coarse_block<T, 3><<<R, threads, shm, st>>>(M, tr, ti, bin, xout, active);
-    else
-        k_coarse_block<T, kMaxCBLevels><<<R, threads, shm, st>>>(M, tr, ti, bin, xout, active);
+    bool d3 = false;
+    for (int l = 0; l < M.nl; ++l) d3 = d3 || M.L[l].nz > 1;
+    if (M.nl <= 3) {
+        if (d3)
+            k_coarse_block<T, 3, true><<<R, threads, shm, st>>>(M, tr, ti, bin, xout, active);
+        else
+            k_coarse_block<T, 3, false><<<R, threads, shm, st>>>(M, tr, ti, bin, xout, active);
+    } else {
+        if (d3)
+            k_coarse_block<T, kMaxCBLevels, true><<<R, threads, shm, st>>>(M, tr, ti, bin, xout, active);
+        else
+            k_coarse_block<T, kMaxCBLevels, false><<<R, threads, shm, st>>>(M, tr, ti, bin, xout, active);
+    }
     LT_HIP(hipGetLastError());
     return 0;
 }
