@@ -72,6 +72,8 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-times", type=int, default=10)
     ap.add_argument("--no-tune", action="store_true", help="keep the default smoother tile shapes")
+    ap.add_argument("--groups", type=int, default=2,
+                    help="solve the sources as this many concurrent groups, one handle and stream each")
     ap.add_argument("--workload", choices=["C2", "C3", "C5"], default="C2",
                     help="C2: the 256x256 workload (default); C3: sensitivities (lt_adjoint) of the "
                          "64x64x32 workload; C5: the batch of six uneven 2D/3D grids in one lt_solve_batch call")
@@ -97,21 +99,47 @@ def _handle(lt, p, tune, nvec):
     return h, tiles
 
 
-def _run_variant(lt, h, p, opts, steps, warmup, profile=0):
+def _merge_stats(sts):
+    """Stats of one solve split over source groups (each group is an independent lt_solve)."""
+    if len(sts) == 1:
+        return sts[0]
+    return {"rc": max(s["rc"] for s in sts), "iters_max": max(s["iters_max"] for s in sts),
+            "vcycles": sum(s["vcycles"] for s in sts), "true_relres_max": max(s["true_relres_max"] for s in sts),
+            "net_applied": sum(s["net_applied"] for s in sts),
+            "net_disabled_at": max(s["net_disabled_at"] for s in sts)}
+
+
+def _solve_groups(lt, hs, p, opts, phi):
+    """All sources in one step: one lt_solve, or with several handles one lt_solve_batch call
+    whose items (contiguous source groups, each on its handle's stream) run concurrently."""
+    if len(hs) == 1:
+        _, st = lt.lt_solve(hs[0], p.sources, p.q, p.times, p.nz_contour, p.receivers, opts, phi_out=phi)
+        return st
+    cuts = np.array_split(np.arange(len(p.sources)), len(hs))
+    items = [dict(handle=h, sources=p.sources[c], q=p.q, times=p.times, nz=p.nz_contour, receivers=p.receivers,
+                  opts=opts, phi_out=phi[c[0]:c[-1] + 1]) for h, c in zip(hs, cuts)]
+    _, sts, rc = lt.lt_solve_batch(items)
+    st = _merge_stats(sts)
+    st["rc"] = max(st["rc"], rc)
+    return st
+
+
+def _run_variant(lt, hs, p, opts, steps, warmup, profile=0):
     """Warm up, then time `steps` solves.  With `profile`, the same `steps` solves
-    are run once more with the library timing every launch of the profiled
-    kernel with HIP events on its own stream and counting its algorithmic bytes
-    (kept out of the headline timing so the events do not slow it)."""
+    are run once more, on the first handle alone, with the library timing every
+    launch of the profiled kernel with HIP events on its own stream and counting
+    its algorithmic bytes (kept out of the headline timing so the events do not slow it)."""
     import torch
     phi = torch.empty((len(p.sources), len(p.receivers), len(p.times)), dtype=torch.float64, device="cuda")
+    h = hs[0]
     st = None
     opts.profile = 0
     for _ in range(warmup):
-        _, st = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, opts, phi_out=phi)
+        st = _solve_groups(lt, hs, p, opts, phi)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        _, st = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, opts, phi_out=phi)
+        st = _solve_groups(lt, hs, p, opts, phi)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     prof = {"launches": 0, "ms": 0.0, "bytes": 0.0}
@@ -167,6 +195,15 @@ def main():
 
     torch.cuda.set_device(0)
     h, tiles = _handle(lt, p, not args.no_tune, len(p.sources))
+    groups = max(1, min(args.groups, len(p.sources)))
+    hs = [h]
+    for _ in range(groups - 1):
+        # the other groups' handles take the first handle's tiles (tuned for the full batch)
+        hg, _ = _handle(lt, p, False, len(p.sources))
+        if tiles:
+            for name, prec in (("fp64", lt.LT_PREC_FP64), ("mixed", lt.LT_PREC_MIXED)):
+                lt.lt_set_tiles(hg, prec, [_tile_id(lt, t) for t in tiles[name]["tiles"]])
+        hs.append(hg)
     pairs = len(p.sources) * len(p.times) * (p.nz_contour // 2)
     res = {}
     variants = [("fp64", lt.LT_PREC_FP64, args.tol_fp64), ("mixed", lt.LT_PREC_MIXED, args.tol_mixed),
@@ -186,13 +223,21 @@ def main():
                             "targets from lt_precond_solve"}
         print(f"[bench] trained U-Net: {training['seconds']:.1f} s, loss {training['final_loss_mean20']:.3f}",
               file=sys.stderr, flush=True)
-        lt.lt_unet_attach(h, net)
+        # each group's handle gets its own copy of the trained network (a network's
+        # workspace serves one solve at a time)
+        nets = [net]
+        for _ in hs[1:]:
+            cp = lt.UNet(seed=0)
+            cp.set_params(net.get_params())
+            nets.append(cp)
+        for hg, ng in zip(hs, nets):
+            lt.lt_unet_attach(hg, ng)
     prof_name = "mixed" if any(v[0] == "mixed" for v in variants) else variants[0][0]
     for name, prec, tol in variants:
         opts = lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau, relax=args.relax,
                             precond=lt.LT_PRECOND_UNET_GMG if name == "learned" else lt.LT_PRECOND_GMG)
         prof_kind = lt.LT_PROF_POST_FINE if name == prof_name else 0
-        dt, st, phi, prof = _run_variant(lt, h, p, opts, args.steps, args.warmup, prof_kind)
+        dt, st, phi, prof = _run_variant(lt, hs, p, opts, args.steps, args.warmup, prof_kind)
         res[name] = dict(dt=dt, st=st, phi=phi, tol=tol, prof=prof)
         print(f"[bench] {name}: {dt * 1e3:.2f} ms/step, {pairs / dt:.0f} solves/s, iters {st['iters_max']}, "
               f"vcycles {st['vcycles']}, true residual {st['true_relres_max']:.2e}, net applied "
@@ -250,7 +295,7 @@ def main():
                    "pairs": pairs, "tol": head["tol"], "relax": args.relax, "variant": hname,
                    "precision": "FP32 V-cycle, FP64 outer",
                    "iters": head["st"]["iters_max"], "vcycles": head["st"]["vcycles"],
-                   "smoother_tiles": tiles},
+                   "source_groups": groups, "smoother_tiles": tiles},
         "variants": {
             name: {"solves_per_s": pairs / r["dt"], "ms_per_step": r["dt"] * 1e3, "tol": r["tol"],
                    "iters": r["st"]["iters_max"], "vcycles": r["st"]["vcycles"],
@@ -265,9 +310,22 @@ def main():
         out["vs_plain_fp64"] = (pairs / head["dt"]) / (pairs / res["fp64"]["dt"])
     print(json.dumps(out), flush=True)
     if net is not None:
-        lt.lt_unet_attach(h, None)
-        net.close()
-    h.close()
+        for hg in hs:
+            lt.lt_unet_attach(hg, None)
+        for ng in nets:
+            ng.close()
+    for hg in hs:
+        hg.close()
+
+
+def _tile_id(lt, shape):
+    for i in range(16):
+        try:
+            if tuple(lt.lt_tile_shape(i)) == tuple(shape):
+                return i
+        except Exception:
+            break
+    raise ValueError(f"unknown tile shape {shape}")
 
 
 def main_adjoint(args):

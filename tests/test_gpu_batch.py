@@ -94,3 +94,28 @@ def test_batch_rejects_repeated_handle(lt):
         lt.lt_solve_batch([it, it])
     assert e.value.code == lt.LT_EINVAL
     h.close()
+
+
+def test_source_groups_equal_one_solve(lt):
+    """The benchmark's split: the sources of one problem solved as two concurrent groups
+    (two handles on the same grid, one lt_solve_batch call) give, bit for bit, the heads
+    and iteration counts of one lt_solve over all sources -- every right-hand side has
+    its own basis, so grouping changes no arithmetic."""
+    p = wl.make_problem("C2", n=(96, 64), nsrc=6, nrec=5)
+    hs = [device_problem_on_stream(lt, p) for _ in range(2)]
+    o = lt.make_opts(tol=1e-8, precision=lt.LT_PREC_MIXED, n_tau=1, relax=3.0)
+    announce("source groups", p.n)
+    whole, st = lt.lt_solve(hs[0], p.sources, p.q, p.times, p.nz_contour, p.receivers, o)
+    whole = whole.cpu().numpy()
+    phi = torch.empty((len(p.sources), len(p.receivers), len(p.times)), dtype=torch.float64, device="cuda")
+    cuts = [slice(0, 3), slice(3, 6)]
+    items = [dict(handle=h, sources=p.sources[c], q=p.q, times=p.times, nz=p.nz_contour, receivers=p.receivers,
+                  opts=o, phi_out=phi[c]) for h, c in zip(hs, cuts)]
+    for _ in range(2):  # the second call reuses every workspace
+        _, sts, rc = lt.lt_solve_batch(items)
+        assert rc == 0
+        np.testing.assert_array_equal(phi.cpu().numpy(), whole)
+        its = np.concatenate([s["iters_per_rhs"] for s in sts])
+        np.testing.assert_array_equal(its, st["iters_per_rhs"])
+    for h in hs:
+        h.close()
