@@ -25,14 +25,42 @@ template <typename T> struct cx {
 };
 
 // ------------------------------------------------------------------ 2D tiles
+// Colour-planar layout: cell (ly, lx) of the extended tile lives in plane (lx + ly) & 1 at
+// ly * W + lx / 2.  The cells one half-sweep updates are then one plane, contiguous, so
+// consecutive threads touch consecutive LDS banks (in row-major order every other word
+// of a row, a two-way bank conflict on every access).  The plane size is 16 modulo 32,
+// so the two colours of a row, loaded and stored by consecutive threads, also fall into
+// different banks.
 template <typename T, int H, int TX, int TY> struct Tile2D {
     static constexpr int EX = TX + 2 * H;
     static constexpr int EY = TY + 2 * H;
-    T xr[EY][EX], xi[EY][EX];
-    T br[EY][EX], bi[EY][EX];
-    T tx[EY][EX], ty[EY][EX];
-    T dr[EY][EX], di[EY][EX];  // inverse of the diagonal D + tau m
+    static_assert(EX % 2 == 0, "tile rows hold whole colour pairs");
+    static constexpr int W = EX / 2;  // cells of one colour in a row
+    static constexpr int PL = EY * W + ((16 - (EY * W) % 32) + 32) % 32;
+    static constexpr int NCELL = 2 * PL;
+    T xr[NCELL], xi[NCELL];
+    T br[NCELL], bi[NCELL];
+    T tx[NCELL], ty[NCELL];
+    T dr[NCELL], di[NCELL];  // inverse of the diagonal D + tau m
+    __device__ static __forceinline__ int at(int ly, int lx) { return ((lx + ly) & 1) * PL + ly * W + (lx >> 1); }
 };
+
+// Element idx of an array with a uniform base: the byte offset is formed in 32 bits (every
+// array these kernels index is far below 4 GiB), so the access takes the scalar base plus a
+// 32-bit vector offset instead of a 64-bit address per thread.
+template <typename T> __device__ __forceinline__ const T& el(const T* base, unsigned idx) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(T));
+}
+template <typename T> __device__ __forceinline__ T& el(T* base, unsigned idx) {
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (unsigned)sizeof(T));
+}
+
+// Sums of products are written as explicit fused multiply-adds in a fixed order, so every
+// tile shape (a different template instance) rounds a cell's update identically.
+template <typename T>
+__device__ __forceinline__ T dot4(T a0, T b0, T a1, T b1, T a2, T b2, T a3, T b3) {
+    return fma(a0, b0, fma(a1, b1, fma(a2, b2, a3 * b3)));
+}
 
 // nhalf half-sweeps of red-black Gauss-Seidel on the tile.  Threads walk the
 // cells of the colour being updated only (half the cells of each row), and
@@ -41,27 +69,29 @@ template <typename T, int H, int TX, int TY> struct Tile2D {
 template <typename T, int H, int TX, int TY>
 __device__ __forceinline__ void tile_sweeps(Tile2D<T, H, TX, TY>& s, int gx0, int gy0, int nx, int ny, int nhalf,
                                             int first_color) {
-    constexpr int EX = Tile2D<T, H, TX, TY>::EX, EY = Tile2D<T, H, TX, TY>::EY;
-    static_assert(EX % 2 == 0, "tile rows hold whole colour pairs");
-    constexpr int W = EX / 2;
+    using S = Tile2D<T, H, TX, TY>;
+    constexpr int EX = S::EX, EY = S::EY, W = S::W, PL = S::PL;
     for (int hs = 0; hs < nhalf; ++hs) {
         const int color = (first_color + hs) & 1;
+        const int q = (color + gx0 + gy0) & 1;  // the plane of this colour
         const int sh = hs + 1;
         const int nrow = EY - 2 * sh;
         for (int c = threadIdx.x; c < nrow * W; c += blockDim.x) {
-            const int ly = sh + c / W;
-            const int lx = 2 * (c % W) + ((color + gx0 + gy0 + ly) & 1);
+            const int ly = sh + c / W, k = c % W;
+            const int p = (q + ly) & 1;  // lx parity of this colour in row ly
+            const int lx = 2 * k + p;
             if (lx < sh || lx >= EX - sh) continue;
             const int gx = gx0 + lx, gy = gy0 + ly;
             if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) continue;
-            const T ore = s.tx[ly][lx] * s.xr[ly][lx + 1] + s.tx[ly][lx - 1] * s.xr[ly][lx - 1] +
-                          s.ty[ly][lx] * s.xr[ly + 1][lx] + s.ty[ly - 1][lx] * s.xr[ly - 1][lx];
-            const T oim = s.tx[ly][lx] * s.xi[ly][lx + 1] + s.tx[ly][lx - 1] * s.xi[ly][lx - 1] +
-                          s.ty[ly][lx] * s.xi[ly + 1][lx] + s.ty[ly - 1][lx] * s.xi[ly - 1][lx];
-            const T nr = s.br[ly][lx] + ore, ni = s.bi[ly][lx] + oim;
-            const T ir = s.dr[ly][lx], ii = s.di[ly][lx];
-            s.xr[ly][lx] = nr * ir - ni * ii;
-            s.xi[ly][lx] = nr * ii + ni * ir;
+            const int own = q * PL + ly * W + k;    // this cell
+            const int oth = (1 - q) * PL + ly * W;  // row ly of the other colour
+            const int e = oth + k + p, w = e - 1, n = oth + W + k, so = oth - W + k;
+            const T ore = dot4(s.tx[own], s.xr[e], s.tx[w], s.xr[w], s.ty[own], s.xr[n], s.ty[so], s.xr[so]);
+            const T oim = dot4(s.tx[own], s.xi[e], s.tx[w], s.xi[w], s.ty[own], s.xi[n], s.ty[so], s.xi[so]);
+            const T nr = s.br[own] + ore, ni = s.bi[own] + oim;
+            const T ir = s.dr[own], ii = s.di[own];
+            s.xr[own] = fma(nr, ir, -(ni * ii));
+            s.xi[own] = fma(nr, ii, ni * ir);
         }
         __syncthreads();
     }
@@ -116,16 +146,16 @@ __device__ __forceinline__ void tile_load(Tile2D<T, H, TX, TY>& s, const LevelVi
         const int c = threadIdx.x + kThreads * k;
         const int lx = c % EX, ly = c / EX;
         const int gx = min(max(gx0 + lx, 0), L.nx - 1), gy = min(max(gy0 + ly, 0), L.ny - 1);
-        const int i = gx + L.nx * gy;
-        vtx[k] = L.Tx[i];
-        vty[k] = L.Ty[i];
-        vd[k] = L.D[i];
-        vm[k] = L.m[i];
-        vbr[k] = br[i];
-        vbi[k] = bi[i];
+        const unsigned i = (unsigned)(gx + L.nx * gy);
+        vtx[k] = el(L.Tx, i);
+        vty[k] = el(L.Ty, i);
+        vd[k] = el(L.D, i);
+        vm[k] = el(L.m, i);
+        vbr[k] = el(br, i);
+        vbi[k] = el(bi, i);
         if (PROLONG) {
-            vxr[k] = xr[i];
-            vxi[k] = xi[i];
+            vxr[k] = el(xr, i);
+            vxi[k] = el(xi, i);
         }
     }
     if (PROLONG) {
@@ -144,8 +174,8 @@ __device__ __forceinline__ void tile_load(Tile2D<T, H, TX, TY>& s, const LevelVi
                     for (int a2 = 0; a2 < nxp; ++a2) {
                         const T w = wx[a2] * wy[b2];
                         const int J = (ix[a2] - px0) + pnx * (iy[b2] - py0);
-                        pr += w * pxr[J];
-                        pi += w * pxi[J];
+                        pr = fma(w, pxr[J], pr);
+                        pi = fma(w, pxi[J], pi);
                     }
                 vxr[k] += pr;
                 vxi[k] += pi;
@@ -160,17 +190,17 @@ __device__ __forceinline__ void tile_load(Tile2D<T, H, TX, TY>& s, const LevelVi
         const int lx = c % EX, ly = c / EX;
         const int gx = gx0 + lx, gy = gy0 + ly;
         const bool in = gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny;
-        s.tx[ly][lx] = in ? vtx[k] : T(0);
-        s.ty[ly][lx] = in ? vty[k] : T(0);
+        s.tx[s.at(ly, lx)] = in ? vtx[k] : T(0);
+        s.ty[s.at(ly, lx)] = in ? vty[k] : T(0);
         // inverse of the diagonal D + tau m (1 outside the grid)
-        const T dr = in ? vd[k] + tr * vm[k] : T(1), di = in ? ti * vm[k] : T(0);
-        const T dd = dr * dr + di * di;
-        s.dr[ly][lx] = dr / dd;
-        s.di[ly][lx] = -di / dd;
-        s.br[ly][lx] = in ? vbr[k] : T(0);
-        s.bi[ly][lx] = in ? vbi[k] : T(0);
-        s.xr[ly][lx] = (PROLONG && in) ? vxr[k] : T(0);
-        s.xi[ly][lx] = (PROLONG && in) ? vxi[k] : T(0);
+        const T dr = in ? fma(tr, vm[k], vd[k]) : T(1), di = in ? ti * vm[k] : T(0);
+        const T dd = fma(dr, dr, di * di);
+        s.dr[s.at(ly, lx)] = dr / dd;
+        s.di[s.at(ly, lx)] = -di / dd;
+        s.br[s.at(ly, lx)] = in ? vbr[k] : T(0);
+        s.bi[s.at(ly, lx)] = in ? vbi[k] : T(0);
+        s.xr[s.at(ly, lx)] = (PROLONG && in) ? vxr[k] : T(0);
+        s.xi[s.at(ly, lx)] = (PROLONG && in) ? vxi[k] : T(0);
     }
 }
 
@@ -188,6 +218,7 @@ __device__ __forceinline__ void stage_patch(const T* __restrict__ er, const T* _
     const int y0 = coy ? max((fy0 >> 1) - 1, 0) : fy0, y1 = coy ? min((fy1 >> 1) + 1, cny - 1) : fy1;
     const int w = x1 - x0 + 1, hgt = y1 - y0 + 1;
     constexpr int MAXP = (EX * (EY / 2 + 3) > (EX / 2 + 3) * EY) ? EX * (EY / 2 + 3) : (EX / 2 + 3) * EY;
+    static_assert(MAXP <= Tile2D<T, H, TX, TY>::NCELL, "the patch is staged in one tile array");
     constexpr int NP = (MAXP + kThreads - 1) / kThreads;
     T vr[NP], vi[NP];
 #pragma unroll
@@ -235,8 +266,8 @@ __global__ __launch_bounds__(256) void k_pre2d(LevelView<T> L, T tr, T ti, const
         const int gx = gx0 + lx, gy = gy0 + ly;
         if (gx < L.nx && gy < L.ny) {
             const int i = gx + L.nx * gy;
-            xr[i] = s.xr[ly][lx];
-            xi[i] = s.xi[ly][lx];
+            xr[i] = s.xr[s.at(ly, lx)];
+            xi[i] = s.xi[s.at(ly, lx)];
         }
     }
     // residual of the interior, summed per aggregate
@@ -249,17 +280,17 @@ __global__ __launch_bounds__(256) void k_pre2d(LevelView<T> L, T tr, T ti, const
         for (int fy = (Y << coy); fy <= (Y << coy) + coy; ++fy)
             for (int fx = (X << cox); fx <= (X << cox) + cox; ++fx) {
                 const int lx = fx - gx0, ly = fy - gy0;
-                T ore = s.tx[ly][lx] * s.xr[ly][lx + 1] + s.tx[ly][lx - 1] * s.xr[ly][lx - 1] +
-                        s.ty[ly][lx] * s.xr[ly + 1][lx] + s.ty[ly - 1][lx] * s.xr[ly - 1][lx];
-                T oim = s.tx[ly][lx] * s.xi[ly][lx + 1] + s.tx[ly][lx - 1] * s.xi[ly][lx - 1] +
-                        s.ty[ly][lx] * s.xi[ly + 1][lx] + s.ty[ly - 1][lx] * s.xi[ly - 1][lx];
+                const int c0 = s.at(ly, lx), ce = s.at(ly, lx + 1), cw = s.at(ly, lx - 1);
+                const int cn = s.at(ly + 1, lx), cs = s.at(ly - 1, lx);
+                const T ore = dot4(s.tx[c0], s.xr[ce], s.tx[cw], s.xr[cw], s.ty[c0], s.xr[cn], s.ty[cs], s.xr[cs]);
+                const T oim = dot4(s.tx[c0], s.xi[ce], s.tx[cw], s.xi[cw], s.ty[c0], s.xi[cn], s.ty[cs], s.xi[cs]);
                 // the tile holds the inverse diagonal: take D + tau m from the level arrays
                 const int fi = fx + L.nx * fy;
-                const T dm = L.m[fi], dre = L.D[fi] + tr * dm, dim = ti * dm;
-                T axr = dre * s.xr[ly][lx] - dim * s.xi[ly][lx] - ore;
-                T axi = dre * s.xi[ly][lx] + dim * s.xr[ly][lx] - oim;
-                ar += s.br[ly][lx] - axr;
-                ai += s.bi[ly][lx] - axi;
+                const T dm = L.m[fi], dre = fma(tr, dm, L.D[fi]), dim = ti * dm;
+                const T axr = fma(dre, s.xr[c0], -(dim * s.xi[c0])) - ore;
+                const T axi = fma(dre, s.xi[c0], dim * s.xr[c0]) - oim;
+                ar += s.br[c0] - axr;
+                ai += s.bi[c0] - axi;
             }
         const size_t I = (size_t)X + (size_t)cnx * Y;
         bc[2 * Nc * r + I] = ar;
@@ -290,10 +321,10 @@ __global__ __launch_bounds__(256) void k_post2d(LevelView<T> L, T tr, T ti, cons
     const int gx0 = blockIdx.x * TX - H, gy0 = blockIdx.y * TY - H;
     const T* er = ec + 2 * Nc * r;
     int px0, py0, pnx;
-    stage_patch<T, H, TX, TY>(er, er + Nc, gx0, gy0, L.nx, L.ny, cnx, cny, cox, coy, &s.xr[0][0], &s.xi[0][0], &px0, &py0,
+    stage_patch<T, H, TX, TY>(er, er + Nc, gx0, gy0, L.nx, L.ny, cnx, cny, cox, coy, s.xr, s.xi, &px0, &py0,
                       &pnx);
     tile_load<T, H, TX, TY, true>(s, L, tr, ti, b + 2 * N * r, b + 2 * N * r + N, xin + 2 * N * r, xin + 2 * N * r + N,
-                          gx0, gy0, &s.xr[0][0], &s.xi[0][0], px0, py0, pnx, cnx, cny, cox, coy, ghost);
+                          gx0, gy0, s.xr, s.xi, px0, py0, pnx, cnx, cny, cox, coy, ghost);
     __syncthreads();
     tile_sweeps<T, H, TX, TY>(s, gx0, gy0, L.nx, L.ny, 2 * NU, 1);
     T* oxr = xout + 2 * N * r;
@@ -303,8 +334,8 @@ __global__ __launch_bounds__(256) void k_post2d(LevelView<T> L, T tr, T ti, cons
         const int gx = gx0 + lx, gy = gy0 + ly;
         if (gx < L.nx && gy < L.ny) {
             const int i = gx + L.nx * gy;
-            oxr[i] = s.xr[ly][lx];
-            oxi[i] = s.xi[ly][lx];
+            oxr[i] = s.xr[s.at(ly, lx)];
+            oxi[i] = s.xi[s.at(ly, lx)];
         }
     }
     if (prof && threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0) {
@@ -343,15 +374,20 @@ __global__ __launch_bounds__(256) void k_post2d_refine(LevelView<T> L, LevelView
     const int gx0 = blockIdx.x * TX - H, gy0 = blockIdx.y * TY - H;
     const T* er = ec + 2 * Nc * r;
     int px0, py0, pnx;
-    stage_patch<T, H, TX, TY>(er, er + Nc, gx0, gy0, L.nx, L.ny, cnx, cny, cox, coy, &s.xr[0][0], &s.xi[0][0], &px0, &py0,
+    stage_patch<T, H, TX, TY>(er, er + Nc, gx0, gy0, L.nx, L.ny, cnx, cny, cox, coy, s.xr, s.xi, &px0, &py0,
                       &pnx);
     tile_load<T, H, TX, TY, true>(s, L, tr, ti, b + 2 * N * r, b + 2 * N * r + N, xin + 2 * N * r, xin + 2 * N * r + N,
-                          gx0, gy0, &s.xr[0][0], &s.xi[0][0], px0, py0, pnx, cnx, cny, cox, coy, ghost);
+                          gx0, gy0, s.xr, s.xi, px0, py0, pnx, cnx, cny, cox, coy, ghost);
     // the FP64 operands of the update do not depend on the sweeps: load them first so
     // their latency overlaps the LDS work
     double* ur = u + ustride * r + (jcol ? 2 * N * (size_t)*jcol : 0);
+    double* ui = ur + N;
     const double* rin = rho_in + 2 * N * r;
+    const double* rini = rin + N;
     double* rout = rho_out + 2 * N * r;
+    double* routi = rout + N;
+    T* lor = lo ? lo + 2 * N * r : nullptr;
+    T* loi = lo ? lor + N : nullptr;
     constexpr int NI = (TX * TY + kThreads - 1) / kThreads;
     double vte[NI], vtw[NI], vtn[NI], vts[NI], vd[NI], vm[NI], vur[NI], vui[NI], vrr[NI], vri[NI];
 #pragma unroll
@@ -359,16 +395,17 @@ __global__ __launch_bounds__(256) void k_post2d_refine(LevelView<T> L, LevelView
         const int c = min((int)threadIdx.x + kThreads * k, TX * TY - 1);
         const int gx = min(gx0 + H + c % TX, L.nx - 1), gy = min(gy0 + H + c / TX, L.ny - 1);
         const int i = gx + L.nx * gy;
-        vte[k] = L64.Tx[i];
-        vtw[k] = L64.Tx[max(i - 1, 0)];
-        vtn[k] = L64.Ty[i];
-        vts[k] = L64.Ty[max(i - L.nx, 0)];
-        vd[k] = L64.D[i];
-        vm[k] = L64.m[i];
-        vur[k] = ur[i];
-        vui[k] = ur[i + N];
-        vrr[k] = rin[i];
-        vri[k] = rin[i + N];
+        const unsigned iu = (unsigned)i;
+        vte[k] = el(L64.Tx, iu);
+        vtw[k] = el(L64.Tx, (unsigned)max(i - 1, 0));
+        vtn[k] = el(L64.Ty, iu);
+        vts[k] = el(L64.Ty, (unsigned)max(i - L.nx, 0));
+        vd[k] = el(L64.D, iu);
+        vm[k] = el(L64.m, iu);
+        vur[k] = el((const double*)ur, iu);
+        vui[k] = el((const double*)ui, iu);
+        vrr[k] = el(rin, iu);
+        vri[k] = el(rini, iu);
     }
     __syncthreads();
     tile_sweeps<T, H, TX, TY>(s, gx0, gy0, L.nx, L.ny, 2 * NU, 1);
@@ -379,26 +416,25 @@ __global__ __launch_bounds__(256) void k_post2d_refine(LevelView<T> L, LevelView
         const int lx = H + c % TX, ly = H + c / TX;
         const int gx = gx0 + lx, gy = gy0 + ly;
         if (c >= TX * TY || gx >= L.nx || gy >= L.ny) continue;
-        const int i = gx + L.nx * gy;
-        const double e0r = (double)s.xr[ly][lx], e0i = (double)s.xi[ly][lx];
+        const unsigned i = (unsigned)(gx + L.nx * gy);
+        const double e0r = (double)s.xr[s.at(ly, lx)], e0i = (double)s.xi[s.at(ly, lx)];
         // (K + tau M) e with the FP64 operator; walls are in D, out-of-grid neighbours hold 0
         const double tE = vte[k], tW = gx > 0 ? vtw[k] : 0.0;
         const double tN = vtn[k], tS = gy > 0 ? vts[k] : 0.0;
-        const double ore = tE * (double)s.xr[ly][lx + 1] + tW * (double)s.xr[ly][lx - 1] +
-                           tN * (double)s.xr[ly + 1][lx] + tS * (double)s.xr[ly - 1][lx];
-        const double oim = tE * (double)s.xi[ly][lx + 1] + tW * (double)s.xi[ly][lx - 1] +
-                           tN * (double)s.xi[ly + 1][lx] + tS * (double)s.xi[ly - 1][lx];
-        const double dre = vd[k] + tr64 * vm[k], dim = ti64 * vm[k];
-        const double are = dre * e0r - dim * e0i - ore;
-        const double aim = dre * e0i + dim * e0r - oim;
-        ur[i] = vur[k] + e0r;
-        ur[i + N] = vui[k] + e0i;
+        const int ce = s.at(ly, lx + 1), cw = s.at(ly, lx - 1), cn = s.at(ly + 1, lx), cs = s.at(ly - 1, lx);
+        const double ore = dot4(tE, (double)s.xr[ce], tW, (double)s.xr[cw], tN, (double)s.xr[cn], tS, (double)s.xr[cs]);
+        const double oim = dot4(tE, (double)s.xi[ce], tW, (double)s.xi[cw], tN, (double)s.xi[cn], tS, (double)s.xi[cs]);
+        const double dre = fma(tr64, vm[k], vd[k]), dim = ti64 * vm[k];
+        const double are = fma(dre, e0r, -(dim * e0i)) - ore;
+        const double aim = fma(dre, e0i, dim * e0r) - oim;
+        el(ur, i) = vur[k] + e0r;
+        el(ui, i) = vui[k] + e0i;
         const double nre = vrr[k] - are, nim = vri[k] - aim;
-        rout[i] = nre;
-        rout[i + N] = nim;
+        el(rout, i) = nre;
+        el(routi, i) = nim;
         if (lo) {
-            lo[2 * N * r + i] = (T)nre;
-            lo[2 * N * r + N + i] = (T)nim;
+            el(lor, i) = (T)nre;
+            el(loi, i) = (T)nim;
         }
         acc += nre * nre + nim * nim;
     }
