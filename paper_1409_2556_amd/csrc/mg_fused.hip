@@ -224,9 +224,9 @@ __device__ __forceinline__ void stage_patch(const T* __restrict__ er, const T* _
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         const int c = min((int)threadIdx.x + kThreads * k, w * hgt - 1);
-        const size_t J = (size_t)(x0 + c % w) + (size_t)cnx * (y0 + c / w);
-        vr[k] = er[J];
-        vi[k] = ei[J];
+        const unsigned J = (unsigned)((x0 + c % w) + cnx * (y0 + c / w));
+        vr[k] = el(er, J);
+        vi[k] = el(ei, J);
     }
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
@@ -265,14 +265,16 @@ __global__ __launch_bounds__(256) void k_pre2d(LevelView<T> L, T tr, T ti, const
         const int lx = H + c % TX, ly = H + c / TX;
         const int gx = gx0 + lx, gy = gy0 + ly;
         if (gx < L.nx && gy < L.ny) {
-            const int i = gx + L.nx * gy;
-            xr[i] = s.xr[s.at(ly, lx)];
-            xi[i] = s.xi[s.at(ly, lx)];
+            const unsigned i = (unsigned)(gx + L.nx * gy);
+            el(xr, i) = s.xr[s.at(ly, lx)];
+            el(xi, i) = s.xi[s.at(ly, lx)];
         }
     }
     // residual of the interior, summed per aggregate
     const int ctx = TX >> cox, cty = TY >> coy;
     const size_t Nc = (size_t)cnx * cny;
+    T* bcr = bc + 2 * Nc * r;
+    T* bci = bcr + Nc;
     for (int c = threadIdx.x; c < ctx * cty; c += blockDim.x) {
         const int X = blockIdx.x * ctx + c % ctx, Y = blockIdx.y * cty + c / ctx;
         if (X >= cnx || Y >= cny) continue;
@@ -285,16 +287,16 @@ __global__ __launch_bounds__(256) void k_pre2d(LevelView<T> L, T tr, T ti, const
                 const T ore = dot4(s.tx[c0], s.xr[ce], s.tx[cw], s.xr[cw], s.ty[c0], s.xr[cn], s.ty[cs], s.xr[cs]);
                 const T oim = dot4(s.tx[c0], s.xi[ce], s.tx[cw], s.xi[cw], s.ty[c0], s.xi[cn], s.ty[cs], s.xi[cs]);
                 // the tile holds the inverse diagonal: take D + tau m from the level arrays
-                const int fi = fx + L.nx * fy;
-                const T dm = L.m[fi], dre = fma(tr, dm, L.D[fi]), dim = ti * dm;
+                const unsigned fi = (unsigned)(fx + L.nx * fy);
+                const T dm = el(L.m, fi), dre = fma(tr, dm, el(L.D, fi)), dim = ti * dm;
                 const T axr = fma(dre, s.xr[c0], -(dim * s.xi[c0])) - ore;
                 const T axi = fma(dre, s.xi[c0], dim * s.xr[c0]) - oim;
                 ar += s.br[c0] - axr;
                 ai += s.bi[c0] - axi;
             }
-        const size_t I = (size_t)X + (size_t)cnx * Y;
-        bc[2 * Nc * r + I] = ar;
-        bc[2 * Nc * r + Nc + I] = ai;
+        const unsigned I = (unsigned)(X + cnx * Y);
+        el(bcr, I) = ar;
+        el(bci, I) = ai;
     }
     if (prof && threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0) {
         // algorithmic bytes of this right-hand side over the level (one count per
@@ -333,9 +335,9 @@ __global__ __launch_bounds__(256) void k_post2d(LevelView<T> L, T tr, T ti, cons
         const int lx = H + c % TX, ly = H + c / TX;
         const int gx = gx0 + lx, gy = gy0 + ly;
         if (gx < L.nx && gy < L.ny) {
-            const int i = gx + L.nx * gy;
-            oxr[i] = s.xr[s.at(ly, lx)];
-            oxi[i] = s.xi[s.at(ly, lx)];
+            const unsigned i = (unsigned)(gx + L.nx * gy);
+            el(oxr, i) = s.xr[s.at(ly, lx)];
+            el(oxi, i) = s.xi[s.at(ly, lx)];
         }
     }
     if (prof && threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0) {
