@@ -527,7 +527,7 @@ int true_residuals(lt_handle* h, const KrylovOut& k, const Plan& plan, lt_stats*
     int rc = 0;
     const int mmax = k.iters_max;
     double* KU = wsp<double>(h, "KU", (size_t)R * std::max(mmax, 1) * 2 * N, &rc);
-    const int nb = true_res_blocks(N);
+    const int nb = true_res_blocks(N, R);
     double* part = wsp<double>(h, "tpart", (size_t)R * Ks * nb, &rc);
     double* tr = wsp<double>(h, "trel", (size_t)R * Ks, &rc);
     if (!KU || !part || !tr) return rc;

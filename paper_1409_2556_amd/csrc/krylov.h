@@ -39,7 +39,7 @@ int launch_inner_update(hipStream_t st, LevelView<double> L, cdouble tau, int R,
 // from K applied once to each used basis column (KU: R * max(mmax, 1) * 2N doubles,
 // part: R * Ks * reduce_blocks(N, R) doubles).
 // blocks per right-hand side of launch_true_residual_cols (its part holds R * Ks * this)
-int true_res_blocks(int N);
+int true_res_blocks(int N, int R);
 int launch_true_residual_cols(hipStream_t st, LevelView<double> L, int R, int Ks, int jmax, int mmax,
                               const double* U, size_t ustride, const double* Y, const int* mcols, const double* zs,
                               const double* b, const double* beta, double* KU, double* part, double* out);

@@ -181,14 +181,12 @@ __global__ void k_inner_finalize(int R, int nb, const double* __restrict__ part,
     // one wavefront per right-hand side sums its partial norms
     const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     for (int r = threadIdx.x >> 6; r < R; r += nw) {
-        // every load is issued before any of them is used (one memory latency, not three)
-        const int on = inner_active[r];
+        if (!inner_active[r]) continue;  // (finished right-hand sides read nothing more)
         double s = 0;
         for (int q = lane; q < nb; q += 64) s += part[(size_t)r * nb + q];
         const double wr = worst[r], prev = rprev[r];
         const int act = active[r], vc = vcycles[r];
         s = wave_sum(s);
-        if (!on) continue;
         if (lane == 0) {
             any = 1;
             double eta = relax_tol / fmax(wr, tol);
@@ -810,7 +808,7 @@ int launch_true_residual_cols(hipStream_t st, LevelView<double> L, int R, int Ks
     if (mmax > 0) {
         k_apply_cols<<<dim3((unsigned)((L.N + kB - 1) / kB), mmax, R), kB, 0, st>>>(L, U, ustride, mcols, KU, kstride);
     }
-    const int nb = true_res_blocks(L.N);
+    const int nb = true_res_blocks(L.N, R);
     // shifts per pass: a multiple of 4 up to 32 that covers Ks with the fewest computed lanes
     int best = 32, cost = 1 << 30;
     for (int w = 4; w <= 32; w += 4) {
@@ -992,10 +990,12 @@ int reduce_blocks(int N, int R) {
     return nb;
 }
 
-int true_res_blocks(int N) {
-    // one cell per thread up to 1024 blocks per right-hand side: the column loop is
-    // latency-bound, so occupancy matters more than the number of partial sums
-    return std::max(1, std::min(1024, (N + kB - 1) / kB));
+int true_res_blocks(int N, int R) {
+    // enough workgroups to fill the chip (about 4096 over all right-hand sides), and no more:
+    // each thread re-reads the uniform y coefficients of every column for every cell it takes,
+    // so with many right-hand sides several cells per thread amortise those loads
+    const int per_rhs = (4096 + R - 1) / std::max(R, 1);
+    return std::max(1, std::min({1024, (N + kB - 1) / kB, per_rhs}));
 }
 
 int launch_norms(hipStream_t st, int N, int R, size_t vstride, const double* x, double* part, double* out,
