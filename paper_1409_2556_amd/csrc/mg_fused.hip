@@ -97,6 +97,27 @@ __device__ __forceinline__ void tile_sweeps(Tile2D<T, H, TX, TY>& s, int gx0, in
     }
 }
 
+// The two taps of prolong_axis with no branch on the count: a missing second tap gets
+// weight 0 and the first tap's index (adding 0 * value leaves a sum unchanged, so sums
+// over both taps equal sums over the taps prolong_axis returns).
+template <typename T>
+__device__ __forceinline__ void prolong_axis2(int f, int nc, int halved, T glo, T ghi, int& i0, int& i1, T& w0,
+                                              T& w1) {
+    if (!halved) {
+        i0 = i1 = f;
+        w0 = T(1);
+        w1 = T(0);
+        return;
+    }
+    const int I = f >> 1;
+    const int J = (f & 1) ? I + 1 : I - 1;
+    const bool lo = J < 0, hi = J >= nc;
+    i0 = I;
+    i1 = (lo || hi) ? I : J;
+    w0 = lo ? T(0.75) + T(0.25) * glo : (hi ? T(0.75) + T(0.25) * ghi : T(0.75));
+    w1 = (lo || hi) ? T(0) : T(0.25);
+}
+
 // Cell-centred linear interpolation weights of one halved axis (ghost mirrored through the wall).
 template <typename T>
 __device__ __forceinline__ int prolong_axis(int f, int nc, int halved, T glo, T ghi, int* idx, T* w) {
@@ -165,18 +186,20 @@ __device__ __forceinline__ void tile_load(Tile2D<T, H, TX, TY>& s, const LevelVi
             const int c = threadIdx.x + kThreads * k;
             const int gx = gx0 + c % EX, gy = gy0 + c / EX;
             if (c < NC && gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
-                int ix[2], iy[2];
-                T wx[2], wy[2];
-                const int nxp = prolong_axis<T>(gx, cnx, cox, (T)ghost.x, (T)ghost.y, ix, wx);
-                const int nyp = prolong_axis<T>(gy, cny, coy, (T)ghost.z, (T)ghost.w, iy, wy);
+                int x0, x1, y0, y1;
+                T wx0, wx1, wy0, wy1;
+                prolong_axis2<T>(gx, cnx, cox, (T)ghost.x, (T)ghost.y, x0, x1, wx0, wx1);
+                prolong_axis2<T>(gy, cny, coy, (T)ghost.z, (T)ghost.w, y0, y1, wy0, wy1);
+                const int r0 = pnx * (y0 - py0) - px0, r1 = pnx * (y1 - py0) - px0;
                 T pr = 0, pi = 0;
-                for (int b2 = 0; b2 < nyp; ++b2)
-                    for (int a2 = 0; a2 < nxp; ++a2) {
-                        const T w = wx[a2] * wy[b2];
-                        const int J = (ix[a2] - px0) + pnx * (iy[b2] - py0);
-                        pr = fma(w, pxr[J], pr);
-                        pi = fma(w, pxi[J], pi);
-                    }
+                pr = fma(wx0 * wy0, pxr[r0 + x0], pr);
+                pi = fma(wx0 * wy0, pxi[r0 + x0], pi);
+                pr = fma(wx1 * wy0, pxr[r0 + x1], pr);
+                pi = fma(wx1 * wy0, pxi[r0 + x1], pi);
+                pr = fma(wx0 * wy1, pxr[r1 + x0], pr);
+                pi = fma(wx0 * wy1, pxi[r1 + x0], pi);
+                pr = fma(wx1 * wy1, pxr[r1 + x1], pr);
+                pi = fma(wx1 * wy1, pxi[r1 + x1], pi);
                 vxr[k] += pr;
                 vxi[k] += pi;
             }
@@ -194,9 +217,9 @@ __device__ __forceinline__ void tile_load(Tile2D<T, H, TX, TY>& s, const LevelVi
         s.ty[s.at(ly, lx)] = in ? vty[k] : T(0);
         // inverse of the diagonal D + tau m (1 outside the grid)
         const T dr = in ? fma(tr, vm[k], vd[k]) : T(1), di = in ? ti * vm[k] : T(0);
-        const T dd = fma(dr, dr, di * di);
-        s.dr[s.at(ly, lx)] = dr / dd;
-        s.di[s.at(ly, lx)] = -di / dd;
+        const T rdd = T(1) / fma(dr, dr, di * di);
+        s.dr[s.at(ly, lx)] = dr * rdd;
+        s.di[s.at(ly, lx)] = -di * rdd;
         s.br[s.at(ly, lx)] = in ? vbr[k] : T(0);
         s.bi[s.at(ly, lx)] = in ? vbi[k] : T(0);
         s.xr[s.at(ly, lx)] = (PROLONG && in) ? vxr[k] : T(0);
