@@ -43,6 +43,16 @@ template <typename T, int H, int TX, int TY> struct Tile2D {
     T tx[NCELL], ty[NCELL];
     T dr[NCELL], di[NCELL];  // inverse of the diagonal D + tau m
     __device__ static __forceinline__ int at(int ly, int lx) { return ((lx + ly) & 1) * PL + ly * W + (lx >> 1); }
+    // cell (ly, lx) and its four neighbours (which lie in the other plane), from one parity
+    __device__ static __forceinline__ void at5(int ly, int lx, int& c, int& e, int& w, int& n, int& so) {
+        const int q = (lx + ly) & 1, k = lx >> 1;
+        c = q * PL + ly * W + k;
+        const int o = (1 - q) * PL + ly * W;
+        e = o + ((lx + 1) >> 1);
+        w = o + ((lx - 1) >> 1);
+        n = o + W + k;
+        so = o - W + k;
+    }
 };
 
 // Element idx of an array with a uniform base: the byte offset is formed in 32 bits (every
@@ -213,17 +223,18 @@ __device__ __forceinline__ void tile_load(Tile2D<T, H, TX, TY>& s, const LevelVi
         const int lx = c % EX, ly = c / EX;
         const int gx = gx0 + lx, gy = gy0 + ly;
         const bool in = gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny;
-        s.tx[s.at(ly, lx)] = in ? vtx[k] : T(0);
-        s.ty[s.at(ly, lx)] = in ? vty[k] : T(0);
+        const int a = s.at(ly, lx);
+        s.tx[a] = in ? vtx[k] : T(0);
+        s.ty[a] = in ? vty[k] : T(0);
         // inverse of the diagonal D + tau m (1 outside the grid)
         const T dr = in ? fma(tr, vm[k], vd[k]) : T(1), di = in ? ti * vm[k] : T(0);
         const T rdd = T(1) / fma(dr, dr, di * di);
-        s.dr[s.at(ly, lx)] = dr * rdd;
-        s.di[s.at(ly, lx)] = -di * rdd;
-        s.br[s.at(ly, lx)] = in ? vbr[k] : T(0);
-        s.bi[s.at(ly, lx)] = in ? vbi[k] : T(0);
-        s.xr[s.at(ly, lx)] = (PROLONG && in) ? vxr[k] : T(0);
-        s.xi[s.at(ly, lx)] = (PROLONG && in) ? vxi[k] : T(0);
+        s.dr[a] = dr * rdd;
+        s.di[a] = -di * rdd;
+        s.br[a] = in ? vbr[k] : T(0);
+        s.bi[a] = in ? vbi[k] : T(0);
+        s.xr[a] = (PROLONG && in) ? vxr[k] : T(0);
+        s.xi[a] = (PROLONG && in) ? vxi[k] : T(0);
     }
 }
 
@@ -305,8 +316,8 @@ __global__ __launch_bounds__(256) void k_pre2d(LevelView<T> L, T tr, T ti, const
         for (int fy = (Y << coy); fy <= (Y << coy) + coy; ++fy)
             for (int fx = (X << cox); fx <= (X << cox) + cox; ++fx) {
                 const int lx = fx - gx0, ly = fy - gy0;
-                const int c0 = s.at(ly, lx), ce = s.at(ly, lx + 1), cw = s.at(ly, lx - 1);
-                const int cn = s.at(ly + 1, lx), cs = s.at(ly - 1, lx);
+                int c0, ce, cw, cn, cs;
+                s.at5(ly, lx, c0, ce, cw, cn, cs);
                 const T ore = dot4(s.tx[c0], s.xr[ce], s.tx[cw], s.xr[cw], s.ty[c0], s.xr[cn], s.ty[cs], s.xr[cs]);
                 const T oim = dot4(s.tx[c0], s.xi[ce], s.tx[cw], s.xi[cw], s.ty[c0], s.xi[cn], s.ty[cs], s.xi[cs]);
                 // the tile holds the inverse diagonal: take D + tau m from the level arrays
@@ -442,11 +453,12 @@ __global__ __launch_bounds__(256) void k_post2d_refine(LevelView<T> L, LevelView
         const int gx = gx0 + lx, gy = gy0 + ly;
         if (c >= TX * TY || gx >= L.nx || gy >= L.ny) continue;
         const unsigned i = (unsigned)(gx + L.nx * gy);
-        const double e0r = (double)s.xr[s.at(ly, lx)], e0i = (double)s.xi[s.at(ly, lx)];
+        int c0, ce, cw, cn, cs;
+        s.at5(ly, lx, c0, ce, cw, cn, cs);
+        const double e0r = (double)s.xr[c0], e0i = (double)s.xi[c0];
         // (K + tau M) e with the FP64 operator; walls are in D, out-of-grid neighbours hold 0
         const double tE = vte[k], tW = gx > 0 ? vtw[k] : 0.0;
         const double tN = vtn[k], tS = gy > 0 ? vts[k] : 0.0;
-        const int ce = s.at(ly, lx + 1), cw = s.at(ly, lx - 1), cn = s.at(ly + 1, lx), cs = s.at(ly - 1, lx);
         const double ore = dot4(tE, (double)s.xr[ce], tW, (double)s.xr[cw], tN, (double)s.xr[cn], tS, (double)s.xr[cs]);
         const double oim = dot4(tE, (double)s.xi[ce], tW, (double)s.xi[cw], tN, (double)s.xi[cn], tS, (double)s.xi[cs]);
         const double dre = fma(tr64, vm[k], vd[k]), dim = ti64 * vm[k];
