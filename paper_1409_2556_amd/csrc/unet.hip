@@ -42,12 +42,15 @@ __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float
 // ---------------------------------------------------------------- 3x3 convolution (MFMA)
 // X [P][cin] bf16 (P = B*H*W pixels, NHWC), Wt [9][cout][cin] bf16, bias [cout] fp32 (nullable).
 // mode 0: Y bf16 = relu?(conv + bias); mode 1: Yf fp32 = conv (overwrite); mode 2: Yf += conv.
+// A wavefront takes NT of the cout / 16 output-channel tiles, from tile NT * blockIdx.y on:
+// small images split their channels over more workgroups (the sums of a tile are the same
+// either way).
 template <int NT>
 __global__ __launch_bounds__(256) void k_conv3(const unsigned short* __restrict__ X, const unsigned short* __restrict__ Wt,
                                                const float* __restrict__ bias, int B, int H, int W, int cin,
-                                               int relu, int mode, unsigned short* __restrict__ Y,
+                                               int cout, int relu, int mode, unsigned short* __restrict__ Y,
                                                float* __restrict__ Yf) {
-    constexpr int cout = 16 * NT;
+    const int cofs = 16 * NT * blockIdx.y;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long P = (long long)B * H * W;
     const long long p0 = ((long long)blockIdx.x * 4 + wave) * 16;  // 16 pixels of one row
@@ -78,7 +81,7 @@ __global__ __launch_bounds__(256) void k_conv3(const unsigned short* __restrict_
                 const unsigned short* wp = Wt + (size_t)((dy + 1) * 3 + j) * cout * cin;
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
-                    b[j][t] = *reinterpret_cast<const v4s*>(wp + (size_t)(16 * t + (lane & 15)) * cin + c0 + kq);
+                    b[j][t] = *reinterpret_cast<const v4s*>(wp + (size_t)(cofs + 16 * t + (lane & 15)) * cin + c0 + kq);
             }
 #pragma unroll
             for (int j = 0; j < 3; ++j)
@@ -89,7 +92,7 @@ __global__ __launch_bounds__(256) void k_conv3(const unsigned short* __restrict_
     // lane holds column co = 16 t + lane%16, rows (pixels) 4 (lane/16) + i
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        const int co = 16 * t + (lane & 15);
+        const int co = cofs + 16 * t + (lane & 15);
         const float bb = bias ? bias[co] : 0.0f;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -518,14 +521,20 @@ static int conv3(hipStream_t st, const unsigned short* X, const unsigned short* 
                  int W, int cin, int cout, int relu, int mode, unsigned short* Y, float* Yf) {
     const long long P = (long long)B * H * W;
     const unsigned grid = (unsigned)((P / 16 + 3) / 4);
-    switch (cout / 16) {
-        case 1: k_conv3<1><<<grid, 256, 0, st>>>(X, Wt, bias, B, H, W, cin, relu, mode, Y, Yf); break;
-        case 2: k_conv3<2><<<grid, 256, 0, st>>>(X, Wt, bias, B, H, W, cin, relu, mode, Y, Yf); break;
-        case 3: k_conv3<3><<<grid, 256, 0, st>>>(X, Wt, bias, B, H, W, cin, relu, mode, Y, Yf); break;
-        case 4: k_conv3<4><<<grid, 256, 0, st>>>(X, Wt, bias, B, H, W, cin, relu, mode, Y, Yf); break;
-        case 6: k_conv3<6><<<grid, 256, 0, st>>>(X, Wt, bias, B, H, W, cin, relu, mode, Y, Yf); break;
-        case 8: k_conv3<8><<<grid, 256, 0, st>>>(X, Wt, bias, B, H, W, cin, relu, mode, Y, Yf); break;
-        default: set_last_error("unet: unsupported channel count"); return LT_EUNSUPPORTED;
+    const int nt = cout / 16;
+    if (grid < 512 && nt > 1) {
+        // too few pixel workgroups to fill the chip: one output-channel tile per wavefront
+        k_conv3<1><<<dim3(grid, nt), 256, 0, st>>>(X, Wt, bias, B, H, W, cin, cout, relu, mode, Y, Yf);
+    } else {
+        switch (nt) {
+            case 1: k_conv3<1><<<grid, 256, 0, st>>>(X, Wt, bias, B, H, W, cin, cout, relu, mode, Y, Yf); break;
+            case 2: k_conv3<2><<<grid, 256, 0, st>>>(X, Wt, bias, B, H, W, cin, cout, relu, mode, Y, Yf); break;
+            case 3: k_conv3<3><<<grid, 256, 0, st>>>(X, Wt, bias, B, H, W, cin, cout, relu, mode, Y, Yf); break;
+            case 4: k_conv3<4><<<grid, 256, 0, st>>>(X, Wt, bias, B, H, W, cin, cout, relu, mode, Y, Yf); break;
+            case 6: k_conv3<6><<<grid, 256, 0, st>>>(X, Wt, bias, B, H, W, cin, cout, relu, mode, Y, Yf); break;
+            case 8: k_conv3<8><<<grid, 256, 0, st>>>(X, Wt, bias, B, H, W, cin, cout, relu, mode, Y, Yf); break;
+            default: set_last_error("unet: unsupported channel count"); return LT_EUNSUPPORTED;
+        }
     }
     LT_HIP(hipGetLastError());
     return 0;
