@@ -944,10 +944,174 @@ __global__ __launch_bounds__(256) void k_sens(LevelView<double> L, const double*
         }
 }
 
+// The same contraction with the fields staged in LDS.  For a fixed cell c the Jacobian is
+// a product over the (shift, face) index,
+//   J_K[s][m] = Re sum_k sum_f (w_k dphi_s,k,f) (dT_f/dln k_c dpsi_m,k,f) + Re sum_k (w_k wall_c phi_s,k) psi_m,k
+//   J_S[s][m] = Re sum_k (w_k z_k m_c phi_s,k) psi_m,k,
+// so a block of kSensCB cells stages, one shift at a time, the weighted differences of every
+// source and receiver field once (kSensA source slots: six faces, the wall term and the
+// storage term; kSensB receiver slots: six faces and the centre), and each thread forms
+// kSensTS sources x kSensTM receivers of one cell from LDS.  Each field value is loaded once per
+// block and shift instead of once per (source, receiver) pair.
+constexpr int kSensCB = 4;                 // cells per block
+constexpr int kSensTPC = kB / kSensCB;     // threads per cell
+constexpr int kSensTS = 5, kSensTM = 4;    // sources x receivers per thread
+constexpr int kSensA = 8, kSensB = 7;      // staged slots per source / receiver field
+
+__global__ __launch_bounds__(256) void k_sens_tile(LevelView<double> L, const double* __restrict__ kappa, int ns,
+                                                   int nr, int nk, int t, int ntimes, const double* __restrict__ X,
+                                                   const double* __restrict__ zs, const double* __restrict__ wq,
+                                                   double* __restrict__ JK, double* __restrict__ JS) {
+    extern __shared__ double sm[];
+    // As[s][slot][cb], Bs[m][slot][cb] as (re, im) pairs
+    double* As = sm;
+    double* Bs = sm + 2 * (size_t)ns * kSensA * kSensCB;
+    const size_t N = L.N;
+    const int cb = threadIdx.x / kSensTPC, g = threadIdx.x % kSensTPC + kSensTPC * blockIdx.y;
+    const int c0 = blockIdx.x * kSensCB;
+    const int c = min(c0 + cb, (int)N - 1);
+    const int ntm = (nr + kSensTM - 1) / kSensTM;
+    const int sb = (g / ntm) * kSensTS, mb = (g % ntm) * kSensTM;
+    const bool work = g < ((ns + kSensTS - 1) / kSensTS) * ntm && c0 + cb < (int)N;
+    // staging: thread j of the block takes (field, cell) items; every thread knows its staged
+    // cell's neighbours and weights
+    const int sy = L.nx, sz = L.nx * L.ny;
+    // per staged cell: dT_f/dln k_c of its six faces, its wall term and its mass (once per block)
+    __shared__ double Wf[6][kSensCB], Wall[kSensCB], Mc[kSensCB];
+    if (threadIdx.x < kSensCB) {
+        const int q = threadIdx.x;
+        const int cc = min(c0 + q, (int)N - 1);
+        const int x = cc % L.nx, y = (cc / L.nx) % L.ny, z = cc / sz;
+        const int has[6] = {x > 0, x + 1 < L.nx, y > 0, y + 1 < L.ny, z > 0, z + 1 < L.nz};
+        const int off[6] = {-1, 1, -sy, sy, -sz, sz};
+        const double kc = kappa[cc];
+        double tin = 0.0;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            double T = 0.0, wf = 0.0;
+            if (has[e]) {
+                if (e == 0) T = L.Tx[cc - 1];
+                if (e == 1) T = L.Tx[cc];
+                if (e == 2) T = L.Ty[cc - sy];
+                if (e == 3) T = L.Ty[cc];
+                if (e == 4) T = L.Tz[cc - sz];
+                if (e == 5) T = L.Tz[cc];
+                const double kj = kappa[cc + off[e]];
+                wf = T * kj / (kc + kj);
+            }
+            tin += T;
+            Wf[e][q] = wf;
+        }
+        Wall[q] = L.D[cc] - tin;  // walls of this cell; their T is proportional to k_c
+        Mc[q] = L.m[cc];
+    }
+    double accK[kSensTS][kSensTM], accS[kSensTS][kSensTM];
+#pragma unroll
+    for (int a = 0; a < kSensTS; ++a)
+#pragma unroll
+        for (int q = 0; q < kSensTM; ++q) accK[a][q] = accS[a][q] = 0.0;
+    const int nitems = (ns + nr) * kSensCB;
+    for (int kk = 0; kk < nk; ++kk) {
+        const int k = t * nk + kk;
+        const c64 w = {wq[2 * k], wq[2 * k + 1]};
+        const c64 zw = cm(w, {zs[2 * k], zs[2 * k + 1]});
+        __syncthreads();  // the previous shift's reads of the stage are done
+        for (int it = threadIdx.x; it < nitems; it += blockDim.x) {
+            const int f = it / kSensCB, q = it % kSensCB;  // field (sources first), staged cell
+            const int cc = min(c0 + q, (int)N - 1);
+            const int x = cc % L.nx, y = (cc / L.nx) % L.ny, z = cc / sz;
+            const int has[6] = {x > 0, x + 1 < L.nx, y > 0, y + 1 < L.ny, z > 0, z + 1 < L.nz};
+            const int off[6] = {-1, 1, -sy, sy, -sz, sz};
+            const double* ph = X + ((size_t)f * nk + kk) * 2 * N;
+            const c64 pc = {ph[cc], ph[cc + N]};
+            c64 d[6];
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                const int nb = has[e] ? cc + off[e] : cc;
+                d[e] = {pc.re - ph[nb], pc.im - ph[nb + N]};
+            }
+            if (f < ns) {
+                // w dphi per face, w wall phi, w z m phi
+                const double wall = Wall[q], mc = Mc[q];
+                double* a = As + 2 * (((size_t)f * kSensA) * kSensCB + q);
+#pragma unroll
+                for (int e = 0; e < 6; ++e) {
+                    const c64 v = cm(w, d[e]);
+                    a[2 * e * kSensCB] = v.re;
+                    a[2 * e * kSensCB + 1] = v.im;
+                }
+                const c64 vw = cm(w, {wall * pc.re, wall * pc.im});
+                const c64 vz = cm(zw, {mc * pc.re, mc * pc.im});
+                a[2 * 6 * kSensCB] = vw.re;
+                a[2 * 6 * kSensCB + 1] = vw.im;
+                a[2 * 7 * kSensCB] = vz.re;
+                a[2 * 7 * kSensCB + 1] = vz.im;
+            } else {
+                // dT_f/dln k_c dpsi per face, psi
+                double* b = Bs + 2 * (((size_t)(f - ns) * kSensB) * kSensCB + q);
+#pragma unroll
+                for (int e = 0; e < 6; ++e) {
+                    const double wf = Wf[e][q];
+                    b[2 * e * kSensCB] = wf * d[e].re;
+                    b[2 * e * kSensCB + 1] = wf * d[e].im;
+                }
+                b[2 * 6 * kSensCB] = pc.re;
+                b[2 * 6 * kSensCB + 1] = pc.im;
+            }
+        }
+        __syncthreads();
+        if (work) {
+#pragma unroll
+            for (int e = 0; e < kSensB; ++e) {
+                c64 bv[kSensTM];
+#pragma unroll
+                for (int q = 0; q < kSensTM; ++q) {
+                    const int m = min(mb + q, nr - 1);
+                    const double* b = Bs + 2 * (((size_t)m * kSensB + e) * kSensCB + cb);
+                    bv[q] = {b[0], b[1]};
+                }
+#pragma unroll
+                for (int a = 0; a < kSensTS; ++a) {
+                    const int sa = min(sb + a, ns - 1);
+                    const double* ap = As + 2 * (((size_t)sa * kSensA + e) * kSensCB + cb);
+                    const c64 av = {ap[0], ap[1]};
+#pragma unroll
+                    for (int q = 0; q < kSensTM; ++q) accK[a][q] += av.re * bv[q].re - av.im * bv[q].im;
+                    if (e == 6) {
+                        // the storage term pairs the same receiver centre with slot 7
+                        const double* zp = As + 2 * (((size_t)sa * kSensA + 7) * kSensCB + cb);
+                        const c64 zv = {zp[0], zp[1]};
+#pragma unroll
+                        for (int q = 0; q < kSensTM; ++q) accS[a][q] += zv.re * bv[q].re - zv.im * bv[q].im;
+                    }
+                }
+            }
+        }
+    }
+    if (!work) return;
+#pragma unroll
+    for (int a = 0; a < kSensTS; ++a)
+#pragma unroll
+        for (int q = 0; q < kSensTM; ++q) {
+            const int sa = sb + a, m = mb + q;
+            if (sa >= ns || m >= nr) continue;
+            const size_t o = (((size_t)sa * nr + m) * ntimes + t) * N + c;
+            if (JK) JK[o] = -2.0 * accK[a][q];
+            if (JS) JS[o] = -2.0 * accS[a][q];
+        }
+}
+
 int launch_sens(hipStream_t st, LevelView<double> L, const double* kappa, int ns, int nr, int nk, int t, int ntimes,
                 const double* X, const double* zs, const double* wq, double* JK, double* JS) {
-    dim3 grid((unsigned)((L.N + kB - 1) / kB), (ns + kSensS - 1) / kSensS, (nr + kSensM - 1) / kSensM);
-    k_sens<<<grid, kB, 0, st>>>(L, kappa, ns, nr, nk, t, ntimes, X, zs, wq, JK, JS);
+    const size_t shm = 2 * sizeof(double) * ((size_t)ns * kSensA + (size_t)nr * kSensB) * kSensCB;
+    if (shm <= 64 * 1024) {
+        const int groups = ((ns + kSensTS - 1) / kSensTS) * ((nr + kSensTM - 1) / kSensTM);
+        dim3 grid((unsigned)((L.N + kSensCB - 1) / kSensCB), (unsigned)((groups + kSensTPC - 1) / kSensTPC));
+        k_sens_tile<<<grid, kB, shm, st>>>(L, kappa, ns, nr, nk, t, ntimes, X, zs, wq, JK, JS);
+    } else {
+        dim3 grid((unsigned)((L.N + kB - 1) / kB), (ns + kSensS - 1) / kSensS, (nr + kSensM - 1) / kSensM);
+        k_sens<<<grid, kB, 0, st>>>(L, kappa, ns, nr, nk, t, ntimes, X, zs, wq, JK, JS);
+    }
     LT_HIP(hipGetLastError());
     return 0;
 }
