@@ -957,6 +957,10 @@ constexpr int kSensCB = 4;                 // cells per block
 constexpr int kSensTPC = kB / kSensCB;     // threads per cell
 constexpr int kSensTS = 5, kSensTM = 4;    // sources x receivers per thread
 constexpr int kSensA = 8, kSensB = 7;      // staged slots per source / receiver field
+// doubles per staged field: 4 words past a multiple of 32 banks, so the consecutive fields
+// the lanes of a wavefront read at once fall into different banks
+constexpr int kSensFS = 2 * kSensA * kSensCB + 2;
+static_assert(kSensFS >= 2 * kSensB * kSensCB && (2 * kSensFS) % 32 == 4, "staged field stride");
 
 __global__ __launch_bounds__(256) void k_sens_tile(LevelView<double> L, const double* __restrict__ kappa, int ns,
                                                    int nr, int nk, int t, int ntimes, const double* __restrict__ X,
@@ -965,19 +969,22 @@ __global__ __launch_bounds__(256) void k_sens_tile(LevelView<double> L, const do
     extern __shared__ double sm[];
     // As[s][slot][cb], Bs[m][slot][cb] as (re, im) pairs
     double* As = sm;
-    double* Bs = sm + 2 * (size_t)ns * kSensA * kSensCB;
+    double* Bs = sm + (size_t)ns * kSensFS;
     const size_t N = L.N;
     const int cb = threadIdx.x / kSensTPC, g = threadIdx.x % kSensTPC + kSensTPC * blockIdx.y;
     const int c0 = blockIdx.x * kSensCB;
     const int c = min(c0 + cb, (int)N - 1);
-    const int ntm = (nr + kSensTM - 1) / kSensTM;
-    const int sb = (g / ntm) * kSensTS, mb = (g % ntm) * kSensTM;
-    const bool work = g < ((ns + kSensTS - 1) / kSensTS) * ntm && c0 + cb < (int)N;
+    // thread (si, mi) takes sources si + a nsg and receivers mi + q ntm: the lanes of a
+    // wavefront then read consecutive fields
+    const int nsg = (ns + kSensTS - 1) / kSensTS, ntm = (nr + kSensTM - 1) / kSensTM;
+    const int si = g / ntm, mi = g % ntm;
+    const bool work = g < nsg * ntm && c0 + cb < (int)N;
     // staging: thread j of the block takes (field, cell) items; every thread knows its staged
     // cell's neighbours and weights
     const int sy = L.nx, sz = L.nx * L.ny;
     // per staged cell: dT_f/dln k_c of its six faces, its wall term and its mass (once per block)
     __shared__ double Wf[6][kSensCB], Wall[kSensCB], Mc[kSensCB];
+    __shared__ int Nb[7][kSensCB];  // the cell itself, then its six neighbours (itself where none)
     if (threadIdx.x < kSensCB) {
         const int q = threadIdx.x;
         const int cc = min(c0 + q, (int)N - 1);
@@ -1001,7 +1008,9 @@ __global__ __launch_bounds__(256) void k_sens_tile(LevelView<double> L, const do
             }
             tin += T;
             Wf[e][q] = wf;
+            Nb[e + 1][q] = has[e] ? cc + off[e] : cc;
         }
+        Nb[0][q] = cc;
         Wall[q] = L.D[cc] - tin;  // walls of this cell; their T is proportional to k_c
         Mc[q] = L.m[cc];
     }
@@ -1011,75 +1020,92 @@ __global__ __launch_bounds__(256) void k_sens_tile(LevelView<double> L, const do
 #pragma unroll
         for (int q = 0; q < kSensTM; ++q) accK[a][q] = accS[a][q] = 0.0;
     const int nitems = (ns + nr) * kSensCB;
+    // the seven stencil values (re, im) of staged item it = (field, cell) at shift kk
+    auto fetch = [&](int it, int kk, double (&v)[14]) {
+        const int f = it / kSensCB, q = it % kSensCB;
+        const double* ph = X + ((size_t)f * nk + kk) * 2 * N;
+        const double* phi = ph + N;
+#pragma unroll
+        for (int e = 0; e < 7; ++e) {
+            const int nb = Nb[e][q];
+            v[2 * e] = ph[nb];
+            v[2 * e + 1] = phi[nb];
+        }
+    };
+    auto stage = [&](int it, const double (&v)[14], c64 w, c64 zw) {
+        const int f = it / kSensCB, q = it % kSensCB;  // field (sources first), staged cell
+        const c64 pc = {v[0], v[1]};
+        c64 d[6];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) d[e] = {pc.re - v[2 * e + 2], pc.im - v[2 * e + 3]};
+        if (f < ns) {
+            // w dphi per face, w wall phi, w z m phi
+            const double wall = Wall[q], mc = Mc[q];
+            double* a = As + (size_t)f * kSensFS + 2 * q;
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                const c64 u = cm(w, d[e]);
+                a[2 * e * kSensCB] = u.re;
+                a[2 * e * kSensCB + 1] = u.im;
+            }
+            const c64 vw = cm(w, {wall * pc.re, wall * pc.im});
+            const c64 vz = cm(zw, {mc * pc.re, mc * pc.im});
+            a[2 * 6 * kSensCB] = vw.re;
+            a[2 * 6 * kSensCB + 1] = vw.im;
+            a[2 * 7 * kSensCB] = vz.re;
+            a[2 * 7 * kSensCB + 1] = vz.im;
+        } else {
+            // dT_f/dln k_c dpsi per face, psi
+            double* b = Bs + (size_t)(f - ns) * kSensFS + 2 * q;
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                const double wf = Wf[e][q];
+                b[2 * e * kSensCB] = wf * d[e].re;
+                b[2 * e * kSensCB + 1] = wf * d[e].im;
+            }
+            b[2 * 6 * kSensCB] = pc.re;
+            b[2 * 6 * kSensCB + 1] = pc.im;
+        }
+    };
+    // each thread's first item of the next shift is loaded while the current shift is formed
+    const int it0 = threadIdx.x;
+    const bool h0 = it0 < nitems;
+    double pv[14];
+    __syncthreads();  // the neighbour table is written
+    if (h0) fetch(it0, 0, pv);
     for (int kk = 0; kk < nk; ++kk) {
         const int k = t * nk + kk;
         const c64 w = {wq[2 * k], wq[2 * k + 1]};
         const c64 zw = cm(w, {zs[2 * k], zs[2 * k + 1]});
         __syncthreads();  // the previous shift's reads of the stage are done
-        for (int it = threadIdx.x; it < nitems; it += blockDim.x) {
-            const int f = it / kSensCB, q = it % kSensCB;  // field (sources first), staged cell
-            const int cc = min(c0 + q, (int)N - 1);
-            const int x = cc % L.nx, y = (cc / L.nx) % L.ny, z = cc / sz;
-            const int has[6] = {x > 0, x + 1 < L.nx, y > 0, y + 1 < L.ny, z > 0, z + 1 < L.nz};
-            const int off[6] = {-1, 1, -sy, sy, -sz, sz};
-            const double* ph = X + ((size_t)f * nk + kk) * 2 * N;
-            const c64 pc = {ph[cc], ph[cc + N]};
-            c64 d[6];
-#pragma unroll
-            for (int e = 0; e < 6; ++e) {
-                const int nb = has[e] ? cc + off[e] : cc;
-                d[e] = {pc.re - ph[nb], pc.im - ph[nb + N]};
-            }
-            if (f < ns) {
-                // w dphi per face, w wall phi, w z m phi
-                const double wall = Wall[q], mc = Mc[q];
-                double* a = As + 2 * (((size_t)f * kSensA) * kSensCB + q);
-#pragma unroll
-                for (int e = 0; e < 6; ++e) {
-                    const c64 v = cm(w, d[e]);
-                    a[2 * e * kSensCB] = v.re;
-                    a[2 * e * kSensCB + 1] = v.im;
-                }
-                const c64 vw = cm(w, {wall * pc.re, wall * pc.im});
-                const c64 vz = cm(zw, {mc * pc.re, mc * pc.im});
-                a[2 * 6 * kSensCB] = vw.re;
-                a[2 * 6 * kSensCB + 1] = vw.im;
-                a[2 * 7 * kSensCB] = vz.re;
-                a[2 * 7 * kSensCB + 1] = vz.im;
-            } else {
-                // dT_f/dln k_c dpsi per face, psi
-                double* b = Bs + 2 * (((size_t)(f - ns) * kSensB) * kSensCB + q);
-#pragma unroll
-                for (int e = 0; e < 6; ++e) {
-                    const double wf = Wf[e][q];
-                    b[2 * e * kSensCB] = wf * d[e].re;
-                    b[2 * e * kSensCB + 1] = wf * d[e].im;
-                }
-                b[2 * 6 * kSensCB] = pc.re;
-                b[2 * 6 * kSensCB + 1] = pc.im;
-            }
+        if (h0) stage(it0, pv, w, zw);
+        for (int it = it0 + (int)blockDim.x; it < nitems; it += blockDim.x) {
+            double v[14];
+            fetch(it, kk, v);
+            stage(it, v, w, zw);
         }
         __syncthreads();
+        if (h0 && kk + 1 < nk) fetch(it0, kk + 1, pv);
         if (work) {
 #pragma unroll
             for (int e = 0; e < kSensB; ++e) {
                 c64 bv[kSensTM];
 #pragma unroll
                 for (int q = 0; q < kSensTM; ++q) {
-                    const int m = min(mb + q, nr - 1);
-                    const double* b = Bs + 2 * (((size_t)m * kSensB + e) * kSensCB + cb);
+                    const int m = min(mi + q * ntm, nr - 1);
+                    const double* b = Bs + (size_t)m * kSensFS + 2 * (e * kSensCB + cb);
                     bv[q] = {b[0], b[1]};
                 }
 #pragma unroll
                 for (int a = 0; a < kSensTS; ++a) {
-                    const int sa = min(sb + a, ns - 1);
-                    const double* ap = As + 2 * (((size_t)sa * kSensA + e) * kSensCB + cb);
+                    const int sa = min(si + a * nsg, ns - 1);
+                    const double* ap = As + (size_t)sa * kSensFS + 2 * (e * kSensCB + cb);
                     const c64 av = {ap[0], ap[1]};
 #pragma unroll
                     for (int q = 0; q < kSensTM; ++q) accK[a][q] += av.re * bv[q].re - av.im * bv[q].im;
                     if (e == 6) {
                         // the storage term pairs the same receiver centre with slot 7
-                        const double* zp = As + 2 * (((size_t)sa * kSensA + 7) * kSensCB + cb);
+                        const double* zp = As + (size_t)sa * kSensFS + 2 * (7 * kSensCB + cb);
                         const c64 zv = {zp[0], zp[1]};
 #pragma unroll
                         for (int q = 0; q < kSensTM; ++q) accS[a][q] += zv.re * bv[q].re - zv.im * bv[q].im;
@@ -1093,7 +1119,7 @@ __global__ __launch_bounds__(256) void k_sens_tile(LevelView<double> L, const do
     for (int a = 0; a < kSensTS; ++a)
 #pragma unroll
         for (int q = 0; q < kSensTM; ++q) {
-            const int sa = sb + a, m = mb + q;
+            const int sa = si + a * nsg, m = mi + q * ntm;
             if (sa >= ns || m >= nr) continue;
             const size_t o = (((size_t)sa * nr + m) * ntimes + t) * N + c;
             if (JK) JK[o] = -2.0 * accK[a][q];
@@ -1103,7 +1129,7 @@ __global__ __launch_bounds__(256) void k_sens_tile(LevelView<double> L, const do
 
 int launch_sens(hipStream_t st, LevelView<double> L, const double* kappa, int ns, int nr, int nk, int t, int ntimes,
                 const double* X, const double* zs, const double* wq, double* JK, double* JS) {
-    const size_t shm = 2 * sizeof(double) * ((size_t)ns * kSensA + (size_t)nr * kSensB) * kSensCB;
+    const size_t shm = sizeof(double) * (size_t)(ns + nr) * kSensFS;
     if (shm <= 64 * 1024) {
         const int groups = ((ns + kSensTS - 1) / kSensTS) * ((nr + kSensTM - 1) / kSensTM);
         dim3 grid((unsigned)((L.N + kSensCB - 1) / kSensCB), (unsigned)((groups + kSensTPC - 1) / kSensTPC));
