@@ -972,7 +972,14 @@ __global__ __launch_bounds__(256) void k_sens_tile(LevelView<double> L, const do
     double* Bs = sm + (size_t)ns * kSensFS;
     const size_t N = L.N;
     const int cb = threadIdx.x / kSensTPC, g = threadIdx.x % kSensTPC + kSensTPC * blockIdx.y;
-    const int c0 = blockIdx.x * kSensCB;
+    // workgroups go to the 8 XCDs in turn; renumber them so each XCD takes one run of
+    // consecutive cells and the short rows of output it writes complete lines in its own L2
+    unsigned bx;
+    {
+        const unsigned W = gridDim.x, w = blockIdx.x, xk = w % 8u, per = W / 8u, extra = W % 8u;
+        bx = xk * per + min(xk, extra) + w / 8u;
+    }
+    const int c0 = (int)bx * kSensCB;
     const int c = min(c0 + cb, (int)N - 1);
     // thread (si, mi) takes sources si + a nsg and receivers mi + q ntm: the lanes of a
     // wavefront then read consecutive fields
