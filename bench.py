@@ -194,8 +194,9 @@ def main():
     from paper_1409_2556_amd import binding as lt
 
     torch.cuda.set_device(0)
-    h, tiles = _handle(lt, p, not args.no_tune, len(p.sources))
     groups = max(1, min(args.groups, len(p.sources)))
+    # tiles tuned for the right-hand sides one launch carries (one group's share)
+    h, tiles = _handle(lt, p, not args.no_tune, -(-len(p.sources) // groups))
     hs = [h]
     for _ in range(groups - 1):
         # the other groups' handles take the first handle's tiles (tuned for the full batch)
