@@ -355,12 +355,14 @@ __global__ void k_features(const T* __restrict__ x, int N, const double* __restr
     for (int c = 5; c < 16; ++c) f[c] = 0;
 }
 
-// rms[b] = sqrt(mean |x_b|^2) over the N cells (one block per sample)
+// rms[b] = sqrt(mean |x_b|^2) over the N cells: kRmsBlocks partial sums per sample
+// (blockIdx.y), then one wavefront per sample adds them
+constexpr int kRmsBlocks = 64;
 template <typename T>
-__global__ void k_rms(const T* __restrict__ x, int N, float* __restrict__ rms) {
-    const int b = blockIdx.x;
+__global__ void k_rms_part(const T* __restrict__ x, int N, double* __restrict__ part) {
+    const int b = blockIdx.y;
     double s = 0;
-    for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 2 * N; i += gridDim.x * blockDim.x) {
         const double v = (double)x[(size_t)b * 2 * N + i];
         s += v * v;
     }
@@ -371,8 +373,14 @@ __global__ void k_rms(const T* __restrict__ x, int N, float* __restrict__ rms) {
     if (threadIdx.x == 0) {
         double t = 0;
         for (int q = 0; q < (int)blockDim.x / 64; ++q) t += red[q];
-        rms[b] = (float)sqrt(t / N);
+        part[(size_t)b * gridDim.x + blockIdx.x] = t;
     }
+}
+__global__ void k_rms_final(const double* __restrict__ part, int N, float* __restrict__ rms) {
+    const int b = blockIdx.x;
+    double s = threadIdx.x < kRmsBlocks ? part[(size_t)b * kRmsBlocks + threadIdx.x] : 0.0;
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (threadIdx.x == 0) rms[b] = (float)sqrt(s / N);
 }
 
 // normalised target: tgt[p][c] = e * D / s_r
@@ -729,9 +737,12 @@ int unet_features(UNet* u, hipStream_t st, const LevelView<double>& L0, double l
     int rc = 0;
     const long long P0 = (long long)B * L0.N;
     float* rms = ubuf<float>(u, "rms", B, &rc);
+    double* rmsp = ubuf<double>(u, "rmsp", (size_t)B * kRmsBlocks, &rc);
     unsigned short* F = ubuf<unsigned short>(u, "a_in", P0 * 16, &rc);
-    if (!rms || !F) return rc;
-    k_rms<T><<<B, 256, 0, st>>>(x, L0.N, rms);
+    if (!rms || !rmsp || !F) return rc;
+    static_assert(kRmsBlocks <= 64, "one wavefront adds the partial sums");
+    k_rms_part<T><<<dim3(kRmsBlocks, B), 256, 0, st>>>(x, L0.N, rmsp);
+    k_rms_final<<<B, 64, 0, st>>>(rmsp, L0.N, rms);
     k_features<T><<<dim3(nb(L0.N), B), 256, 0, st>>>(x, L0.N, L0.D, L0.m, lnDbar, tau.real(), tau.imag(), rms, F);
     LT_HIP(hipGetLastError());
     return 0;
