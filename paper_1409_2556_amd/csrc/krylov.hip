@@ -709,7 +709,7 @@ __global__ void k_apply_cols(LevelView<double> L, const double* __restrict__ U, 
     o[i + N] = L.D[i] * xi[i] - sim;
 }
 
-template <int kTrK>  // shifts per pass
+template <int kTrK, bool STAGED>  // shifts per pass; y coefficients staged in LDS (m * kTrK of them)
 __global__ __launch_bounds__(256) void k_true_res_cols(LevelView<double> L, int Ks, int k0, int kc, int jmax,
                                                        const double* __restrict__ U, size_t ustride,
                                                        const double* __restrict__ KU, size_t kstride,
@@ -731,6 +731,16 @@ __global__ __launch_bounds__(256) void k_true_res_cols(LevelView<double> L, int 
     }
     const double* Ur = U + ustride * r;
     const double* KUr = KU + kstride * r;
+    // this pass's y coefficients of every column, read by all lanes at once from LDS
+    extern __shared__ double ys[];  // [m][kTrK] (re, im)
+    if (STAGED) {
+        for (int q = threadIdx.x; q < m * kTrK; q += blockDim.x) {
+            const int j = q / kTrK, cc = min(q % kTrK, kc - 1);
+            ys[2 * q] = Yr[(size_t)j * 2 * Ks + 2 * (k0 + cc)];
+            ys[2 * q + 1] = Yr[(size_t)j * 2 * Ks + 2 * (k0 + cc) + 1];
+        }
+        __syncthreads();
+    }
     for (int i = blockIdx.x * kB + threadIdx.x; i < L.N; i += gridDim.x * kB) {
         double ar[kTrK], ai[kTrK];
         const double b0 = br[i], b1 = br[i + N];
@@ -757,10 +767,10 @@ __global__ __launch_bounds__(256) void k_true_res_cols(LevelView<double> L, int 
                 nk0 = KUr[o];
                 nk1 = KUr[o + N];
             }
-            const double* y = Yr + (size_t)j * 2 * Ks + 2 * k0;
+            const double* y = STAGED ? ys + 2 * j * kTrK : Yr + (size_t)j * 2 * Ks + 2 * k0;
 #pragma unroll
             for (int c = 0; c < kTrK; ++c) {
-                const int cc = min(c, kc - 1);
+                const int cc = STAGED ? c : min(c, kc - 1);
                 // t = K u + z m u;  acc -= y t
                 const double tr = kr + (zr[c] * ur - zi[c] * ui), ti = ki + (zr[c] * ui + zi[c] * ur);
                 const double yr = y[2 * cc], yi = y[2 * cc + 1];
@@ -821,8 +831,12 @@ int launch_true_residual_cols(hipStream_t st, LevelView<double> L, int R, int Ks
     for (int k0 = 0; k0 < Ks; k0 += best) {
         const int kc = std::min(best, Ks - k0);
 #define LT_TR(W)                                                                                                \
-    k_true_res_cols<W><<<dim3(nb, R), kB, 0, st>>>(L, Ks, k0, kc, jmax, U, ustride, KU, kstride, Y, mcols, zs, b, \
-                                                   part)
+    if (sizeof(double) * 2 * W * (size_t)std::max(mmax, 1) <= 64 * 1024)                                    \
+        k_true_res_cols<W, true><<<dim3(nb, R), kB, sizeof(double) * 2 * W * (size_t)std::max(mmax, 1), st>>>( \
+            L, Ks, k0, kc, jmax, U, ustride, KU, kstride, Y, mcols, zs, b, part);                               \
+    else                                                                                                        \
+        k_true_res_cols<W, false><<<dim3(nb, R), kB, 0, st>>>(L, Ks, k0, kc, jmax, U, ustride, KU, kstride, Y,  \
+                                                              mcols, zs, b, part)
         switch (best) {
             case 4: LT_TR(4); break;
             case 8: LT_TR(8); break;
