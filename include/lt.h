@@ -183,7 +183,8 @@ int lt_setup(const lt_grid* grid, const double* kappa, const double* S, const lt
  * solutions of eqn:multipleshifted, computed with the flexible shifted
  * Krylov method of Section 3.  phi_out: device float64 [ns][nr][ntimes].
  * Returns LT_WNOTCONV if some shift missed the tolerance after maxit
- * outer iterations (phi_out then holds the best estimate). */
+ * outer iterations (phi_out then holds the best estimate); LT_EINVAL, before
+ * any work, for more than 1000 sources. */
 int lt_solve(lt_handle* h, const lt_points* sources, double q, const double* times, int ntimes,
              const lt_contour* contour, const lt_points* receivers, const lt_opts* opts,
              double* phi_out, lt_stats* stats);
@@ -197,7 +198,8 @@ int lt_solve(lt_handle* h, const lt_points* sources, double q, const double* tim
  * the heads' weighting |w_k qhat_k| and the storage term's |w_k qhat_k z_k|
  * in the convergence test.  Near steady state the storage sensitivity is a
  * vanishing sum of contour terms of its early-time size, so its error is set
- * by tol relative to that size, not to its own norm. */
+ * by tol relative to that size, not to its own norm.  LT_EINVAL, before any
+ * work, for more than 1000 sources and receivers together. */
 int lt_adjoint(lt_handle* h, const lt_points* sources, double q, const lt_points* receivers,
                const double* times, int ntimes, const lt_contour* contour, const lt_opts* opts,
                double* dlnK, double* dlnS, lt_stats* stats);

@@ -349,8 +349,8 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     if (!h->pinned) LT_HIP(hipHostMalloc(&h->pinned, 4096, hipHostMallocDefault));
     int* hflag = static_cast<int*>(h->pinned);
     int* hact = hflag + 16;
-    if (R > 1000) {
-        set_last_error("at most 1000 right-hand sides per batch");
+    if (R > kMaxRhs) {
+        set_last_error("at most " + std::to_string(kMaxRhs) + " right-hand sides per call");
         return LT_EINVAL;
     }
     double* b = out->b;
@@ -749,6 +749,10 @@ int lt_solve(lt_handle* h, const lt_points* sources, double q, const double* tim
         set_last_error("lt_solve: bad argument");
         return LT_EINVAL;
     }
+    if (sources->n > kMaxRhs) {
+        set_last_error("lt_solve: at most " + std::to_string(kMaxRhs) + " sources per call");
+        return LT_EINVAL;
+    }
     for (int t = 0; t < ntimes; ++t)
         if (!(times[t] > 0.0) || !std::isfinite(times[t])) {
             set_last_error("lt_solve: times must be positive");
@@ -802,6 +806,10 @@ int lt_adjoint(lt_handle* h, const lt_points* sources, double q, const lt_points
     if (!h || !sources || sources->n < 1 || !receivers || receivers->n < 1 || !times || ntimes < 1 || !contour ||
         (!dlnK && !dlnS) || !std::isfinite(q)) {
         set_last_error("lt_adjoint: bad argument");
+        return LT_EINVAL;
+    }
+    if (sources->n + (long long)receivers->n > kMaxRhs) {
+        set_last_error("lt_adjoint: at most " + std::to_string(kMaxRhs) + " sources and receivers per call");
         return LT_EINVAL;
     }
     for (int t = 0; t < ntimes; ++t)

@@ -15,6 +15,7 @@
 namespace lt {
 
 using cdouble = std::complex<double>;
+constexpr int kMaxRhs = 1000;  // right-hand sides per solve (the host flag buffer holds that many)
 constexpr int kMaxTunedLevels = 16;  // levels whose smoother tile shape can be tuned
 
 // ---------------------------------------------------------------- errors

@@ -41,6 +41,14 @@ def test_bad_arguments_raise(lt):
     with pytest.raises(lt.LTError):
         lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers,
                     lt.make_opts(precond=lt.LT_PRECOND_UNET_GMG))
+    # at most 1000 right-hand sides per call (sources; sources and receivers for the adjoint)
+    many = np.tile(np.asarray(p.sources, dtype=np.float64)[:1], (1001, 1))
+    with pytest.raises(lt.LTError) as e:
+        lt.lt_solve(h, many, p.q, p.times, p.nz_contour, p.receivers)
+    assert e.value.code == lt.LT_EINVAL
+    with pytest.raises(lt.LTError) as e:
+        lt.lt_adjoint(h, many[:999], p.q, many[:2], p.times, p.nz_contour)
+    assert e.value.code == lt.LT_EINVAL
     h.close()
 
 
