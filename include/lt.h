@@ -53,6 +53,7 @@ enum { LT_BC_DIRICHLET0 = 0, LT_BC_NEUMANN0 = 1 };
 enum { LT_PREC_FP64 = 0, LT_PREC_MIXED = 1 };   /* V-cycle in FP64 or FP32   */
 enum { LT_PROF_OFF = 0, LT_PROF_PRE_FINE = 1, LT_PROF_POST_FINE = 2 };
 enum { LT_PRECOND_GMG = 0, LT_PRECOND_UNET_GMG = 1 };
+enum { LT_METHOD_GMRES = 0, LT_METHOD_FOM = 1 };
 
 typedef struct lt_handle lt_handle;
 
@@ -129,7 +130,12 @@ typedef struct {
  *              and size, and replayed; 0 (default): launched kernel by
  *              kernel.  Results are identical.  Needs a handle on a stream
  *              of its own (the legacy default stream cannot be captured;
- *              there, and when profiling, steps are launched directly). */
+ *              there, and when profiling, steps are launched directly).
+ *   method     LT_METHOD_GMRES (default): per shift, y minimises the residual
+ *              over the basis (FGMRES-Sh).  LT_METHOD_FOM: y solves the square
+ *              Hessenberg system (FFOM-Sh), the other variant of the paper's
+ *              flexible shifted algorithm (Section 3); its residual is the
+ *              GMRES one divided by the cosine of the last Givens rotation. */
 typedef struct {
     double tol;
     int maxit;
@@ -144,6 +150,7 @@ typedef struct {
     int precond;
     double net_keep;
     int graph;
+    int method;
 } lt_opts;
 
 /* Statistics of the last call.  Pointer members are optional host arrays the

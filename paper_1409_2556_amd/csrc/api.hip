@@ -109,7 +109,7 @@ int validate_opts(const lt_opts* o) {
     if (!(o->tol > 0.0) || o->maxit < 1 || o->maxit > 2000 || o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 ||
         o->inner_max < 1 || !(o->relax > 0.0) || o->profile < 0 || o->profile > LT_PROF_POST_FINE ||
         (o->precond != LT_PRECOND_GMG && o->precond != LT_PRECOND_UNET_GMG) || !(o->net_keep >= 0.0) ||
-        (o->graph != 0 && o->graph != 1) ||
+        (o->graph != 0 && o->graph != 1) || (o->method != LT_METHOD_GMRES && o->method != LT_METHOD_FOM) ||
         (o->precision != LT_PREC_FP64 && o->precision != LT_PREC_MIXED)) {
         set_last_error("invalid lt_opts");
         return LT_EINVAL;
@@ -485,7 +485,8 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
         LT_TRY(launch_cgs2(st, N, R, j, m, U, ustride, Q, qstride, H, hstride, hrstride, part, pstride, c1, c2,
                            cstride, scale, partn, active));
         if (np > 0) LT_TRY(launch_gather(st, R, N, np, rec->off, rec->cell, rec->wt, U, ustride, j, G, jmax, active));
-        LT_TRY(launch_ls_update(st, R, Ks, j, tau, zs, omega, o.tol, H, hstride, hrstride, beta, ls, active, mcols,
+        LT_TRY(launch_ls_update(st, R, Ks, j, tau, zs, omega, o.tol, o.method == LT_METHOD_FOM, H, hstride, hrstride,
+                                beta, ls, active, mcols,
                                 worst, conv));
     }
     if (!out->converged) {
@@ -495,7 +496,7 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
         for (int r = 0; r < R; ++r) n_active += hact[r];
         out->converged = n_active == 0;
     }
-    LT_TRY(launch_backsolve(st, R, Ks, mcols, ls, Y, jmax));
+    LT_TRY(launch_backsolve(st, R, Ks, mcols, ls, Y, jmax, o.method == LT_METHOD_FOM));
     std::vector<int> hm(R), hv(R), hn(2);
     LT_HIP(hipMemcpyAsync(hn.data(), netc, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     LT_HIP(hipMemcpyAsync(hm.data(), mcols, R * sizeof(int), hipMemcpyDeviceToHost, st));

@@ -53,12 +53,15 @@ int launch_inner_finalize(hipStream_t st, int nb, int R, const double* part, con
 int launch_cgs2(hipStream_t st, int N, int R, int j, const double* m, const double* U, size_t ustride, double* Q,
                 size_t qstride, double* H, int hstride, size_t hrstride, double* part, int pstride, double* c1,
                 double* c2, int cstride, double* scale, double* partn, const int* active);
+// fom: the FOM residual (GMRES residual / cosine of the last rotation) decides convergence
 int launch_ls_update(hipStream_t st, int R, int Ks, int j, cdouble tau, const double* zs, const double* omega,
-                     double tol, const double* H, int hstride, size_t hrstride, const double* beta,
+                     double tol, bool fom, const double* H, int hstride, size_t hrstride, const double* beta,
                      const LSState& s, int* active, int* mcols, double* worst, int* conv);
 int launch_gather(hipStream_t st, int R, int N, int np, const int* off, const int* cell, const double* wt,
                   const double* U, size_t ustride, int j, double* G, int jmax, const int* active);
-int launch_backsolve(hipStream_t st, int R, int Ks, const int* mcols, const LSState& s, double* Y, int jmax);
+// fom: y solves the square Hessenberg system (FOM) instead of the least-squares problem
+int launch_backsolve(hipStream_t st, int R, int Ks, const int* mcols, const LSState& s, double* Y, int jmax,
+                     bool fom = false);
 int launch_heads(hipStream_t st, int R, int np, int ntimes, int nk, const double* wq, const double* G,
                  const double* Y, const int* mcols, int jmax, double* phi);
 int launch_form_x(hipStream_t st, int N, int R, int nc, int k0, int Ks, const double* U, size_t ustride,

@@ -475,7 +475,7 @@ __global__ void k_iter_begin(int R, const int* __restrict__ active, int* __restr
 // Its QR factorisation is extended by one Givens rotation per column; |g_{j+1}| is the
 // GMRES residual norm of the shift.
 __global__ void k_ls_update(int R, int Ks, int j, double tau_re, double tau_im, const double* __restrict__ zs,
-                            const double* __restrict__ omega, double tol, const double* __restrict__ H,
+                            const double* __restrict__ omega, double tol, int fom, const double* __restrict__ H,
                             int hstride, size_t hrstride, const double* __restrict__ beta, LSState st,
                             int* __restrict__ active, int* __restrict__ mcols, double* __restrict__ worst,
                             int* __restrict__ conv_flags) {
@@ -549,7 +549,10 @@ __global__ void k_ls_update(int R, int Ks, int j, double tau_re, double tau_im, 
         st.g[2 * ((size_t)j * P + base) + 1] = gt.im;
         st.g[2 * ((size_t)(j + 1) * P + base)] = gn.re;
         st.g[2 * ((size_t)(j + 1) * P + base) + 1] = gn.im;
+        // FOM: the square system's residual is |h_{j+1,j} y_j| = |g_{j+1}| / c (infinite when the
+        // square system is singular, c = 0)
         double res = hypot(gn.re, gn.im) / beta[r];
+        if (fom) res = c > 0.0 ? res / c : HUGE_VAL;
         double wres = omega[k] * res;
         st.res[base] = res;
         myw = fmax(myw, wres);
@@ -576,8 +579,11 @@ __global__ void k_ls_update(int R, int Ks, int j, double tau_re, double tau_im, 
 }
 
 // y = R^{-1} g for each pair, m = mcols[r] columns.  Y[r][j][k].
+// FOM (fom != 0): the square system shares R and g except in the last row, whose entries
+// before the last rotation are r_mm c and g_m / c, so y_m = g_m / (c^2 r_mm); the other
+// rows back-substitute as before (c = 0, a singular square system, keeps the GMRES y).
 __global__ void k_backsolve(int R, int Ks, const int* __restrict__ mcols, LSState st, double* __restrict__ Y,
-                            int jmax) {
+                            int jmax, int fom) {
     int r = blockIdx.y;
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= Ks) return;
@@ -597,6 +603,13 @@ __global__ void k_backsolve(int R, int Ks, const int* __restrict__ mcols, LSStat
         }
         size_t rj = (size_t)(j * (j + 1) / 2 + j) * P + base;
         c64 y = cd(acc, {st.Rm[2 * rj], st.Rm[2 * rj + 1]});
+        if (fom && j == m - 1) {
+            const double c = st.cs[(size_t)j * P + base];
+            if (c > 0.0) {
+                y.re /= c * c;
+                y.im /= c * c;
+            }
+        }
         Yr[(size_t)j * 2 * Ks + 2 * k] = y.re;
         Yr[(size_t)j * 2 * Ks + 2 * k + 1] = y.im;
     }
@@ -1294,13 +1307,13 @@ int launch_cgs2(hipStream_t st, int N, int R, int j, const double* m, const doub
 }
 
 int launch_ls_update(hipStream_t st, int R, int Ks, int j, cdouble tau, const double* zs, const double* omega,
-                     double tol, const double* H, int hstride, size_t hrstride, const double* beta,
+                     double tol, bool fom, const double* H, int hstride, size_t hrstride, const double* beta,
                      const LSState& s, int* active, int* mcols, double* worst, int* conv) {
     int threads = ((Ks + 63) / 64) * 64;
     if (threads > kB) threads = kB;
     size_t shm = sizeof(double) * 2 * (j + 2);
-    k_ls_update<<<R, threads, shm, st>>>(R, Ks, j, tau.real(), tau.imag(), zs, omega, tol, H, hstride, hrstride,
-                                         beta, s, active, mcols, worst, conv);
+    k_ls_update<<<R, threads, shm, st>>>(R, Ks, j, tau.real(), tau.imag(), zs, omega, tol, fom ? 1 : 0, H, hstride,
+                                         hrstride, beta, s, active, mcols, worst, conv);
     LT_HIP(hipGetLastError());
     return 0;
 }
@@ -1313,8 +1326,9 @@ int launch_gather(hipStream_t st, int R, int N, int np, const int* off, const in
     return 0;
 }
 
-int launch_backsolve(hipStream_t st, int R, int Ks, const int* mcols, const LSState& s, double* Y, int jmax) {
-    k_backsolve<<<dim3(nb_for(Ks), R), kB, 0, st>>>(R, Ks, mcols, s, Y, jmax);
+int launch_backsolve(hipStream_t st, int R, int Ks, const int* mcols, const LSState& s, double* Y, int jmax,
+                     bool fom) {
+    k_backsolve<<<dim3(nb_for(Ks), R), kB, 0, st>>>(R, Ks, mcols, s, Y, jmax, fom ? 1 : 0);
     LT_HIP(hipGetLastError());
     return 0;
 }

@@ -79,3 +79,21 @@ def test_contraction_paths_agree(lt):
             print("contraction paths", sl, err, flush=True)
             assert err <= 1e-10
     h.close()
+
+
+def test_fom_sensitivities_match_oracle(lt):
+    """lt_adjoint with the FOM variant of the flexible shifted method, same bar as GMRES."""
+    spec = CASES["2d_20x16"]
+    p = wl.make_problem(spec["name"], **spec["kw"])
+    announce("adjoint fom", p.n)
+    h = device_problem(lt, p)
+    opts = lt.make_opts(tol=1e-11, precision=0, n_tau=p.n_tau, method=lt.LT_METHOD_FOM)
+    JK, JS, st = lt.lt_adjoint(h, p.sources, p.q, p.receivers, p.times, p.nz_contour, opts)
+    assert st["rc"] == 0
+    rK, rS = jacobian(p.n, p.h, p.kappa, p.S, p.sources, p.receivers, p.times, p.nz_contour, q=p.q, ndim=p.ndim)
+    for got, ref in ((JK.cpu().numpy(), rK), (JS.cpu().numpy(), rS)):
+        scale = np.abs(ref).max(axis=-1, keepdims=True)
+        err = (np.abs(got - ref) / scale).max()
+        print("adjoint fom err", err, flush=True)
+        assert err <= 1e-6
+    h.close()

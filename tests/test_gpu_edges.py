@@ -29,6 +29,7 @@ def test_bad_arguments_raise(lt):
         dict(opts=lt.make_opts(precision=7)),
         dict(opts=lt.make_opts(nu1=0, nu2=0)),
         dict(opts=lt.make_opts(graph=2)),
+        dict(opts=lt.make_opts(method=2)),
         dict(q=float("nan")),
     ]
     for c in cases:
