@@ -70,14 +70,15 @@ def shifted_fields(K, m, rhs, shifts, workers=1):
 
 
 def heads(n, h, kappa, S, sources, receivers, times, nz, q=1.0, bc=(0,) * 6,
-          phi0=None, workers=1, ndim=None):
+          phi0=None, workers=1, ndim=None, sy=0.0):
     """Heads phi[source, receiver, time] (float64).
 
     With ``phi0`` (an [N] initial head) the term M phi0 is added to every
     source's right-hand side with factor 1 (Section 3, the two-system split);
-    ``q = 0`` leaves only the initial-value problem.
+    ``q = 0`` leaves only the initial-value problem.  ``sy`` is the specific
+    yield of the faces that ``bc`` marks as water table.
     """
-    K, m = assemble(n, h, kappa, S, bc, ndim=ndim)
+    K, m = assemble(n, h, kappa, S, bc, ndim=ndim, sy=sy)
     Bs = point_weights(n, h, sources)
     Br = point_weights(n, h, receivers)
     N = K.shape[0]
@@ -108,7 +109,8 @@ def heads(n, h, kappa, S, sources, receivers, times, nz, q=1.0, bc=(0,) * 6,
 def heads_problem(p, workers=1, phi0=None):
     """heads() for a workloads.Problem."""
     return heads(p.n, p.h, p.kappa, p.S, p.sources, p.receivers, p.times,
-                 p.nz_contour, q=p.q, bc=p.bc, phi0=phi0, workers=workers, ndim=p.ndim)
+                 p.nz_contour, q=p.q, bc=p.bc, phi0=phi0, workers=workers, ndim=p.ndim,
+                 sy=p.sy)
 
 
 def default_workers():

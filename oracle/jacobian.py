@@ -17,13 +17,14 @@ reduces to on the FV operator:
 
 With T_f = 2 A k_i k_j / (h (k_i + k_j)):  dT_f / d ln k_i = T_f k_j / (k_i + k_j);
 a Dirichlet wall face T_b = 2 k_i A / h gives dT_b / d ln k_i = T_b;
-dm_c / d ln S_c = m_c.
+dm_c / d ln S_c = S_c V_c (a water-table face's S_y A storage does not
+depend on S, so it stays out of this derivative).
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .fv import assemble, point_weights, _ndim
+from .fv import assemble, point_weights, storage_mass, _ndim
 from .contour import talbot_nodes
 from .heads import shifted_fields
 
@@ -57,12 +58,13 @@ def _face_lists(n, h, kappa, bc, ndim):
 
 
 def jacobian(n, h, kappa, S, sources, receivers, times, nz, q=1.0, bc=(0,) * 6,
-             workers=1, ndim=None):
+             workers=1, ndim=None, sy=0.0):
     """Return (J_lnK, J_lnS), each [ns, nr, nt, N] float64."""
     n = tuple(int(a) for a in n)
     if ndim is None:
         ndim = _ndim(n)
-    K, m = assemble(n, h, kappa, S, bc, ndim=ndim)
+    K, m = assemble(n, h, kappa, S, bc, ndim=ndim, sy=sy)
+    mS = storage_mass(n, h, S)
     Bs = point_weights(n, h, sources)
     Br = point_weights(n, h, receivers)
     N = K.shape[0]
@@ -92,7 +94,7 @@ def jacobian(n, h, kappa, S, sources, receivers, times, nz, q=1.0, bc=(0,) * 6,
             for (i, Tb) in walls:
                 prod = np.einsum("fs,fr->srf", phi[i], psi[i])
                 np.add.at(gK, (slice(None), slice(None), i), Tb * prod)
-            gS = z[k] * m[None, None, :] * np.einsum("cs,cr->src", phi, psi)
+            gS = z[k] * mS[None, None, :] * np.einsum("cs,cr->src", phi, psi)
             accK -= c * gK
             accS -= c * gS
         JK[:, :, it, :] = 2.0 * accK.real

@@ -36,7 +36,8 @@ class Problem:
     times: np.ndarray       # [nt] physical times
     nz_contour: int         # full-contour Talbot nodes per time
     q: float = 1.0          # constant pumping rate from t = 0
-    bc: tuple = (0, 0, 0, 0, 0, 0)   # 0 = zero Dirichlet, 1 = zero Neumann, per face -x,+x,-y,+y,-z,+z
+    bc: tuple = (0, 0, 0, 0, 0, 0)   # 0 = zero Dirichlet, 1 = zero Neumann, 2 = water table; faces -x,+x,-y,+y,-z,+z
+    sy: float = 0.0                  # specific yield of the water-table faces
     n_tau: int = 1
     meta: dict = field(default_factory=dict)
 
