@@ -87,7 +87,7 @@ def _handle(lt, p, tune, nvec):
     S = torch.tensor(p.S, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     stream = torch.cuda.Stream()
-    h = lt.lt_setup(p.ndim, p.n, p.h, kap, S, bc=p.bc, stream=stream)
+    h = lt.lt_setup(p.ndim, p.n, p.h, kap, S, bc=p.bc, stream=stream, sy=p.sy)
     h._torch_stream = stream
     tiles = {}
     if tune:

@@ -49,7 +49,7 @@ enum {
     LT_WNOTCONV = 1       /* maxit reached before every shift met the tolerance */
 };
 
-enum { LT_BC_DIRICHLET0 = 0, LT_BC_NEUMANN0 = 1 };
+enum { LT_BC_DIRICHLET0 = 0, LT_BC_NEUMANN0 = 1, LT_BC_WATER_TABLE = 2 };
 enum { LT_PREC_FP64 = 0, LT_PREC_MIXED = 1 };   /* V-cycle in FP64 or FP32   */
 enum { LT_PROF_OFF = 0, LT_PROF_PRE_FINE = 1, LT_PROF_POST_FINE = 2 };
 enum { LT_PRECOND_GMG = 0, LT_PRECOND_UNET_GMG = 1 };
@@ -66,9 +66,19 @@ typedef struct {
     double h[3];
 } lt_grid;
 
-/* Boundary condition per wall, order -x, +x, -y, +y, -z, +z. */
+/* Boundary condition per wall, order -x, +x, -y, +y, -z, +z
+ * (eqn:timedomain): LT_BC_DIRICHLET0 holds the head at zero,
+ * LT_BC_NEUMANN0 carries no flux, LT_BC_WATER_TABLE is the linearised water
+ * table, whose outward flux is -sy times the rate of change of the head.  A
+ * water-table face carries no conductive flux; its storage sy * (face area)
+ * joins the lumped mass of the cell behind it (the boundary term of M in
+ * Section 2.1), so M = diag(S V) + that term.  sy is the specific yield of
+ * every water-table face (finite, >= 0; ignored when no face has that type).
+ * A water-table face must lie on one of the grid's ndim axes.  The storage
+ * sensitivity (lt_adjoint) differentiates S V only: sy is not a parameter. */
 typedef struct {
     int face[6];
+    double sy;
 } lt_bc;
 
 /* n points (wells); host array xyz[3 n] of coordinates in the domain

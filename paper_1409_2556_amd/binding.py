@@ -20,7 +20,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 LT_OK, LT_EINVAL, LT_EHIP, LT_ENOMEM, LT_EUNSUPPORTED, LT_WNOTCONV = 0, -1, -2, -3, -4, 1
-LT_BC_DIRICHLET0, LT_BC_NEUMANN0 = 0, 1
+LT_BC_DIRICHLET0, LT_BC_NEUMANN0, LT_BC_WATER_TABLE = 0, 1, 2
 LT_PREC_FP64, LT_PREC_MIXED = 0, 1
 LT_PROF_OFF, LT_PROF_PRE_FINE, LT_PROF_POST_FINE = 0, 1, 2
 LT_PRECOND_GMG, LT_PRECOND_UNET_GMG = 0, 1
@@ -32,7 +32,7 @@ class lt_grid(C.Structure):
 
 
 class lt_bc(C.Structure):
-    _fields_ = [("face", C.c_int * 6)]
+    _fields_ = [("face", C.c_int * 6), ("sy", C.c_double)]
 
 
 class lt_points(C.Structure):
@@ -218,9 +218,9 @@ class Handle:
             pass
 
 
-def lt_setup(ndim, n, h, kappa, S, bc=(0, 0, 0, 0, 0, 0), stream=None) -> Handle:
+def lt_setup(ndim, n, h, kappa, S, bc=(0, 0, 0, 0, 0, 0), stream=None, sy=0.0) -> Handle:
     g = lt_grid(int(ndim), (C.c_int * 3)(*[int(a) for a in n]), (C.c_double * 3)(*[float(a) for a in h]))
-    b = lt_bc((C.c_int * 6)(*[int(a) for a in bc]))
+    b = lt_bc((C.c_int * 6)(*[int(a) for a in bc]), float(sy))
     out = _h()
     sp = _stream_ptr(stream)
     _check(_lib.lt_setup(C.byref(g), _dev_f64(kappa, "kappa"), _dev_f64(S, "S"), C.byref(b), sp, C.byref(out)))

@@ -12,6 +12,7 @@
 // relaxation keeps it below the tolerance (inexact Krylov).  The FP64 true
 // residual of every (rhs, shift) is computed at exit.
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -659,12 +660,29 @@ int lt_setup(const lt_grid* grid, const double* kappa, const double* S, const lt
         h->bc = *bc;
     else
         std::memset(&h->bc, 0, sizeof(h->bc));
+    bool water_table = false;
     for (int f = 0; f < 6; ++f) {
-        if (h->bc.face[f] != LT_BC_DIRICHLET0 && h->bc.face[f] != LT_BC_NEUMANN0) {
+        const int t = h->bc.face[f];
+        if (t != LT_BC_DIRICHLET0 && t != LT_BC_NEUMANN0 && t != LT_BC_WATER_TABLE) {
             delete h;
             set_last_error("lt_setup: unknown boundary condition");
             return LT_EINVAL;
         }
+        if (t == LT_BC_WATER_TABLE) {
+            if (f / 2 >= grid->ndim) {
+                delete h;
+                set_last_error("lt_setup: a water-table face must lie on a grid axis");
+                return LT_EINVAL;
+            }
+            water_table = true;
+        }
+    }
+    if (!water_table)
+        h->bc.sy = 0.0;
+    else if (!(h->bc.sy >= 0.0) || !std::isfinite(h->bc.sy)) {
+        delete h;
+        set_last_error("lt_setup: the specific yield must be finite and >= 0");
+        return LT_EINVAL;
     }
     h->stream = static_cast<hipStream_t>(hip_stream);
     if (hipGetDevice(&h->device) != hipSuccess) {
@@ -859,8 +877,10 @@ int lt_adjoint(lt_handle* h, const lt_points* sources, double q, const lt_points
     if (!X) return rc;
     for (int t = 0; t < ntimes; ++t) {
         LT_TRY(launch_form_x(h->stream, h->N, R, nk, t * nk, k.Ks, k.U, k.ustride, k.Y, k.jmax, k.mcols, X));
-        LT_TRY(launch_sens(h->stream, h->levels[0].v64(), h->kappa.as<double>(), ns, nr, nk, t, ntimes, X, k.zs,
-                           k.wq, dlnK, dlnS));
+        const LevelView<double> L0 = h->levels[0].v64();
+        const double* mS = h->mstor.p ? h->mstor.as<double>() : L0.m;
+        LT_TRY(launch_sens(h->stream, L0, h->kappa.as<double>(), mS, ns, nr, nk, t, ntimes, X, k.zs, k.wq, dlnK,
+                           dlnS));
     }
     if (o.true_residual) LT_TRY(true_residuals(h, k, plan, stats));
     LT_HIP(hipStreamSynchronize(h->stream));

@@ -70,7 +70,8 @@ template <typename T>
 int launch_net_scale(hipStream_t st, LevelView<double> L, cdouble tau, int R, T* d, const double* v, double* part,
                      const int* active);
 int launch_net_guard(hipStream_t st, int R, int nb, const double* part, const int* active, int* bad, int* counts);
-int launch_sens(hipStream_t st, LevelView<double> L, const double* kappa, int ns, int nr, int nk, int t, int ntimes,
-                const double* X, const double* zs, const double* wq, double* JK, double* JS);
+// mS: the storage part S V of the fine-level mass (L.m less any water-table term)
+int launch_sens(hipStream_t st, LevelView<double> L, const double* kappa, const double* mS, int ns, int nr, int nk,
+                int t, int ntimes, const double* X, const double* zs, const double* wq, double* JK, double* JS);
 
 }  // namespace lt

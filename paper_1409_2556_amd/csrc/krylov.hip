@@ -880,7 +880,8 @@ int launch_true_residual_cols(hipStream_t st, LevelView<double> L, int R, int Ks
 // the loops unroll and all loads of a shift are in flight together.
 constexpr int kSensS = 1;
 constexpr int kSensM = 2;
-__global__ __launch_bounds__(256) void k_sens(LevelView<double> L, const double* __restrict__ kappa, int ns, int nr,
+__global__ __launch_bounds__(256) void k_sens(LevelView<double> L, const double* __restrict__ kappa,
+                                              const double* __restrict__ mS, int ns, int nr,
                                               int nk, int t, int ntimes, const double* __restrict__ X,
                                               const double* __restrict__ zs, const double* __restrict__ wq,
                                               double* __restrict__ JK, double* __restrict__ JS) {
@@ -915,7 +916,7 @@ __global__ __launch_bounds__(256) void k_sens(LevelView<double> L, const double*
         wf[f] = has[f] ? T * kj / (kc + kj) : 0.0;
     }
     const double wall = L.D[c] - tin;  // walls of this cell; their T is proportional to k_c
-    const double mc = L.m[c];
+    const double mc = mS[c];  // S V: the storage the parameter owns
     double aK[kSensS][kSensM], aS[kSensS][kSensM];
 #pragma unroll
     for (int a = 0; a < kSensS; ++a)
@@ -989,7 +990,8 @@ constexpr int kSensA = 8, kSensB = 7;      // staged slots per source / receiver
 constexpr int kSensFS = 2 * kSensA * kSensCB + 2;
 static_assert(kSensFS >= 2 * kSensB * kSensCB && (2 * kSensFS) % 32 == 4, "staged field stride");
 
-__global__ __launch_bounds__(256) void k_sens_tile(LevelView<double> L, const double* __restrict__ kappa, int ns,
+__global__ __launch_bounds__(256) void k_sens_tile(LevelView<double> L, const double* __restrict__ kappa,
+                                                   const double* __restrict__ mS, int ns,
                                                    int nr, int nk, int t, int ntimes, const double* __restrict__ X,
                                                    const double* __restrict__ zs, const double* __restrict__ wq,
                                                    double* __restrict__ JK, double* __restrict__ JS) {
@@ -1046,7 +1048,7 @@ __global__ __launch_bounds__(256) void k_sens_tile(LevelView<double> L, const do
         }
         Nb[0][q] = cc;
         Wall[q] = L.D[cc] - tin;  // walls of this cell; their T is proportional to k_c
-        Mc[q] = L.m[cc];
+        Mc[q] = mS[cc];
     }
     double accK[kSensTS][kSensTM], accS[kSensTS][kSensTM];
 #pragma unroll
@@ -1161,16 +1163,16 @@ __global__ __launch_bounds__(256) void k_sens_tile(LevelView<double> L, const do
         }
 }
 
-int launch_sens(hipStream_t st, LevelView<double> L, const double* kappa, int ns, int nr, int nk, int t, int ntimes,
-                const double* X, const double* zs, const double* wq, double* JK, double* JS) {
+int launch_sens(hipStream_t st, LevelView<double> L, const double* kappa, const double* mS, int ns, int nr, int nk,
+                int t, int ntimes, const double* X, const double* zs, const double* wq, double* JK, double* JS) {
     const size_t shm = sizeof(double) * (size_t)(ns + nr) * kSensFS;
     if (shm <= 64 * 1024) {
         const int groups = ((ns + kSensTS - 1) / kSensTS) * ((nr + kSensTM - 1) / kSensTM);
         dim3 grid((unsigned)((L.N + kSensCB - 1) / kSensCB), (unsigned)((groups + kSensTPC - 1) / kSensTPC));
-        k_sens_tile<<<grid, kB, shm, st>>>(L, kappa, ns, nr, nk, t, ntimes, X, zs, wq, JK, JS);
+        k_sens_tile<<<grid, kB, shm, st>>>(L, kappa, mS, ns, nr, nk, t, ntimes, X, zs, wq, JK, JS);
     } else {
         dim3 grid((unsigned)((L.N + kB - 1) / kB), (ns + kSensS - 1) / kSensS, (nr + kSensM - 1) / kSensM);
-        k_sens<<<grid, kB, 0, st>>>(L, kappa, ns, nr, nk, t, ntimes, X, zs, wq, JK, JS);
+        k_sens<<<grid, kB, 0, st>>>(L, kappa, mS, ns, nr, nk, t, ntimes, X, zs, wq, JK, JS);
     }
     LT_HIP(hipGetLastError());
     return 0;

@@ -88,6 +88,7 @@ struct lt_handle {
     std::vector<lt::CoarseInverse> coarse_cache;
     std::vector<double> coarse_host;  // coarsest level coefficients [5][Nc] on the host
     lt::DevBuf kappa;                 // copy of the fine-grid conductivity (sensitivities)
+    lt::DevBuf mstor;                 // S V per fine cell when water-table storage joins the mass
     // tile shape id of the fused 2D smoothers per level, [0]: FP64, [1]: FP32 (lt_autotune)
     int tiles[2][16] = {};
     double lnDbar = 0.0;              // mean of ln D over the fine grid (network features)

@@ -81,9 +81,12 @@ __device__ __forceinline__ cpx<T> offsum(const LevelView<T>& L, const T* xr, con
 // ------------------------------------------------------------------ assembly
 // Fine-level coefficients from kappa and S.  out = [Tx, Ty, Tz, D(unused here), m],
 // walls = [Wx, Wy, Wz] (wall transmissibility per axis, summed over both walls).
+// A water-table wall adds sy * area to m (no conductive flux); mstor, when
+// given, receives the storage part S V alone.
 __global__ void k_fine_assemble(const double* __restrict__ kappa, const double* __restrict__ S, int nx,
                                 int ny, int nz, int ndim, double hx, double hy, double hz, int4 bclo,
-                                int4 bchi, double* __restrict__ out, double* __restrict__ walls) {
+                                int4 bchi, double sy, double* __restrict__ out, double* __restrict__ walls,
+                                double* __restrict__ mstor) {
     const int N = nx * ny * nz;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
@@ -96,6 +99,7 @@ __global__ void k_fine_assemble(const double* __restrict__ kappa, const double* 
     int lo[3] = {bclo.x, bclo.y, bclo.z};
     int hi[3] = {bchi.x, bchi.y, bchi.z};
     double ki = kappa[i];
+    double wt = 0.0;  // water-table storage of this cell's walls
     for (int a = 0; a < 3; ++a) {
         double T = 0.0, W = 0.0;
         if (a < ndim) {
@@ -106,11 +110,15 @@ __global__ void k_fine_assemble(const double* __restrict__ kappa, const double* 
             }
             if (c[a] == 0 && lo[a] == LT_BC_DIRICHLET0) W += 2.0 * ki * area / h[a];
             if (c[a] == n[a] - 1 && hi[a] == LT_BC_DIRICHLET0) W += 2.0 * ki * area / h[a];
+            if (c[a] == 0 && lo[a] == LT_BC_WATER_TABLE) wt += sy * area;
+            if (c[a] == n[a] - 1 && hi[a] == LT_BC_WATER_TABLE) wt += sy * area;
         }
         out[(size_t)a * N + i] = T;
         walls[(size_t)a * N + i] = W;
     }
-    out[(size_t)4 * N + i] = S[i] * V;
+    const double ms = S[i] * V;
+    out[(size_t)4 * N + i] = ms + wt;
+    if (mstor) mstor[i] = ms;
 }
 
 // Aggregate a fine level into a coarse one (see the file comment).
@@ -447,9 +455,14 @@ int mg_build(lt_handle* h, const double* kappa, const double* S) {
     LT_TRY(walls_f.reserve(sizeof(double) * 3 * (size_t)f.N));
     int4 lo = {h->bc.face[0], h->bc.face[2], h->bc.face[4], 0};
     int4 hi = {h->bc.face[1], h->bc.face[3], h->bc.face[5], 0};
+    double* mstor = nullptr;
+    if (h->bc.sy > 0.0) {
+        LT_TRY(h->mstor.reserve(sizeof(double) * (size_t)f.N));
+        mstor = h->mstor.as<double>();
+    }
     k_fine_assemble<<<nblk(f.N), kBlock, 0, st>>>(kappa, S, f.n[0], f.n[1], f.n[2], g.ndim, f.h[0], f.h[1],
-                                                   f.h[2], lo, hi, lv[0].c64.as<double>(),
-                                                   walls_f.as<double>());
+                                                   f.h[2], lo, hi, h->bc.sy, lv[0].c64.as<double>(),
+                                                   walls_f.as<double>(), mstor);
     LT_HIP(hipGetLastError());
     k_finish_diag<<<nblk(f.N), kBlock, 0, st>>>(lv[0].c64.as<double>(), walls_f.as<double>(), f.n[0], f.n[1],
                                                 f.n[2]);
@@ -625,8 +638,10 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
         if (!xpost[l]) return rc;
     }
     xpost[0] = x0;
-    const T gsign[2] = {T(-1), T(1)};  // Dirichlet, Neumann ghost parity
-    auto g = [&](int face) { return gsign[h->bc.face[face] == LT_BC_NEUMANN0 ? 1 : 0]; };
+    // ghost parity of the correction at a wall: odd at a Dirichlet wall, even at
+    // a no-flux one (a water-table wall carries no conductive flux either)
+    const T gsign[2] = {T(-1), T(1)};
+    auto g = [&](int face) { return gsign[h->bc.face[face] == LT_BC_DIRICHLET0 ? 0 : 1]; };
     // ---- down
     for (int l = 0; l < lc; ++l) {
         const Level& L = h->levels[l];

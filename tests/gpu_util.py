@@ -6,7 +6,7 @@ def device_problem(lt, p, bc=None):
     import torch
     kap = torch.tensor(p.kappa, dtype=torch.float64, device="cuda")
     S = torch.tensor(p.S, dtype=torch.float64, device="cuda")
-    return lt.lt_setup(p.ndim, p.n, p.h, kap, S, bc=bc if bc is not None else p.bc)
+    return lt.lt_setup(p.ndim, p.n, p.h, kap, S, bc=bc if bc is not None else p.bc, sy=p.sy)
 
 
 def rel_err_per_source(got, ref):
@@ -27,6 +27,6 @@ def device_problem_on_stream(lt, p):
     S = torch.tensor(p.S, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     s = torch.cuda.Stream()
-    h = lt.lt_setup(p.ndim, p.n, p.h, kap, S, bc=p.bc, stream=s)
+    h = lt.lt_setup(p.ndim, p.n, p.h, kap, S, bc=p.bc, stream=s, sy=p.sy)
     h._torch_stream = s
     return h

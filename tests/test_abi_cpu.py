@@ -1,6 +1,7 @@
 """The C ABI library loads without a GPU and exports every function that
 include/lt.h declares; host-only entry points behave (no GPU compute)."""
 import ctypes
+import ctypes as C
 import os
 import re
 
@@ -67,3 +68,22 @@ def test_error_codes_without_gpu(lib):
     assert so.lt_tile_shape(4, lib.C.byref(tx), lib.C.byref(tx)) == lib.LT_EINVAL
     assert so.lt_autotune(None, 0, 2, 2, 1, None, 0, None) == lib.LT_EINVAL
     assert so.lt_set_tiles(None, 0, None, 0) == lib.LT_EINVAL
+
+
+def test_setup_rejects_bad_water_table_without_gpu(lib):
+    """Boundary arguments are checked before any device call."""
+    so = lib._lib
+    buf = np.ones(16)
+    ptr = buf.ctypes.data_as(lib._vp) if hasattr(lib, "_vp") else buf.ctypes.data
+    g = lib.lt_grid(2, (C.c_int * 3)(4, 4, 1), (C.c_double * 3)(0.25, 0.25, 1.0))
+    out = lib._h()
+    assert C.sizeof(lib.lt_bc) == 32
+    for faces, sy in (((0, 0, 0, 0, 0, 2), 0.1),        # water table on a wall a 2D grid lacks
+                      ((0, 0, 0, 2, 0, 0), -1.0),       # negative specific yield
+                      ((0, 0, 0, 2, 0, 0), float("nan")),
+                      ((0, 0, 0, 3, 0, 0), 0.0)):       # unknown type
+        b = lib.lt_bc((C.c_int * 6)(*faces), sy)
+        assert so.lt_setup(C.byref(g), ptr, ptr, C.byref(b), None, C.byref(out)) == lib.LT_EINVAL
+    # a valid water table passes the checks and stops only at the missing device
+    b = lib.lt_bc((C.c_int * 6)(0, 0, 0, 2, 0, 0), 0.1)
+    assert so.lt_setup(C.byref(g), ptr, ptr, C.byref(b), None, C.byref(out)) == lib.LT_EHIP
