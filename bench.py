@@ -77,7 +77,31 @@ def _parse():
     ap.add_argument("--workload", choices=["C2", "C3", "C5"], default="C2",
                     help="C2: the 256x256 workload (default); C3: sensitivities (lt_adjoint) of the "
                          "64x64x32 workload; C5: the batch of six uneven 2D/3D grids in one lt_solve_batch call")
+    ap.add_argument("--water-table", type=float, default=None, metavar="SY",
+                    help="C2/C3: make the top wall (+y in 2D, +z in 3D) a linearised water table with this "
+                         "specific yield (the other walls keep zero head)")
+    ap.add_argument("--n-tau", type=int, default=None,
+                    help="C2/C3: preconditioner shifts cycled over the outer iterations (default: the workload's)")
     return ap.parse_args()
+
+
+def _with_boundary(p, args):
+    """The workload, with its top wall turned into a water table when asked (--water-table),
+    and another preconditioner-shift count (--n-tau)."""
+    from dataclasses import replace
+    if args.n_tau is not None:
+        p = replace(p, n_tau=int(args.n_tau))
+    if args.water_table is None:
+        return p
+    bc = list(p.bc)
+    bc[2 * p.ndim - 1] = 2
+    return replace(p, bc=tuple(bc), sy=float(args.water_table))
+
+
+def _boundary_config(p):
+    if p.sy > 0 or 2 in p.bc:
+        return {"boundary": "zero head, water table on the top wall", "sy": p.sy}
+    return {}
 
 
 def _handle(lt, p, tune, nvec):
@@ -162,7 +186,7 @@ def _cpu_baseline(p, ntimes):
     workers = min(os.cpu_count() or 1, 16)
     t0 = time.perf_counter()
     ref = heads(p.n, p.h, p.kappa, p.S, p.sources, p.receivers, p.times[:ntimes], p.nz_contour,
-                q=p.q, bc=p.bc, workers=workers, ndim=p.ndim)
+                q=p.q, bc=p.bc, workers=workers, ndim=p.ndim, sy=p.sy)
     dt = time.perf_counter() - t0
     pairs = len(p.sources) * ntimes * (p.nz_contour // 2)
     return ref, {"value": pairs / dt, "unit": "shifted solves/s", "cores": workers, "kind": "oracle",
@@ -181,7 +205,7 @@ def main():
     if args.workload == "C3":
         return main_adjoint(args)
     import workloads as wl
-    p = wl.make_problem(WORKLOAD)
+    p = _with_boundary(wl.make_problem(WORKLOAD), args)
     # the CPU oracle runs first, before this process touches the GPU
     cpu, ref = None, None
     nt = args.cpu_sample_times
@@ -296,7 +320,7 @@ def main():
                    "pairs": pairs, "tol": head["tol"], "relax": args.relax, "variant": hname,
                    "precision": "FP32 V-cycle, FP64 outer",
                    "iters": head["st"]["iters_max"], "vcycles": head["st"]["vcycles"],
-                   "source_groups": groups, "smoother_tiles": tiles},
+                   "source_groups": groups, "smoother_tiles": tiles, "n_tau": p.n_tau, **_boundary_config(p)},
         "variants": {
             name: {"solves_per_s": pairs / r["dt"], "ms_per_step": r["dt"] * 1e3, "tol": r["tol"],
                    "iters": r["st"]["iters_max"], "vcycles": r["st"]["vcycles"],
@@ -334,7 +358,7 @@ def main_adjoint(args):
     sides x 24 shifts = 1,752 shifted solves per lt_adjoint call, contracted to d phi / d ln kappa
     and d phi / d ln S of every cell for 25 x 48 x 2 (source, receiver, time) triples."""
     import workloads as wl
-    p = wl.make_problem("C3")
+    p = _with_boundary(wl.make_problem("C3"), args)
     nrhs = len(p.sources) + len(p.receivers)
     pairs = nrhs * len(p.times) * (p.nz_contour // 2)
     cpu, ref = None, None
@@ -345,7 +369,7 @@ def main_adjoint(args):
         workers = min(os.cpu_count() or 1, 16)
         t0 = time.perf_counter()
         ref = heads(p.n, p.h, p.kappa, p.S, p.sources, p.receivers, p.times[:1], p.nz_contour, q=p.q, bc=p.bc,
-                    workers=workers, ndim=p.ndim)
+                    workers=workers, ndim=p.ndim, sy=p.sy)
         dt = time.perf_counter() - t0
         nshift = p.nz_contour // 2
         cpu = {"value": nrhs * nshift / dt, "unit": "shifted solves/s", "cores": workers, "kind": "oracle",
@@ -410,7 +434,8 @@ def main_adjoint(args):
                                "receivers (adjoint), times {0.3, 1.2}, 24-node Talbot, 3 tau, lt_adjoint "
                                "(d phi / d ln kappa and d ln S of every cell)",
                    "rhs": nrhs, "pairs": pairs, "variant": "mixed", "tol": head["tol"],
-                   "iters": head["st"]["iters_max"], "vcycles": head["st"]["vcycles"]},
+                   "iters": head["st"]["iters_max"], "vcycles": head["st"]["vcycles"], "n_tau": p.n_tau,
+                   **_boundary_config(p)},
         "variants": {n: {"solves_per_s": pairs / r["dt"], "ms_per_step": r["dt"] * 1e3, "tol": r["tol"],
                          "iters": r["st"]["iters_max"], "vcycles": r["st"]["vcycles"],
                          "true_relres_weighted_max": r["st"]["true_relres_max"]} for n, r in res.items()},
