@@ -54,6 +54,7 @@ enum { LT_PREC_FP64 = 0, LT_PREC_MIXED = 1 };   /* V-cycle in FP64 or FP32   */
 enum { LT_PROF_OFF = 0, LT_PROF_PRE_FINE = 1, LT_PROF_POST_FINE = 2 };
 enum { LT_PRECOND_GMG = 0, LT_PRECOND_UNET_GMG = 1 };
 enum { LT_METHOD_GMRES = 0, LT_METHOD_FOM = 1 };
+enum { LT_CONV_WEIGHTED = 0, LT_CONV_RELATIVE = 1 };
 
 typedef struct lt_handle lt_handle;
 
@@ -145,7 +146,12 @@ typedef struct {
  *              over the basis (FGMRES-Sh).  LT_METHOD_FOM: y solves the square
  *              Hessenberg system (FFOM-Sh), the other variant of the paper's
  *              flexible shifted algorithm (Section 3); its residual is the
- *              GMRES one divided by the cosine of the last Givens rotation. */
+ *              GMRES one divided by the cosine of the last Givens rotation.
+ *   conv       LT_CONV_WEIGHTED (default): the weighted test under tol above.
+ *              LT_CONV_RELATIVE: every shift until ||r_k|| <= tol ||b||, the
+ *              plain relative residual test of the experiments in Section
+ *              4.1 (stricter: shifts of small weight are solved as far as
+ *              the others). */
 typedef struct {
     double tol;
     int maxit;
@@ -161,6 +167,7 @@ typedef struct {
     double net_keep;
     int graph;
     int method;
+    int conv;
 } lt_opts;
 
 /* Statistics of the last call.  Pointer members are optional host arrays the

@@ -25,6 +25,7 @@ LT_PREC_FP64, LT_PREC_MIXED = 0, 1
 LT_PROF_OFF, LT_PROF_PRE_FINE, LT_PROF_POST_FINE = 0, 1, 2
 LT_PRECOND_GMG, LT_PRECOND_UNET_GMG = 0, 1
 LT_METHOD_GMRES, LT_METHOD_FOM = 0, 1
+LT_CONV_WEIGHTED, LT_CONV_RELATIVE = 0, 1
 
 
 class lt_grid(C.Structure):
@@ -48,7 +49,7 @@ class lt_opts(C.Structure):
                 ("tau_reim", C.POINTER(C.c_double)), ("nu1", C.c_int), ("nu2", C.c_int),
                 ("inner_max", C.c_int), ("relax", C.c_double), ("true_residual", C.c_int),
                 ("profile", C.c_int), ("precond", C.c_int), ("net_keep", C.c_double),
-                ("graph", C.c_int), ("method", C.c_int)]
+                ("graph", C.c_int), ("method", C.c_int), ("conv", C.c_int)]
 
 
 class lt_stats(C.Structure):

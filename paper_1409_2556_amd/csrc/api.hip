@@ -111,6 +111,7 @@ int validate_opts(const lt_opts* o) {
         o->inner_max < 1 || !(o->relax > 0.0) || o->profile < 0 || o->profile > LT_PROF_POST_FINE ||
         (o->precond != LT_PRECOND_GMG && o->precond != LT_PRECOND_UNET_GMG) || !(o->net_keep >= 0.0) ||
         (o->graph != 0 && o->graph != 1) || (o->method != LT_METHOD_GMRES && o->method != LT_METHOD_FOM) ||
+        (o->conv != LT_CONV_WEIGHTED && o->conv != LT_CONV_RELATIVE) ||
         (o->precision != LT_PREC_FP64 && o->precision != LT_PREC_MIXED)) {
         set_last_error("invalid lt_opts");
         return LT_EINVAL;

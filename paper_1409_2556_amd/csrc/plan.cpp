@@ -65,6 +65,7 @@ int make_plan(const double* times, int ntimes, int nz, double q, const lt_opts* 
             const cdouble v = p->wq[(size_t)t * p->nk + k], zk = p->z[(size_t)t * p->nk + k];
             double a = mx > 0 ? std::abs(v) / mx : 1.0;
             if (storage && mz > 0) a = std::max(a, std::abs(v * zk) / mz);
+            if (o->conv == LT_CONV_RELATIVE) a = 1.0;  // every shift to tol ||b||
             p->omega[(size_t)t * p->nk + k] = a;
         }
     }

@@ -51,7 +51,7 @@ def test_error_codes_without_gpu(lib):
         assert lib.lt_strerror(c).startswith("LT_")
     o = lib.lt_opts_default()
     assert o.tol == 1e-10 and o.nu1 == 2 and o.nu2 == 2 and o.precision == lib.LT_PREC_FP64
-    assert o.method == lib.LT_METHOD_GMRES and o.graph == 0
+    assert o.method == lib.LT_METHOD_GMRES and o.graph == 0 and o.conv == lib.LT_CONV_WEIGHTED
     so.lt_destroy(None)  # accepted
     # batches are checked before any GPU work: no items, too many, a missing handle
     items = (lib.lt_solve_item * 2)()

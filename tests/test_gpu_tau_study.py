@@ -1,0 +1,34 @@
+"""The one-shift against several-shift comparison of Section 4.1 on the
+single-well workload: both preconditioner schedules reach the oracle's heads,
+and cycling several shifts takes fewer outer iterations than the single
+shift (the trend of the paper's Tables 1-3)."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle.heads import heads_problem
+from gpu_util import device_problem, rel_err_per_source, announce
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("relax,inner_max,conv", [(1e-4, 60, 1), (3.0, 30, 1), (3.0, 30, 0)])
+def test_flexible_beats_single_and_both_match_oracle(lt, relax, inner_max, conv):
+    p = wl.make_problem("W1", n=(64, 64))
+    announce("tau study", p.n, relax, conv)
+    ref = heads_problem(p)
+    h = device_problem(lt, p)
+    its = {}
+    for n_tau in (1, 2):
+        opts = lt.make_opts(tol=1e-10, precision=lt.LT_PREC_FP64, n_tau=n_tau, relax=relax,
+                            inner_max=inner_max, maxit=400, conv=conv)
+        phi, st = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, opts)
+        err = rel_err_per_source(phi.cpu().numpy(), ref)
+        print("n_tau", n_tau, "iters", st["iters_max"], "err", err.max(), flush=True)
+        assert st["rc"] == 0
+        assert err.max() <= 1e-6
+        if conv == lt.LT_CONV_RELATIVE:   # every shift's own residual meets the tolerance
+            assert st["true_relres"].max() <= 5e-10
+        its[n_tau] = st["iters_max"]
+    assert its[2] < its[1]
+    h.close()

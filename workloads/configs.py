@@ -63,12 +63,14 @@ def _field(n, h, ell, var, seed):
 
 def make_problem(name: str, n: Optional[tuple] = None, seed: Optional[int] = None,
                  literal_times: bool = False, nsrc: Optional[int] = None,
-                 nrec: Optional[int] = None, ntimes: Optional[int] = None) -> Problem:
+                 nrec: Optional[int] = None, ntimes: Optional[int] = None,
+                 var: Optional[float] = None) -> Problem:
     """Build one of the named workloads, optionally reduced in size.
 
     ``n`` replaces the grid (the unit domain is kept, so the spacing
     follows), ``seed`` the field seed, ``nsrc``/``nrec``/``ntimes`` keep the
-    first few sources, receivers or times.
+    first few sources, receivers or times, ``var`` replaces the variance of
+    ln kappa.
     """
     spec = dict(CONFIGS[name])
     nn = tuple(n) if n is not None else spec["n"]
@@ -76,7 +78,7 @@ def make_problem(name: str, n: Optional[tuple] = None, seed: Optional[int] = Non
     ext = spec.get("extent", (1.0,) * ndim)
     h = tuple(e / a for e, a in zip(ext, nn))
     s = spec["seed"] if seed is None else seed
-    kappa = _field(nn, h, spec["ell"], spec["var"], s)
+    kappa = _field(nn, h, spec["ell"], spec["var"] if var is None else float(var), s)
     N = int(np.prod(nn))
     if spec.get("S_loguniform"):
         lo, hi = spec["S_loguniform"]
@@ -134,6 +136,13 @@ CONFIGS = {
                S_loguniform=(1e-6, 1e-4), S_seed=302,
                sources=_C3_SOURCES, receivers=_C3_RECEIVERS,
                times=[0.3, 1.2], nz=24, n_tau=3),
+    # the single-well test of Section 4.1: one well pumping at the centre, observed at (0.7, 0.7)
+    # (the paper's (50, 50) and (70, 70) m in its 100 m square), ln kappa variance 1.6, the
+    # 5 minute sample (0.3 diffusion times), 40-node contour, 128x128 cells
+    "W1": dict(n=(128, 128), var=1.6, ell=(0.2, 0.2, 0.2), seed=401, S=1e-5,
+               sources=[(0.5, 0.5, 0.0)],
+               receivers=[(0.7, 0.7, 0.0), (0.3, 0.7, 0.0), (0.7, 0.3, 0.0), (0.3, 0.3, 0.0)],
+               times=[0.3], nz=40, n_tau=1),
     # learned-preconditioner evaluation fields (training fields use seeds 10000+)
     "C4_256": dict(n=(256, 256), var=1.0, ell=(0.1, 0.1, 0.1), seed=20000, S=1e-5,
                    sources=_C2_SOURCES, receivers=_C2_WELLS, times=[0.3], nz=40, n_tau=1),
