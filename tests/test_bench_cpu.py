@@ -25,3 +25,19 @@ def test_group_statistics_merge():
     assert m == {"rc": 1, "iters_max": 22, "vcycles": 882, "true_relres_max": 8e-7, "net_applied": 2,
                  "net_disabled_at": 2}
     assert bench._merge_stats([a]) is a
+
+
+def test_water_table_and_tau_options():
+    sys.path.insert(0, ROOT)
+    import argparse
+    import bench
+    import workloads as wl
+    p2 = wl.make_problem("C1")
+    p3 = wl.make_problem("C3", n=(8, 6, 4))
+    a = argparse.Namespace(water_table=1e-4, n_tau=3)
+    q2, q3 = bench._with_boundary(p2, a), bench._with_boundary(p3, a)
+    assert q2.bc == (0, 0, 0, 2, 0, 0) and q2.sy == 1e-4 and q2.n_tau == 3   # +y in 2D
+    assert q3.bc == (0, 0, 0, 0, 0, 2) and q3.sy == 1e-4                      # +z in 3D
+    assert bench._boundary_config(q3)["sy"] == 1e-4
+    same = bench._with_boundary(p2, argparse.Namespace(water_table=None, n_tau=None))
+    assert same is p2 and bench._boundary_config(same) == {}
