@@ -101,3 +101,38 @@ def test_sensitivities_match_oracle(lt, case):
         print(case, "adjoint err", err, flush=True)
         assert err <= 1e-6
     h.close()
+
+
+def test_batch_mixes_boundaries_bit_exactly(lt):
+    """One lt_solve_batch call over a water-table problem and a zero-head problem on other grids
+    gives, bit for bit, the heads of the two single calls (the boundary lives in the handle)."""
+    from gpu_util import device_problem_on_stream
+    pw = _problem("2d_ragged_30x22")
+    pd = wl.make_problem("C3", n=(10, 6, 5), nsrc=2, nrec=4)
+    announce("water-table batch", pw.n, pd.n)
+    hs = [device_problem_on_stream(lt, q) for q in (pw, pd)]
+    o = lt.make_opts(tol=1e-10, precision=lt.LT_PREC_FP64, n_tau=2)
+    singles = [lt.lt_solve(h, q.sources, q.q, q.times, q.nz_contour, q.receivers, o)[0].cpu().numpy()
+               for h, q in zip(hs, (pw, pd))]
+    items = [dict(handle=h, sources=q.sources, q=q.q, times=q.times, nz=q.nz_contour, receivers=q.receivers,
+                  opts=o) for h, q in zip(hs, (pw, pd))]
+    phis, sts, rc = lt.lt_solve_batch(items)
+    assert rc == 0
+    for got, want in zip(phis, singles):
+        np.testing.assert_array_equal(got.cpu().numpy(), want)
+    ref = heads_problem(pw)
+    assert rel_err_per_source(singles[0], ref).max() <= 1e-6
+    for h in hs:
+        h.close()
+
+
+def test_fom_variant_with_water_table(lt):
+    p = _problem("3d_ragged_10x6x5")
+    announce("water-table fom", p.n)
+    ref = heads_problem(p)
+    h = device_problem(lt, p)
+    opts = lt.make_opts(tol=1e-10, precision=0, n_tau=p.n_tau, method=lt.LT_METHOD_FOM)
+    phi, st = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, opts)
+    assert st["rc"] == 0
+    assert rel_err_per_source(phi.cpu().numpy(), ref).max() <= 1e-6
+    h.close()
