@@ -196,8 +196,11 @@ void lt_opts_default(lt_opts* o);
  * grid cells, float64, x fastest; both strictly positive) and the multigrid
  * hierarchy.  hip_stream is a hipStream_t (NULL = the default stream); all
  * later work of the handle goes to it.  The handle copies what it needs, so
- * kappa and S may be freed after the call.  Section 2.1 (semi-discrete
- * system); the finite-volume form is stated at the top of this file. */
+ * kappa and S may be freed after the call.  bc may be NULL (every wall zero
+ * head).  LT_EINVAL for an unknown wall type, a water-table wall on an axis
+ * beyond ndim, or a specific yield that is negative or not finite (all
+ * checked before any device call).  Section 2.1 (semi-discrete system); the
+ * finite-volume form is stated at the top of this file. */
 int lt_setup(const lt_grid* grid, const double* kappa, const double* S, const lt_bc* bc,
              void* hip_stream, lt_handle** out);
 
