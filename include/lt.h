@@ -92,6 +92,27 @@ typedef struct {
     const double* xyz;
 } lt_points;
 
+/* What drives a solve: the transformed semi-discrete system of Section 2.1,
+ *     (K + z M) phi_hat(z) = sum_s qhat_s(z) b_s + M phi0,
+ * with b_s the weights of well s (lt_points) and qhat_s(z) = q_s / z for a
+ * constant rate q_s switched on at t = 0.  Heads are linear in the data, so
+ * each well is solved as its own right-hand side q_s b_s and reported on its
+ * own output row.
+ *   pts   the pumping wells (pts.n >= 0).
+ *   q     host [pts.n] pumping rate of each well (finite; 0 leaves the row
+ *         zero); NULL: every rate 1.
+ *   phi0  device float64 [N] initial head, or NULL for phi(0) = 0.  Its term
+ *         M phi0 is one more right-hand side, weighed in the contour sum by
+ *         w_k alone (factor 1, not qhat; the two-system split of Section 3),
+ *         and its heads are added to every well's row.  With pts.n = 0 the
+ *         output has one row holding the initial-value heads alone.
+ * lt_adjoint takes wells only (phi0 must be NULL). */
+typedef struct {
+    lt_points pts;
+    const double* q;
+    const double* phi0;
+} lt_sources;
+
 /* Talbot contour with nz nodes on the full contour per time (nz even);
  * nz/2 shifted systems are solved per time (eqn:half). */
 typedef struct {
@@ -102,7 +123,9 @@ typedef struct {
  * fills the defaults.
  *   tol        weighted per-shift tolerance: shift k of time t is converged
  *              when |w_k qhat_k| ||r_k|| <= tol * max_{k' at t} |w_k' qhat_k'| ||b||
- *              (weights from eqn:half; residual bound of Proposition 1).
+ *              (weights from eqn:half; residual bound of Proposition 1), i.e.
+ *              omega_k ||r_k|| / ||b|| <= tol with omega_k the ratio of the
+ *              two weights.  phi0's right-hand side weighs by |w_k| alone.
  *   maxit      maximum outer (Arnoldi) iterations per right-hand side.
  *   precision  LT_PREC_FP64 or LT_PREC_MIXED (V-cycle in FP32; Arnoldi,
  *              least squares, residuals and the contour sum stay FP64).
@@ -117,8 +140,10 @@ typedef struct {
  *   inner_max  maximum V-cycles per outer iteration (iterative refinement).
  *   relax      inner tolerance factor: the refinement stops when
  *              ||v - (K + tau M) u|| <= relax * tol / (worst weighted residual).
- *   true_residual  1: compute the FP64 true residual of every (rhs, shift)
- *              at exit (reported in lt_stats).
+ *   true_residual  1 (default): compute the FP64 true residual of every
+ *              (rhs, shift) at exit, report it in lt_stats, and let it decide
+ *              the status and the re-solves described at lt_solve.  0: skip
+ *              it; the status then rests on the least-squares residuals.
  *   profile    0: off.  LT_PROF_PRE_FINE / LT_PROF_POST_FINE: time every launch
  *              of the fine-grid pre- / post-smoothing kernel with HIP events on
  *              the handle's stream and count its algorithmic bytes (reported
@@ -178,16 +203,20 @@ typedef struct {
     int iters_max;        /* outer iterations of the slowest right-hand side  */
     int vcycles;          /* V-cycles applied, summed over right-hand sides   */
     int levels;           /* multigrid levels                                  */
-    double true_relres_max;      /* max over (rhs, shift) of weighted true residual / tol-scale */
+    double true_relres_max;      /* max over (rhs, shift) of the weighted true residual
+                                    omega_k ||b - (K + z_k M) x_k|| / ||b|| (compared with tol) */
     double seconds;              /* wall time of the call                    */
     int* iters_per_rhs;          /* [n_rhs] or NULL                          */
-    double* true_relres;         /* [n_rhs][n_shifts] ||b - (K+zM)x|| / ||b|| or NULL */
+    double* true_relres;         /* [n_rhs][n_shifts] ||b - (K+zM)x|| / ||b|| or NULL
+                                    (rows: the wells, then phi0's term if given) */
     int net_applied;             /* network guesses applied (rhs x outer iterations) */
     int net_rejected;            /* of which discarded by the residual guard      */
     int net_disabled_at;         /* outer iteration after which it was switched off (0: never) */
     int prof_launches;           /* profiled launches (opts.profile)          */
     double prof_ms;              /* their summed device time, milliseconds    */
     double prof_bytes;           /* their summed algorithmic bytes            */
+    int resolves;                /* right-hand sides solved again because their
+                                    weighted true residual missed tol          */
 } lt_stats;
 
 void lt_opts_default(lt_opts* o);
@@ -198,36 +227,46 @@ void lt_opts_default(lt_opts* o);
  * later work of the handle goes to it.  The handle copies what it needs, so
  * kappa and S may be freed after the call.  bc may be NULL (every wall zero
  * head).  LT_EINVAL for an unknown wall type, a water-table wall on an axis
- * beyond ndim, or a specific yield that is negative or not finite (all
- * checked before any device call).  Section 2.1 (semi-discrete system); the
+ * beyond ndim, a specific yield that is negative or not finite, or fewer
+ * than 2 or more than 2^28 cells (the fused smoothers address a vector with
+ * 32-bit byte offsets); all checked before any device call.  Section 2.1 (semi-discrete system); the
  * finite-volume form is stated at the top of this file. */
 int lt_setup(const lt_grid* grid, const double* kappa, const double* S, const lt_bc* bc,
              void* hip_stream, lt_handle** out);
 
 /* Heads phi[s][r][t] at receivers r and times t (host array times[ntimes],
- * strictly positive) for unit-location sources s pumping at constant rate q
- * from t = 0 (qhat(z) = q / z): the contour sum of eqn:half over the
- * solutions of eqn:multipleshifted, computed with the flexible shifted
- * Krylov method of Section 3.  phi_out: device float64 [ns][nr][ntimes].
- * Returns LT_WNOTCONV if some shift missed the tolerance after maxit
- * outer iterations (phi_out then holds the best estimate); LT_EINVAL, before
- * any work, for more than 1000 sources. */
-int lt_solve(lt_handle* h, const lt_points* sources, double q, const double* times, int ntimes,
+ * strictly positive) for the wells and initial head of `src` (lt_sources):
+ * the contour sum of eqn:half over the solutions of eqn:multipleshifted,
+ * computed with the flexible shifted Krylov method of Section 3.
+ * phi_out: device float64 [max(ns, 1)][nr][ntimes], ns = src->pts.n.
+ * Status: the flexible Arnoldi stops when every shift meets opts.tol by its
+ * least-squares residual; then (opts.true_residual = 1) the FP64 true
+ * residual of every (rhs, shift) is computed, and a right-hand side whose
+ * weighted true residual misses tol (relaxed preconditioner solves leave a
+ * gap between the two) is solved again from the start with the inner
+ * tolerance tightened by the measured excess, at most twice
+ * (lt_stats.resolves).  LT_WNOTCONV if some shift still misses tol, by
+ * either residual, after that (phi_out then holds the best estimate).
+ * LT_EINVAL, before any work, for more than 1000 right-hand sides, a
+ * non-finite rate, or neither wells nor phi0. */
+int lt_solve(lt_handle* h, const lt_sources* src, const double* times, int ntimes,
              const lt_contour* contour, const lt_points* receivers, const lt_opts* opts,
              double* phi_out, lt_stats* stats);
 
 /* Sensitivities of phi[s][r][t] to ln kappa and ln S of every cell
- * (Section 5.2, adjoint state through the Laplace transform), for sources
- * pumping at rate q: forward fields for every source and adjoint fields for
+ * (Section 5.2, adjoint state through the Laplace transform), for the wells of
+ * src (rates src->q as in lt_solve; src->phi0 must be NULL, else
+ * LT_EUNSUPPORTED): forward fields for every well and adjoint fields for
  * every receiver (complex symmetric operator: no conjugation), contracted
  * cell by cell and summed over the contour.  dlnK, dlnS: device float64
  * [ns][nr][ntimes][N]; either may be NULL.  Every shift meets the stricter of
  * the heads' weighting |w_k qhat_k| and the storage term's |w_k qhat_k z_k|
  * in the convergence test.  Near steady state the storage sensitivity is a
  * vanishing sum of contour terms of its early-time size, so its error is set
- * by tol relative to that size, not to its own norm.  LT_EINVAL, before any
- * work, for more than 1000 sources and receivers together. */
-int lt_adjoint(lt_handle* h, const lt_points* sources, double q, const lt_points* receivers,
+ * by tol relative to that size, not to its own norm.  The status follows the
+ * true residual as in lt_solve.  LT_EINVAL, before any work, for more than
+ * 1000 wells and receivers together. */
+int lt_adjoint(lt_handle* h, const lt_sources* src, const lt_points* receivers,
                const double* times, int ntimes, const lt_contour* contour, const lt_opts* opts,
                double* dlnK, double* dlnS, lt_stats* stats);
 
@@ -252,22 +291,20 @@ int lt_adjoint(lt_handle* h, const lt_points* sources, double q, const lt_points
  * rules above (then no item runs). */
 typedef struct {
     lt_handle* h;
-    const lt_points* sources;
-    double q;
+    const lt_sources* src;
     const double* times;      /* host [ntimes] */
     int ntimes;
     const lt_contour* contour;
     const lt_points* receivers;
     const lt_opts* opts;      /* NULL: lt_opts_default */
-    double* phi_out;          /* device float64 [ns][nr][ntimes] */
+    double* phi_out;          /* device float64 [max(ns, 1)][nr][ntimes] */
     lt_stats* stats;          /* or NULL */
     int status;               /* out: the item's return code */
 } lt_solve_item;
 
 typedef struct {
     lt_handle* h;
-    const lt_points* sources;
-    double q;
+    const lt_sources* src;
     const lt_points* receivers;
     const double* times;      /* host [ntimes] */
     int ntimes;
@@ -368,6 +405,20 @@ int lt_autotune(lt_handle* h, int precision, int nu1, int nu2, int nvec, int* ti
 int lt_set_tiles(lt_handle* h, int precision, const int* tiles, int n);
 /* Interior cells (tx, ty) of tile shape `id`; LT_EINVAL for an unknown id. */
 int lt_tile_shape(int id, int* tx, int* ty);
+
+/* Diagnostic: the flexible Arnoldi relation that the last lt_solve or
+ * lt_adjoint on h built for right-hand side `rhs` (eqn:shiftedarnoldimod;
+ * Algorithm "Flexible FOM/GMRES for shifted systems"):
+ *     M U_m = V_{m+1} Hbar_m,  V_{m+1}^H V_{m+1} = I,
+ * u_j the preconditioned vectors, m the columns its shifts used (*m_out).
+ * Host arrays, NULL to skip: V [mmax+1][2][N], U [mmax][2][N] (complex
+ * planes), Hbar [mmax][mmax+1] complex (re, im) stored by column (column j
+ * holds rows 0..m).  Only the first m (V: m+1) columns are written.  After a
+ * breakdown (h_{m+1,m} = 0) the last column of V is zero.  LT_EINVAL if no
+ * solve has run on h (or its basis was released by an error), rhs is out of
+ * range, or mmax < m (then *m_out still receives m).  Synchronises the
+ * handle's stream. */
+int lt_krylov_basis(lt_handle* h, int rhs, int mmax, double* V, double* U, double* Hbar, int* m_out);
 
 /* Number of cells per axis of multigrid level `level` (n_out[3]); returns
  * the number of levels, or a negative error code. */

@@ -73,32 +73,40 @@ def heads(n, h, kappa, S, sources, receivers, times, nz, q=1.0, bc=(0,) * 6,
           phi0=None, workers=1, ndim=None, sy=0.0):
     """Heads phi[source, receiver, time] (float64).
 
+    ``q`` is one pumping rate for every source or one per source (qhat = q_s / z).
     With ``phi0`` (an [N] initial head) the term M phi0 is added to every
     source's right-hand side with factor 1 (Section 3, the two-system split);
-    ``q = 0`` leaves only the initial-value problem.  ``sy`` is the specific
-    yield of the faces that ``bc`` marks as water table.
+    ``q = 0`` leaves only the initial-value problem, and with no sources at all
+    the result has one row holding it.  ``sy`` is the specific yield of the
+    faces that ``bc`` marks as water table.
     """
     K, m = assemble(n, h, kappa, S, bc, ndim=ndim, sy=sy)
-    Bs = point_weights(n, h, sources)
-    Br = point_weights(n, h, receivers)
     N = K.shape[0]
-    ns, nr, nt = Bs.shape[0], Br.shape[0], len(times)
+    src = np.asarray(sources, dtype=np.float64).reshape(-1, 3)
+    Br = point_weights(n, h, receivers)
+    ns, nr, nt = src.shape[0], Br.shape[0], len(times)
+    if ns == 0 and phi0 is None:
+        raise ValueError("no sources and no initial head")
+    qs = np.broadcast_to(np.asarray(q, dtype=np.float64), (ns,))
     # columns: the sources' b, then (optionally) M phi0
-    cols = [Bs.T.toarray()]
+    cols = [point_weights(n, h, src).T.toarray() if ns > 0 else np.zeros((N, 0))]
     if phi0 is not None:
         cols.append((m * np.asarray(phi0, dtype=np.float64)).reshape(N, 1))
     rhs = np.hstack(cols)
     nodes = [talbot_nodes(nz, t) for t in times]
     shifts = np.concatenate([z for z, _ in nodes])
     gathered = _map_shifts(K, m, rhs, shifts, "gather", Br=Br, workers=workers)
-    phi = np.zeros((ns, nr, nt))
+    rows = max(ns, 1)
+    phi = np.zeros((rows, nr, nt))
     kk = 0
     for it, (z, w) in enumerate(nodes):
-        acc = np.zeros((nr, ns), dtype=np.complex128)
+        acc = np.zeros((nr, rows), dtype=np.complex128)
         for k in range(len(z)):
             G = gathered[kk]
             kk += 1
-            term = (q / z[k]) * G[:, :ns]
+            term = np.zeros((nr, rows), dtype=np.complex128)
+            if ns > 0:
+                term += (qs / z[k]) * G[:, :ns]
             if phi0 is not None:
                 term = term + G[:, ns:ns + 1]
             acc += w[k] * term

@@ -59,7 +59,8 @@ def _face_lists(n, h, kappa, bc, ndim):
 
 def jacobian(n, h, kappa, S, sources, receivers, times, nz, q=1.0, bc=(0,) * 6,
              workers=1, ndim=None, sy=0.0):
-    """Return (J_lnK, J_lnS), each [ns, nr, nt, N] float64."""
+    """Return (J_lnK, J_lnS), each [ns, nr, nt, N] float64; ``q`` is one rate for every
+    source or one per source."""
     n = tuple(int(a) for a in n)
     if ndim is None:
         ndim = _ndim(n)
@@ -69,6 +70,7 @@ def jacobian(n, h, kappa, S, sources, receivers, times, nz, q=1.0, bc=(0,) * 6,
     Br = point_weights(n, h, receivers)
     N = K.shape[0]
     ns, nr, nt = Bs.shape[0], Br.shape[0], len(times)
+    qs = np.broadcast_to(np.asarray(q, dtype=np.float64), (ns,))
     faces, walls = _face_lists(n, h, kappa, bc, ndim)
     rhs = np.hstack([Bs.T.toarray(), Br.T.toarray()])
     nodes = [talbot_nodes(nz, t) for t in times]
@@ -84,7 +86,7 @@ def jacobian(n, h, kappa, S, sources, receivers, times, nz, q=1.0, bc=(0,) * 6,
             phi = X[kk][:, :ns]          # [N, ns]
             psi = X[kk][:, ns:]          # [N, nr]
             kk += 1
-            c = w[k] * q / z[k]
+            c = (w[k] / z[k]) * qs[:, None, None]
             # psi^T (dK/dln k_c) phi, accumulated per cell c
             gK = np.zeros((ns, nr, N), dtype=np.complex128)
             for (i, j, T, dTi, dTj) in faces:

@@ -40,6 +40,10 @@ class lt_points(C.Structure):
     _fields_ = [("n", C.c_int), ("xyz", C.POINTER(C.c_double))]
 
 
+class lt_sources(C.Structure):
+    _fields_ = [("pts", lt_points), ("q", C.POINTER(C.c_double)), ("phi0", C.c_void_p)]
+
+
 class lt_contour(C.Structure):
     _fields_ = [("nz", C.c_int)]
 
@@ -57,7 +61,8 @@ class lt_stats(C.Structure):
                 ("levels", C.c_int), ("true_relres_max", C.c_double), ("seconds", C.c_double),
                 ("iters_per_rhs", C.POINTER(C.c_int)), ("true_relres", C.POINTER(C.c_double)),
                 ("net_applied", C.c_int), ("net_rejected", C.c_int), ("net_disabled_at", C.c_int),
-                ("prof_launches", C.c_int), ("prof_ms", C.c_double), ("prof_bytes", C.c_double)]
+                ("prof_launches", C.c_int), ("prof_ms", C.c_double), ("prof_bytes", C.c_double),
+                ("resolves", C.c_int)]
 
 
 _vp = C.c_void_p
@@ -66,14 +71,14 @@ _h = C.c_void_p
 
 
 class lt_solve_item(C.Structure):
-    _fields_ = [("h", _h), ("sources", C.POINTER(lt_points)), ("q", C.c_double), ("times", _dp),
+    _fields_ = [("h", _h), ("src", C.POINTER(lt_sources)), ("times", _dp),
                 ("ntimes", C.c_int), ("contour", C.POINTER(lt_contour)), ("receivers", C.POINTER(lt_points)),
                 ("opts", C.POINTER(lt_opts)), ("phi_out", _vp), ("stats", C.POINTER(lt_stats)),
                 ("status", C.c_int)]
 
 
 class lt_adjoint_item(C.Structure):
-    _fields_ = [("h", _h), ("sources", C.POINTER(lt_points)), ("q", C.c_double),
+    _fields_ = [("h", _h), ("src", C.POINTER(lt_sources)),
                 ("receivers", C.POINTER(lt_points)), ("times", _dp), ("ntimes", C.c_int),
                 ("contour", C.POINTER(lt_contour)), ("opts", C.POINTER(lt_opts)), ("dlnK", _vp), ("dlnS", _vp),
                 ("stats", C.POINTER(lt_stats)), ("status", C.c_int)]
@@ -82,10 +87,10 @@ _lib.lt_opts_default.argtypes = [C.POINTER(lt_opts)]
 _lib.lt_opts_default.restype = None
 _lib.lt_setup.argtypes = [C.POINTER(lt_grid), _vp, _vp, C.POINTER(lt_bc), _vp, C.POINTER(_h)]
 _lib.lt_setup.restype = C.c_int
-_lib.lt_solve.argtypes = [_h, C.POINTER(lt_points), C.c_double, _dp, C.c_int, C.POINTER(lt_contour),
+_lib.lt_solve.argtypes = [_h, C.POINTER(lt_sources), _dp, C.c_int, C.POINTER(lt_contour),
                           C.POINTER(lt_points), C.POINTER(lt_opts), _vp, C.POINTER(lt_stats)]
 _lib.lt_solve.restype = C.c_int
-_lib.lt_adjoint.argtypes = [_h, C.POINTER(lt_points), C.c_double, C.POINTER(lt_points), _dp, C.c_int,
+_lib.lt_adjoint.argtypes = [_h, C.POINTER(lt_sources), C.POINTER(lt_points), _dp, C.c_int,
                             C.POINTER(lt_contour), C.POINTER(lt_opts), _vp, _vp, C.POINTER(lt_stats)]
 _lib.lt_adjoint.restype = C.c_int
 _lib.lt_solve_batch.argtypes = [C.POINTER(lt_solve_item), C.c_int]
@@ -104,6 +109,8 @@ _lib.lt_apply_operator.argtypes = [_h, C.c_int, C.c_double, C.c_double, _vp, _vp
 _lib.lt_apply_operator.restype = C.c_int
 _lib.lt_vcycle.argtypes = [_h, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int]
 _lib.lt_vcycle.restype = C.c_int
+_lib.lt_krylov_basis.argtypes = [_h, C.c_int, C.c_int, _dp, _dp, _dp, C.POINTER(C.c_int)]
+_lib.lt_krylov_basis.restype = C.c_int
 _lib.lt_level_shape.argtypes = [_h, C.c_int, C.POINTER(C.c_int)]
 _lib.lt_level_shape.restype = C.c_int
 _lib.lt_strerror.argtypes = [C.c_int]
@@ -169,10 +176,21 @@ def _dev_f64(t, name):
 
 
 def _points(xyz):
-    a = np.ascontiguousarray(np.atleast_2d(np.asarray(xyz, dtype=np.float64)))
+    a = np.asarray(xyz, dtype=np.float64)
+    a = np.ascontiguousarray(a.reshape(0, 3) if a.size == 0 else np.atleast_2d(a))
     if a.shape[1] != 3:
         raise ValueError("points must have shape [n, 3]")
     return lt_points(a.shape[0], a.ctypes.data_as(_dp)), a
+
+
+def _sources(xyz, q, phi0=None):
+    """lt_sources for wells at xyz pumping at rates q (scalar or one per well) and an
+    optional initial head phi0 (float64 CUDA tensor [N]); returns it with what it points to."""
+    sp, sa = _points(xyz)
+    qa = np.ascontiguousarray(np.broadcast_to(np.asarray(q, dtype=np.float64), (sa.shape[0],)).copy())
+    ptr0 = _dev_f64(phi0, "phi0") if phi0 is not None else None
+    src = lt_sources(sp, qa.ctypes.data_as(_dp), ptr0)
+    return src, (sp, sa, qa, phi0)
 
 
 def lt_opts_default() -> lt_opts:
@@ -243,34 +261,40 @@ def _stats_dict(st, it, tr, rc, nrhs, nshift):
             "seconds": st.seconds, "iters_per_rhs": it.copy(), "true_relres": tr.reshape(nrhs, nshift).copy(),
             "net_applied": st.net_applied, "net_rejected": st.net_rejected,
             "net_disabled_at": st.net_disabled_at,
-            "prof_launches": st.prof_launches, "prof_ms": st.prof_ms, "prof_bytes": st.prof_bytes}
+            "prof_launches": st.prof_launches, "prof_ms": st.prof_ms, "prof_bytes": st.prof_bytes,
+            "resolves": st.resolves}
 
 
-def lt_solve(handle: Handle, sources, q, times, nz, receivers, opts: lt_opts | None = None, phi_out=None):
-    """Heads [ns, nr, nt] as a float64 CUDA tensor, plus a stats dict."""
+def lt_solve(handle: Handle, sources, q, times, nz, receivers, opts: lt_opts | None = None, phi_out=None,
+             phi0=None):
+    """Heads [max(ns, 1), nr, nt] as a float64 CUDA tensor, plus a stats dict.
+
+    ``q``: one rate for every well or one per well; ``phi0``: optional initial head
+    (float64 CUDA tensor [N]) whose heads are added to every row."""
     import torch
-    sp, sa = _points(sources)
+    src, keep = _sources(sources, q, phi0)
     rp, ra = _points(receivers)
     t = np.ascontiguousarray(np.asarray(times, dtype=np.float64).ravel())
-    ns, nr, nt = sa.shape[0], ra.shape[0], t.size
+    ns, nr, nt = keep[1].shape[0], ra.shape[0], t.size
+    nrhs = ns + (1 if phi0 is not None else 0)
     if phi_out is None:
-        phi_out = torch.empty((ns, nr, nt), dtype=torch.float64, device="cuda")
+        phi_out = torch.empty((max(ns, 1), nr, nt), dtype=torch.float64, device="cuda")
     con = lt_contour(int(nz))
     o = opts if opts is not None else lt_opts_default()
-    st, it, tr = _stats(ns, nt * (int(nz) // 2))
-    rc = _check(_lib.lt_solve(handle.ptr, C.byref(sp), float(q), t.ctypes.data_as(_dp), nt, C.byref(con),
+    st, it, tr = _stats(nrhs, nt * (int(nz) // 2))
+    rc = _check(_lib.lt_solve(handle.ptr, C.byref(src), t.ctypes.data_as(_dp), nt, C.byref(con),
                               C.byref(rp), C.byref(o), _dev_f64(phi_out, "phi_out"), C.byref(st)))
-    return phi_out, _stats_dict(st, it, tr, rc, ns, nt * (int(nz) // 2))
+    return phi_out, _stats_dict(st, it, tr, rc, nrhs, nt * (int(nz) // 2))
 
 
 def lt_adjoint(handle: Handle, sources, q, receivers, times, nz, opts: lt_opts | None = None,
                dlnK=None, dlnS=None):
     """Sensitivities [ns, nr, nt, N] to ln kappa and ln S (float64 CUDA tensors) and stats."""
     import torch
-    sp, sa = _points(sources)
+    src, keep = _sources(sources, q)
     rp, ra = _points(receivers)
     t = np.ascontiguousarray(np.asarray(times, dtype=np.float64).ravel())
-    ns, nr, nt = sa.shape[0], ra.shape[0], t.size
+    ns, nr, nt = keep[1].shape[0], ra.shape[0], t.size
     shape = (ns, nr, nt, handle.N)
     if dlnK is None:
         dlnK = torch.empty(shape, dtype=torch.float64, device="cuda")
@@ -279,7 +303,7 @@ def lt_adjoint(handle: Handle, sources, q, receivers, times, nz, opts: lt_opts |
     con = lt_contour(int(nz))
     o = opts if opts is not None else lt_opts_default()
     st, it, tr = _stats(ns + nr, nt * (int(nz) // 2))
-    rc = _check(_lib.lt_adjoint(handle.ptr, C.byref(sp), float(q), C.byref(rp), t.ctypes.data_as(_dp), nt,
+    rc = _check(_lib.lt_adjoint(handle.ptr, C.byref(src), C.byref(rp), t.ctypes.data_as(_dp), nt,
                                 C.byref(con), C.byref(o), _dev_f64(dlnK, "dlnK"), _dev_f64(dlnS, "dlnS"),
                                 C.byref(st)))
     return dlnK, dlnS, _stats_dict(st, it, tr, rc, ns + nr, nt * (int(nz) // 2))
@@ -289,7 +313,7 @@ def lt_solve_batch(problems):
     """Solve several problems in one lt_solve_batch call.
 
     ``problems``: sequence of dicts with keys handle, sources, q, times, nz,
-    receivers and optionally opts and phi_out (the arguments of lt_solve).
+    receivers and optionally opts, phi0 and phi_out (the arguments of lt_solve).
     Returns (list of phi tensors, list of stats dicts, batch return code).
     """
     import torch
@@ -297,23 +321,25 @@ def lt_solve_batch(problems):
     items = (lt_solve_item * n)()
     keep, outs, meta = [], [], []
     for i, pr in enumerate(problems):
-        sp, sa = _points(pr["sources"])
+        phi0 = pr.get("phi0")
+        src, sk = _sources(pr["sources"], pr.get("q", 1.0), phi0)
         rp, ra = _points(pr["receivers"])
         t = np.ascontiguousarray(np.asarray(pr["times"], dtype=np.float64).ravel())
-        ns, nr, nt = sa.shape[0], ra.shape[0], t.size
+        ns, nr, nt = sk[1].shape[0], ra.shape[0], t.size
+        nrhs = ns + (1 if phi0 is not None else 0)
         nz = int(pr["nz"])
         phi = pr.get("phi_out")
         if phi is None:
-            phi = torch.empty((ns, nr, nt), dtype=torch.float64, device="cuda")
+            phi = torch.empty((max(ns, 1), nr, nt), dtype=torch.float64, device="cuda")
         con = lt_contour(nz)
         o = pr.get("opts") or lt_opts_default()
-        st, it, tr = _stats(ns, nt * (nz // 2))
-        keep.append((sp, sa, rp, ra, t, con, o, st, it, tr))
-        items[i] = lt_solve_item(pr["handle"].ptr, C.pointer(sp), float(pr.get("q", 1.0)), t.ctypes.data_as(_dp),
+        st, it, tr = _stats(nrhs, nt * (nz // 2))
+        keep.append((src, sk, rp, ra, t, con, o, st, it, tr))
+        items[i] = lt_solve_item(pr["handle"].ptr, C.pointer(src), t.ctypes.data_as(_dp),
                                  nt, C.pointer(con), C.pointer(rp), C.pointer(o), _dev_f64(phi, "phi_out"),
                                  C.pointer(st), 0)
         outs.append(phi)
-        meta.append((ns, nt * (nz // 2)))
+        meta.append((nrhs, nt * (nz // 2)))
     rc = _check(_lib.lt_solve_batch(items, n))
     stats = [_stats_dict(k[7], k[8], k[9], items[i].status, *meta[i]) for i, k in enumerate(keep)]
     return outs, stats, rc
@@ -323,26 +349,31 @@ def lt_adjoint_batch(problems):
     """Sensitivities of several problems in one lt_adjoint_batch call.
 
     ``problems``: dicts with keys handle, sources, q, receivers, times, nz and
-    optionally opts.  Returns (list of (dlnK, dlnS), list of stats, code).
+    optionally opts, dlnK and dlnS (output tensors).  Returns (list of (dlnK, dlnS),
+    list of stats, code).
     """
     import torch
     n = len(problems)
     items = (lt_adjoint_item * n)()
     keep, outs, meta = [], [], []
     for i, pr in enumerate(problems):
-        sp, sa = _points(pr["sources"])
+        src, sk = _sources(pr["sources"], pr.get("q", 1.0))
         rp, ra = _points(pr["receivers"])
         t = np.ascontiguousarray(np.asarray(pr["times"], dtype=np.float64).ravel())
-        ns, nr, nt = sa.shape[0], ra.shape[0], t.size
+        ns, nr, nt = sk[1].shape[0], ra.shape[0], t.size
         nz = int(pr["nz"])
         shape = (ns, nr, nt, pr["handle"].N)
-        dK = torch.empty(shape, dtype=torch.float64, device="cuda")
-        dS = torch.empty(shape, dtype=torch.float64, device="cuda")
+        dK = pr.get("dlnK")
+        dS = pr.get("dlnS")
+        if dK is None:
+            dK = torch.empty(shape, dtype=torch.float64, device="cuda")
+        if dS is None:
+            dS = torch.empty(shape, dtype=torch.float64, device="cuda")
         con = lt_contour(nz)
         o = pr.get("opts") or lt_opts_default()
         st, it, tr = _stats(ns + nr, nt * (nz // 2))
-        keep.append((sp, sa, rp, ra, t, con, o, st, it, tr))
-        items[i] = lt_adjoint_item(pr["handle"].ptr, C.pointer(sp), float(pr.get("q", 1.0)), C.pointer(rp),
+        keep.append((src, sk, rp, ra, t, con, o, st, it, tr))
+        items[i] = lt_adjoint_item(pr["handle"].ptr, C.pointer(src), C.pointer(rp),
                                    t.ctypes.data_as(_dp), nt, C.pointer(con), C.pointer(o),
                                    _dev_f64(dK, "dlnK"), _dev_f64(dS, "dlnS"), C.pointer(st), 0)
         outs.append((dK, dS))
@@ -391,6 +422,26 @@ def lt_vcycle(handle: Handle, tau, precision, nu1, nu2, b, x, nvec):
                                  _dev_f64(b, "b"), _dev_f64(x, "x"), int(nvec)))
 
 
+def lt_krylov_basis(handle: Handle, rhs):
+    """(V [m+1, N] complex, U [m, N] complex, Hbar [m+1, m] complex) of the last solve's basis
+    for right-hand side `rhs` (numpy arrays)."""
+    m = C.c_int()
+    rc = _lib.lt_krylov_basis(handle.ptr, int(rhs), 0, None, None, None, C.byref(m))
+    mm = m.value
+    if rc < 0 and mm == 0:
+        raise LTError(rc)
+    N = handle.N
+    V = np.zeros((mm + 1) * 2 * N)
+    U = np.zeros(max(mm, 1) * 2 * N)
+    H = np.zeros(max(mm, 1) * (mm + 1) * 2)
+    _check(_lib.lt_krylov_basis(handle.ptr, int(rhs), mm, V.ctypes.data_as(_dp), U.ctypes.data_as(_dp),
+                                H.ctypes.data_as(_dp), C.byref(m)))
+    V = V.reshape(mm + 1, 2, N)
+    U = U.reshape(-1, 2, N)[:mm]
+    Hc = H.reshape(-1, mm + 1, 2)[:mm]
+    return (V[:, 0] + 1j * V[:, 1], U[:, 0] + 1j * U[:, 1], (Hc[..., 0] + 1j * Hc[..., 1]).T)
+
+
 def lt_level_shape(handle: Handle, level):
     n = (C.c_int * 3)()
     nl = _check(_lib.lt_level_shape(handle.ptr, int(level), n))
@@ -410,7 +461,8 @@ _ABI_NAMES = ["lt_opts_default", "lt_setup", "lt_solve", "lt_adjoint", "lt_talbo
               "lt_vcycle", "lt_level_shape", "lt_strerror", "lt_last_error", "lt_destroy", "lt_unet_create",
               "lt_unet_nparams", "lt_unet_get_params", "lt_unet_set_params", "lt_unet_apply",
               "lt_unet_train_step", "lt_unet_grad", "lt_unet_attach", "lt_unet_destroy", "lt_precond_solve",
-              "lt_solve_batch", "lt_adjoint_batch", "lt_autotune", "lt_set_tiles", "lt_tile_shape"]
+              "lt_solve_batch", "lt_adjoint_batch", "lt_autotune", "lt_set_tiles", "lt_tile_shape",
+              "lt_krylov_basis"]
 
 
 # ---------------------------------------------------------------- learned preconditioner

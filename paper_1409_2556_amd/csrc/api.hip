@@ -130,11 +130,14 @@ struct KrylovOut {
     double* beta = nullptr;   // [R]
     double* b = nullptr;      // [R][2][N]
     double* zs = nullptr;     // [Ks] complex
-    double* omega = nullptr;  // [Ks]
+    double* omega = nullptr;  // [2][Ks]: wells' weights, then the initial head's
     double* wq = nullptr;     // [Ks] complex
+    double* w = nullptr;      // [Ks] complex (the initial head's factor-1 weights)
+    int rinit = 0;            // first right-hand side weighed by w (R: none)
     int iters_max = 0, vcycles = 0;
     int net_applied = 0, net_rejected = 0, net_disabled_at = 0;
     bool converged = true;
+    std::vector<int> notconv;  // [R] 1 where the Arnoldi stopped at maxit
 };
 
 // One step of the iterative refinement of u_j ~ (K + tau M)^{-1} v_j for the
@@ -241,8 +244,12 @@ int graph_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, si
 }
 
 // Batched flexible shifted GMRES for R right-hand sides b (device [R][2][N], already
-// filled).  Gathers B_rec u_j for `rec` if given.
-int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const DevPoints* rec, KrylovOut* out) {
+// filled).  Gathers B_rec u_j for `rec` if given.  Right-hand sides from rinit on weigh
+// their shifts by |w_k| (the initial head's term).  With `only` (host [R] flags), just
+// those right-hand sides are solved; the others keep the basis, gathers and column
+// counts of the previous call on the same workspace.
+int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int rinit, const DevPoints* rec,
+               KrylovOut* out, const std::vector<int>* only = nullptr) {
     hipStream_t st = h->stream;
     const int N = h->N;
     const int jmax = o.maxit;
@@ -252,6 +259,7 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     out->R = R;
     out->Ks = Ks;
     out->jmax = jmax;
+    h->last_R = 0;  // set again once the basis is complete
     const size_t qstride = (size_t)(jmax + 1) * N2, ustride = (size_t)jmax * N2;
     double* Q = wsp<double>(h, "Q", (size_t)R * qstride, &rc);
     if (!Q) return rc;
@@ -326,7 +334,7 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     ls.res = wsp<double>(h, "res", P, &rc);
     int* conv = wsp<int>(h, "conv", P, &rc);
     double* Y = wsp<double>(h, "Y", (size_t)R * jmax * 2 * Ks, &rc);
-    double* tabs = wsp<double>(h, "tabs", 5 * (size_t)Ks, &rc);
+    double* tabs = wsp<double>(h, "tabs", 8 * (size_t)Ks, &rc);
     if (!ls.Rm || !ls.cs || !ls.sn || !ls.g || !ls.res || !conv || !Y || !tabs) return rc;
     double* G = nullptr;
     int np = rec ? rec->n : 0;
@@ -336,15 +344,19 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     }
     double* zs = tabs;
     double* wq = tabs + 2 * Ks;
-    double* omega = tabs + 4 * Ks;
+    double* wk = tabs + 4 * Ks;
+    double* omega = tabs + 6 * Ks;  // [2][Ks]
     {
-        std::vector<double> t(5 * (size_t)Ks);
+        std::vector<double> t(8 * (size_t)Ks);
         for (int k = 0; k < Ks; ++k) {
             t[2 * k] = plan.z[k].real();
             t[2 * k + 1] = plan.z[k].imag();
             t[2 * Ks + 2 * k] = plan.wq[k].real();
             t[2 * Ks + 2 * k + 1] = plan.wq[k].imag();
-            t[4 * Ks + k] = plan.omega[k];
+            t[4 * Ks + 2 * k] = plan.w[k].real();
+            t[4 * Ks + 2 * k + 1] = plan.w[k].imag();
+            t[6 * Ks + k] = plan.omega[k];
+            t[7 * Ks + k] = plan.omega_init[k];
         }
         LT_HIP(hipMemcpyAsync(tabs, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, st));
     }
@@ -370,19 +382,27 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
         LT_HIP(hipMemcpyAsync(hb.data(), beta, R * sizeof(double), hipMemcpyDeviceToHost, st));
         LT_HIP(hipStreamSynchronize(st));
         std::vector<int> ii(6 * (size_t)R + 12, 0);
-        for (int r = 0; r < R; ++r) ii[r] = hb[r] > 0.0 ? 1 : 0;
+        for (int r = 0; r < R; ++r) ii[r] = hb[r] > 0.0 && (!only || (*only)[r]) ? 1 : 0;
         probe_rhs = -1;
         for (int r = 0; r < R && probe_rhs < 0; ++r)
-            if (hb[r] > 0.0) probe_rhs = r;
+            if (ii[r]) probe_rhs = r;
         if (probe_rhs >= 0) ii[5 * (size_t)R + 8 + probe_rhs] = 1;
-        LT_HIP(hipMemcpyAsync(ints, ii.data(), ii.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        if (!only) {
+            LT_HIP(hipMemcpyAsync(ints, ii.data(), ii.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        } else {
+            // keep the column counts of the right-hand sides that are not solved again
+            LT_HIP(hipMemcpyAsync(ints, ii.data(), 2 * (size_t)R * sizeof(int), hipMemcpyHostToDevice, st));
+            LT_HIP(hipMemcpyAsync(ints + 3 * (size_t)R, ii.data() + 3 * (size_t)R, (ii.size() - 3 * (size_t)R) * sizeof(int),
+                                  hipMemcpyHostToDevice, st));
+        }
     }
     const LevelView<double> L0 = h->levels[0].v64();
     const double* m = L0.m;
     int* jdev = count + 3;  // basis column the refinement steps update (device)
     // captured steps need a stream of the handle's own (the legacy default stream cannot be captured)
     const bool use_graphs = o.graph && !h->prof_target && st != nullptr;
-    int n_active = R;
+    int n_active = 0;
+    for (int r = 0; r < R; ++r) n_active += (!only || (*only)[r]) ? 1 : 0;
     int j = 0;
     int inner_guess = 2;
     const bool debug = std::getenv("LT_DEBUG") != nullptr;
@@ -487,17 +507,18 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
         LT_TRY(launch_cgs2(st, N, R, j, m, U, ustride, Q, qstride, H, hstride, hrstride, part, pstride, c1, c2,
                            cstride, scale, partn, active));
         if (np > 0) LT_TRY(launch_gather(st, R, N, np, rec->off, rec->cell, rec->wt, U, ustride, j, G, jmax, active));
-        LT_TRY(launch_ls_update(st, R, Ks, j, tau, zs, omega, o.tol, o.method == LT_METHOD_FOM, H, hstride, hrstride,
-                                beta, ls, active, mcols,
-                                worst, conv));
+        LT_TRY(launch_ls_update(st, R, Ks, j, tau, zs, omega, rinit, o.tol, o.method == LT_METHOD_FOM, H, hstride,
+                                hrstride, beta, ls, active, mcols, worst, conv));
     }
-    if (!out->converged) {
-        LT_HIP(hipMemcpyAsync(hact, active, R * sizeof(int), hipMemcpyDeviceToHost, st));
-        LT_HIP(hipStreamSynchronize(st));
-        n_active = 0;
-        for (int r = 0; r < R; ++r) n_active += hact[r];
-        out->converged = n_active == 0;
+    LT_HIP(hipMemcpyAsync(hact, active, R * sizeof(int), hipMemcpyDeviceToHost, st));
+    LT_HIP(hipStreamSynchronize(st));
+    n_active = 0;
+    out->notconv.assign(R, 0);
+    for (int r = 0; r < R; ++r) {
+        n_active += hact[r];
+        out->notconv[r] = hact[r];
     }
+    out->converged = n_active == 0;
     LT_TRY(launch_backsolve(st, R, Ks, mcols, ls, Y, jmax, o.method == LT_METHOD_FOM));
     std::vector<int> hm(R), hv(R), hn(2);
     LT_HIP(hipMemcpyAsync(hn.data(), netc, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -512,6 +533,8 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
         out->iters_max = std::max(out->iters_max, hm[r]);
         out->vcycles += hv[r];
     }
+    h->last_R = R;
+    h->last_jmax = jmax;
     out->U = U;
     out->ustride = ustride;
     out->Y = Y;
@@ -521,10 +544,14 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, const De
     out->zs = zs;
     out->omega = omega;
     out->wq = wq;
+    out->w = wk;
+    out->rinit = rinit;
     return 0;
 }
 
-int true_residuals(lt_handle* h, const KrylovOut& k, const Plan& plan, lt_stats* stats) {
+// FP64 true residuals of every (rhs, shift); wr[r] receives each right-hand side's largest
+// weighted value omega_k ||b - (K + z_k M) x_k|| / ||b||.
+int true_residuals(lt_handle* h, const KrylovOut& k, const Plan& plan, lt_stats* stats, std::vector<double>* wr) {
     hipStream_t st = h->stream;
     const int N = h->N, R = k.R, Ks = k.Ks;
     int rc = 0;
@@ -540,12 +567,71 @@ int true_residuals(lt_handle* h, const KrylovOut& k, const Plan& plan, lt_stats*
     LT_HIP(hipMemcpyAsync(ht.data(), tr, ht.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     LT_HIP(hipStreamSynchronize(st));
     double mx = 0.0;
-    for (int r = 0; r < R; ++r)
-        for (int kk = 0; kk < Ks; ++kk) mx = std::max(mx, plan.omega[kk] * ht[(size_t)r * Ks + kk]);
+    wr->assign(R, 0.0);
+    for (int r = 0; r < R; ++r) {
+        const std::vector<double>& om = r >= k.rinit ? plan.omega_init : plan.omega;
+        for (int kk = 0; kk < Ks; ++kk) (*wr)[r] = std::max((*wr)[r], om[kk] * ht[(size_t)r * Ks + kk]);
+        mx = std::max(mx, (*wr)[r]);
+    }
     if (stats) {
         stats->true_relres_max = mx;
         if (stats->true_relres) std::memcpy(stats->true_relres, ht.data(), ht.size() * sizeof(double));
     }
+    return 0;
+}
+
+// The flexible Arnoldi of run_krylov, then the FP64 true residual as the judge: a
+// right-hand side whose Arnoldi converged but whose weighted true residual misses tol
+// (the gap that relaxed preconditioner solves leave, sum_j y_j rho_j) is solved again
+// from the start with the tolerance, and with it the inner tolerance relax * tol, scaled
+// by 0.5 / excess; at most twice.  *ok: every (rhs, shift) meets tol by both residuals.
+int solve_checked(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int rinit, const DevPoints* rec,
+                  KrylovOut* k, lt_stats* stats, int* resolves, bool* ok) {
+    *resolves = 0;
+    LT_TRY(run_krylov(h, plan, o, R, rinit, rec, k));
+    std::vector<int> nc = k->notconv;
+    int vcycles = k->vcycles, napp = k->net_applied, nrej = k->net_rejected;
+    bool tr_ok = true;
+    if (o.true_residual) {
+        std::vector<double> wr;
+        double tcur = o.tol;
+        for (int attempt = 0;; ++attempt) {
+            LT_TRY(true_residuals(h, *k, plan, stats, &wr));
+            std::vector<int> redo(R, 0);
+            double excess = 0.0;
+            int nredo = 0;
+            tr_ok = true;
+            for (int r = 0; r < R; ++r) {
+                if (!(wr[r] <= o.tol)) {
+                    tr_ok = false;
+                    if (!nc[r]) {
+                        redo[r] = 1;
+                        ++nredo;
+                        excess = std::max(excess, std::isfinite(wr[r]) ? wr[r] / o.tol : 1e6);
+                    }
+                }
+            }
+            if (nredo == 0 || attempt == 2) break;
+            lt_opts o2 = o;
+            tcur *= 0.5 / excess;
+            o2.tol = tcur;
+            *resolves += nredo;
+            LT_TRY(run_krylov(h, plan, o2, R, rinit, rec, k, &redo));
+            for (int r = 0; r < R; ++r)
+                if (redo[r]) nc[r] = k->notconv[r];
+            vcycles += k->vcycles;
+            napp += k->net_applied;
+            nrej += k->net_rejected;
+        }
+    }
+    k->vcycles = vcycles;
+    k->net_applied = napp;
+    k->net_rejected = nrej;
+    bool conv = true;
+    for (int r = 0; r < R; ++r) conv = conv && !nc[r];
+    k->notconv = nc;
+    k->converged = conv;
+    *ok = conv && tr_ok;
     return 0;
 }
 
@@ -583,8 +669,9 @@ int prof_finish(lt_handle* h, lt_stats* s) {
     return 0;
 }
 
-void fill_stats(lt_stats* s, const KrylovOut& k, int nlev, double secs) {
+void fill_stats(lt_stats* s, const KrylovOut& k, int nlev, double secs, int resolves) {
     if (!s) return;
+    s->resolves = resolves;
     s->n_rhs = k.R;
     s->n_shifts = k.Ks;
     s->iters_max = k.iters_max;
@@ -594,6 +681,41 @@ void fill_stats(lt_stats* s, const KrylovOut& k, int nlev, double secs) {
     s->net_disabled_at = k.net_disabled_at;
     s->levels = nlev;
     s->seconds = secs;
+}
+
+// Checks of an lt_sources (before any work).  adjoint: wells only, and receivers count
+// towards the right-hand sides.
+int check_sources(const lt_sources* src, int extra_rhs, bool adjoint, const char* who) {
+    if (!src || src->pts.n < 0 || (src->pts.n > 0 && !src->pts.xyz)) {
+        set_last_error(std::string(who) + ": bad sources");
+        return LT_EINVAL;
+    }
+    if (adjoint && src->phi0) {
+        set_last_error(std::string(who) + ": the sensitivities take wells only (phi0 must be NULL)");
+        return LT_EUNSUPPORTED;
+    }
+    if (src->pts.n == 0 && (adjoint || !src->phi0)) {
+        set_last_error(std::string(who) + ": no wells and no initial head");
+        return LT_EINVAL;
+    }
+    if ((long long)src->pts.n + (src->phi0 ? 1 : 0) + extra_rhs > kMaxRhs) {
+        set_last_error(std::string(who) + ": at most " + std::to_string(kMaxRhs) + " right-hand sides per call");
+        return LT_EINVAL;
+    }
+    if (src->q)
+        for (int i = 0; i < src->pts.n; ++i)
+            if (!std::isfinite(src->q[i])) {
+                set_last_error(std::string(who) + ": rates must be finite");
+                return LT_EINVAL;
+            }
+    return 0;
+}
+
+// Weights of the wells' right-hand sides q_s B_s^T (heads are linear in the rates).
+void scale_by_rates(const lt_sources* src, PointsCSR* c) {
+    if (!src->q) return;
+    for (int s = 0; s < src->pts.n; ++s)
+        for (int e = c->off[s]; e < c->off[s + 1]; ++e) c->wt[e] *= src->q[s];
 }
 
 }  // namespace
@@ -650,8 +772,8 @@ int lt_setup(const lt_grid* grid, const double* kappa, const double* S, const lt
         }
     }
     long long Nll = (long long)grid->n[0] * grid->n[1] * grid->n[2];
-    if (Nll < 2 || Nll > (1LL << 30)) {
-        set_last_error("lt_setup: grid too small or too large");
+    if (Nll < 2 || Nll > kMaxCells) {
+        set_last_error("lt_setup: grid too small or too large (2 to 2^28 cells)");
         return LT_EINVAL;
     }
     lt_handle* h = new (std::nothrow) lt_handle();
@@ -736,6 +858,52 @@ int lt_talbot(int nz, double t, double* z_reim, double* w_reim) {
     return 0;
 }
 
+int lt_krylov_basis(lt_handle* h, int rhs, int mmax, double* V, double* U, double* Hbar, int* m_out) {
+    if (!h || h->last_R < 1 || rhs < 0 || rhs >= h->last_R || mmax < 0) {
+        set_last_error("lt_krylov_basis: no basis for this right-hand side");
+        return LT_EINVAL;
+    }
+    hipStream_t st = h->stream;
+    const int R = h->last_R, jmax = h->last_jmax;
+    const size_t N2 = 2 * (size_t)h->N;
+    const size_t qstride = (size_t)(jmax + 1) * N2, ustride = (size_t)jmax * N2;
+    const int hstride = 2 * (jmax + 2);
+    const double* Q = h->ws["Q"].as<double>();
+    const double* Ud = h->ws["U"].as<double>();
+    const double* Hd = h->ws["H"].as<double>();
+    const int* ints = h->ws["ints"].as<int>();
+    const double* small = h->ws["small"].as<double>();
+    int m = 0;
+    double scale = 0;
+    LT_HIP(hipStreamSynchronize(st));
+    LT_HIP(hipMemcpy(&m, ints + 2 * (size_t)R + rhs, sizeof(int), hipMemcpyDeviceToHost));  // mcols
+    LT_HIP(hipMemcpy(&scale, small + rhs, sizeof(double), hipMemcpyDeviceToHost));
+    if (m_out) *m_out = m;
+    if (mmax < m) {
+        set_last_error("lt_krylov_basis: mmax is smaller than the basis");
+        return LT_EINVAL;
+    }
+    if (V && m > 0) {
+        // the last column is kept unnormalised by the solver (its scale 1 / h_{m+1,m} is applied
+        // by the next iteration's first read)
+        LT_HIP(hipMemcpy(V, Q + qstride * rhs, (m + 1) * N2 * sizeof(double), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < N2; ++i) V[(size_t)m * N2 + i] *= scale;
+    }
+    if (U && m > 0) LT_HIP(hipMemcpy(U, Ud + ustride * rhs, m * N2 * sizeof(double), hipMemcpyDeviceToHost));
+    if (Hbar && m > 0) {
+        std::vector<double> hc((size_t)m * hstride);
+        LT_HIP(hipMemcpy(hc.data(), Hd + (size_t)jmax * hstride * rhs, hc.size() * sizeof(double),
+                         hipMemcpyDeviceToHost));
+        for (int j = 0; j < m; ++j)
+            for (int i = 0; i <= m; ++i) {
+                const bool in = i <= j + 1;
+                Hbar[2 * ((size_t)j * (m + 1) + i)] = in ? hc[(size_t)j * hstride + 2 * i] : 0.0;
+                Hbar[2 * ((size_t)j * (m + 1) + i) + 1] = in ? hc[(size_t)j * hstride + 2 * i + 1] : 0.0;
+            }
+    }
+    return LT_OK;
+}
+
 int lt_apply_operator(lt_handle* h, int level, double tau_re, double tau_im, const double* x, double* y, int nvec) {
     if (!h || !x || !y || nvec < 1 || level < 0 || level >= (int)h->levels.size()) return LT_EINVAL;
     return apply_operator<double>(h, level, cdouble(tau_re, tau_im), x, y, nvec, nullptr);
@@ -760,19 +928,14 @@ int lt_vcycle(lt_handle* h, double tau_re, double tau_im, int precision, int nu1
     return LT_EINVAL;
 }
 
-int lt_solve(lt_handle* h, const lt_points* sources, double q, const double* times, int ntimes,
-             const lt_contour* contour, const lt_points* receivers, const lt_opts* opts, double* phi_out,
-             lt_stats* stats) {
+int lt_solve(lt_handle* h, const lt_sources* src, const double* times, int ntimes, const lt_contour* contour,
+             const lt_points* receivers, const lt_opts* opts, double* phi_out, lt_stats* stats) {
     auto t0 = std::chrono::steady_clock::now();
-    if (!h || !sources || sources->n < 1 || !times || ntimes < 1 || !contour || !receivers || receivers->n < 1 ||
-        !phi_out || !std::isfinite(q)) {
+    if (!h || !times || ntimes < 1 || !contour || !receivers || receivers->n < 1 || !phi_out) {
         set_last_error("lt_solve: bad argument");
         return LT_EINVAL;
     }
-    if (sources->n > kMaxRhs) {
-        set_last_error("lt_solve: at most " + std::to_string(kMaxRhs) + " sources per call");
-        return LT_EINVAL;
-    }
+    LT_TRY(check_sources(src, 0, false, "lt_solve"));
     for (int t = 0; t < ntimes; ++t)
         if (!(times[t] > 0.0) || !std::isfinite(times[t])) {
             set_last_error("lt_solve: times must be positive");
@@ -790,48 +953,49 @@ int lt_solve(lt_handle* h, const lt_points* sources, double q, const double* tim
         return LT_EINVAL;
     }
     Plan plan;
-    LT_TRY(make_plan(times, ntimes, contour->nz, q, &o, &plan));
+    LT_TRY(make_plan(times, ntimes, contour->nz, 1.0, &o, &plan));
     PointsCSR sc, rcsr;
-    LT_TRY(points_csr(h->grid, sources, &sc));
+    LT_TRY(points_csr(h->grid, &src->pts, &sc));
+    scale_by_rates(src, &sc);
     LT_TRY(points_csr(h->grid, receivers, &rcsr));
     DevPoints ds, dr;
     LT_TRY(upload_points(h, sc, "src", &ds));
     LT_TRY(upload_points(h, rcsr, "rec", &dr));
-    const int R = sources->n;
+    const int ns = src->pts.n;
+    const int R = ns + (src->phi0 ? 1 : 0);
+    const int rinit = src->phi0 ? ns : R;
     const size_t N2 = 2 * (size_t)h->N;
     int rc = 0;
     double* b = wsp<double>(h, "b", R * N2, &rc);
     if (!b) return rc;
     LT_HIP(hipMemsetAsync(b, 0, R * N2 * sizeof(double), h->stream));
-    LT_TRY(launch_scatter_points(h->stream, R, h->N, ds.off, ds.cell, ds.wt, b));
+    if (ns > 0) LT_TRY(launch_scatter_points(h->stream, ns, h->N, ds.off, ds.cell, ds.wt, b));
+    if (src->phi0) LT_TRY(launch_mass_rhs(h->stream, h->N, h->levels[0].v64().m, src->phi0, b + (size_t)ns * N2));
     KrylovOut k;
     k.b = b;
     LT_TRY(prof_start(h, o.profile));
-    LT_TRY(run_krylov(h, plan, o, R, &dr, &k));
-    LT_TRY(launch_heads(h->stream, R, dr.n, ntimes, plan.nk, k.wq, k.G, k.Y, k.mcols, k.jmax, phi_out));
-    if (o.true_residual) LT_TRY(true_residuals(h, k, plan, stats));
+    int resolves = 0;
+    bool ok = false;
+    LT_TRY(solve_checked(h, plan, o, R, rinit, &dr, &k, stats, &resolves, &ok));
+    LT_TRY(launch_heads(h->stream, ns, src->phi0 ? ns : -1, dr.n, ntimes, plan.nk, k.wq, k.w, k.G, k.Y, k.mcols,
+                        k.jmax, phi_out));
     LT_HIP(hipStreamSynchronize(h->stream));
     if (stats && stats->iters_per_rhs)
         LT_HIP(hipMemcpy(stats->iters_per_rhs, k.mcols, R * sizeof(int), hipMemcpyDeviceToHost));
     LT_TRY(prof_finish(h, stats));
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    fill_stats(stats, k, (int)h->levels.size(), secs);
-    return k.converged ? LT_OK : LT_WNOTCONV;
+    fill_stats(stats, k, (int)h->levels.size(), secs, resolves);
+    return ok ? LT_OK : LT_WNOTCONV;
 }
 
-int lt_adjoint(lt_handle* h, const lt_points* sources, double q, const lt_points* receivers, const double* times,
-               int ntimes, const lt_contour* contour, const lt_opts* opts, double* dlnK, double* dlnS,
-               lt_stats* stats) {
+int lt_adjoint(lt_handle* h, const lt_sources* src, const lt_points* receivers, const double* times, int ntimes,
+               const lt_contour* contour, const lt_opts* opts, double* dlnK, double* dlnS, lt_stats* stats) {
     auto t0 = std::chrono::steady_clock::now();
-    if (!h || !sources || sources->n < 1 || !receivers || receivers->n < 1 || !times || ntimes < 1 || !contour ||
-        (!dlnK && !dlnS) || !std::isfinite(q)) {
+    if (!h || !receivers || receivers->n < 1 || !times || ntimes < 1 || !contour || (!dlnK && !dlnS)) {
         set_last_error("lt_adjoint: bad argument");
         return LT_EINVAL;
     }
-    if (sources->n + (long long)receivers->n > kMaxRhs) {
-        set_last_error("lt_adjoint: at most " + std::to_string(kMaxRhs) + " sources and receivers per call");
-        return LT_EINVAL;
-    }
+    LT_TRY(check_sources(src, receivers->n, true, "lt_adjoint"));
     for (int t = 0; t < ntimes; ++t)
         if (!(times[t] > 0.0) || !std::isfinite(times[t])) {
             set_last_error("lt_adjoint: times must be positive");
@@ -849,19 +1013,23 @@ int lt_adjoint(lt_handle* h, const lt_points* sources, double q, const lt_points
         return LT_EINVAL;
     }
     Plan plan;
-    LT_TRY(make_plan(times, ntimes, contour->nz, q, &o, &plan, true));
-    // right-hand sides: every source's b, then every receiver's B_m^T (adjoint fields)
-    lt_points all;
-    std::vector<double> xyz(3 * (size_t)(sources->n + receivers->n));
-    std::memcpy(xyz.data(), sources->xyz, sizeof(double) * 3 * sources->n);
-    std::memcpy(xyz.data() + 3 * sources->n, receivers->xyz, sizeof(double) * 3 * receivers->n);
-    all.n = sources->n + receivers->n;
-    all.xyz = xyz.data();
-    PointsCSR ac;
-    LT_TRY(points_csr(h->grid, &all, &ac));
+    LT_TRY(make_plan(times, ntimes, contour->nz, 1.0, &o, &plan, true));
+    // right-hand sides: every well's q_s b_s, then every receiver's B_m^T (adjoint fields)
+    const int ns = src->pts.n, nr = receivers->n, R = ns + nr;
+    PointsCSR sc, rcsr, ac;
+    LT_TRY(points_csr(h->grid, &src->pts, &sc));
+    scale_by_rates(src, &sc);
+    LT_TRY(points_csr(h->grid, receivers, &rcsr));
+    ac = sc;
+    for (int i = 0; i < nr; ++i) {
+        for (int e = rcsr.off[i]; e < rcsr.off[i + 1]; ++e) {
+            ac.cell.push_back(rcsr.cell[e]);
+            ac.wt.push_back(rcsr.wt[e]);
+        }
+        ac.off.push_back((int)ac.cell.size());
+    }
     DevPoints da;
     LT_TRY(upload_points(h, ac, "adj", &da));
-    const int ns = sources->n, nr = receivers->n, R = ns + nr;
     const size_t N2 = 2 * (size_t)h->N;
     int rc = 0;
     double* b = wsp<double>(h, "b", R * N2, &rc);
@@ -871,7 +1039,9 @@ int lt_adjoint(lt_handle* h, const lt_points* sources, double q, const lt_points
     KrylovOut k;
     k.b = b;
     LT_TRY(prof_start(h, o.profile));
-    LT_TRY(run_krylov(h, plan, o, R, nullptr, &k));
+    int resolves = 0;
+    bool ok = false;
+    LT_TRY(solve_checked(h, plan, o, R, R, nullptr, &k, stats, &resolves, &ok));
     // nodal fields of one time at a time, then the cell-wise contraction
     const int nk = plan.nk;
     double* X = wsp<double>(h, "Xadj", (size_t)R * nk * N2, &rc);
@@ -883,14 +1053,13 @@ int lt_adjoint(lt_handle* h, const lt_points* sources, double q, const lt_points
         LT_TRY(launch_sens(h->stream, L0, h->kappa.as<double>(), mS, ns, nr, nk, t, ntimes, X, k.zs, k.wq, dlnK,
                            dlnS));
     }
-    if (o.true_residual) LT_TRY(true_residuals(h, k, plan, stats));
     LT_HIP(hipStreamSynchronize(h->stream));
     if (stats && stats->iters_per_rhs)
         LT_HIP(hipMemcpy(stats->iters_per_rhs, k.mcols, R * sizeof(int), hipMemcpyDeviceToHost));
     LT_TRY(prof_finish(h, stats));
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    fill_stats(stats, k, (int)h->levels.size(), secs);
-    return k.converged ? LT_OK : LT_WNOTCONV;
+    fill_stats(stats, k, (int)h->levels.size(), secs, resolves);
+    return ok ? LT_OK : LT_WNOTCONV;
 }
 
 // ---------------------------------------------------------------- learned preconditioner

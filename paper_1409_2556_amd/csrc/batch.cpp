@@ -96,8 +96,8 @@ int lt_solve_batch(lt_solve_item* items, int n) {
     for (int i = 0; i < n; ++i) dev[i] = items[i].h->device;
     int rc = run_items(n, dev, status.data(), [items](int i) {
         lt_solve_item& it = items[i];
-        return lt_solve(it.h, it.sources, it.q, it.times, it.ntimes, it.contour, it.receivers, it.opts,
-                        it.phi_out, it.stats);
+        return lt_solve(it.h, it.src, it.times, it.ntimes, it.contour, it.receivers, it.opts, it.phi_out,
+                        it.stats);
     });
     for (int i = 0; i < n; ++i) items[i].status = status[i];
     return rc;
@@ -109,8 +109,8 @@ int lt_adjoint_batch(lt_adjoint_item* items, int n) {
     for (int i = 0; i < n; ++i) dev[i] = items[i].h->device;
     int rc = run_items(n, dev, status.data(), [items](int i) {
         lt_adjoint_item& it = items[i];
-        return lt_adjoint(it.h, it.sources, it.q, it.receivers, it.times, it.ntimes, it.contour, it.opts, it.dlnK,
-                          it.dlnS, it.stats);
+        return lt_adjoint(it.h, it.src, it.receivers, it.times, it.ntimes, it.contour, it.opts, it.dlnK, it.dlnS,
+                          it.stats);
     });
     for (int i = 0; i < n; ++i) items[i].status = status[i];
     return rc;

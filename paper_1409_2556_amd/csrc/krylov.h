@@ -54,16 +54,21 @@ int launch_cgs2(hipStream_t st, int N, int R, int j, const double* m, const doub
                 size_t qstride, double* H, int hstride, size_t hrstride, double* part, int pstride, double* c1,
                 double* c2, int cstride, double* scale, double* partn, const int* active);
 // fom: the FOM residual (GMRES residual / cosine of the last rotation) decides convergence
+// omega: [2][Ks] shift weights, the second row for right-hand sides r >= rinit (the initial head's term)
 int launch_ls_update(hipStream_t st, int R, int Ks, int j, cdouble tau, const double* zs, const double* omega,
-                     double tol, bool fom, const double* H, int hstride, size_t hrstride, const double* beta,
-                     const LSState& s, int* active, int* mcols, double* worst, int* conv);
+                     int rinit, double tol, bool fom, const double* H, int hstride, size_t hrstride,
+                     const double* beta, const LSState& s, int* active, int* mcols, double* worst, int* conv);
 int launch_gather(hipStream_t st, int R, int N, int np, const int* off, const int* cell, const double* wt,
                   const double* U, size_t ustride, int j, double* G, int jmax, const int* active);
 // fom: y solves the square Hessenberg system (FOM) instead of the least-squares problem
 int launch_backsolve(hipStream_t st, int R, int Ks, const int* mcols, const LSState& s, double* Y, int jmax,
                      bool fom = false);
-int launch_heads(hipStream_t st, int R, int np, int ntimes, int nk, const double* wq, const double* G,
-                 const double* Y, const int* mcols, int jmax, double* phi);
+// heads of the Rs wells (weights wq), plus the initial head's right-hand side r0 (weights w) on
+// every row when r0 >= 0; phi: [max(Rs, 1)][np][ntimes]
+int launch_heads(hipStream_t st, int Rs, int r0, int np, int ntimes, int nk, const double* wq, const double* w,
+                 const double* G, const double* Y, const int* mcols, int jmax, double* phi);
+// b[0:N] = m .* phi0 (the real plane of the initial head's right-hand side M phi0)
+int launch_mass_rhs(hipStream_t st, int N, const double* m, const double* phi0, double* b);
 int launch_form_x(hipStream_t st, int N, int R, int nc, int k0, int Ks, const double* U, size_t ustride,
                   const double* Y, int jmax, const int* mcols, double* X);
 template <typename T>

@@ -475,12 +475,15 @@ __global__ void k_iter_begin(int R, const int* __restrict__ active, int* __restr
 // Its QR factorisation is extended by one Givens rotation per column; |g_{j+1}| is the
 // GMRES residual norm of the shift.
 __global__ void k_ls_update(int R, int Ks, int j, double tau_re, double tau_im, const double* __restrict__ zs,
-                            const double* __restrict__ omega, double tol, int fom, const double* __restrict__ H,
+                            const double* __restrict__ omega, int rinit, double tol, int fom,
+                            const double* __restrict__ H,
                             int hstride, size_t hrstride, const double* __restrict__ beta, LSState st,
                             int* __restrict__ active, int* __restrict__ mcols, double* __restrict__ worst,
                             int* __restrict__ conv_flags) {
     int r = blockIdx.x;
     if (!active[r]) return;
+    // right-hand sides from rinit on (the initial head's term) weigh their shifts by |w_k|
+    const double* om = omega + (r >= rinit ? Ks : 0);
     extern __shared__ double sh[];  // h column, 2 (j + 2) doubles
     const double* Hc = H + hrstride * r + (size_t)hstride * j;
     for (int c = threadIdx.x; c < 2 * (j + 2); c += blockDim.x) sh[c] = Hc[c];
@@ -553,7 +556,7 @@ __global__ void k_ls_update(int R, int Ks, int j, double tau_re, double tau_im, 
         // square system is singular, c = 0)
         double res = hypot(gn.re, gn.im) / beta[r];
         if (fom) res = c > 0.0 ? res / c : HUGE_VAL;
-        double wres = omega[k] * res;
+        double wres = om[k] * res;
         st.res[base] = res;
         myw = fmax(myw, wres);
         int ok = wres <= tol;
@@ -635,15 +638,13 @@ __global__ void k_gather(int R, int N, int np, const int* __restrict__ off, cons
     g[2 * p + 1] = im;
 }
 
-// phi[r][p][t] = 2 Re sum_{k in t} wq_k sum_j G[r][j][p] Y[r][j][k]
-__global__ void k_heads(int R, int np, int ntimes, int nk, const double* __restrict__ wq,
-                        const double* __restrict__ G, const double* __restrict__ Y, const int* __restrict__ mcols,
-                        int jmax, double* __restrict__ phi) {
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= R * np * ntimes) return;
-    int t = idx % ntimes, p = (idx / ntimes) % np, r = idx / (ntimes * np);
-    const int Ks = ntimes * nk;
-    const int m = mcols[r];
+// phi[s][p][t] = 2 Re sum_{k in t} ( wq_k sum_j G[s][j][p] Y[s][j][k]
+//                                    + w_k sum_j G[r0][j][p] Y[r0][j][k] ),
+// the second term (the initial head's right-hand side r0, factor 1) only when r0 >= 0;
+// rows s < Rs are the wells (with Rs = 0 the one row holds the initial head's heads alone).
+__device__ __forceinline__ double heads_term(int r, int p, int t, int nk, int Ks, int np, const double* __restrict__ wk,
+                                             const double* __restrict__ G, const double* __restrict__ Y, int m,
+                                             int jmax) {
     double acc = 0;
     for (int kk = 0; kk < nk; ++kk) {
         int k = t * nk + kk;
@@ -655,10 +656,31 @@ __global__ void k_heads(int R, int np, int ntimes, int nk, const double* __restr
             s.re += pr.re;
             s.im += pr.im;
         }
-        c64 w = {wq[2 * k], wq[2 * k + 1]};
+        c64 w = {wk[2 * k], wk[2 * k + 1]};
         acc += w.re * s.re - w.im * s.im;
     }
+    return acc;
+}
+
+__global__ void k_heads(int Rs, int r0, int np, int ntimes, int nk, const double* __restrict__ wq,
+                        const double* __restrict__ w, const double* __restrict__ G, const double* __restrict__ Y,
+                        const int* __restrict__ mcols, int jmax, double* __restrict__ phi) {
+    const int rows = Rs > 0 ? Rs : 1;
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= rows * np * ntimes) return;
+    int t = idx % ntimes, p = (idx / ntimes) % np, s = idx / (ntimes * np);
+    const int Ks = ntimes * nk;
+    double acc = 0;
+    if (s < Rs) acc = heads_term(s, p, t, nk, Ks, np, wq, G, Y, mcols[s], jmax);
+    if (r0 >= 0) acc += heads_term(r0, p, t, nk, Ks, np, w, G, Y, mcols[r0], jmax);
     phi[idx] = 2.0 * acc;
+}
+
+// b = M phi0 (real part; the imaginary plane stays as the caller cleared it)
+__global__ void k_mass_rhs(int N, const double* __restrict__ m, const double* __restrict__ phi0,
+                           double* __restrict__ b) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) b[i] = m[i] * phi0[i];
 }
 
 // ---------------------------------------------------------------- true residual
@@ -1309,13 +1331,13 @@ int launch_cgs2(hipStream_t st, int N, int R, int j, const double* m, const doub
 }
 
 int launch_ls_update(hipStream_t st, int R, int Ks, int j, cdouble tau, const double* zs, const double* omega,
-                     double tol, bool fom, const double* H, int hstride, size_t hrstride, const double* beta,
-                     const LSState& s, int* active, int* mcols, double* worst, int* conv) {
+                     int rinit, double tol, bool fom, const double* H, int hstride, size_t hrstride,
+                     const double* beta, const LSState& s, int* active, int* mcols, double* worst, int* conv) {
     int threads = ((Ks + 63) / 64) * 64;
     if (threads > kB) threads = kB;
     size_t shm = sizeof(double) * 2 * (j + 2);
-    k_ls_update<<<R, threads, shm, st>>>(R, Ks, j, tau.real(), tau.imag(), zs, omega, tol, fom ? 1 : 0, H, hstride,
-                                         hrstride, beta, s, active, mcols, worst, conv);
+    k_ls_update<<<R, threads, shm, st>>>(R, Ks, j, tau.real(), tau.imag(), zs, omega, rinit, tol, fom ? 1 : 0, H,
+                                         hstride, hrstride, beta, s, active, mcols, worst, conv);
     LT_HIP(hipGetLastError());
     return 0;
 }
@@ -1335,11 +1357,17 @@ int launch_backsolve(hipStream_t st, int R, int Ks, const int* mcols, const LSSt
     return 0;
 }
 
-int launch_heads(hipStream_t st, int R, int np, int ntimes, int nk, const double* wq, const double* G,
-                 const double* Y, const int* mcols, int jmax, double* phi) {
-    int tot = R * np * ntimes;
+int launch_heads(hipStream_t st, int Rs, int r0, int np, int ntimes, int nk, const double* wq, const double* w,
+                 const double* G, const double* Y, const int* mcols, int jmax, double* phi) {
+    int tot = (Rs > 0 ? Rs : 1) * np * ntimes;
     if (tot == 0) return 0;
-    k_heads<<<nb_for(tot), kB, 0, st>>>(R, np, ntimes, nk, wq, G, Y, mcols, jmax, phi);
+    k_heads<<<nb_for(tot), kB, 0, st>>>(Rs, r0, np, ntimes, nk, wq, w, G, Y, mcols, jmax, phi);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_mass_rhs(hipStream_t st, int N, const double* m, const double* phi0, double* b) {
+    k_mass_rhs<<<nb_for(N), kB, 0, st>>>(N, m, phi0, b);
     LT_HIP(hipGetLastError());
     return 0;
 }

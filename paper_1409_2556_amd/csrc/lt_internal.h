@@ -16,7 +16,10 @@ namespace lt {
 
 using cdouble = std::complex<double>;
 constexpr int kMaxRhs = 1000;  // right-hand sides per solve (the host flag buffer holds that many)
-constexpr int kMaxTunedLevels = 16;  // levels whose smoother tile shape can be tuned
+constexpr int kMaxTunedLevels = 16;
+// Cells per grid.  The fused smoothers address a vector plane with 32-bit byte offsets
+// (cell index times 8 for FP64 must stay below 2^32) and several kernels form 2 N in int.
+constexpr long long kMaxCells = 1LL << 28;  // levels whose smoother tile shape can be tuned
 
 // ---------------------------------------------------------------- errors
 #define LT_HIP(...)                                                      \
@@ -102,6 +105,7 @@ struct lt_handle {
     std::map<std::vector<unsigned long long>, std::pair<hipGraphExec_t, int>> graphs;
     unsigned long long graphs_gen = 0;  // ws_gen the cached graphs were captured at
     void* pinned = nullptr;  // small pinned host area for flags
+    int last_R = 0, last_jmax = 0;  // shape of the basis the last solve left in the workspaces
     // profiling of one kernel family (opts.profile): event pairs and a byte counter
     int prof_target = 0;
     std::vector<hipEvent_t> prof_events;
@@ -132,6 +136,8 @@ struct Plan {
     std::vector<cdouble> z;             // [ntimes * nk]
     std::vector<cdouble> wq;            // w_k * qhat(z_k)  [ntimes * nk]
     std::vector<double> omega;          // |wq| / max |wq| within the same time
+    std::vector<cdouble> w;             // w_k alone (the initial head's term)  [ntimes * nk]
+    std::vector<double> omega_init;     // |w| / max |w| within the same time
     std::vector<cdouble> tau_sched;     // cyclic preconditioner shifts
 };
 int talbot(int nz, double t, cdouble* z, cdouble* w);

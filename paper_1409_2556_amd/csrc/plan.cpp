@@ -47,17 +47,25 @@ int make_plan(const double* times, int ntimes, int nz, double q, const lt_opts* 
     p->z.assign((size_t)ntimes * p->nk, 0.0);
     p->wq.assign((size_t)ntimes * p->nk, 0.0);
     p->omega.assign((size_t)ntimes * p->nk, 0.0);
+    p->w.assign((size_t)ntimes * p->nk, 0.0);
+    p->omega_init.assign((size_t)ntimes * p->nk, 0.0);
     std::vector<cdouble> w(p->nk);
     for (int t = 0; t < ntimes; ++t) {
         LT_TRY(talbot(nz, times[t], &p->z[(size_t)t * p->nk], w.data()));
-        double mx = 0.0, mz = 0.0;
+        double mx = 0.0, mz = 0.0, mw = 0.0;
         for (int k = 0; k < p->nk; ++k) {
             cdouble zk = p->z[(size_t)t * p->nk + k];
             cdouble v = w[k] * (q / zk);  // qhat(z) = q / z for a constant rate from t = 0
             p->wq[(size_t)t * p->nk + k] = v;
+            p->w[(size_t)t * p->nk + k] = w[k];
             mx = std::max(mx, std::abs(v));
             mz = std::max(mz, std::abs(v * zk));
+            mw = std::max(mw, std::abs(w[k]));
         }
+        // the initial head's term M phi0 enters with factor 1: its shifts weigh by |w_k|
+        for (int k = 0; k < p->nk; ++k)
+            p->omega_init[(size_t)t * p->nk + k] =
+                o->conv == LT_CONV_RELATIVE ? 1.0 : (mw > 0 ? std::abs(w[k]) / mw : 1.0);
         // Heads weigh shift k by |w_k qhat_k|.  The storage sensitivity weighs the same
         // fields by |w_k qhat_k z_k| (the z dM/dp term of Section 5.2), so for it each
         // shift must meet the stricter of the two weightings.

@@ -87,3 +87,18 @@ def test_setup_rejects_bad_water_table_without_gpu(lib):
     # a valid water table passes the checks and stops only at the missing device
     b = lib.lt_bc((C.c_int * 6)(0, 0, 0, 2, 0, 0), 0.1)
     assert so.lt_setup(C.byref(g), ptr, ptr, C.byref(b), None, C.byref(out)) == lib.LT_EHIP
+
+
+def test_setup_rejects_grids_beyond_the_cell_limit_without_gpu(lib):
+    """More than 2^28 cells would overflow the smoothers' 32-bit byte offsets of an FP64
+    vector plane; lt_setup refuses such a grid before touching the device."""
+    so = lib._lib
+    buf = np.ones(16)
+    ptr = buf.ctypes.data
+    out = lib._h()
+    big = lib.lt_grid(3, (C.c_int * 3)(1024, 1024, 257), (C.c_double * 3)(1.0, 1.0, 1.0))
+    assert so.lt_setup(C.byref(big), ptr, ptr, None, None, C.byref(out)) == lib.LT_EINVAL
+    assert "2^28" in lib.lt_last_error()
+    # exactly 2^28 cells passes the size check and stops only at the missing device
+    edge = lib.lt_grid(3, (C.c_int * 3)(1024, 1024, 256), (C.c_double * 3)(1.0, 1.0, 1.0))
+    assert so.lt_setup(C.byref(edge), ptr, ptr, None, None, C.byref(out)) == lib.LT_EHIP

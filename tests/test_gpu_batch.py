@@ -10,7 +10,7 @@ import torch
 
 import workloads as wl
 from oracle.heads import heads
-from gpu_util import device_problem_on_stream, rel_err_per_source, announce
+from gpu_util import device_problem_on_stream, announce, check_heads
 
 pytestmark = pytest.mark.gpu
 
@@ -57,11 +57,11 @@ def test_batch_matches_oracle(lt):
     assert rc == 0
     for p, got, st in zip(ps, outs, stats):
         ref = heads(p.n, p.h, p.kappa, p.S, p.sources, p.receivers, p.times, p.nz_contour, q=p.q, workers=8)
-        err = rel_err_per_source(got.cpu().numpy(), ref).max()
-        print(p.name, p.n, "iters", st["iters_max"], "err", err, "true", st["true_relres_max"], flush=True)
-        assert err <= 1e-6
-        # the refinement gap of the inexact inner solves adds a few tol (relax 1)
-        assert st["true_relres_max"] <= 1e-9
+        print(p.name, p.n, "iters", st["iters_max"], "resolves", st["resolves"], "true", st["true_relres_max"],
+              flush=True)
+        check_heads(got.cpu().numpy(), ref, 1e-6, f"batch {p.name}")
+        # rc 0: the FP64 true residual met the weighted tolerance
+        assert st["true_relres_max"] <= 1e-10
     for h in hs:
         h.close()
 

@@ -10,7 +10,7 @@ import torch
 
 import workloads as wl
 from oracle.heads import heads
-from gpu_util import device_problem, rel_err_per_source, announce
+from gpu_util import device_problem, announce, check_heads
 
 pytestmark = pytest.mark.gpu
 
@@ -74,7 +74,7 @@ def test_tiny_grids_match_oracle(lt, n):
     phi, st = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, lt.make_opts(tol=1e-12))
     ref = heads(p.n, p.h, p.kappa, p.S, p.sources, p.receivers, p.times, p.nz_contour, q=p.q, ndim=p.ndim)
     assert st["rc"] == 0
-    assert rel_err_per_source(phi.cpu().numpy(), ref).max() <= 1e-8
+    check_heads(phi.cpu().numpy(), ref, 1e-8, f"tiny {n}")
     h.close()
 
 
@@ -86,7 +86,7 @@ def test_wells_on_walls_and_corners(lt):
     phi, st = lt.lt_solve(h, pts, 1.0, p.times, p.nz_contour, pts, lt.make_opts(tol=1e-12))
     ref = heads(p.n, p.h, p.kappa, p.S, pts, pts, p.times, p.nz_contour, q=1.0, ndim=p.ndim)
     assert st["rc"] == 0
-    assert rel_err_per_source(phi.cpu().numpy(), ref).max() <= 1e-8
+    check_heads(phi.cpu().numpy(), ref, 1e-8, "wall wells")
     h.close()
 
 

@@ -10,7 +10,7 @@ import pytest
 import workloads as wl
 from oracle.fv import assemble
 from oracle.heads import heads_problem, heads
-from gpu_util import device_problem, rel_err_per_source, announce
+from gpu_util import device_problem, check_heads, announce
 
 pytestmark = pytest.mark.gpu
 
@@ -125,13 +125,12 @@ def test_heads_match_oracle(lt, case, prec):
     phi, st = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, opts)
     got = phi.cpu().numpy()
     ref = heads_problem(p)
-    err = rel_err_per_source(got, ref)
-    print(case, prec, "iters", st["iters_max"], "vcycles", st["vcycles"], "err", err,
+    print(case, prec, "iters", st["iters_max"], "vcycles", st["vcycles"], "resolves", st["resolves"],
           "true", st["true_relres_max"], flush=True)
     assert st["rc"] == 0
-    assert err.max() <= (1e-6 if prec == 0 else 1e-5)
-    # the FP64 true residual of every shift meets the weighted tolerance (small slack for relaxation)
-    assert st["true_relres_max"] <= 5 * tol
+    check_heads(got, ref, 1e-6 if prec == 0 else 1e-5, f"{case} prec {prec}")
+    # a return code of 0 means the FP64 true residual of every shift met the weighted tolerance
+    assert st["true_relres_max"] <= tol
     h.close()
 
 
@@ -180,10 +179,9 @@ def test_fom_heads_match_oracle(lt, case, prec):
     of = lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau, method=lt.LT_METHOD_FOM)
     _, sg = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, og)
     phi, sf = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, of)
-    err = rel_err_per_source(phi.cpu().numpy(), ref)
-    print(case, prec, "fom iters", sf["iters_max"], "gmres iters", sg["iters_max"], "err", err.max(), flush=True)
+    print(case, prec, "fom iters", sf["iters_max"], "gmres iters", sg["iters_max"], flush=True)
     assert sf["rc"] == 0
-    assert err.max() <= (1e-6 if prec == 0 else 1e-5)
-    assert sf["true_relres_max"] <= 5 * tol
+    check_heads(phi.cpu().numpy(), ref, 1e-6 if prec == 0 else 1e-5, f"fom {case} prec {prec}")
+    assert sf["true_relres_max"] <= tol
     assert sf["iters_max"] >= sg["iters_max"]
     h.close()

@@ -10,7 +10,7 @@ import pytest
 
 import workloads as wl
 from oracle.heads import heads_problem
-from gpu_util import device_problem, rel_err_per_source, announce
+from gpu_util import device_problem, announce, check_heads
 
 pytestmark = pytest.mark.gpu
 
@@ -26,14 +26,13 @@ def test_flexible_beats_single_and_both_match_oracle(lt, relax, inner_max, conv)
         opts = lt.make_opts(tol=1e-10, precision=lt.LT_PREC_FP64, n_tau=n_tau, relax=relax,
                             inner_max=inner_max, maxit=400, conv=conv)
         phi, st = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, opts)
-        err = rel_err_per_source(phi.cpu().numpy(), ref)
-        print("n_tau", n_tau, "iters", st["iters_max"], "err", err.max(), flush=True)
+        print("n_tau", n_tau, "iters", st["iters_max"], "resolves", st["resolves"], flush=True)
         assert st["rc"] == 0
-        assert err.max() <= 1e-6
+        check_heads(phi.cpu().numpy(), ref, 1e-6, f"tau study n_tau {n_tau} relax {relax} conv {conv}")
         if conv == lt.LT_CONV_RELATIVE:
-            # every shift's own true residual meets the tolerance, up to the gap that relaxed
-            # (relax > 1) preconditioner solves leave between the Arnoldi and the true residual
-            assert st["true_relres"].max() <= 5e-10 * max(1.0, relax)
+            # rc 0: every shift's own FP64 true residual met the tolerance (relaxed solves whose
+            # gap opened are solved again with a tighter inner tolerance)
+            assert st["true_relres"].max() <= 1e-10
         its[n_tau] = st["iters_max"]
     if conv == lt.LT_CONV_WEIGHTED:
         assert its[2] < its[1]

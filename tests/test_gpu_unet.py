@@ -8,7 +8,7 @@ import workloads as wl
 import unet_reference as ref
 from oracle.fv import assemble
 from oracle.heads import heads_problem
-from gpu_util import device_problem, rel_err_per_source, announce
+from gpu_util import device_problem, check_heads, announce
 
 pytestmark = pytest.mark.gpu
 
@@ -113,13 +113,42 @@ def test_solver_with_network_still_matches_oracle(lt, kind, prec):
     tol = 1e-10 if prec == 0 else 1e-8
     o = lt.make_opts(tol=tol, precision=prec, precond=lt.LT_PRECOND_UNET_GMG)
     phi, st = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, o)
-    err = rel_err_per_source(phi.cpu().numpy(), heads_problem(p))
-    print(kind, prec, "err", err, "net", st["net_applied"], st["net_rejected"], "vc", st["vcycles"], flush=True)
-    assert err.max() <= (1e-6 if prec == 0 else 1e-5)
-    assert st["true_relres_max"] <= 5 * tol
+    print(kind, prec, "net", st["net_applied"], st["net_rejected"], "vc", st["vcycles"], flush=True)
+    assert st["rc"] == 0
+    check_heads(phi.cpu().numpy(), heads_problem(p), 1e-6 if prec == 0 else 1e-5, f"unet {kind} prec {prec}")
+    assert st["true_relres_max"] <= tol
     assert st["net_applied"] > 0
     if kind == "nan":
         assert st["net_rejected"] == st["net_applied"]
+    lt.lt_unet_attach(h, None)
+    net.close()
+    h.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_trained_network_in_the_solver_matches_oracle(lt, prec):
+    """A network trained by the library's own kernels (400 Adam steps on 128x128 fields), kept
+    on for every preconditioner solve of an unseen 256x256 field: the heads still match the
+    direct-solve oracle element by element, since every guess is followed by the V-cycle
+    refinement and the true residual judges the result."""
+    from paper_1409_2556_amd.train_unet import train
+    p = wl.make_problem("C4_256", nsrc=3, nrec=8)
+    announce("trained unet solver", prec, p.n)
+    net, hist = train(steps=400, batch=8, lr=1e-3, verbose=False)
+    print("training loss (last 20)", float(np.mean(hist[-20:])), flush=True)
+    assert np.mean(hist[-20:]) < np.mean(hist[:20])
+    h = device_problem(lt, p)
+    lt.lt_unet_attach(h, net)
+    tol = 1e-10 if prec == 0 else 1e-8
+    o = lt.make_opts(tol=tol, precision=prec, precond=lt.LT_PRECOND_UNET_GMG, net_keep=1e30)
+    phi, st = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, o)
+    print(prec, "net", st["net_applied"], st["net_rejected"], "disabled", st["net_disabled_at"], "iters",
+          st["iters_max"], "vcycles", st["vcycles"], "true", st["true_relres_max"], flush=True)
+    assert st["rc"] == 0
+    assert st["net_disabled_at"] == 0 and st["net_applied"] >= st["iters_max"]
+    check_heads(phi.cpu().numpy(), heads_problem(p, workers=8), 1e-6 if prec == 0 else 1e-5,
+                f"trained unet prec {prec}")
+    assert st["true_relres_max"] <= tol
     lt.lt_unet_attach(h, None)
     net.close()
     h.close()

@@ -18,7 +18,7 @@ import workloads as wl
 from oracle.fv import assemble
 from oracle.heads import heads_problem
 from oracle.jacobian import jacobian
-from gpu_util import device_problem, rel_err_per_source, announce
+from gpu_util import device_problem, rel_err_per_source, check_heads, announce
 
 pytestmark = pytest.mark.gpu
 
@@ -73,11 +73,10 @@ def test_heads_match_oracle(lt, case, prec):
     tol = 1e-10 if prec == 0 else 1e-8
     opts = lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau)
     phi, st = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, opts)
-    err = rel_err_per_source(phi.cpu().numpy(), ref)
-    print(case, prec, "iters", st["iters_max"], "err", err.max(), flush=True)
+    print(case, prec, "iters", st["iters_max"], "resolves", st["resolves"], flush=True)
     assert st["rc"] == 0
-    assert err.max() <= (1e-6 if prec == 0 else 1e-5)
-    assert st["true_relres_max"] <= 5 * tol
+    check_heads(phi.cpu().numpy(), ref, 1e-6 if prec == 0 else 1e-5, f"water table {case} prec {prec}")
+    assert st["true_relres_max"] <= tol
     h.close()
 
 
@@ -121,7 +120,7 @@ def test_batch_mixes_boundaries_bit_exactly(lt):
     for got, want in zip(phis, singles):
         np.testing.assert_array_equal(got.cpu().numpy(), want)
     ref = heads_problem(pw)
-    assert rel_err_per_source(singles[0], ref).max() <= 1e-6
+    check_heads(singles[0], ref, 1e-6, "water-table batch")
     for h in hs:
         h.close()
 
@@ -134,5 +133,5 @@ def test_fom_variant_with_water_table(lt):
     opts = lt.make_opts(tol=1e-10, precision=0, n_tau=p.n_tau, method=lt.LT_METHOD_FOM)
     phi, st = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, opts)
     assert st["rc"] == 0
-    assert rel_err_per_source(phi.cpu().numpy(), ref).max() <= 1e-6
+    check_heads(phi.cpu().numpy(), ref, 1e-6, "water-table fom")
     h.close()

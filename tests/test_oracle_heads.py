@@ -137,3 +137,57 @@ def test_direct_solves_are_exact():
         A = K.toarray() + zk * np.diag(m)
         np.testing.assert_allclose(x, np.linalg.solve(A, rhs), rtol=1e-12)
         assert np.abs(A @ x - rhs).max() <= 1e-13 * np.abs(A).max() * np.abs(x).max()
+
+
+def _exact_ivp(K, m, phi0, t):
+    """phi(t) for M phi' + K phi = 0, phi(0) = phi0, by the same eigendecomposition."""
+    Ms, Mi = np.sqrt(m), 1.0 / np.sqrt(m)
+    A = Mi[:, None] * K.toarray() * Mi[None, :]
+    lam, Q = np.linalg.eigh(A)
+    return Mi * (Q @ (np.exp(-lam * t) * (Q.T @ (Ms * phi0))))
+
+
+@pytest.mark.parametrize("n", [(6, 5, 1), (4, 3, 3)])
+def test_initial_head_and_rates_match_dense_exponential(n):
+    """Two wells at different rates plus a random initial head: each row is the exact
+    semi-discrete solution q_s (pumping response of well s) + (decay of phi0), within the
+    contour's error (Section 2.1 transformed system with the M phi0 term)."""
+    n, h, kap, S = _tiny(n, seed=8)
+    N = int(np.prod(n))
+    src = [(0.5, 0.45, 0.5), (0.3, 0.7, 0.3)]
+    rates = np.array([1.7, -0.6])
+    rec = [(0.2, 0.3, 0.4), (0.75, 0.6, 0.6)]
+    phi0 = np.random.default_rng(4).standard_normal(N)
+    nz = 24
+    times = wl.T_D * np.array([0.01, 0.1, 1.0])
+    phi = heads(n, h, kap, S, src, rec, times, nz, q=rates, phi0=phi0)
+    K, m = assemble(n, h, kap, S)
+    B = point_weights(n, h, src).toarray()
+    Br = point_weights(n, h, rec).toarray()
+    scale = max(np.abs(Br @ _exact(K, m, B[0], 1e3)).max(), np.abs(phi0).max())
+    tol = 20.0 * 3.89 ** (-nz) * np.exp(0.171 * nz) + 1e-12
+    for it, t in enumerate(times):
+        ivp = Br @ _exact_ivp(K, m, phi0, t)
+        for s in range(2):
+            ex = Br @ _exact(K, m, B[s], t, q=rates[s]) + ivp
+            assert np.abs(phi[s, :, it] - ex).max() <= tol * scale
+
+
+def test_initial_head_alone_gives_one_row():
+    """With no wells the result is one row of initial-value heads, equal to the phi0 part of
+    any run with wells (superposition)."""
+    n, h, kap, S = _tiny((7, 6, 1), seed=2)
+    N = int(np.prod(n))
+    phi0 = np.random.default_rng(1).standard_normal(N)
+    rec = [(0.2, 0.3, 0.0), (0.6, 0.5, 0.0)]
+    times = wl.T_D * np.array([0.02, 0.3])
+    alone = heads(n, h, kap, S, np.zeros((0, 3)), rec, times, 20, phi0=phi0)
+    assert alone.shape == (1, 2, 2)
+    both = heads(n, h, kap, S, [(0.5, 0.5, 0.0)], rec, times, 20, q=2.0, phi0=phi0)
+    wells = heads(n, h, kap, S, [(0.5, 0.5, 0.0)], rec, times, 20, q=2.0)
+    np.testing.assert_allclose(both - wells, alone, rtol=1e-10, atol=1e-14)
+    K, m = assemble(n, h, kap, S)
+    Br = point_weights(n, h, rec).toarray()
+    for it, t in enumerate(times):
+        ex = Br @ _exact_ivp(K, m, phi0, t)
+        assert np.abs(alone[0, :, it] - ex).max() <= 1e-6 * np.abs(phi0).max()
