@@ -243,9 +243,11 @@ int lt_setup(const lt_grid* grid, const double* kappa, const double* S, const lt
  * least-squares residual; then (opts.true_residual = 1) the FP64 true
  * residual of every (rhs, shift) is computed, and a right-hand side whose
  * weighted true residual misses tol (relaxed preconditioner solves leave a
- * gap between the two) is solved again from the start with the inner
- * tolerance tightened by the measured excess, at most twice
- * (lt_stats.resolves).  LT_WNOTCONV if some shift still misses tol, by
+ * gap between the two) is solved again from the start with its tolerance,
+ * and with it the inner tolerance, tightened by its own measured excess
+ * (rounded to a power of two, so a right-hand side's result does not
+ * depend on the others in the call) and four times the V-cycles per
+ * preconditioner solve, at most twice (lt_stats.resolves).  LT_WNOTCONV if some shift still misses tol, by
  * either residual, after that (phi_out then holds the best estimate).
  * LT_EINVAL, before any work, for more than 1000 right-hand sides, a
  * non-finite rate, or neither wells nor phi0. */

@@ -583,8 +583,12 @@ int true_residuals(lt_handle* h, const KrylovOut& k, const Plan& plan, lt_stats*
 // The flexible Arnoldi of run_krylov, then the FP64 true residual as the judge: a
 // right-hand side whose Arnoldi converged but whose weighted true residual misses tol
 // (the gap that relaxed preconditioner solves leave, sum_j y_j rho_j) is solved again
-// from the start with the tolerance, and with it the inner tolerance relax * tol, scaled
-// by 0.5 / excess; at most twice.  *ok: every (rhs, shift) meets tol by both residuals.
+// from the start with its own tolerance, and with it the inner tolerance relax * tol,
+// scaled by 0.5 / excess (its own excess, rounded down to a power of two), and with four
+// times the V-cycles allowed per preconditioner solve (a weak coarse-grid solve can need
+// more than inner_max to reach the tighter inner tolerance); at most twice.  Right-hand sides with the same factor are solved again together; the factor
+// depends on the right-hand side alone, so its result does not depend on which other
+// right-hand sides share the call.  *ok: every (rhs, shift) meets tol by both residuals.
 int solve_checked(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int rinit, const DevPoints* rec,
                   KrylovOut* k, lt_stats* stats, int* resolves, bool* ok) {
     *resolves = 0;
@@ -594,34 +598,37 @@ int solve_checked(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int r
     bool tr_ok = true;
     if (o.true_residual) {
         std::vector<double> wr;
-        double tcur = o.tol;
+        std::vector<int> tshift(R, 0);  // tolerance of rhs r: tol * 2^-tshift[r]
         for (int attempt = 0;; ++attempt) {
             LT_TRY(true_residuals(h, *k, plan, stats, &wr));
-            std::vector<int> redo(R, 0);
-            double excess = 0.0;
-            int nredo = 0;
+            std::map<int, std::vector<int>> groups;  // new tshift -> its right-hand sides
             tr_ok = true;
             for (int r = 0; r < R; ++r) {
                 if (!(wr[r] <= o.tol)) {
                     tr_ok = false;
                     if (!nc[r]) {
-                        redo[r] = 1;
-                        ++nredo;
-                        excess = std::max(excess, std::isfinite(wr[r]) ? wr[r] / o.tol : 1e6);
+                        const double excess = std::isfinite(wr[r]) ? std::min(wr[r] / o.tol, 1e6) : 1e6;
+                        // 0.5 / excess rounded down to a power of two
+                        const int e = (int)std::ceil(std::log2(2.0 * excess) - 1e-12);
+                        tshift[r] += std::max(e, 1);
+                        groups[tshift[r]].push_back(r);
                     }
                 }
             }
-            if (nredo == 0 || attempt == 2) break;
-            lt_opts o2 = o;
-            tcur *= 0.5 / excess;
-            o2.tol = tcur;
-            *resolves += nredo;
-            LT_TRY(run_krylov(h, plan, o2, R, rinit, rec, k, &redo));
-            for (int r = 0; r < R; ++r)
-                if (redo[r]) nc[r] = k->notconv[r];
-            vcycles += k->vcycles;
-            napp += k->net_applied;
-            nrej += k->net_rejected;
+            if (groups.empty() || attempt == 2) break;
+            for (const auto& g : groups) {
+                std::vector<int> redo(R, 0);
+                for (int r : g.second) redo[r] = 1;
+                lt_opts o2 = o;
+                o2.tol = std::ldexp(o.tol, -g.first);
+                o2.inner_max = std::min(o.inner_max << (2 * (attempt + 1)), 1000);
+                *resolves += (int)g.second.size();
+                LT_TRY(run_krylov(h, plan, o2, R, rinit, rec, k, &redo));
+                for (int r : g.second) nc[r] = k->notconv[r];
+                vcycles += k->vcycles;
+                napp += k->net_applied;
+                nrej += k->net_rejected;
+            }
         }
     }
     k->vcycles = vcycles;

@@ -615,6 +615,11 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
     const bool cb = lc < nl && nl - lc <= kMaxCBLevels;
     if (!cb) lc = nl - 1;  // generic path down to the coarsest level
     const bool fused2d = h->grid.ndim == 2 && nu1 >= 1 && nu1 <= 3 && nu2 >= 1 && nu2 <= 3;
+    // 3D levels: z-marching tiles (mg3d.hip) for FP32 cycles of up to two sweeps, whose
+    // per-thread plane ring fits the register file
+    const bool fused3d = h->grid.ndim == 3 && sizeof(T) == 4 && nu1 >= 1 && nu1 <= 2 && nu2 >= 1 && nu2 <= 2;
+    const bool fusedT = fused2d || fused3d;
+    auto tile3_of = [&](int l) { return h->levels[l].n[0] >= 32 ? 0 : 1; };
     const int* tiles = h->tiles[sizeof(T) == 4 ? 1 : 0];
     auto tile_of = [&](int l) { return l < kMaxTunedLevels ? tiles[l] : 0; };
     const char* tag = sizeof(T) == 8 ? "64_" : "32_";
@@ -626,13 +631,13 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
             bs[l] = wsp<T>(h, (std::string("mgb") + tag + std::to_string(l)).c_str(), per, &rc);
             if (!bs[l]) return rc;
         }
-        if (l == 0 && (!fused2d || lc == 0)) {
+        if (l == 0 && (!fusedT || lc == 0)) {
             xpre[0] = x0;
         } else {
             xpre[l] = wsp<T>(h, (std::string("mgx") + tag + std::to_string(l)).c_str(), per, &rc);
             if (!xpre[l]) return rc;
         }
-        xpost[l] = fused2d && l > 0 && l < lc
+        xpost[l] = fusedT && l > 0 && l < lc
                        ? wsp<T>(h, (std::string("mgy") + tag + std::to_string(l)).c_str(), per, &rc)
                        : xpre[l];
         if (!xpost[l]) return rc;
@@ -654,6 +659,15 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
             if (prof) LT_TRY(prof_begin(h, LT_PROF_PRE_FINE, &pc, &e0, &e1));
             LT_TRY(launch_pre2d<T>(st, v, tr, ti, nu1, tile_of(l), bs[l], xpre[l], C.n[0], C.n[1], C.coarsened_from_fine[0],
                                    C.coarsened_from_fine[1], bs[l + 1], R, active, pc, e0, e1));
+            if (prof) LT_TRY(prof_end(h, LT_PROF_PRE_FINE));
+        } else if (fused3d) {
+            unsigned long long* pc = nullptr;
+            const bool prof = l == 0 && h->prof_target == LT_PROF_PRE_FINE;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (prof) LT_TRY(prof_begin(h, LT_PROF_PRE_FINE, &pc, &e0, &e1));
+            LT_TRY(launch_pre3d<T>(st, v, tr, ti, nu1, tile3_of(l), bs[l], xpre[l], C.n[0], C.n[1], C.n[2],
+                                   C.coarsened_from_fine[0], C.coarsened_from_fine[1], C.coarsened_from_fine[2],
+                                   bs[l + 1], R, active, pc, e0, e1));
             if (prof) LT_TRY(prof_end(h, LT_PROF_PRE_FINE));
         } else {
             const size_t per = 2 * (size_t)L.N;
@@ -738,6 +752,16 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
                                         C.coarsened_from_fine[0], C.coarsened_from_fine[1], gh, xpost[l], R, active,
                                         pc, e0, e1));
             }
+            if (prof) LT_TRY(prof_end(h, LT_PROF_POST_FINE));
+        } else if (fused3d) {
+            G6 gh = {{(double)g(0), (double)g(1), (double)g(2), (double)g(3), (double)g(4), (double)g(5)}};
+            unsigned long long* pc = nullptr;
+            const bool prof = l == 0 && h->prof_target == LT_PROF_POST_FINE;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (prof) LT_TRY(prof_begin(h, LT_PROF_POST_FINE, &pc, &e0, &e1));
+            LT_TRY(launch_post3d<T>(st, v, tr, ti, nu2, tile3_of(l), bs[l], xpre[l], xpost[l + 1], C.n[0], C.n[1],
+                                    C.n[2], C.coarsened_from_fine[0], C.coarsened_from_fine[1],
+                                    C.coarsened_from_fine[2], gh, xpost[l], R, active, pc, e0, e1));
             if (prof) LT_TRY(prof_end(h, LT_PROF_POST_FINE));
         } else {
             dim3 grid(nblk(L.N), R);

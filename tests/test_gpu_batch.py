@@ -54,6 +54,9 @@ def test_batch_matches_oracle(lt):
     opts = [lt.make_opts(tol=1e-10, precision=lt.LT_PREC_FP64, n_tau=p.n_tau, maxit=80) for p in ps]
     announce("batch vs oracle")
     outs, stats, rc = lt.lt_solve_batch([_item(p, h, o) for p, h, o in zip(ps, hs, opts)])
+    for p, st in zip(ps, stats):
+        print(p.name, p.n, "rc", st["rc"], "iters", st["iters_max"], "resolves", st["resolves"], "true",
+              st["true_relres_max"], flush=True)
     assert rc == 0
     for p, got, st in zip(ps, outs, stats):
         ref = heads(p.n, p.h, p.kappa, p.S, p.sources, p.receivers, p.times, p.nz_contour, q=p.q, workers=8)
