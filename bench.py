@@ -1,22 +1,29 @@
 """Throughput of the Laplace-transform shifted-system solver on one MI355X.
 
-One step = one lt_solve of the 256x256 workload: ln(kappa) a Gaussian
-random field (exponential covariance, variance 1, correlation length 0.1),
-S = 1e-5, zero-Dirichlet walls, 8 pumping wells and 16 observation wells on
-a 4x4 pattern, 10 log-spaced times in [0.01, 10] diffusion times, a 20-node
-Talbot contour (10 solved shifts per time, 100 per right-hand side), one
-preconditioner shift; heads at every receiver and time, with the FP64 true
-residual of all 800 (rhs, shift) systems.  Inputs are resident on the GPU
-before the timed region.  Metric: shifted solves per second (rhs x shift
-pairs / wall time), counted only when the heads agree with the CPU oracle
-to 1e-5 relative.
+Default workload (--workload C5J): six Jacobian-assembly problems on uneven
+grids (128^2, 256^2, 512^2 in 2D; 32^3, 64^3, 128x128x64 in 3D; ln kappa
+Gaussian random fields, 2D as the 256x256 workload, 3D anisotropic with
+log-uniform storage), each with 16 pumping wells and 32 observation wells,
+times {0.3, 1.2} diffusion times and a 24-node Talbot contour.  One step is
+one lt_adjoint_batch call: for every problem the forward fields of the 16
+wells and the adjoint fields of the 32 receivers (48 right-hand sides x 24
+shifts = 1,152 shifted solves, 6,912 over the batch), contracted cell by
+cell into d phi / d ln kappa and d phi / d ln S for every (well, receiver,
+time) triple.  Inputs are resident on the GPU before the timed region.
+Metric: shifted solves per second, counted only when the sensitivities of
+the 128x128 problem agree with the CPU oracle's Jacobian to 1e-5 of each
+map's largest entry.
 
-Three variants are timed: FP64 throughout ("fp64", the plain method), the
-FP32 V-cycle inside the FP64 outer solve ("mixed"), and "learned": mixed
-precision with the U-Net preconditioner giving each preconditioner solve its
-first guess (trained on the GPU just before, on 128x128 fields; training
+Variants: FP64 throughout ("fp64", the plain method), the FP32 V-cycle
+inside the FP64 outer solve ("mixed"), and "learned": mixed precision with
+the U-Net preconditioner giving each preconditioner solve of the 2D problems
+its first guess (trained on the GPU just before, on 128x128 fields; training
 time reported separately), switched off by the solver once its guesses stop
-paying for themselves.  The headline value is the learned variant.
+paying for themselves, the V-cycle the fallback (3D problems: V-cycle only).
+The headline value is the learned variant.
+
+--workload C2 times the 256x256 heads workload (lt_solve), C3 the 64x64x32
+sensitivities (lt_adjoint), C5 the six grids' heads (lt_solve_batch).
 """
 from __future__ import annotations
 
@@ -37,16 +44,16 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_post2d_refine_traffic.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1409_2556_amd", "csrc", "mg_fused.hip")
 
 
-def _measured_traffic():
+def _measured_traffic(traffic_file=TRAFFIC_FILE, kernel_src=KERNEL_SRC):
     """HBM bytes per launch of the profiled kernel from the committed counter
     summary, or None once the kernel source differs from the profiled one."""
     import hashlib
     import re
     try:
-        txt = open(TRAFFIC_FILE).read()
+        txt = open(traffic_file).read()
         want = re.search(r"sha256\[:16\] = ([0-9a-f]{16})", txt).group(1)
         val = float(re.search(r"traffic_bytes_per_launch: ([0-9.]+)", txt).group(1))
-        have = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+        have = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
     except (OSError, AttributeError):
         return None
     return val if have == want else None
@@ -74,9 +81,16 @@ def _parse():
     ap.add_argument("--no-tune", action="store_true", help="keep the default smoother tile shapes")
     ap.add_argument("--groups", type=int, default=2,
                     help="solve the sources as this many concurrent groups, one handle and stream each")
-    ap.add_argument("--workload", choices=["C2", "C3", "C5"], default="C2",
-                    help="C2: the 256x256 workload (default); C3: sensitivities (lt_adjoint) of the "
-                         "64x64x32 workload; C5: the batch of six uneven 2D/3D grids in one lt_solve_batch call")
+    ap.add_argument("--workload", choices=["C5J", "C2", "C3", "C5"], default="C5J",
+                    help="C5J (default): the six Jacobian-assembly problems in one lt_adjoint_batch call; "
+                         "C2: the 256x256 heads workload; C3: sensitivities (lt_adjoint) of the "
+                         "64x64x32 workload; C5: the six grids' heads in one lt_solve_batch call")
+    ap.add_argument("--tol-jacobian", type=float, default=3e-10,
+                    help="C5J: weighted tolerance of every variant (equal accuracy)")
+    ap.add_argument("--relax-jacobian", type=float, default=0.3,
+                    help="C5J: inner tolerance factor of every variant")
+    ap.add_argument("--maxit", type=int, default=48,
+                    help="C5J: outer iterations the basis workspace is sized for")
     ap.add_argument("--water-table", type=float, default=None, metavar="SY",
                     help="C2/C3: make the top wall (+y in 2D, +z in 3D) a linearised water table with this "
                          "specific yield (the other walls keep zero head)")
@@ -200,6 +214,8 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "C5J":
+        return main_jacobian(args)
     if args.workload == "C5":
         return main_batch(args)
     if args.workload == "C3":
@@ -447,6 +463,206 @@ def main_adjoint(args):
     }
     print(json.dumps(out), flush=True)
     h.close()
+
+
+C5J_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c5j_post3d_traffic.md")
+C5J_KERNEL_SRC = os.path.join(ROOT, "paper_1409_2556_amd", "csrc", "mg3d.hip")
+
+
+def _map_err(got, ref, scale=None):
+    """Element-wise error of sensitivity maps [..., N]: max over maps of max_c |got - ref| / scale,
+    scale = each map's largest |ref| (or the given one, broadcast over the maps)."""
+    import torch
+    d = (got - ref).abs().amax(dim=-1)
+    n = ref.abs().amax(dim=-1) if scale is None else scale
+    return float((d / n).max())
+
+
+def _cpu_jacobian(p):
+    """The oracle as it stands on a bounded sample: the full Jacobian (both maps, every well,
+    receiver, time and cell) of the batch's 128x128 problem by SuperLU per shift."""
+    from oracle.jacobian import jacobian
+    workers = min(os.cpu_count() or 1, 16)
+    t0 = time.perf_counter()
+    JK, JS = jacobian(p.n, p.h, p.kappa, p.S, p.sources, p.receivers, p.times, p.nz_contour, q=p.q, bc=p.bc,
+                      workers=workers, ndim=p.ndim)
+    dt = time.perf_counter() - t0
+    nrhs = len(p.sources) + len(p.receivers)
+    npair = nrhs * len(p.times) * (p.nz_contour // 2)
+    return (JK, JS), {"value": npair / dt, "unit": "shifted solves/s", "cores": workers, "kind": "oracle",
+                      "sample": f"the 128x128 problem of the batch: {len(p.sources)} wells + {len(p.receivers)} "
+                                f"receivers x {len(p.times)} times x {p.nz_contour // 2} shifts = {npair} pairs, "
+                                f"SuperLU per shift, contracted to both sensitivity maps of all cells "
+                                f"({dt:.1f} s)"}
+
+
+def main_jacobian(args):
+    """The six Jacobian-assembly problems (128^2, 256^2, 512^2, 32^3, 64^3, 128x128x64; 16 wells +
+    32 receivers, 2 times, 24-node contour each) in one lt_adjoint_batch call per step."""
+    import workloads as wl
+    ps = wl.make_batch()
+    nrhs = [len(p.sources) + len(p.receivers) for p in ps]
+    pairs = sum(n * len(p.times) * (p.nz_contour // 2) for n, p in zip(nrhs, ps))
+    small = ps[0]
+    cpu, ref = None, None
+    if not args.no_cpu_baseline:
+        ref, cpu = _cpu_jacobian(small)
+        print(f"[bench] oracle sample: {cpu['value']:.2f} solves/s, {cpu['sample']}", file=sys.stderr, flush=True)
+    import torch
+    from paper_1409_2556_amd import binding as lt
+    torch.cuda.set_device(0)
+    hs, tiles = [], {}
+    for p, n in zip(ps, nrhs):
+        h, t = _handle(lt, p, not args.no_tune, n)
+        hs.append(h)
+        tiles[p.name] = t
+    outs = [(torch.empty((len(p.sources), len(p.receivers), len(p.times), p.N), dtype=torch.float64, device="cuda"),
+             torch.empty((len(p.sources), len(p.receivers), len(p.times), p.N), dtype=torch.float64, device="cuda"))
+            for p in ps]
+    # the same cells of every problem are compared between variants (the maps' scales come from
+    # all cells of the FP64 run)
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    samp = [torch.randperm(p.N, generator=gen)[:min(p.N, 8192)].cuda() for p in ps]
+    net_2d = [p.ndim == 2 and p.n[0] % 128 == 0 and p.n[1] % 8 == 0 for p in ps]
+    training, nets = None, []
+    tol = args.tol_jacobian
+    variants = [("fp64", lt.LT_PREC_FP64), ("mixed", lt.LT_PREC_MIXED), ("learned", lt.LT_PREC_MIXED)]
+    if args.variant != "all":
+        variants = [v for v in variants if v[0] in (args.variant, "fp64")]
+    if any(v[0] == "learned" for v in variants):
+        from paper_1409_2556_amd.train_unet import train
+        t0 = time.perf_counter()
+        net, hist = train(steps=args.train_steps, batch=8, lr=1e-3, verbose=False)
+        torch.cuda.synchronize()
+        training = {"steps": args.train_steps, "seconds": time.perf_counter() - t0,
+                    "final_loss_mean20": float(np.mean(hist[-20:])),
+                    "data": "128x128 GRF fields (seeds 10000-10007), point-source and smooth residuals, "
+                            "targets from lt_precond_solve"}
+        print(f"[bench] trained U-Net: {training['seconds']:.1f} s, loss {training['final_loss_mean20']:.3f}",
+              file=sys.stderr, flush=True)
+        first = True
+        for h, ok in zip(hs, net_2d):
+            if ok:
+                # one copy per handle: a network's workspace serves one solve at a time
+                if first:
+                    ng, first = net, False
+                else:
+                    ng = lt.UNet(seed=0)
+                    ng.set_params(net.get_params())
+                nets.append(ng)
+                lt.lt_unet_attach(h, ng)
+    res, fp64_samp = {}, None
+    for name, prec in variants:
+        opts = [lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau, maxit=args.maxit, relax=args.relax_jacobian,
+                             precond=lt.LT_PRECOND_UNET_GMG if (name == "learned" and ok) else lt.LT_PRECOND_GMG)
+                for p, ok in zip(ps, net_2d)]
+        items = [dict(handle=h, sources=p.sources, q=p.q, receivers=p.receivers, times=p.times, nz=p.nz_contour,
+                      opts=o, dlnK=dK, dlnS=dS) for p, h, o, (dK, dS) in zip(ps, hs, opts, outs)]
+        sts, rc = None, None
+        for _ in range(args.warmup):
+            _, sts, rc = lt.lt_adjoint_batch(items)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, sts, rc = lt.lt_adjoint_batch(items)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        r = {"dt": dt, "tol": tol, "rc": rc, "sts": sts}
+        if ref is not None:
+            dK, dS = outs[0]
+            rK = torch.from_numpy(ref[0]).cuda()
+            rS = torch.from_numpy(ref[1]).cuda()
+            r["oracle_128"] = {"dlnK": _map_err(dK, rK),
+                               "dlnS_vs_scale_over_times": _map_err(dS, rS, rS.abs().amax(dim=(-2, -1))[..., None]),
+                               "dlnS_per_map": _map_err(dS, rS)}
+            del rK, rS
+        cur = [(dK[..., i], dS[..., i]) for (dK, dS), i in zip(outs, samp)]
+        if name == "fp64":
+            scales = [(dK.abs().amax(dim=-1), dS.abs().amax(dim=(-2, -1))[..., None]) for dK, dS in outs]
+            fp64_samp = [(a.clone(), b.clone(), sc) for (a, b), sc in zip(cur, scales)]
+        else:
+            r["vs_fp64_sampled"] = {
+                p.name: {"dlnK": _map_err(a, fa, sk), "dlnS_vs_scale_over_times": _map_err(b, fb, ss)}
+                for p, (a, b), (fa, fb, (sk, ss)) in zip(ps, cur, fp64_samp)}
+        res[name] = r
+        print(f"[bench] C5J {name}: {dt * 1e3:.1f} ms/step, {pairs / dt:.0f} solves/s, rc {rc}, oracle_128 "
+              f"{r.get('oracle_128')}, vs fp64 {r.get('vs_fp64_sampled')}", file=sys.stderr, flush=True)
+        for p, st in zip(ps, sts):
+            print(f"[bench]   {p.name}: iters {st['iters_max']} vcycles {st['vcycles']} resolves "
+                  f"{st['resolves']} true {st['true_relres_max']:.2e} net {st['net_applied']} "
+                  f"({st['seconds'] * 1e3:.1f} ms)", file=sys.stderr, flush=True)
+    # the dominant solver kernel, timed live: the 3D fine-level post-smoother of the largest
+    # problem, every launch bracketed by HIP events on its handle's stream, in a pass of its own
+    # (the same call with the same right-hand sides, outside the timed steps)
+    roofline = None
+    pname = "learned" if "learned" in res else "mixed"
+    if pname in res:
+        big = max(range(len(ps)), key=lambda i: ps[i].N)
+        p, h = ps[big], hs[big]
+        o = lt.make_opts(tol=tol, precision=lt.LT_PREC_MIXED, n_tau=p.n_tau, maxit=args.maxit,
+                         relax=args.relax_jacobian, profile=lt.LT_PROF_POST_FINE)
+        dK, dS = outs[big]
+        _, _, stp = lt.lt_adjoint(h, p.sources, p.q, p.receivers, p.times, p.nz_contour, o, dlnK=dK, dlnS=dS)
+        torch.cuda.synchronize()
+        if stp["prof_launches"] > 0 and stp["prof_ms"] > 0:
+            avg_s = stp["prof_ms"] * 1e-3 / stp["prof_launches"]
+            bpl = stp["prof_bytes"] / stp["prof_launches"]
+            ach = bpl / avg_s / 1e9
+            roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": ach / HBM_PEAK_GBS, "traffic": _measured_traffic(C5J_TRAFFIC_FILE, C5J_KERNEL_SRC),
+                        "kernel": "k_smooth3d<float,2,32,8,post> (fine level of the 128x128x64 problem: "
+                                  "prolongation + 2 red-black sweeps, z-marching tiles)",
+                        "avg_launch_us": avg_s * 1e6, "bytes_per_launch": bpl, "launches": stp["prof_launches"]}
+    if args.pmc_calibrate:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] copy calibration: 536870912 bytes read and written", file=sys.stderr, flush=True)
+    hname = "learned" if "learned" in res else ("mixed" if "mixed" in res else "fp64")
+    head = res[hname]
+    o128 = head.get("oracle_128")
+    valid = head["rc"] == 0 and (o128 is None or (o128["dlnK"] <= 1e-5 and o128["dlnS_vs_scale_over_times"] <= 1e-5))
+    out = {
+        "metric": "shifted solves/sec (RHS\u00d7shift, rel head err 1e-5): learned+mixed vs plain FGMRES",
+        "value": pairs / head["dt"] if valid else 0.0,
+        "unit": "shifted solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["dt"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": "six Jacobian-assembly problems on uneven grids (128^2, 256^2, 512^2 2D; 32^3, "
+                               "64^3, 128x128x64 3D), 16 wells + 32 receivers each, times {0.3, 1.2}, "
+                               "24-node Talbot, sensitivities d phi / d ln kappa and d ln S of every cell, "
+                               "one lt_adjoint_batch call",
+                   "pairs": pairs, "rhs_per_problem": nrhs, "variant": hname, "tol": tol, "maxit": args.maxit,
+                   "relax": args.relax_jacobian,
+                   "accuracy": "sensitivity maps of the 128x128 problem vs the oracle, element-wise, relative "
+                               "to each map's largest entry (storage: to the largest over both times)",
+                   "smoother_tiles": tiles},
+        "variants": {n: {"solves_per_s": pairs / r["dt"], "ms_per_step": r["dt"] * 1e3, "tol": r["tol"], "rc": r["rc"],
+                         "vs_oracle_128": r.get("oracle_128"), "vs_fp64_sampled": r.get("vs_fp64_sampled"),
+                         "per_problem": {p.name: {"iters": s["iters_max"], "vcycles": s["vcycles"],
+                                                  "resolves": s["resolves"],
+                                                  "true_relres_weighted_max": s["true_relres_max"],
+                                                  "net_applied": s["net_applied"],
+                                                  "net_disabled_after_iteration": s["net_disabled_at"],
+                                                  "solve_ms": s["seconds"] * 1e3}
+                                         for p, s in zip(ps, r["sts"])}}
+                     for n, r in res.items()},
+        "training": training,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if "fp64" in res:
+        out["vs_plain_fp64"] = res["fp64"]["dt"] / head["dt"]
+    if "mixed" in res and hname == "learned":
+        out["learned_vs_mixed"] = res["mixed"]["dt"] / head["dt"]
+    print(json.dumps(out), flush=True)
+    for h in hs:
+        lt.lt_unet_attach(h, None)
+    for ng in nets:
+        ng.close()
+    for h in hs:
+        h.close()
 
 
 def main_batch(args):

@@ -616,8 +616,11 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
     if (!cb) lc = nl - 1;  // generic path down to the coarsest level
     const bool fused2d = h->grid.ndim == 2 && nu1 >= 1 && nu1 <= 3 && nu2 >= 1 && nu2 <= 3;
     // 3D levels: z-marching tiles (mg3d.hip) for FP32 cycles of up to two sweeps, whose
-    // per-thread plane ring fits the register file
-    const bool fused3d = h->grid.ndim == 3 && sizeof(T) == 4 && nu1 >= 1 && nu1 <= 2 && nu2 >= 1 && nu2 <= 2;
+    // per-thread plane ring fits the register file, on hierarchies that halve x and y
+    // at every level above the single-workgroup ones
+    bool fused3d = h->grid.ndim == 3 && sizeof(T) == 4 && nu1 >= 1 && nu1 <= 2 && nu2 >= 1 && nu2 <= 2;
+    for (int l = 1; l <= lc && l < nl && fused3d; ++l)
+        fused3d = h->levels[l].coarsened_from_fine[0] && h->levels[l].coarsened_from_fine[1];
     const bool fusedT = fused2d || fused3d;
     auto tile3_of = [&](int l) { return h->levels[l].n[0] >= 32 ? 0 : 1; };
     const int* tiles = h->tiles[sizeof(T) == 4 ? 1 : 0];
