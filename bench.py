@@ -89,6 +89,8 @@ def _parse():
                     help="C5J: weighted tolerance of every variant (equal accuracy)")
     ap.add_argument("--relax-jacobian", type=float, default=0.3,
                     help="C5J: inner tolerance factor of every variant")
+    ap.add_argument("--nu3d", type=int, default=2,
+                    help="C5J: red-black sweeps before and after the coarse correction on the 3D problems")
     ap.add_argument("--maxit", type=int, default=48,
                     help="C5J: outer iterations the basis workspace is sized for")
     ap.add_argument("--water-table", type=float, default=None, metavar="SY",
@@ -554,7 +556,8 @@ def main_jacobian(args):
     res, fp64_samp = {}, None
     for name, prec in variants:
         opts = [lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau, maxit=args.maxit, relax=args.relax_jacobian,
-                             precond=lt.LT_PRECOND_UNET_GMG if (name == "learned" and ok) else lt.LT_PRECOND_GMG)
+                             precond=lt.LT_PRECOND_UNET_GMG if (name == "learned" and ok) else lt.LT_PRECOND_GMG,
+                             **({"nu1": args.nu3d, "nu2": args.nu3d} if p.ndim == 3 else {}))
                 for p, ok in zip(ps, net_2d)]
         items = [dict(handle=h, sources=p.sources, q=p.q, receivers=p.receivers, times=p.times, nz=p.nz_contour,
                       opts=o, dlnK=dK, dlnS=dS) for p, h, o, (dK, dS) in zip(ps, hs, opts, outs)]
@@ -600,7 +603,8 @@ def main_jacobian(args):
         big = max(range(len(ps)), key=lambda i: ps[i].N)
         p, h = ps[big], hs[big]
         o = lt.make_opts(tol=tol, precision=lt.LT_PREC_MIXED, n_tau=p.n_tau, maxit=args.maxit,
-                         relax=args.relax_jacobian, profile=lt.LT_PROF_POST_FINE)
+                         relax=args.relax_jacobian, profile=lt.LT_PROF_POST_FINE,
+                         **({"nu1": args.nu3d, "nu2": args.nu3d} if p.ndim == 3 else {}))
         dK, dS = outs[big]
         _, _, stp = lt.lt_adjoint(h, p.sources, p.q, p.receivers, p.times, p.nz_contour, o, dlnK=dK, dlnS=dS)
         torch.cuda.synchronize()
