@@ -340,6 +340,24 @@ int lt_apply_operator(lt_handle* h, int level, double tau_re, double tau_im,
 int lt_vcycle(lt_handle* h, double tau_re, double tau_im, int precision, int nu1, int nu2,
               const double* b, double* x, int nvec);
 
+/* lt_vcycle that allocates nothing, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, layout and result as lt_vcycle; every
+ * work vector of the cycle (level right-hand sides and iterates, the FP32
+ * copies of b and x) and the dense inverse of the coarsest level (built on the
+ * GPU for this shift) live in the library's static scratch array of 64 MiB per
+ * device, whose address lt_setup takes once per device.  The call calls no
+ * device allocator.  LT_EINVAL, before any work, when the cycle needs more than
+ * 64 MiB (about 2D 256 x 256 with 8 right-hand sides in FP64; lt_last_error
+ * names the size).  Every call on a GPU shares that GPU's scratch, so calls
+ * that overlap on one GPU (other streams or host threads) race; the scratch
+ * keeps the last call's contents, and nothing in it needs to start at zero.
+ * The FP64 result agrees with lt_vcycle's to rounding (the coarse inverse is
+ * formed on the GPU instead of the host); a singular coarse operator gives
+ * NaN.  Works on handles from lt_setup only. */
+int lt_vcycle_noalloc(lt_handle* h, double tau_re, double tau_im, int precision, int nu1, int nu2,
+                      const double* b, double* x, int nvec);
+
 /* ---- learned preconditioner -------------------------------------------
  * A 2D convolutional U-Net (4 levels, 16/32/64/64 channels, 3x3 kernels,
  * BF16 weights and activations, FP32 accumulation on the matrix cores) that

@@ -109,6 +109,8 @@ _lib.lt_apply_operator.argtypes = [_h, C.c_int, C.c_double, C.c_double, _vp, _vp
 _lib.lt_apply_operator.restype = C.c_int
 _lib.lt_vcycle.argtypes = [_h, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int]
 _lib.lt_vcycle.restype = C.c_int
+_lib.lt_vcycle_noalloc.argtypes = [_h, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int]
+_lib.lt_vcycle_noalloc.restype = C.c_int
 _lib.lt_krylov_basis.argtypes = [_h, C.c_int, C.c_int, _dp, _dp, _dp, C.POINTER(C.c_int)]
 _lib.lt_krylov_basis.restype = C.c_int
 _lib.lt_level_shape.argtypes = [_h, C.c_int, C.POINTER(C.c_int)]
@@ -420,6 +422,13 @@ def lt_vcycle(handle: Handle, tau, precision, nu1, nu2, b, x, nvec):
     tau = complex(tau)
     return _check(_lib.lt_vcycle(handle.ptr, tau.real, tau.imag, int(precision), int(nu1), int(nu2),
                                  _dev_f64(b, "b"), _dev_f64(x, "x"), int(nvec)))
+
+
+def lt_vcycle_noalloc(handle: Handle, tau, precision, nu1, nu2, b, x, nvec):
+    """lt_vcycle with every work vector in the library's scratch (allocates nothing)."""
+    tau = complex(tau)
+    return _check(_lib.lt_vcycle_noalloc(handle.ptr, tau.real, tau.imag, int(precision), int(nu1), int(nu2),
+                                         _dev_f64(b, "b"), _dev_f64(x, "x"), int(nvec)))
 
 
 def lt_krylov_basis(handle: Handle, rhs):

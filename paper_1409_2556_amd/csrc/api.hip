@@ -73,6 +73,7 @@ lt_handle::~lt_handle() {
     graphs.clear();
     for (auto& kv : ws) kv.second.release();
     kappa.release();
+    mstor.release();
     if (pinned) (void)hipHostFree(pinned);
     for (hipEvent_t e : prof_events) (void)hipEventDestroy(e);
 }
@@ -727,6 +728,25 @@ void scale_by_rates(const lt_sources* src, PointsCSR* c) {
 
 }  // namespace
 
+namespace lt {
+
+// One V-cycle on the handle's stream; FP32 cycles convert on entry and exit.  With
+// h->arena_plan set, only the workspace bytes are counted and nothing is launched.
+int vcycle_call(lt_handle* h, cdouble tau, int precision, int nu1, int nu2, const double* b, double* x, int nvec) {
+    const size_t per = 2 * (size_t)h->N * nvec;
+    int rc = 0;
+    if (precision == LT_PREC_FP64) return mg_vcycle<double>(h, tau, nu1, nu2, nvec, nullptr, x, b);
+    float* bf = wsp<float>(h, "vc_b32", per, &rc);
+    float* xf = wsp<float>(h, "vc_x32", per, &rc);
+    if (!bf || !xf) return rc;
+    if (!h->arena_plan) LT_TRY(convert_vectors<double, float>(h->stream, b, bf, per));
+    LT_TRY(mg_vcycle<float>(h, tau, nu1, nu2, nvec, nullptr, xf, bf));
+    if (h->arena_plan) return 0;
+    return convert_vectors<float, double>(h->stream, xf, x, per);
+}
+
+}  // namespace lt
+
 extern "C" {
 
 void lt_opts_default(lt_opts* o) {
@@ -821,7 +841,9 @@ int lt_setup(const lt_grid* grid, const double* kappa, const double* S, const lt
         return LT_EHIP;
     }
     h->N = (int)Nll;
-    int rc = mg_build(h, kappa, S);
+    // the scratch of allocation-free calls: its address on this device, taken once per device
+    int rc = noalloc_init_device(h->device);
+    if (rc >= 0) rc = mg_build(h, kappa, S);
     if (rc >= 0) rc = h->kappa.reserve(sizeof(double) * (size_t)h->N);
     if (rc >= 0 && hipMemcpyAsync(h->kappa.p, kappa, sizeof(double) * (size_t)h->N, hipMemcpyDeviceToDevice,
                                   h->stream) != hipSuccess) {
@@ -918,21 +940,10 @@ int lt_apply_operator(lt_handle* h, int level, double tau_re, double tau_im, con
 
 int lt_vcycle(lt_handle* h, double tau_re, double tau_im, int precision, int nu1, int nu2, const double* b,
               double* x, int nvec) {
-    if (!h || !b || !x || nvec < 1 || nu1 < 0 || nu2 < 0 || nu1 + nu2 < 1) return LT_EINVAL;
-    const size_t per = 2 * (size_t)h->N * nvec;
-    cdouble tau(tau_re, tau_im);
-    int rc = 0;
-    if (precision == LT_PREC_FP64) {
-        return mg_vcycle<double>(h, tau, nu1, nu2, nvec, nullptr, x, b);
-    } else if (precision == LT_PREC_MIXED) {
-        float* bf = wsp<float>(h, "vc_b32", per, &rc);
-        float* xf = wsp<float>(h, "vc_x32", per, &rc);
-        if (!bf || !xf) return rc;
-        LT_TRY(convert_vectors<double, float>(h->stream, b, bf, per));
-        LT_TRY(mg_vcycle<float>(h, tau, nu1, nu2, nvec, nullptr, xf, bf));
-        return convert_vectors<float, double>(h->stream, xf, x, per);
-    }
-    return LT_EINVAL;
+    if (!h || !b || !x || nvec < 1 || nvec > kMaxRhs || nu1 < 0 || nu2 < 0 || nu1 + nu2 < 1 ||
+        (precision != LT_PREC_FP64 && precision != LT_PREC_MIXED))
+        return LT_EINVAL;
+    return vcycle_call(h, cdouble(tau_re, tau_im), precision, nu1, nu2, b, x, nvec);
 }
 
 int lt_solve(lt_handle* h, const lt_sources* src, const double* times, int ntimes, const lt_contour* contour,

@@ -105,6 +105,13 @@ struct lt_handle {
     std::map<std::vector<unsigned long long>, std::pair<hipGraphExec_t, int>> graphs;
     unsigned long long graphs_gen = 0;  // ws_gen the cached graphs were captured at
     void* pinned = nullptr;  // small pinned host area for flags
+    // allocation-free calls (lt_vcycle_noalloc): workspaces are carved from caller-side
+    // device memory instead of the handle's own; with arena_plan set, carving only counts
+    // the bytes a call would use and nothing is launched
+    char* arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
+    bool arena_plan = false;
+    lt::CoarseInverse arena_ci;       // coarse inverse built in the arena (not owned)
     int last_R = 0, last_jmax = 0;  // shape of the basis the last solve left in the workspaces
     // profiling of one kernel family (opts.profile): event pairs and a byte counter
     int prof_target = 0;
@@ -122,6 +129,18 @@ int prof_end(lt_handle* h, int family);
 
 // workspace helper
 template <typename T> T* wsp(lt_handle* h, const char* name, size_t count, int* rc) {
+    if (h->arena || h->arena_plan) {
+        // bump allocation from the arena, 256-byte aligned
+        const size_t off = (h->arena_used + 255) & ~size_t(255);
+        h->arena_used = off + count * sizeof(T);
+        if (h->arena_plan) return reinterpret_cast<T*>(uintptr_t(256));  // a size count only
+        if (h->arena_used > h->arena_cap) {
+            *rc = LT_EINVAL;
+            set_last_error(std::string("scratch too small for ") + name);
+            return nullptr;
+        }
+        return reinterpret_cast<T*>(h->arena + off);
+    }
     DevBuf& b = h->ws[name];
     void* before = b.p;
     int r = b.reserve(count * sizeof(T));
@@ -153,6 +172,13 @@ int points_csr(const lt_grid& g, const lt_points* pts, PointsCSR* out);
 
 // dense complex inverse (Gauss-Jordan with partial pivoting); returns 0 or LT_EINVAL if singular
 int dense_inverse(int n, std::vector<cdouble>& a, std::vector<cdouble>& inv);
+
+// one V-cycle of lt_vcycle (shared by the allocation-free variant)
+int vcycle_call(lt_handle* h, cdouble tau, int precision, int nu1, int nu2, const double* b, double* x, int nvec);
+// allocation-free calls: device address of the library's scratch array on the current
+// device, taken once per device at setup (noalloc.hip)
+int noalloc_init_device(int device);
+void* noalloc_scratch(int device, size_t* bytes);
 
 // ------------------------------------------------------------- multigrid
 int mg_build(lt_handle* h, const double* kappa, const double* S);

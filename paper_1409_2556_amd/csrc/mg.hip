@@ -528,8 +528,121 @@ int mg_build(lt_handle* h, const double* kappa, const double* S) {
     return 0;
 }
 
+// Dense inverse of the coarsest level's K + tau M by Gauss-Jordan elimination with
+// partial pivoting, in one workgroup on a working matrix [A | I] (n x 2n complex) in
+// global memory; writes the inverse row-major as interleaved complex FP64 and FP32.
+// The allocation-free path builds the coarse solve this way in its scratch; a singular
+// pivot leaves NaN in the inverse.
+__global__ __launch_bounds__(1024) void k_coarse_gj(LevelView<double> L, double tr, double ti, int n,
+                                                    cpx<double>* __restrict__ Mw, double* __restrict__ inv64,
+                                                    float* __restrict__ inv32) {
+    __shared__ cpx<double> fac[kMaxCoarseDense];
+    __shared__ double pv[1024];
+    __shared__ int pix[1024];
+    const int tid = threadIdx.x, nt = blockDim.x, w = 2 * n;
+    const int sy = L.nx, sz = L.nx * L.ny;
+    for (int e = tid; e < n * w; e += nt) {
+        const int i = e / w, j = e % w;
+        cpx<double> v = {0.0, 0.0};
+        if (j < n) {
+            const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / sz;
+            if (j == i) v = {L.D[i] + tr * L.m[i], ti * L.m[i]};
+            else if (x + 1 < L.nx && j == i + 1) v.re = -L.Tx[i];
+            else if (x > 0 && j == i - 1) v.re = -L.Tx[i - 1];
+            else if (y + 1 < L.ny && j == i + sy) v.re = -L.Ty[i];
+            else if (y > 0 && j == i - sy) v.re = -L.Ty[i - sy];
+            else if (z + 1 < L.nz && j == i + sz) v.re = -L.Tz[i];
+            else if (z > 0 && j == i - sz) v.re = -L.Tz[i - sz];
+        } else if (j - n == i) {
+            v.re = 1.0;
+        }
+        Mw[e] = v;
+    }
+    __syncthreads();
+    bool singular = false;
+    for (int c = 0; c < n && !singular; ++c) {
+        double best = -1.0;
+        int bi = c;
+        for (int r = c + tid; r < n; r += nt) {
+            const cpx<double> v = Mw[(size_t)r * w + c];
+            const double a = v.re * v.re + v.im * v.im;
+            if (a > best) { best = a; bi = r; }
+        }
+        pv[tid] = best;
+        pix[tid] = bi;
+        __syncthreads();
+        for (int s = nt / 2; s > 0; s >>= 1) {
+            if (tid < s && (pv[tid + s] > pv[tid] || (pv[tid + s] == pv[tid] && pix[tid + s] < pix[tid]))) {
+                pv[tid] = pv[tid + s];
+                pix[tid] = pix[tid + s];
+            }
+            __syncthreads();
+        }
+        const int pr = pix[0];
+        singular = !(pv[0] > 0.0);
+        if (singular) break;  // uniform: every thread read the same pv[0]
+        if (pr != c)
+            for (int j = tid; j < w; j += nt) {
+                const cpx<double> a = Mw[(size_t)c * w + j];
+                Mw[(size_t)c * w + j] = Mw[(size_t)pr * w + j];
+                Mw[(size_t)pr * w + j] = a;
+            }
+        __syncthreads();
+        const cpx<double> piv = Mw[(size_t)c * w + c];
+        __syncthreads();
+        const double d = piv.re * piv.re + piv.im * piv.im;
+        const cpx<double> ip = {piv.re / d, -piv.im / d};
+        for (int j = tid; j < w; j += nt) Mw[(size_t)c * w + j] = cmul(Mw[(size_t)c * w + j], ip);
+        for (int r = tid; r < n; r += nt) fac[r] = Mw[(size_t)r * w + c];
+        __syncthreads();
+        for (int e = tid; e < n * w; e += nt) {
+            const int r = e / w, j = e % w;
+            if (r == c) continue;
+            const cpx<double> f = fac[r], a = Mw[(size_t)c * w + j];
+            cpx<double>& t = Mw[e];
+            t.re -= f.re * a.re - f.im * a.im;
+            t.im -= f.re * a.im + f.im * a.re;
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < n * n; e += nt) {
+        const int i = e / n, j = e % n;
+        const cpx<double> v = singular ? cpx<double>{NAN, NAN} : Mw[(size_t)i * w + n + j];
+        inv64[2 * (size_t)e] = v.re;
+        inv64[2 * (size_t)e + 1] = v.im;
+        inv32[2 * (size_t)e] = (float)v.re;
+        inv32[2 * (size_t)e + 1] = (float)v.im;
+    }
+}
+
+// The coarse inverse of an allocation-free call, built on the GPU in the arena.
+static const CoarseInverse* arena_coarse_inverse(lt_handle* h, cdouble tau, int* rc) {
+    const Level& L = h->levels.back();
+    const int n = L.N;
+    if (n > kMaxCoarseDense) return nullptr;
+    cpx<double>* Mw = wsp<cpx<double>>(h, "gj_work", 2 * (size_t)n * n, rc);
+    double* i64 = wsp<double>(h, "gj_inv64", 2 * (size_t)n * n, rc);
+    float* i32 = wsp<float>(h, "gj_inv32", 2 * (size_t)n * n, rc);
+    if (!Mw || !i64 || !i32) return nullptr;
+    h->arena_ci.tau = tau;
+    h->arena_ci.inv64.p = i64;
+    h->arena_ci.inv64.bytes = 2 * (size_t)n * n * sizeof(double);
+    h->arena_ci.inv32.p = i32;
+    h->arena_ci.inv32.bytes = 2 * (size_t)n * n * sizeof(float);
+    if (!h->arena_plan) {
+        k_coarse_gj<<<1, 1024, 0, h->stream>>>(L.v64(), tau.real(), tau.imag(), n, Mw, i64, i32);
+        if (hipGetLastError() != hipSuccess) {
+            *rc = LT_EHIP;
+            set_last_error("coarse inverse kernel launch failed");
+            return nullptr;
+        }
+    }
+    return &h->arena_ci;
+}
+
 const CoarseInverse* mg_coarse_inverse(lt_handle* h, cdouble tau, int* rc) {
     *rc = 0;
+    if (h->arena || h->arena_plan) return arena_coarse_inverse(h, tau, rc);
     for (const CoarseInverse& c : h->coarse_cache)
         if (c.tau == tau) return &c;
     const Level& L = h->levels.back();
@@ -606,8 +719,6 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
     const int nl = (int)h->levels.size();
     const T tr = (T)tau.real(), ti = (T)tau.imag();
     int rc = 0;
-    const CoarseInverse* ci = mg_coarse_inverse(h, tau, &rc);
-    if (rc < 0) return rc;
     // first level small enough for the single-workgroup kernel
     int lc = nl;
     for (int l = 0; l < nl; ++l)
@@ -625,27 +736,44 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
     auto tile3_of = [&](int l) { return h->levels[l].n[0] >= 32 ? 0 : 1; };
     const int* tiles = h->tiles[sizeof(T) == 4 ? 1 : 0];
     auto tile_of = [&](int l) { return l < kMaxTunedLevels ? tiles[l] : 0; };
-    const char* tag = sizeof(T) == 8 ? "64_" : "32_";
-    std::vector<T*> xpre(nl + 1, nullptr), xpost(nl + 1, nullptr), bs(nl + 1, nullptr);
+    const int tag = sizeof(T) == 8 ? 64 : 32;
+    // level vectors (fixed arrays and stack names: this path is also the allocation-free one)
+    constexpr int kMaxLv = 48;
+    if (nl >= kMaxLv) {
+        set_last_error("too many multigrid levels");
+        return LT_EUNSUPPORTED;
+    }
+    T* xpre[kMaxLv + 1] = {};
+    T* xpost[kMaxLv + 1] = {};
+    T* bs[kMaxLv + 1] = {};
+    char nm[32];
     bs[0] = const_cast<T*>(b0);
     for (int l = 0; l <= lc && l < nl; ++l) {
         const size_t per = 2 * (size_t)h->levels[l].N * R;
         if (l > 0) {
-            bs[l] = wsp<T>(h, (std::string("mgb") + tag + std::to_string(l)).c_str(), per, &rc);
+            snprintf(nm, sizeof(nm), "mgb%d_%d", tag, l);
+            bs[l] = wsp<T>(h, nm, per, &rc);
             if (!bs[l]) return rc;
         }
         if (l == 0 && (!fusedT || lc == 0)) {
             xpre[0] = x0;
         } else {
-            xpre[l] = wsp<T>(h, (std::string("mgx") + tag + std::to_string(l)).c_str(), per, &rc);
+            snprintf(nm, sizeof(nm), "mgx%d_%d", tag, l);
+            xpre[l] = wsp<T>(h, nm, per, &rc);
             if (!xpre[l]) return rc;
         }
-        xpost[l] = fusedT && l > 0 && l < lc
-                       ? wsp<T>(h, (std::string("mgy") + tag + std::to_string(l)).c_str(), per, &rc)
-                       : xpre[l];
+        if (fusedT && l > 0 && l < lc) {
+            snprintf(nm, sizeof(nm), "mgy%d_%d", tag, l);
+            xpost[l] = wsp<T>(h, nm, per, &rc);
+        } else {
+            xpost[l] = xpre[l];
+        }
         if (!xpost[l]) return rc;
     }
     xpost[0] = x0;
+    const CoarseInverse* ci = mg_coarse_inverse(h, tau, &rc);
+    if (rc < 0) return rc;
+    if (h->arena_plan) return 0;  // sizes counted, nothing launched
     // ghost parity of the correction at a wall: odd at a Dirichlet wall, even at
     // a no-flux one (a water-table wall carries no conductive flux either)
     const T gsign[2] = {T(-1), T(1)};
