@@ -467,8 +467,8 @@ def main_adjoint(args):
     h.close()
 
 
-C5J_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c5j_post3d_traffic.md")
-C5J_KERNEL_SRC = os.path.join(ROOT, "paper_1409_2556_amd", "csrc", "mg3d.hip")
+C5J_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c5j_gs_color_half_traffic.md")
+C5J_KERNEL_SRC = os.path.join(ROOT, "paper_1409_2556_amd", "csrc", "mg.hip")
 
 
 def _map_err(got, ref, scale=None):
@@ -594,16 +594,17 @@ def main_jacobian(args):
             print(f"[bench]   {p.name}: iters {st['iters_max']} vcycles {st['vcycles']} resolves "
                   f"{st['resolves']} true {st['true_relres_max']:.2e} net {st['net_applied']} "
                   f"({st['seconds'] * 1e3:.1f} ms)", file=sys.stderr, flush=True)
-    # the dominant solver kernel, timed live: the 3D fine-level post-smoother of the largest
-    # problem, every launch bracketed by HIP events on its handle's stream, in a pass of its own
-    # (the same call with the same right-hand sides, outside the timed steps)
+    # the dominant solver kernel, timed live: the one-colour Gauss-Seidel half-sweep on the fine
+    # level of the largest (3D) problem, every launch bracketed by HIP events on its handle's
+    # stream, in a pass of its own (the same call with the same right-hand sides, outside the
+    # timed steps)
     roofline = None
     pname = "learned" if "learned" in res else "mixed"
     if pname in res:
         big = max(range(len(ps)), key=lambda i: ps[i].N)
         p, h = ps[big], hs[big]
         o = lt.make_opts(tol=tol, precision=lt.LT_PREC_MIXED, n_tau=p.n_tau, maxit=args.maxit,
-                         relax=args.relax_jacobian, profile=lt.LT_PROF_POST_FINE,
+                         relax=args.relax_jacobian, profile=lt.LT_PROF_SWEEP3D,
                          **({"nu1": args.nu3d, "nu2": args.nu3d} if p.ndim == 3 else {}))
         dK, dS = outs[big]
         _, _, stp = lt.lt_adjoint(h, p.sources, p.q, p.receivers, p.times, p.nz_contour, o, dlnK=dK, dlnS=dS)
@@ -614,8 +615,8 @@ def main_jacobian(args):
             ach = bpl / avg_s / 1e9
             roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": ach / HBM_PEAK_GBS, "traffic": _measured_traffic(C5J_TRAFFIC_FILE, C5J_KERNEL_SRC),
-                        "kernel": "k_smooth3d<float,2,32,8,post> (fine level of the 128x128x64 problem: "
-                                  "prolongation + 2 red-black sweeps, z-marching tiles)",
+                        "kernel": "k_gs_color_half<float> (one red-black colour of a Gauss-Seidel sweep on "
+                                  "the fine level of the 128x128x64 problem, all right-hand sides of a launch)",
                         "avg_launch_us": avg_s * 1e6, "bytes_per_launch": bpl, "launches": stp["prof_launches"]}
     if args.pmc_calibrate:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")

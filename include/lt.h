@@ -51,7 +51,7 @@ enum {
 
 enum { LT_BC_DIRICHLET0 = 0, LT_BC_NEUMANN0 = 1, LT_BC_WATER_TABLE = 2 };
 enum { LT_PREC_FP64 = 0, LT_PREC_MIXED = 1 };   /* V-cycle in FP64 or FP32   */
-enum { LT_PROF_OFF = 0, LT_PROF_PRE_FINE = 1, LT_PROF_POST_FINE = 2 };
+enum { LT_PROF_OFF = 0, LT_PROF_PRE_FINE = 1, LT_PROF_POST_FINE = 2, LT_PROF_SWEEP3D = 3 };
 enum { LT_PRECOND_GMG = 0, LT_PRECOND_UNET_GMG = 1 };
 enum { LT_METHOD_GMRES = 0, LT_METHOD_FOM = 1 };
 enum { LT_CONV_WEIGHTED = 0, LT_CONV_RELATIVE = 1 };
@@ -145,9 +145,11 @@ typedef struct {
  *              the status and the re-solves described at lt_solve.  0: skip
  *              it; the status then rests on the least-squares residuals.
  *   profile    0: off.  LT_PROF_PRE_FINE / LT_PROF_POST_FINE: time every launch
- *              of the fine-grid pre- / post-smoothing kernel with HIP events on
- *              the handle's stream and count its algorithmic bytes (reported
- *              in lt_stats.prof_*).
+ *              of the fine-grid pre- / post-smoothing kernel of a 2D grid with
+ *              HIP events on the handle's stream and count its algorithmic
+ *              bytes (reported in lt_stats.prof_*); LT_PROF_SWEEP3D: the same
+ *              for every one-colour Gauss-Seidel half-sweep on the fine grid
+ *              of a 3D grid.
  *   precond    LT_PRECOND_GMG: V-cycle refinement only.  LT_PRECOND_UNET_GMG:
  *              preconditioner solves start from the attached network's guess
  *              (lt_unet_attach, 2D grids whose nx is a multiple of 128 and ny of

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblt.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["mg.hip", "mg_fused.hip", "mg3d.hip", "krylov.hip", "unet.hip", "api.hip", "plan.cpp", "batch.cpp",
+SOURCES = ["mg.hip", "mg_fused.hip", "krylov.hip", "unet.hip", "api.hip", "plan.cpp", "batch.cpp",
            "tune.hip", "noalloc.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

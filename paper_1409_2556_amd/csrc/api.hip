@@ -109,7 +109,7 @@ int upload_points(lt_handle* h, const PointsCSR& c, const char* tag, DevPoints* 
 int validate_opts(const lt_opts* o) {
     if (!o) return 0;
     if (!(o->tol > 0.0) || o->maxit < 1 || o->maxit > 2000 || o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 ||
-        o->inner_max < 1 || !(o->relax > 0.0) || o->profile < 0 || o->profile > LT_PROF_POST_FINE ||
+        o->inner_max < 1 || !(o->relax > 0.0) || o->profile < 0 || o->profile > LT_PROF_SWEEP3D ||
         (o->precond != LT_PRECOND_GMG && o->precond != LT_PRECOND_UNET_GMG) || !(o->net_keep >= 0.0) ||
         (o->graph != 0 && o->graph != 1) || (o->method != LT_METHOD_GMRES && o->method != LT_METHOD_FOM) ||
         (o->conv != LT_CONV_WEIGHTED && o->conv != LT_CONV_RELATIVE) ||

@@ -14,12 +14,15 @@
 #include "lt_internal.h"
 #include "mg_fused.h"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <cmath>
 
 namespace lt {
 
 static constexpr int kBlock = 256;
+static constexpr int kSweepRhs = 4;  // right-hand sides per thread of a one-colour half-sweep
 static constexpr int kMaxCoarseDense = 512;
 
 int DevBuf::reserve(size_t n) {
@@ -233,12 +236,23 @@ __global__ void k_gs_color(LevelView<T> L, T tr, T ti, int color, T* __restrict_
 }
 
 // The same half-sweep with one thread per cell of the colour (nx even): thread k takes
-// the k-th cell of that colour in storage order, so no lane idles.
-template <typename T>
+// the k-th cell of that colour in storage order, so no lane idles.  A thread serves its
+// cell for RB consecutive right-hand sides: the coefficients are loaded once and reused
+// (they are shared by every right-hand side), and the RB updates are independent.
+template <typename T, int RB>
 __global__ void k_gs_color_half(LevelView<T> L, T tr, T ti, int color, T* __restrict__ x,
-                                const T* __restrict__ b, const int* __restrict__ active) {
-    int r = blockIdx.y;
-    if (active && !active[r]) return;
+                                const T* __restrict__ b, const int* __restrict__ active, int R,
+                                unsigned long long* __restrict__ prof, unsigned long long prof_bytes) {
+    const int r0 = blockIdx.y * RB;
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        const int r = r0 + q;
+        const bool on = r < R && (!active || active[r]);
+        any = any || on;
+        if (on && prof && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(prof, prof_bytes);
+    }
+    if (!any) return;
     const int W = L.nx >> 1;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (L.N >> 1)) return;
@@ -246,64 +260,130 @@ __global__ void k_gs_color_half(LevelView<T> L, T tr, T ti, int color, T* __rest
     const int Y = row % L.ny, Z = row / L.ny;
     const int X = 2 * (k - row * W) + ((Y + Z + color) & 1);
     const int i = X + L.nx * row;
+    const int sy = L.nx, sz = L.nx * L.ny;
+    // neighbours in offsum's order (+x, -x, +y, -y, +z, -z); a missing one has coupling 0
+    // and reads the cell itself
+    const bool hx = X + 1 < L.nx, lx = X > 0, hy = Y + 1 < L.ny, ly = Y > 0, hz = Z + 1 < L.nz, lz = Z > 0;
+    const int nb[6] = {hx ? i + 1 : i, lx ? i - 1 : i, hy ? i + sy : i, ly ? i - sy : i, hz ? i + sz : i,
+                       lz ? i - sz : i};
+    const T tc[6] = {hx ? L.Tx[i] : T(0), lx ? L.Tx[i - 1] : T(0), hy ? L.Ty[i] : T(0),
+                     ly ? L.Ty[i - sy] : T(0), hz ? L.Tz[i] : T(0), lz ? L.Tz[i - sz] : T(0)};
+    const cpx<T> d = {L.D[i] + tr * L.m[i], ti * L.m[i]};
     const size_t N = L.N;
-    T* xr = x + 2 * N * r;
-    T* xi = xr + N;
-    const T* br = b + 2 * N * r;
-    cpx<T> off = offsum(L, xr, xi, i, X, Y, Z);
-    cpx<T> num = {br[i] + off.re, br[i + N] + off.im};
-    cpx<T> d = {L.D[i] + tr * L.m[i], ti * L.m[i]};
-    cpx<T> v = cdiv(num, d);
-    xr[i] = v.re;
-    xi[i] = v.im;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        const int r = r0 + q;
+        if (r >= R || (active && !active[r])) continue;
+        T* xr = x + 2 * N * r;
+        T* xi = xr + N;
+        const T* br = b + 2 * N * r;
+        cpx<T> off = {0, 0};
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            off.re += tc[a] * xr[nb[a]];
+            off.im += tc[a] * xi[nb[a]];
+        }
+        const cpx<T> num = {br[i] + off.re, br[i + N] + off.im};
+        const cpx<T> v = cdiv(num, d);
+        xr[i] = v.re;
+        xi[i] = v.im;
+    }
 }
 
+// prof (fine level, opts.profile = LT_PROF_SWEEP3D): every launch bracketed by HIP events
+// on the stream and its algorithmic bytes counted: per active right-hand side, b of the
+// colour's cells in, x of the other colour in, x of the colour out (complex: 12 bytes of T
+// per cell in FP32 terms, 3 sizeof(T) per cell), plus the coefficients Tx, Ty, Tz of every
+// cell and D, m of the colour's cells, shared by the R right-hand sides (4 sizeof(T) per cell)
 template <typename T>
-static void gs_half_sweep(hipStream_t st, const LevelView<T>& L, T tr, T ti, int color, T* x, const T* b, int R,
-                          const int* active) {
-    if ((L.nx & 1) == 0)
-        k_gs_color_half<T><<<dim3((unsigned)((L.N / 2 + 255) / 256), R), 256, 0, st>>>(L, tr, ti, color, x, b,
-                                                                                      active);
-    else
+static int gs_half_sweep(lt_handle* h, hipStream_t st, const LevelView<T>& L, T tr, T ti, int color, T* x,
+                         const T* b, int R, const int* active, bool fine) {
+    if ((L.nx & 1) == 0) {
+        const dim3 grid((unsigned)((L.N / 2 + 255) / 256), (R + kSweepRhs - 1) / kSweepRhs);
+        if (fine && h->prof_target == LT_PROF_SWEEP3D) {
+            unsigned long long* pc = nullptr;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            LT_TRY(prof_begin(h, LT_PROF_SWEEP3D, &pc, &e0, &e1));
+            const unsigned long long per = (unsigned long long)((double)L.N * 3.0 * sizeof(T) +
+                                                                (double)L.N * 4.0 * sizeof(T) / R);
+            hipExtLaunchKernelGGL((k_gs_color_half<T, kSweepRhs>), grid, dim3(256), 0, st, e0, e1, 0, L, tr, ti,
+                                  color, x, b, active, R, pc, per);
+            LT_TRY(prof_end(h, LT_PROF_SWEEP3D));
+        } else {
+            k_gs_color_half<T, kSweepRhs><<<grid, 256, 0, st>>>(L, tr, ti, color, x, b, active, R, nullptr, 0ull);
+        }
+    } else {
         k_gs_color<T><<<dim3((unsigned)((L.N + 255) / 256), R), 256, 0, st>>>(L, tr, ti, color, x, b, active);
+    }
+    LT_HIP(hipGetLastError());
+    return 0;
 }
 
 // Coarse right-hand side = sum over the aggregate of the fine residual b - A x;
-// the coarse iterate is cleared.
-template <typename T>
+// the coarse iterate is cleared.  A thread serves its coarse cell for RB consecutive
+// right-hand sides (the coefficients of the aggregate are loaded once).
+template <typename T, int RB>
 __global__ void k_resid_restrict(LevelView<T> F, int cnx, int cny, int cnz, int cox, int coy, int coz,
                                  T tr, T ti, const T* __restrict__ xf, const T* __restrict__ bf,
-                                 T* __restrict__ bc, T* __restrict__ xc, const int* __restrict__ active) {
-    int r = blockIdx.y;
-    if (active && !active[r]) return;
+                                 T* __restrict__ bc, T* __restrict__ xc, const int* __restrict__ active, int R) {
+    const int r0 = blockIdx.y * RB;
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) any = any || (r0 + q < R && (!active || active[r0 + q]));
+    if (!any) return;
     const int Nc = cnx * cny * cnz;
     int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= Nc) return;
     int Xc = I % cnx, Yc = (I / cnx) % cny, Zc = I / (cnx * cny);
     const size_t N = F.N;
-    const T* xr = xf + 2 * N * r;
-    const T* xi = xr + N;
-    const T* br = bf + 2 * N * r;
-    const T* bi = br + N;
     int x0 = cox ? 2 * Xc : Xc, x1 = cox ? 2 * Xc + 1 : Xc;
     int y0 = coy ? 2 * Yc : Yc, y1 = coy ? 2 * Yc + 1 : Yc;
     int z0 = coz ? 2 * Zc : Zc, z1 = coz ? 2 * Zc + 1 : Zc;
-    cpx<T> acc = {0, 0};
+    cpx<T> acc[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) acc[q] = {0, 0};
+    const int sy = F.nx, sz = F.nx * F.ny;
     for (int z = z0; z <= z1; ++z)
         for (int y = y0; y <= y1; ++y)
             for (int x = x0; x <= x1; ++x) {
-                int i = x + F.nx * (y + F.ny * z);
-                cpx<T> off = offsum(F, xr, xi, i, x, y, z);
-                cpx<T> d = {F.D[i] + tr * F.m[i], ti * F.m[i]};
-                cpx<T> ax = cmul(d, cpx<T>{xr[i], xi[i]});
-                acc.re += br[i] - (ax.re - off.re);
-                acc.im += bi[i] - (ax.im - off.im);
+                const int i = x + F.nx * (y + F.ny * z);
+                // neighbours in offsum's order; a missing one has coupling 0 and reads the cell
+                const bool hx = x + 1 < F.nx, lx = x > 0, hy = y + 1 < F.ny, ly = y > 0, hz = z + 1 < F.nz,
+                           lz = z > 0;
+                const int nb[6] = {hx ? i + 1 : i, lx ? i - 1 : i, hy ? i + sy : i, ly ? i - sy : i,
+                                   hz ? i + sz : i, lz ? i - sz : i};
+                const T tc[6] = {hx ? F.Tx[i] : T(0), lx ? F.Tx[i - 1] : T(0), hy ? F.Ty[i] : T(0),
+                                 ly ? F.Ty[i - sy] : T(0), hz ? F.Tz[i] : T(0), lz ? F.Tz[i - sz] : T(0)};
+                const cpx<T> d = {F.D[i] + tr * F.m[i], ti * F.m[i]};
+#pragma unroll
+                for (int q = 0; q < RB; ++q) {
+                    const int r = r0 + q;
+                    if (r >= R || (active && !active[r])) continue;
+                    const T* xr = xf + 2 * N * r;
+                    const T* xi = xr + N;
+                    const T* br = bf + 2 * N * r;
+                    const T* bi = br + N;
+                    cpx<T> off = {0, 0};
+#pragma unroll
+                    for (int a = 0; a < 6; ++a) {
+                        off.re += tc[a] * xr[nb[a]];
+                        off.im += tc[a] * xi[nb[a]];
+                    }
+                    const cpx<T> ax = cmul(d, cpx<T>{xr[i], xi[i]});
+                    acc[q].re += br[i] - (ax.re - off.re);
+                    acc[q].im += bi[i] - (ax.im - off.im);
+                }
             }
     const size_t M = Nc;
-    bc[2 * M * r + I] = acc.re;
-    bc[2 * M * r + M + I] = acc.im;
-    xc[2 * M * r + I] = 0;
-    xc[2 * M * r + M + I] = 0;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        const int r = r0 + q;
+        if (r >= R || (active && !active[r])) continue;
+        bc[2 * M * r + I] = acc[q].re;
+        bc[2 * M * r + M + I] = acc[q].im;
+        xc[2 * M * r + I] = 0;
+        xc[2 * M * r + M + I] = 0;
+    }
 }
 
 // Prolongation P e_coarse at fine cell (x, y, z): cell-centred linear interpolation
@@ -379,27 +459,32 @@ __global__ void k_prolong(int fnx, int fny, int fnz, int cnx, int cny, int cnz, 
 
 // The first half-sweep of red-black Gauss-Seidel from x = 0: colour-0 cells see only
 // zero neighbours and take b / d, colour-1 cells stay 0.  Replaces clearing x and the
-// first sweep of colour 0.
-template <typename T>
+// first sweep of colour 0.  RB right-hand sides per thread (D and m loaded once).
+template <typename T, int RB>
 __global__ void k_gs_first(LevelView<T> L, T tr, T ti, T* __restrict__ x, const T* __restrict__ b,
-                           const int* __restrict__ active) {
-    int r = blockIdx.y;
-    if (active && !active[r]) return;
+                           const int* __restrict__ active, int R) {
+    const int r0 = blockIdx.y * RB;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= L.N) return;
     const int X = i % L.nx, Y = (i / L.nx) % L.ny, Z = i / (L.nx * L.ny);
+    const bool c0 = ((X + Y + Z) & 1) == 0;
+    const cpx<T> d = {L.D[i] + tr * L.m[i], ti * L.m[i]};
     const size_t N = L.N;
-    T* xr = x + 2 * N * r;
-    T* xi = xr + N;
-    if (((X + Y + Z) & 1) == 0) {
-        const T* br = b + 2 * N * r;
-        const cpx<T> d = {L.D[i] + tr * L.m[i], ti * L.m[i]};
-        const cpx<T> v = cdiv(cpx<T>{br[i], br[i + N]}, d);
-        xr[i] = v.re;
-        xi[i] = v.im;
-    } else {
-        xr[i] = 0;
-        xi[i] = 0;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        const int r = r0 + q;
+        if (r >= R || (active && !active[r])) continue;
+        T* xr = x + 2 * N * r;
+        T* xi = xr + N;
+        if (c0) {
+            const T* br = b + 2 * N * r;
+            const cpx<T> v = cdiv(cpx<T>{br[i], br[i + N]}, d);
+            xr[i] = v.re;
+            xi[i] = v.im;
+        } else {
+            xr[i] = 0;
+            xi[i] = 0;
+        }
     }
 }
 
@@ -726,14 +811,7 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
     const bool cb = lc < nl && nl - lc <= kMaxCBLevels;
     if (!cb) lc = nl - 1;  // generic path down to the coarsest level
     const bool fused2d = h->grid.ndim == 2 && nu1 >= 1 && nu1 <= 3 && nu2 >= 1 && nu2 <= 3;
-    // 3D levels: z-marching tiles (mg3d.hip) for FP32 cycles of up to two sweeps, whose
-    // per-thread plane ring fits the register file, on hierarchies that halve x and y
-    // at every level above the single-workgroup ones
-    bool fused3d = h->grid.ndim == 3 && sizeof(T) == 4 && nu1 >= 1 && nu1 <= 2 && nu2 >= 1 && nu2 <= 2;
-    for (int l = 1; l <= lc && l < nl && fused3d; ++l)
-        fused3d = h->levels[l].coarsened_from_fine[0] && h->levels[l].coarsened_from_fine[1];
-    const bool fusedT = fused2d || fused3d;
-    auto tile3_of = [&](int l) { return h->levels[l].n[0] >= 32 ? 0 : 1; };
+    const bool fusedT = fused2d;
     const int* tiles = h->tiles[sizeof(T) == 4 ? 1 : 0];
     auto tile_of = [&](int l) { return l < kMaxTunedLevels ? tiles[l] : 0; };
     const int tag = sizeof(T) == 8 ? 64 : 32;
@@ -791,31 +869,23 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
             LT_TRY(launch_pre2d<T>(st, v, tr, ti, nu1, tile_of(l), bs[l], xpre[l], C.n[0], C.n[1], C.coarsened_from_fine[0],
                                    C.coarsened_from_fine[1], bs[l + 1], R, active, pc, e0, e1));
             if (prof) LT_TRY(prof_end(h, LT_PROF_PRE_FINE));
-        } else if (fused3d) {
-            unsigned long long* pc = nullptr;
-            const bool prof = l == 0 && h->prof_target == LT_PROF_PRE_FINE;
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (prof) LT_TRY(prof_begin(h, LT_PROF_PRE_FINE, &pc, &e0, &e1));
-            LT_TRY(launch_pre3d<T>(st, v, tr, ti, nu1, tile3_of(l), bs[l], xpre[l], C.n[0], C.n[1], C.n[2],
-                                   C.coarsened_from_fine[0], C.coarsened_from_fine[1], C.coarsened_from_fine[2],
-                                   bs[l + 1], R, active, pc, e0, e1));
-            if (prof) LT_TRY(prof_end(h, LT_PROF_PRE_FINE));
         } else {
             const size_t per = 2 * (size_t)L.N;
             dim3 grid(nblk(L.N), R);
             if (nu1 > 0) {
                 // from x = 0 (level 0 here; coarser levels are cleared by the restriction)
-                k_gs_first<T><<<grid, kBlock, 0, st>>>(v, tr, ti, xpre[l], bs[l], active);
-                gs_half_sweep<T>(st, v, tr, ti, 1, xpre[l], bs[l], R, active);
+                k_gs_first<T, kSweepRhs><<<dim3(nblk(L.N), (R + kSweepRhs - 1) / kSweepRhs), kBlock, 0, st>>>(
+                    v, tr, ti, xpre[l], bs[l], active, R);
+                LT_TRY(gs_half_sweep<T>(h, st, v, tr, ti, 1, xpre[l], bs[l], R, active, l == 0));
             } else if (l == 0) {
                 k_zero<T><<<dim3(nblk(per), R), kBlock, 0, st>>>(xpre[0], per, active);
             }
             for (int s = 1; s < nu1; ++s)
                 for (int c = 0; c < 2; ++c)
-                    gs_half_sweep<T>(st, v, tr, ti, c, xpre[l], bs[l], R, active);
-            k_resid_restrict<T><<<dim3(nblk(C.N), R), kBlock, 0, st>>>(
+                    LT_TRY(gs_half_sweep<T>(h, st, v, tr, ti, c, xpre[l], bs[l], R, active, l == 0));
+            k_resid_restrict<T, kSweepRhs><<<dim3(nblk(C.N), (R + kSweepRhs - 1) / kSweepRhs), kBlock, 0, st>>>(
                 v, C.n[0], C.n[1], C.n[2], C.coarsened_from_fine[0], C.coarsened_from_fine[1],
-                C.coarsened_from_fine[2], tr, ti, xpre[l], bs[l], bs[l + 1], xpre[l + 1], active);
+                C.coarsened_from_fine[2], tr, ti, xpre[l], bs[l], bs[l + 1], xpre[l + 1], active, R);
             LT_HIP(hipGetLastError());
         }
     }
@@ -855,7 +925,7 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
             LevelView<T> v = view<T>(L);
             for (int s = 0; s < 64; ++s)
                 for (int c = 0; c < 2; ++c)
-                    gs_half_sweep<T>(st, v, tr, ti, c, xpre[lc], bs[lc], R, active);
+                    LT_TRY(gs_half_sweep<T>(h, st, v, tr, ti, c, xpre[lc], bs[lc], R, active, lc == 0));
         }
         LT_HIP(hipGetLastError());
         xpost[lc] = xpre[lc];
@@ -884,16 +954,6 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
                                         pc, e0, e1));
             }
             if (prof) LT_TRY(prof_end(h, LT_PROF_POST_FINE));
-        } else if (fused3d) {
-            G6 gh = {{(double)g(0), (double)g(1), (double)g(2), (double)g(3), (double)g(4), (double)g(5)}};
-            unsigned long long* pc = nullptr;
-            const bool prof = l == 0 && h->prof_target == LT_PROF_POST_FINE;
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (prof) LT_TRY(prof_begin(h, LT_PROF_POST_FINE, &pc, &e0, &e1));
-            LT_TRY(launch_post3d<T>(st, v, tr, ti, nu2, tile3_of(l), bs[l], xpre[l], xpost[l + 1], C.n[0], C.n[1],
-                                    C.n[2], C.coarsened_from_fine[0], C.coarsened_from_fine[1],
-                                    C.coarsened_from_fine[2], gh, xpost[l], R, active, pc, e0, e1));
-            if (prof) LT_TRY(prof_end(h, LT_PROF_POST_FINE));
         } else {
             dim3 grid(nblk(L.N), R);
             k_prolong<T><<<grid, kBlock, 0, st>>>(L.n[0], L.n[1], L.n[2], C.n[0], C.n[1], C.n[2],
@@ -902,7 +962,7 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
                                                   xpost[l + 1], xpre[l], active);
             for (int s = 0; s < nu2; ++s)
                 for (int c = 1; c >= 0; --c)
-                    gs_half_sweep<T>(st, v, tr, ti, c, xpre[l], bs[l], R, active);
+                    LT_TRY(gs_half_sweep<T>(h, st, v, tr, ti, c, xpre[l], bs[l], R, active, l == 0));
             xpost[l] = xpre[l];
             LT_HIP(hipGetLastError());
         }

@@ -14,10 +14,6 @@ struct T4 {
     double x, y, z, w;  // ghost parity of the -x, +x, -y, +y walls
 };
 
-struct G6 {
-    double g[6];  // ghost parity of the -x, +x, -y, +y, -z, +z walls
-};
-
 template <typename T> struct CBLevel {
     int nx, ny, nz, N;
     int cox, coy, coz;  // axes halved to make this level from the finer one
@@ -57,18 +53,6 @@ int launch_post2d_refine(hipStream_t st, const LevelView<T>& L, const LevelView<
                          const double* rho_in, double* rho_out, T* lo, double* part, int R, const int* active,
                          unsigned long long* prof, int* nparts, hipEvent_t ev0 = nullptr,
                          hipEvent_t ev1 = nullptr);
-// Fused 3D smoothing (mg3d.hip): pre-smoothing from x = 0 with residual restriction,
-// and prolongation plus post-smoothing, one launch each per level; tile 0: 32 x 8, 1: 16 x 8.
-constexpr int kNumTiles3 = 2;
-template <typename T>
-int launch_pre3d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, int tile, const T* b, T* x, int cnx,
-                 int cny, int cnz, int cox, int coy, int coz, T* bc, int R, const int* active,
-                 unsigned long long* prof, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-template <typename T>
-int launch_post3d(hipStream_t st, const LevelView<T>& L, T tr, T ti, int nu, int tile, const T* b, const T* xin,
-                  const T* ec, int cnx, int cny, int cnz, int cox, int coy, int coz, G6 ghost, T* xout, int R,
-                  const int* active, unsigned long long* prof, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-
 template <typename T>
 int launch_coarse_block(hipStream_t st, const CBMeta<T>& M, T tr, T ti, const T* bin, T* xout, int R,
                         const int* active);
