@@ -162,7 +162,7 @@ int refine_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, s
         LT_TRY(mg_vcycle<float>(h, tau, o.nu1, o.nu2, R, inner_active, e32, lo32, &ra));
         if (nparts < 0) {
             LT_TRY(launch_inner_update<float>(st, L0, tau, R, e32, U, ustride, jdev, rho, lo32_next, part,
-                                              inner_active));
+                                              inner_active, h->cp32 ? 1 : 0));
             nparts = reduce_blocks(h->N, R);
         }
     } else {
@@ -416,7 +416,8 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int rini
         double* vj = Q + (size_t)j * N2;
         const double* vscale = j > 0 ? scale : nullptr;  // v_j is normalised by its first read
         if (mixed)
-            LT_TRY(launch_inner_init<float>(st, N, R, qstride, vj, uj, ustride, rho, lo32, active, vscale));
+            LT_TRY(launch_inner_init<float>(st, N, R, qstride, vj, uj, ustride, rho, lo32, active, vscale,
+                                            h->cp32 ? h->grid.n[0] : 0, h->grid.n[1]));
         else
             LT_TRY(launch_inner_init<double>(st, N, R, qstride, vj, uj, ustride, rho, (double*)nullptr, active,
                                              vscale));
@@ -739,10 +740,12 @@ int vcycle_call(lt_handle* h, cdouble tau, int precision, int nu1, int nu2, cons
     float* bf = wsp<float>(h, "vc_b32", per, &rc);
     float* xf = wsp<float>(h, "vc_x32", per, &rc);
     if (!bf || !xf) return rc;
-    if (!h->arena_plan) LT_TRY(convert_vectors<double, float>(h->stream, b, bf, per));
+    // the FP32 cycle's vectors are colour-planar on 3D grids that allow it
+    const int cpnx = h->cp32 ? h->grid.n[0] : 0;
+    if (!h->arena_plan) LT_TRY(convert_vectors_cp<double, float>(h->stream, b, bf, nvec, h->N, cpnx, h->grid.n[1], 0));
     LT_TRY(mg_vcycle<float>(h, tau, nu1, nu2, nvec, nullptr, xf, bf));
     if (h->arena_plan) return 0;
-    return convert_vectors<float, double>(h->stream, xf, x, per);
+    return convert_vectors_cp<float, double>(h->stream, xf, x, nvec, h->N, cpnx, h->grid.n[1], 1);
 }
 
 }  // namespace lt

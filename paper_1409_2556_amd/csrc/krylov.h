@@ -27,14 +27,19 @@ int launch_norms(hipStream_t st, int N, int R, size_t vstride, const double* x, 
 int launch_scale_into(hipStream_t st, int N, int R, size_t instride, size_t outstride, const double* in,
                       const double* nrm, double* out);
 template <typename T>
+// cpnx > 0: lo is written in colour-planar order of an nx = cpnx, ny = cpny grid (the order
+// of a 3D handle's FP32 V-cycle vectors)
 int launch_inner_init(hipStream_t st, int N, int R, size_t qstride, double* v, double* u, size_t ustride,
-                      double* rho, T* lo, const int* active, const double* scale = nullptr);
+                      double* rho, T* lo, const int* active, const double* scale = nullptr, int cpnx = 0,
+                      int cpny = 0);
 // inner_active = active; clear the refinement step counters; count[3] = j; rprev = 1
 int launch_iter_begin(hipStream_t st, int R, const int* active, int* inner_active, int* count, int j,
                       double* rprev);
 template <typename T>
+// cp: e is read and lo written in colour-planar order
 int launch_inner_update(hipStream_t st, LevelView<double> L, cdouble tau, int R, const T* e, double* u,
-                        size_t ustride, const int* jcol, double* rho, T* lo, double* part, const int* inner_active);
+                        size_t ustride, const int* jcol, double* rho, T* lo, double* part, const int* inner_active,
+                        int cp = 0);
 // out[r][k] = ||b_r - (K + z_k M) U_r y_rk|| / beta_r for every right-hand side and shift,
 // from K applied once to each used basis column (KU: R * max(mmax, 1) * 2N doubles,
 // part: R * Ks * reduce_blocks(N, R) doubles).

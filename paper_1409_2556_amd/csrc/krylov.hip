@@ -103,7 +103,7 @@ __global__ void k_scale_into(int N, size_t instride, size_t outstride, const dou
 template <typename T>
 __global__ void k_inner_init(int N, size_t qstride, double* __restrict__ v, double* __restrict__ u,
                              size_t ustride, double* __restrict__ rho, T* __restrict__ lo,
-                             const int* __restrict__ active, const double* __restrict__ scale) {
+                             const int* __restrict__ active, const double* __restrict__ scale, int cpnx, int cpny) {
     int r = blockIdx.y;
     if (active && !active[r]) return;
     size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
@@ -116,7 +116,16 @@ __global__ void k_inner_init(int N, size_t qstride, double* __restrict__ v, doub
     }
     u[ustride * r + i] = 0.0;
     rho[2 * (size_t)N * r + i] = x;
-    if (lo) lo[2 * (size_t)N * r + i] = (T)x;
+    if (lo) {
+        // the low-precision copy in the V-cycle's order (colour-planar when cpnx > 0)
+        size_t o = i;
+        if (cpnx) {
+            const int plane = i >= (size_t)N ? 1 : 0, c = (int)(i - (size_t)plane * N);
+            const int X = c % cpnx, Y = (c / cpnx) % cpny, Z = c / (cpnx * cpny);
+            o = (size_t)plane * N + (size_t)(((X + Y + Z) & 1) * (N >> 1) + (c >> 1));
+        }
+        lo[2 * (size_t)N * r + o] = (T)x;
+    }
 }
 
 // u += e; rho -= (K + tau M) e; lo = (T) rho; partial ||rho||^2
@@ -124,7 +133,7 @@ template <typename T>
 __global__ void k_inner_update(LevelView<double> L, double tr, double ti, const T* __restrict__ e,
                                double* __restrict__ u, size_t ustride, const int* __restrict__ jcol,
                                double* __restrict__ rho, T* __restrict__ lo, double* __restrict__ part,
-                               const int* __restrict__ active) {
+                               const int* __restrict__ active, int cp) {
     int r = blockIdx.y;
     if (active && !active[r]) return;
     const size_t N = L.N;
@@ -135,16 +144,21 @@ __global__ void k_inner_update(LevelView<double> L, double tr, double ti, const 
     double v[1] = {0};
     for (int i = blockIdx.x * kB + threadIdx.x; i < L.N; i += gridDim.x * kB) {
         int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+        // positions of e (the V-cycle's output): natural, or colour-planar, where every
+        // neighbour has the other colour
+        const int c = (x + y + z) & 1, half = L.N >> 1;
+        const int own = cp ? c * half + (i >> 1) : i;
+        auto ep = [&](int j) { return cp ? (1 - c) * half + (j >> 1) : j; };
         double sre = 0, sim = 0;
-        if (x + 1 < L.nx) { double t = L.Tx[i]; sre += t * (double)er[i + 1]; sim += t * (double)ei[i + 1]; }
-        if (x > 0) { double t = L.Tx[i - 1]; sre += t * (double)er[i - 1]; sim += t * (double)ei[i - 1]; }
+        if (x + 1 < L.nx) { double t = L.Tx[i]; const int q = ep(i + 1); sre += t * (double)er[q]; sim += t * (double)ei[q]; }
+        if (x > 0) { double t = L.Tx[i - 1]; const int q = ep(i - 1); sre += t * (double)er[q]; sim += t * (double)ei[q]; }
         const int sy = L.nx, sz = L.nx * L.ny;
-        if (y + 1 < L.ny) { double t = L.Ty[i]; sre += t * (double)er[i + sy]; sim += t * (double)ei[i + sy]; }
-        if (y > 0) { double t = L.Ty[i - sy]; sre += t * (double)er[i - sy]; sim += t * (double)ei[i - sy]; }
-        if (z + 1 < L.nz) { double t = L.Tz[i]; sre += t * (double)er[i + sz]; sim += t * (double)ei[i + sz]; }
-        if (z > 0) { double t = L.Tz[i - sz]; sre += t * (double)er[i - sz]; sim += t * (double)ei[i - sz]; }
+        if (y + 1 < L.ny) { double t = L.Ty[i]; const int q = ep(i + sy); sre += t * (double)er[q]; sim += t * (double)ei[q]; }
+        if (y > 0) { double t = L.Ty[i - sy]; const int q = ep(i - sy); sre += t * (double)er[q]; sim += t * (double)ei[q]; }
+        if (z + 1 < L.nz) { double t = L.Tz[i]; const int q = ep(i + sz); sre += t * (double)er[q]; sim += t * (double)ei[q]; }
+        if (z > 0) { double t = L.Tz[i - sz]; const int q = ep(i - sz); sre += t * (double)er[q]; sim += t * (double)ei[q]; }
         double dre = L.D[i] + tr * L.m[i], dim = ti * L.m[i];
-        double xre = (double)er[i], xim = (double)ei[i];
+        double xre = (double)er[own], xim = (double)ei[own];
         double are = dre * xre - dim * xim - sre;
         double aim = dre * xim + dim * xre - sim;
         ur[i] += xre;
@@ -153,8 +167,8 @@ __global__ void k_inner_update(LevelView<double> L, double tr, double ti, const 
         rr[i] = nre;
         rr[i + N] = nim;
         if (lo) {
-            lo[2 * N * r + i] = (T)nre;
-            lo[2 * N * r + N + i] = (T)nim;
+            lo[2 * N * r + own] = (T)nre;
+            lo[2 * N * r + N + own] = (T)nim;
         }
         v[0] += nre * nre + nim * nim;
     }
@@ -1264,16 +1278,16 @@ int launch_scale_into(hipStream_t st, int N, int R, size_t instride, size_t outs
 
 template <typename T>
 int launch_inner_init(hipStream_t st, int N, int R, size_t qstride, double* v, double* u, size_t ustride,
-                      double* rho, T* lo, const int* active, const double* scale) {
+                      double* rho, T* lo, const int* active, const double* scale, int cpnx, int cpny) {
     k_inner_init<T><<<dim3(nb_for(2 * (size_t)N), R), kB, 0, st>>>(N, qstride, v, u, ustride, rho, lo, active,
-                                                                   scale);
+                                                                   scale, cpnx, cpny);
     LT_HIP(hipGetLastError());
     return 0;
 }
 template int launch_inner_init<double>(hipStream_t, int, int, size_t, double*, double*, size_t, double*,
-                                       double*, const int*, const double*);
+                                       double*, const int*, const double*, int, int);
 template int launch_inner_init<float>(hipStream_t, int, int, size_t, double*, double*, size_t, double*,
-                                      float*, const int*, const double*);
+                                      float*, const int*, const double*, int, int);
 
 int launch_iter_begin(hipStream_t st, int R, const int* active, int* inner_active, int* count, int j,
                       double* rprev) {
@@ -1284,17 +1298,18 @@ int launch_iter_begin(hipStream_t st, int R, const int* active, int* inner_activ
 
 template <typename T>
 int launch_inner_update(hipStream_t st, LevelView<double> L, cdouble tau, int R, const T* e, double* u,
-                        size_t ustride, const int* jcol, double* rho, T* lo, double* part, const int* inner_active) {
+                        size_t ustride, const int* jcol, double* rho, T* lo, double* part, const int* inner_active,
+                        int cp) {
     int nb = reduce_blocks(L.N, R);
     k_inner_update<T><<<dim3(nb, R), kB, 0, st>>>(L, tau.real(), tau.imag(), e, u, ustride, jcol, rho, lo, part,
-                                                  inner_active);
+                                                  inner_active, cp);
     LT_HIP(hipGetLastError());
     return 0;
 }
 template int launch_inner_update<double>(hipStream_t, LevelView<double>, cdouble, int, const double*, double*,
-                                         size_t, const int*, double*, double*, double*, const int*);
+                                         size_t, const int*, double*, double*, double*, const int*, int);
 template int launch_inner_update<float>(hipStream_t, LevelView<double>, cdouble, int, const float*, double*,
-                                        size_t, const int*, double*, float*, double*, const int*);
+                                        size_t, const int*, double*, float*, double*, const int*, int);
 
 int launch_inner_finalize(hipStream_t st, int nb, int R, const double* part, const int* active, const double* worst,
                           double relax_tol, double tol, int inner_max, int* inner_active, int* vcycles, int* count,

@@ -95,6 +95,10 @@ struct lt_handle {
     // tile shape id of the fused 2D smoothers per level, [0]: FP64, [1]: FP32 (lt_autotune)
     int tiles[2][16] = {};
     double lnDbar = 0.0;              // mean of ln D over the fine grid (network features)
+    // FP32 V-cycle vectors of a 3D grid in colour-planar order (cells of colour (x+y+z) & 1 = c
+    // contiguous from c N/2 on), on the fine level and every level above the single-workgroup
+    // ones; set at setup when each such level has an even nx
+    bool cp32 = false;
     struct lt_unet* unet = nullptr;   // attached learned preconditioner (not owned)
     // workspaces (grow-only, owned by the handle); ws_gen changes whenever a
     // workspace or cached coarse inverse moves, which retires captured graphs
@@ -207,5 +211,10 @@ template <typename T>
 int apply_operator(lt_handle* h, int level, cdouble tau, const T* x, T* y, int R, const int* active);
 template <typename S, typename D>
 int convert_vectors(hipStream_t st, const S* in, D* out, size_t count);
+// nvec complex vectors [nvec][2][N] converted between precisions, and between the natural
+// order and the colour-planar order of an nx = cpnx, ny = cpny grid (dir 0: natural to
+// colour-planar, 1: back); cpnx = 0: natural order on both sides
+template <typename S, typename D>
+int convert_vectors_cp(hipStream_t st, const S* in, D* out, int nvec, int N, int cpnx, int cpny, int dir);
 
 }  // namespace lt

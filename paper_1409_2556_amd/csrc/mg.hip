@@ -65,6 +65,14 @@ template <typename T> __device__ __forceinline__ cpx<T> cdiv(cpx<T> a, cpx<T> b)
     return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
 }
 
+// Colour-planar order (FP32 cycles of 3D grids, levels above the single-workgroup ones): the
+// cells of colour c = (x + y + z) & 1 are stored contiguously from c N/2 on, in storage
+// order (nx even), so a one-colour half-sweep reads and writes whole cache lines of one
+// colour.  Position of cell i = (x, y, z):
+__device__ __forceinline__ int cp_at(int i, int x, int y, int z, int N) {
+    return ((x + y + z) & 1) * (N >> 1) + (i >> 1);
+}
+
 // Off-diagonal sum  sum_nbr T x_nbr  at cell i = (x, y, z) of plane pair (re, im).
 template <typename T>
 __device__ __forceinline__ cpx<T> offsum(const LevelView<T>& L, const T* xr, const T* xi, int i, int x,
@@ -187,6 +195,30 @@ int convert_vectors(hipStream_t st, const S* in, D* out, size_t count) {
     LT_HIP(hipGetLastError());
     return 0;
 }
+template <typename S, typename D>
+__global__ void k_convert_cp(const S* __restrict__ in, D* __restrict__ out, int N, int nx, int ny, int dir) {
+    const size_t plane = blockIdx.y;  // vector * 2 + (re, im)
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int X = i % nx, Y = (i / nx) % ny, Z = i / (nx * ny);
+    const int p = cp_at(i, X, Y, Z, N);
+    const size_t base = plane * N;
+    if (dir == 0)
+        out[base + p] = (D)in[base + i];
+    else
+        out[base + i] = (D)in[base + p];
+}
+
+template <typename S, typename D>
+int convert_vectors_cp(hipStream_t st, const S* in, D* out, int nvec, int N, int cpnx, int cpny, int dir) {
+    if (!cpnx) return convert_vectors<S, D>(st, in, out, 2 * (size_t)N * nvec);
+    k_convert_cp<S, D><<<dim3((unsigned)((N + kBlock - 1) / kBlock), 2 * nvec), kBlock, 0, st>>>(in, out, N, cpnx, cpny, dir);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+template int convert_vectors_cp<double, float>(hipStream_t, const double*, float*, int, int, int, int, int);
+template int convert_vectors_cp<float, double>(hipStream_t, const float*, double*, int, int, int, int, int);
+
 template int convert_vectors<double, float>(hipStream_t, const double*, float*, size_t);
 template int convert_vectors<float, double>(hipStream_t, const float*, double*, size_t);
 template int convert_vectors<double, double>(hipStream_t, const double*, double*, size_t);
@@ -239,7 +271,7 @@ __global__ void k_gs_color(LevelView<T> L, T tr, T ti, int color, T* __restrict_
 // the k-th cell of that colour in storage order, so no lane idles.  A thread serves its
 // cell for RB consecutive right-hand sides: the coefficients are loaded once and reused
 // (they are shared by every right-hand side), and the RB updates are independent.
-template <typename T, int RB>
+template <typename T, int RB, bool CP>
 __global__ void k_gs_color_half(LevelView<T> L, T tr, T ti, int color, T* __restrict__ x,
                                 const T* __restrict__ b, const int* __restrict__ active, int R,
                                 unsigned long long* __restrict__ prof, unsigned long long prof_bytes) {
@@ -270,6 +302,13 @@ __global__ void k_gs_color_half(LevelView<T> L, T tr, T ti, int color, T* __rest
                      ly ? L.Ty[i - sy] : T(0), hz ? L.Tz[i] : T(0), lz ? L.Tz[i - sz] : T(0)};
     const cpx<T> d = {L.D[i] + tr * L.m[i], ti * L.m[i]};
     const size_t N = L.N;
+    // positions in the vectors: this cell and its neighbours (all of the other colour; a
+    // missing neighbour's position is a valid cell read with coupling 0)
+    const int half = L.N >> 1;
+    const int own = CP ? color * half + k : i;
+    int np[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) np[a] = CP ? (1 - color) * half + (nb[a] >> 1) : nb[a];
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
         const int r = r0 + q;
@@ -280,13 +319,13 @@ __global__ void k_gs_color_half(LevelView<T> L, T tr, T ti, int color, T* __rest
         cpx<T> off = {0, 0};
 #pragma unroll
         for (int a = 0; a < 6; ++a) {
-            off.re += tc[a] * xr[nb[a]];
-            off.im += tc[a] * xi[nb[a]];
+            off.re += tc[a] * xr[np[a]];
+            off.im += tc[a] * xi[np[a]];
         }
-        const cpx<T> num = {br[i] + off.re, br[i + N] + off.im};
+        const cpx<T> num = {br[own] + off.re, br[own + N] + off.im};
         const cpx<T> v = cdiv(num, d);
-        xr[i] = v.re;
-        xi[i] = v.im;
+        xr[own] = v.re;
+        xi[own] = v.im;
     }
 }
 
@@ -297,7 +336,7 @@ __global__ void k_gs_color_half(LevelView<T> L, T tr, T ti, int color, T* __rest
 // cell and D, m of the colour's cells, shared by the R right-hand sides (4 sizeof(T) per cell)
 template <typename T>
 static int gs_half_sweep(lt_handle* h, hipStream_t st, const LevelView<T>& L, T tr, T ti, int color, T* x,
-                         const T* b, int R, const int* active, bool fine) {
+                         const T* b, int R, const int* active, bool fine, bool cp = false) {
     if ((L.nx & 1) == 0) {
         const dim3 grid((unsigned)((L.N / 2 + 255) / 256), (R + kSweepRhs - 1) / kSweepRhs);
         if (fine && h->prof_target == LT_PROF_SWEEP3D) {
@@ -306,11 +345,19 @@ static int gs_half_sweep(lt_handle* h, hipStream_t st, const LevelView<T>& L, T 
             LT_TRY(prof_begin(h, LT_PROF_SWEEP3D, &pc, &e0, &e1));
             const unsigned long long per = (unsigned long long)((double)L.N * 3.0 * sizeof(T) +
                                                                 (double)L.N * 4.0 * sizeof(T) / R);
-            hipExtLaunchKernelGGL((k_gs_color_half<T, kSweepRhs>), grid, dim3(256), 0, st, e0, e1, 0, L, tr, ti,
-                                  color, x, b, active, R, pc, per);
+            if (cp)
+                hipExtLaunchKernelGGL((k_gs_color_half<T, kSweepRhs, true>), grid, dim3(256), 0, st, e0, e1, 0, L, tr,
+                                      ti, color, x, b, active, R, pc, per);
+            else
+                hipExtLaunchKernelGGL((k_gs_color_half<T, kSweepRhs, false>), grid, dim3(256), 0, st, e0, e1, 0, L, tr,
+                                      ti, color, x, b, active, R, pc, per);
             LT_TRY(prof_end(h, LT_PROF_SWEEP3D));
+        } else if (cp) {
+            k_gs_color_half<T, kSweepRhs, true><<<grid, 256, 0, st>>>(L, tr, ti, color, x, b, active, R, nullptr,
+                                                                      0ull);
         } else {
-            k_gs_color_half<T, kSweepRhs><<<grid, 256, 0, st>>>(L, tr, ti, color, x, b, active, R, nullptr, 0ull);
+            k_gs_color_half<T, kSweepRhs, false><<<grid, 256, 0, st>>>(L, tr, ti, color, x, b, active, R, nullptr,
+                                                                       0ull);
         }
     } else {
         k_gs_color<T><<<dim3((unsigned)((L.N + 255) / 256), R), 256, 0, st>>>(L, tr, ti, color, x, b, active);
@@ -325,7 +372,8 @@ static int gs_half_sweep(lt_handle* h, hipStream_t st, const LevelView<T>& L, T 
 template <typename T, int RB>
 __global__ void k_resid_restrict(LevelView<T> F, int cnx, int cny, int cnz, int cox, int coy, int coz,
                                  T tr, T ti, const T* __restrict__ xf, const T* __restrict__ bf,
-                                 T* __restrict__ bc, T* __restrict__ xc, const int* __restrict__ active, int R) {
+                                 T* __restrict__ bc, T* __restrict__ xc, const int* __restrict__ active, int R,
+                                 int cpf, int cpc) {
     const int r0 = blockIdx.y * RB;
     bool any = false;
 #pragma unroll
@@ -355,6 +403,12 @@ __global__ void k_resid_restrict(LevelView<T> F, int cnx, int cny, int cnz, int 
                 const T tc[6] = {hx ? F.Tx[i] : T(0), lx ? F.Tx[i - 1] : T(0), hy ? F.Ty[i] : T(0),
                                  ly ? F.Ty[i - sy] : T(0), hz ? F.Tz[i] : T(0), lz ? F.Tz[i - sz] : T(0)};
                 const cpx<T> d = {F.D[i] + tr * F.m[i], ti * F.m[i]};
+                // positions in the fine vectors (colour-planar: the neighbours have the other colour)
+                const int c = (x + y + z) & 1, half = F.N >> 1;
+                const int own = cpf ? c * half + (i >> 1) : i;
+                int np[6];
+#pragma unroll
+                for (int a = 0; a < 6; ++a) np[a] = cpf ? (1 - c) * half + (nb[a] >> 1) : nb[a];
 #pragma unroll
                 for (int q = 0; q < RB; ++q) {
                     const int r = r0 + q;
@@ -366,23 +420,24 @@ __global__ void k_resid_restrict(LevelView<T> F, int cnx, int cny, int cnz, int 
                     cpx<T> off = {0, 0};
 #pragma unroll
                     for (int a = 0; a < 6; ++a) {
-                        off.re += tc[a] * xr[nb[a]];
-                        off.im += tc[a] * xi[nb[a]];
+                        off.re += tc[a] * xr[np[a]];
+                        off.im += tc[a] * xi[np[a]];
                     }
-                    const cpx<T> ax = cmul(d, cpx<T>{xr[i], xi[i]});
-                    acc[q].re += br[i] - (ax.re - off.re);
-                    acc[q].im += bi[i] - (ax.im - off.im);
+                    const cpx<T> ax = cmul(d, cpx<T>{xr[own], xi[own]});
+                    acc[q].re += br[own] - (ax.re - off.re);
+                    acc[q].im += bi[own] - (ax.im - off.im);
                 }
             }
     const size_t M = Nc;
+    const int Ic = cpc ? cp_at(I, Xc, Yc, Zc, Nc) : I;
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
         const int r = r0 + q;
         if (r >= R || (active && !active[r])) continue;
-        bc[2 * M * r + I] = acc[q].re;
-        bc[2 * M * r + M + I] = acc[q].im;
-        xc[2 * M * r + I] = 0;
-        xc[2 * M * r + M + I] = 0;
+        bc[2 * M * r + Ic] = acc[q].re;
+        bc[2 * M * r + M + Ic] = acc[q].im;
+        xc[2 * M * r + Ic] = 0;
+        xc[2 * M * r + M + Ic] = 0;
     }
 }
 
@@ -392,7 +447,7 @@ __global__ void k_resid_restrict(LevelView<T> F, int cnx, int cny, int cnz, int 
 template <typename T>
 __device__ __forceinline__ cpx<T> prolong_value(int x, int y, int z, int cnx, int cny, int cnz, int cox, int coy,
                                                 int coz, const T* glo, const T* ghi, const T* __restrict__ er,
-                                                const T* __restrict__ ei) {
+                                                const T* __restrict__ ei, int cpc = 0) {
     int ia[3][2];
     T wa[3][2];
     int na[3];
@@ -429,7 +484,8 @@ __device__ __forceinline__ cpx<T> prolong_value(int x, int y, int z, int cnx, in
         for (int b = 0; b < na[1]; ++b)
             for (int a = 0; a < na[0]; ++a) {
                 T w = wa[0][a] * wa[1][b] * wa[2][c];
-                size_t J = ia[0][a] + (size_t)cnx * (ia[1][b] + (size_t)cny * ia[2][c]);
+                int J = ia[0][a] + cnx * (ia[1][b] + cny * ia[2][c]);
+                if (cpc) J = cp_at(J, ia[0][a], ia[1][b], ia[2][c], cnx * cny * cnz);
                 acc.re += w * er[J];
                 acc.im += w * ei[J];
             }
@@ -440,7 +496,7 @@ __device__ __forceinline__ cpx<T> prolong_value(int x, int y, int z, int cnx, in
 template <typename T>
 __global__ void k_prolong(int fnx, int fny, int fnz, int cnx, int cny, int cnz, int cox, int coy, int coz,
                           T glox, T ghix, T gloy, T ghiy, T gloz, T ghiz, const T* __restrict__ ec,
-                          T* __restrict__ xf, const int* __restrict__ active) {
+                          T* __restrict__ xf, const int* __restrict__ active, int cpf, int cpc) {
     int r = blockIdx.y;
     if (active && !active[r]) return;
     const int Nf = fnx * fny * fnz;
@@ -451,10 +507,11 @@ __global__ void k_prolong(int fnx, int fny, int fnz, int cnx, int cny, int cnz, 
     const T ghi[3] = {ghix, ghiy, ghiz};
     const size_t Mc = (size_t)cnx * cny * cnz;
     const T* er = ec + 2 * Mc * r;
-    const cpx<T> acc = prolong_value<T>(x, y, z, cnx, cny, cnz, cox, coy, coz, glo, ghi, er, er + Mc);
+    const cpx<T> acc = prolong_value<T>(x, y, z, cnx, cny, cnz, cox, coy, coz, glo, ghi, er, er + Mc, cpc);
     const size_t Nfs = Nf;
-    xf[2 * Nfs * r + i] += acc.re;
-    xf[2 * Nfs * r + Nfs + i] += acc.im;
+    const int p = cpf ? cp_at(i, x, y, z, Nf) : i;
+    xf[2 * Nfs * r + p] += acc.re;
+    xf[2 * Nfs * r + Nfs + p] += acc.im;
 }
 
 // The first half-sweep of red-black Gauss-Seidel from x = 0: colour-0 cells see only
@@ -462,12 +519,21 @@ __global__ void k_prolong(int fnx, int fny, int fnz, int cnx, int cny, int cnz, 
 // first sweep of colour 0.  RB right-hand sides per thread (D and m loaded once).
 template <typename T, int RB>
 __global__ void k_gs_first(LevelView<T> L, T tr, T ti, T* __restrict__ x, const T* __restrict__ b,
-                           const int* __restrict__ active, int R) {
+                           const int* __restrict__ active, int R, int cp) {
     const int r0 = blockIdx.y * RB;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= L.N) return;
-    const int X = i % L.nx, Y = (i / L.nx) % L.ny, Z = i / (L.nx * L.ny);
-    const bool c0 = ((X + Y + Z) & 1) == 0;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;  // position in the vectors
+    if (p >= L.N) return;
+    int i = p, c0 = 0;
+    if (cp) {
+        // the cell at colour-planar position p
+        const int half = L.N >> 1, c = p >= half ? 1 : 0, k = p - c * half, W = L.nx >> 1;
+        const int row = k / W, Y = row % L.ny, Z = row / L.ny;
+        i = 2 * (k - row * W) + ((Y + Z + c) & 1) + L.nx * row;
+        c0 = c == 0;
+    } else {
+        const int X = i % L.nx, Y = (i / L.nx) % L.ny, Z = i / (L.nx * L.ny);
+        c0 = ((X + Y + Z) & 1) == 0;
+    }
     const cpx<T> d = {L.D[i] + tr * L.m[i], ti * L.m[i]};
     const size_t N = L.N;
 #pragma unroll
@@ -478,12 +544,12 @@ __global__ void k_gs_first(LevelView<T> L, T tr, T ti, T* __restrict__ x, const 
         T* xi = xr + N;
         if (c0) {
             const T* br = b + 2 * N * r;
-            const cpx<T> v = cdiv(cpx<T>{br[i], br[i + N]}, d);
-            xr[i] = v.re;
-            xi[i] = v.im;
+            const cpx<T> v = cdiv(cpx<T>{br[p], br[p + N]}, d);
+            xr[p] = v.re;
+            xi[p] = v.im;
         } else {
-            xr[i] = 0;
-            xi[i] = 0;
+            xr[p] = 0;
+            xi[p] = 0;
         }
     }
 }
@@ -602,6 +668,18 @@ int mg_build(lt_handle* h, const double* kappa, const double* S) {
         double s = 0;
         for (double d : D) s += std::log(d);
         h->lnDbar = s / f.N;
+    }
+    // colour-planar FP32 vectors for 3D grids whose levels above the single-workgroup ones
+    // (those with more than kCoarseBlockCells cells, at most kMaxCBLevels below them) all
+    // have an even number of cells along x
+    {
+        const int nl = (int)lv.size();
+        int lc = nl;
+        for (int l = 0; l < nl; ++l)
+            if (lv[l].N <= kCoarseBlockCells) { lc = l; break; }
+        bool ok = h->grid.ndim == 3 && lc > 0 && lc < nl && nl - lc <= kMaxCBLevels;
+        for (int l = 0; l < lc && ok; ++l) ok = (lv[l].n[0] % 2) == 0;
+        h->cp32 = ok;
     }
     // coarsest coefficients on the host for the dense coarse solve
     const Level& Lc = lv.back();
@@ -812,6 +890,11 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
     if (!cb) lc = nl - 1;  // generic path down to the coarsest level
     const bool fused2d = h->grid.ndim == 2 && nu1 >= 1 && nu1 <= 3 && nu2 >= 1 && nu2 <= 3;
     const bool fusedT = fused2d;
+    // FP32 cycles of 3D grids keep the generic levels' vectors in colour-planar order (the
+    // handle decided at setup whether every such level allows it); the single-workgroup
+    // levels use the natural order
+    const bool cp = !fused2d && sizeof(T) == 4 && h->cp32 && cb;
+    auto cpl = [&](int l) { return cp && l < lc ? 1 : 0; };
     const int* tiles = h->tiles[sizeof(T) == 4 ? 1 : 0];
     auto tile_of = [&](int l) { return l < kMaxTunedLevels ? tiles[l] : 0; };
     const int tag = sizeof(T) == 8 ? 64 : 32;
@@ -875,17 +958,18 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
             if (nu1 > 0) {
                 // from x = 0 (level 0 here; coarser levels are cleared by the restriction)
                 k_gs_first<T, kSweepRhs><<<dim3(nblk(L.N), (R + kSweepRhs - 1) / kSweepRhs), kBlock, 0, st>>>(
-                    v, tr, ti, xpre[l], bs[l], active, R);
-                LT_TRY(gs_half_sweep<T>(h, st, v, tr, ti, 1, xpre[l], bs[l], R, active, l == 0));
+                    v, tr, ti, xpre[l], bs[l], active, R, cpl(l));
+                LT_TRY(gs_half_sweep<T>(h, st, v, tr, ti, 1, xpre[l], bs[l], R, active, l == 0, cpl(l)));
             } else if (l == 0) {
                 k_zero<T><<<dim3(nblk(per), R), kBlock, 0, st>>>(xpre[0], per, active);
             }
             for (int s = 1; s < nu1; ++s)
                 for (int c = 0; c < 2; ++c)
-                    LT_TRY(gs_half_sweep<T>(h, st, v, tr, ti, c, xpre[l], bs[l], R, active, l == 0));
+                    LT_TRY(gs_half_sweep<T>(h, st, v, tr, ti, c, xpre[l], bs[l], R, active, l == 0, cpl(l)));
             k_resid_restrict<T, kSweepRhs><<<dim3(nblk(C.N), (R + kSweepRhs - 1) / kSweepRhs), kBlock, 0, st>>>(
                 v, C.n[0], C.n[1], C.n[2], C.coarsened_from_fine[0], C.coarsened_from_fine[1],
-                C.coarsened_from_fine[2], tr, ti, xpre[l], bs[l], bs[l + 1], xpre[l + 1], active, R);
+                C.coarsened_from_fine[2], tr, ti, xpre[l], bs[l], bs[l + 1], xpre[l + 1], active, R, cpl(l),
+                cpl(l + 1));
             LT_HIP(hipGetLastError());
         }
     }
@@ -959,10 +1043,10 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
             k_prolong<T><<<grid, kBlock, 0, st>>>(L.n[0], L.n[1], L.n[2], C.n[0], C.n[1], C.n[2],
                                                   C.coarsened_from_fine[0], C.coarsened_from_fine[1],
                                                   C.coarsened_from_fine[2], g(0), g(1), g(2), g(3), g(4), g(5),
-                                                  xpost[l + 1], xpre[l], active);
+                                                  xpost[l + 1], xpre[l], active, cpl(l), cpl(l + 1));
             for (int s = 0; s < nu2; ++s)
                 for (int c = 1; c >= 0; --c)
-                    LT_TRY(gs_half_sweep<T>(h, st, v, tr, ti, c, xpre[l], bs[l], R, active, l == 0));
+                    LT_TRY(gs_half_sweep<T>(h, st, v, tr, ti, c, xpre[l], bs[l], R, active, l == 0, cpl(l)));
             xpost[l] = xpre[l];
             LT_HIP(hipGetLastError());
         }
