@@ -148,7 +148,8 @@ struct KrylovOut {
 // enqueues work; u_j is U advanced by the device column index jdev.
 // *swapped = 1 when the FP64 residual moved to rho_next.
 int refine_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, size_t ustride, const int* jdev,
-                float* e32, double* e64, float* lo32, float* lo32_next, double* rho, double* rho_next, double* part,
+                float* e32, double* e64, float* lo32, float* lo32_next, double* lo64, double* rho, double* rho_next,
+                double* part,
                 const int* active, int* inner_active, const double* worst, int* vcyc, int* count, double* rprev,
                 int* est, int* swapped) {
     hipStream_t st = h->stream;
@@ -162,15 +163,16 @@ int refine_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, s
         LT_TRY(mg_vcycle<float>(h, tau, o.nu1, o.nu2, R, inner_active, e32, lo32, &ra));
         if (nparts < 0) {
             LT_TRY(launch_inner_update<float>(st, L0, tau, R, e32, U, ustride, jdev, rho, lo32_next, part,
-                                              inner_active, h->cp32 ? 1 : 0));
+                                              inner_active, h->cp3d ? 1 : 0));
             nparts = reduce_blocks(h->N, R);
         }
     } else {
         RefineArgs ra{U, ustride, jdev, rho, rho_next, nullptr, part, &nparts};
-        LT_TRY(mg_vcycle<double>(h, tau, o.nu1, o.nu2, R, inner_active, e64, rho, &ra));
+        // 3D grids: the cycle reads the colour-planar copy of rho, which the update refreshes
+        LT_TRY(mg_vcycle<double>(h, tau, o.nu1, o.nu2, R, inner_active, e64, lo64 ? lo64 : rho, &ra));
         if (nparts < 0) {
-            LT_TRY(launch_inner_update<double>(st, L0, tau, R, e64, U, ustride, jdev, rho, (double*)nullptr, part,
-                                               inner_active));
+            LT_TRY(launch_inner_update<double>(st, L0, tau, R, e64, U, ustride, jdev, rho, lo64, part,
+                                               inner_active, lo64 ? 1 : 0));
             nparts = reduce_blocks(h->N, R);
         } else {
             *swapped = 1;
@@ -184,7 +186,8 @@ int refine_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, s
 // captured step bakes in is part of the key: sizes, options, the shift, the
 // buffers, and the workspace generation (any reallocation retires all graphs).
 int graph_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, size_t ustride, const int* jdev,
-               float* e32, double* e64, float* lo32, float* lo32_next, double* rho, double* rho_next, double* part,
+               float* e32, double* e64, float* lo32, float* lo32_next, double* lo64, double* rho, double* rho_next,
+               double* part,
                const int* active, int* inner_active, const double* worst, int* vcyc, int* count, double* rprev,
                int* est, int* swapped) {
     hipStream_t st = h->stream;
@@ -206,7 +209,7 @@ int graph_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, si
     std::vector<unsigned long long> key = {
         (unsigned long long)o.precision, (unsigned long long)R, (unsigned long long)o.nu1, (unsigned long long)o.nu2,
         bits(tau.real()), bits(tau.imag()), bits(o.relax * o.tol), bits(o.tol), (unsigned long long)o.inner_max,
-        ptr(U), ustride, ptr(jdev), ptr(e32), ptr(e64), ptr(lo32), ptr(lo32_next), ptr(rho), ptr(rho_next),
+        ptr(U), ustride, ptr(jdev), ptr(e32), ptr(e64), ptr(lo32), ptr(lo32_next), ptr(lo64), ptr(rho), ptr(rho_next),
         ptr(part), ptr(active), ptr(inner_active), ptr(worst), ptr(vcyc), ptr(count), ptr(rprev), ptr(est),
         h->ws_gen};
     auto it = h->graphs.find(key);
@@ -218,7 +221,7 @@ int graph_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, si
         const unsigned long long gen = h->ws_gen;
         LT_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         int sw = 0;
-        const int rcs = refine_step(h, o, R, tau, U, ustride, jdev, e32, e64, lo32, lo32_next, rho, rho_next, part,
+        const int rcs = refine_step(h, o, R, tau, U, ustride, jdev, e32, e64, lo32, lo32_next, lo64, rho, rho_next, part,
                                     active, inner_active, worst, vcyc, count, rprev, est, &sw);
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(st, &g);
@@ -230,7 +233,7 @@ int graph_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, si
                 return LT_EHIP;
             }
             // a workspace moved while capturing: launch this step directly
-            return refine_step(h, o, R, tau, U, ustride, jdev, e32, e64, lo32, lo32_next, rho, rho_next, part,
+            return refine_step(h, o, R, tau, U, ustride, jdev, e32, e64, lo32, lo32_next, lo64, rho, rho_next, part,
                                active, inner_active, worst, vcyc, count, rprev, est, swapped);
         }
         hipGraphExec_t ex = nullptr;
@@ -285,6 +288,12 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int rini
     } else {
         e64 = wsp<double>(h, "e64", R * N2, &rc);
         if (!e64) return rc;
+    }
+    // FP64 cycles of a 3D grid read a colour-planar copy of rho (the FP32 ones lo32)
+    double* lo64 = nullptr;
+    if (!mixed && h->cp3d) {
+        lo64 = wsp<double>(h, "lo64", R * N2, &rc);
+        if (!lo64) return rc;
     }
     const int hstride = 2 * (jmax + 2);
     const size_t hrstride = (size_t)jmax * hstride;
@@ -417,10 +426,10 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int rini
         const double* vscale = j > 0 ? scale : nullptr;  // v_j is normalised by its first read
         if (mixed)
             LT_TRY(launch_inner_init<float>(st, N, R, qstride, vj, uj, ustride, rho, lo32, active, vscale,
-                                            h->cp32 ? h->grid.n[0] : 0, h->grid.n[1]));
+                                            h->cp3d ? h->grid.n[0] : 0, h->grid.n[1]));
         else
-            LT_TRY(launch_inner_init<double>(st, N, R, qstride, vj, uj, ustride, rho, (double*)nullptr, active,
-                                             vscale));
+            LT_TRY(launch_inner_init<double>(st, N, R, qstride, vj, uj, ustride, rho, lo64, active, vscale,
+                                             h->cp3d ? h->grid.n[0] : 0, h->grid.n[1]));
         if (use_net && probe_rhs >= 0) {
             // learned first guess u = alpha net(v), alpha minimising ||v - alpha (K + tau M) net(v)||;
             // rho = v - (K + tau M) u; discarded where it is not finite or does not help.  Until
@@ -460,10 +469,10 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int rini
             for (int b2 = 0; b2 < batch && step < o.inner_max; ++b2, ++step) {
                 int swapped = 0;
                 if (use_graphs && j > 0) {
-                    LT_TRY(graph_step(h, o, R, tau, U, ustride, jdev, e32, e64, lo32, lo32_next, rho, rho_next, part,
+                    LT_TRY(graph_step(h, o, R, tau, U, ustride, jdev, e32, e64, lo32, lo32_next, lo64, rho, rho_next, part,
                                       active, inner_active, worst, vcyc, count, rprev, est, &swapped));
                 } else {
-                    LT_TRY(refine_step(h, o, R, tau, U, ustride, jdev, e32, e64, lo32, lo32_next, rho, rho_next, part,
+                    LT_TRY(refine_step(h, o, R, tau, U, ustride, jdev, e32, e64, lo32, lo32_next, lo64, rho, rho_next, part,
                                        active, inner_active, worst, vcyc, count, rprev, est, &swapped));
                 }
                 if (mixed) std::swap(lo32, lo32_next);
@@ -736,12 +745,23 @@ namespace lt {
 int vcycle_call(lt_handle* h, cdouble tau, int precision, int nu1, int nu2, const double* b, double* x, int nvec) {
     const size_t per = 2 * (size_t)h->N * nvec;
     int rc = 0;
-    if (precision == LT_PREC_FP64) return mg_vcycle<double>(h, tau, nu1, nu2, nvec, nullptr, x, b);
+    if (precision == LT_PREC_FP64) {
+        if (!h->cp3d) return mg_vcycle<double>(h, tau, nu1, nu2, nvec, nullptr, x, b);
+        // 3D: the cycle's vectors in colour-planar order
+        double* bc = wsp<double>(h, "vc_b64", per, &rc);
+        double* xc = wsp<double>(h, "vc_x64", per, &rc);
+        if (!bc || !xc) return rc;
+        if (!h->arena_plan)
+            LT_TRY(convert_vectors_cp<double, double>(h->stream, b, bc, nvec, h->N, h->grid.n[0], h->grid.n[1], 0));
+        LT_TRY(mg_vcycle<double>(h, tau, nu1, nu2, nvec, nullptr, xc, bc));
+        if (h->arena_plan) return 0;
+        return convert_vectors_cp<double, double>(h->stream, xc, x, nvec, h->N, h->grid.n[0], h->grid.n[1], 1);
+    }
     float* bf = wsp<float>(h, "vc_b32", per, &rc);
     float* xf = wsp<float>(h, "vc_x32", per, &rc);
     if (!bf || !xf) return rc;
     // the FP32 cycle's vectors are colour-planar on 3D grids that allow it
-    const int cpnx = h->cp32 ? h->grid.n[0] : 0;
+    const int cpnx = h->cp3d ? h->grid.n[0] : 0;
     if (!h->arena_plan) LT_TRY(convert_vectors_cp<double, float>(h->stream, b, bf, nvec, h->N, cpnx, h->grid.n[1], 0));
     LT_TRY(mg_vcycle<float>(h, tau, nu1, nu2, nvec, nullptr, xf, bf));
     if (h->arena_plan) return 0;
@@ -1205,16 +1225,20 @@ int lt_precond_solve(lt_handle* h, double tau_re, double tau_im, int nvec, const
     const int nb = reduce_blocks(N, nvec);
     double* part = wsp<double>(h, "ps_part", (size_t)nvec * nb, &rc);
     double* nrm = wsp<double>(h, "ps_nrm", 2 * (size_t)nvec, &rc);
-    if (!rho || !x || !part || !nrm) return rc;
+    // 3D grids: the cycle reads a colour-planar copy of the residual and returns its
+    // correction in that order
+    double* lo = h->cp3d ? wsp<double>(h, "ps_lo", nvec * N2, &rc) : nullptr;
+    if (!rho || !x || !part || !nrm || (h->cp3d && !lo)) return rc;
     const cdouble tau(tau_re, tau_im);
     const LevelView<double> L0 = h->levels[0].v64();
     LT_HIP(hipMemcpyAsync(rho, r, nvec * N2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (lo) LT_TRY(convert_vectors_cp<double, double>(st, r, lo, nvec, N, h->grid.n[0], h->grid.n[1], 0));
     LT_HIP(hipMemsetAsync(e, 0, nvec * N2 * sizeof(double), st));
     LT_TRY(launch_norms(st, N, nvec, N2, r, part, nrm + nvec, nullptr));
     std::vector<double> hn(2 * (size_t)nvec);
     for (int c = 0; c < maxcycles; ++c) {
-        LT_TRY(mg_vcycle<double>(h, tau, 2, 2, nvec, nullptr, x, rho));
-        LT_TRY(launch_inner_update<double>(st, L0, tau, nvec, x, e, N2, nullptr, rho, (double*)nullptr, part, nullptr));
+        LT_TRY(mg_vcycle<double>(h, tau, 2, 2, nvec, nullptr, x, lo ? lo : rho));
+        LT_TRY(launch_inner_update<double>(st, L0, tau, nvec, x, e, N2, nullptr, rho, lo, part, nullptr, lo ? 1 : 0));
         LT_TRY(launch_norms(st, N, nvec, N2, rho, part, nrm, nullptr));
         LT_HIP(hipMemcpyAsync(hn.data(), nrm, 2 * nvec * sizeof(double), hipMemcpyDeviceToHost, st));
         LT_HIP(hipStreamSynchronize(st));

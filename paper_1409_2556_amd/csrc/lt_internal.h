@@ -95,10 +95,10 @@ struct lt_handle {
     // tile shape id of the fused 2D smoothers per level, [0]: FP64, [1]: FP32 (lt_autotune)
     int tiles[2][16] = {};
     double lnDbar = 0.0;              // mean of ln D over the fine grid (network features)
-    // FP32 V-cycle vectors of a 3D grid in colour-planar order (cells of colour (x+y+z) & 1 = c
+    // V-cycle vectors of a 3D grid in colour-planar order (cells of colour (x+y+z) & 1 = c
     // contiguous from c N/2 on), on the fine level and every level above the single-workgroup
     // ones; set at setup when each such level has an even nx
-    bool cp32 = false;
+    bool cp3d = false;
     struct lt_unet* unet = nullptr;   // attached learned preconditioner (not owned)
     // workspaces (grow-only, owned by the handle); ws_gen changes whenever a
     // workspace or cached coarse inverse moves, which retires captured graphs

@@ -218,6 +218,7 @@ int convert_vectors_cp(hipStream_t st, const S* in, D* out, int nvec, int N, int
 }
 template int convert_vectors_cp<double, float>(hipStream_t, const double*, float*, int, int, int, int, int);
 template int convert_vectors_cp<float, double>(hipStream_t, const float*, double*, int, int, int, int, int);
+template int convert_vectors_cp<double, double>(hipStream_t, const double*, double*, int, int, int, int, int);
 
 template int convert_vectors<double, float>(hipStream_t, const double*, float*, size_t);
 template int convert_vectors<float, double>(hipStream_t, const float*, double*, size_t);
@@ -669,7 +670,7 @@ int mg_build(lt_handle* h, const double* kappa, const double* S) {
         for (double d : D) s += std::log(d);
         h->lnDbar = s / f.N;
     }
-    // colour-planar FP32 vectors for 3D grids whose levels above the single-workgroup ones
+    // colour-planar V-cycle vectors for 3D grids whose levels above the single-workgroup ones
     // (those with more than kCoarseBlockCells cells, at most kMaxCBLevels below them) all
     // have an even number of cells along x
     {
@@ -679,7 +680,7 @@ int mg_build(lt_handle* h, const double* kappa, const double* S) {
             if (lv[l].N <= kCoarseBlockCells) { lc = l; break; }
         bool ok = h->grid.ndim == 3 && lc > 0 && lc < nl && nl - lc <= kMaxCBLevels;
         for (int l = 0; l < lc && ok; ++l) ok = (lv[l].n[0] % 2) == 0;
-        h->cp32 = ok;
+        h->cp3d = ok;
     }
     // coarsest coefficients on the host for the dense coarse solve
     const Level& Lc = lv.back();
@@ -890,10 +891,10 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
     if (!cb) lc = nl - 1;  // generic path down to the coarsest level
     const bool fused2d = h->grid.ndim == 2 && nu1 >= 1 && nu1 <= 3 && nu2 >= 1 && nu2 <= 3;
     const bool fusedT = fused2d;
-    // FP32 cycles of 3D grids keep the generic levels' vectors in colour-planar order (the
-    // handle decided at setup whether every such level allows it); the single-workgroup
-    // levels use the natural order
-    const bool cp = !fused2d && sizeof(T) == 4 && h->cp32 && cb;
+    // cycles of 3D grids keep the generic levels' vectors in colour-planar order (the handle
+    // decided at setup whether every such level allows it); the single-workgroup levels use
+    // the natural order
+    const bool cp = !fused2d && h->cp3d && cb;
     auto cpl = [&](int l) { return cp && l < lc ? 1 : 0; };
     const int* tiles = h->tiles[sizeof(T) == 4 ? 1 : 0];
     auto tile_of = [&](int l) { return l < kMaxTunedLevels ? tiles[l] : 0; };
