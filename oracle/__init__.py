@@ -13,11 +13,14 @@ fv        cell-centred finite-volume K, lumped M, point-source weights
 contour   optimised Talbot nodes and trapezoid weights (Section 2.2)
 heads     heads at receivers by one direct solve per shift (eqn:half)
 jacobian  sensitivities to ln(kappa), ln(S) by the discrete adjoint (Section 5.2)
+krylov    Algorithm 1 (flexible shifted FOM/GMRES) with exact shift-and-invert
+          preconditioners, and the preconditioner schedule of Section 3
 """
 from .fv import assemble, point_weights
 from .contour import talbot_nodes, talbot_full
 from .heads import heads, shifted_fields
 from .jacobian import jacobian
+from .krylov import flexible_shifted, shift_invert, tau_schedule
 
 __all__ = ["assemble", "point_weights", "talbot_nodes", "talbot_full", "heads",
-           "shifted_fields", "jacobian"]
+           "shifted_fields", "jacobian", "flexible_shifted", "shift_invert", "tau_schedule"]
