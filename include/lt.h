@@ -52,7 +52,7 @@ enum {
 enum { LT_BC_DIRICHLET0 = 0, LT_BC_NEUMANN0 = 1, LT_BC_WATER_TABLE = 2 };
 enum { LT_PREC_FP64 = 0, LT_PREC_MIXED = 1 };   /* V-cycle in FP64 or FP32   */
 enum { LT_PROF_OFF = 0, LT_PROF_PRE_FINE = 1, LT_PROF_POST_FINE = 2, LT_PROF_SWEEP3D = 3 };
-enum { LT_PRECOND_GMG = 0, LT_PRECOND_UNET_GMG = 1 };
+enum { LT_PRECOND_GMG = 0, LT_PRECOND_UNET_GMG = 1, LT_PRECOND_EXACT = 2 };
 enum { LT_METHOD_GMRES = 0, LT_METHOD_FOM = 1 };
 enum { LT_CONV_WEIGHTED = 0, LT_CONV_RELATIVE = 1 };
 
@@ -133,7 +133,10 @@ typedef struct {
  *              (1: the node of smallest non-negative real part; 2: that node
  *              three times, then the node of largest real part twice, repeated
  *              (the rule of Section 3); 3: smallest, median-|z| and largest
- *              real part in turn).  Ignored when tau_reim is given.
+ *              real part in turn).  With LT_PRECOND_EXACT the candidates are
+ *              all nodes, so the smallest real part may be negative, as in the
+ *              paper's schedule (n_tau 1 is then its 'Single' solver, 2 its
+ *              'Flexible' one, Section 4.1).  Ignored when tau_reim is given.
  *   tau_reim   optional host array [2 n_tau] of explicit shifts (re, im),
  *              used cyclically.
  *   nu1, nu2   red-black Gauss-Seidel sweeps before / after coarse correction.
@@ -150,7 +153,14 @@ typedef struct {
  *              bytes (reported in lt_stats.prof_*); LT_PROF_SWEEP3D: the same
  *              for every one-colour Gauss-Seidel half-sweep on the fine grid
  *              of a 3D grid.
- *   precond    LT_PRECOND_GMG: V-cycle refinement only.  LT_PRECOND_UNET_GMG:
+ *   precond    LT_PRECOND_EXACT: each u_j = (K + tau_j M)^{-1} v_j is applied
+ *              exactly (to rounding) by a factorisation of K + tau_j M made once
+ *              per shift and kept on the handle (lt_shift_invert; the
+ *              factorised shift-and-invert preconditioner of Section 3, so
+ *              Algorithm 1 runs as printed, with no inner iteration).  FP64
+ *              whatever `precision` says; nu1, nu2, inner_max, relax and graph
+ *              are not used.  Limits are those of lt_shift_invert.
+ *              LT_PRECOND_GMG: V-cycle refinement only.  LT_PRECOND_UNET_GMG:
  *              preconditioner solves start from the attached network's guess
  *              (lt_unet_attach, 2D grids whose nx is a multiple of 128 and ny of
  *              8).  The network is first tried on one right-hand side (a batch
@@ -219,6 +229,9 @@ typedef struct {
     double prof_bytes;           /* their summed algorithmic bytes            */
     int resolves;                /* right-hand sides solved again because their
                                     weighted true residual missed tol          */
+    int factorizations;          /* shifts factorised by this call (LT_PRECOND_EXACT;
+                                    cached ones are reused, not counted)       */
+    double factor_ms;            /* host wall time of those factorisations, ms */
 } lt_stats;
 
 void lt_opts_default(lt_opts* o);
@@ -405,6 +418,24 @@ void lt_unet_destroy(lt_unet* u);
  * tol is not reached. */
 int lt_precond_solve(lt_handle* h, double tau_re, double tau_im, int nvec, const double* r, double* e, double tol,
                      int maxcycles);
+
+/* x = (K + tau M)^{-1} b exactly (to FP64 rounding) for nvec complex device
+ * vectors b, x [nvec][2][N]: the factorised shift-and-invert preconditioner
+ * of Section 3 (eqn for (K + z_k M)(K + tau M)^{-1}), the one LT_PRECOND_EXACT
+ * applies.  The first call for a shift factorises K + tau M (block cyclic
+ * reduction over the slices of the grid's last axis: rows of nx cells in 2D,
+ * planes of nx ny cells in 3D; dense nb x nb complex blocks, about
+ * 2 n nb^2 x 16 bytes of device memory for n slices of nb cells) and keeps
+ * the factorisation on the handle (the last 4 shifts used); later calls with
+ * the same shift only solve.  x must not overlap b.  No pivoting is done, so
+ * the shift must be one for which none is needed: Im tau != 0 (the Hermitian
+ * part of -i sign(Im tau) (K + tau M) is then definite), or real tau > 0, or
+ * tau = 0 on a grid with a zero-head wall.  Errors: LT_EINVAL for nvec < 1
+ * or > 1000, x overlapping b, any other shift, a slice of more than 1024
+ * cells or more than 65535 slices, or a zero or non-finite pivot met on the way; LT_ENOMEM when the
+ * factorisation does not fit.  Synchronises the handle's stream after a
+ * factorisation, not after a solve. */
+int lt_shift_invert(lt_handle* h, double tau_re, double tau_im, int nvec, const double* b, double* x);
 
 /* ---- tile-shape autotuner ----------------------------------------------
  * The fused 2D smoothing kernels (fine and intermediate multigrid levels of

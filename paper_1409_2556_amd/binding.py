@@ -23,7 +23,7 @@ LT_OK, LT_EINVAL, LT_EHIP, LT_ENOMEM, LT_EUNSUPPORTED, LT_WNOTCONV = 0, -1, -2, 
 LT_BC_DIRICHLET0, LT_BC_NEUMANN0, LT_BC_WATER_TABLE = 0, 1, 2
 LT_PREC_FP64, LT_PREC_MIXED = 0, 1
 LT_PROF_OFF, LT_PROF_PRE_FINE, LT_PROF_POST_FINE, LT_PROF_SWEEP3D = 0, 1, 2, 3
-LT_PRECOND_GMG, LT_PRECOND_UNET_GMG = 0, 1
+LT_PRECOND_GMG, LT_PRECOND_UNET_GMG, LT_PRECOND_EXACT = 0, 1, 2
 LT_METHOD_GMRES, LT_METHOD_FOM = 0, 1
 LT_CONV_WEIGHTED, LT_CONV_RELATIVE = 0, 1
 
@@ -62,7 +62,7 @@ class lt_stats(C.Structure):
                 ("iters_per_rhs", C.POINTER(C.c_int)), ("true_relres", C.POINTER(C.c_double)),
                 ("net_applied", C.c_int), ("net_rejected", C.c_int), ("net_disabled_at", C.c_int),
                 ("prof_launches", C.c_int), ("prof_ms", C.c_double), ("prof_bytes", C.c_double),
-                ("resolves", C.c_int)]
+                ("resolves", C.c_int), ("factorizations", C.c_int), ("factor_ms", C.c_double)]
 
 
 _vp = C.c_void_p
@@ -111,6 +111,8 @@ _lib.lt_vcycle.argtypes = [_h, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int
 _lib.lt_vcycle.restype = C.c_int
 _lib.lt_vcycle_noalloc.argtypes = [_h, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int]
 _lib.lt_vcycle_noalloc.restype = C.c_int
+_lib.lt_shift_invert.argtypes = [_h, C.c_double, C.c_double, C.c_int, _vp, _vp]
+_lib.lt_shift_invert.restype = C.c_int
 _lib.lt_krylov_basis.argtypes = [_h, C.c_int, C.c_int, _dp, _dp, _dp, C.POINTER(C.c_int)]
 _lib.lt_krylov_basis.restype = C.c_int
 _lib.lt_level_shape.argtypes = [_h, C.c_int, C.POINTER(C.c_int)]
@@ -264,7 +266,7 @@ def _stats_dict(st, it, tr, rc, nrhs, nshift):
             "net_applied": st.net_applied, "net_rejected": st.net_rejected,
             "net_disabled_at": st.net_disabled_at,
             "prof_launches": st.prof_launches, "prof_ms": st.prof_ms, "prof_bytes": st.prof_bytes,
-            "resolves": st.resolves}
+            "resolves": st.resolves, "factorizations": st.factorizations, "factor_ms": st.factor_ms}
 
 
 def lt_solve(handle: Handle, sources, q, times, nz, receivers, opts: lt_opts | None = None, phi_out=None,
@@ -429,6 +431,13 @@ def lt_vcycle_noalloc(handle: Handle, tau, precision, nu1, nu2, b, x, nvec):
     tau = complex(tau)
     return _check(_lib.lt_vcycle_noalloc(handle.ptr, tau.real, tau.imag, int(precision), int(nu1), int(nu2),
                                          _dev_f64(b, "b"), _dev_f64(x, "x"), int(nvec)))
+
+
+def lt_shift_invert(handle: Handle, tau, b, x, nvec):
+    """x = (K + tau M)^{-1} b for nvec complex vectors [nvec][2][N] (float64 CUDA tensors)."""
+    tau = complex(tau)
+    return _check(_lib.lt_shift_invert(handle.ptr, tau.real, tau.imag, int(nvec), _dev_f64(b, "b"),
+                                       _dev_f64(x, "x")))
 
 
 def lt_krylov_basis(handle: Handle, rhs):

@@ -74,6 +74,7 @@ lt_handle::~lt_handle() {
     for (auto& kv : ws) kv.second.release();
     kappa.release();
     mstor.release();
+    for (lt::ExactFactor& f : exact_cache) f.release();
     if (pinned) (void)hipHostFree(pinned);
     for (hipEvent_t e : prof_events) (void)hipEventDestroy(e);
 }
@@ -110,7 +111,8 @@ int validate_opts(const lt_opts* o) {
     if (!o) return 0;
     if (!(o->tol > 0.0) || o->maxit < 1 || o->maxit > 2000 || o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 ||
         o->inner_max < 1 || !(o->relax > 0.0) || o->profile < 0 || o->profile > LT_PROF_SWEEP3D ||
-        (o->precond != LT_PRECOND_GMG && o->precond != LT_PRECOND_UNET_GMG) || !(o->net_keep >= 0.0) ||
+        (o->precond != LT_PRECOND_GMG && o->precond != LT_PRECOND_UNET_GMG && o->precond != LT_PRECOND_EXACT) ||
+        !(o->net_keep >= 0.0) ||
         (o->graph != 0 && o->graph != 1) || (o->method != LT_METHOD_GMRES && o->method != LT_METHOD_FOM) ||
         (o->conv != LT_CONV_WEIGHTED && o->conv != LT_CONV_RELATIVE) ||
         (o->precision != LT_PREC_FP64 && o->precision != LT_PREC_MIXED)) {
@@ -416,14 +418,49 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int rini
     int j = 0;
     int inner_guess = 2;
     const bool debug = std::getenv("LT_DEBUG") != nullptr;
+    const bool exact = o.precond == LT_PRECOND_EXACT;
+    if (exact) {
+        // factorise every shift of the schedule up front (each once; cached on the handle)
+        for (size_t i = 0; i < plan.tau_sched.size() && i < (size_t)kExactCache; ++i) {
+            exact_factor(h, plan.tau_sched[i], &rc);
+            if (rc < 0) return rc;
+        }
+    }
     out->converged = false;
     for (j = 0; j < jmax; ++j) {
         cdouble tau = plan.tau_sched[j % plan.tau_sched.size()];
-        // inner refinement of u_j ~ (K + tau M)^{-1} v_j
         LT_TRY(launch_iter_begin(st, R, active, inner_active, count, j, rprev));  // jdev = count + 3
         double* uj = U + (size_t)j * N2;
         double* vj = Q + (size_t)j * N2;
         const double* vscale = j > 0 ? scale : nullptr;  // v_j is normalised by its first read
+        if (exact) {
+            // stop as soon as the last least-squares update converged every shift
+            if (j > 0) {
+                LT_HIP(hipMemcpyAsync(hact, active, R * sizeof(int), hipMemcpyDeviceToHost, st));
+                LT_HIP(hipStreamSynchronize(st));
+                n_active = 0;
+                for (int r = 0; r < R; ++r) n_active += hact[r];
+                if (n_active == 0) {
+                    out->converged = true;
+                    break;
+                }
+            }
+            // u_j = (K + tau_j M)^{-1} v_j by the factorisation of tau_j: the Arnoldi relation
+            // of the flexible method then holds to rounding, with no inner iteration
+            const ExactFactor* F = exact_factor(h, tau, &rc);
+            if (!F) return rc;
+            LT_TRY(launch_inner_init<double>(st, N, R, qstride, vj, uj, ustride, rho, (double*)nullptr, active,
+                                             vscale, 0, 0));
+            LT_TRY(exact_apply(h, F, R, rho, N2, uj, ustride, active));
+            LT_TRY(launch_cgs2(st, N, R, j, m, U, ustride, Q, qstride, H, hstride, hrstride, part, pstride, c1, c2,
+                               cstride, scale, partn, active));
+            if (np > 0)
+                LT_TRY(launch_gather(st, R, N, np, rec->off, rec->cell, rec->wt, U, ustride, j, G, jmax, active));
+            LT_TRY(launch_ls_update(st, R, Ks, j, tau, zs, omega, rinit, o.tol, o.method == LT_METHOD_FOM, H, hstride,
+                                    hrstride, beta, ls, active, mcols, worst, conv));
+            continue;
+        }
+        // inner refinement of u_j ~ (K + tau M)^{-1} v_j
         if (mixed)
             LT_TRY(launch_inner_init<float>(st, N, R, qstride, vj, uj, ustride, rho, lo32, active, vscale,
                                             h->cp3d ? h->grid.n[0] : 0, h->grid.n[1]));
@@ -687,9 +724,11 @@ int prof_finish(lt_handle* h, lt_stats* s) {
     return 0;
 }
 
-void fill_stats(lt_stats* s, const KrylovOut& k, int nlev, double secs, int resolves) {
+void fill_stats(lt_stats* s, const KrylovOut& k, int nlev, double secs, int resolves, const lt_handle* h) {
     if (!s) return;
     s->resolves = resolves;
+    s->factorizations = h->exact_factorizations;
+    s->factor_ms = h->exact_factor_ms;
     s->n_rhs = k.R;
     s->n_shifts = k.Ks;
     s->iters_max = k.iters_max;
@@ -1014,6 +1053,8 @@ int lt_solve(lt_handle* h, const lt_sources* src, const double* times, int ntime
     if (src->phi0) LT_TRY(launch_mass_rhs(h->stream, h->N, h->levels[0].v64().m, src->phi0, b + (size_t)ns * N2));
     KrylovOut k;
     k.b = b;
+    h->exact_factorizations = 0;
+    h->exact_factor_ms = 0.0;
     LT_TRY(prof_start(h, o.profile));
     int resolves = 0;
     bool ok = false;
@@ -1025,7 +1066,7 @@ int lt_solve(lt_handle* h, const lt_sources* src, const double* times, int ntime
         LT_HIP(hipMemcpy(stats->iters_per_rhs, k.mcols, R * sizeof(int), hipMemcpyDeviceToHost));
     LT_TRY(prof_finish(h, stats));
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    fill_stats(stats, k, (int)h->levels.size(), secs, resolves);
+    fill_stats(stats, k, (int)h->levels.size(), secs, resolves, h);
     return ok ? LT_OK : LT_WNOTCONV;
 }
 
@@ -1079,6 +1120,8 @@ int lt_adjoint(lt_handle* h, const lt_sources* src, const lt_points* receivers, 
     LT_TRY(launch_scatter_points(h->stream, R, h->N, da.off, da.cell, da.wt, b));
     KrylovOut k;
     k.b = b;
+    h->exact_factorizations = 0;
+    h->exact_factor_ms = 0.0;
     LT_TRY(prof_start(h, o.profile));
     int resolves = 0;
     bool ok = false;
@@ -1099,7 +1142,7 @@ int lt_adjoint(lt_handle* h, const lt_sources* src, const lt_points* receivers, 
         LT_HIP(hipMemcpy(stats->iters_per_rhs, k.mcols, R * sizeof(int), hipMemcpyDeviceToHost));
     LT_TRY(prof_finish(h, stats));
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    fill_stats(stats, k, (int)h->levels.size(), secs, resolves);
+    fill_stats(stats, k, (int)h->levels.size(), secs, resolves, h);
     return ok ? LT_OK : LT_WNOTCONV;
 }
 
@@ -1247,6 +1290,23 @@ int lt_precond_solve(lt_handle* h, double tau_re, double tau_im, int nvec, const
         if (done) return LT_OK;
     }
     return LT_WNOTCONV;
+}
+
+int lt_shift_invert(lt_handle* h, double tau_re, double tau_im, int nvec, const double* b, double* x) {
+    if (!h || !b || !x || nvec < 1 || nvec > kMaxRhs) {
+        set_last_error("lt_shift_invert: bad argument");
+        return LT_EINVAL;
+    }
+    const size_t bytes = (size_t)nvec * 2 * (size_t)h->N * sizeof(double);
+    const uintptr_t pb = (uintptr_t)b, px = (uintptr_t)x;
+    if (pb < px + bytes && px < pb + bytes) {
+        set_last_error("lt_shift_invert: x overlaps b");
+        return LT_EINVAL;
+    }
+    int rc = 0;
+    const ExactFactor* F = exact_factor(h, cdouble(tau_re, tau_im), &rc);
+    if (!F) return rc;
+    return exact_apply(h, F, nvec, b, 2 * (size_t)h->N, x, 2 * (size_t)h->N);
 }
 
 

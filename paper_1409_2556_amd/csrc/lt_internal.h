@@ -79,6 +79,24 @@ struct CoarseInverse {
     DevBuf inv64, inv32;  // [N][N] complex (interleaved re, im), row-major
 };
 
+// Exact (K + tau M)^{-1} by block cyclic reduction over the slices of the last axis
+// (exact.hip).  Level l has nl[l] blocks; its odd-positioned ones are eliminated with
+// their inverses Dinv (slots dinv[l] ...) and, above level 0, P = Dinv F_{i-1}^T and
+// Q = Dinv F_i (slots pm[l] ..., qm[l] ...); the last level has one block (slot dinv[top]).
+constexpr int kExactMaxBlock = 1024;  // cells per slice
+constexpr int kExactCache = 4;        // factorised shifts kept per handle
+struct ExactFactor {
+    bool valid = false;
+    cdouble tau;
+    int nb = 0, n = 0;    // cells per slice, slices
+    size_t ms = 0;        // doubles per dense block ([2][nb][nb])
+    std::vector<int> nl;
+    std::vector<size_t> dinv, pm, qm;
+    DevBuf mats;
+    unsigned long long tick = 0;
+    void release();
+};
+
 }  // namespace lt
 
 struct lt_handle {
@@ -117,6 +135,12 @@ struct lt_handle {
     bool arena_plan = false;
     lt::CoarseInverse arena_ci;       // coarse inverse built in the arena (not owned)
     int last_R = 0, last_jmax = 0;  // shape of the basis the last solve left in the workspaces
+    // factorised shifts of the exact preconditioner (capacity reserved up front, so entries
+    // never move), their use counter, and factorisations / milliseconds since the last reset
+    std::vector<lt::ExactFactor> exact_cache;
+    unsigned long long exact_tick = 0;
+    int exact_factorizations = 0;
+    double exact_factor_ms = 0.0;
     // profiling of one kernel family (opts.profile): event pairs and a byte counter
     int prof_target = 0;
     std::vector<hipEvent_t> prof_events;
@@ -183,6 +207,20 @@ int vcycle_call(lt_handle* h, cdouble tau, int precision, int nu1, int nu2, cons
 // device, taken once per device at setup (noalloc.hip)
 int noalloc_init_device(int device);
 void* noalloc_scratch(int device, size_t* bytes);
+
+// ------------------------------------------------------------- exact preconditioner
+// slice shape: nb cells per slice of the last axis, n slices
+int exact_slices(const lt_handle* h, int* nb, int* n);
+// the factorisation of K + tau M (cached per handle; the least recently used of
+// kExactCache entries is replaced); synchronises the stream once
+const ExactFactor* exact_factor(lt_handle* h, cdouble tau, int* rc);
+// x = (K + tau M)^{-1} b for R complex vectors (right-hand side r at b + r brs, planes N
+// apart; likewise x); enqueued on the handle's stream.  active (device [R] or nullptr):
+// x of a right-hand side marked 0 is left untouched
+int exact_apply(lt_handle* h, const ExactFactor* F, int R, const double* b, size_t brs, double* x, size_t xrs,
+                const int* active = nullptr);
+// bytes of dense blocks one exact_apply reads
+size_t exact_matrix_bytes(const ExactFactor* F);
 
 // ------------------------------------------------------------- multigrid
 int mg_build(lt_handle* h, const double* kappa, const double* S);

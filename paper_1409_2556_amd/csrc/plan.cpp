@@ -82,12 +82,15 @@ int make_plan(const double* times, int ntimes, int nz, double q, const lt_opts* 
         for (int i = 0; i < o->n_tau; ++i) p->tau_sched.emplace_back(o->tau_reim[2 * i], o->tau_reim[2 * i + 1]);
         return 0;
     }
-    // Candidates: contour nodes with Re z >= 0.  A V-cycle needs K + tau M with a
-    // non-negative real shift; the paper's rule (Section 3) takes the nodes of
-    // smallest and largest real part, here restricted to that half plane.
+    // Candidates: the rule of Section 3 takes the contour nodes of smallest and largest
+    // real part over every time.  A V-cycle needs K + tau M with a non-negative real
+    // shift, so for the multigrid preconditioners the candidates are restricted to that
+    // half plane; the exact factorisation takes every node (the smallest real part is
+    // then negative, with Im z != 0).
+    const bool any_half_plane = o->precond == LT_PRECOND_EXACT;
     std::vector<cdouble> cand;
     for (const cdouble& z : p->z)
-        if (z.real() >= 0.0) cand.push_back(z);
+        if (any_half_plane || z.real() >= 0.0) cand.push_back(z);
     if (cand.empty()) cand.push_back(cdouble(0.0, 0.0));
     auto lessre = [](const cdouble& a, const cdouble& b) { return a.real() < b.real(); };
     cdouble t1 = *std::min_element(cand.begin(), cand.end(), lessre);
