@@ -23,7 +23,9 @@ paying for themselves, the V-cycle the fallback (3D problems: V-cycle only).
 The headline value is the learned variant.
 
 --workload C2 times the 256x256 heads workload (lt_solve), C3 the 64x64x32
-sensitivities (lt_adjoint), C5 the six grids' heads (lt_solve_batch).
+sensitivities (lt_adjoint), C5 the six grids' heads (lt_solve_batch), EXACT the
+single-well test of Section 4.1 with the exact shift-and-invert preconditioner
+('Single' and 'Flexible' over the variances, times and grid sizes of Tables 1-3).
 """
 from __future__ import annotations
 
@@ -81,10 +83,11 @@ def _parse():
     ap.add_argument("--no-tune", action="store_true", help="keep the default smoother tile shapes")
     ap.add_argument("--groups", type=int, default=2,
                     help="solve the sources as this many concurrent groups, one handle and stream each")
-    ap.add_argument("--workload", choices=["C5J", "C2", "C3", "C5"], default="C5J",
+    ap.add_argument("--workload", choices=["C5J", "C2", "C3", "C5", "EXACT"], default="C5J",
                     help="C5J (default): the six Jacobian-assembly problems in one lt_adjoint_batch call; "
                          "C2: the 256x256 heads workload; C3: sensitivities (lt_adjoint) of the "
-                         "64x64x32 workload; C5: the six grids' heads in one lt_solve_batch call")
+                         "64x64x32 workload; C5: the six grids' heads in one lt_solve_batch call; "
+                         "EXACT: the single-well test with the exact shift-and-invert preconditioner")
     ap.add_argument("--tol-jacobian", type=float, default=3e-10,
                     help="C5J: weighted tolerance of every variant (equal accuracy)")
     ap.add_argument("--relax-jacobian", type=float, default=0.3,
@@ -218,6 +221,8 @@ def main():
         sys.exit(2)
     if args.workload == "C5J":
         return main_jacobian(args)
+    if args.workload == "EXACT":
+        return main_exact(args)
     if args.workload == "C5":
         return main_batch(args)
     if args.workload == "C3":
@@ -746,6 +751,139 @@ def main_batch(args):
     print(json.dumps(out), flush=True)
     for h in hs:
         h.close()
+
+
+def _exact_problem(wl, var=1.6, n=(128, 128), t=0.3, wells=None):
+    """The single-well test (W1: one well at the centre, receivers at (0.7, 0.7) and its mirror
+    images, 40-node contour) with the given variance, grid and time (diffusion times)."""
+    from dataclasses import replace
+    p = wl.make_problem("W1", n=n, var=var)
+    p = replace(p, times=np.array([t]) * wl.configs.T_D)
+    if wells is not None:
+        p = replace(p, sources=wells)
+    return p
+
+
+def main_exact(args):
+    """Section 4.1's single-well test with the exact shift-and-invert preconditioner: per case, the
+    'Single' solver (tau_bar_1, the contour node of smallest real part) and the 'Flexible' one
+    (tau_bar_1 three times, tau_bar_2 (largest real part) twice, repeated), relative tolerance
+    1e-10.  One step is one lt_solve with the factorisations of the schedule's shifts cached on the
+    handle (their time, on the first call, is reported separately as factor_ms)."""
+    import workloads as wl
+    import workloads.configs  # noqa: F401  (T_D)
+    tol = 1e-10
+    head_p = _exact_problem(wl)
+    nshift = head_p.nz_contour // 2
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle.contour import talbot_nodes
+        from oracle.fv import assemble, point_weights
+        from oracle.krylov import flexible_shifted, tau_schedule
+        try:
+            from threadpoolctl import threadpool_limits
+            threadpool_limits(1)
+        except Exception:
+            pass
+        K, m = assemble(head_p.n, head_p.h, head_p.kappa, head_p.S)
+        b = point_weights(head_p.n, head_p.h, head_p.sources).toarray()[0]
+        z = talbot_nodes(head_p.nz_contour, head_p.times[0])[0]
+        reps, t0 = 0, time.perf_counter()
+        while reps < 3 or time.perf_counter() - t0 < 10.0:
+            out = flexible_shifted(K, m, b, tau_schedule(z, 2), z, tol, 400)
+            reps += 1
+        dt = (time.perf_counter() - t0) / reps
+        cpu = {"value": nshift / dt, "unit": "shifted solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"the oracle's Algorithm 1 (SuperLU per preconditioner shift, 'Flexible' schedule) on "
+                         f"the headline case: 1 well x {nshift} shifts, {out['iters']} iterations, "
+                         f"{reps} repetitions ({dt * reps:.1f} s)"}
+        print(f"[bench] oracle Algorithm 1: {cpu['value']:.2f} solves/s ({dt * 1e3:.0f} ms/solve)", file=sys.stderr,
+              flush=True)
+    import torch
+    from paper_1409_2556_amd import binding as lt
+    from oracle.heads import heads_problem
+    torch.cuda.set_device(0)
+
+    def handle(p):
+        kap = torch.tensor(p.kappa, dtype=torch.float64, device="cuda")
+        S = torch.tensor(p.S, dtype=torch.float64, device="cuda")
+        return lt.lt_setup(p.ndim, p.n, p.h, kap, S, bc=p.bc, sy=p.sy)
+
+    def run(p, n_tau, check=False, profile=0):
+        h = handle(p)
+        o = lt.make_opts(tol=tol, maxit=400, n_tau=n_tau, precond=lt.LT_PRECOND_EXACT, conv=lt.LT_CONV_RELATIVE)
+        phi, st0 = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, o)
+        for _ in range(args.warmup):
+            lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            phi, st = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, o)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        r = {"iters": int(st["iters_max"]), "ms": dt * 1e3, "factor_ms": st0["factor_ms"],
+             "factorizations": st0["factorizations"], "rc": st["rc"],
+             "solves_per_s": len(p.sources) * nshift / dt, "true_relres_max": st["true_relres_max"]}
+        if check:
+            ref = heads_problem(p)
+            got = phi.cpu().numpy()
+            r["rel_head_err"] = float((np.abs(got - ref).max(axis=(1, 2)) / np.abs(ref).max(axis=(1, 2))).max())
+        if profile:
+            op = lt.make_opts(tol=tol, maxit=400, n_tau=n_tau, precond=lt.LT_PRECOND_EXACT,
+                              conv=lt.LT_CONV_RELATIVE, profile=profile)
+            _, sp_ = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, op)
+            r["prof"] = {"launches": sp_["prof_launches"], "ms": sp_["prof_ms"], "bytes": sp_["prof_bytes"]}
+        h.close()
+        return r
+
+    tables = {"variance_128": {}, "time_128_var1.6": {}, "grid_var1.6": {}}
+    for var in (0.8, 1.6, 3.5):
+        p = _exact_problem(wl, var=var)
+        tables["variance_128"][str(var)] = {s: run(p, nt, check=True) for s, nt in (("single", 1), ("flexible", 2))}
+        print(f"[bench] EXACT var {var}: {tables['variance_128'][str(var)]}", file=sys.stderr, flush=True)
+    for t in (0.06, 1.2):
+        p = _exact_problem(wl, t=t)
+        tables["time_128_var1.6"][str(t)] = {s: run(p, nt, check=True) for s, nt in (("single", 1), ("flexible", 2))}
+        print(f"[bench] EXACT t {t}: {tables['time_128_var1.6'][str(t)]}", file=sys.stderr, flush=True)
+    for n in (64, 256, 512):
+        p = _exact_problem(wl, n=(n, n))
+        tables["grid_var1.6"][f"{n}^2"] = {s: run(p, nt) for s, nt in (("single", 1), ("flexible", 2))}
+        print(f"[bench] EXACT grid {n}: {tables['grid_var1.6'][f'{n}^2']}", file=sys.stderr, flush=True)
+    head = run(head_p, 2, check=True, profile=lt.LT_PROF_EXACT)
+    wells = np.asarray(wl.configs._C2_WELLS, dtype=np.float64)
+    multi = run(_exact_problem(wl, wells=wells), 2, check=True, profile=lt.LT_PROF_EXACT)
+    print(f"[bench] EXACT headline {head}\n[bench] EXACT 16 wells {multi}", file=sys.stderr, flush=True)
+
+    def roof(r, what):
+        pr = r["prof"]
+        avg = pr["ms"] / max(pr["launches"], 1) * 1e-3
+        per = pr["bytes"] / max(pr["launches"], 1)
+        ach = per / avg / 1e9 if avg > 0 else 0.0
+        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": None, "kernel": f"k_ex_solve (dense block products of the exact solve, {what})",
+                "avg_launch_us": avg * 1e6, "bytes_per_launch": per, "launches": pr["launches"]}
+
+    valid = head["rc"] == 0 and head["rel_head_err"] <= 1e-5
+    out = {
+        "metric": "shifted solves/sec (RHS×shift, rel head err 1e-5): learned+mixed vs plain FGMRES",
+        "value": head["solves_per_s"] if valid else 0.0,
+        "unit": "shifted solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "single-well test of Section 4.1: 128x128 GRF (ln kappa variance 1.6, corr 0.2), "
+                               "one well at the centre, 4 receivers, the 5-minute sample (0.3 diffusion times), "
+                               "40-node Talbot (20 shifts), relative tolerance 1e-10, exact shift-and-invert "
+                               "preconditioner, 'Flexible' schedule",
+                   "precond": "exact (block cyclic reduction, factorised once per shift)",
+                   "factor_ms_per_shift": head["factor_ms"] / max(head["factorizations"], 1),
+                   "iters": head["iters"], "rel_head_err_vs_oracle": head["rel_head_err"]},
+        "tables": tables,
+        "sixteen_wells": {k: v for k, v in multi.items() if k != "prof"},
+        "roofline": roof(head, "one well"),
+        "roofline_sixteen_wells": roof(multi, "16 wells"),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -51,7 +51,7 @@ enum {
 
 enum { LT_BC_DIRICHLET0 = 0, LT_BC_NEUMANN0 = 1, LT_BC_WATER_TABLE = 2 };
 enum { LT_PREC_FP64 = 0, LT_PREC_MIXED = 1 };   /* V-cycle in FP64 or FP32   */
-enum { LT_PROF_OFF = 0, LT_PROF_PRE_FINE = 1, LT_PROF_POST_FINE = 2, LT_PROF_SWEEP3D = 3 };
+enum { LT_PROF_OFF = 0, LT_PROF_PRE_FINE = 1, LT_PROF_POST_FINE = 2, LT_PROF_SWEEP3D = 3, LT_PROF_EXACT = 4 };
 enum { LT_PRECOND_GMG = 0, LT_PRECOND_UNET_GMG = 1, LT_PRECOND_EXACT = 2 };
 enum { LT_METHOD_GMRES = 0, LT_METHOD_FOM = 1 };
 enum { LT_CONV_WEIGHTED = 0, LT_CONV_RELATIVE = 1 };
@@ -152,7 +152,10 @@ typedef struct {
  *              HIP events on the handle's stream and count its algorithmic
  *              bytes (reported in lt_stats.prof_*); LT_PROF_SWEEP3D: the same
  *              for every one-colour Gauss-Seidel half-sweep on the fine grid
- *              of a 3D grid.
+ *              of a 3D grid; LT_PROF_EXACT: every dense block-product launch
+ *              of the exact preconditioner's solves (LT_PRECOND_EXACT), whose
+ *              algorithmic bytes are the dense blocks and vector blocks it
+ *              must move.
  *   precond    LT_PRECOND_EXACT: each u_j = (K + tau_j M)^{-1} v_j is applied
  *              exactly (to rounding) by a factorisation of K + tau_j M made once
  *              per shift and kept on the handle (lt_shift_invert; the

@@ -22,7 +22,7 @@ _lib = C.CDLL(LIB_PATH)
 LT_OK, LT_EINVAL, LT_EHIP, LT_ENOMEM, LT_EUNSUPPORTED, LT_WNOTCONV = 0, -1, -2, -3, -4, 1
 LT_BC_DIRICHLET0, LT_BC_NEUMANN0, LT_BC_WATER_TABLE = 0, 1, 2
 LT_PREC_FP64, LT_PREC_MIXED = 0, 1
-LT_PROF_OFF, LT_PROF_PRE_FINE, LT_PROF_POST_FINE, LT_PROF_SWEEP3D = 0, 1, 2, 3
+LT_PROF_OFF, LT_PROF_PRE_FINE, LT_PROF_POST_FINE, LT_PROF_SWEEP3D, LT_PROF_EXACT = 0, 1, 2, 3, 4
 LT_PRECOND_GMG, LT_PRECOND_UNET_GMG, LT_PRECOND_EXACT = 0, 1, 2
 LT_METHOD_GMRES, LT_METHOD_FOM = 0, 1
 LT_CONV_WEIGHTED, LT_CONV_RELATIVE = 0, 1

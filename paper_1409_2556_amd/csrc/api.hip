@@ -110,7 +110,7 @@ int upload_points(lt_handle* h, const PointsCSR& c, const char* tag, DevPoints* 
 int validate_opts(const lt_opts* o) {
     if (!o) return 0;
     if (!(o->tol > 0.0) || o->maxit < 1 || o->maxit > 2000 || o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 ||
-        o->inner_max < 1 || !(o->relax > 0.0) || o->profile < 0 || o->profile > LT_PROF_SWEEP3D ||
+        o->inner_max < 1 || !(o->relax > 0.0) || o->profile < 0 || o->profile > LT_PROF_EXACT ||
         (o->precond != LT_PRECOND_GMG && o->precond != LT_PRECOND_UNET_GMG && o->precond != LT_PRECOND_EXACT) ||
         !(o->net_keep >= 0.0) ||
         (o->graph != 0 && o->graph != 1) || (o->method != LT_METHOD_GMRES && o->method != LT_METHOD_FOM) ||
@@ -693,6 +693,7 @@ int solve_checked(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int r
 int prof_start(lt_handle* h, int target) {
     h->prof_target = target;
     h->prof_used = 0;
+    h->prof_host_bytes = 0.0;
     if (!target) return 0;
     int rc = 0;
     h->prof_counter = wsp<unsigned long long>(h, "prof_counter", 1, &rc);
@@ -718,7 +719,7 @@ int prof_finish(lt_handle* h, lt_stats* s) {
     if (s) {
         s->prof_launches = h->prof_used / 2;
         s->prof_ms = ms;
-        s->prof_bytes = (double)bytes;
+        s->prof_bytes = (double)bytes + h->prof_host_bytes;
     }
     h->prof_target = 0;
     return 0;

@@ -26,6 +26,8 @@
 // row-major).  Vectors of the caller are [R][2][N] (slice q of right-hand side r, plane c at
 // r * rstride + c * N + q * nb); reduced right-hand sides and partial solutions of the
 // levels are [block][R][2][nb] workspaces.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -38,9 +40,6 @@ namespace {
 
 constexpr int kGJW = 16;   // Gauss-Jordan panel width
 constexpr int kGJTI = 16;  // rows per workgroup of the Gauss-Jordan update
-constexpr int kBA = 64;    // output rows per workgroup of a block product (solve)
-constexpr int kBR = 16;    // right-hand sides per workgroup of a block product
-constexpr int kBK = 32;    // inner-dimension chunk of a block product
 constexpr int kGT = 64;    // GEMM output tile
 constexpr int kGK = 16;    // GEMM inner chunk
 
@@ -178,9 +177,10 @@ __global__ __launch_bounds__(256) void k_gj_panel(double* __restrict__ mats, siz
         if (c >= k0 && c < k0 + w) continue;
         double xr[kGJW], xi[kGJW];
 #pragma unroll
-        for (int t = 0; t < kGJW; ++t) {
-            xr[t] = t < w ? Ar[(size_t)(k0 + t) * nb + c] : 0.0;
-            xi[t] = t < w ? Ai[(size_t)(k0 + t) * nb + c] : 0.0;
+        for (int t = 0; t < kGJW; ++t) {  // rows past w read row k0 (P^{-1} is zero there)
+            const size_t o = (size_t)(k0 + (t < w ? t : 0)) * nb + c;
+            xr[t] = Ar[o];
+            xi[t] = Ai[o];
         }
 #pragma unroll 1
         for (int t = 0; t < w; ++t) {
@@ -218,23 +218,35 @@ __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ mats, si
     __syncthreads();
     for (int c = tid; c < nb; c += 256) {
         if (c >= k0 && c < k0 + w) continue;
-        double rr[kGJW], ri[kGJW];
+        // keep the reads of C from LDS inside the loop (hoisted, 512 values would not fit in registers)
+        asm volatile("" ::: "memory");
+        // every load first (clamped rows; C and P^{-1} are zero past w), then the updates
+        double rr[kGJW], ri[kGJW], xr[kGJTI], xi[kGJTI];
 #pragma unroll
         for (int u = 0; u < kGJW; ++u) {
-            rr[u] = u < w ? Ar[(size_t)(k0 + u) * nb + c] : 0.0;
-            ri[u] = u < w ? Ai[(size_t)(k0 + u) * nb + c] : 0.0;
+            const size_t o = (size_t)(k0 + (u < w ? u : 0)) * nb + c;
+            rr[u] = Ar[o];
+            ri[u] = Ai[o];
         }
+#pragma unroll
+        for (int r = 0; r < kGJTI; ++r) {
+            const size_t o = (size_t)min(i0 + r, nb - 1) * nb + c;
+            xr[r] = Ar[o];
+            xi[r] = Ai[o];
+        }
+#pragma unroll
         for (int r = 0; r < kGJTI; ++r) {
             const int row = i0 + r;
-            if (row >= nb || (row >= k0 && row < k0 + w)) continue;
             double sr = 0.0, si = 0.0;
 #pragma unroll
             for (int u = 0; u < kGJW; ++u) {
                 sr += cr[r][u] * rr[u] - ci[r][u] * ri[u];
                 si += cr[r][u] * ri[u] + ci[r][u] * rr[u];
             }
-            Ar[(size_t)row * nb + c] -= sr;
-            Ai[(size_t)row * nb + c] -= si;
+            if (row < nb && !(row >= k0 && row < k0 + w)) {
+                Ar[(size_t)row * nb + c] = xr[r] - sr;
+                Ai[(size_t)row * nb + c] = xi[r] - si;
+            }
         }
     }
     {
@@ -270,47 +282,47 @@ __global__ __launch_bounds__(256) void k_ex_gemm(int nb, double alpha, double be
     __shared__ double asr[kGK][kGT + 1], asi[kGK][kGT + 1], bsr[kGK][kGT + 1], bsi[kGK][kGT + 1];
     const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
     double accr[4][4] = {}, acci[4][4] = {};
+    // this thread's tile entries: (row, k) of op(A) and (k, col) of op(B) for q < 4
+    constexpr int Q = kGT * kGK / 256;
+    int arow[Q], ak[Q], bk[Q], bcol[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int idx = tid + 256 * q;
+        arow[q] = TA ? idx % kGT : idx / kGK;
+        ak[q] = TA ? idx / kGT : idx % kGK;
+        bcol[q] = TB ? idx / kGK : idx % kGT;
+        bk[q] = TB ? idx % kGK : idx / kGT;
+    }
+    double ra[Q], ia[Q], rb[Q], ib[Q];  // the next chunk, in flight during the current one
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int gr = r0 + arow[q], gk = k0 + ak[q];
+            const bool oka = gr < nb && gk < nb;
+            const size_t oa = oka ? (TA ? (size_t)gk * nb + gr : (size_t)gr * nb + gk) : 0;
+            ra[q] = Ar[oa];
+            ia[q] = Ai[oa];
+            if (!oka) ra[q] = ia[q] = 0.0;
+            const int gc = c0 + bcol[q], gkb = k0 + bk[q];
+            const bool okb = gc < nb && gkb < nb;
+            const size_t ob = okb ? (TB ? (size_t)gc * nb + gkb : (size_t)gkb * nb + gc) : 0;
+            rb[q] = Br[ob];
+            ib[q] = Bi[ob];
+            if (!okb) rb[q] = ib[q] = 0.0;
+        }
+    };
+    fetch(0);
     for (int k0 = 0; k0 < nb; k0 += kGK) {
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < kGT * kGK / 256; ++q) {
-            const int idx = tid + 256 * q;
-            int row, k;
-            if (TA) {
-                row = idx % kGT;
-                k = idx / kGT;
-            } else {
-                k = idx % kGK;
-                row = idx / kGK;
-            }
-            const int gr = r0 + row, gk = k0 + k;
-            double vr = 0.0, vi = 0.0;
-            if (gr < nb && gk < nb) {
-                const size_t o = TA ? (size_t)gk * nb + gr : (size_t)gr * nb + gk;
-                vr = Ar[o];
-                vi = Ai[o];
-            }
-            asr[k][row] = vr;
-            asi[k][row] = vi;
-            int col, kb;
-            if (TB) {
-                kb = idx % kGK;
-                col = idx / kGK;
-            } else {
-                col = idx % kGT;
-                kb = idx / kGT;
-            }
-            const int gc = c0 + col, gkb = k0 + kb;
-            double wr = 0.0, wi = 0.0;
-            if (gc < nb && gkb < nb) {
-                const size_t o = TB ? (size_t)gc * nb + gkb : (size_t)gkb * nb + gc;
-                wr = Br[o];
-                wi = Bi[o];
-            }
-            bsr[kb][col] = wr;
-            bsi[kb][col] = wi;
+        for (int q = 0; q < Q; ++q) {
+            asr[ak[q]][arow[q]] = ra[q];
+            asi[ak[q]][arow[q]] = ia[q];
+            bsr[bk[q]][bcol[q]] = rb[q];
+            bsi[bk[q]][bcol[q]] = ib[q];
         }
         __syncthreads();
+        if (k0 + kGK < nb) fetch(k0 + kGK);
 #pragma unroll 4
         for (int k = 0; k < kGK; ++k) {
             double ar[4], ai[4], br[4], bi[4];
@@ -355,12 +367,12 @@ struct ExVec {
     size_t rs, ps;
 };
 
-// One term  sign * op(S) v  of a block product; op(S) = S^T when trans is set.  When T1 is
-// given, v is replaced by v + T1 o w1 (+ T2 o w2): level 0's back substitution folds its
-// diagonal couplings into the product's input.
+// One term  sign * S^T v  of a block product, S a stored dense block read as S[k][a] (each
+// block is stored in the orientation its product needs).  When T1 is given, v is replaced by
+// v + T1 o w1 (+ T2 o w2): level 0's back substitution folds its diagonal couplings into the
+// product's input.
 struct ExTerm {
     const double* S;
-    int trans;
     double sign;
     ExVec v;
     const double* T1;
@@ -375,7 +387,7 @@ struct ExSolve {
     int mode, nb, R, n, nl;           // n: slices; nl: blocks at this level
     const double* mats;
     size_t ms;                        // doubles per dense block
-    size_t dinv, pm, qm;              // first slot of Dinv / P / Q at this level
+    size_t dinv, pm, qm, ptm, qtm;    // first slot of Dinv / P / Q / P^T / Q^T at this level
     const double* b;                  // caller's right-hand side, slice q at b + q nb
     size_t brs;
     double* x;                        // caller's solution
@@ -394,15 +406,26 @@ __device__ inline ExVec ws_vec(const double* base, size_t bs, int blk, int nb) {
     return ExVec{base + (size_t)blk * bs, 2 * (size_t)nb, (size_t)nb};
 }
 
-// y (kBA rows from a0, kBR right-hand sides from r0) = y0 + sum_t sign_t op(S_t) v_t
-__global__ __launch_bounds__(256) void k_ex_solve(ExSolve A) {
+constexpr int kExKG = 16;  // k-groups (waves) per row tile of a block product
+
+// y (64 rows from a0, NR right-hand sides from r0) = y0 + sum_t sign_t S_t^T v_t.  Thread (a, g)
+// takes row a0 + a and the inner indices k = g, g + KG, ...: per k a wave reads 64 consecutive
+// entries of row k of each plane of S (coalesced) straight from HBM, and the right-hand sides'
+// entries at k from LDS (the same address for every lane), where the workgroup stages them a
+// slice at a time.  The matrices are read once and the loads of successive k are independent;
+// 16 k-groups keep a thread's share of the inner dimension short (a few round trips to HBM).
+// The KG partial sums of a row are added through LDS at the end.
+// COMB: level 0's back substitution (the one mode whose term has couplings).
+template <bool COMB, int NR>
+__global__ __launch_bounds__(64 * kExKG) void k_ex_solve(ExSolve A) {
+    constexpr int KG = kExKG;
     const int nb = A.nb, o = blockIdx.z;
-    const int a0 = blockIdx.x * kBA, r0 = blockIdx.y * kBR;
+    const int a0 = blockIdx.x * 64, r0 = blockIdx.y * NR;
     // up to three terms at fixed positions (S == nullptr: absent), so that they stay in registers
     ExTerm terms[3];
     const ExVec none{nullptr, 0, 0};
 #pragma unroll
-    for (int t = 0; t < 3; ++t) terms[t] = ExTerm{nullptr, 0, 0.0, none, nullptr, none, nullptr, none};
+    for (int t = 0; t < 3; ++t) terms[t] = ExTerm{nullptr, 0.0, none, nullptr, none, nullptr, none};
     ExVec y0{nullptr, 0, 0};
     double* yp;
     size_t yrs, yps;
@@ -414,8 +437,8 @@ __global__ __launch_bounds__(256) void k_ex_solve(ExSolve A) {
         yp = A.Xl + (size_t)o * A.bs;
         yrs = 2 * (size_t)nb;
         yps = wps;
-        terms[0] = ExTerm{mat(A.dinv + o), 1, 1.0, ExVec{A.b + (size_t)(2 * o + 1) * nb, A.brs, A.N}, nullptr,
-                          none, nullptr, none};
+        terms[0] = ExTerm{mat(A.dinv + o), 1.0, ExVec{A.b + (size_t)(2 * o + 1) * nb, A.brs, A.N}, nullptr, none,
+                          nullptr, none};
         break;
     case kModeReduce:  // B'_o = B_{2o} - Q_{2o-1}^T B_{2o-1} - P_{2o+1}^T B_{2o+1}
         yp = A.Bn + (size_t)o * A.bs;
@@ -423,11 +446,9 @@ __global__ __launch_bounds__(256) void k_ex_solve(ExSolve A) {
         yps = wps;
         y0 = ws_vec(A.Bl, A.bs, 2 * o, nb);
         if (o >= 1)
-            terms[0] = ExTerm{mat(A.qm + o - 1), 1, -1.0, ws_vec(A.Bl, A.bs, 2 * o - 1, nb), nullptr, none, nullptr,
-                              none};
+            terms[0] = ExTerm{mat(A.qm + o - 1), -1.0, ws_vec(A.Bl, A.bs, 2 * o - 1, nb), nullptr, none, nullptr, none};
         if (2 * o + 1 < A.nl)
-            terms[1] = ExTerm{mat(A.pm + o), 1, -1.0, ws_vec(A.Bl, A.bs, 2 * o + 1, nb), nullptr, none, nullptr,
-                              none};
+            terms[1] = ExTerm{mat(A.pm + o), -1.0, ws_vec(A.Bl, A.bs, 2 * o + 1, nb), nullptr, none, nullptr, none};
         break;
     case kModeTop:  // the last block (or the only slice: caller's vectors)
         if (A.n == 1) {
@@ -435,12 +456,12 @@ __global__ __launch_bounds__(256) void k_ex_solve(ExSolve A) {
             yrs = A.xrs;
             yps = A.N;
             to_caller = true;
-            terms[0] = ExTerm{mat(A.dinv), 1, 1.0, ExVec{A.b, A.brs, A.N}, nullptr, none, nullptr, none};
+            terms[0] = ExTerm{mat(A.dinv), 1.0, ExVec{A.b, A.brs, A.N}, nullptr, none, nullptr, none};
         } else {
             yp = A.Xl;
             yrs = 2 * (size_t)nb;
             yps = wps;
-            terms[0] = ExTerm{mat(A.dinv), 1, 1.0, ws_vec(A.Bl, A.bs, 0, nb), nullptr, none, nullptr, none};
+            terms[0] = ExTerm{mat(A.dinv), 1.0, ws_vec(A.Bl, A.bs, 0, nb), nullptr, none, nullptr, none};
         }
         break;
     case kModeBack: {  // X_o = X'_{o/2} (even);  Dinv_s B_o - P_s X'_s - Q_s X'_{s+1} (odd, s = (o-1)/2)
@@ -451,10 +472,10 @@ __global__ __launch_bounds__(256) void k_ex_solve(ExSolve A) {
             y0 = ws_vec(A.Xn, A.bs, o / 2, nb);
         } else {
             const int s = (o - 1) / 2;
-            terms[0] = ExTerm{mat(A.dinv + s), 1, 1.0, ws_vec(A.Bl, A.bs, o, nb), nullptr, none, nullptr, none};
-            terms[1] = ExTerm{mat(A.pm + s), 0, -1.0, ws_vec(A.Xn, A.bs, s, nb), nullptr, none, nullptr, none};
+            terms[0] = ExTerm{mat(A.dinv + s), 1.0, ws_vec(A.Bl, A.bs, o, nb), nullptr, none, nullptr, none};
+            terms[1] = ExTerm{mat(A.ptm + s), -1.0, ws_vec(A.Xn, A.bs, s, nb), nullptr, none, nullptr, none};
             if (o + 1 < A.nl)
-                terms[2] = ExTerm{mat(A.qm + s), 0, -1.0, ws_vec(A.Xn, A.bs, s + 1, nb), nullptr, none, nullptr, none};
+                terms[2] = ExTerm{mat(A.qtm + s), -1.0, ws_vec(A.Xn, A.bs, s + 1, nb), nullptr, none, nullptr, none};
         }
         break;
     }
@@ -468,7 +489,7 @@ __global__ __launch_bounds__(256) void k_ex_solve(ExSolve A) {
         } else {
             const int s = (o - 1) / 2;
             const bool right = o + 1 < A.n;
-            terms[0] = ExTerm{mat(A.dinv + s), 1, 1.0, ExVec{A.b + (size_t)o * nb, A.brs, A.N},
+            terms[0] = ExTerm{mat(A.dinv + s), 1.0, ExVec{A.b + (size_t)o * nb, A.brs, A.N},
                               A.Tl + (size_t)(o - 1) * nb, ws_vec(A.Xn, A.bs, s, nb),
                               right ? A.Tl + (size_t)o * nb : nullptr, right ? ws_vec(A.Xn, A.bs, s + 1, nb) : none};
         }
@@ -476,95 +497,83 @@ __global__ __launch_bounds__(256) void k_ex_solve(ExSolve A) {
     }
     }
 
-    __shared__ double msr[kBK][kBA + 1], msi[kBK][kBA + 1];
-    __shared__ double2 vs[kBK][kBR];
-    const int tid = threadIdx.x, a = tid % kBA, rg = tid / kBA;  // rows a0 + a; rhs r0 + rg + 4 j
-    double accr[4], acci[4];
+    const int a = threadIdx.x % 64, g = threadIdx.x / 64;
+    const int row = a0 + a;
+    const int rowc = row < nb ? row : nb - 1;  // rows past nb read a valid entry, never written
+    // one LDS buffer: a slice of the right-hand sides (KC inner indices x NR, the couplings of
+    // level 0 already folded in), then the partial sums (KG x NR x 64, real and imaginary)
+    constexpr int KC = 2048 / NR;
+    __shared__ double2 lds[2048];
+    double accr[NR], acci[NR];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        accr[j] = 0.0;
-        acci[j] = 0.0;
-        const int r = r0 + rg + 4 * j;
-        if (y0.p && a0 + a < nb && r < A.R) {
-            accr[j] = y0.p[(size_t)r * y0.rs + a0 + a];
-            acci[j] = y0.p[(size_t)r * y0.rs + y0.ps + a0 + a];
-        }
-    }
+    for (int j = 0; j < NR; ++j) accr[j] = acci[j] = 0.0;
     const size_t nn = (size_t)nb * nb;
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
         const ExTerm& T = terms[t];
         if (!T.S) continue;
-        const double* Sr = T.S;
-        const double* Si = T.S + nn;
-        for (int k0 = 0; k0 < nb; k0 += kBK) {
-            __syncthreads();
-            // S tile: entry (k, a) of op(S)^T, i.e. S[k][a] (trans) or S[a][k]
-#pragma unroll
-            for (int q = 0; q < kBK * kBA / 256; ++q) {
-                const int idx = tid + 256 * q;
-                int kk, aa;
-                if (T.trans) {
-                    aa = idx % kBA;
-                    kk = idx / kBA;
-                } else {
-                    kk = idx % kBK;
-                    aa = idx / kBK;
-                }
-                const int gk = k0 + kk, ga = a0 + aa;
-                double vr = 0.0, vi = 0.0;
-                if (gk < nb && ga < nb) {
-                    const size_t off = T.trans ? (size_t)gk * nb + ga : (size_t)ga * nb + gk;
-                    vr = T.sign * Sr[off];
-                    vi = T.sign * Si[off];
-                }
-                msr[kk][aa] = vr;
-                msi[kk][aa] = vi;
-            }
-            // v tile
-#pragma unroll
-            for (int q = 0; q < kBK * kBR / 256; ++q) {
-                const int idx = tid + 256 * q;
-                const int kk = idx % kBK, rr = idx / kBK;
-                const int gk = k0 + kk, r = r0 + rr;
-                double vr = 0.0, vi = 0.0;
-                if (gk < nb && r < A.R) {
-                    vr = T.v.p[(size_t)r * T.v.rs + gk];
-                    vi = T.v.p[(size_t)r * T.v.rs + T.v.ps + gk];
+        const double* Sr = T.S + rowc;
+        const double* Si = T.S + nn + rowc;
+        for (int kc0 = 0; kc0 < nb; kc0 += KC) {
+            const int kc = min(KC, nb - kc0);
+            __syncthreads();  // the previous slice is no longer read
+            for (int idx = threadIdx.x; idx < kc * NR; idx += 64 * KG) {
+                const int kk = idx % kc, j = idx / kc;
+                const int k = kc0 + kk;
+                const size_t r = (size_t)min(r0 + j, A.R - 1);  // past R: computed and dropped
+                double vr = T.v.p[r * T.v.rs + k], vi = T.v.p[r * T.v.rs + T.v.ps + k];
+                if (COMB) {
                     if (T.T1) {
-                        const double c1 = T.T1[gk];
-                        vr += c1 * T.w1.p[(size_t)r * T.w1.rs + gk];
-                        vi += c1 * T.w1.p[(size_t)r * T.w1.rs + T.w1.ps + gk];
+                        vr += T.T1[k] * T.w1.p[r * T.w1.rs + k];
+                        vi += T.T1[k] * T.w1.p[r * T.w1.rs + T.w1.ps + k];
                     }
                     if (T.T2) {
-                        const double c2 = T.T2[gk];
-                        vr += c2 * T.w2.p[(size_t)r * T.w2.rs + gk];
-                        vi += c2 * T.w2.p[(size_t)r * T.w2.rs + T.w2.ps + gk];
+                        vr += T.T2[k] * T.w2.p[r * T.w2.rs + k];
+                        vi += T.T2[k] * T.w2.p[r * T.w2.rs + T.w2.ps + k];
                     }
                 }
-                vs[kk][rr] = make_double2(vr, vi);
+                lds[kk * NR + j] = make_double2(T.sign * vr, T.sign * vi);
             }
             __syncthreads();
-#pragma unroll 8
-            for (int kk = 0; kk < kBK; ++kk) {
-                const double mr = msr[kk][a], mi = msi[kk][a];
+#pragma unroll 4
+            for (int kk = g; kk < kc; kk += KG) {
+                const size_t k = (size_t)(kc0 + kk);
+                const double sr = Sr[k * nb], si = Si[k * nb];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const double2 v = vs[kk][rg + 4 * j];
-                    accr[j] += mr * v.x - mi * v.y;
-                    acci[j] += mr * v.y + mi * v.x;
+                for (int j = 0; j < NR; ++j) {
+                    const double2 v = lds[kk * NR + j];
+                    accr[j] += sr * v.x - si * v.y;
+                    acci[j] += sr * v.y + si * v.x;
                 }
             }
         }
     }
-    if (a0 + a < nb) {
+    // add the KG groups' partial sums, JR right-hand sides at a time (KG x JR x 64 complex in LDS)
+    constexpr int JR = NR < 2 ? NR : 2;
+    double* redr = reinterpret_cast<double*>(lds);
+    double* redi = redr + KG * JR * 64;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = r0 + rg + 4 * j;
-            if (r < A.R && !(to_caller && A.active && !A.active[r])) {
-                yp[(size_t)r * yrs + a0 + a] = accr[j];
-                yp[(size_t)r * yrs + yps + a0 + a] = acci[j];
+    for (int j0 = 0; j0 < NR; j0 += JR) {
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < JR; ++jj) {
+            redr[(g * JR + jj) * 64 + a] = accr[j0 + jj];
+            redi[(g * JR + jj) * 64 + a] = acci[j0 + jj];
+        }
+        __syncthreads();
+        const int r = r0 + j0 + g;  // wave g < JR finishes right-hand side j0 + g
+        if (g < JR && row < nb && r < A.R && !(to_caller && A.active && !A.active[r])) {
+            double sr = 0.0, si = 0.0;
+            if (y0.p) {
+                sr = y0.p[(size_t)r * y0.rs + row];
+                si = y0.p[(size_t)r * y0.rs + y0.ps + row];
             }
+            for (int q = 0; q < KG; ++q) {
+                sr += redr[(q * JR + g) * 64 + a];
+                si += redi[(q * JR + g) * 64 + a];
+            }
+            yp[(size_t)r * yrs + row] = sr;
+            yp[(size_t)r * yrs + yps + row] = si;
         }
     }
 }
@@ -588,6 +597,45 @@ __global__ __launch_bounds__(256) void k_ex_reduce0(int nb, int R, int n, const 
 }
 
 inline unsigned nblk(size_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// right-hand sides per workgroup: the smallest of 1, 2, 4, 8 that covers R (8 beyond)
+inline int solve_nr(int R) { return R >= 8 ? 8 : R >= 4 ? (R == 4 ? 4 : 8) : R >= 2 ? (R == 2 ? 2 : 4) : 1; }
+
+template <bool COMB, int NR>
+hipError_t launch_nr(const ExSolve& A, dim3 g, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    hipExtLaunchKernelGGL((k_ex_solve<COMB, NR>), g, dim3(64 * kExKG), 0, st, e0, e1, 0, A);
+    return hipGetLastError();
+}
+
+template <bool COMB>
+hipError_t dispatch_nr(const ExSolve& A, dim3 g, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    switch (solve_nr(A.R)) {
+    case 1: return launch_nr<COMB, 1>(A, g, st, e0, e1);
+    case 2: return launch_nr<COMB, 2>(A, g, st, e0, e1);
+    case 4: return launch_nr<COMB, 4>(A, g, st, e0, e1);
+    default: return launch_nr<COMB, 8>(A, g, st, e0, e1);
+    }
+}
+
+hipError_t dispatch_solve(const ExSolve& A, dim3 g, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    return A.mode == kModeBack0 ? dispatch_nr<true>(A, g, st, e0, e1) : dispatch_nr<false>(A, g, st, e0, e1);
+}
+
+// One block-product launch of a solve; with opts.profile = LT_PROF_EXACT it is bracketed by
+// HIP events and its algorithmic bytes (dense blocks and vector blocks it must move) counted.
+int launch_solve(lt_handle* h, const ExSolve& A, dim3 g, double bytes) {
+    hipStream_t st = h->stream;
+    if (h->prof_target == LT_PROF_EXACT) {
+        unsigned long long* pc = nullptr;
+        hipEvent_t e0, e1;
+        LT_TRY(prof_begin(h, LT_PROF_EXACT, &pc, &e0, &e1));
+        LT_HIP(dispatch_solve(A, g, st, e0, e1));
+        h->prof_host_bytes += bytes;
+        return prof_end(h, LT_PROF_EXACT);
+    }
+    LT_HIP(dispatch_solve(A, g, st, nullptr, nullptr));
+    return 0;
+}
 
 int invert_batch(hipStream_t st, double* mats, size_t ms, int nb, int count, int* flag) {
     if (count <= 0) return 0;
@@ -700,6 +748,8 @@ const ExactFactor* exact_factor(lt_handle* h, cdouble tau, int* rc) {
     F->dinv.assign(top + 1, 0);
     F->pm.assign(top + 1, 0);
     F->qm.assign(top + 1, 0);
+    F->ptm.assign(top + 1, 0);
+    F->qtm.assign(top + 1, 0);
     size_t slots = 0;
     for (int l = 0; l < top; ++l) {
         F->dinv[l] = slots;
@@ -710,6 +760,10 @@ const ExactFactor* exact_factor(lt_handle* h, cdouble tau, int* rc) {
         F->pm[l] = slots;
         slots += F->nl[l] / 2;
         F->qm[l] = slots;
+        slots += F->nl[l] / 2;
+        F->ptm[l] = slots;
+        slots += F->nl[l] / 2;
+        F->qtm[l] = slots;
         slots += F->nl[l] / 2;
     }
     const size_t ms = F->ms;
@@ -757,6 +811,11 @@ const ExactFactor* exact_factor(lt_handle* h, cdouble tau, int* rc) {
             // P_s = Dinv_s F_{2s}^T, Q_s = Dinv_s F_{2s+1}
             if ((r = gemm_batch(st, nb, el, 0, 1, 1.0, 0.0, Dv, ms, Fc, 2 * ms, Pm, ms)) < 0) return fail(r);
             if ((r = gemm_batch(st, nb, nq, 0, 0, 1.0, 0.0, Dv, ms, Fc + ms, 2 * ms, Qm, ms)) < 0) return fail(r);
+            // and their transposes (Dinv is symmetric): P_s^T = F_{2s} Dinv_s, Q_s^T = F_{2s+1}^T Dinv_s
+            if ((r = gemm_batch(st, nb, el, 0, 0, 1.0, 0.0, Fc, 2 * ms, Dv, ms, M + F->ptm[l] * ms, ms)) < 0)
+                return fail(r);
+            if ((r = gemm_batch(st, nb, nq, 1, 0, 1.0, 0.0, Fc + ms, 2 * ms, Dv, ms, M + F->qtm[l] * ms, ms)) < 0)
+                return fail(r);
             // D'_k = D_{2k} - F_{2k-1}^T Q_{k-1} - F_{2k} P_k;  F'_k = -F_{2k} Q_k
             if ((r = copy_blocks(st, Dx, Dc, ms, 2, nn1)) < 0) return fail(r);
             if ((r = gemm_batch(st, nb, nn1 - 1, 1, 0, -1.0, 1.0, Fc + ms, 2 * ms, Qm, ms, Dx + ms, ms)) < 0)
@@ -805,14 +864,14 @@ int exact_apply(lt_handle* h, const ExactFactor* F, int R, const double* b, size
     A.active = active;
     const LevelView<double> L = h->levels[0].v64();
     A.Tl = h->grid.ndim == 3 ? L.Tz : L.Ty;
-    const unsigned gx = nblk(nb, kBA), gy = nblk(R, kBR);
+    const unsigned gx = nblk(nb, 64), gy = nblk(R, solve_nr(R));
+    // algorithmic bytes: a dense block, a block of R vectors
+    const double mb = (double)F->ms * sizeof(double), vb = 2.0 * R * nb * sizeof(double);
     if (n == 1) {
         A.mode = kModeTop;
         A.nl = 1;
         A.dinv = F->dinv[0];
-        k_ex_solve<<<dim3(gx, gy, 1), 256, 0, st>>>(A);
-        LT_HIP(hipGetLastError());
-        return 0;
+        return launch_solve(h, A, dim3(gx, gy, 1), mb + 2 * vb);
     }
     // workspaces: T0 (n/2 blocks), then B_l and X_l for l = 1..top
     const size_t bs = 2 * (size_t)R * nb;
@@ -833,8 +892,7 @@ int exact_apply(lt_handle* h, const ExactFactor* F, int R, const double* b, size
     A.nl = n;
     A.dinv = F->dinv[0];
     A.Xl = W;
-    k_ex_solve<<<dim3(gx, gy, n / 2), 256, 0, st>>>(A);
-    LT_HIP(hipGetLastError());
+    LT_TRY(launch_solve(h, A, dim3(gx, gy, n / 2), (n / 2) * (mb + 2 * vb)));
     k_ex_reduce0<<<dim3(nblk(bs, 256), F->nl[1]), 256, 0, st>>>(nb, R, n, b, brs, A.N, A.Tl, W, W + boff[1], bs);
     LT_HIP(hipGetLastError());
     for (int l = 1; l < top; ++l) {
@@ -844,35 +902,32 @@ int exact_apply(lt_handle* h, const ExactFactor* F, int R, const double* b, size
         A.qm = F->qm[l];
         A.Bl = W + boff[l];
         A.Bn = W + boff[l + 1];
-        k_ex_solve<<<dim3(gx, gy, F->nl[l + 1]), 256, 0, st>>>(A);
-        LT_HIP(hipGetLastError());
+        const int nl = F->nl[l], nn1 = F->nl[l + 1];
+        LT_TRY(launch_solve(h, A, dim3(gx, gy, nn1), (nn1 - 1 + nl / 2) * mb + (nl + nn1) * vb));
     }
     A.mode = kModeTop;
     A.nl = 1;
     A.dinv = F->dinv[top];
     A.Bl = W + boff[top];
     A.Xl = W + xoff[top];
-    k_ex_solve<<<dim3(gx, gy, 1), 256, 0, st>>>(A);
-    LT_HIP(hipGetLastError());
+    LT_TRY(launch_solve(h, A, dim3(gx, gy, 1), mb + 2 * vb));
     for (int l = top - 1; l >= 1; --l) {
         A.mode = kModeBack;
         A.nl = F->nl[l];
         A.dinv = F->dinv[l];
-        A.pm = F->pm[l];
-        A.qm = F->qm[l];
+        A.ptm = F->ptm[l];
+        A.qtm = F->qtm[l];
         A.Bl = W + boff[l];
         A.Xl = W + xoff[l];
         A.Xn = W + xoff[l + 1];
-        k_ex_solve<<<dim3(gx, gy, F->nl[l]), 256, 0, st>>>(A);
-        LT_HIP(hipGetLastError());
+        const int nl = F->nl[l], el = nl / 2, nq = (nl - 1) / 2;
+        LT_TRY(launch_solve(h, A, dim3(gx, gy, nl), (2 * el + nq) * mb + (el + F->nl[l + 1] + nl) * vb));
     }
     A.mode = kModeBack0;
     A.nl = n;
     A.dinv = F->dinv[0];
     A.Xn = W + xoff[1];
-    k_ex_solve<<<dim3(gx, gy, n), 256, 0, st>>>(A);
-    LT_HIP(hipGetLastError());
-    return 0;
+    return launch_solve(h, A, dim3(gx, gy, n), (n / 2) * mb + (n / 2 + F->nl[1] + n) * vb);
 }
 
 size_t exact_matrix_bytes(const ExactFactor* F) {

@@ -82,7 +82,8 @@ struct CoarseInverse {
 // Exact (K + tau M)^{-1} by block cyclic reduction over the slices of the last axis
 // (exact.hip).  Level l has nl[l] blocks; its odd-positioned ones are eliminated with
 // their inverses Dinv (slots dinv[l] ...) and, above level 0, P = Dinv F_{i-1}^T and
-// Q = Dinv F_i (slots pm[l] ..., qm[l] ...); the last level has one block (slot dinv[top]).
+// Q = Dinv F_i (slots pm[l] ..., qm[l] ...) with their transposes (ptm[l] ..., qtm[l] ...);
+// the last level has one block (slot dinv[top]).
 constexpr int kExactMaxBlock = 1024;  // cells per slice
 constexpr int kExactCache = 4;        // factorised shifts kept per handle
 struct ExactFactor {
@@ -91,7 +92,7 @@ struct ExactFactor {
     int nb = 0, n = 0;    // cells per slice, slices
     size_t ms = 0;        // doubles per dense block ([2][nb][nb])
     std::vector<int> nl;
-    std::vector<size_t> dinv, pm, qm;
+    std::vector<size_t> dinv, pm, qm, ptm, qtm;
     DevBuf mats;
     unsigned long long tick = 0;
     void release();
@@ -146,6 +147,7 @@ struct lt_handle {
     std::vector<hipEvent_t> prof_events;
     int prof_used = 0;
     unsigned long long* prof_counter = nullptr;  // device
+    double prof_host_bytes = 0.0;  // bytes of profiled launches counted on the host
     ~lt_handle();
 };
 
