@@ -383,11 +383,19 @@ struct ExTerm {
 
 enum { kModeT0 = 0, kModeReduce = 2, kModeTop = 3, kModeBack = 4, kModeBack0 = 5 };
 
+// Where the blocks of a level's vectors live: block i of right-hand side r, plane c at
+// base + i * bstride + r * rs + c * ps.  Levels below the tail: [block][R][2][nb]; the tail
+// level: [R][2][nl nb] (contiguous per right-hand side, for its dense product).
+struct ExLay {
+    size_t bstride, rs, ps;
+};
+
 struct ExSolve {
-    int mode, nb, R, n, nl;           // n: slices; nl: blocks at this level
+    int mode, nb, R, n, nl;           // n: slices; nl: blocks at this level; nb: rows (the tail: nl nb)
     const double* mats;
     size_t ms;                        // doubles per dense block
     size_t dinv, pm, qm, ptm, qtm;    // first slot of Dinv / P / Q / P^T / Q^T at this level
+    const double* tail;               // the tail's dense inverse (kModeTop)
     const double* b;                  // caller's right-hand side, slice q at b + q nb
     size_t brs;
     double* x;                        // caller's solution
@@ -397,13 +405,15 @@ struct ExSolve {
     double* Bn;                       // the next level's
     double* Xl;                       // this level's solution blocks (or level 0's T = Dinv b)
     const double* Xn;                 // the next level's solution blocks
-    size_t bs;                        // block stride of the workspaces (2 R nb)
+    ExLay ll, ln;                     // layouts of this level's and the next level's vectors
     const double* Tl;                 // couplings along the slicing axis (T of the last axis)
     const int* active;                // [R] or nullptr: the caller's x of a right-hand side marked 0 is kept
+    int ks;                           // kModeTop: the inner dimension is split over ks workgroups ...
+    double* part;                     // ... whose partial products go to part[ks][R][2][nb]
 };
 
-__device__ inline ExVec ws_vec(const double* base, size_t bs, int blk, int nb) {
-    return ExVec{base + (size_t)blk * bs, 2 * (size_t)nb, (size_t)nb};
+__device__ inline ExVec ws_vec(const double* base, const ExLay& L, int blk) {
+    return ExVec{base + (size_t)blk * L.bstride, L.rs, L.ps};
 }
 
 constexpr int kExKG = 16;  // k-groups (waves) per row tile of a block product
@@ -420,7 +430,10 @@ template <bool COMB, int NR>
 __global__ __launch_bounds__(64 * kExKG) void k_ex_solve(ExSolve A) {
     constexpr int KG = kExKG;
     const int nb = A.nb, o = blockIdx.z;
-    const int a0 = blockIdx.x * 64, r0 = blockIdx.y * NR;
+    const int kp = blockIdx.y % A.ks;  // part of the inner dimension (kModeTop only; else 0 of 1)
+    const int a0 = blockIdx.x * 64, r0 = (blockIdx.y / A.ks) * NR;
+    const int kspan = (nb + A.ks - 1) / A.ks;
+    const int kb = kp * kspan, ke = min(nb, kb + kspan);
     // up to three terms at fixed positions (S == nullptr: absent), so that they stay in registers
     ExTerm terms[3];
     const ExVec none{nullptr, 0, 0};
@@ -431,51 +444,56 @@ __global__ __launch_bounds__(64 * kExKG) void k_ex_solve(ExSolve A) {
     size_t yrs, yps;
     bool to_caller = false;  // y is the caller's x (masked by active)
     auto mat = [&](size_t slot) { return A.mats + slot * A.ms; };
-    const size_t wps = nb;
+    const ExLay t0lay{2 * (size_t)A.R * nb, 2 * (size_t)nb, (size_t)nb};  // level 0's T = Dinv b
     switch (A.mode) {
     case kModeT0:  // T0[o] = Dinv0[o] b_{2o+1}
-        yp = A.Xl + (size_t)o * A.bs;
-        yrs = 2 * (size_t)nb;
-        yps = wps;
+        yp = A.Xl + (size_t)o * t0lay.bstride;
+        yrs = t0lay.rs;
+        yps = t0lay.ps;
         terms[0] = ExTerm{mat(A.dinv + o), 1.0, ExVec{A.b + (size_t)(2 * o + 1) * nb, A.brs, A.N}, nullptr, none,
                           nullptr, none};
         break;
     case kModeReduce:  // B'_o = B_{2o} - Q_{2o-1}^T B_{2o-1} - P_{2o+1}^T B_{2o+1}
-        yp = A.Bn + (size_t)o * A.bs;
-        yrs = 2 * (size_t)nb;
-        yps = wps;
-        y0 = ws_vec(A.Bl, A.bs, 2 * o, nb);
+        yp = A.Bn + (size_t)o * A.ln.bstride;
+        yrs = A.ln.rs;
+        yps = A.ln.ps;
+        y0 = ws_vec(A.Bl, A.ll, 2 * o);
         if (o >= 1)
-            terms[0] = ExTerm{mat(A.qm + o - 1), -1.0, ws_vec(A.Bl, A.bs, 2 * o - 1, nb), nullptr, none, nullptr, none};
+            terms[0] = ExTerm{mat(A.qm + o - 1), -1.0, ws_vec(A.Bl, A.ll, 2 * o - 1), nullptr, none, nullptr, none};
         if (2 * o + 1 < A.nl)
-            terms[1] = ExTerm{mat(A.pm + o), -1.0, ws_vec(A.Bl, A.bs, 2 * o + 1, nb), nullptr, none, nullptr, none};
+            terms[1] = ExTerm{mat(A.pm + o), -1.0, ws_vec(A.Bl, A.ll, 2 * o + 1), nullptr, none, nullptr, none};
         break;
-    case kModeTop:  // the last block (or the only slice: caller's vectors)
-        if (A.n == 1) {
+    case kModeTop:  // the tail's dense inverse on its right-hand side (one slice: the caller's vectors),
+                    // or, split over ks, partial products into part
+        if (A.ks > 1) {
+            yp = A.part + (size_t)kp * A.R * 2 * nb;
+            yrs = 2 * (size_t)nb;
+            yps = nb;
+        } else if (A.n == 1) {
             yp = A.x;
             yrs = A.xrs;
             yps = A.N;
             to_caller = true;
-            terms[0] = ExTerm{mat(A.dinv), 1.0, ExVec{A.b, A.brs, A.N}, nullptr, none, nullptr, none};
         } else {
             yp = A.Xl;
-            yrs = 2 * (size_t)nb;
-            yps = wps;
-            terms[0] = ExTerm{mat(A.dinv), 1.0, ws_vec(A.Bl, A.bs, 0, nb), nullptr, none, nullptr, none};
+            yrs = A.ll.rs;
+            yps = A.ll.ps;
         }
+        terms[0] = ExTerm{A.tail, 1.0, A.n == 1 ? ExVec{A.b, A.brs, A.N} : ExVec{A.Bl, A.ll.rs, A.ll.ps}, nullptr,
+                          none, nullptr, none};
         break;
     case kModeBack: {  // X_o = X'_{o/2} (even);  Dinv_s B_o - P_s X'_s - Q_s X'_{s+1} (odd, s = (o-1)/2)
-        yp = A.Xl + (size_t)o * A.bs;
-        yrs = 2 * (size_t)nb;
-        yps = wps;
+        yp = A.Xl + (size_t)o * A.ll.bstride;
+        yrs = A.ll.rs;
+        yps = A.ll.ps;
         if (!(o & 1)) {
-            y0 = ws_vec(A.Xn, A.bs, o / 2, nb);
+            y0 = ws_vec(A.Xn, A.ln, o / 2);
         } else {
             const int s = (o - 1) / 2;
-            terms[0] = ExTerm{mat(A.dinv + s), 1.0, ws_vec(A.Bl, A.bs, o, nb), nullptr, none, nullptr, none};
-            terms[1] = ExTerm{mat(A.ptm + s), -1.0, ws_vec(A.Xn, A.bs, s, nb), nullptr, none, nullptr, none};
+            terms[0] = ExTerm{mat(A.dinv + s), 1.0, ws_vec(A.Bl, A.ll, o), nullptr, none, nullptr, none};
+            terms[1] = ExTerm{mat(A.ptm + s), -1.0, ws_vec(A.Xn, A.ln, s), nullptr, none, nullptr, none};
             if (o + 1 < A.nl)
-                terms[2] = ExTerm{mat(A.qtm + s), -1.0, ws_vec(A.Xn, A.bs, s + 1, nb), nullptr, none, nullptr, none};
+                terms[2] = ExTerm{mat(A.qtm + s), -1.0, ws_vec(A.Xn, A.ln, s + 1), nullptr, none, nullptr, none};
         }
         break;
     }
@@ -485,13 +503,13 @@ __global__ __launch_bounds__(64 * kExKG) void k_ex_solve(ExSolve A) {
         yps = A.N;
         to_caller = true;
         if (!(o & 1)) {
-            y0 = ws_vec(A.Xn, A.bs, o / 2, nb);
+            y0 = ws_vec(A.Xn, A.ln, o / 2);
         } else {
             const int s = (o - 1) / 2;
             const bool right = o + 1 < A.n;
             terms[0] = ExTerm{mat(A.dinv + s), 1.0, ExVec{A.b + (size_t)o * nb, A.brs, A.N},
-                              A.Tl + (size_t)(o - 1) * nb, ws_vec(A.Xn, A.bs, s, nb),
-                              right ? A.Tl + (size_t)o * nb : nullptr, right ? ws_vec(A.Xn, A.bs, s + 1, nb) : none};
+                              A.Tl + (size_t)(o - 1) * nb, ws_vec(A.Xn, A.ln, s),
+                              right ? A.Tl + (size_t)o * nb : nullptr, right ? ws_vec(A.Xn, A.ln, s + 1) : none};
         }
         break;
     }
@@ -514,8 +532,8 @@ __global__ __launch_bounds__(64 * kExKG) void k_ex_solve(ExSolve A) {
         if (!T.S) continue;
         const double* Sr = T.S + rowc;
         const double* Si = T.S + nn + rowc;
-        for (int kc0 = 0; kc0 < nb; kc0 += KC) {
-            const int kc = min(KC, nb - kc0);
+        for (int kc0 = kb; kc0 < ke; kc0 += KC) {
+            const int kc = min(KC, ke - kc0);
             __syncthreads();  // the previous slice is no longer read
             for (int idx = threadIdx.x; idx < kc * NR; idx += 64 * KG) {
                 const int kk = idx % kc, j = idx / kc;
@@ -579,21 +597,59 @@ __global__ __launch_bounds__(64 * kExKG) void k_ex_solve(ExSolve A) {
 }
 
 // Level 0 reduction with diagonal couplings: B1_k = b_{2k} + T_{2k-1} o T0[k-1] + T_{2k} o T0[k]
-// (f = -T), one thread per (rhs, plane, cell) of one block.
+// (f = -T), one thread per (rhs, plane, cell) of one block; B1 in layout L1.
 __global__ __launch_bounds__(256) void k_ex_reduce0(int nb, int R, int n, const double* __restrict__ b, size_t brs,
                                                     size_t N, const double* __restrict__ Tl,
                                                     const double* __restrict__ T0, double* __restrict__ B1,
-                                                    size_t bs) {
+                                                    ExLay L1) {
     const int k = blockIdx.y, p = 2 * k;
+    const size_t bs = 2 * (size_t)R * nb;  // T0's block stride
     const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= 2 * (size_t)R * nb) return;
+    if (e >= bs) return;
     const int a = (int)(e % nb);
     const int c = (int)((e / nb) % 2);
     const int r = (int)(e / (2 * (size_t)nb));
     double v = b[(size_t)r * brs + (size_t)c * N + (size_t)p * nb + a];
     if (p >= 1) v += Tl[(size_t)(p - 1) * nb + a] * T0[(size_t)(k - 1) * bs + e];
     if (p + 1 < n) v += Tl[(size_t)p * nb + a] * T0[(size_t)k * bs + e];
-    B1[(size_t)k * bs + e] = v;
+    B1[(size_t)k * L1.bstride + (size_t)r * L1.rs + (size_t)c * L1.ps + a] = v;
+}
+
+// The tail's k-split partial products summed: X = sum_p part[p] (X and part [R][2][m]).
+__global__ __launch_bounds__(256) void k_ex_sum_parts(size_t len, int ks, const double* __restrict__ part,
+                                                      double* __restrict__ X) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= len) return;
+    double v = 0.0;
+    for (int p = 0; p < ks; ++p) v += part[(size_t)p * len + e];
+    X[e] = v;
+}
+
+// The tail level's reduced system as one dense matrix of m = nl nb unknowns: diagonal blocks
+// D_i, block (i, i + 1) F_i and block (i + 1, i) F_i^T.
+__global__ __launch_bounds__(256) void k_ex_tail(int nb, int nl, const double* __restrict__ D,
+                                                 const double* __restrict__ Fb, size_t ms, double* __restrict__ out) {
+    const size_t m = (size_t)nl * nb, mm = m * m, nn = (size_t)nb * nb;
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= mm) return;
+    const size_t I = e / m, J = e % m;
+    const int bi = (int)(I / nb), bj = (int)(J / nb), a = (int)(I % nb), c = (int)(J % nb);
+    double re = 0.0, im = 0.0;
+    if (bi == bj) {
+        const double* g = D + (size_t)bi * ms;
+        re = g[(size_t)a * nb + c];
+        im = g[nn + (size_t)a * nb + c];
+    } else if (bj == bi + 1) {
+        const double* g = Fb + (size_t)bi * ms;
+        re = g[(size_t)a * nb + c];
+        im = g[nn + (size_t)a * nb + c];
+    } else if (bi == bj + 1) {
+        const double* g = Fb + (size_t)bj * ms;
+        re = g[(size_t)c * nb + a];
+        im = g[nn + (size_t)c * nb + a];
+    }
+    out[e] = re;
+    out[mm + e] = im;
 }
 
 inline unsigned nblk(size_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -744,7 +800,16 @@ const ExactFactor* exact_factor(lt_handle* h, cdouble tau, int* rc) {
     F->ms = 2 * (size_t)nb * nb;
     F->nl.assign(1, n);
     while (F->nl.back() > 1) F->nl.push_back((F->nl.back() + 1) / 2);
-    const int top = (int)F->nl.size() - 1;
+    // the tail: the first level above 0 whose whole reduced system has at most kExactTail
+    // unknowns (one slice: level 0 itself) is inverted as one dense matrix
+    int top = 0;
+    if (n > 1) {
+        top = 1;
+        while (top + 1 < (int)F->nl.size() && (size_t)F->nl[top] * nb > (size_t)kExactTail) ++top;
+    }
+    F->nl.resize(top + 1);
+    F->top = top;
+    F->mtop = (size_t)F->nl[top] * nb;
     F->dinv.assign(top + 1, 0);
     F->pm.assign(top + 1, 0);
     F->qm.assign(top + 1, 0);
@@ -755,7 +820,6 @@ const ExactFactor* exact_factor(lt_handle* h, cdouble tau, int* rc) {
         F->dinv[l] = slots;
         slots += F->nl[l] / 2;
     }
-    F->dinv[top] = slots++;
     for (int l = 1; l < top; ++l) {
         F->pm[l] = slots;
         slots += F->nl[l] / 2;
@@ -766,10 +830,13 @@ const ExactFactor* exact_factor(lt_handle* h, cdouble tau, int* rc) {
         F->qtm[l] = slots;
         slots += F->nl[l] / 2;
     }
+    F->tail_off = slots * F->ms;
+    const size_t mt = F->mtop, mst = 2 * mt * mt;  // the tail's doubles
     const size_t ms = F->ms;
-    *rc = F->mats.reserve(slots * ms * sizeof(double));
+    *rc = F->mats.reserve((F->tail_off + mst) * sizeof(double));
     if (*rc < 0) return nullptr;
     double* M = F->mats.as<double>();
+    double* Mt = M + F->tail_off;
     const int half = (n + 1) / 2;
     double* tmp = top >= 1 ? wsp<double>(h, "ex_tmp", 4 * (size_t)half * ms, rc) : nullptr;
     if (top >= 1 && !tmp) return nullptr;
@@ -786,9 +853,9 @@ const ExactFactor* exact_factor(lt_handle* h, cdouble tau, int* rc) {
     int r = 0;
     if (hipMemsetAsync(flag, 0, sizeof(int), st) != hipSuccess) return fail(LT_EHIP);
     if (n == 1) {
-        k_ex_dense<<<dim3(nblk(nn, 256), 1), 256, 0, st>>>(op, 0, 1, M + F->dinv[0] * ms, ms);
+        k_ex_dense<<<dim3(nblk(nn, 256), 1), 256, 0, st>>>(op, 0, 1, Mt, mst);
         if (hipGetLastError() != hipSuccess) return fail(LT_EHIP);
-        if ((r = invert_batch(st, M + F->dinv[0] * ms, ms, nb, 1, flag)) < 0) return fail(r);
+        if ((r = invert_batch(st, Mt, mst, nb, 1, flag)) < 0) return fail(r);
     } else {
         // level 0: invert the odd slices, then the Schur step onto the even ones
         const int e0 = n / 2;
@@ -825,8 +892,10 @@ const ExactFactor* exact_factor(lt_handle* h, cdouble tau, int* rc) {
             std::swap(Dc, Dx);
             std::swap(Fc, Fx);
         }
-        if ((r = copy_blocks(st, M + F->dinv[top] * ms, Dc, ms, 1, 1)) < 0) return fail(r);
-        if ((r = invert_batch(st, M + F->dinv[top] * ms, ms, nb, 1, flag)) < 0) return fail(r);
+        // the tail: level top's blocks (D_i in Dc, F_i in Fc) as one dense matrix, inverted
+        k_ex_tail<<<nblk(mt * mt, 256), 256, 0, st>>>(nb, F->nl[top], Dc, Fc, ms, Mt);
+        if (hipGetLastError() != hipSuccess) return fail(LT_EHIP);
+        if ((r = invert_batch(st, Mt, mst, (int)mt, 1, flag)) < 0) return fail(r);
     }
     int hf = 0;
     if (hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -849,32 +918,39 @@ int exact_apply(lt_handle* h, const ExactFactor* F, int R, const double* b, size
                 const int* active) {
     if (R <= 0) return 0;
     hipStream_t st = h->stream;
-    const int nb = F->nb, n = F->n, top = (int)F->nl.size() - 1;
+    const int nb = F->nb, n = F->n, top = F->top;
+    const size_t m = F->mtop;
     ExSolve A{};
     A.nb = nb;
     A.R = R;
     A.n = n;
     A.mats = F->mats.as<double>();
     A.ms = F->ms;
+    A.tail = F->mats.as<double>() + F->tail_off;
     A.b = b;
     A.brs = brs;
     A.x = x;
     A.xrs = xrs;
     A.N = (size_t)h->N;
     A.active = active;
+    A.ks = 1;
     const LevelView<double> L = h->levels[0].v64();
     A.Tl = h->grid.ndim == 3 ? L.Tz : L.Ty;
-    const unsigned gx = nblk(nb, 64), gy = nblk(R, solve_nr(R));
+    const int nr = solve_nr(R);
+    const unsigned gx = nblk(nb, 64), gy = nblk(R, nr);
     // algorithmic bytes: a dense block, a block of R vectors
     const double mb = (double)F->ms * sizeof(double), vb = 2.0 * R * nb * sizeof(double);
+    const double tb = 2.0 * m * m * sizeof(double);  // the tail's matrix
     if (n == 1) {
         A.mode = kModeTop;
         A.nl = 1;
-        A.dinv = F->dinv[0];
-        return launch_solve(h, A, dim3(gx, gy, 1), mb + 2 * vb);
+        return launch_solve(h, A, dim3(gx, gy, 1), tb + 2 * vb);
     }
-    // workspaces: T0 (n/2 blocks), then B_l and X_l for l = 1..top
+    // workspaces: T0 (n/2 blocks), B_l and X_l for l = 1..top, the tail's partial products
     const size_t bs = 2 * (size_t)R * nb;
+    auto lay = [&](int l) {
+        return l == top ? ExLay{(size_t)nb, 2 * m, m} : ExLay{bs, 2 * (size_t)nb, (size_t)nb};
+    };
     std::vector<size_t> boff(top + 1, 0), xoff(top + 1, 0);
     size_t tot = (size_t)(n / 2) * bs;
     for (int l = 1; l <= top; ++l) {
@@ -883,17 +959,22 @@ int exact_apply(lt_handle* h, const ExactFactor* F, int R, const double* b, size
         xoff[l] = tot;
         tot += (size_t)F->nl[l] * bs;
     }
+    // the tail's product: split its inner dimension so that the launch fills the GPU
+    const unsigned gxt = nblk(m, 64);
+    int ks = (int)std::min<size_t>(16, std::max<size_t>(1, 256 / ((size_t)gxt * gy)));
+    ks = (int)std::min<size_t>(ks, std::max<size_t>(1, m / 64));
+    const size_t poff = tot;
+    if (ks > 1) tot += (size_t)ks * R * 2 * m;
     int rc = 0;
     double* W = wsp<double>(h, "ex_vec", tot, &rc);
     if (!W) return rc;
-    A.bs = bs;
     // level 0: T0 = Dinv0 b_odd, then B1
     A.mode = kModeT0;
     A.nl = n;
     A.dinv = F->dinv[0];
     A.Xl = W;
     LT_TRY(launch_solve(h, A, dim3(gx, gy, n / 2), (n / 2) * (mb + 2 * vb)));
-    k_ex_reduce0<<<dim3(nblk(bs, 256), F->nl[1]), 256, 0, st>>>(nb, R, n, b, brs, A.N, A.Tl, W, W + boff[1], bs);
+    k_ex_reduce0<<<dim3(nblk(bs, 256), F->nl[1]), 256, 0, st>>>(nb, R, n, b, brs, A.N, A.Tl, W, W + boff[1], lay(1));
     LT_HIP(hipGetLastError());
     for (int l = 1; l < top; ++l) {
         A.mode = kModeReduce;
@@ -902,15 +983,28 @@ int exact_apply(lt_handle* h, const ExactFactor* F, int R, const double* b, size
         A.qm = F->qm[l];
         A.Bl = W + boff[l];
         A.Bn = W + boff[l + 1];
+        A.ll = lay(l);
+        A.ln = lay(l + 1);
         const int nl = F->nl[l], nn1 = F->nl[l + 1];
         LT_TRY(launch_solve(h, A, dim3(gx, gy, nn1), (nn1 - 1 + nl / 2) * mb + (nl + nn1) * vb));
     }
+    // the tail: X_top = (dense inverse) B_top, contiguous [R][2][m]
     A.mode = kModeTop;
-    A.nl = 1;
-    A.dinv = F->dinv[top];
+    A.nl = F->nl[top];
+    A.nb = (int)m;
     A.Bl = W + boff[top];
     A.Xl = W + xoff[top];
-    LT_TRY(launch_solve(h, A, dim3(gx, gy, 1), mb + 2 * vb));
+    A.ll = lay(top);
+    A.ks = ks;
+    A.part = W + poff;
+    LT_TRY(launch_solve(h, A, dim3(gxt, gy * ks, 1), tb + 2.0 * R * m * sizeof(double) * (ks > 1 ? ks : 1)));
+    if (ks > 1) {
+        const size_t len = (size_t)R * 2 * m;
+        k_ex_sum_parts<<<nblk(len, 256), 256, 0, st>>>(len, ks, W + poff, W + xoff[top]);
+        LT_HIP(hipGetLastError());
+    }
+    A.nb = nb;
+    A.ks = 1;
     for (int l = top - 1; l >= 1; --l) {
         A.mode = kModeBack;
         A.nl = F->nl[l];
@@ -920,6 +1014,8 @@ int exact_apply(lt_handle* h, const ExactFactor* F, int R, const double* b, size
         A.Bl = W + boff[l];
         A.Xl = W + xoff[l];
         A.Xn = W + xoff[l + 1];
+        A.ll = lay(l);
+        A.ln = lay(l + 1);
         const int nl = F->nl[l], el = nl / 2, nq = (nl - 1) / 2;
         LT_TRY(launch_solve(h, A, dim3(gx, gy, nl), (2 * el + nq) * mb + (el + F->nl[l + 1] + nl) * vb));
     }
@@ -927,21 +1023,20 @@ int exact_apply(lt_handle* h, const ExactFactor* F, int R, const double* b, size
     A.nl = n;
     A.dinv = F->dinv[0];
     A.Xn = W + xoff[1];
+    A.ln = lay(1);
     return launch_solve(h, A, dim3(gx, gy, n), (n / 2) * mb + (n / 2 + F->nl[1] + n) * vb);
 }
 
 size_t exact_matrix_bytes(const ExactFactor* F) {
     // dense blocks one solve reads: level 0's inverses twice (reduction and back
-    // substitution), then Dinv, P, Q of each eliminated block at the upper levels
-    // (P and Q once on the way up and once down), and the last block once
-    size_t blocks = 2 * (size_t)(F->n / 2);
-    const int top = (int)F->nl.size() - 1;
-    for (int l = 1; l < top; ++l) {
+    // substitution), Dinv, P, Q, P^T, Q^T of each eliminated block of the levels below the
+    // tail (each once), and the tail's dense inverse once
+    size_t blocks = F->n > 1 ? 2 * (size_t)(F->n / 2) : 0;
+    for (int l = 1; l < F->top; ++l) {
         const int el = F->nl[l] / 2, nq = (F->nl[l] - 1) / 2;
-        blocks += (size_t)el + 2 * (size_t)el + 2 * (size_t)nq;
+        blocks += 3 * (size_t)el + 2 * (size_t)nq;
     }
-    blocks += 1;
-    return blocks * F->ms * sizeof(double);
+    return blocks * F->ms * sizeof(double) + 2 * F->mtop * F->mtop * sizeof(double);
 }
 
 }  // namespace lt

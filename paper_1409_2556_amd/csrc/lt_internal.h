@@ -82,15 +82,20 @@ struct CoarseInverse {
 // Exact (K + tau M)^{-1} by block cyclic reduction over the slices of the last axis
 // (exact.hip).  Level l has nl[l] blocks; its odd-positioned ones are eliminated with
 // their inverses Dinv (slots dinv[l] ...) and, above level 0, P = Dinv F_{i-1}^T and
-// Q = Dinv F_i (slots pm[l] ..., qm[l] ...) with their transposes (ptm[l] ..., qtm[l] ...);
-// the last level has one block (slot dinv[top]).
+// Q = Dinv F_i (slots pm[l] ..., qm[l] ...) with their transposes (ptm[l] ..., qtm[l] ...).
+// The reduction stops at level top, the first above 0 whose whole reduced system has at most
+// kExactTail unknowns (level 0 for one slice): that system's dense inverse, [2][mtop][mtop]
+// with mtop = nl[top] nb, is stored from double tail_off of mats on.
 constexpr int kExactMaxBlock = 1024;  // cells per slice
+constexpr int kExactTail = 2048;      // unknowns of the level solved by one dense inverse
 constexpr int kExactCache = 4;        // factorised shifts kept per handle
 struct ExactFactor {
     bool valid = false;
     cdouble tau;
     int nb = 0, n = 0;    // cells per slice, slices
     size_t ms = 0;        // doubles per dense block ([2][nb][nb])
+    int top = 0;
+    size_t mtop = 0, tail_off = 0;
     std::vector<int> nl;
     std::vector<size_t> dinv, pm, qm, ptm, qtm;
     DevBuf mats;
