@@ -87,7 +87,7 @@ struct CoarseInverse {
 // kExactTail unknowns (level 0 for one slice): that system's dense inverse, [2][mtop][mtop]
 // with mtop = nl[top] nb, is stored from double tail_off of mats on.
 constexpr int kExactMaxBlock = 1024;  // cells per slice
-constexpr int kExactTail = 2048;      // unknowns of the level solved by one dense inverse
+constexpr int kExactTail = 1024;      // unknowns of the level solved by one dense inverse
 constexpr int kExactCache = 4;        // factorised shifts kept per handle
 struct ExactFactor {
     bool valid = false;
