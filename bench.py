@@ -79,6 +79,9 @@ def _parse():
                     help="after the solves, copy a 512 MiB buffer once (a plain copy kernel of known "
                          "size, to scale hardware byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--exact-cases", choices=["all", "headline", "one"], default="all",
+                    help="EXACT: every case of Tables 1-3, only the headline (one well and 16 wells), or only "
+                         "the one-well headline")
     ap.add_argument("--cpu-sample-times", type=int, default=10)
     ap.add_argument("--no-tune", action="store_true", help="keep the default smoother tile shapes")
     ap.add_argument("--groups", type=int, default=2,
@@ -474,6 +477,8 @@ def main_adjoint(args):
 
 C5J_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c5j_gs_color_half_traffic.md")
 C5J_KERNEL_SRC = os.path.join(ROOT, "paper_1409_2556_amd", "csrc", "mg.hip")
+EXACT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "exact_k_ex_solve.md")
+EXACT_KERNEL_SRC = os.path.join(ROOT, "paper_1409_2556_amd", "csrc", "exact.hip")
 
 
 def _map_err(got, ref, scale=None):
@@ -837,30 +842,38 @@ def main_exact(args):
         return r
 
     tables = {"variance_128": {}, "time_128_var1.6": {}, "grid_var1.6": {}}
-    for var in (0.8, 1.6, 3.5):
+    for var in ((0.8, 1.6, 3.5) if args.exact_cases == "all" else ()):
         p = _exact_problem(wl, var=var)
         tables["variance_128"][str(var)] = {s: run(p, nt, check=True) for s, nt in (("single", 1), ("flexible", 2))}
         print(f"[bench] EXACT var {var}: {tables['variance_128'][str(var)]}", file=sys.stderr, flush=True)
-    for t in (0.06, 1.2):
+    for t in ((0.06, 1.2) if args.exact_cases == "all" else ()):
         p = _exact_problem(wl, t=t)
         tables["time_128_var1.6"][str(t)] = {s: run(p, nt, check=True) for s, nt in (("single", 1), ("flexible", 2))}
         print(f"[bench] EXACT t {t}: {tables['time_128_var1.6'][str(t)]}", file=sys.stderr, flush=True)
-    for n in (64, 256, 512):
+    for n in ((64, 256, 512) if args.exact_cases == "all" else ()):
         p = _exact_problem(wl, n=(n, n))
         tables["grid_var1.6"][f"{n}^2"] = {s: run(p, nt) for s, nt in (("single", 1), ("flexible", 2))}
         print(f"[bench] EXACT grid {n}: {tables['grid_var1.6'][f'{n}^2']}", file=sys.stderr, flush=True)
     head = run(head_p, 2, check=True, profile=lt.LT_PROF_EXACT)
     wells = np.asarray(wl.configs._C2_WELLS, dtype=np.float64)
-    multi = run(_exact_problem(wl, wells=wells), 2, check=True, profile=lt.LT_PROF_EXACT)
+    multi = None
+    if args.exact_cases != "one":
+        multi = run(_exact_problem(wl, wells=wells), 2, check=True, profile=lt.LT_PROF_EXACT)
     print(f"[bench] EXACT headline {head}\n[bench] EXACT 16 wells {multi}", file=sys.stderr, flush=True)
+    if args.pmc_calibrate:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] copy calibration: 536870912 bytes read and written", file=sys.stderr, flush=True)
 
-    def roof(r, what):
+    def roof(r, what, traffic=None):
         pr = r["prof"]
         avg = pr["ms"] / max(pr["launches"], 1) * 1e-3
         per = pr["bytes"] / max(pr["launches"], 1)
         ach = per / avg / 1e9 if avg > 0 else 0.0
         return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                "traffic": None, "kernel": f"k_ex_solve (dense block products of the exact solve, {what})",
+                "traffic": traffic, "kernel": f"k_ex_solve (dense block products of the exact solve, {what})",
                 "avg_launch_us": avg * 1e6, "bytes_per_launch": per, "launches": pr["launches"]}
 
     valid = head["rc"] == 0 and head["rel_head_err"] <= 1e-5
@@ -878,9 +891,9 @@ def main_exact(args):
                    "factor_ms_per_shift": head["factor_ms"] / max(head["factorizations"], 1),
                    "iters": head["iters"], "rel_head_err_vs_oracle": head["rel_head_err"]},
         "tables": tables,
-        "sixteen_wells": {k: v for k, v in multi.items() if k != "prof"},
-        "roofline": roof(head, "one well"),
-        "roofline_sixteen_wells": roof(multi, "16 wells"),
+        "sixteen_wells": {k: v for k, v in multi.items() if k != "prof"} if multi else None,
+        "roofline": roof(head, "one well", _measured_traffic(EXACT_TRAFFIC_FILE, EXACT_KERNEL_SRC)),
+        "roofline_sixteen_wells": roof(multi, "16 wells") if multi else None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
