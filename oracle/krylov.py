@@ -51,14 +51,16 @@ def tau_schedule(shifts, n_tau):
     raise ValueError("n_tau must be 1 or 2")
 
 
-def flexible_shifted(K, m, b, taus, shifts, tol, maxit, method="gmres", weights=None):
+def flexible_shifted(K, m, b, taus, shifts, tol, maxit, method="gmres", weights=None, precond=None):
     """Algorithm 1 for one right-hand side b (real or complex [N]).
 
     ``taus``: preconditioner shifts used cyclically (tau_j = taus[(j - 1) % len]);
     ``shifts``: the z_k; a shift is converged when weights_k ||r_k|| <= tol ||b||, with
     r_k the small problem's residual (weights default 1: the relative test of
-    Section 4.1).  Returns a dict with x [nk, N], iters (steps taken), res [nk]
-    (||r_k|| / ||b||), conv [nk], conv_at [nk] (step at which each shift met the
+    Section 4.1).  ``precond(tau, v)``, if given, replaces the exact solve of
+    (K + tau M) u = v (a test hook for inexact preconditioners).  Returns a dict
+    with x [nk, N], iters (steps taken), res [nk] (||r_k|| / ||b||), conv [nk],
+    conv_at [nk] (step at which each shift met the
     test, 0 if never), V [N, iters + 1], U [N, iters], Hbar [iters + 1, iters],
     T [iters] and breakdown (True when h_{j+1, j} = 0 ended the loop).
     """
@@ -92,7 +94,7 @@ def flexible_shifted(K, m, b, taus, shifts, tol, maxit, method="gmres", weights=
     for j in range(1, maxit + 1):
         tau = complex(taus[(j - 1) % len(taus)])
         T[j - 1] = tau
-        u = solve(tau, V[:, j - 1])
+        u = solve(tau, V[:, j - 1]) if precond is None else np.asarray(precond(tau, V[:, j - 1]), dtype=np.complex128)
         U[:, j - 1] = u
         s = m * u
         for i in range(j):
