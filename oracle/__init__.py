@@ -15,12 +15,17 @@ heads     heads at receivers by one direct solve per shift (eqn:half)
 jacobian  sensitivities to ln(kappa), ln(S) by the discrete adjoint (Section 5.2)
 krylov    Algorithm 1 (flexible shifted FOM/GMRES) with exact shift-and-invert
           preconditioners, and the preconditioner schedule of Section 3
+geostat   the quasi-linear geostatistical inversion (Section 5.1, Algorithm 2)
+timestep  Crank-Nicolson heads (the inversion's data with model error, Section 5.3)
 """
 from .fv import assemble, point_weights
 from .contour import talbot_nodes, talbot_full
 from .heads import heads, shifted_fields
 from .jacobian import jacobian
 from .krylov import flexible_shifted, shift_invert, tau_schedule
+from .geostat import exp_covariance, gauss_newton_step, saddle_update
+from .timestep import crank_nicolson_heads
 
 __all__ = ["assemble", "point_weights", "talbot_nodes", "talbot_full", "heads",
-           "shifted_fields", "jacobian", "flexible_shifted", "shift_invert", "tau_schedule"]
+           "shifted_fields", "jacobian", "flexible_shifted", "shift_invert", "tau_schedule",
+           "exp_covariance", "gauss_newton_step", "saddle_update", "crank_nicolson_heads"]

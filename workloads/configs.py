@@ -121,6 +121,8 @@ _C5_SOURCES_3D = np.array([(x, y, 0.5) for y in (0.2, 0.4, 0.6, 0.8) for x in (0
 _C5_RECEIVERS_3D = np.array([(x, y, z) for z in (0.25, 0.75)
                              for y in (0.3, 0.5, 0.7, 0.9) for x in (0.3, 0.5, 0.7, 0.9)])
 
+_THT_WELLS = _wells_2d(np.linspace(0.2, 0.8, 6))
+
 CONFIGS = {
     # 2D 32x32, one central source, four receivers, 5 times, 16-node contour
     "C1": dict(n=(32, 32), var=1.0, ell=(0.2, 0.2, 0.2), seed=101, S=1e-5,
@@ -165,6 +167,11 @@ CONFIGS = {
     "C5_128x64": dict(n=(128, 128, 64), var=2.0, ell=(0.2, 0.2, 0.05), seed=506,
                       S_loguniform=(1e-6, 1e-4), S_seed=516,
                       sources=_C5_SOURCES_3D, receivers=_C5_RECEIVERS_3D, times=[0.3, 1.2], nz=24, n_tau=3),
+    # transient hydraulic tomography (Section 5.3): one well pumping at the centre, 36
+    # observation wells evenly in [0.2, 0.8]^2, the 8, 10 and 20 minute samples (0.48, 0.6 and
+    # 1.2 diffusion times), 20-node contour, 100x100 cells (the paper: 101^2 grid points)
+    "THT": dict(n=(100, 100), var=1.0, ell=(0.2, 0.2, 0.2), seed=601, S=1e-5,
+                sources=[(0.5, 0.5, 0.0)], receivers=_THT_WELLS, times=[0.48, 0.6, 1.2], nz=20, n_tau=2),
     "C4_train": dict(n=(128, 128), var=1.0, ell=(0.1, 0.1, 0.1), seed=10000, S=1e-5,
                      sources=_C2_SOURCES, receivers=_C2_WELLS, times=[0.3], nz=40, n_tau=1),
 }
