@@ -422,6 +422,55 @@ void lt_unet_destroy(lt_unet* u);
 int lt_precond_solve(lt_handle* h, double tau_re, double tau_im, int nvec, const double* r, double* e, double tol,
                      int maxcycles);
 
+/* ---- geostatistical inversion (Section 5.1, Algorithm 2) ---------------
+ * Unknowns s = ln kappa per cell with the prior s ~ N(X beta, Q): X a column
+ * of ones (one unknown constant mean) and Q the exponential covariance
+ * Q(x, x') = cov_var exp(-|(x - x') / cov_len|) (per-axis lengths, the first
+ * ndim used) over the cell centres.  Measurements y = h(s) + eps with
+ * eps ~ N(0, r I): the heads of the wells src (rates q as in lt_sources) at
+ * the observation wells obs and the times, ordered (well, receiver, time),
+ * M = src.n obs.n ntimes of them (at most 4096).  opts (NULL: defaults) are
+ * those of the forward (lt_solve) and adjoint (lt_adjoint) solves. */
+typedef struct {
+    lt_points src;
+    const double* q;
+    lt_points obs;
+    const double* times;
+    int ntimes;
+    lt_contour contour;
+    double cov_var;
+    double cov_len[3];
+    double r;
+    const lt_opts* opts;
+} lt_geostat;
+
+/* out = Q v for nvec device vectors v, out [nvec][N] (float64; out must not
+ * overlap v): the prior covariance product of Algorithm 2 (the paper forms
+ * Q J^T by FFT or hierarchical matrices; here each tile of Q is evaluated
+ * in LDS and never stored).  LT_EINVAL for nvec < 1 or a variance or length
+ * that is not positive and finite. */
+int lt_cov_apply(lt_handle* h, double var, const double* len, int nvec, const double* v, double* out);
+
+/* One Gauss-Newton step of Algorithm 2 at s (device [N], the ln kappa the
+ * handle was set up with: the caller keeps the two consistent): h(s) and
+ * J = dh/ds (lt_solve, lt_adjoint), Q J^T, and the saddle-point system of
+ * eq:inversion1 for xi and beta; s_next (device [N]) = X beta + Q J^T xi.
+ * y: device [M]; hs (device [M] or NULL) receives h(s); *beta (or NULL) the
+ * mean; stats (or NULL) those of the forward solve.  LT_WNOTCONV when a
+ * forward or adjoint solve missed its tolerance (the step is still taken);
+ * LT_EINVAL for bad arguments or a singular saddle-point system. */
+int lt_geostat_step(lt_handle* h, const lt_geostat* g, const double* y, const double* s, double* s_next,
+                    double* hs, double* beta, lt_stats* stats);
+
+/* Algorithm 2 for iters Gauss-Newton steps from s0 (device [N]): each step
+ * sets the operator up for kappa = exp(s_k) (lt_setup with grid, bc, S: S
+ * device [N]) on hip_stream and calls lt_geostat_step.  s_out: device [N].
+ * misfit (host [iters] or NULL): |y - h(s_k)|^2 / r at each step's start;
+ * step (host [iters] or NULL): |s_{k+1} - s_k| / |s_{k+1}|. */
+int lt_geostat_invert(const lt_grid* grid, const lt_bc* bc, const double* S, const lt_geostat* g,
+                      const double* y, const double* s0, int iters, void* hip_stream, double* s_out,
+                      double* misfit, double* step);
+
 /* x = (K + tau M)^{-1} b exactly (to FP64 rounding) for nvec complex device
  * vectors b, x [nvec][2][N]: the factorised shift-and-invert preconditioner
  * of Section 3 (eqn for (K + z_k M)(K + tau M)^{-1}), the one LT_PRECOND_EXACT

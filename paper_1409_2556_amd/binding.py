@@ -48,6 +48,13 @@ class lt_contour(C.Structure):
     _fields_ = [("nz", C.c_int)]
 
 
+class lt_geostat(C.Structure):
+    _fields_ = [("src", lt_points), ("q", C.POINTER(C.c_double)), ("obs", lt_points),
+                ("times", C.POINTER(C.c_double)), ("ntimes", C.c_int), ("contour", lt_contour),
+                ("cov_var", C.c_double), ("cov_len", C.c_double * 3), ("r", C.c_double),
+                ("opts", C.c_void_p)]
+
+
 class lt_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("precision", C.c_int), ("n_tau", C.c_int),
                 ("tau_reim", C.POINTER(C.c_double)), ("nu1", C.c_int), ("nu2", C.c_int),
@@ -111,6 +118,12 @@ _lib.lt_vcycle.argtypes = [_h, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int
 _lib.lt_vcycle.restype = C.c_int
 _lib.lt_vcycle_noalloc.argtypes = [_h, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int]
 _lib.lt_vcycle_noalloc.restype = C.c_int
+_lib.lt_cov_apply.argtypes = [_h, C.c_double, _dp, C.c_int, _vp, _vp]
+_lib.lt_cov_apply.restype = C.c_int
+_lib.lt_geostat_step.argtypes = [_h, C.c_void_p, _vp, _vp, _vp, _vp, _dp, C.c_void_p]
+_lib.lt_geostat_step.restype = C.c_int
+_lib.lt_geostat_invert.argtypes = [C.c_void_p, C.c_void_p, _vp, C.c_void_p, _vp, _vp, C.c_int, _vp, _vp, _dp, _dp]
+_lib.lt_geostat_invert.restype = C.c_int
 _lib.lt_shift_invert.argtypes = [_h, C.c_double, C.c_double, C.c_int, _vp, _vp]
 _lib.lt_shift_invert.restype = C.c_int
 _lib.lt_krylov_basis.argtypes = [_h, C.c_int, C.c_int, _dp, _dp, _dp, C.POINTER(C.c_int)]
@@ -438,6 +451,55 @@ def lt_shift_invert(handle: Handle, tau, b, x, nvec):
     tau = complex(tau)
     return _check(_lib.lt_shift_invert(handle.ptr, tau.real, tau.imag, int(nvec), _dev_f64(b, "b"),
                                        _dev_f64(x, "x")))
+
+
+def lt_cov_apply(handle: Handle, var, length, v, out, nvec):
+    """out = Q v for nvec float64 CUDA vectors [nvec][N] (exponential covariance, lengths per axis)."""
+    ln = np.ascontiguousarray(np.broadcast_to(np.asarray(length, dtype=np.float64), (3,)).copy())
+    return _check(_lib.lt_cov_apply(handle.ptr, float(var), ln.ctypes.data_as(_dp), int(nvec), _dev_f64(v, "v"),
+                                    _dev_f64(out, "out")))
+
+
+def _geostat(sources, q, observations, times, nz, var, length, r, opts):
+    sp, sa = _points(sources)
+    qa = np.ascontiguousarray(np.broadcast_to(np.asarray(q, dtype=np.float64), (sa.shape[0],)).copy())
+    op, oa = _points(observations)
+    t = np.ascontiguousarray(np.asarray(times, dtype=np.float64).ravel())
+    ln = np.broadcast_to(np.asarray(length, dtype=np.float64), (3,))
+    g = lt_geostat(sp, qa.ctypes.data_as(_dp), op, t.ctypes.data_as(_dp), t.size, lt_contour(int(nz)), float(var),
+                   (C.c_double * 3)(*[float(a) for a in ln]), float(r),
+                   C.cast(C.pointer(opts), C.c_void_p) if opts is not None else None)
+    return g, (sp, sa, qa, op, oa, t, opts), sa.shape[0] * oa.shape[0] * t.size
+
+
+def lt_geostat_step(handle: Handle, sources, q, observations, times, nz, var, length, r, y, s, s_next,
+                    opts: lt_opts | None = None):
+    """One Gauss-Newton step of Algorithm 2 at s (the handle's ln kappa): fills s_next (float64 CUDA
+    [N]) and returns (h(s) as a float64 CUDA tensor [M], beta, return code)."""
+    import torch
+    g, keep, M = _geostat(sources, q, observations, times, nz, var, length, r, opts)
+    hs = torch.empty(M, dtype=torch.float64, device="cuda")
+    beta = C.c_double()
+    rc = _check(_lib.lt_geostat_step(handle.ptr, C.byref(g), _dev_f64(y, "y"), _dev_f64(s, "s"),
+                                     _dev_f64(s_next, "s_next"), _dev_f64(hs, "hs"), C.byref(beta), None))
+    return hs, beta.value, rc
+
+
+def lt_geostat_invert(ndim, n, h, S, sources, q, observations, times, nz, var, length, r, y, s0, iters,
+                      bc=(0, 0, 0, 0, 0, 0), sy=0.0, opts: lt_opts | None = None, stream=None):
+    """Algorithm 2 for iters steps from s0: (s as a float64 CUDA tensor [N], misfit per step,
+    relative step size per step, return code)."""
+    import torch
+    gr = lt_grid(int(ndim), (C.c_int * 3)(*[int(a) for a in n]), (C.c_double * 3)(*[float(a) for a in h]))
+    b = lt_bc((C.c_int * 6)(*[int(a) for a in bc]), float(sy))
+    g, keep, M = _geostat(sources, q, observations, times, nz, var, length, r, opts)
+    out = torch.empty_like(s0)
+    mis = np.zeros(iters)
+    stp = np.zeros(iters)
+    rc = _check(_lib.lt_geostat_invert(C.byref(gr), C.byref(b), _dev_f64(S, "S"), C.byref(g), _dev_f64(y, "y"),
+                                       _dev_f64(s0, "s0"), int(iters), _stream_ptr(stream), _dev_f64(out, "s_out"),
+                                       mis.ctypes.data_as(_dp), stp.ctypes.data_as(_dp)))
+    return out, mis, stp, rc
 
 
 def lt_krylov_basis(handle: Handle, rhs):
