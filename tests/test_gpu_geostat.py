@@ -3,8 +3,8 @@ tomography case of Section 5.3) against the oracle.
 
 * lt_cov_apply against the dense exponential covariance on 2D and 3D grids (ragged against the
   64-cell tiles, anisotropic lengths, more vectors than one workgroup's 32).
-* One Gauss-Newton step from two linearisation points, and three steps of the whole inversion,
-  against the oracle's: the data are Crank-Nicolson heads of the true field (model error, as in
+* One Gauss-Newton step from two linearisation points, and three steps of the whole inversion
+  (with the multigrid and with the exact shift-and-invert preconditioner), against the oracle's: the data are Crank-Nicolson heads of the true field (model error, as in
   the paper) with 2 % noise.  Bars: h(s) 1e-9 of its largest entry; beta and s_{k+1} 1e-8
   (relative to |beta| and the largest |s_{k+1}|); the inversion's iterate 1e-8 and misfits 1e-7
   after three steps.  The heads' and Jacobian's errors, ~1e-12 of their scale at the solver
@@ -61,7 +61,9 @@ def _data(p, seed=7):
     return y, (0.02 * np.sqrt(np.mean(y0 ** 2))) ** 2
 
 
-def _opts(lt):
+def _opts(lt, precond="gmg"):
+    if precond == "exact":
+        return lt.make_opts(tol=1e-12, maxit=200, n_tau=2, precond=lt.LT_PRECOND_EXACT)
     return lt.make_opts(tol=1e-12, maxit=200)
 
 
@@ -88,15 +90,17 @@ def test_step_matches_oracle(lt, start):
     h.close()
 
 
-def test_inversion_matches_oracle(lt):
+@pytest.mark.parametrize("precond", ["gmg", "exact"])
+def test_inversion_matches_oracle(lt, precond):
     p = wl.make_problem("THT", n=(32, 32))
-    announce("geostat inversion")
+    announce("geostat inversion", precond)
     y, r = _data(p)
     iters = 3
     S = torch.tensor(p.S, dtype=torch.float64, device="cuda")
     s0 = torch.zeros(p.N, dtype=torch.float64, device="cuda")
     s, mis, stp, rc = lt.lt_geostat_invert(p.ndim, p.n, p.h, S, p.sources, p.q, p.receivers, p.times, p.nz_contour,
-                                           VAR, ELL, r, torch.tensor(y, device="cuda"), s0, iters, opts=_opts(lt))
+                                           VAR, ELL, r, torch.tensor(y, device="cuda"), s0, iters,
+                                           opts=_opts(lt, precond))
     assert rc == 0
     Q = exp_covariance(p.n, p.h, VAR, ELL, p.ndim)
     sr = np.zeros(p.N)
@@ -108,6 +112,7 @@ def test_inversion_matches_oracle(lt):
         sr = out["s_next"]
     es = np.abs(s.cpu().numpy() - sr).max() / np.abs(sr).max()
     em = np.abs(mis - np.array(mref)) / np.array(mref)
-    print(f"[geostat] inversion: s err {es:.2e}; misfit gpu {mis} oracle {mref}; steps {stp}", flush=True)
+    print(f"[geostat] inversion ({precond}): s err {es:.2e}; misfit gpu {mis} oracle {mref}; steps {stp}",
+          flush=True)
     assert es <= 1e-8 and em.max() <= 1e-7
     assert mis[-1] < mis[0]
