@@ -101,6 +101,8 @@ def _parse():
                     help="C5J: weighted tolerance of every variant (equal accuracy)")
     ap.add_argument("--relax-jacobian", type=float, default=0.3,
                     help="C5J: inner tolerance factor of every variant")
+    ap.add_argument("--tau-adapt", type=int, choices=[0, 1], default=0,
+                    help="C5J/C2: preconditioner shifts from the residual estimates (opts.tau_adapt)")
     ap.add_argument("--nu3d", type=int, default=2,
                     help="C5J: red-black sweeps before and after the coarse correction on the 3D problems")
     ap.add_argument("--maxit", type=int, default=48,
@@ -293,7 +295,7 @@ def main():
             lt.lt_unet_attach(hg, ng)
     prof_name = "mixed" if any(v[0] == "mixed" for v in variants) else variants[0][0]
     for name, prec, tol in variants:
-        opts = lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau, relax=args.relax,
+        opts = lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau, relax=args.relax, tau_adapt=args.tau_adapt,
                             precond=lt.LT_PRECOND_UNET_GMG if name == "learned" else lt.LT_PRECOND_GMG)
         prof_kind = lt.LT_PROF_POST_FINE if name == prof_name else 0
         dt, st, phi, prof = _run_variant(lt, hs, p, opts, args.steps, args.warmup, prof_kind)
@@ -574,6 +576,7 @@ def main_jacobian(args):
     res, fp64_samp = {}, None
     for name, prec in variants:
         opts = [lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau, maxit=args.maxit, relax=args.relax_jacobian,
+                             tau_adapt=args.tau_adapt,
                              precond=lt.LT_PRECOND_UNET_GMG if (name == "learned" and ok) else lt.LT_PRECOND_GMG,
                              **({"nu1": args.nu3d, "nu2": args.nu3d} if p.ndim == 3 else {}))
                 for p, ok in zip(ps, net_2d)]
@@ -622,7 +625,7 @@ def main_jacobian(args):
         big = max(range(len(ps)), key=lambda i: ps[i].N)
         p, h = ps[big], hs[big]
         o = lt.make_opts(tol=tol, precision=lt.LT_PREC_MIXED, n_tau=p.n_tau, maxit=args.maxit,
-                         relax=args.relax_jacobian, profile=lt.LT_PROF_SWEEP3D,
+                         relax=args.relax_jacobian, profile=lt.LT_PROF_SWEEP3D, tau_adapt=args.tau_adapt,
                          **({"nu1": args.nu3d, "nu2": args.nu3d} if p.ndim == 3 else {}))
         dK, dS = outs[big]
         _, _, stp = lt.lt_adjoint(h, p.sources, p.q, p.receivers, p.times, p.nz_contour, o, dlnK=dK, dlnS=dS)

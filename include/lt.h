@@ -191,7 +191,21 @@ typedef struct {
  *              LT_CONV_RELATIVE: every shift until ||r_k|| <= tol ||b||, the
  *              plain relative residual test of the experiments in Section
  *              4.1 (stricter: shifts of small weight are solved as far as
- *              the others). */
+ *              the others).
+ *   tau_adapt  0 (default): preconditioner shifts from n_tau / tau_reim in
+ *              turn.  1: after the first outer iteration each shift is
+ *              chosen from the residual estimates (the a-posteriori
+ *              estimate of Section 3, |w_k eta_k|: the least-squares residual
+ *              of each shift, weighted as in the convergence test): the
+ *              contour node with the largest weighted residual among those
+ *              not yet converged, over all right-hand sides of the call,
+ *              becomes the next shift (the V-cycle preconditioners take its
+ *              projection onto Re tau >= 0, i Im z for a node left of the
+ *              imaginary axis; LT_PRECOND_EXACT takes the nearest of the
+ *              schedule's shifts, so nothing more is factorised).  The paper
+ *              leaves the choice of shifts open (Sections 3 and 6); this is
+ *              the build's own rule.  Costs one small device-to-host copy
+ *              per outer iteration. */
 typedef struct {
     double tol;
     int maxit;
@@ -208,6 +222,7 @@ typedef struct {
     int graph;
     int method;
     int conv;
+    int tau_adapt;
 } lt_opts;
 
 /* Statistics of the last call.  Pointer members are optional host arrays the

@@ -51,14 +51,34 @@ def tau_schedule(shifts, n_tau):
     raise ValueError("n_tau must be 1 or 2")
 
 
-def flexible_shifted(K, m, b, taus, shifts, tol, maxit, method="gmres", weights=None, precond=None):
+def adaptive_shift(z, w, res, conv, candidates=None):
+    """The next preconditioner shift from the residual estimates: the unconverged shift z_k of
+    largest weighted residual w_k ||r_k||, or the nearest of ``candidates`` to it; without
+    candidates, z_k itself when Re z_k >= 0, else i Im z_k (a multigrid preconditioner needs a
+    non-negative real part).  None when every shift has converged."""
+    wr = np.where(conv, -np.inf, w * res)
+    k = int(np.argmax(wr))
+    if not np.isfinite(wr[k]):
+        return None
+    zk = complex(z[k])
+    if candidates is not None:
+        c = np.asarray(candidates, dtype=np.complex128)
+        return complex(c[np.argmin(np.abs(c - zk))])
+    return zk if zk.real >= 0 else complex(0.0, zk.imag)
+
+
+def flexible_shifted(K, m, b, taus, shifts, tol, maxit, method="gmres", weights=None, precond=None,
+                     adapt=False, candidates=None):
     """Algorithm 1 for one right-hand side b (real or complex [N]).
 
     ``taus``: preconditioner shifts used cyclically (tau_j = taus[(j - 1) % len]);
     ``shifts``: the z_k; a shift is converged when weights_k ||r_k|| <= tol ||b||, with
     r_k the small problem's residual (weights default 1: the relative test of
     Section 4.1).  ``precond(tau, v)``, if given, replaces the exact solve of
-    (K + tau M) u = v (a test hook for inexact preconditioners).  Returns a dict
+    (K + tau M) u = v (a test hook for inexact preconditioners).  ``adapt``: from the
+    second step on, tau_j = adaptive_shift(...) of the previous step's residuals (the build's
+    own rule for choosing shifts from the a-posteriori estimates; ``candidates`` as there)
+    instead of the cyclic schedule.  Returns a dict
     with x [nk, N], iters (steps taken), res [nk] (||r_k|| / ||b||), conv [nk],
     conv_at [nk] (step at which each shift met the
     test, 0 if never), V [N, iters + 1], U [N, iters], Hbar [iters + 1, iters],
@@ -93,6 +113,10 @@ def flexible_shifted(K, m, b, taus, shifts, tol, maxit, method="gmres", weights=
     breakdown = False
     for j in range(1, maxit + 1):
         tau = complex(taus[(j - 1) % len(taus)])
+        if adapt and j > 1:
+            t_ad = adaptive_shift(z, w, res, conv, candidates)
+            if t_ad is not None:
+                tau = t_ad
         T[j - 1] = tau
         u = solve(tau, V[:, j - 1]) if precond is None else np.asarray(precond(tau, V[:, j - 1]), dtype=np.complex128)
         U[:, j - 1] = u

@@ -114,7 +114,7 @@ int validate_opts(const lt_opts* o) {
         (o->precond != LT_PRECOND_GMG && o->precond != LT_PRECOND_UNET_GMG && o->precond != LT_PRECOND_EXACT) ||
         !(o->net_keep >= 0.0) ||
         (o->graph != 0 && o->graph != 1) || (o->method != LT_METHOD_GMRES && o->method != LT_METHOD_FOM) ||
-        (o->conv != LT_CONV_WEIGHTED && o->conv != LT_CONV_RELATIVE) ||
+        (o->conv != LT_CONV_WEIGHTED && o->conv != LT_CONV_RELATIVE) || (o->tau_adapt != 0 && o->tau_adapt != 1) ||
         (o->precision != LT_PREC_FP64 && o->precision != LT_PREC_MIXED)) {
         set_last_error("invalid lt_opts");
         return LT_EINVAL;
@@ -427,8 +427,41 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int rini
         }
     }
     out->converged = false;
+    // adaptive shifts: the weighted least-squares residuals of the last outer iteration
+    std::vector<double> hres(o.tau_adapt ? (size_t)R * Ks : 0);
+    std::vector<cdouble> cand;  // the exact preconditioner's candidates: the schedule's distinct shifts
+    for (const cdouble& t : plan.tau_sched)
+        if (std::find(cand.begin(), cand.end(), t) == cand.end()) cand.push_back(t);
     for (j = 0; j < jmax; ++j) {
         cdouble tau = plan.tau_sched[j % plan.tau_sched.size()];
+        if (o.tau_adapt && j > 0) {
+            LT_HIP(hipMemcpyAsync(hres.data(), ls.res, hres.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+            LT_HIP(hipMemcpyAsync(hact, active, R * sizeof(int), hipMemcpyDeviceToHost, st));
+            LT_HIP(hipStreamSynchronize(st));
+            double best = -1.0;
+            int kbest = -1;
+            for (int r = 0; r < R; ++r) {
+                if (!hact[r]) continue;
+                const std::vector<double>& om = r >= rinit ? plan.omega_init : plan.omega;
+                for (int k = 0; k < Ks; ++k) {
+                    const double w = om[k] * hres[(size_t)r * Ks + k];  // the convergence test's weighting
+                    if (w > o.tol && w > best) {
+                        best = w;
+                        kbest = k;
+                    }
+                }
+            }
+            if (kbest >= 0) {
+                const cdouble zc = plan.z[kbest];
+                if (exact) {
+                    tau = cand[0];
+                    for (const cdouble& c : cand)
+                        if (std::abs(c - zc) < std::abs(tau - zc)) tau = c;
+                } else {
+                    tau = zc.real() >= 0.0 ? zc : cdouble(0.0, zc.imag());
+                }
+            }
+        }
         LT_TRY(launch_iter_begin(st, R, active, inner_active, count, j, rprev));  // jdev = count + 3
         double* uj = U + (size_t)j * N2;
         double* vj = Q + (size_t)j * N2;

@@ -244,3 +244,31 @@ def test_adjoint_matches_oracle(lt):
     print(f"[adjoint] exact: dlnK {ek:.2e} dlnS {es:.2e}", flush=True)
     assert ek <= 1e-6 and es <= 1e-6
     h.close()
+
+
+@pytest.mark.parametrize("t", [0.06, 0.3])
+def test_adaptive_shifts_match_oracle(lt, t):
+    # opts.tau_adapt: after the first iteration the next shift is the nearer of the two factorised
+    # shifts to the unconverged node of largest weighted residual; the oracle's Algorithm 1 with
+    # the same rule takes the same steps
+    from dataclasses import replace
+    p = wl.make_problem("W1")
+    p = replace(p, times=np.array([t]) * wl.T_D)
+    announce("adaptive shifts, exact", t)
+    h = device_problem(lt, p)
+    ref = heads_problem(p)
+    o = lt.make_opts(tol=1e-10, maxit=400, n_tau=2, precond=lt.LT_PRECOND_EXACT, conv=lt.LT_CONV_RELATIVE,
+                     tau_adapt=1)
+    phi, st = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, o)
+    assert st["rc"] == 0
+    check_heads(phi.cpu().numpy(), ref, 1e-7, f"W1 t {t} adaptive exact")
+    K, m = assemble(p.n, p.h, p.kappa, p.S, p.bc, ndim=p.ndim)
+    z = talbot_nodes(p.nz_contour, p.times[0])[0]
+    sched = tau_schedule(z, 2)
+    b = point_weights(p.n, p.h, p.sources).toarray()[0]
+    want = flexible_shifted(K, m, b, sched, z, 1e-10, 400, adapt=True, candidates=[sched[0], sched[3]])["iters"]
+    fixed = flexible_shifted(K, m, b, sched, z, 1e-10, 400)["iters"]
+    got = int(st["iters_per_rhs"][0])
+    print(f"[iters] adaptive exact t {t}: gpu {got} oracle {want} (fixed schedule {fixed})", flush=True)
+    assert abs(got - want) <= 1
+    h.close()
