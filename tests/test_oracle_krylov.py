@@ -99,3 +99,28 @@ def test_tau_schedule_follows_the_rule_of_section_3():
     assert t == [lo, lo, lo, hi, hi]
     assert lo.real < 0 < lo.imag  # the paper's first preconditioner shift has a negative real part
     assert tau_schedule(z, 1) == [lo]
+
+
+def test_adaptive_shift_rule():
+    from oracle.krylov import adaptive_shift
+    z = np.array([-3 + 4j, 1 + 2j, 5 + 1j])
+    w = np.array([1.0, 1.0, 0.5])
+    res = np.array([0.1, 0.3, 0.9])
+    conv = np.array([False, False, False])
+    # weighted residuals 0.1, 0.3, 0.45: the third node
+    assert adaptive_shift(z, w, res, conv) == 5 + 1j
+    # converged shifts are skipped; a node left of the imaginary axis is projected onto it
+    conv2 = np.array([False, True, True])
+    assert adaptive_shift(z, w, res, conv2) == 4j
+    # candidates: the nearest one
+    assert adaptive_shift(z, w, res, conv2, candidates=[-2 + 3j, 6 + 0j]) == -2 + 3j
+    assert adaptive_shift(z, w, res, np.array([True, True, True])) is None
+
+
+def test_adaptive_shifts_still_solve_the_systems():
+    K, m, b, z = _problem()
+    out = flexible_shifted(K, m, b, tau_schedule(z, 2), z, tol=1e-9, maxit=80, adapt=True)
+    assert out["conv"].all() and len(set(np.round(out["T"], 6))) > 2
+    for k in range(z.size):
+        xd = shift_invert(K, m, z[k], b)
+        assert np.linalg.norm(out["x"][k] - xd) <= 1e-6 * np.linalg.norm(xd)
