@@ -165,7 +165,7 @@ int refine_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, s
         LT_TRY(mg_vcycle<float>(h, tau, o.nu1, o.nu2, R, inner_active, e32, lo32, &ra));
         if (nparts < 0) {
             LT_TRY(launch_inner_update<float>(st, L0, tau, R, e32, U, ustride, jdev, rho, lo32_next, part,
-                                              inner_active, h->cp3d ? 1 : 0));
+                                              inner_active, h->cp3d ? 1 : 0, ra.list));
             nparts = reduce_blocks(h->N, R);
         }
     } else {
@@ -174,7 +174,7 @@ int refine_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, s
         LT_TRY(mg_vcycle<double>(h, tau, o.nu1, o.nu2, R, inner_active, e64, lo64 ? lo64 : rho, &ra));
         if (nparts < 0) {
             LT_TRY(launch_inner_update<double>(st, L0, tau, R, e64, U, ustride, jdev, rho, lo64, part,
-                                               inner_active, lo64 ? 1 : 0));
+                                               inner_active, lo64 ? 1 : 0, ra.list));
             nparts = reduce_blocks(h->N, R);
         } else {
             *swapped = 1;

@@ -39,7 +39,7 @@ template <typename T>
 // cp: e is read and lo written in colour-planar order
 int launch_inner_update(hipStream_t st, LevelView<double> L, cdouble tau, int R, const T* e, double* u,
                         size_t ustride, const int* jcol, double* rho, T* lo, double* part, const int* inner_active,
-                        int cp = 0);
+                        int cp = 0, const int* list = nullptr);
 // out[r][k] = ||b_r - (K + z_k M) U_r y_rk|| / beta_r for every right-hand side and shift,
 // from K applied once to each used basis column (KU: R * max(mmax, 1) * 2N doubles,
 // part: R * Ks * reduce_blocks(N, R) doubles).

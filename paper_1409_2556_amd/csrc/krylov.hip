@@ -177,6 +177,76 @@ __global__ void k_inner_update(LevelView<double> L, double tr, double ti, const 
     if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = o[0];
 }
 
+// The same update for the RB right-hand sides of a group (group_rhs over the list of the
+// cycle that produced e): a thread loads the FP64 coefficients and neighbour positions of
+// its cells once for the group.  part[r * gridDim.x + block] as above.
+template <typename T, int RB>
+__global__ void k_inner_update_rb(LevelView<double> L, double tr, double ti, const T* __restrict__ e,
+                                  double* __restrict__ u, size_t ustride, const int* __restrict__ jcol,
+                                  double* __restrict__ rho, T* __restrict__ lo, double* __restrict__ part,
+                                  const int* __restrict__ list, int R, int cp) {
+    int rs[RB];
+    group_rhs<RB>(list, R, blockIdx.y, rs);
+    if (rs[0] < 0) return;
+    const size_t N = L.N;
+    const size_t jo = jcol ? 2 * N * (size_t)*jcol : 0;
+    const int half = L.N >> 1, sy = L.nx, sz = L.nx * L.ny;
+    double v[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) v[q] = 0.0;
+    for (int i = blockIdx.x * kB + threadIdx.x; i < L.N; i += gridDim.x * kB) {
+        const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+        // positions of e (the cycle's output): natural, or colour-planar, where every
+        // neighbour has the other colour; a missing neighbour has coupling 0 and a valid index
+        const int c = (x + y + z) & 1;
+        const int own = cp ? c * half + (i >> 1) : i;
+        const bool hx = x + 1 < L.nx, lx = x > 0, hy = y + 1 < L.ny, ly = y > 0, hz = z + 1 < L.nz, lz = z > 0;
+        const int nb[6] = {hx ? i + 1 : i, lx ? i - 1 : i, hy ? i + sy : i, ly ? i - sy : i, hz ? i + sz : i,
+                           lz ? i - sz : i};
+        const double tc[6] = {hx ? L.Tx[i] : 0.0, lx ? L.Tx[i - 1] : 0.0, hy ? L.Ty[i] : 0.0,
+                              ly ? L.Ty[i - sy] : 0.0, hz ? L.Tz[i] : 0.0, lz ? L.Tz[i - sz] : 0.0};
+        int np[6];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) np[a] = cp ? (1 - c) * half + (nb[a] >> 1) : nb[a];
+        const double dre = L.D[i] + tr * L.m[i], dim = ti * L.m[i];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int r = rs[q];
+            if (r < 0) continue;
+            const T* er = e + 2 * N * r;
+            const T* ei = er + N;
+            double sre = 0, sim = 0;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                sre += tc[a] * (double)er[np[a]];
+                sim += tc[a] * (double)ei[np[a]];
+            }
+            const double xre = (double)er[own], xim = (double)ei[own];
+            const double are = dre * xre - dim * xim - sre;
+            const double aim = dre * xim + dim * xre - sim;
+            double* ur = u + ustride * r + jo;
+            double* rr = rho + 2 * N * r;
+            ur[i] += xre;
+            ur[i + N] += xim;
+            const double nre = rr[i] - are, nim = rr[i + N] - aim;
+            rr[i] = nre;
+            rr[i + N] = nim;
+            if (lo) {
+                lo[2 * N * r + own] = (T)nre;
+                lo[2 * N * r + N + own] = (T)nim;
+            }
+            v[q] += nre * nre + nim * nim;
+        }
+    }
+    double o[RB];
+    block_reduce<RB>(v, o);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+            if (rs[q] >= 0) part[(size_t)rs[q] * gridDim.x + blockIdx.x] = o[q];
+    }
+}
+
 // inner_active[r] = active[r] && ||rho_r|| > eta_r && step + 1 < inner_max; counts vcycles.
 // count[0] = right-hand sides still refining; count[1] = step + 1 if any right-hand
 // side was refined in this step (the number of steps this outer iteration needed).
@@ -1299,17 +1369,21 @@ int launch_iter_begin(hipStream_t st, int R, const int* active, int* inner_activ
 template <typename T>
 int launch_inner_update(hipStream_t st, LevelView<double> L, cdouble tau, int R, const T* e, double* u,
                         size_t ustride, const int* jcol, double* rho, T* lo, double* part, const int* inner_active,
-                        int cp) {
+                        int cp, const int* list) {
     int nb = reduce_blocks(L.N, R);
-    k_inner_update<T><<<dim3(nb, R), kB, 0, st>>>(L, tau.real(), tau.imag(), e, u, ustride, jcol, rho, lo, part,
-                                                  inner_active, cp);
+    if (list)
+        k_inner_update_rb<T, kSweepRhs><<<dim3(nb, (R + kSweepRhs - 1) / kSweepRhs), kB, 0, st>>>(
+            L, tau.real(), tau.imag(), e, u, ustride, jcol, rho, lo, part, list, R, cp);
+    else
+        k_inner_update<T><<<dim3(nb, R), kB, 0, st>>>(L, tau.real(), tau.imag(), e, u, ustride, jcol, rho, lo, part,
+                                                      inner_active, cp);
     LT_HIP(hipGetLastError());
     return 0;
 }
 template int launch_inner_update<double>(hipStream_t, LevelView<double>, cdouble, int, const double*, double*,
-                                         size_t, const int*, double*, double*, double*, const int*, int);
+                                         size_t, const int*, double*, double*, double*, const int*, int, const int*);
 template int launch_inner_update<float>(hipStream_t, LevelView<double>, cdouble, int, const float*, double*,
-                                        size_t, const int*, double*, float*, double*, const int*, int);
+                                        size_t, const int*, double*, float*, double*, const int*, int, const int*);
 
 int launch_inner_finalize(hipStream_t st, int nb, int R, const double* part, const int* active, const double* worst,
                           double relax_tol, double tol, int inner_max, int* inner_active, int* vcycles, int* count,

@@ -248,10 +248,29 @@ struct RefineArgs {
     void* lo;
     double* part;
     int* nparts;
+    const int* list = nullptr;  // set by the cycle: its list of active right-hand sides (group_rhs), if any
 };
+
+// Right-hand sides per thread of the 3D multigrid kernels and the refinement update.
+constexpr int kSweepRhs = 4;
+
+// The right-hand sides that a kernel serves in groups of RB.  With a list (list[0] = the
+// number of active right-hand sides, list[1 + j] = the j-th active index in increasing
+// order), group g takes active ones g RB .. g RB + RB - 1, so every group but the last is
+// full and what a group loads once (coefficients, indices) serves RB right-hand sides;
+// without one, group g takes g RB .. g RB + RB - 1 of all R.  -1: no right-hand side there.
+template <int RB>
+__device__ __forceinline__ void group_rhs(const int* __restrict__ list, int R, int g, int (&rs)[RB]) {
+    const int n = list ? list[0] : R;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        const int j = g * RB + q;
+        rs[q] = j < n ? (list ? list[1 + j] : j) : -1;
+    }
+}
 template <typename T>
 int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* active,
-              T* x0, const T* b0, const RefineArgs* refine = nullptr);
+              T* x0, const T* b0, RefineArgs* refine = nullptr);
 template <typename T>
 int apply_operator(lt_handle* h, int level, cdouble tau, const T* x, T* y, int R, const int* active);
 template <typename S, typename D>

@@ -22,7 +22,6 @@
 namespace lt {
 
 static constexpr int kBlock = 256;
-static constexpr int kSweepRhs = 4;  // right-hand sides per thread of a one-colour half-sweep
 static constexpr int kMaxCoarseDense = 512;
 
 int DevBuf::reserve(size_t n) {
@@ -268,24 +267,43 @@ __global__ void k_gs_color(LevelView<T> L, T tr, T ti, int color, T* __restrict_
     xi[i] = v.im;
 }
 
+// The list of active right-hand sides that group_rhs reads, from R <= 1024 flags: one workgroup of 1024 threads, one flag per
+// thread; positions from the wave's ballot and the counts of the waves before it.
+__global__ void __launch_bounds__(1024) k_active_list(const int* __restrict__ active, int R, int* __restrict__ list) {
+    __shared__ int wcount[16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const bool on = t < R && active[t] != 0;
+    const unsigned long long m = __ballot(on ? 1 : 0);
+    if (lane == 0) wcount[w] = __popcll(m);
+    __syncthreads();
+    int base = 0, total = 0;
+    for (int k = 0; k < 16; ++k) {
+        base += k < w ? wcount[k] : 0;
+        total += wcount[k];
+    }
+    if (on) list[1 + base + __popcll(m & ((1ull << lane) - 1ull))] = t;
+    if (t == 0) list[0] = total;
+}
+
 // The same half-sweep with one thread per cell of the colour (nx even): thread k takes
 // the k-th cell of that colour in storage order, so no lane idles.  A thread serves its
-// cell for RB consecutive right-hand sides: the coefficients are loaded once and reused
-// (they are shared by every right-hand side), and the RB updates are independent.
+// cell for the RB right-hand sides of its group (group_rhs): the coefficients are loaded
+// once and reused (they are shared by every right-hand side), and the RB updates are
+// independent.  prof: per launch, prof_once bytes plus prof_bytes per right-hand side served.
 template <typename T, int RB, bool CP>
 __global__ void k_gs_color_half(LevelView<T> L, T tr, T ti, int color, T* __restrict__ x,
-                                const T* __restrict__ b, const int* __restrict__ active, int R,
-                                unsigned long long* __restrict__ prof, unsigned long long prof_bytes) {
-    const int r0 = blockIdx.y * RB;
-    bool any = false;
+                                const T* __restrict__ b, const int* __restrict__ list, int R,
+                                unsigned long long* __restrict__ prof, unsigned long long prof_bytes,
+                                unsigned long long prof_once) {
+    int rs[RB];
+    group_rhs<RB>(list, R, blockIdx.y, rs);
+    if (rs[0] < 0) return;
+    if (prof && blockIdx.x == 0 && threadIdx.x == 0) {
+        unsigned long long add = blockIdx.y == 0 ? prof_once : 0ull;
 #pragma unroll
-    for (int q = 0; q < RB; ++q) {
-        const int r = r0 + q;
-        const bool on = r < R && (!active || active[r]);
-        any = any || on;
-        if (on && prof && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(prof, prof_bytes);
+        for (int q = 0; q < RB; ++q) add += rs[q] >= 0 ? prof_bytes : 0ull;
+        atomicAdd(prof, add);
     }
-    if (!any) return;
     const int W = L.nx >> 1;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (L.N >> 1)) return;
@@ -312,8 +330,8 @@ __global__ void k_gs_color_half(LevelView<T> L, T tr, T ti, int color, T* __rest
     for (int a = 0; a < 6; ++a) np[a] = CP ? (1 - color) * half + (nb[a] >> 1) : nb[a];
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
-        const int r = r0 + q;
-        if (r >= R || (active && !active[r])) continue;
+        const int r = rs[q];
+        if (r < 0) continue;
         T* xr = x + 2 * N * r;
         T* xi = xr + N;
         const T* br = b + 2 * N * r;
@@ -333,32 +351,34 @@ __global__ void k_gs_color_half(LevelView<T> L, T tr, T ti, int color, T* __rest
 // prof (fine level, opts.profile = LT_PROF_SWEEP3D): every launch bracketed by HIP events
 // on the stream and its algorithmic bytes counted: per active right-hand side, b of the
 // colour's cells in, x of the other colour in, x of the colour out (complex: 12 bytes of T
-// per cell in FP32 terms, 3 sizeof(T) per cell), plus the coefficients Tx, Ty, Tz of every
-// cell and D, m of the colour's cells, shared by the R right-hand sides (4 sizeof(T) per cell)
+// per cell in FP32 terms, 3 sizeof(T) per cell), plus, once per launch, the coefficients
+// Tx, Ty, Tz of every cell and D, m of the colour's cells (4 sizeof(T) per cell).
+// list: the active right-hand sides (group_rhs), or null for all R; active: their flags,
+// for the one-thread-per-cell fallback of odd nx.
 template <typename T>
 static int gs_half_sweep(lt_handle* h, hipStream_t st, const LevelView<T>& L, T tr, T ti, int color, T* x,
-                         const T* b, int R, const int* active, bool fine, bool cp = false) {
+                         const T* b, int R, const int* active, const int* list, bool fine, bool cp = false) {
     if ((L.nx & 1) == 0) {
         const dim3 grid((unsigned)((L.N / 2 + 255) / 256), (R + kSweepRhs - 1) / kSweepRhs);
         if (fine && h->prof_target == LT_PROF_SWEEP3D) {
             unsigned long long* pc = nullptr;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             LT_TRY(prof_begin(h, LT_PROF_SWEEP3D, &pc, &e0, &e1));
-            const unsigned long long per = (unsigned long long)((double)L.N * 3.0 * sizeof(T) +
-                                                                (double)L.N * 4.0 * sizeof(T) / R);
+            const unsigned long long per = (unsigned long long)L.N * 3ull * sizeof(T);
+            const unsigned long long once = (unsigned long long)L.N * 4ull * sizeof(T);
             if (cp)
                 hipExtLaunchKernelGGL((k_gs_color_half<T, kSweepRhs, true>), grid, dim3(256), 0, st, e0, e1, 0, L, tr,
-                                      ti, color, x, b, active, R, pc, per);
+                                      ti, color, x, b, list, R, pc, per, once);
             else
                 hipExtLaunchKernelGGL((k_gs_color_half<T, kSweepRhs, false>), grid, dim3(256), 0, st, e0, e1, 0, L, tr,
-                                      ti, color, x, b, active, R, pc, per);
+                                      ti, color, x, b, list, R, pc, per, once);
             LT_TRY(prof_end(h, LT_PROF_SWEEP3D));
         } else if (cp) {
-            k_gs_color_half<T, kSweepRhs, true><<<grid, 256, 0, st>>>(L, tr, ti, color, x, b, active, R, nullptr,
-                                                                      0ull);
+            k_gs_color_half<T, kSweepRhs, true><<<grid, 256, 0, st>>>(L, tr, ti, color, x, b, list, R, nullptr,
+                                                                      0ull, 0ull);
         } else {
-            k_gs_color_half<T, kSweepRhs, false><<<grid, 256, 0, st>>>(L, tr, ti, color, x, b, active, R, nullptr,
-                                                                       0ull);
+            k_gs_color_half<T, kSweepRhs, false><<<grid, 256, 0, st>>>(L, tr, ti, color, x, b, list, R, nullptr,
+                                                                       0ull, 0ull);
         }
     } else {
         k_gs_color<T><<<dim3((unsigned)((L.N + 255) / 256), R), 256, 0, st>>>(L, tr, ti, color, x, b, active);
@@ -368,18 +388,16 @@ static int gs_half_sweep(lt_handle* h, hipStream_t st, const LevelView<T>& L, T 
 }
 
 // Coarse right-hand side = sum over the aggregate of the fine residual b - A x;
-// the coarse iterate is cleared.  A thread serves its coarse cell for RB consecutive
-// right-hand sides (the coefficients of the aggregate are loaded once).
+// the coarse iterate is cleared.  A thread serves its coarse cell for the RB right-hand
+// sides of its group (group_rhs; the coefficients of the aggregate are loaded once).
 template <typename T, int RB>
 __global__ void k_resid_restrict(LevelView<T> F, int cnx, int cny, int cnz, int cox, int coy, int coz,
                                  T tr, T ti, const T* __restrict__ xf, const T* __restrict__ bf,
-                                 T* __restrict__ bc, T* __restrict__ xc, const int* __restrict__ active, int R,
+                                 T* __restrict__ bc, T* __restrict__ xc, const int* __restrict__ list, int R,
                                  int cpf, int cpc) {
-    const int r0 = blockIdx.y * RB;
-    bool any = false;
-#pragma unroll
-    for (int q = 0; q < RB; ++q) any = any || (r0 + q < R && (!active || active[r0 + q]));
-    if (!any) return;
+    int rs[RB];
+    group_rhs<RB>(list, R, blockIdx.y, rs);
+    if (rs[0] < 0) return;
     const int Nc = cnx * cny * cnz;
     int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= Nc) return;
@@ -412,8 +430,8 @@ __global__ void k_resid_restrict(LevelView<T> F, int cnx, int cny, int cnz, int 
                 for (int a = 0; a < 6; ++a) np[a] = cpf ? (1 - c) * half + (nb[a] >> 1) : nb[a];
 #pragma unroll
                 for (int q = 0; q < RB; ++q) {
-                    const int r = r0 + q;
-                    if (r >= R || (active && !active[r])) continue;
+                    const int r = rs[q];
+                    if (r < 0) continue;
                     const T* xr = xf + 2 * N * r;
                     const T* xi = xr + N;
                     const T* br = bf + 2 * N * r;
@@ -433,8 +451,8 @@ __global__ void k_resid_restrict(LevelView<T> F, int cnx, int cny, int cnz, int 
     const int Ic = cpc ? cp_at(I, Xc, Yc, Zc, Nc) : I;
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
-        const int r = r0 + q;
-        if (r >= R || (active && !active[r])) continue;
+        const int r = rs[q];
+        if (r < 0) continue;
         bc[2 * M * r + Ic] = acc[q].re;
         bc[2 * M * r + M + Ic] = acc[q].im;
         xc[2 * M * r + Ic] = 0;
@@ -442,86 +460,101 @@ __global__ void k_resid_restrict(LevelView<T> F, int cnx, int cny, int cnz, int 
     }
 }
 
-// Prolongation P e_coarse at fine cell (x, y, z): cell-centred linear interpolation
-// along every halved axis (the ghost beyond a wall mirrors the boundary cell with
-// parity g: -1 Dirichlet, +1 Neumann).
-template <typename T>
-__device__ __forceinline__ cpx<T> prolong_value(int x, int y, int z, int cnx, int cny, int cnz, int cox, int coy,
-                                                int coz, const T* glo, const T* ghi, const T* __restrict__ er,
-                                                const T* __restrict__ ei, int cpc = 0) {
-    int ia[3][2];
-    T wa[3][2];
-    int na[3];
-    const int c3[3] = {x, y, z};
+// x_fine += P e_coarse for the RB right-hand sides of a group (group_rhs).  A thread takes one
+// position of the fine vectors (colour-planar when cpf) and forms the interpolation's taps
+// once for the group: two per halved axis, an absent one with weight 0 at a valid index, so
+// the eight loads of a right-hand side issue without a data-dependent loop.  c0only: colour-0
+// cells only (positions below N/2 when cpf), for a post-smoother that starts with colour 1:
+// that half-sweep sets every colour-1 cell from its colour-0 neighbours without reading it.
+template <typename T, int RB>
+__global__ void k_prolong_rb(int fnx, int fny, int fnz, int cnx, int cny, int cnz, int cox, int coy, int coz,
+                             T glox, T ghix, T gloy, T ghiy, T gloz, T ghiz, const T* __restrict__ ec,
+                             T* __restrict__ xf, const int* __restrict__ list, int R, int cpf, int cpc, int c0only) {
+    int rs[RB];
+    group_rhs<RB>(list, R, blockIdx.y, rs);
+    if (rs[0] < 0) return;
+    const int Nf = fnx * fny * fnz;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;  // position in the fine vectors
+    if (p >= ((c0only && cpf) ? (Nf >> 1) : Nf)) return;
+    int c3[3];
+    if (cpf) {
+        const int half = Nf >> 1, c = p >= half ? 1 : 0, k = p - c * half, W = fnx >> 1;
+        const int row = k / W;
+        c3[1] = row % fny;
+        c3[2] = row / fny;
+        c3[0] = 2 * (k - row * W) + ((c3[1] + c3[2] + c) & 1);
+    } else {
+        c3[0] = p % fnx;
+        c3[1] = (p / fnx) % fny;
+        c3[2] = p / (fnx * fny);
+        if (c0only && ((c3[0] + c3[1] + c3[2]) & 1)) return;
+    }
     const int co[3] = {cox, coy, coz};
     const int cn[3] = {cnx, cny, cnz};
-    for (int a = 0; a < 3; ++a) {
-        if (!co[a]) {
-            ia[a][0] = c3[a];
-            wa[a][0] = 1;
-            na[a] = 1;
-            continue;
-        }
-        int I = c3[a] >> 1;
-        int J = (c3[a] & 1) ? I + 1 : I - 1;
-        if (J < 0) {
-            ia[a][0] = I;
-            wa[a][0] = T(0.75) + T(0.25) * glo[a];
-            na[a] = 1;
-        } else if (J >= cn[a]) {
-            ia[a][0] = I;
-            wa[a][0] = T(0.75) + T(0.25) * ghi[a];
-            na[a] = 1;
-        } else {
-            ia[a][0] = I;
-            wa[a][0] = T(0.75);
-            ia[a][1] = J;
-            wa[a][1] = T(0.25);
-            na[a] = 2;
-        }
-    }
-    cpx<T> acc = {0, 0};
-    for (int c = 0; c < na[2]; ++c)
-        for (int b = 0; b < na[1]; ++b)
-            for (int a = 0; a < na[0]; ++a) {
-                T w = wa[0][a] * wa[1][b] * wa[2][c];
-                int J = ia[0][a] + cnx * (ia[1][b] + cny * ia[2][c]);
-                if (cpc) J = cp_at(J, ia[0][a], ia[1][b], ia[2][c], cnx * cny * cnz);
-                acc.re += w * er[J];
-                acc.im += w * ei[J];
-            }
-    return acc;
-}
-
-// x_fine += P e_coarse with cell-centred linear interpolation per halved axis.
-template <typename T>
-__global__ void k_prolong(int fnx, int fny, int fnz, int cnx, int cny, int cnz, int cox, int coy, int coz,
-                          T glox, T ghix, T gloy, T ghiy, T gloz, T ghiz, const T* __restrict__ ec,
-                          T* __restrict__ xf, const int* __restrict__ active, int cpf, int cpc) {
-    int r = blockIdx.y;
-    if (active && !active[r]) return;
-    const int Nf = fnx * fny * fnz;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= Nf) return;
-    int x = i % fnx, y = (i / fnx) % fny, z = i / (fnx * fny);
     const T glo[3] = {glox, gloy, gloz};
     const T ghi[3] = {ghix, ghiy, ghiz};
-    const size_t Mc = (size_t)cnx * cny * cnz;
-    const T* er = ec + 2 * Mc * r;
-    const cpx<T> acc = prolong_value<T>(x, y, z, cnx, cny, cnz, cox, coy, coz, glo, ghi, er, er + Mc, cpc);
+    int ia[3][2];
+    T wa[3][2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!co[a]) {
+            ia[a][0] = ia[a][1] = c3[a];
+            wa[a][0] = T(1);
+            wa[a][1] = T(0);
+            continue;
+        }
+        // cell-centred linear interpolation: 3/4 of the parent, 1/4 of its neighbour on the
+        // child's side; beyond a wall the ghost mirrors the parent with parity glo / ghi
+        const int I = c3[a] >> 1, J = (c3[a] & 1) ? I + 1 : I - 1;
+        ia[a][0] = I;
+        if (J < 0 || J >= cn[a]) {
+            ia[a][1] = I;
+            wa[a][0] = T(0.75) + T(0.25) * (J < 0 ? glo[a] : ghi[a]);
+            wa[a][1] = T(0);
+        } else {
+            ia[a][1] = J;
+            wa[a][0] = T(0.75);
+            wa[a][1] = T(0.25);
+        }
+    }
+    const int Mc = cnx * cny * cnz;
+    int J[8];
+    T W[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int a = t & 1, b = (t >> 1) & 1, c = t >> 2;
+        W[t] = wa[0][a] * wa[1][b] * wa[2][c];
+        const int idx = ia[0][a] + cnx * (ia[1][b] + cny * ia[2][c]);
+        J[t] = cpc ? cp_at(idx, ia[0][a], ia[1][b], ia[2][c], Mc) : idx;
+    }
     const size_t Nfs = Nf;
-    const int p = cpf ? cp_at(i, x, y, z, Nf) : i;
-    xf[2 * Nfs * r + p] += acc.re;
-    xf[2 * Nfs * r + Nfs + p] += acc.im;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        const int r = rs[q];
+        if (r < 0) continue;
+        const T* er = ec + 2 * (size_t)Mc * r;
+        const T* ei = er + Mc;
+        cpx<T> acc = {0, 0};
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            acc.re += W[t] * er[J[t]];
+            acc.im += W[t] * ei[J[t]];
+        }
+        xf[2 * Nfs * r + p] += acc.re;
+        xf[2 * Nfs * r + Nfs + p] += acc.im;
+    }
 }
 
 // The first half-sweep of red-black Gauss-Seidel from x = 0: colour-0 cells see only
 // zero neighbours and take b / d, colour-1 cells stay 0.  Replaces clearing x and the
-// first sweep of colour 0.  RB right-hand sides per thread (D and m loaded once).
+// first sweep of colour 0.  The RB right-hand sides of a group (group_rhs) per thread
+// (D and m loaded once).
 template <typename T, int RB>
 __global__ void k_gs_first(LevelView<T> L, T tr, T ti, T* __restrict__ x, const T* __restrict__ b,
-                           const int* __restrict__ active, int R, int cp) {
-    const int r0 = blockIdx.y * RB;
+                           const int* __restrict__ list, int R, int cp) {
+    int rs[RB];
+    group_rhs<RB>(list, R, blockIdx.y, rs);
+    if (rs[0] < 0) return;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;  // position in the vectors
     if (p >= L.N) return;
     int i = p, c0 = 0;
@@ -539,8 +572,8 @@ __global__ void k_gs_first(LevelView<T> L, T tr, T ti, T* __restrict__ x, const 
     const size_t N = L.N;
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
-        const int r = r0 + q;
-        if (r >= R || (active && !active[r])) continue;
+        const int r = rs[q];
+        if (r < 0) continue;
         T* xr = x + 2 * N * r;
         T* xi = xr + N;
         if (c0) {
@@ -878,7 +911,7 @@ template int apply_operator<float>(lt_handle*, int, cdouble, const float*, float
 
 template <typename T>
 int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* active, T* x0, const T* b0,
-              const RefineArgs* refine) {
+              RefineArgs* refine) {
     hipStream_t st = h->stream;
     const int nl = (int)h->levels.size();
     const T tr = (T)tau.real(), ti = (T)tau.imag();
@@ -933,9 +966,21 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
         if (!xpost[l]) return rc;
     }
     xpost[0] = x0;
+    // the generic levels' kernels take the active right-hand sides as a list (group_rhs)
+    int* alist = nullptr;
+    if (!fused2d && active) {
+        static_assert(kMaxRhs <= 1024, "k_active_list takes one flag per thread of 1024");
+        alist = wsp<int>(h, "mgalist", (size_t)R + 1, &rc);
+        if (!alist) return rc;
+    }
     const CoarseInverse* ci = mg_coarse_inverse(h, tau, &rc);
     if (rc < 0) return rc;
     if (h->arena_plan) return 0;  // sizes counted, nothing launched
+    if (alist) {
+        k_active_list<<<1, 1024, 0, st>>>(active, R, alist);
+        LT_HIP(hipGetLastError());
+    }
+    if (refine) refine->list = alist;
     // ghost parity of the correction at a wall: odd at a Dirichlet wall, even at
     // a no-flux one (a water-table wall carries no conductive flux either)
     const T gsign[2] = {T(-1), T(1)};
@@ -959,17 +1004,17 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
             if (nu1 > 0) {
                 // from x = 0 (level 0 here; coarser levels are cleared by the restriction)
                 k_gs_first<T, kSweepRhs><<<dim3(nblk(L.N), (R + kSweepRhs - 1) / kSweepRhs), kBlock, 0, st>>>(
-                    v, tr, ti, xpre[l], bs[l], active, R, cpl(l));
-                LT_TRY(gs_half_sweep<T>(h, st, v, tr, ti, 1, xpre[l], bs[l], R, active, l == 0, cpl(l)));
+                    v, tr, ti, xpre[l], bs[l], alist, R, cpl(l));
+                LT_TRY(gs_half_sweep<T>(h, st, v, tr, ti, 1, xpre[l], bs[l], R, active, alist, l == 0, cpl(l)));
             } else if (l == 0) {
                 k_zero<T><<<dim3(nblk(per), R), kBlock, 0, st>>>(xpre[0], per, active);
             }
             for (int s = 1; s < nu1; ++s)
                 for (int c = 0; c < 2; ++c)
-                    LT_TRY(gs_half_sweep<T>(h, st, v, tr, ti, c, xpre[l], bs[l], R, active, l == 0, cpl(l)));
+                    LT_TRY(gs_half_sweep<T>(h, st, v, tr, ti, c, xpre[l], bs[l], R, active, alist, l == 0, cpl(l)));
             k_resid_restrict<T, kSweepRhs><<<dim3(nblk(C.N), (R + kSweepRhs - 1) / kSweepRhs), kBlock, 0, st>>>(
                 v, C.n[0], C.n[1], C.n[2], C.coarsened_from_fine[0], C.coarsened_from_fine[1],
-                C.coarsened_from_fine[2], tr, ti, xpre[l], bs[l], bs[l + 1], xpre[l + 1], active, R, cpl(l),
+                C.coarsened_from_fine[2], tr, ti, xpre[l], bs[l], bs[l + 1], xpre[l + 1], alist, R, cpl(l),
                 cpl(l + 1));
             LT_HIP(hipGetLastError());
         }
@@ -1010,7 +1055,7 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
             LevelView<T> v = view<T>(L);
             for (int s = 0; s < 64; ++s)
                 for (int c = 0; c < 2; ++c)
-                    LT_TRY(gs_half_sweep<T>(h, st, v, tr, ti, c, xpre[lc], bs[lc], R, active, lc == 0));
+                    LT_TRY(gs_half_sweep<T>(h, st, v, tr, ti, c, xpre[lc], bs[lc], R, active, alist, lc == 0));
         }
         LT_HIP(hipGetLastError());
         xpost[lc] = xpre[lc];
@@ -1040,14 +1085,16 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
             }
             if (prof) LT_TRY(prof_end(h, LT_PROF_POST_FINE));
         } else {
-            dim3 grid(nblk(L.N), R);
-            k_prolong<T><<<grid, kBlock, 0, st>>>(L.n[0], L.n[1], L.n[2], C.n[0], C.n[1], C.n[2],
-                                                  C.coarsened_from_fine[0], C.coarsened_from_fine[1],
-                                                  C.coarsened_from_fine[2], g(0), g(1), g(2), g(3), g(4), g(5),
-                                                  xpost[l + 1], xpre[l], active, cpl(l), cpl(l + 1));
+            // the post-smoother below starts with colour 1, which overwrites those cells
+            const int c0only = nu2 >= 1 ? 1 : 0;
+            const size_t np = (c0only && cpl(l)) ? L.N / 2 : L.N;
+            k_prolong_rb<T, kSweepRhs><<<dim3(nblk(np), (R + kSweepRhs - 1) / kSweepRhs), kBlock, 0, st>>>(
+                L.n[0], L.n[1], L.n[2], C.n[0], C.n[1], C.n[2], C.coarsened_from_fine[0], C.coarsened_from_fine[1],
+                C.coarsened_from_fine[2], g(0), g(1), g(2), g(3), g(4), g(5), xpost[l + 1], xpre[l], alist, R, cpl(l),
+                cpl(l + 1), c0only);
             for (int s = 0; s < nu2; ++s)
                 for (int c = 1; c >= 0; --c)
-                    LT_TRY(gs_half_sweep<T>(h, st, v, tr, ti, c, xpre[l], bs[l], R, active, l == 0, cpl(l)));
+                    LT_TRY(gs_half_sweep<T>(h, st, v, tr, ti, c, xpre[l], bs[l], R, active, alist, l == 0, cpl(l)));
             xpost[l] = xpre[l];
             LT_HIP(hipGetLastError());
         }
@@ -1055,7 +1102,7 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
     return 0;
 }
 template int mg_vcycle<double>(lt_handle*, cdouble, int, int, int, const int*, double*, const double*,
-                               const RefineArgs*);
-template int mg_vcycle<float>(lt_handle*, cdouble, int, int, int, const int*, float*, const float*, const RefineArgs*);
+                               RefineArgs*);
+template int mg_vcycle<float>(lt_handle*, cdouble, int, int, int, const int*, float*, const float*, RefineArgs*);
 
 }  // namespace lt
