@@ -305,7 +305,7 @@ __global__ void k_gs_color_half(LevelView<T> L, T tr, T ti, int color, T* __rest
         atomicAdd(prof, add);
     }
     const int W = L.nx >> 1;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (k >= (L.N >> 1)) return;
     const int row = k / W;  // y + ny z
     const int Y = row % L.ny, Z = row / L.ny;
@@ -355,11 +355,13 @@ __global__ void k_gs_color_half(LevelView<T> L, T tr, T ti, int color, T* __rest
 // Tx, Ty, Tz of every cell and D, m of the colour's cells (4 sizeof(T) per cell).
 // list: the active right-hand sides (group_rhs), or null for all R; active: their flags,
 // for the one-thread-per-cell fallback of odd nx.
+constexpr int kHalfSweepRhs = 8;  // right-hand sides per thread of a one-colour half-sweep
+
 template <typename T>
 static int gs_half_sweep(lt_handle* h, hipStream_t st, const LevelView<T>& L, T tr, T ti, int color, T* x,
                          const T* b, int R, const int* active, const int* list, bool fine, bool cp = false) {
     if ((L.nx & 1) == 0) {
-        const dim3 grid((unsigned)((L.N / 2 + 255) / 256), (R + kSweepRhs - 1) / kSweepRhs);
+        const dim3 grid((unsigned)((L.N / 2 + 255) / 256), (R + kHalfSweepRhs - 1) / kHalfSweepRhs);
         if (fine && h->prof_target == LT_PROF_SWEEP3D) {
             unsigned long long* pc = nullptr;
             hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -367,17 +369,17 @@ static int gs_half_sweep(lt_handle* h, hipStream_t st, const LevelView<T>& L, T 
             const unsigned long long per = (unsigned long long)L.N * 3ull * sizeof(T);
             const unsigned long long once = (unsigned long long)L.N * 4ull * sizeof(T);
             if (cp)
-                hipExtLaunchKernelGGL((k_gs_color_half<T, kSweepRhs, true>), grid, dim3(256), 0, st, e0, e1, 0, L, tr,
+                hipExtLaunchKernelGGL((k_gs_color_half<T, kHalfSweepRhs, true>), grid, dim3(256), 0, st, e0, e1, 0, L, tr,
                                       ti, color, x, b, list, R, pc, per, once);
             else
-                hipExtLaunchKernelGGL((k_gs_color_half<T, kSweepRhs, false>), grid, dim3(256), 0, st, e0, e1, 0, L, tr,
+                hipExtLaunchKernelGGL((k_gs_color_half<T, kHalfSweepRhs, false>), grid, dim3(256), 0, st, e0, e1, 0, L, tr,
                                       ti, color, x, b, list, R, pc, per, once);
             LT_TRY(prof_end(h, LT_PROF_SWEEP3D));
         } else if (cp) {
-            k_gs_color_half<T, kSweepRhs, true><<<grid, 256, 0, st>>>(L, tr, ti, color, x, b, list, R, nullptr,
+            k_gs_color_half<T, kHalfSweepRhs, true><<<grid, 256, 0, st>>>(L, tr, ti, color, x, b, list, R, nullptr,
                                                                       0ull, 0ull);
         } else {
-            k_gs_color_half<T, kSweepRhs, false><<<grid, 256, 0, st>>>(L, tr, ti, color, x, b, list, R, nullptr,
+            k_gs_color_half<T, kHalfSweepRhs, false><<<grid, 256, 0, st>>>(L, tr, ti, color, x, b, list, R, nullptr,
                                                                        0ull, 0ull);
         }
     } else {
@@ -399,7 +401,7 @@ __global__ void k_resid_restrict(LevelView<T> F, int cnx, int cny, int cnz, int 
     group_rhs<RB>(list, R, blockIdx.y, rs);
     if (rs[0] < 0) return;
     const int Nc = cnx * cny * cnz;
-    int I = blockIdx.x * blockDim.x + threadIdx.x;
+    int I = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (I >= Nc) return;
     int Xc = I % cnx, Yc = (I / cnx) % cny, Zc = I / (cnx * cny);
     const size_t N = F.N;
@@ -474,7 +476,7 @@ __global__ void k_prolong_rb(int fnx, int fny, int fnz, int cnx, int cny, int cn
     group_rhs<RB>(list, R, blockIdx.y, rs);
     if (rs[0] < 0) return;
     const int Nf = fnx * fny * fnz;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;  // position in the fine vectors
+    const int p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;  // position in the fine vectors
     if (p >= ((c0only && cpf) ? (Nf >> 1) : Nf)) return;
     int c3[3];
     if (cpf) {
