@@ -1085,22 +1085,22 @@ __global__ __launch_bounds__(256) void k_sens(LevelView<double> L, const double*
 // so a block of kSensCB cells stages, one shift at a time, the weighted differences of every
 // source and receiver field once (kSensA source slots: six faces, the wall term and the
 // storage term; kSensB receiver slots: six faces and the centre), and each thread forms
-// kSensTS sources x kSensTM receivers of one cell from LDS.  Each field value is loaded once per
-// block and shift instead of once per (source, receiver) pair.
-constexpr int kSensCB = 4;                 // cells per block
-constexpr int kSensTPC = kB / kSensCB;     // threads per cell
-constexpr int kSensTS = 5, kSensTM = 4;    // sources x receivers per thread
+// TS sources x TM receivers of one cell from LDS.  Each field value is loaded once per
+// block and shift instead of once per (source, receiver) pair.  CB cells per block; the
+// launcher picks the shape whose threads all have work for the call's field counts.
 constexpr int kSensA = 8, kSensB = 7;      // staged slots per source / receiver field
 // doubles per staged field: 4 words past a multiple of 32 banks, so the consecutive fields
 // the lanes of a wavefront read at once fall into different banks
-constexpr int kSensFS = 2 * kSensA * kSensCB + 2;
-static_assert(kSensFS >= 2 * kSensB * kSensCB && (2 * kSensFS) % 32 == 4, "staged field stride");
+constexpr int sens_fs(int CB) { return 2 * kSensA * CB + 2; }
 
+template <int CB, int TS, int TM>
 __global__ __launch_bounds__(256) void k_sens_tile(LevelView<double> L, const double* __restrict__ kappa,
                                                    const double* __restrict__ mS, int ns,
                                                    int nr, int nk, int t, int ntimes, const double* __restrict__ X,
                                                    const double* __restrict__ zs, const double* __restrict__ wq,
                                                    double* __restrict__ JK, double* __restrict__ JS) {
+    constexpr int kSensCB = CB, kSensTPC = kB / CB, kSensTS = TS, kSensTM = TM, kSensFS = sens_fs(CB);
+    static_assert(kSensFS >= 2 * kSensB * kSensCB && (2 * kSensFS) % 32 == 4, "staged field stride");
     extern __shared__ double sm[];
     // As[s][slot][cb], Bs[m][slot][cb] as (re, im) pairs
     double* As = sm;
@@ -1269,13 +1269,27 @@ __global__ __launch_bounds__(256) void k_sens_tile(LevelView<double> L, const do
         }
 }
 
+template <int CB, int TS, int TM>
+static void launch_sens_tile(hipStream_t st, LevelView<double> L, const double* kappa, const double* mS, int ns,
+                             int nr, int nk, int t, int ntimes, const double* X, const double* zs, const double* wq,
+                             double* JK, double* JS) {
+    const size_t shm = sizeof(double) * (size_t)(ns + nr) * sens_fs(CB);
+    const int groups = ((ns + TS - 1) / TS) * ((nr + TM - 1) / TM);
+    const int tpc = kB / CB;
+    dim3 grid((unsigned)((L.N + CB - 1) / CB), (unsigned)((groups + tpc - 1) / tpc));
+    k_sens_tile<CB, TS, TM><<<grid, kB, shm, st>>>(L, kappa, mS, ns, nr, nk, t, ntimes, X, zs, wq, JK, JS);
+}
+
 int launch_sens(hipStream_t st, LevelView<double> L, const double* kappa, const double* mS, int ns, int nr, int nk,
                 int t, int ntimes, const double* X, const double* zs, const double* wq, double* JK, double* JS) {
-    const size_t shm = sizeof(double) * (size_t)(ns + nr) * kSensFS;
-    if (shm <= 64 * 1024) {
-        const int groups = ((ns + kSensTS - 1) / kSensTS) * ((nr + kSensTM - 1) / kSensTM);
-        dim3 grid((unsigned)((L.N + kSensCB - 1) / kSensCB), (unsigned)((groups + kSensTPC - 1) / kSensTPC));
-        k_sens_tile<<<grid, kB, shm, st>>>(L, kappa, mS, ns, nr, nk, t, ntimes, X, zs, wq, JK, JS);
+    // 8 cells x (4 sources x 4 receivers per thread) when one block's 32 threads per cell cover
+    // every (source, receiver) pair; else 4 cells x (5 x 4), several blocks per cell when needed
+    const bool fit8 = ((ns + 3) / 4) * ((nr + 3) / 4) <= kB / 8 &&
+                      sizeof(double) * (size_t)(ns + nr) * sens_fs(8) <= 64 * 1024;
+    if (fit8) {
+        launch_sens_tile<8, 4, 4>(st, L, kappa, mS, ns, nr, nk, t, ntimes, X, zs, wq, JK, JS);
+    } else if (sizeof(double) * (size_t)(ns + nr) * sens_fs(4) <= 64 * 1024) {
+        launch_sens_tile<4, 5, 4>(st, L, kappa, mS, ns, nr, nk, t, ntimes, X, zs, wq, JK, JS);
     } else {
         dim3 grid((unsigned)((L.N + kB - 1) / kB), (ns + kSensS - 1) / kSensS, (nr + kSensM - 1) / kSensM);
         k_sens<<<grid, kB, 0, st>>>(L, kappa, mS, ns, nr, nk, t, ntimes, X, zs, wq, JK, JS);
