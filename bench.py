@@ -49,14 +49,19 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1409_2556_amd", "csrc", "mg_fused.hip")
 
 def _measured_traffic(traffic_file=TRAFFIC_FILE, kernel_src=KERNEL_SRC):
     """HBM bytes per launch of the profiled kernel from the committed counter
-    summary, or None once the kernel source differs from the profiled one."""
+    summary, or None once the kernel source (one file, or several hashed in order)
+    differs from the profiled one."""
     import hashlib
     import re
+    srcs = [kernel_src] if isinstance(kernel_src, str) else list(kernel_src)
     try:
         txt = open(traffic_file).read()
         want = re.search(r"sha256\[:16\] = ([0-9a-f]{16})", txt).group(1)
         val = float(re.search(r"traffic_bytes_per_launch: ([0-9.]+)", txt).group(1))
-        have = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+        hsh = hashlib.sha256()
+        for f in srcs:
+            hsh.update(open(f, "rb").read())
+        have = hsh.hexdigest()[:16]
     except (OSError, AttributeError):
         return None
     return val if have == want else None
@@ -491,7 +496,8 @@ def main_adjoint(args):
 
 
 C5J_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c5j_gs_color_half_traffic.md")
-C5J_KERNEL_SRC = os.path.join(ROOT, "paper_1409_2556_amd", "csrc", "mg.hip")
+C5J_KERNEL_SRC = (os.path.join(ROOT, "paper_1409_2556_amd", "csrc", "mg.hip"),
+                  os.path.join(ROOT, "paper_1409_2556_amd", "csrc", "lt_internal.h"))
 EXACT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "exact_k_ex_solve.md")
 EXACT_KERNEL_SRC = os.path.join(ROOT, "paper_1409_2556_amd", "csrc", "exact.hip")
 
