@@ -106,7 +106,7 @@ def _parse():
     ap.add_argument("--tol-jacobian", type=float, default=3e-10,
                     help="C5J: weighted tolerance of every variant (equal accuracy)")
     ap.add_argument("--relax-jacobian", type=float, default=0.3,
-                    help="C5J: inner tolerance factor of every variant")
+                    help="C5J, C3, C5: inner tolerance factor of every variant")
     ap.add_argument("--tau-adapt", type=int, choices=[0, 1], default=None,
                     help="C5J/C2: 1: preconditioner shifts from the residual estimates (opts.tau_adapt; every "
                          "variant alike); 0: the fixed schedule (default: 1 for C2, 0 for C5J, whose storage "
@@ -429,7 +429,7 @@ def main_adjoint(args):
     h, tiles = _handle(lt, p, False, nrhs)
     res = {}
     for name, prec, tol in (("fp64", lt.LT_PREC_FP64, 1e-10), ("mixed", lt.LT_PREC_MIXED, 1e-9)):
-        o = lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau, maxit=64, relax=1.0)
+        o = lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau, maxit=64, relax=args.relax_jacobian)
         out = None
         for _ in range(args.warmup):
             out = lt.lt_adjoint(h, p.sources, p.q, p.receivers, p.times, p.nz_contour, o)
@@ -479,7 +479,7 @@ def main_adjoint(args):
         "config": {"workload": "3D 64x64x32 GRF (var 2, corr 0.2/0.2/0.05), log-uniform S, 25 sources + 48 "
                                "receivers (adjoint), times {0.3, 1.2}, 24-node Talbot, 3 tau, lt_adjoint "
                                "(d phi / d ln kappa and d ln S of every cell)",
-                   "rhs": nrhs, "pairs": pairs, "variant": "mixed", "tol": head["tol"],
+                   "rhs": nrhs, "pairs": pairs, "variant": "mixed", "tol": head["tol"], "relax": args.relax_jacobian,
                    "iters": head["st"]["iters_max"], "vcycles": head["st"]["vcycles"], "n_tau": p.n_tau,
                    **_boundary_config(p)},
         "variants": {n: {"solves_per_s": pairs / r["dt"], "ms_per_step": r["dt"] * 1e3, "tol": r["tol"],
@@ -734,7 +734,7 @@ def main_batch(args):
     res = {}
     # mixed tol 3e-9: the 1e-5 head bar holds on every grid of the batch (the largest 3D grid needs it)
     for name, prec, tol in (("fp64", lt.LT_PREC_FP64, 1e-9), ("mixed", lt.LT_PREC_MIXED, 3e-9)):
-        opts = [lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau, maxit=64, relax=1.0) for p in ps]
+        opts = [lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau, maxit=64, relax=args.relax_jacobian) for p in ps]
         items = [dict(handle=h, sources=p.sources, q=p.q, times=p.times, nz=p.nz_contour, receivers=p.receivers,
                       opts=o) for p, h, o in zip(ps, hs, opts)]
         for _ in range(args.warmup):
@@ -768,7 +768,7 @@ def main_batch(args):
         "config": {"workload": "batch of six uneven grids (128^2, 256^2, 512^2, 32^3, 64^3, 128x128x64), "
                                "16 sources x 32 receivers each, times {0.3, 1.2}, 24-node Talbot, "
                                "lt_solve_batch (one stream per problem)",
-                   "pairs": pairs, "variant": "mixed", "smoother_tiles": tiles},
+                   "pairs": pairs, "variant": "mixed", "relax": args.relax_jacobian, "smoother_tiles": tiles},
         "variants": {n: {"solves_per_s": pairs / r["dt"], "ms_per_step": r["dt"] * 1e3, "tol": r["tol"],
                          "rel_head_err_vs_oracle_128": r["err"], "per_problem": r["per_problem"]}
                      for n, r in res.items()},
