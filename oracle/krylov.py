@@ -25,6 +25,9 @@ The preconditioner schedule of Section 3 (tau_schedule) takes the shift of small
 real part (tau_bar_1) and of largest real part (tau_bar_2) among all shifts, and uses
 tau_bar_1 for three steps and tau_bar_2 for two, repeated; a single preconditioner is
 tau_bar_1 alone (the 'Single' solver of Section 4.1).
+
+restarted_fom restarts the FOM variant from its residuals, which an exact preconditioner makes
+collinear with the next basis vector (Section 3.1: r_k = -eta_k v_{m+1}).
 """
 from __future__ import annotations
 
@@ -149,3 +152,95 @@ def flexible_shifted(K, m, b, taus, shifts, tol, maxit, method="gmres", weights=
     x = np.stack([U[:, :len(Y[k])] @ Y[k] for k in range(nk)])
     return {"x": x, "iters": j, "res": res, "conv": conv, "conv_at": conv_at,
             "V": V[:, :j + 1], "U": U[:, :j], "Hbar": H[:j + 1, :j], "T": T[:j], "breakdown": breakdown}
+
+
+def restarted_fom(K, m, b, taus, shifts, tol, cycle, max_cycles, weights=None, precond=None):
+    """FFOM-Sh restarted every ``cycle`` steps from its collinear residuals (exact preconditioners).
+
+    With FOM and an exact preconditioner, the residual of every shift after m steps of
+    Algorithm 1 is b - (K + z_k M) x_k = -eta_k v_{m+1}, with the a-posteriori quantity
+    eta_k = h_{m+1,m} (z_k - tau_m) e_m^T H_m(z_k; T_m)^{-1} beta e_1 of Section 3.1: one
+    vector for all shifts.  A restart therefore continues with one basis started at
+    v_1 = v_{m+1}, in which shift k solves (K + z_k M) d_k = -eta_k v_1: its small problem
+    H_m(z_k; T_m) y = beta_k e_1 takes beta_k = -eta_k (complex) instead of ||b||.  The
+    preconditioner shifts run through ``taus`` cyclically across restarts (step j of the whole
+    solve uses taus[(j - 1) % len]).  A shift is converged when w_k |eta_k| <= tol ||b||.
+
+    Returns a dict with x [nk, N], cycles, iters (steps over all cycles), res [nk]
+    (|eta_k| / ||b|| after the last step that updated shift k), conv [nk], and per cycle the
+    pairs (v_{m+1}, eta) in ``history`` for tests of the collinearity.
+    """
+    m = np.asarray(m, dtype=np.float64)
+    z = np.asarray(shifts, dtype=np.complex128).ravel()
+    nk = z.size
+    w = np.ones(nk) if weights is None else np.asarray(weights, dtype=np.float64)
+    b = np.asarray(b, dtype=np.complex128)
+    N = b.size
+    bnorm = np.linalg.norm(b)
+    lus = {}
+
+    def solve(tau, v):
+        key = (float(tau.real), float(tau.imag))
+        if key not in lus:
+            A = (K + sp.diags(tau * m)).astype(np.complex128).tocsc()
+            lus[key] = splu(A, permc_spec="MMD_AT_PLUS_A")
+        return lus[key].solve(v)
+
+    x = np.zeros((nk, N), dtype=np.complex128)
+    conv = np.zeros(nk, dtype=bool)
+    res = np.full(nk, np.inf)
+    beta_k = np.full(nk, bnorm, dtype=np.complex128)  # the first cycle starts from b itself
+    v1 = b / bnorm
+    step = 0
+    history = []
+    cycles = 0
+    for cycles in range(1, max_cycles + 1):
+        V = np.zeros((N, cycle + 1), dtype=np.complex128)
+        U = np.zeros((N, cycle), dtype=np.complex128)
+        H = np.zeros((cycle + 1, cycle), dtype=np.complex128)
+        T = np.zeros(cycle, dtype=np.complex128)
+        V[:, 0] = v1
+        eta = np.zeros(nk, dtype=np.complex128)
+        Y = [None] * nk
+        done = conv.copy()  # shifts already converged take no part in this cycle
+        j = 0
+        for j in range(1, cycle + 1):
+            step += 1
+            tau = complex(taus[(step - 1) % len(taus)])
+            T[j - 1] = tau
+            u = solve(tau, V[:, j - 1]) if precond is None else np.asarray(precond(tau, V[:, j - 1]),
+                                                                            dtype=np.complex128)
+            U[:, j - 1] = u
+            s = m * u
+            for i in range(j):
+                H[i, j - 1] = np.vdot(V[:, i], s)
+                s = s - H[i, j - 1] * V[:, i]
+            H[j, j - 1] = np.linalg.norm(s)
+            if H[j, j - 1] != 0.0:
+                V[:, j] = s / H[j, j - 1]
+            for k in range(nk):
+                if done[k]:
+                    continue
+                # the square FOM system of this cycle, right-hand side beta_k e_1
+                Hz = np.eye(j, dtype=np.complex128) + H[:j, :j] @ np.diag(z[k] - T[:j])
+                rhs = np.zeros(j, dtype=np.complex128)
+                rhs[0] = beta_k[k]
+                y = np.linalg.solve(Hz, rhs)
+                Y[k] = y
+                eta[k] = H[j, j - 1] * (z[k] - T[j - 1]) * y[j - 1]
+                res[k] = abs(eta[k]) / bnorm
+                if w[k] * res[k] <= tol or H[j, j - 1] == 0.0:
+                    done[k] = True
+            if done.all():
+                break
+        for k in range(nk):
+            if Y[k] is not None:
+                x[k] += U[:, :len(Y[k])] @ Y[k]
+        history.append((V[:, j].copy(), eta.copy()))
+        conv = done
+        if conv.all():
+            break
+        # restart: every unconverged shift's residual is -eta_k v_{j+1}
+        v1 = V[:, j].copy()
+        beta_k = -eta
+    return {"x": x, "cycles": cycles, "iters": step, "res": res, "conv": conv, "history": history}

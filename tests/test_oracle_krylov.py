@@ -8,7 +8,10 @@ shift-and-invert preconditioners), each against something other than the oracle:
 * the shift equal to a single preconditioner's tau, solved at the first step;
 * the happy breakdown of an eigenmode right-hand side, against the closed-form
   eigenvalue of the homogeneous grid (x_k = b / (S V (lambda + z_k)));
-* FOM against GMRES (same basis; FOM's residual is never below GMRES's).
+* FOM against GMRES (same basis; FOM's residual is never below GMRES's);
+* the restarted FOM: its residuals against -eta_k v_{m+1} by sparse products (the
+  collinearity of Section 3.1), its solutions against direct solves, and a cycle longer than
+  the solve against FOM without restarts.
 """
 import numpy as np
 import pytest
@@ -17,7 +20,7 @@ from scipy.sparse.linalg import spsolve
 
 from oracle.contour import talbot_nodes
 from oracle.fv import assemble, point_weights
-from oracle.krylov import flexible_shifted, shift_invert, tau_schedule
+from oracle.krylov import flexible_shifted, restarted_fom, shift_invert, tau_schedule
 from workloads.configs import T_D, make_problem
 
 
@@ -124,3 +127,43 @@ def test_adaptive_shifts_still_solve_the_systems():
     for k in range(z.size):
         xd = shift_invert(K, m, z[k], b)
         assert np.linalg.norm(out["x"][k] - xd) <= 1e-6 * np.linalg.norm(xd)
+
+
+def test_fom_residuals_are_collinear_with_the_next_basis_vector():
+    """Section 3.1: with an exact preconditioner the FOM residual of every shift after m steps
+    is -eta_k v_{m+1}.  Pinned by explicit sparse products: the true residual of each shift
+    still active at the end of a 4-step cycle, against -eta_k times the cycle's last basis
+    vector."""
+    K, m, b, z = _problem()
+    out = restarted_fom(K, m, b, tau_schedule(z, 2), z, tol=0.0, cycle=4, max_cycles=1)
+    v5, eta = out["history"][0]
+    for k in range(z.size):
+        r = b - (K + sp.diags(z[k] * m)) @ out["x"][k]
+        assert np.linalg.norm(r + eta[k] * v5) <= 1e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(v5) == pytest.approx(1.0, abs=1e-12)
+
+
+def test_restarted_fom_solves_the_systems():
+    """Restarts every 3 steps from the collinear residuals: every shift's true residual meets
+    the test (a sparse product) and the solution matches a direct solve."""
+    K, m, b, z = _problem()
+    out = restarted_fom(K, m, b, tau_schedule(z, 2), z, tol=1e-9, cycle=3, max_cycles=60)
+    assert out["conv"].all() and out["cycles"] > 2
+    for k in range(z.size):
+        A = (K + sp.diags(z[k] * m)).tocsc()
+        r = b - A @ out["x"][k]
+        assert np.linalg.norm(r) <= 1.05e-9 * np.linalg.norm(b)
+        xd = spsolve(A.astype(np.complex128), b.astype(np.complex128))
+        assert np.linalg.norm(out["x"][k] - xd) <= 1e-6 * np.linalg.norm(xd)
+
+
+def test_restart_longer_than_the_solve_is_plain_fom():
+    """A cycle longer than the steps needed never restarts: the same steps, residuals and
+    solutions as FOM without restarts."""
+    K, m, b, z = _problem(n=(20, 18))
+    taus = tau_schedule(z, 2)
+    f = flexible_shifted(K, m, b, taus, z, tol=1e-9, maxit=80, method="fom")
+    r = restarted_fom(K, m, b, taus, z, tol=1e-9, cycle=80, max_cycles=1)
+    assert r["cycles"] == 1 and r["iters"] == f["iters"]
+    assert np.allclose(r["res"], f["res"], rtol=1e-9, atol=1e-15)
+    assert np.abs(r["x"] - f["x"]).max() <= 1e-12 * np.abs(f["x"]).max()
