@@ -205,7 +205,19 @@ typedef struct {
  *              schedule's shifts, so nothing more is factorised).  The paper
  *              leaves the choice of shifts open (Sections 3 and 6); this is
  *              the build's own rule.  Costs one small device-to-host copy
- *              per outer iteration. */
+ *              per outer iteration.
+ *   restart    0 (default): one basis per solve, up to maxit columns.  m > 0
+ *              (lt_solve with LT_PRECOND_EXACT and LT_METHOD_FOM only, else
+ *              LT_EINVAL; other calls return LT_EUNSUPPORTED): the basis
+ *              restarts every m steps from the residuals, which FOM with an
+ *              exact preconditioner makes collinear (Section 3.1: the residual
+ *              of shift k after m steps is -eta_k v_{m+1}): the next cycle
+ *              starts at v_{m+1}, and shift k's small problem takes -eta_k as
+ *              its first right-hand-side entry.  maxit bounds the steps over
+ *              all cycles (rounded up to whole cycles); the heads of the cycles
+ *              are summed, and the true residual is that of each right-hand
+ *              side's last cycle.  Extra device memory per right-hand side: one
+ *              vector and one complex per shift. */
 typedef struct {
     double tol;
     int maxit;
@@ -223,6 +235,7 @@ typedef struct {
     int method;
     int conv;
     int tau_adapt;
+    int restart;
 } lt_opts;
 
 /* Statistics of the last call.  Pointer members are optional host arrays the

@@ -60,7 +60,8 @@ class lt_opts(C.Structure):
                 ("tau_reim", C.POINTER(C.c_double)), ("nu1", C.c_int), ("nu2", C.c_int),
                 ("inner_max", C.c_int), ("relax", C.c_double), ("true_residual", C.c_int),
                 ("profile", C.c_int), ("precond", C.c_int), ("net_keep", C.c_double),
-                ("graph", C.c_int), ("method", C.c_int), ("conv", C.c_int), ("tau_adapt", C.c_int)]
+                ("graph", C.c_int), ("method", C.c_int), ("conv", C.c_int), ("tau_adapt", C.c_int),
+                ("restart", C.c_int)]
 
 
 class lt_stats(C.Structure):

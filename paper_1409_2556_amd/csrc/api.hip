@@ -115,8 +115,13 @@ int validate_opts(const lt_opts* o) {
         !(o->net_keep >= 0.0) ||
         (o->graph != 0 && o->graph != 1) || (o->method != LT_METHOD_GMRES && o->method != LT_METHOD_FOM) ||
         (o->conv != LT_CONV_WEIGHTED && o->conv != LT_CONV_RELATIVE) || (o->tau_adapt != 0 && o->tau_adapt != 1) ||
-        (o->precision != LT_PREC_FP64 && o->precision != LT_PREC_MIXED)) {
+        (o->precision != LT_PREC_FP64 && o->precision != LT_PREC_MIXED) || o->restart < 0) {
         set_last_error("invalid lt_opts");
+        return LT_EINVAL;
+    }
+    if (o->restart > 0 && (o->precond != LT_PRECOND_EXACT || o->method != LT_METHOD_FOM)) {
+        set_last_error("lt_opts.restart needs LT_PRECOND_EXACT and LT_METHOD_FOM (the residuals are collinear only "
+                       "for FOM with an exact preconditioner)");
         return LT_EINVAL;
     }
     return 0;
@@ -141,6 +146,16 @@ struct KrylovOut {
     int net_applied = 0, net_rejected = 0, net_disabled_at = 0;
     bool converged = true;
     std::vector<int> notconv;  // [R] 1 where the Arnoldi stopped at maxit
+    double* Q = nullptr;       // [R][jmax + 1][2][N] the basis V (column j unnormalised after its step)
+    size_t qstride = 0;
+    double* eta = nullptr;     // [R][Ks] complex: FOM's eta_k of each pair's last step
+};
+
+// A cycle of a restarted solve: the least-squares start (per-pair g_0, the original norms)
+// and the steps taken before it (the preconditioner schedule continues from there).
+struct RestartIn {
+    LSStart start;
+    int j0 = 0;
 };
 
 // One step of the iterative refinement of u_j ~ (K + tau M)^{-1} v_j for the
@@ -255,7 +270,7 @@ int graph_step(lt_handle* h, const lt_opts& o, int R, cdouble tau, double* U, si
 // those right-hand sides are solved; the others keep the basis, gathers and column
 // counts of the previous call on the same workspace.
 int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int rinit, const DevPoints* rec,
-               KrylovOut* out, const std::vector<int>* only = nullptr) {
+               KrylovOut* out, const std::vector<int>* only = nullptr, const RestartIn* rin = nullptr) {
     hipStream_t st = h->stream;
     const int N = h->N;
     const int jmax = o.maxit;
@@ -344,6 +359,12 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int rini
     ls.sn = wsp<double>(h, "sn", 2 * P * jmax, &rc);
     ls.g = wsp<double>(h, "g", 2 * P * (jmax + 1), &rc);
     ls.res = wsp<double>(h, "res", P, &rc);
+    if (o.method == LT_METHOD_FOM) {
+        ls.eta = wsp<double>(h, "eta", 2 * P, &rc);
+        if (!ls.eta) return rc;
+    }
+    const LSStart start = rin ? rin->start : LSStart();
+    const int j0 = rin ? rin->j0 : 0;
     int* conv = wsp<int>(h, "conv", P, &rc);
     double* Y = wsp<double>(h, "Y", (size_t)R * jmax * 2 * Ks, &rc);
     double* tabs = wsp<double>(h, "tabs", 8 * (size_t)Ks, &rc);
@@ -433,7 +454,7 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int rini
     for (const cdouble& t : plan.tau_sched)
         if (std::find(cand.begin(), cand.end(), t) == cand.end()) cand.push_back(t);
     for (j = 0; j < jmax; ++j) {
-        cdouble tau = plan.tau_sched[j % plan.tau_sched.size()];
+        cdouble tau = plan.tau_sched[(j + j0) % plan.tau_sched.size()];
         if (o.tau_adapt && j > 0) {
             LT_HIP(hipMemcpyAsync(hres.data(), ls.res, hres.size() * sizeof(double), hipMemcpyDeviceToHost, st));
             LT_HIP(hipMemcpyAsync(hact, active, R * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -490,7 +511,7 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int rini
             if (np > 0)
                 LT_TRY(launch_gather(st, R, N, np, rec->off, rec->cell, rec->wt, U, ustride, j, G, jmax, active));
             LT_TRY(launch_ls_update(st, R, Ks, j, tau, zs, omega, rinit, o.tol, o.method == LT_METHOD_FOM, H, hstride,
-                                    hrstride, beta, ls, active, mcols, worst, conv));
+                                    hrstride, beta, ls, active, mcols, worst, conv, start));
             continue;
         }
         // inner refinement of u_j ~ (K + tau M)^{-1} v_j
@@ -589,7 +610,7 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int rini
                            cstride, scale, partn, active));
         if (np > 0) LT_TRY(launch_gather(st, R, N, np, rec->off, rec->cell, rec->wt, U, ustride, j, G, jmax, active));
         LT_TRY(launch_ls_update(st, R, Ks, j, tau, zs, omega, rinit, o.tol, o.method == LT_METHOD_FOM, H, hstride,
-                                hrstride, beta, ls, active, mcols, worst, conv));
+                                hrstride, beta, ls, active, mcols, worst, conv, start));
     }
     LT_HIP(hipMemcpyAsync(hact, active, R * sizeof(int), hipMemcpyDeviceToHost, st));
     LT_HIP(hipStreamSynchronize(st));
@@ -627,6 +648,9 @@ int run_krylov(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int rini
     out->wq = wq;
     out->w = wk;
     out->rinit = rinit;
+    out->Q = Q;
+    out->qstride = qstride;
+    out->eta = ls.eta;
     return 0;
 }
 
@@ -673,6 +697,10 @@ int true_residuals(lt_handle* h, const KrylovOut& k, const Plan& plan, lt_stats*
 int solve_checked(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int rinit, const DevPoints* rec,
                   KrylovOut* k, lt_stats* stats, int* resolves, bool* ok) {
     *resolves = 0;
+    if (o.restart > 0) {
+        set_last_error("lt_opts.restart: only lt_solve restarts");
+        return LT_EUNSUPPORTED;
+    }
     LT_TRY(run_krylov(h, plan, o, R, rinit, rec, k));
     std::vector<int> nc = k->notconv;
     int vcycles = k->vcycles, napp = k->net_applied, nrej = k->net_rejected;
@@ -719,6 +747,122 @@ int solve_checked(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int r
     for (int r = 0; r < R; ++r) conv = conv && !nc[r];
     k->notconv = nc;
     k->converged = conv;
+    *ok = conv && tr_ok;
+    return 0;
+}
+
+// FFOM-Sh with the exact preconditioner, restarted every o.restart steps.  With FOM and an
+// exact preconditioner the residual of every shift after m steps is -eta_k v_{m+1} (Section
+// 3.1): one vector for all shifts of a right-hand side.  Each cycle is one run of the Krylov
+// loop: the first on b with g_0 = ||b|| for every shift, each later one, for the right-hand
+// sides not yet converged, on the previous cycle's last basis vector v_{m+1} with
+// g_0 = -eta_k per shift.  Residuals are measured against the original ||b||, the
+// preconditioner schedule continues across cycles, and the heads of the cycles are summed.
+// The FP64 true residual of a pair is that of its right-hand side's last cycle (whose
+// right-hand side is the residual left by the cycles before): with y / (g_0 / ||v||), the
+// coefficients for the unit right-hand side v / ||v||, the usual kernels measure
+// ||v - A U y|| / ||v||, which |g_0| / ||b|| turns into the pair's residual relative to ||b||.
+int solve_restarted(lt_handle* h, const Plan& plan, const lt_opts& o, int R, int rinit, const DevPoints* rec, int ns,
+                    int ntimes, double* phi_out, KrylovOut* k, lt_stats* stats, std::vector<int>* iters, bool* ok) {
+    hipStream_t st = h->stream;
+    const int N = h->N;
+    const size_t N2 = 2 * (size_t)N;
+    const int Ks = plan.ntimes * plan.nk;
+    int rc = 0;
+    const double* b0 = k->b;
+    double* cb = wsp<double>(h, "rs_b", R * N2, &rc);                  // each cycle's right-hand sides
+    double* g0 = wsp<double>(h, "rs_g0", 2 * (size_t)R * Ks, &rc);     // each pair's g_0 (complex)
+    double* bn = wsp<double>(h, "rs_bnorm", R, &rc);                   // ||b||
+    double* cn = wsp<double>(h, "rs_cnorm", R, &rc);                   // ||v|| of the last cycle
+    double* npart = wsp<double>(h, "rs_part", (size_t)R * reduce_blocks(N, R), &rc);
+    int* rflag = wsp<int>(h, "rs_flag", R, &rc);
+    if (!cb || !g0 || !bn || !cn || !npart || !rflag) return rc;
+    LT_TRY(launch_norms(st, N, R, N2, b0, npart, bn, nullptr));
+    LT_TRY(launch_fill_g0(st, R, Ks, bn, g0));
+    LT_HIP(hipMemcpyAsync(cb, b0, R * N2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    const size_t nphi = (size_t)(ns > 0 ? ns : 1) * rec->n * ntimes;
+    LT_HIP(hipMemsetAsync(phi_out, 0, nphi * sizeof(double), st));
+    // every cycle reserves the same basis, so a right-hand side that has finished keeps its
+    // last cycle's basis, least-squares state and gathers until the end
+    lt_opts oc = o;
+    oc.maxit = o.restart;
+    const int max_cycles = (o.maxit + o.restart - 1) / o.restart;
+    std::vector<int> only(R, 1), mlast(R, 0), hm(R);
+    iters->assign(R, 0);
+    k->b = cb;
+    int vcycles = 0;
+    for (int c = 0; c < max_cycles; ++c) {
+        RestartIn rin;
+        rin.start.g0 = g0;
+        rin.start.bnorm = bn;
+        rin.j0 = c * o.restart;
+        LT_TRY(run_krylov(h, plan, oc, R, rinit, rec, k, c ? &only : nullptr, &rin));
+        vcycles += k->vcycles;
+        // this cycle's heads: the right-hand sides it did not solve keep their earlier column
+        // counts, which count zero in the sum
+        LT_HIP(hipMemcpyAsync(hm.data(), k->mcols, R * sizeof(int), hipMemcpyDeviceToHost, st));
+        LT_HIP(hipStreamSynchronize(st));
+        for (int r = 0; r < R; ++r) {
+            if (!only[r]) {
+                hm[r] = 0;
+            } else {
+                mlast[r] = hm[r];
+                (*iters)[r] += hm[r];
+            }
+        }
+        LT_HIP(hipMemcpyAsync(k->mcols, hm.data(), R * sizeof(int), hipMemcpyHostToDevice, st));
+        LT_TRY(launch_heads(st, ns, rinit < R ? rinit : -1, rec->n, ntimes, plan.nk, k->wq, k->w, k->G, k->Y,
+                            k->mcols, k->jmax, phi_out, true));
+        LT_HIP(hipStreamSynchronize(st));
+        if (k->converged) break;
+        // the right-hand sides that go on, from their collinear residuals
+        for (int r = 0; r < R; ++r) only[r] = k->notconv[r];
+        LT_HIP(hipMemcpyAsync(rflag, only.data(), R * sizeof(int), hipMemcpyHostToDevice, st));
+        LT_TRY(launch_restart_rhs(st, R, N, Ks, k->Q, k->qstride, k->mcols, rflag, k->eta, cb, g0));
+        LT_HIP(hipStreamSynchronize(st));
+    }
+    bool conv = true;
+    for (int r = 0; r < R; ++r) conv = conv && !k->notconv[r];
+    k->converged = conv;
+    k->vcycles = vcycles;
+    k->iters_max = 0;
+    for (int r = 0; r < R; ++r) k->iters_max = std::max(k->iters_max, (*iters)[r]);
+    LT_HIP(hipMemcpyAsync(k->mcols, mlast.data(), R * sizeof(int), hipMemcpyHostToDevice, st));
+    bool tr_ok = true;
+    if (o.true_residual) {
+        const int mmax = *std::max_element(mlast.begin(), mlast.end());
+        double* KU = wsp<double>(h, "KU", (size_t)R * std::max(mmax, 1) * N2, &rc);
+        const int nb = true_res_blocks(N, R);
+        double* part = wsp<double>(h, "tpart", (size_t)R * Ks * nb, &rc);
+        double* tr = wsp<double>(h, "trel", (size_t)R * Ks, &rc);
+        if (!KU || !part || !tr) return rc;
+        LT_TRY(launch_norms(st, N, R, N2, cb, npart, cn, nullptr));
+        LT_TRY(launch_unscale_y(st, R, Ks, k->jmax, k->mcols, g0, cn, k->Y));
+        LT_TRY(launch_true_residual_cols(st, h->levels[0].v64(), R, Ks, k->jmax, mmax, k->U, k->ustride, k->Y,
+                                         k->mcols, k->zs, cb, cn, KU, part, tr));
+        std::vector<double> ht((size_t)R * Ks), hg((size_t)2 * R * Ks), hb(R);
+        LT_HIP(hipMemcpyAsync(ht.data(), tr, ht.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        LT_HIP(hipMemcpyAsync(hg.data(), g0, hg.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        LT_HIP(hipMemcpyAsync(hb.data(), bn, R * sizeof(double), hipMemcpyDeviceToHost, st));
+        LT_HIP(hipStreamSynchronize(st));
+        double mx = 0.0;
+        for (int r = 0; r < R; ++r) {
+            const std::vector<double>& om = r >= rinit ? plan.omega_init : plan.omega;
+            double wr = 0.0;
+            for (int kk = 0; kk < Ks; ++kk) {
+                const size_t pi = (size_t)r * Ks + kk;
+                const double rel = hb[r] > 0.0 ? ht[pi] * std::hypot(hg[2 * pi], hg[2 * pi + 1]) / hb[r] : 0.0;
+                ht[pi] = rel;
+                wr = std::max(wr, om[kk] * rel);
+            }
+            mx = std::max(mx, wr);
+            tr_ok = tr_ok && wr <= o.tol;
+        }
+        if (stats) {
+            stats->true_relres_max = mx;
+            if (stats->true_relres) std::memcpy(stats->true_relres, ht.data(), ht.size() * sizeof(double));
+        }
+    }
     *ok = conv && tr_ok;
     return 0;
 }
@@ -1092,12 +1236,19 @@ int lt_solve(lt_handle* h, const lt_sources* src, const double* times, int ntime
     LT_TRY(prof_start(h, o.profile));
     int resolves = 0;
     bool ok = false;
-    LT_TRY(solve_checked(h, plan, o, R, rinit, &dr, &k, stats, &resolves, &ok));
-    LT_TRY(launch_heads(h->stream, ns, src->phi0 ? ns : -1, dr.n, ntimes, plan.nk, k.wq, k.w, k.G, k.Y, k.mcols,
-                        k.jmax, phi_out));
-    LT_HIP(hipStreamSynchronize(h->stream));
-    if (stats && stats->iters_per_rhs)
-        LT_HIP(hipMemcpy(stats->iters_per_rhs, k.mcols, R * sizeof(int), hipMemcpyDeviceToHost));
+    if (o.restart > 0) {
+        std::vector<int> its;
+        LT_TRY(solve_restarted(h, plan, o, R, rinit, &dr, ns, ntimes, phi_out, &k, stats, &its, &ok));
+        LT_HIP(hipStreamSynchronize(h->stream));
+        if (stats && stats->iters_per_rhs) std::memcpy(stats->iters_per_rhs, its.data(), R * sizeof(int));
+    } else {
+        LT_TRY(solve_checked(h, plan, o, R, rinit, &dr, &k, stats, &resolves, &ok));
+        LT_TRY(launch_heads(h->stream, ns, src->phi0 ? ns : -1, dr.n, ntimes, plan.nk, k.wq, k.w, k.G, k.Y, k.mcols,
+                            k.jmax, phi_out));
+        LT_HIP(hipStreamSynchronize(h->stream));
+        if (stats && stats->iters_per_rhs)
+            LT_HIP(hipMemcpy(stats->iters_per_rhs, k.mcols, R * sizeof(int), hipMemcpyDeviceToHost));
+    }
     LT_TRY(prof_finish(h, stats));
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     fill_stats(stats, k, (int)h->levels.size(), secs, resolves, h);

@@ -17,6 +17,15 @@ struct LSState {
     double* sn;
     double* g;
     double* res;
+    double* eta = nullptr;  // FOM: eta_k of the last step per pair (complex), the residual's coefficient on v_{j+1}
+};
+
+// Restarted solves (the FOM variant with an exact preconditioner): the first entry g_0 of
+// every pair's least-squares right-hand side (complex per pair; null: beta[r]) and the norm
+// the residuals are measured against (per right-hand side; null: beta).
+struct LSStart {
+    const double* g0 = nullptr;
+    const double* bnorm = nullptr;
 };
 
 int reduce_blocks(int N, int R);
@@ -62,7 +71,8 @@ int launch_cgs2(hipStream_t st, int N, int R, int j, const double* m, const doub
 // omega: [2][Ks] shift weights, the second row for right-hand sides r >= rinit (the initial head's term)
 int launch_ls_update(hipStream_t st, int R, int Ks, int j, cdouble tau, const double* zs, const double* omega,
                      int rinit, double tol, bool fom, const double* H, int hstride, size_t hrstride,
-                     const double* beta, const LSState& s, int* active, int* mcols, double* worst, int* conv);
+                     const double* beta, const LSState& s, int* active, int* mcols, double* worst, int* conv,
+                     const LSStart& start = LSStart());
 int launch_gather(hipStream_t st, int R, int N, int np, const int* off, const int* cell, const double* wt,
                   const double* U, size_t ustride, int j, double* G, int jmax, const int* active);
 // fom: y solves the square Hessenberg system (FOM) instead of the least-squares problem
@@ -71,7 +81,17 @@ int launch_backsolve(hipStream_t st, int R, int Ks, const int* mcols, const LSSt
 // heads of the Rs wells (weights wq), plus the initial head's right-hand side r0 (weights w) on
 // every row when r0 >= 0; phi: [max(Rs, 1)][np][ntimes]
 int launch_heads(hipStream_t st, int Rs, int r0, int np, int ntimes, int nk, const double* wq, const double* w,
-                 const double* G, const double* Y, const int* mcols, int jmax, double* phi);
+                 const double* G, const double* Y, const int* mcols, int jmax, double* phi, bool accumulate = false);
+// Restarts: g0[r][k] = (bnorm[r], 0) for every pair
+int launch_fill_g0(hipStream_t st, int R, int Ks, const double* bnorm, double* g0);
+// Restarts: for right-hand sides with restart[r]: b[r] = Q[r][:, mcols[r]] (the next basis vector,
+// unnormalised) and g0[r][k] = -eta[r][k]
+int launch_restart_rhs(hipStream_t st, int R, int N, int Ks, const double* Q, size_t qstride, const int* mcols,
+                       const int* restart, const double* eta, double* b, double* g0);
+// Y[r][j][k] /= g0[r][k] / bnorm[r] (0 where that is 0), j < mcols[r]: the coefficients of a
+// unit right-hand side b / ||b|| per pair, for the true residual of a restarted cycle
+int launch_unscale_y(hipStream_t st, int R, int Ks, int jmax, const int* mcols, const double* g0, const double* bnorm,
+                     double* Y);
 // b[0:N] = m .* phi0 (the real plane of the initial head's right-hand side M phi0)
 int launch_mass_rhs(hipStream_t st, int N, const double* m, const double* phi0, double* b);
 int launch_form_x(hipStream_t st, int N, int R, int nc, int k0, int Ks, const double* U, size_t ustride,

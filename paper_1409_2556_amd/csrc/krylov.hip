@@ -563,7 +563,8 @@ __global__ void k_ls_update(int R, int Ks, int j, double tau_re, double tau_im, 
                             const double* __restrict__ H,
                             int hstride, size_t hrstride, const double* __restrict__ beta, LSState st,
                             int* __restrict__ active, int* __restrict__ mcols, double* __restrict__ worst,
-                            int* __restrict__ conv_flags) {
+                            int* __restrict__ conv_flags, const double* __restrict__ g0,
+                            const double* __restrict__ bnorm) {
     int r = blockIdx.x;
     if (!active[r]) return;
     // right-hand sides from rinit on (the initial head's term) weigh their shifts by |w_k|
@@ -626,7 +627,7 @@ __global__ void k_ls_update(int R, int Ks, int j, double tau_re, double tau_im, 
         // g: g_j <- c g_j ; g_{j+1} = -conj(s) g_j
         c64 gj;
         if (j == 0) {
-            gj = {beta[r], 0.0};
+            gj = g0 ? c64{g0[2 * base], g0[2 * base + 1]} : c64{beta[r], 0.0};
         } else {
             gj = {st.g[2 * ((size_t)j * P + base)], st.g[2 * ((size_t)j * P + base) + 1]};
         }
@@ -638,8 +639,22 @@ __global__ void k_ls_update(int R, int Ks, int j, double tau_re, double tau_im, 
         st.g[2 * ((size_t)(j + 1) * P + base) + 1] = gn.im;
         // FOM: the square system's residual is |h_{j+1,j} y_j| = |g_{j+1}| / c (infinite when the
         // square system is singular, c = 0)
-        double res = hypot(gn.re, gn.im) / beta[r];
+        const double bn = bnorm ? bnorm[r] : beta[r];
+        double res = hypot(gn.re, gn.im) / bn;
         if (fom) res = c > 0.0 ? res / c : HUGE_VAL;
+        if (fom && st.eta) {
+            // eta = (z - tau_j) h_{j+1,j} y_j with y_j = g_j / cur, the square system's last
+            // unknown (cur: its last diagonal entry before this step's rotation); the residual
+            // of this pair is -eta v_{j+1}
+            c64 e = {0.0, 0.0};
+            if (na > 0.0) {
+                const c64 sg = cm(sub, gj);
+                const double d2 = cur.re * cur.re + cur.im * cur.im;
+                e = {(sg.re * cur.re + sg.im * cur.im) / d2, (sg.im * cur.re - sg.re * cur.im) / d2};
+            }
+            st.eta[2 * base] = e.re;
+            st.eta[2 * base + 1] = e.im;
+        }
         double wres = om[k] * res;
         st.res[base] = res;
         myw = fmax(myw, wres);
@@ -748,7 +763,7 @@ __device__ __forceinline__ double heads_term(int r, int p, int t, int nk, int Ks
 
 __global__ void k_heads(int Rs, int r0, int np, int ntimes, int nk, const double* __restrict__ wq,
                         const double* __restrict__ w, const double* __restrict__ G, const double* __restrict__ Y,
-                        const int* __restrict__ mcols, int jmax, double* __restrict__ phi) {
+                        const int* __restrict__ mcols, int jmax, double* __restrict__ phi, int accumulate) {
     const int rows = Rs > 0 ? Rs : 1;
     int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= rows * np * ntimes) return;
@@ -757,7 +772,51 @@ __global__ void k_heads(int Rs, int r0, int np, int ntimes, int nk, const double
     double acc = 0;
     if (s < Rs) acc = heads_term(s, p, t, nk, Ks, np, wq, G, Y, mcols[s], jmax);
     if (r0 >= 0) acc += heads_term(r0, p, t, nk, Ks, np, w, G, Y, mcols[r0], jmax);
-    phi[idx] = 2.0 * acc;
+    phi[idx] = accumulate ? phi[idx] + 2.0 * acc : 2.0 * acc;
+}
+
+// ---------------------------------------------------------------- restarts
+__global__ void k_fill_g0(int R, int Ks, const double* __restrict__ bnorm, double* __restrict__ g0) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= R * Ks) return;
+    g0[2 * i] = bnorm[i / Ks];
+    g0[2 * i + 1] = 0.0;
+}
+
+// one workgroup row per right-hand side: the cycle's last basis vector becomes the next
+// cycle's right-hand side, and each pair's coefficient on it is -eta
+__global__ void k_restart_rhs(int R, int N, int Ks, const double* __restrict__ Q, size_t qstride,
+                              const int* __restrict__ mcols, const int* __restrict__ restart,
+                              const double* __restrict__ eta, double* __restrict__ b, double* __restrict__ g0) {
+    const int r = blockIdx.y;
+    if (!restart[r]) return;
+    const size_t N2 = 2 * (size_t)N;
+    const double* q = Q + qstride * r + N2 * mcols[r];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N2; i += (size_t)gridDim.x * blockDim.x)
+        b[N2 * r + i] = q[i];
+    if (blockIdx.x == 0)
+        for (int k = threadIdx.x; k < Ks; k += blockDim.x) {
+            const size_t pi = (size_t)r * Ks + k;
+            g0[2 * pi] = -eta[2 * pi];
+            g0[2 * pi + 1] = -eta[2 * pi + 1];
+        }
+}
+
+__global__ void k_unscale_y(int R, int Ks, int jmax, const int* __restrict__ mcols, const double* __restrict__ g0,
+                            const double* __restrict__ bnorm, double* __restrict__ Y) {
+    const int r = blockIdx.y, k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Ks) return;
+    const size_t pi = (size_t)r * Ks + k;
+    // sigma = g0 / bnorm; y <- y / sigma = y conj(sigma) / |sigma|^2
+    const double sr = g0[2 * pi] / bnorm[r], si = g0[2 * pi + 1] / bnorm[r];
+    const double d2 = sr * sr + si * si;
+    double* Yr = Y + (size_t)r * jmax * 2 * Ks;
+    for (int j = 0; j < mcols[r]; ++j) {
+        double* y = Yr + (size_t)j * 2 * Ks + 2 * k;
+        const double yr = y[0], yi = y[1];
+        y[0] = d2 > 0.0 ? (yr * sr + yi * si) / d2 : 0.0;
+        y[1] = d2 > 0.0 ? (yi * sr - yr * si) / d2 : 0.0;
+    }
 }
 
 // b = M phi0 (real part; the imaginary plane stays as the caller cleared it)
@@ -1435,12 +1494,14 @@ int launch_cgs2(hipStream_t st, int N, int R, int j, const double* m, const doub
 
 int launch_ls_update(hipStream_t st, int R, int Ks, int j, cdouble tau, const double* zs, const double* omega,
                      int rinit, double tol, bool fom, const double* H, int hstride, size_t hrstride,
-                     const double* beta, const LSState& s, int* active, int* mcols, double* worst, int* conv) {
+                     const double* beta, const LSState& s, int* active, int* mcols, double* worst, int* conv,
+                     const LSStart& start) {
     int threads = ((Ks + 63) / 64) * 64;
     if (threads > kB) threads = kB;
     size_t shm = sizeof(double) * 2 * (j + 2);
     k_ls_update<<<R, threads, shm, st>>>(R, Ks, j, tau.real(), tau.imag(), zs, omega, rinit, tol, fom ? 1 : 0, H,
-                                         hstride, hrstride, beta, s, active, mcols, worst, conv);
+                                         hstride, hrstride, beta, s, active, mcols, worst, conv, start.g0,
+                                         start.bnorm);
     LT_HIP(hipGetLastError());
     return 0;
 }
@@ -1461,10 +1522,31 @@ int launch_backsolve(hipStream_t st, int R, int Ks, const int* mcols, const LSSt
 }
 
 int launch_heads(hipStream_t st, int Rs, int r0, int np, int ntimes, int nk, const double* wq, const double* w,
-                 const double* G, const double* Y, const int* mcols, int jmax, double* phi) {
+                 const double* G, const double* Y, const int* mcols, int jmax, double* phi, bool accumulate) {
     int tot = (Rs > 0 ? Rs : 1) * np * ntimes;
     if (tot == 0) return 0;
-    k_heads<<<nb_for(tot), kB, 0, st>>>(Rs, r0, np, ntimes, nk, wq, w, G, Y, mcols, jmax, phi);
+    k_heads<<<nb_for(tot), kB, 0, st>>>(Rs, r0, np, ntimes, nk, wq, w, G, Y, mcols, jmax, phi, accumulate ? 1 : 0);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_fill_g0(hipStream_t st, int R, int Ks, const double* bnorm, double* g0) {
+    k_fill_g0<<<nb_for(R * Ks), kB, 0, st>>>(R, Ks, bnorm, g0);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_restart_rhs(hipStream_t st, int R, int N, int Ks, const double* Q, size_t qstride, const int* mcols,
+                       const int* restart, const double* eta, double* b, double* g0) {
+    const unsigned nbx = (unsigned)std::min<size_t>((2 * (size_t)N + kB - 1) / kB, 1024);
+    k_restart_rhs<<<dim3(nbx, R), kB, 0, st>>>(R, N, Ks, Q, qstride, mcols, restart, eta, b, g0);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_unscale_y(hipStream_t st, int R, int Ks, int jmax, const int* mcols, const double* g0, const double* bnorm,
+                     double* Y) {
+    k_unscale_y<<<dim3((Ks + 63) / 64, R), 64, 0, st>>>(R, Ks, jmax, mcols, g0, bnorm, Y);
     LT_HIP(hipGetLastError());
     return 0;
 }
