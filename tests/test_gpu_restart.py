@@ -7,6 +7,7 @@ coefficient -eta_k per shift; opts.restart) against the oracle.
   the oracle's restarted FOM (same basis, same test), for cycles of 5 and 12 steps; a cycle
   longer than the solve gives the heads and steps of FOM without restarts.
 * Several wells that converge in different cycles, and several times in one basis.
+* Per-well rates and the initial head's term (its own contour weights) under restarts.
 * Refusals: restarts need FOM and the exact preconditioner, and only lt_solve restarts.
 """
 import numpy as np
@@ -98,4 +99,25 @@ def test_restart_refusals(lt):
     with pytest.raises(lt.LTError) as e:
         lt.lt_adjoint(h, p.sources, p.q, p.receivers, p.times, p.nz_contour, _opts(lt, 4))
     assert e.value.code == lt.LT_EUNSUPPORTED
+    h.close()
+
+
+def test_restart_with_rates_and_initial_head(lt):
+    # per-well rates and the initial head's term M phi0 (its shifts weigh by w_k alone, its
+    # heads enter every row): restarted against the oracle's heads
+    from oracle.heads import heads
+    p = wl.make_problem("C2", n=(48, 40), nsrc=3, ntimes=3)
+    rates = np.array([1.0, -0.5, 2.5])
+    phi0 = np.exp(wl.gaussian_random_field((48, 40), (1 / 48, 1 / 40), (0.2, 0.2), 1.0, 77)).flatten(order="F") - 1.0
+    announce("restarted FOM, rates + phi0")
+    ref = heads(p.n, p.h, p.kappa, p.S, p.sources, p.receivers, p.times, p.nz_contour, q=rates, phi0=phi0,
+                ndim=p.ndim)
+    h = device_problem(lt, p)
+    ph0 = torch.tensor(phi0, dtype=torch.float64, device="cuda")
+    o = lt.make_opts(tol=1e-10, maxit=400, n_tau=2, precond=lt.LT_PRECOND_EXACT, method=lt.LT_METHOD_FOM, restart=6)
+    phi, st = lt.lt_solve(h, p.sources, rates, p.times, p.nz_contour, p.receivers, o, phi0=ph0)
+    print(f"[restart] rates + phi0: steps {[int(v) for v in st['iters_per_rhs']]}, true residual "
+          f"{st['true_relres_max']:.2e}", flush=True)
+    assert st["rc"] == 0 and st["n_rhs"] == 4
+    check_heads(phi.cpu().numpy(), ref, 1e-6, "restart 6, rates + phi0")
     h.close()
