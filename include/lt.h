@@ -206,7 +206,7 @@ typedef struct {
  *              leaves the choice of shifts open (Sections 3 and 6); this is
  *              the build's own rule.  Costs one small device-to-host copy
  *              per outer iteration.
- *   restart    0 (default): one basis per solve, up to maxit columns.  m > 0
+ *   restart    0 (default): one basis per solve, up to maxit columns.  m in 1..2000
  *              (lt_solve with LT_PRECOND_EXACT and LT_METHOD_FOM only, else
  *              LT_EINVAL; other calls return LT_EUNSUPPORTED): the basis
  *              restarts every m steps from the residuals, which FOM with an

@@ -115,7 +115,7 @@ int validate_opts(const lt_opts* o) {
         !(o->net_keep >= 0.0) ||
         (o->graph != 0 && o->graph != 1) || (o->method != LT_METHOD_GMRES && o->method != LT_METHOD_FOM) ||
         (o->conv != LT_CONV_WEIGHTED && o->conv != LT_CONV_RELATIVE) || (o->tau_adapt != 0 && o->tau_adapt != 1) ||
-        (o->precision != LT_PREC_FP64 && o->precision != LT_PREC_MIXED) || o->restart < 0) {
+        (o->precision != LT_PREC_FP64 && o->precision != LT_PREC_MIXED) || o->restart < 0 || o->restart > 2000) {
         set_last_error("invalid lt_opts");
         return LT_EINVAL;
     }

@@ -89,7 +89,8 @@ def test_restarted_wells_finish_in_different_cycles(lt):
 def test_restart_refusals(lt):
     p = wl.make_problem("W1", n=(32, 32))
     h = device_problem(lt, p)
-    for kw in (dict(precond=lt.LT_PRECOND_GMG), dict(method=lt.LT_METHOD_GMRES), dict(restart=-1)):
+    for kw in (dict(precond=lt.LT_PRECOND_GMG), dict(method=lt.LT_METHOD_GMRES), dict(restart=-1),
+               dict(restart=2001)):
         o = _opts(lt, 4)
         for k, v in kw.items():
             setattr(o, k, v)
