@@ -17,6 +17,7 @@ krylov    Algorithm 1 (flexible shifted FOM/GMRES) with exact shift-and-invert
           preconditioners, and the preconditioner schedule of Section 3
 geostat   the quasi-linear geostatistical inversion (Section 5.1, Algorithm 2)
 timestep  Crank-Nicolson heads (the inversion's data with model error, Section 5.3)
+p1        piecewise-linear finite elements on a triangulated rectangle, lumped mass (Section 2.1)
 """
 from .fv import assemble, point_weights
 from .contour import talbot_nodes, talbot_full
@@ -25,7 +26,9 @@ from .jacobian import jacobian
 from .krylov import flexible_shifted, shift_invert, tau_schedule
 from .geostat import exp_covariance, gauss_newton_step, saddle_update
 from .timestep import crank_nicolson_heads
+from .p1 import assemble_p1, point_weights_p1, heads_p1
 
 __all__ = ["assemble", "point_weights", "talbot_nodes", "talbot_full", "heads",
            "shifted_fields", "jacobian", "flexible_shifted", "shift_invert", "tau_schedule",
-           "exp_covariance", "gauss_newton_step", "saddle_update", "crank_nicolson_heads"]
+           "exp_covariance", "gauss_newton_step", "saddle_update", "crank_nicolson_heads",
+           "assemble_p1", "point_weights_p1", "heads_p1"]
