@@ -280,6 +280,24 @@ void lt_opts_default(lt_opts* o);
 int lt_setup(const lt_grid* grid, const double* kappa, const double* S, const lt_bc* bc,
              void* hip_stream, lt_handle** out);
 
+/* The same handle for P1 finite elements (Section 2.1's weak form with
+ * piecewise-linear basis functions) on a 2D grid of cells: `cells` (ndim 2,
+ * n[0], n[1] >= 3 cells, n[2] = 1, spacings h[0], h[1]), each cell split by
+ * its anti-diagonal into two right triangles; kappa and S (device float64
+ * [n[1]][n[0]], x fastest) are per cell and hold on both its triangles.
+ * Every wall holds zero head; the unknowns are the interior vertices,
+ * (n[0] - 1) x (n[1] - 1), x fastest.  The mass matrix is lumped (M_ii = sum
+ * of S |e| / 3 over the triangles at vertex i).  A right triangle couples the
+ * ends of its hypotenuse by zero, so K is a five-point stencil on the
+ * vertices and every solver path applies unchanged.  Wells and receivers
+ * take the P1 basis functions at their position (barycentric coordinates in
+ * their triangle).  lt_solve, lt_solve_batch, lt_shift_invert, lt_vcycle and
+ * lt_precond_solve accept the handle.  lt_adjoint returns LT_EUNSUPPORTED:
+ * its sensitivities are those of the finite-volume operator.  Errors:
+ * LT_EINVAL for a NULL argument or a bad grid, LT_EHIP for no device. */
+int lt_setup_p1(const lt_grid* cells, const double* kappa, const double* S, void* hip_stream,
+                lt_handle** out);
+
 /* Heads phi[s][r][t] at receivers r and times t (host array times[ntimes],
  * strictly positive) for the wells and initial head of `src` (lt_sources):
  * the contour sum of eqn:half over the solutions of eqn:multipleshifted,

@@ -95,6 +95,8 @@ _lib.lt_opts_default.argtypes = [C.POINTER(lt_opts)]
 _lib.lt_opts_default.restype = None
 _lib.lt_setup.argtypes = [C.POINTER(lt_grid), _vp, _vp, C.POINTER(lt_bc), _vp, C.POINTER(_h)]
 _lib.lt_setup.restype = C.c_int
+_lib.lt_setup_p1.argtypes = [C.POINTER(lt_grid), _vp, _vp, _vp, C.POINTER(_h)]
+_lib.lt_setup_p1.restype = C.c_int
 _lib.lt_solve.argtypes = [_h, C.POINTER(lt_sources), _dp, C.c_int, C.POINTER(lt_contour),
                           C.POINTER(lt_points), C.POINTER(lt_opts), _vp, C.POINTER(lt_stats)]
 _lib.lt_solve.restype = C.c_int
@@ -262,6 +264,17 @@ def lt_setup(ndim, n, h, kappa, S, bc=(0, 0, 0, 0, 0, 0), stream=None, sy=0.0) -
     sp = _stream_ptr(stream)
     _check(_lib.lt_setup(C.byref(g), _dev_f64(kappa, "kappa"), _dev_f64(S, "S"), C.byref(b), sp, C.byref(out)))
     return Handle(out, g, sp)
+
+
+def lt_setup_p1(n, h, kappa, S, stream=None) -> Handle:
+    """P1 elements on an n[0] x n[1] cell grid (kappa, S per cell, float64 CUDA tensors); the
+    handle's unknowns are the (n[0] - 1) x (n[1] - 1) interior vertices."""
+    g = lt_grid(2, (C.c_int * 3)(int(n[0]), int(n[1]), 1), (C.c_double * 3)(float(h[0]), float(h[1]), 1.0))
+    out = _h()
+    sp = _stream_ptr(stream)
+    _check(_lib.lt_setup_p1(C.byref(g), _dev_f64(kappa, "kappa"), _dev_f64(S, "S"), sp, C.byref(out)))
+    gv = lt_grid(2, (C.c_int * 3)(int(n[0]) - 1, int(n[1]) - 1, 1), (C.c_double * 3)(float(h[0]), float(h[1]), 1.0))
+    return Handle(out, gv, sp)
 
 
 def _stats(nrhs, nshift):
@@ -538,7 +551,7 @@ def exported_symbols():
     return [name for name in _ABI_NAMES if hasattr(_lib, name)]
 
 
-_ABI_NAMES = ["lt_opts_default", "lt_setup", "lt_solve", "lt_adjoint", "lt_talbot", "lt_apply_operator",
+_ABI_NAMES = ["lt_opts_default", "lt_setup", "lt_setup_p1", "lt_solve", "lt_adjoint", "lt_talbot", "lt_apply_operator",
               "lt_vcycle", "lt_level_shape", "lt_strerror", "lt_last_error", "lt_destroy", "lt_unet_create",
               "lt_unet_nparams", "lt_unet_get_params", "lt_unet_set_params", "lt_unet_apply",
               "lt_unet_train_step", "lt_unet_grad", "lt_unet_attach", "lt_unet_destroy", "lt_precond_solve",

@@ -1098,6 +1098,48 @@ int lt_setup(const lt_grid* grid, const double* kappa, const double* S, const lt
     return LT_OK;
 }
 
+int lt_setup_p1(const lt_grid* cells, const double* kappa, const double* S, void* hip_stream, lt_handle** out) {
+    if (!cells || !kappa || !S || !out) {
+        set_last_error("lt_setup_p1: NULL argument");
+        return LT_EINVAL;
+    }
+    *out = nullptr;
+    if (cells->ndim != 2 || cells->n[2] != 1 || cells->n[0] < 3 || cells->n[1] < 3 || !(cells->h[0] > 0.0) ||
+        !(cells->h[1] > 0.0)) {
+        set_last_error("lt_setup_p1: a 2D grid of at least 3 x 3 cells with positive spacings");
+        return LT_EINVAL;
+    }
+    const long long Nll = (long long)(cells->n[0] - 1) * (cells->n[1] - 1);
+    if (Nll > kMaxCells) {
+        set_last_error("lt_setup_p1: grid too large");
+        return LT_EINVAL;
+    }
+    lt_handle* h = new (std::nothrow) lt_handle();
+    if (!h) return LT_ENOMEM;
+    h->p1 = true;
+    h->cells = *cells;
+    // the unknowns: the interior vertices, spaced like the cells
+    h->grid = *cells;
+    h->grid.n[0] = cells->n[0] - 1;
+    h->grid.n[1] = cells->n[1] - 1;
+    std::memset(&h->bc, 0, sizeof(h->bc));  // zero head on every wall
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        set_last_error("lt_setup_p1: no HIP device");
+        return LT_EHIP;
+    }
+    h->N = (int)Nll;
+    int rc = noalloc_init_device(h->device);
+    if (rc >= 0) rc = mg_build(h, kappa, S, &h->cells);
+    if (rc < 0) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return LT_OK;
+}
+
 void lt_destroy(lt_handle* h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
@@ -1213,9 +1255,14 @@ int lt_solve(lt_handle* h, const lt_sources* src, const double* times, int ntime
     Plan plan;
     LT_TRY(make_plan(times, ntimes, contour->nz, 1.0, &o, &plan));
     PointsCSR sc, rcsr;
-    LT_TRY(points_csr(h->grid, &src->pts, &sc));
+    if (h->p1) {
+        LT_TRY(points_csr_p1(h->cells, &src->pts, &sc));
+        LT_TRY(points_csr_p1(h->cells, receivers, &rcsr));
+    } else {
+        LT_TRY(points_csr(h->grid, &src->pts, &sc));
+        LT_TRY(points_csr(h->grid, receivers, &rcsr));
+    }
     scale_by_rates(src, &sc);
-    LT_TRY(points_csr(h->grid, receivers, &rcsr));
     DevPoints ds, dr;
     LT_TRY(upload_points(h, sc, "src", &ds));
     LT_TRY(upload_points(h, rcsr, "rec", &dr));
@@ -1261,6 +1308,10 @@ int lt_adjoint(lt_handle* h, const lt_sources* src, const lt_points* receivers, 
     if (!h || !receivers || receivers->n < 1 || !times || ntimes < 1 || !contour || (!dlnK && !dlnS)) {
         set_last_error("lt_adjoint: bad argument");
         return LT_EINVAL;
+    }
+    if (h->p1) {
+        set_last_error("lt_adjoint: the sensitivities are those of the finite-volume operator (not of P1 handles)");
+        return LT_EUNSUPPORTED;
     }
     LT_TRY(check_sources(src, receivers->n, true, "lt_adjoint"));
     for (int t = 0; t < ntimes; ++t)

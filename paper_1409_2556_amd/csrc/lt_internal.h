@@ -115,6 +115,8 @@ struct lt_handle {
     std::vector<lt::CoarseInverse> coarse_cache;
     std::vector<double> coarse_host;  // coarsest level coefficients [5][Nc] on the host
     lt::DevBuf kappa;                 // copy of the fine-grid conductivity (sensitivities)
+    bool p1 = false;                  // P1 elements: the unknowns are the interior vertices of `cells`
+    lt_grid cells{};                  // P1: the cell grid the triangulation comes from
     lt::DevBuf mstor;                 // S V per fine cell when water-table storage joins the mass
     // tile shape id of the fused 2D smoothers per level, [0]: FP64, [1]: FP32 (lt_autotune)
     int tiles[2][16] = {};
@@ -204,6 +206,9 @@ struct PointsCSR {
     std::vector<double> wt;
 };
 int points_csr(const lt_grid& g, const lt_points* pts, PointsCSR* out);
+// P1 handles: the basis functions at each point (barycentric coordinates in the triangle of
+// the cell grid `cells` that contains it), over the interior vertices
+int points_csr_p1(const lt_grid& cells, const lt_points* pts, PointsCSR* out);
 
 // dense complex inverse (Gauss-Jordan with partial pivoting); returns 0 or LT_EINVAL if singular
 int dense_inverse(int n, std::vector<cdouble>& a, std::vector<cdouble>& inv);
@@ -230,7 +235,7 @@ int exact_apply(lt_handle* h, const ExactFactor* F, int R, const double* b, size
 size_t exact_matrix_bytes(const ExactFactor* F);
 
 // ------------------------------------------------------------- multigrid
-int mg_build(lt_handle* h, const double* kappa, const double* S);
+int mg_build(lt_handle* h, const double* kappa, const double* S, const lt_grid* p1_cells = nullptr);
 const CoarseInverse* mg_coarse_inverse(lt_handle* h, cdouble tau, int* rc);
 // One V-cycle on level 0 for R complex vectors: b0, x0 in the level-0 work arrays of
 // precision T (x0 is overwritten).  active: device [R] mask or nullptr.

@@ -169,6 +169,40 @@ __global__ void k_coarsen(const double* __restrict__ fc, const double* __restric
 }
 
 // D_i = sum_a (W_a[i] + T_a[i] + T_a[i - e_a]).
+// P1 finite elements (Section 2.1's weak form) on a 2D cell grid ncx x ncy split into right
+// triangles (each cell by its anti-diagonal), lumped mass, zero head on every wall, assembled
+// on the interior vertices (ncx - 1) x (ncy - 1), x fastest.  A right triangle couples the
+// two ends of its hypotenuse by zero, so the stiffness is a five-point stencil: the edge from
+// vertex (I, J) to (I + 1, J) carries hy/hx times the mean kappa of the two cells beside it,
+// the edge to (I, J + 1) hx/hy times theirs; an edge to a wall vertex is a wall term.  The
+// lumped mass sums S |e| / 3 over the six triangles at the vertex.  Same layout as
+// k_fine_assemble (Tx, Ty, Tz, D by k_finish_diag, m; walls per axis).
+__global__ void k_p1_assemble(const double* __restrict__ kappa, const double* __restrict__ S, int ncx, int ncy,
+                              double hx, double hy, double* __restrict__ out, double* __restrict__ walls) {
+    const int nvx = ncx - 1, nvy = ncy - 1, N = nvx * nvy;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int x = i % nvx, y = i / nvx, I = x + 1, J = y + 1;  // vertex (I, J); cell (a, b) has corner (a, b) lowest
+    const double kc00 = kappa[(I - 1) + ncx * (J - 1)], kc10 = kappa[I + ncx * (J - 1)];
+    const double kc01 = kappa[(I - 1) + ncx * J], kc11 = kappa[I + ncx * J];
+    const double ax = hy / hx, ay = hx / hy;
+    const double e_right = ax * 0.5 * (kc10 + kc11);  // to (I + 1, J): cells (I, J - 1), (I, J)
+    const double e_left = ax * 0.5 * (kc00 + kc01);   // to (I - 1, J): cells (I - 1, J - 1), (I - 1, J)
+    const double e_up = ay * 0.5 * (kc01 + kc11);     // to (I, J + 1): cells (I - 1, J), (I, J)
+    const double e_down = ay * 0.5 * (kc00 + kc10);  // to (I, J - 1): cells (I - 1, J - 1), (I, J - 1)
+    const size_t n = N;
+    out[i] = x + 1 < nvx ? e_right : 0.0;
+    out[n + i] = y + 1 < nvy ? e_up : 0.0;
+    out[2 * n + i] = 0.0;
+    walls[i] = (x == 0 ? e_left : 0.0) + (x + 1 == nvx ? e_right : 0.0);
+    walls[n + i] = (y == 0 ? e_down : 0.0) + (y + 1 == nvy ? e_up : 0.0);
+    walls[2 * n + i] = 0.0;
+    const double s00 = S[(I - 1) + ncx * (J - 1)], s10 = S[I + ncx * (J - 1)];
+    const double s01 = S[(I - 1) + ncx * J], s11 = S[I + ncx * J];
+    // six triangles: one of cell (I, J), two of (I - 1, J), two of (I, J - 1), one of (I - 1, J - 1)
+    out[4 * n + i] = hx * hy / 6.0 * (s11 + 2.0 * s01 + 2.0 * s10 + s00);
+}
+
 __global__ void k_finish_diag(double* __restrict__ c, const double* __restrict__ w, int nx, int ny, int nz) {
     const int N = nx * ny * nz;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -624,7 +658,7 @@ __global__ void k_zero(T* __restrict__ x, size_t per, const int* __restrict__ ac
 // ------------------------------------------------------------------ host side
 static inline unsigned nblk(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-int mg_build(lt_handle* h, const double* kappa, const double* S) {
+int mg_build(lt_handle* h, const double* kappa, const double* S, const lt_grid* p1_cells) {
     const lt_grid& g = h->grid;
     hipStream_t st = h->stream;
     std::vector<Level>& lv = h->levels;
@@ -647,9 +681,13 @@ int mg_build(lt_handle* h, const double* kappa, const double* S) {
         LT_TRY(h->mstor.reserve(sizeof(double) * (size_t)f.N));
         mstor = h->mstor.as<double>();
     }
-    k_fine_assemble<<<nblk(f.N), kBlock, 0, st>>>(kappa, S, f.n[0], f.n[1], f.n[2], g.ndim, f.h[0], f.h[1],
-                                                   f.h[2], lo, hi, h->bc.sy, lv[0].c64.as<double>(),
-                                                   walls_f.as<double>(), mstor);
+    if (p1_cells)
+        k_p1_assemble<<<nblk(f.N), kBlock, 0, st>>>(kappa, S, p1_cells->n[0], p1_cells->n[1], p1_cells->h[0],
+                                                    p1_cells->h[1], lv[0].c64.as<double>(), walls_f.as<double>());
+    else
+        k_fine_assemble<<<nblk(f.N), kBlock, 0, st>>>(kappa, S, f.n[0], f.n[1], f.n[2], g.ndim, f.h[0], f.h[1],
+                                                       f.h[2], lo, hi, h->bc.sy, lv[0].c64.as<double>(),
+                                                       walls_f.as<double>(), mstor);
     LT_HIP(hipGetLastError());
     k_finish_diag<<<nblk(f.N), kBlock, 0, st>>>(lv[0].c64.as<double>(), walls_f.as<double>(), f.n[0], f.n[1],
                                                 f.n[2]);

@@ -162,6 +162,48 @@ int points_csr(const lt_grid& g, const lt_points* pts, PointsCSR* out) {
     return 0;
 }
 
+int points_csr_p1(const lt_grid& c, const lt_points* pts, PointsCSR* out) {
+    out->off.assign(1, 0);
+    out->cell.clear();
+    out->wt.clear();
+    if (!pts || pts->n <= 0) return 0;
+    if (!pts->xyz) {
+        set_last_error("points: xyz is NULL");
+        return LT_EINVAL;
+    }
+    const int nx = c.n[0], ny = c.n[1];
+    const double hx = c.h[0], hy = c.h[1];
+    for (int p = 0; p < pts->n; ++p) {
+        const double x = pts->xyz[3 * p], y = pts->xyz[3 * p + 1];
+        if (!(x >= 0.0 && x <= nx * hx && y >= 0.0 && y <= ny * hy)) {
+            set_last_error("points: coordinate outside the domain");
+            return LT_EINVAL;
+        }
+        const int i = std::min(std::max((int)std::floor(x / hx), 0), nx - 1);
+        const int j = std::min(std::max((int)std::floor(y / hy), 0), ny - 1);
+        const double xi = x / hx - i, eta = y / hy - j;
+        int vi[3], vj[3];
+        double lam[3];
+        if (xi + eta <= 1.0) {  // the triangle (i, j), (i + 1, j), (i, j + 1)
+            vi[0] = i; vj[0] = j; lam[0] = 1.0 - xi - eta;
+            vi[1] = i + 1; vj[1] = j; lam[1] = xi;
+            vi[2] = i; vj[2] = j + 1; lam[2] = eta;
+        } else {                // the triangle (i + 1, j + 1), (i, j + 1), (i + 1, j)
+            vi[0] = i + 1; vj[0] = j + 1; lam[0] = xi + eta - 1.0;
+            vi[1] = i; vj[1] = j + 1; lam[1] = 1.0 - xi;
+            vi[2] = i + 1; vj[2] = j; lam[2] = 1.0 - eta;
+        }
+        for (int a = 0; a < 3; ++a) {
+            // wall vertices hold zero head
+            if (vi[a] <= 0 || vj[a] <= 0 || vi[a] >= nx || vj[a] >= ny || lam[a] == 0.0) continue;
+            out->cell.push_back((vi[a] - 1) + (nx - 1) * (vj[a] - 1));
+            out->wt.push_back(lam[a]);
+        }
+        out->off.push_back((int)out->cell.size());
+    }
+    return 0;
+}
+
 int dense_inverse(int n, std::vector<cdouble>& a, std::vector<cdouble>& inv) {
     inv.assign((size_t)n * n, 0.0);
     for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
