@@ -115,6 +115,9 @@ def _parse():
                     help="C5J: red-black sweeps before and after the coarse correction on the 3D problems")
     ap.add_argument("--maxit", type=int, default=48,
                     help="C5J: outer iterations the basis workspace is sized for")
+    ap.add_argument("--p1", action="store_true",
+                    help="C2: the same workload on P1 finite elements (lt_setup_p1: 257x257 cells, the 256x256 "
+                         "interior vertices as unknowns; the oracle sample from the P1 oracle)")
     ap.add_argument("--water-table", type=float, default=None, metavar="SY",
                     help="C2/C3: make the top wall (+y in 2D, +z in 3D) a linearised water table with this "
                          "specific yield (the other walls keep zero head)")
@@ -142,14 +145,18 @@ def _boundary_config(p):
     return {}
 
 
-def _handle(lt, p, tune, nvec):
-    """Handle on a stream of its own, with smoother tiles tuned for both precisions (setup, untimed)."""
+def _handle(lt, p, tune, nvec, p1=False):
+    """Handle on a stream of its own, with smoother tiles tuned for both precisions (setup, untimed).
+    p1: P1 elements on the problem's cells (the interior vertices as unknowns)."""
     import torch
     kap = torch.tensor(p.kappa, dtype=torch.float64, device="cuda")
     S = torch.tensor(p.S, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     stream = torch.cuda.Stream()
-    h = lt.lt_setup(p.ndim, p.n, p.h, kap, S, bc=p.bc, stream=stream, sy=p.sy)
+    if p1:
+        h = lt.lt_setup_p1(p.n[:2], p.h[:2], kap, S, stream=stream)
+    else:
+        h = lt.lt_setup(p.ndim, p.n, p.h, kap, S, bc=p.bc, stream=stream, sy=p.sy)
     h._torch_stream = stream
     tiles = {}
     if tune:
@@ -217,14 +224,19 @@ def _run_variant(lt, hs, p, opts, steps, warmup, profile=0):
     return dt, st, phi.cpu().numpy(), prof
 
 
-def _cpu_baseline(p, ntimes):
+def _cpu_baseline(p, ntimes, p1=False):
     """The oracle as it stands, on a bounded sample: every source, the first
     `ntimes` measurement times (ntimes * N_z/2 factorisations)."""
-    from oracle.heads import heads
     workers = min(os.cpu_count() or 1, 16)
     t0 = time.perf_counter()
-    ref = heads(p.n, p.h, p.kappa, p.S, p.sources, p.receivers, p.times[:ntimes], p.nz_contour,
-                q=p.q, bc=p.bc, workers=workers, ndim=p.ndim, sy=p.sy)
+    if p1:
+        from oracle.p1 import heads_p1
+        ref = heads_p1(p.n[:2], p.h[:2], p.kappa, p.S, p.sources, p.receivers, p.times[:ntimes], p.nz_contour,
+                       q=p.q, workers=workers)
+    else:
+        from oracle.heads import heads
+        ref = heads(p.n, p.h, p.kappa, p.S, p.sources, p.receivers, p.times[:ntimes], p.nz_contour,
+                    q=p.q, bc=p.bc, workers=workers, ndim=p.ndim, sy=p.sy)
     dt = time.perf_counter() - t0
     pairs = len(p.sources) * ntimes * (p.nz_contour // 2)
     return ref, {"value": pairs / dt, "unit": "shifted solves/s", "cores": workers, "kind": "oracle",
@@ -251,12 +263,18 @@ def main():
     if args.workload == "C3":
         return main_adjoint(args)
     import workloads as wl
-    p = _with_boundary(wl.make_problem(WORKLOAD), args)
+    if args.p1:
+        if args.water_table is not None:
+            print(json.dumps({"error": "--p1 takes zero-head walls only"}))
+            sys.exit(2)
+        p = wl.make_problem(WORKLOAD, n=(257, 257))  # 256 x 256 interior vertices
+    else:
+        p = _with_boundary(wl.make_problem(WORKLOAD), args)
     # the CPU oracle runs first, before this process touches the GPU
     cpu, ref = None, None
     nt = args.cpu_sample_times
     if not args.no_cpu_baseline:
-        ref, cpu = _cpu_baseline(p, nt)
+        ref, cpu = _cpu_baseline(p, nt, p1=args.p1)
         print(f"[bench] oracle sample: {cpu['value']:.2f} solves/s on {cpu['cores']} cores", file=sys.stderr,
               flush=True)
 
@@ -266,11 +284,11 @@ def main():
     torch.cuda.set_device(0)
     groups = max(1, min(args.groups, len(p.sources)))
     # tiles tuned for the right-hand sides one launch carries (one group's share)
-    h, tiles = _handle(lt, p, not args.no_tune, -(-len(p.sources) // groups))
+    h, tiles = _handle(lt, p, not args.no_tune, -(-len(p.sources) // groups), p1=args.p1)
     hs = [h]
     for _ in range(groups - 1):
         # the other groups' handles take the first handle's tiles (tuned for the full batch)
-        hg, _ = _handle(lt, p, False, len(p.sources))
+        hg, _ = _handle(lt, p, False, len(p.sources), p1=args.p1)
         if tiles:
             for name, prec in (("fp64", lt.LT_PREC_FP64), ("mixed", lt.LT_PREC_MIXED)):
                 lt.lt_set_tiles(hg, prec, [_tile_id(lt, t) for t in tiles[name]["tiles"]])
@@ -339,8 +357,8 @@ def main():
         achieved = bytes_per_launch / avg_s / 1e9
         t0 = (tiles.get(prof_name) or {}).get("tiles") or [[32, 16]]
         tx, ty = t0[0]
-        # the committed counter run used the 32x16 fine-level tile
-        traffic = _measured_traffic() if (tx, ty) == (32, 16) else None
+        # the committed counter run used the 32x16 fine-level tile (and the FV operator)
+        traffic = _measured_traffic() if (tx, ty) == (32, 16) and not args.p1 else None
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                     "kernel": f"k_post2d_refine<float,2,{tx},{ty}> (fine-grid prolongation, 2 red-black sweeps, "
@@ -360,7 +378,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64+f32",
         "data": "synthetic",
-        "config": {"workload": "2D 256x256 GRF aquifer (var 1, corr 0.1), 8 sources x 16 receivers, "
+        "config": {"workload": ("2D P1 finite elements, 256x256 interior vertices of a 257x257-cell GRF aquifer "
+                                "(right triangles, lumped mass)" if args.p1 else "2D 256x256 GRF aquifer") +
+                               " (var 1, corr 0.1), 8 sources x 16 receivers, "
                                "10 times, 20-node Talbot, 1 tau, GMG V(2,2) RB-GS",
                    "rhs": len(p.sources), "shifts_per_rhs": len(p.times) * (p.nz_contour // 2),
                    "pairs": pairs, "tol": head["tol"], "relax": args.relax, "variant": hname, "tau_adapt": args.tau_adapt,

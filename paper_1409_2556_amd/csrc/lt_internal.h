@@ -68,6 +68,11 @@ struct Level {
     int N;
     double h[3];
     int coarsened_from_fine[3];  // axes halved when this level was built from the finer one
+    // distance from a zero-head wall to the first unknown, in units of h, per axis: 1/2 for
+    // cell-centred unknowns at every level; 1 on the vertex grid of P1 elements, where an
+    // aggregate of two moves it to delta / 2 + 1/4 (coarse wall terms and the prolongation's
+    // wall weights follow it)
+    double delta[3] = {0.5, 0.5, 0.5};
     // coefficients: [5][N] = Tx, Ty, Tz, D, m
     DevBuf c64, c32;
     LevelView<double> v64() const;

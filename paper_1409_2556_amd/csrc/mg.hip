@@ -134,7 +134,7 @@ __global__ void k_fine_assemble(const double* __restrict__ kappa, const double* 
 // Aggregate a fine level into a coarse one (see the file comment).
 __global__ void k_coarsen(const double* __restrict__ fc, const double* __restrict__ fw, int fnx, int fny,
                           int fnz, int cnx, int cny, int cnz, int cox, int coy, int coz,
-                          double* __restrict__ cc, double* __restrict__ cw) {
+                          double* __restrict__ cc, double* __restrict__ cw, double3 wscale) {
     const int Nc = cnx * cny * cnz;
     const int Nf = fnx * fny * fnz;
     int I = blockIdx.x * blockDim.x + threadIdx.x;
@@ -160,10 +160,13 @@ __global__ void k_coarsen(const double* __restrict__ fc, const double* __restric
                     if (fc3[a] == k1[a]) Tsum[a] += fc[(size_t)a * Nf + f];
                 }
             }
+    // wscale: the wall terms' correction where the wall is not half a spacing from the first
+    // unknown (delta_fine / delta_coarse; 1 for cell-centred levels)
+    const double ws[3] = {wscale.x, wscale.y, wscale.z};
     for (int a = 0; a < 3; ++a) {
         double fa = co[a] ? 0.5 : 1.0;
         cc[(size_t)a * Nc + I] = fa * Tsum[a];
-        cw[(size_t)a * Nc + I] = fa * Wsum[a];
+        cw[(size_t)a * Nc + I] = fa * Wsum[a] * ws[a];
     }
     cc[(size_t)4 * Nc + I] = msum;
 }
@@ -670,6 +673,7 @@ int mg_build(lt_handle* h, const double* kappa, const double* S, const lt_grid* 
         f.coarsened_from_fine[a] = 0;
     }
     f.N = g.n[0] * g.n[1] * g.n[2];
+    if (p1_cells) f.delta[0] = f.delta[1] = 1.0;  // vertices: the walls lie one spacing out
     lv.push_back(f);
     DevBuf walls_f, walls_c;
     LT_TRY(lv[0].c64.reserve(sizeof(double) * 5 * (size_t)f.N));
@@ -708,17 +712,22 @@ int mg_build(lt_handle* h, const double* kappa, const double* S, const lt_grid* 
         }
         if (!any) break;
         Level C;
+        double ws[3];
         for (int a = 0; a < 3; ++a) {
             C.n[a] = co[a] ? L.n[a] / 2 : L.n[a];
             C.h[a] = co[a] ? L.h[a] * 2 : L.h[a];
             C.coarsened_from_fine[a] = co[a];
+            C.delta[a] = co[a] ? 0.5 * L.delta[a] + 0.25 : L.delta[a];
+            // a wall term is kappa A / (delta h): the aggregation's rule holds it for delta = 1/2
+            ws[a] = co[a] ? L.delta[a] / C.delta[a] : 1.0;
         }
         C.N = C.n[0] * C.n[1] * C.n[2];
         LT_TRY(C.c64.reserve(sizeof(double) * 5 * (size_t)C.N));
         LT_TRY(walls_c.reserve(sizeof(double) * 3 * (size_t)C.N));
         k_coarsen<<<nblk(C.N), kBlock, 0, st>>>(L.c64.as<double>(), walls_f.as<double>(), L.n[0], L.n[1],
                                                 L.n[2], C.n[0], C.n[1], C.n[2], co[0], co[1], co[2],
-                                                C.c64.as<double>(), walls_c.as<double>());
+                                                C.c64.as<double>(), walls_c.as<double>(),
+                                                make_double3(ws[0], ws[1], ws[2]));
         LT_HIP(hipGetLastError());
         k_finish_diag<<<nblk(C.N), kBlock, 0, st>>>(C.c64.as<double>(), walls_c.as<double>(), C.n[0], C.n[1],
                                                     C.n[2]);
@@ -1025,6 +1034,18 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
     // a no-flux one (a water-table wall carries no conductive flux either)
     const T gsign[2] = {T(-1), T(1)};
     auto g = [&](int face) { return gsign[h->bc.face[face] == LT_BC_DIRICHLET0 ? 0 : 1]; };
+    // the same for the prolongation from level l + 1 to level l: at a zero-head wall the fine
+    // unknown nearest it takes delta_l / (2 delta_{l+1}) of its aggregate's value (the linear
+    // interpolation to zero at the wall), i.e. the ghost parity 4 delta_l / (2 delta_{l+1}) - 3,
+    // which is -1 for cell-centred levels
+    auto gl = [&](int l, int face) {
+        if (h->bc.face[face] != LT_BC_DIRICHLET0) return T(1);
+        const int a = face / 2;
+        const Level& F = h->levels[l];
+        const Level& Cl = h->levels[l + 1];
+        if (!Cl.coarsened_from_fine[a]) return T(-1);
+        return T(4.0 * F.delta[a] / (2.0 * Cl.delta[a]) - 3.0);
+    };
     // ---- down
     for (int l = 0; l < lc; ++l) {
         const Level& L = h->levels[l];
@@ -1106,7 +1127,7 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
         const Level& C = h->levels[l + 1];
         LevelView<T> v = view<T>(L);
         if (fused2d) {
-            T4 gh = {(double)g(0), (double)g(1), (double)g(2), (double)g(3)};
+            T4 gh = {(double)gl(l, 0), (double)gl(l, 1), (double)gl(l, 2), (double)gl(l, 3)};
             unsigned long long* pc = nullptr;
             const bool prof = l == 0 && h->prof_target == LT_PROF_POST_FINE;
             hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1130,7 +1151,8 @@ int mg_vcycle(lt_handle* h, cdouble tau, int nu1, int nu2, int R, const int* act
             const size_t np = (c0only && cpl(l)) ? L.N / 2 : L.N;
             k_prolong_rb<T, kSweepRhs><<<dim3(nblk(np), (R + kSweepRhs - 1) / kSweepRhs), kBlock, 0, st>>>(
                 L.n[0], L.n[1], L.n[2], C.n[0], C.n[1], C.n[2], C.coarsened_from_fine[0], C.coarsened_from_fine[1],
-                C.coarsened_from_fine[2], g(0), g(1), g(2), g(3), g(4), g(5), xpost[l + 1], xpre[l], alist, R, cpl(l),
+                C.coarsened_from_fine[2], gl(l, 0), gl(l, 1), gl(l, 2), gl(l, 3), gl(l, 4), gl(l, 5), xpost[l + 1], xpre[l],
+                alist, R, cpl(l),
                 cpl(l + 1), c0only);
             for (int s = 0; s < nu2; ++s)
                 for (int c = 1; c >= 0; --c)
