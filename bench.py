@@ -857,9 +857,10 @@ def main_exact(args):
         S = torch.tensor(p.S, dtype=torch.float64, device="cuda")
         return lt.lt_setup(p.ndim, p.n, p.h, kap, S, bc=p.bc, sy=p.sy)
 
-    def run(p, n_tau, check=False, profile=0):
+    def run(p, n_tau, check=False, profile=0, **extra):
         h = handle(p)
-        o = lt.make_opts(tol=tol, maxit=400, n_tau=n_tau, precond=lt.LT_PRECOND_EXACT, conv=lt.LT_CONV_RELATIVE)
+        o = lt.make_opts(tol=tol, maxit=400, n_tau=n_tau, precond=lt.LT_PRECOND_EXACT, conv=lt.LT_CONV_RELATIVE,
+                         **extra)
         phi, st0 = lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, o)
         for _ in range(args.warmup):
             lt.lt_solve(h, p.sources, p.q, p.times, p.nz_contour, p.receivers, o)
@@ -884,7 +885,7 @@ def main_exact(args):
         h.close()
         return r
 
-    tables = {"variance_128": {}, "time_128_var1.6": {}, "grid_var1.6": {}}
+    tables = {"variance_128": {}, "time_128_var1.6": {}, "grid_var1.6": {}, "fom_restart_128": {}}
     for var in ((0.8, 1.6, 3.5) if args.exact_cases == "all" else ()):
         p = _exact_problem(wl, var=var)
         tables["variance_128"][str(var)] = {s: run(p, nt, check=True) for s, nt in (("single", 1), ("flexible", 2))}
@@ -897,6 +898,11 @@ def main_exact(args):
         p = _exact_problem(wl, n=(n, n))
         tables["grid_var1.6"][f"{n}^2"] = {s: run(p, nt) for s, nt in (("single", 1), ("flexible", 2))}
         print(f"[bench] EXACT grid {n}: {tables['grid_var1.6'][f'{n}^2']}", file=sys.stderr, flush=True)
+    # the FOM variant restarted every m steps from its collinear residuals (0: never), the
+    # headline problem: the basis holds m columns instead of all of them
+    for m in ((0, 5, 10, 20) if args.exact_cases == "all" else ()):
+        tables["fom_restart_128"][str(m)] = run(head_p, 2, check=True, method=lt.LT_METHOD_FOM, restart=m)
+        print(f"[bench] EXACT FOM restart {m}: {tables['fom_restart_128'][str(m)]}", file=sys.stderr, flush=True)
     head = run(head_p, 2, check=True, profile=lt.LT_PROF_EXACT)
     wells = np.asarray(wl.configs._C2_WELLS, dtype=np.float64)
     multi = None
