@@ -1,22 +1,26 @@
-"""Piecewise-linear (P1) finite elements on a triangulated rectangle (Section 2.1's weak form).
+"""Piecewise-linear (P1) finite elements on a subdivided box (Section 2.1's weak form).
 
 Oracle (test infrastructure only).
 
 The weak form of Section 2.1 with continuous piecewise-linear basis functions phi_i gives
 M dphi/dt + K phi = q b with K_ij = sum_e kappa_e int_e grad phi_i . grad phi_j and
-b_i = phi_i(x_well).  The mesh here: an nx x ny grid of cells of size hx x hy, each cell
-split by its anti-diagonal into two right triangles,
+b_i = phi_i(x_well).  The meshes here subdivide a grid of cells (hx x hy, or hx x hy x hz):
 
-    T1 = (v00, v10, v01)  (right angle at v00),    T2 = (v11, v01, v10)  (right angle at v11),
+* 2D: each cell split by its anti-diagonal into two right triangles,
+  T1 = (v00, v10, v01) (right angle at v00) and T2 = (v11, v01, v10) (right angle at v11);
+* 3D: each cell split into the six path tetrahedra of the Kuhn subdivision, one per order
+  (a1, a2, a3) of the axes: v000, v000 + e_a1, v000 + e_a1 + e_a2, v111.
 
-both with the cell's kappa and S.  Every wall holds zero head, so the unknowns are the
-interior vertices (nx - 1) x (ny - 1), x fastest.  The mass matrix is lumped: M_ii =
-sum_e S_e |e| / 3 over the triangles that touch vertex i (the paper's consistent mass is
-replaced by its row sums, so that M stays diagonal).
+Every element takes its cell's kappa and S.  Every wall holds zero head, so the unknowns are
+the interior vertices, x fastest.  The mass matrix is lumped: M_ii = sum_e S_e |e| / (d + 1)
+over the elements that touch vertex i (the paper's consistent mass replaced by its row sums,
+so that M stays diagonal).
 
-Everything below is the element-by-element definition: local gradients of the barycentric
-coordinates, local stiffness kappa |e| grad lambda_a . grad lambda_b, local lumped mass,
-assembled by index; point values by the barycentric coordinates of the containing triangle.
+Everything below is the element-by-element definition: gradients of the barycentric
+coordinates from the inverse of the element's affine map, local stiffness
+kappa |e| grad lambda_a . grad lambda_b, local lumped mass, assembled by index; point values
+by the barycentric coordinates in an element that contains the point (found by trying the
+elements of its cell).
 """
 from __future__ import annotations
 
@@ -27,61 +31,90 @@ from .contour import talbot_nodes
 from .heads import _map_shifts
 
 
-def _triangles(nx, ny, hx, hy):
-    """Vertex coordinates [3, 2] and vertex indices (i, j) of every triangle, with its cell."""
+def _dims(n, h):
+    n = [int(v) for v in n]
+    h = [float(v) for v in h]
+    d = 3 if len(n) > 2 and n[2] > 1 else 2
+    return d, n[:d], h[:d]
+
+
+def _cell_elements(idx, d):
+    """Vertex index tuples of the elements of the cell with lowest corner idx."""
+    import itertools
+    if d == 2:
+        i, j = idx
+        v00, v10, v01, v11 = (i, j), (i + 1, j), (i, j + 1), (i + 1, j + 1)
+        return [(v00, v10, v01), (v11, v01, v10)]
     out = []
-    for j in range(ny):
-        for i in range(nx):
-            c = i + nx * j
-            v00, v10, v01, v11 = (i, j), (i + 1, j), (i, j + 1), (i + 1, j + 1)
-            for tri in ((v00, v10, v01), (v11, v01, v10)):
-                xy = np.array([[a * hx, b * hy] for a, b in tri], dtype=np.float64)
-                out.append((xy, tri, c))
+    for order in itertools.permutations(range(3)):
+        v = list(idx)
+        path = [tuple(v)]
+        for a in order:
+            v[a] += 1
+            path.append(tuple(v))
+        out.append(tuple(path))
+    return out
+
+
+def _elements(n, h):
+    """(vertex coordinates [d + 1, d], vertex index tuples, cell) of every element."""
+    import itertools
+    d, n, h = _dims(n, h)
+    out = []
+    for idx in itertools.product(*[range(n[a]) for a in reversed(range(d))]):
+        idx = tuple(reversed(idx))  # x fastest
+        c = 0
+        for a in reversed(range(d)):
+            c = c * n[a] + idx[a]
+        for el in _cell_elements(idx, d):
+            xy = np.array([[v[a] * h[a] for a in range(d)] for v in el], dtype=np.float64)
+            out.append((xy, el, c))
     return out
 
 
 def _local(xy):
-    """Area and gradients [3, 2] of the barycentric coordinates of a triangle."""
-    x, y = xy[:, 0], xy[:, 1]
-    det = (x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0])
-    area = 0.5 * abs(det)
-    # grad lambda_a = (y_b - y_c, x_c - x_b) / det for (a, b, c) cyclic
-    g = np.zeros((3, 2))
-    for a in range(3):
-        b, c = (a + 1) % 3, (a + 2) % 3
-        g[a] = [(y[b] - y[c]) / det, (x[c] - x[b]) / det]
-    return area, g
+    """Measure and gradients [d + 1, d] of the barycentric coordinates of a simplex."""
+    d = xy.shape[1]
+    A = np.hstack([np.ones((d + 1, 1)), xy])  # lambda_i(x) = [1, x] . Ainv[:, i]
+    Ainv = np.linalg.inv(A)
+    vol = abs(np.linalg.det(xy[1:] - xy[0])) / np.prod(np.arange(1, d + 1))
+    return vol, Ainv[1:, :].T
 
 
-def vertex_index(nx, ny):
-    """Map (i, j) of a vertex to its unknown's index, or -1 on a wall (zero head)."""
+def vertex_index(n, h=None):
+    """Map the index tuple of a vertex to its unknown's index, or -1 on a wall (zero head)."""
+    n = [int(v) for v in n]
+    d = 3 if len(n) > 2 and n[2] > 1 else 2
+    n = n[:d]
+
     def idx(v):
-        i, j = v
-        if i <= 0 or j <= 0 or i >= nx or j >= ny:
+        if any(v[a] <= 0 or v[a] >= n[a] for a in range(d)):
             return -1
-        return (i - 1) + (nx - 1) * (j - 1)
+        k = 0
+        for a in reversed(range(d)):
+            k = k * (n[a] - 1) + (v[a] - 1)
+        return k
     return idx
 
 
 def assemble_p1(n, h, kappa, S):
-    """K (sparse) and the lumped mass m over the interior vertices of an n[0] x n[1] cell grid."""
-    nx, ny = int(n[0]), int(n[1])
-    hx, hy = float(h[0]), float(h[1])
+    """K (sparse) and the lumped mass m over the interior vertices of a cell grid n (2D or 3D)."""
+    d, nn, hh = _dims(n, h)
     kappa = np.asarray(kappa, dtype=np.float64).ravel()
     S = np.asarray(S, dtype=np.float64).ravel()
-    idx = vertex_index(nx, ny)
-    N = (nx - 1) * (ny - 1)
+    idx = vertex_index(n)
+    N = int(np.prod([v - 1 for v in nn]))
     rows, cols, vals = [], [], []
     m = np.zeros(N)
-    for xy, tri, c in _triangles(nx, ny, hx, hy):
-        area, g = _local(xy)
-        ke = kappa[c] * area * (g @ g.T)
-        ids = [idx(v) for v in tri]
-        for a in range(3):
+    for xy, el, c in _elements(n, h):
+        vol, g = _local(xy)
+        ke = kappa[c] * vol * (g @ g.T)
+        ids = [idx(v) for v in el]
+        for a in range(d + 1):
             if ids[a] < 0:
                 continue
-            m[ids[a]] += S[c] * area / 3.0
-            for b in range(3):
+            m[ids[a]] += S[c] * vol / (d + 1)
+            for b in range(d + 1):
                 if ids[b] < 0:
                     continue
                 rows.append(ids[a])
@@ -93,30 +126,28 @@ def assemble_p1(n, h, kappa, S):
 
 
 def point_weights_p1(n, h, coords):
-    """Sparse [npoints, N]: the P1 basis functions at each point (barycentric coordinates in
-    the triangle that contains it; vertices on a wall carry zero head and are dropped)."""
-    nx, ny = int(n[0]), int(n[1])
-    hx, hy = float(h[0]), float(h[1])
-    idx = vertex_index(nx, ny)
+    """Sparse [npoints, N]: the P1 basis functions at each point (barycentric coordinates in an
+    element of its cell that contains it; vertices on a wall carry zero head and are dropped)."""
+    d, nn, hh = _dims(n, h)
+    idx = vertex_index(n)
     pts = np.asarray(coords, dtype=np.float64).reshape(-1, 3)
     rows, cols, vals = [], [], []
-    for p, (x, y, _) in enumerate(pts):
-        i = min(max(int(np.floor(x / hx)), 0), nx - 1)
-        j = min(max(int(np.floor(y / hy)), 0), ny - 1)
-        xi, eta = x / hx - i, y / hy - j
-        if xi + eta <= 1.0:
-            tri = ((i, j), (i + 1, j), (i, j + 1))
-            lam = (1.0 - xi - eta, xi, eta)
-        else:
-            tri = ((i + 1, j + 1), (i, j + 1), (i + 1, j))
-            lam = (xi + eta - 1.0, 1.0 - xi, 1.0 - eta)
-        for v, l in zip(tri, lam):
+    for p, x in enumerate(pts):
+        cell = tuple(min(max(int(np.floor(x[a] / hh[a])), 0), nn[a] - 1) for a in range(d))
+        for el in _cell_elements(cell, d):
+            xy = np.array([[v[a] * hh[a] for a in range(d)] for v in el], dtype=np.float64)
+            A = np.hstack([np.ones((d + 1, 1)), xy])
+            lam = np.linalg.solve(A.T, np.concatenate([[1.0], x[:d]]))
+            if lam.min() >= -1e-12:
+                break
+        for v, l in zip(el, lam):
             k = idx(v)
-            if k >= 0 and l != 0.0:
+            if k >= 0 and abs(l) > 1e-14:
                 rows.append(p)
                 cols.append(k)
                 vals.append(l)
-    return sp.csr_matrix((vals, (rows, cols)), shape=(pts.shape[0], (nx - 1) * (ny - 1)))
+    N = int(np.prod([v - 1 for v in nn]))
+    return sp.csr_matrix((vals, (rows, cols)), shape=(pts.shape[0], N))
 
 
 def heads_p1(n, h, kappa, S, sources, receivers, times, nz, q=1.0, workers=1):
