@@ -281,15 +281,18 @@ int lt_setup(const lt_grid* grid, const double* kappa, const double* S, const lt
              void* hip_stream, lt_handle** out);
 
 /* The same handle for P1 finite elements (Section 2.1's weak form with
- * piecewise-linear basis functions) on a 2D grid of cells: `cells` (ndim 2,
- * n[0], n[1] >= 3 cells, n[2] = 1, spacings h[0], h[1]), each cell split by
- * its anti-diagonal into two right triangles; kappa and S (device float64
- * [n[1]][n[0]], x fastest) are per cell and hold on both its triangles.
- * Every wall holds zero head; the unknowns are the interior vertices,
- * (n[0] - 1) x (n[1] - 1), x fastest.  The mass matrix is lumped (M_ii = sum
- * of S |e| / 3 over the triangles at vertex i).  A right triangle couples the
- * ends of its hypotenuse by zero, so K is a five-point stencil on the
- * vertices and every solver path applies unchanged.  Wells and receivers
+ * piecewise-linear basis functions) on a grid of cells: `cells` (ndim 2 or
+ * 3, at least 3 cells per axis, n[2] = 1 in 2D, positive spacings).  2D: each
+ * cell split by its anti-diagonal into two right triangles; 3D: each cell
+ * split into the six path tetrahedra of the Kuhn subdivision (v000,
+ * v000 + e_a, v000 + e_a + e_b, v111 for every order of the axes).  kappa
+ * and S (device float64, per cell, x fastest) hold on all of a cell's
+ * elements.  Every wall holds zero head; the unknowns are the interior
+ * vertices, (n[0] - 1) x (n[1] - 1) [x (n[2] - 1)], x fastest.  The mass
+ * matrix is lumped (M_ii = sum of S |e| / (d + 1) over the elements at
+ * vertex i).  These elements couple no vertex pair off the axes, so K is a
+ * five- or seven-point stencil on the vertices and every solver path
+ * applies unchanged.  Wells and receivers
  * take the P1 basis functions at their position (barycentric coordinates in
  * their triangle).  lt_solve, lt_solve_batch, lt_shift_invert, lt_vcycle and
  * lt_precond_solve accept the handle.  lt_adjoint returns LT_EUNSUPPORTED:

@@ -267,13 +267,16 @@ def lt_setup(ndim, n, h, kappa, S, bc=(0, 0, 0, 0, 0, 0), stream=None, sy=0.0) -
 
 
 def lt_setup_p1(n, h, kappa, S, stream=None) -> Handle:
-    """P1 elements on an n[0] x n[1] cell grid (kappa, S per cell, float64 CUDA tensors); the
-    handle's unknowns are the (n[0] - 1) x (n[1] - 1) interior vertices."""
-    g = lt_grid(2, (C.c_int * 3)(int(n[0]), int(n[1]), 1), (C.c_double * 3)(float(h[0]), float(h[1]), 1.0))
+    """P1 elements on a 2D (n[0] x n[1]) or 3D (n[0] x n[1] x n[2], n[2] > 1) cell grid (kappa, S
+    per cell, float64 CUDA tensors); the handle's unknowns are the interior vertices."""
+    nd = 3 if len(n) > 2 and int(n[2]) > 1 else 2
+    nn = [int(v) for v in n[:nd]] + [1] * (3 - nd)
+    hh = [float(v) for v in h[:nd]] + [1.0] * (3 - nd)
+    g = lt_grid(nd, (C.c_int * 3)(*nn), (C.c_double * 3)(*hh))
     out = _h()
     sp = _stream_ptr(stream)
     _check(_lib.lt_setup_p1(C.byref(g), _dev_f64(kappa, "kappa"), _dev_f64(S, "S"), sp, C.byref(out)))
-    gv = lt_grid(2, (C.c_int * 3)(int(n[0]) - 1, int(n[1]) - 1, 1), (C.c_double * 3)(float(h[0]), float(h[1]), 1.0))
+    gv = lt_grid(nd, (C.c_int * 3)(*[v - 1 if a < nd else 1 for a, v in enumerate(nn)]), (C.c_double * 3)(*hh))
     return Handle(out, gv, sp)
 
 

@@ -1104,12 +1104,15 @@ int lt_setup_p1(const lt_grid* cells, const double* kappa, const double* S, void
         return LT_EINVAL;
     }
     *out = nullptr;
-    if (cells->ndim != 2 || cells->n[2] != 1 || cells->n[0] < 3 || cells->n[1] < 3 || !(cells->h[0] > 0.0) ||
-        !(cells->h[1] > 0.0)) {
-        set_last_error("lt_setup_p1: a 2D grid of at least 3 x 3 cells with positive spacings");
+    bool ok = cells->ndim == 2 || cells->ndim == 3;
+    for (int a = 0; a < 3 && ok; ++a)
+        ok = a < cells->ndim ? cells->n[a] >= 3 && cells->h[a] > 0.0 : cells->n[a] == 1;
+    if (!ok) {
+        set_last_error("lt_setup_p1: a 2D or 3D grid of at least 3 cells per axis with positive spacings");
         return LT_EINVAL;
     }
-    const long long Nll = (long long)(cells->n[0] - 1) * (cells->n[1] - 1);
+    const long long Nll = (long long)(cells->n[0] - 1) * (cells->n[1] - 1) *
+                          (cells->ndim == 3 ? cells->n[2] - 1 : 1);
     if (Nll > kMaxCells) {
         set_last_error("lt_setup_p1: grid too large");
         return LT_EINVAL;
@@ -1120,8 +1123,7 @@ int lt_setup_p1(const lt_grid* cells, const double* kappa, const double* S, void
     h->cells = *cells;
     // the unknowns: the interior vertices, spaced like the cells
     h->grid = *cells;
-    h->grid.n[0] = cells->n[0] - 1;
-    h->grid.n[1] = cells->n[1] - 1;
+    for (int a = 0; a < cells->ndim; ++a) h->grid.n[a] = cells->n[a] - 1;
     std::memset(&h->bc, 0, sizeof(h->bc));  // zero head on every wall
     h->stream = static_cast<hipStream_t>(hip_stream);
     if (hipGetDevice(&h->device) != hipSuccess) {

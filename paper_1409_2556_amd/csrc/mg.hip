@@ -206,6 +206,49 @@ __global__ void k_p1_assemble(const double* __restrict__ kappa, const double* __
     out[4 * n + i] = hx * hy / 6.0 * (s11 + 2.0 * s01 + 2.0 * s10 + s00);
 }
 
+// The same in 3D: each cell of an ncx x ncy x ncz grid split into the six path tetrahedra of
+// the Kuhn subdivision (v000, v000 + e_a, v000 + e_a + e_b, v111 for every order of the axes).
+// Their barycentric gradients are orthogonal for every pair of vertices off an axis, so the
+// stiffness is a seven-point stencil on the interior vertices.  An x edge lies in six
+// tetrahedra of its four cells: two of the cell beyond it in y and z and two of the one
+// behind it in both, one of each of the other two; each adds kappa hy hz / (6 hx) (y and z
+// edges alike).  A vertex lies in all six tetrahedra of the two cells it is the lowest or the
+// highest corner of and in two of each of its other six cells, each adding S |e| / 4.
+__global__ void k_p1_assemble3d(const double* __restrict__ kappa, const double* __restrict__ S, int ncx, int ncy,
+                                int ncz, double hx, double hy, double hz, double* __restrict__ out,
+                                double* __restrict__ walls) {
+    const int nvx = ncx - 1, nvy = ncy - 1, nvz = ncz - 1, N = nvx * nvy * nvz;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int x = i % nvx, y = (i / nvx) % nvy, z = i / (nvx * nvy);
+    const int I = x + 1, J = y + 1, K = z + 1;
+    auto kc = [&](int a, int b, int c) { return kappa[a + ncx * (b + ncy * c)]; };
+    auto sc = [&](int a, int b, int c) { return S[a + ncx * (b + ncy * c)]; };
+    // the edge from (I, J, K) along +x lies in cells (I, J - 1 .. J, K - 1 .. K); along -x in
+    // cells (I - 1, ...); the cell that holds it as its (y, z) = (0, 0) or (1, 1) edge counts twice
+    const double ax = hy * hz / (6.0 * hx), ay = hx * hz / (6.0 * hy), az = hx * hy / (6.0 * hz);
+    const double xp = ax * (2.0 * kc(I, J - 1, K - 1) + 2.0 * kc(I, J, K) + kc(I, J - 1, K) + kc(I, J, K - 1));
+    const double xm = ax * (2.0 * kc(I - 1, J - 1, K - 1) + 2.0 * kc(I - 1, J, K) + kc(I - 1, J - 1, K) +
+                            kc(I - 1, J, K - 1));
+    const double yp = ay * (2.0 * kc(I - 1, J, K - 1) + 2.0 * kc(I, J, K) + kc(I, J, K - 1) + kc(I - 1, J, K));
+    const double ym = ay * (2.0 * kc(I - 1, J - 1, K - 1) + 2.0 * kc(I, J - 1, K) + kc(I, J - 1, K - 1) +
+                            kc(I - 1, J - 1, K));
+    const double zp = az * (2.0 * kc(I - 1, J - 1, K) + 2.0 * kc(I, J, K) + kc(I - 1, J, K) + kc(I, J - 1, K));
+    const double zm = az * (2.0 * kc(I - 1, J - 1, K - 1) + 2.0 * kc(I, J, K - 1) + kc(I - 1, J, K - 1) +
+                            kc(I, J - 1, K - 1));
+    const size_t n = N;
+    out[i] = x + 1 < nvx ? xp : 0.0;
+    out[n + i] = y + 1 < nvy ? yp : 0.0;
+    out[2 * n + i] = z + 1 < nvz ? zp : 0.0;
+    walls[i] = (x == 0 ? xm : 0.0) + (x + 1 == nvx ? xp : 0.0);
+    walls[n + i] = (y == 0 ? ym : 0.0) + (y + 1 == nvy ? yp : 0.0);
+    walls[2 * n + i] = (z == 0 ? zm : 0.0) + (z + 1 == nvz ? zp : 0.0);
+    const double six = sc(I, J, K) + sc(I - 1, J - 1, K - 1);
+    const double two = sc(I - 1, J, K) + sc(I, J - 1, K) + sc(I, J, K - 1) + sc(I - 1, J - 1, K) +
+                       sc(I - 1, J, K - 1) + sc(I, J - 1, K - 1);
+    out[4 * n + i] = hx * hy * hz / 24.0 * (6.0 * six + 2.0 * two);
+}
+
 __global__ void k_finish_diag(double* __restrict__ c, const double* __restrict__ w, int nx, int ny, int nz) {
     const int N = nx * ny * nz;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -673,7 +716,8 @@ int mg_build(lt_handle* h, const double* kappa, const double* S, const lt_grid* 
         f.coarsened_from_fine[a] = 0;
     }
     f.N = g.n[0] * g.n[1] * g.n[2];
-    if (p1_cells) f.delta[0] = f.delta[1] = 1.0;  // vertices: the walls lie one spacing out
+    if (p1_cells)  // vertices: the walls lie one spacing out
+        for (int a = 0; a < p1_cells->ndim; ++a) f.delta[a] = 1.0;
     lv.push_back(f);
     DevBuf walls_f, walls_c;
     LT_TRY(lv[0].c64.reserve(sizeof(double) * 5 * (size_t)f.N));
@@ -685,7 +729,11 @@ int mg_build(lt_handle* h, const double* kappa, const double* S, const lt_grid* 
         LT_TRY(h->mstor.reserve(sizeof(double) * (size_t)f.N));
         mstor = h->mstor.as<double>();
     }
-    if (p1_cells)
+    if (p1_cells && p1_cells->ndim == 3)
+        k_p1_assemble3d<<<nblk(f.N), kBlock, 0, st>>>(kappa, S, p1_cells->n[0], p1_cells->n[1], p1_cells->n[2],
+                                                      p1_cells->h[0], p1_cells->h[1], p1_cells->h[2],
+                                                      lv[0].c64.as<double>(), walls_f.as<double>());
+    else if (p1_cells)
         k_p1_assemble<<<nblk(f.N), kBlock, 0, st>>>(kappa, S, p1_cells->n[0], p1_cells->n[1], p1_cells->h[0],
                                                     p1_cells->h[1], lv[0].c64.as<double>(), walls_f.as<double>());
     else

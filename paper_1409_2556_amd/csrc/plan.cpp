@@ -173,6 +173,37 @@ int points_csr_p1(const lt_grid& c, const lt_points* pts, PointsCSR* out) {
     }
     const int nx = c.n[0], ny = c.n[1];
     const double hx = c.h[0], hy = c.h[1];
+    if (c.ndim == 3) {
+        // the Kuhn tetrahedron of the cell that holds the point: the path through the axes in
+        // decreasing order of the local coordinates, with barycentric coordinates
+        // (1 - c1, c1 - c2, c2 - c3, c3) for the sorted coordinates c1 >= c2 >= c3
+        for (int p = 0; p < pts->n; ++p) {
+            int cell[3], ax[3] = {0, 1, 2};
+            double loc[3];
+            for (int a = 0; a < 3; ++a) {
+                const double x = pts->xyz[3 * p + a];
+                if (!(x >= 0.0 && x <= c.n[a] * c.h[a])) {
+                    set_last_error("points: coordinate outside the domain");
+                    return LT_EINVAL;
+                }
+                cell[a] = std::min(std::max((int)std::floor(x / c.h[a]), 0), c.n[a] - 1);
+                loc[a] = x / c.h[a] - cell[a];
+            }
+            std::sort(ax, ax + 3, [&](int u, int v) { return loc[u] > loc[v]; });
+            int v[3] = {cell[0], cell[1], cell[2]};
+            const double lam[4] = {1.0 - loc[ax[0]], loc[ax[0]] - loc[ax[1]], loc[ax[1]] - loc[ax[2]], loc[ax[2]]};
+            for (int s = 0; s < 4; ++s) {
+                if (s > 0) ++v[ax[s - 1]];
+                bool wall = false;
+                for (int a = 0; a < 3; ++a) wall = wall || v[a] <= 0 || v[a] >= c.n[a];
+                if (wall || lam[s] == 0.0) continue;
+                out->cell.push_back((v[0] - 1) + (c.n[0] - 1) * ((v[1] - 1) + (c.n[1] - 1) * (v[2] - 1)));
+                out->wt.push_back(lam[s]);
+            }
+            out->off.push_back((int)out->cell.size());
+        }
+        return 0;
+    }
     for (int p = 0; p < pts->n; ++p) {
         const double x = pts->xyz[3 * p], y = pts->xyz[3 * p + 1];
         if (!(x >= 0.0 && x <= nx * hx && y >= 0.0 && y <= ny * hy)) {

@@ -10,6 +10,8 @@ element-by-element assembly.
 * Refusals: grids of fewer than 3 x 3 cells or not 2D, and lt_adjoint (its sensitivities
   are those of the finite-volume operator).
 * The V-cycle's contraction on the vertex grid (about 0.25 per cycle, as on cells).
+* 3D (the Kuhn subdivision): the operator element by element and heads in both precisions
+  against the oracle, and the V-cycle's contraction.
 """
 import numpy as np
 import pytest
@@ -104,3 +106,68 @@ def test_p1_vcycle_contracts_like_the_cell_centred_one(lt):
         print(f"[P1] tau {tau}: contraction per cycle {[round(v, 3) for v in rates]}", flush=True)
         assert max(rates[4:]) <= 0.4
     hd.close()
+
+
+def test_p1_3d_operator_and_heads_match_oracle(lt):
+    # the Kuhn subdivision of a 3D cell grid: the operator element by element, then heads
+    n, h = (9, 7, 6), (1 / 9, 1 / 7, 0.5 / 6)
+    rng = np.random.default_rng(8)
+    kappa = np.exp(rng.standard_normal(n[0] * n[1] * n[2]))
+    S = np.exp(rng.standard_normal(n[0] * n[1] * n[2])) * 1e-4
+    announce("P1 3D operator", n)
+    hd = _handle(lt, n, h, kappa, S)
+    K, m = assemble_p1(n, h, kappa, S)
+    assert hd.N == K.shape[0]
+    xc = rng.standard_normal((2, hd.N)) + 1j * rng.standard_normal((2, hd.N))
+    x = torch.tensor(np.stack([xc.real, xc.imag], axis=1), dtype=torch.float64, device="cuda").contiguous()
+    y = torch.empty_like(x)
+    for tau in (0.0, 3e5 + 2e6j):
+        lt.lt_apply_operator(hd, 0, tau, x, y, 2)
+        torch.cuda.synchronize()
+        got = y.cpu().numpy()
+        got = got[:, 0] + 1j * got[:, 1]
+        ref = np.stack([K @ v + tau * m * v for v in xc])
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    hd.close()
+    p = wl.make_problem("C3", n=(17, 15, 13), nsrc=2, nrec=4, ntimes=2)
+    announce("P1 3D heads", p.n)
+    ref = heads_p1(p.n, p.h, p.kappa, p.S, p.sources, p.receivers, p.times, p.nz_contour, q=p.q)
+    hd = _handle(lt, p.n, p.h, p.kappa, p.S)
+    for prec, tol, bar in ((lt.LT_PREC_FP64, 1e-10, 1e-6), (lt.LT_PREC_MIXED, 1e-8, 1e-5)):
+        phi, st = lt.lt_solve(hd, p.sources, p.q, p.times, p.nz_contour, p.receivers,
+                              lt.make_opts(tol=tol, precision=prec, n_tau=p.n_tau))
+        assert st["rc"] == 0
+        print(f"[P1 3D] precision {prec}: iters {st['iters_max']} vcycles {st['vcycles']} levels {st['levels']}",
+              flush=True)
+        check_heads(phi.cpu().numpy(), ref, bar, f"P1 3D 17x15x13 precision {prec}")
+    hd.close()
+
+
+def _rates(lt, hd, tau, cycles=10):
+    rng = np.random.default_rng(0)
+    r = torch.tensor(rng.standard_normal((1, 2, hd.N)), dtype=torch.float64, device="cuda").contiguous()
+    e, Ae = torch.empty_like(r), torch.empty_like(r)
+    rates = []
+    for _ in range(cycles):
+        lt.lt_vcycle(hd, tau, lt.LT_PREC_FP64, 2, 2, r, e, 1)
+        lt.lt_apply_operator(hd, 0, tau, e, Ae, 1)
+        r2 = (r - Ae).contiguous()
+        rates.append(float(torch.linalg.vector_norm(r2) / torch.linalg.vector_norm(r)))
+        r = r2
+    return rates
+
+
+def test_p1_3d_vcycle_contracts_like_the_cell_centred_one(lt):
+    # 32 x 32 x 16 vertex unknowns against 32 x 32 x 16 cells of the same field statistics
+    tau = 1e5 + 3e5j
+    p = wl.make_problem("C3", n=(33, 33, 17))
+    hp = _handle(lt, p.n, p.h, p.kappa, p.S)
+    q = wl.make_problem("C3", n=(32, 32, 16))
+    hf = lt.lt_setup(q.ndim, q.n, q.h, torch.tensor(q.kappa, device="cuda"), torch.tensor(q.S, device="cuda"))
+    announce("P1 3D V-cycle contraction")
+    rp, rf = _rates(lt, hp, tau), _rates(lt, hf, tau)
+    print(f"[P1 3D] contraction per cycle {[round(v, 3) for v in rp]}; cells {[round(v, 3) for v in rf]}",
+          flush=True)
+    assert max(rp[5:]) <= max(rf[5:]) + 0.1
+    hp.close()
+    hf.close()
