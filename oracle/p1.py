@@ -171,3 +171,53 @@ def heads_p1(n, h, kappa, S, sources, receivers, times, nz, q=1.0, workers=1):
             kk += 1
         phi[:, :, it] = 2.0 * acc.real.T
     return phi
+
+
+def jacobian_p1(n, h, kappa, S, sources, receivers, times, nz, q=1.0, workers=1):
+    """Sensitivities d phi[s, r, t] / d ln kappa_c and / d ln S_c of the P1 heads, for every cell c,
+    by the discrete adjoint (Section 5.2): with phi_sk = (K + z_k M)^{-1} qhat_k b_s and
+    psi_rk = (K + z_k M)^{-T} B_r^T,
+
+        d phi / d p_c = -2 Re sum_k w_k psi_rk^T (dK/dp_c + z_k dM/dp_c) phi_sk,
+
+    where dK/d ln kappa_c = kappa_c sum_{e in c} K_e(kappa = 1) and dM/d ln S_c =
+    S_c sum_{e in c} (|e| / (d + 1)) at the element's vertices (element by element, as in
+    assemble_p1).  Returns (JK, JS), each [ns, nr, nt, ncells]."""
+    d, nn, hh = _dims(n, h)
+    kappa = np.asarray(kappa, dtype=np.float64).ravel()
+    S = np.asarray(S, dtype=np.float64).ravel()
+    K, m = assemble_p1(n, h, kappa, S)
+    B = point_weights_p1(n, h, sources)
+    Br = point_weights_p1(n, h, receivers)
+    idx = vertex_index(n)
+    ns, nr, nt = B.shape[0], Br.shape[0], len(times)
+    ncells = int(np.prod(nn))
+    qs = np.broadcast_to(np.asarray(q, dtype=np.float64), (ns,))
+    nodes = [talbot_nodes(nz, t) for t in times]
+    shifts = np.concatenate([z for z, _ in nodes])
+    # forward fields (columns: sources) and adjoint fields (columns: receivers); K and M are
+    # symmetric, so the adjoint solve uses the same matrix
+    rhs = np.hstack([B.T.toarray(), Br.T.toarray()])
+    X = _map_shifts(K, m, rhs, shifts, "full", workers=workers)
+    elems = _elements(n, h)
+    JK = np.zeros((ns, nr, nt, ncells))
+    JS = np.zeros((ns, nr, nt, ncells))
+    kk = 0
+    for it, (z, w) in enumerate(nodes):
+        for k in range(len(z)):
+            Xk = X[kk]
+            kk += 1
+            phi = Xk[:, :ns] * (qs / z[k])[None, :]
+            psi = Xk[:, ns:]
+            for xy, el, c in elems:
+                vol, g = _local(xy)
+                ids = [idx(v) for v in el]
+                # element vectors, zero at wall vertices
+                pe = np.array([phi[i] if i >= 0 else np.zeros(ns) for i in ids])  # [d+1, ns]
+                qe = np.array([psi[i] if i >= 0 else np.zeros(nr) for i in ids])  # [d+1, nr]
+                ke = kappa[c] * vol * (g @ g.T)
+                dK = qe.T @ ke @ pe  # [nr, ns]
+                dM = S[c] * vol / (d + 1) * (qe.T @ pe)
+                JK[:, :, it, c] += -2.0 * (w[k] * dK).real.T
+                JS[:, :, it, c] += -2.0 * (w[k] * z[k] * dM).real.T
+    return JK, JS

@@ -210,3 +210,34 @@ def test_3d_eigenmode_decays_at_its_closed_form_rate():
                 v[idx((I, J, Kk))] = np.sin(np.pi * I * h[0]) * np.sin(np.pi * J * h[1]) * np.sin(np.pi * Kk * h[2])
     lam = kap / Sv * sum(4 / ha ** 2 * np.sin(np.pi * ha / 2) ** 2 for ha in h)
     assert np.linalg.norm(K @ v - lam * m * v) <= 1e-10 * np.linalg.norm(K @ v)
+
+
+@pytest.mark.parametrize("n", [(7, 6), (5, 4, 4)])
+def test_jacobian_matches_central_differences(n):
+    """The adjoint sensitivities of the P1 heads against central differences of heads_p1 in
+    ln kappa_c and ln S_c (a few cells, step 1e-4), relative to each map's largest entry."""
+    from oracle.p1 import jacobian_p1
+    d = len(n)
+    h = tuple(1.0 / v for v in n)
+    rng = np.random.default_rng(6)
+    nc = int(np.prod(n))
+    kap = np.exp(0.6 * rng.standard_normal(nc))
+    S = np.exp(0.3 * rng.standard_normal(nc)) * 1e-3
+    pad = (0.0,) if d == 2 else ()
+    src = np.array([[0.41, 0.47] + ([0.5] if d == 3 else [0.0])])
+    rec = np.array([[0.62, 0.33] + ([0.45] if d == 3 else [0.0]), [0.3, 0.7] + ([0.6] if d == 3 else [0.0])])
+    times = [2e-4, 1e-3]  # 0.2 and 1 diffusion time S L^2 / kappa: storage still matters
+    JK, JS = jacobian_p1(n, h, kap, S, src, rec, times, 24)
+    eps = 1e-4
+    for c in rng.choice(nc, 4, replace=False):
+        for which, J in (("k", JK), ("s", JS)):
+            up_k, dn_k, up_s, dn_s = kap.copy(), kap.copy(), S.copy(), S.copy()
+            if which == "k":
+                up_k[c] *= np.exp(eps)
+                dn_k[c] *= np.exp(-eps)
+            else:
+                up_s[c] *= np.exp(eps)
+                dn_s[c] *= np.exp(-eps)
+            fd = (heads_p1(n, h, up_k, up_s, src, rec, times, 24) - heads_p1(n, h, dn_k, dn_s, src, rec, times, 24)) / (2 * eps)
+            scale = np.abs(J).max()
+            assert np.abs(J[..., c] - fd).max() <= 1e-6 * scale, (which, c)
