@@ -295,8 +295,8 @@ int lt_setup(const lt_grid* grid, const double* kappa, const double* S, const lt
  * applies unchanged.  Wells and receivers
  * take the P1 basis functions at their position (barycentric coordinates in
  * their triangle).  lt_solve, lt_solve_batch, lt_shift_invert, lt_vcycle and
- * lt_precond_solve accept the handle.  lt_adjoint returns LT_EUNSUPPORTED:
- * its sensitivities are those of the finite-volume operator.  Errors:
+ * lt_precond_solve accept the handle, and so does lt_adjoint: its
+ * sensitivities are then to ln kappa and ln S of every cell of `cells`.  Errors:
  * LT_EINVAL for a NULL argument or a bad grid, LT_EHIP for no device. */
 int lt_setup_p1(const lt_grid* cells, const double* kappa, const double* S, void* hip_stream,
                 lt_handle** out);
@@ -328,7 +328,10 @@ int lt_solve(lt_handle* h, const lt_sources* src, const double* times, int ntime
  * LT_EUNSUPPORTED): forward fields for every well and adjoint fields for
  * every receiver (complex symmetric operator: no conjugation), contracted
  * cell by cell and summed over the contour.  dlnK, dlnS: device float64
- * [ns][nr][ntimes][N]; either may be NULL.  Every shift meets the stricter of
+ * [ns][nr][ntimes][N]; either may be NULL.  For a P1 handle (lt_setup_p1)
+ * the last index runs over the cells of its cell grid instead, x fastest:
+ * dK/dln kappa_c is kappa_c times the cell's element stiffness at kappa = 1,
+ * dM/dln S_c its lumped element masses.  Every shift meets the stricter of
  * the heads' weighting |w_k qhat_k| and the storage term's |w_k qhat_k z_k|
  * in the convergence test.  Near steady state the storage sensitivity is a
  * vanishing sum of contour terms of its early-time size, so its error is set

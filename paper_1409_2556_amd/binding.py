@@ -236,14 +236,20 @@ def make_opts(**kw) -> lt_opts:
 class Handle:
     """Owns an lt_handle; lt_destroy on close or garbage collection."""
 
-    def __init__(self, ptr, grid, stream):
+    def __init__(self, ptr, grid, stream, nparam=None):
         self.ptr = ptr
         self.grid = grid
         self.stream = stream
+        self._nparam = nparam
 
     @property
     def N(self):
         return self.grid.n[0] * self.grid.n[1] * self.grid.n[2]
+
+    @property
+    def nparam(self):
+        """Cells the sensitivities run over (the cells of a P1 handle's cell grid, else N)."""
+        return self.N if self._nparam is None else self._nparam
 
     def close(self):
         if self.ptr:
@@ -277,7 +283,7 @@ def lt_setup_p1(n, h, kappa, S, stream=None) -> Handle:
     sp = _stream_ptr(stream)
     _check(_lib.lt_setup_p1(C.byref(g), _dev_f64(kappa, "kappa"), _dev_f64(S, "S"), sp, C.byref(out)))
     gv = lt_grid(nd, (C.c_int * 3)(*[v - 1 if a < nd else 1 for a, v in enumerate(nn)]), (C.c_double * 3)(*hh))
-    return Handle(out, gv, sp)
+    return Handle(out, gv, sp, nparam=nn[0] * nn[1] * nn[2])
 
 
 def _stats(nrhs, nshift):
@@ -323,13 +329,13 @@ def lt_solve(handle: Handle, sources, q, times, nz, receivers, opts: lt_opts | N
 
 def lt_adjoint(handle: Handle, sources, q, receivers, times, nz, opts: lt_opts | None = None,
                dlnK=None, dlnS=None):
-    """Sensitivities [ns, nr, nt, N] to ln kappa and ln S (float64 CUDA tensors) and stats."""
+    """Sensitivities [ns, nr, nt, handle.nparam] to ln kappa and ln S (float64 CUDA tensors) and stats."""
     import torch
     src, keep = _sources(sources, q)
     rp, ra = _points(receivers)
     t = np.ascontiguousarray(np.asarray(times, dtype=np.float64).ravel())
     ns, nr, nt = keep[1].shape[0], ra.shape[0], t.size
-    shape = (ns, nr, nt, handle.N)
+    shape = (ns, nr, nt, handle.nparam)
     if dlnK is None:
         dlnK = torch.empty(shape, dtype=torch.float64, device="cuda")
     if dlnS is None:
@@ -396,7 +402,7 @@ def lt_adjoint_batch(problems):
         t = np.ascontiguousarray(np.asarray(pr["times"], dtype=np.float64).ravel())
         ns, nr, nt = sk[1].shape[0], ra.shape[0], t.size
         nz = int(pr["nz"])
-        shape = (ns, nr, nt, pr["handle"].N)
+        shape = (ns, nr, nt, pr["handle"].nparam)
         dK = pr.get("dlnK")
         dS = pr.get("dlnS")
         if dK is None:

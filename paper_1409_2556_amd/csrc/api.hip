@@ -1134,6 +1134,16 @@ int lt_setup_p1(const lt_grid* cells, const double* kappa, const double* S, void
     h->N = (int)Nll;
     int rc = noalloc_init_device(h->device);
     if (rc >= 0) rc = mg_build(h, kappa, S, &h->cells);
+    // the parameters the sensitivities are taken to: kappa then S, per cell of `cells`
+    const size_t nc = (size_t)cells->n[0] * cells->n[1] * (cells->ndim == 3 ? cells->n[2] : 1);
+    if (rc >= 0) rc = h->kappa.reserve(2 * sizeof(double) * nc);
+    if (rc >= 0 && (hipMemcpyAsync(h->kappa.p, kappa, sizeof(double) * nc, hipMemcpyDeviceToDevice, h->stream) !=
+                        hipSuccess ||
+                    hipMemcpyAsync(h->kappa.as<double>() + nc, S, sizeof(double) * nc, hipMemcpyDeviceToDevice,
+                                   h->stream) != hipSuccess)) {
+        set_last_error("lt_setup_p1: copying kappa and S failed");
+        rc = LT_EHIP;
+    }
     if (rc < 0) {
         delete h;
         return rc;
@@ -1311,10 +1321,6 @@ int lt_adjoint(lt_handle* h, const lt_sources* src, const lt_points* receivers, 
         set_last_error("lt_adjoint: bad argument");
         return LT_EINVAL;
     }
-    if (h->p1) {
-        set_last_error("lt_adjoint: the sensitivities are those of the finite-volume operator (not of P1 handles)");
-        return LT_EUNSUPPORTED;
-    }
     LT_TRY(check_sources(src, receivers->n, true, "lt_adjoint"));
     for (int t = 0; t < ntimes; ++t)
         if (!(times[t] > 0.0) || !std::isfinite(times[t])) {
@@ -1337,9 +1343,14 @@ int lt_adjoint(lt_handle* h, const lt_sources* src, const lt_points* receivers, 
     // right-hand sides: every well's q_s b_s, then every receiver's B_m^T (adjoint fields)
     const int ns = src->pts.n, nr = receivers->n, R = ns + nr;
     PointsCSR sc, rcsr, ac;
-    LT_TRY(points_csr(h->grid, &src->pts, &sc));
+    if (h->p1) {
+        LT_TRY(points_csr_p1(h->cells, &src->pts, &sc));
+        LT_TRY(points_csr_p1(h->cells, receivers, &rcsr));
+    } else {
+        LT_TRY(points_csr(h->grid, &src->pts, &sc));
+        LT_TRY(points_csr(h->grid, receivers, &rcsr));
+    }
     scale_by_rates(src, &sc);
-    LT_TRY(points_csr(h->grid, receivers, &rcsr));
     ac = sc;
     for (int i = 0; i < nr; ++i) {
         for (int e = rcsr.off[i]; e < rcsr.off[i + 1]; ++e) {
@@ -1370,6 +1381,13 @@ int lt_adjoint(lt_handle* h, const lt_sources* src, const lt_points* receivers, 
     if (!X) return rc;
     for (int t = 0; t < ntimes; ++t) {
         LT_TRY(launch_form_x(h->stream, h->N, R, nk, t * nk, k.Ks, k.U, k.ustride, k.Y, k.jmax, k.mcols, X));
+        if (h->p1) {
+            const size_t nc = (size_t)h->cells.n[0] * h->cells.n[1] * (h->cells.ndim == 3 ? h->cells.n[2] : 1);
+            const double* pk = h->kappa.as<double>();
+            LT_TRY(launch_sens_p1(h->stream, h->cells, pk, pk + nc, ns, nr, nk, t, ntimes, (size_t)h->N, X, k.zs,
+                                  k.wq, dlnK, dlnS));
+            continue;
+        }
         const LevelView<double> L0 = h->levels[0].v64();
         const double* mS = h->mstor.p ? h->mstor.as<double>() : L0.m;
         LT_TRY(launch_sens(h->stream, L0, h->kappa.as<double>(), mS, ns, nr, nk, t, ntimes, X, k.zs, k.wq, dlnK,

@@ -101,6 +101,10 @@ int launch_net_scale(hipStream_t st, LevelView<double> L, cdouble tau, int R, T*
                      const int* active);
 int launch_net_guard(hipStream_t st, int R, int nb, const double* part, const int* active, int* bad, int* counts);
 // mS: the storage part S V of the fine-level mass (L.m less any water-table term)
+// P1 handles: the same contraction per cell of `cells` (fields on its interior vertices)
+int launch_sens_p1(hipStream_t st, const lt_grid& cells, const double* kappa, const double* S, int ns, int nr,
+                   int nk, int t, int ntimes, size_t N, const double* X, const double* zs, const double* wq,
+                   double* JK, double* JS);
 int launch_sens(hipStream_t st, LevelView<double> L, const double* kappa, const double* mS, int ns, int nr, int nk,
                 int t, int ntimes, const double* X, const double* zs, const double* wq, double* JK, double* JS);
 

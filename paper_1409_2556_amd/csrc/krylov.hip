@@ -1339,6 +1339,134 @@ static void launch_sens_tile(hipStream_t st, LevelView<double> L, const double* 
     k_sens_tile<CB, TS, TM><<<grid, kB, shm, st>>>(L, kappa, mS, ns, nr, nk, t, ntimes, X, zs, wq, JK, JS);
 }
 
+// The same contraction for P1 elements (parameters per cell of the cell grid; fields on its
+// interior vertices, zero at wall vertices).  dK/dln kappa_c is kappa_c times the cell's
+// element stiffness at kappa = 1, which couples only the corners along the cell's edges:
+// in 2D its four edges, each with hy / (2 hx) (x edges) or hx / (2 hy) (y edges); in 3D its
+// twelve edges, an x edge with (tetrahedra holding it) x hy hz / (6 hx), two for the edges at
+// (y, z) = (0, 0) and (1, 1), one for the other two (y and z edges alike).  dM/dln S_c puts
+// S_c |e| / (d + 1) on each corner per element holding it: corner weights 1, 2, 2, 1 (v00,
+// v10, v01, v11) times hx hy / 6 in 2D; 6 at v000 and v111, 2 elsewhere, times
+// hx hy hz / 24 in 3D.  One thread per cell and per (source, kSensM receivers).
+__global__ __launch_bounds__(256) void k_sens_p1(int ncx, int ncy, int ncz, double hx, double hy, double hz,
+                                                 const double* __restrict__ kappa, const double* __restrict__ S,
+                                                 int ns, int nr, int nk, int t, int ntimes, size_t N,
+                                                 const double* __restrict__ X, const double* __restrict__ zs,
+                                                 const double* __restrict__ wq, double* __restrict__ JK,
+                                                 double* __restrict__ JS) {
+    const int nc = ncx * ncy * ncz;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const int s0 = blockIdx.y, m0 = blockIdx.z * kSensM;
+    const bool d3 = ncz > 1;
+    const int i = c % ncx, j = (c / ncx) % ncy, l = c / (ncx * ncy);
+    const int nvx = ncx - 1, nvy = ncy - 1;
+    // corners v(a, b, e), a + 2 b + 4 e; -1 on a wall
+    int vi[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int I = i + (q & 1), J = j + ((q >> 1) & 1), Kz = l + ((q >> 2) & 1);
+        const bool in = I > 0 && I < ncx && J > 0 && J < ncy && (!d3 || (Kz > 0 && Kz < ncz));
+        vi[q] = (q >= 4 && !d3) || !in ? -1 : (I - 1) + nvx * ((J - 1) + nvy * (d3 ? Kz - 1 : 0));
+    }
+    // edges (corner pair, weight at kappa = 1)
+    int ea[12], eb[12];
+    double ew[12];
+    int ne = 0;
+    if (!d3) {
+        const double ax = hy / (2.0 * hx), ay = hx / (2.0 * hy);
+        ea[0] = 0; eb[0] = 1; ew[0] = ax;  // (00, 10)
+        ea[1] = 2; eb[1] = 3; ew[1] = ax;  // (01, 11)
+        ea[2] = 0; eb[2] = 2; ew[2] = ay;  // (00, 01)
+        ea[3] = 1; eb[3] = 3; ew[3] = ay;  // (10, 11)
+        ne = 4;
+    } else {
+        const double ax = hy * hz / (6.0 * hx), ay = hx * hz / (6.0 * hy), az = hx * hy / (6.0 * hz);
+        // x edges at (b, e): (0, 0) and (1, 1) in two tetrahedra, (1, 0) and (0, 1) in one
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int b = q & 1, e = q >> 1;
+            ea[ne] = 2 * b + 4 * e; eb[ne] = 1 + 2 * b + 4 * e; ew[ne] = ax * (b == e ? 2.0 : 1.0); ++ne;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int a = q & 1, e = q >> 1;
+            ea[ne] = a + 4 * e; eb[ne] = a + 2 + 4 * e; ew[ne] = ay * (a == e ? 2.0 : 1.0); ++ne;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int a = q & 1, b = q >> 1;
+            ea[ne] = a + 2 * b; eb[ne] = a + 2 * b + 4; ew[ne] = az * (a == b ? 2.0 : 1.0); ++ne;
+        }
+    }
+    double mw[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        if (!d3) mw[q] = q >= 4 ? 0.0 : hx * hy / 6.0 * ((q == 0 || q == 3) ? 1.0 : 2.0);
+        else mw[q] = hx * hy * hz / 24.0 * ((q == 0 || q == 7) ? 6.0 : 2.0);
+    }
+    const double kc = kappa[c], sc = S[c];
+    double aK[kSensM], aS[kSensM];
+#pragma unroll
+    for (int q = 0; q < kSensM; ++q) aK[q] = aS[q] = 0.0;
+    const int sa = min(s0, ns - 1);
+    for (int kk = 0; kk < nk; ++kk) {
+        const int k = t * nk + kk;
+        const c64 w = {wq[2 * k], wq[2 * k + 1]};
+        const c64 zw = cm(w, {zs[2 * k], zs[2 * k + 1]});
+        const double* ph = X + ((size_t)sa * nk + kk) * 2 * N;
+        c64 pv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pv[q] = vi[q] >= 0 ? c64{ph[vi[q]], ph[vi[q] + N]} : c64{0.0, 0.0};
+#pragma unroll
+        for (int r = 0; r < kSensM; ++r) {
+            const int m = min(m0 + r, nr - 1);
+            const double* ps = X + ((size_t)(ns + m) * nk + kk) * 2 * N;
+            c64 qv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) qv[q] = vi[q] >= 0 ? c64{ps[vi[q]], ps[vi[q] + N]} : c64{0.0, 0.0};
+            c64 gK = {0.0, 0.0}, gS = {0.0, 0.0};
+            for (int e = 0; e < ne; ++e) {
+                const c64 dp = {pv[ea[e]].re - pv[eb[e]].re, pv[ea[e]].im - pv[eb[e]].im};
+                const c64 dq = {qv[ea[e]].re - qv[eb[e]].re, qv[ea[e]].im - qv[eb[e]].im};
+                const c64 p = cm(dp, dq);
+                gK.re += ew[e] * p.re;
+                gK.im += ew[e] * p.im;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const c64 p = cm(pv[q], qv[q]);
+                gS.re += mw[q] * p.re;
+                gS.im += mw[q] * p.im;
+            }
+            aK[r] += kc * (w.re * gK.re - w.im * gK.im);
+            aS[r] += sc * (zw.re * gS.re - zw.im * gS.im);
+        }
+    }
+    if (s0 >= ns) return;
+#pragma unroll
+    for (int r = 0; r < kSensM; ++r) {
+        const int m = m0 + r;
+        if (m >= nr) continue;
+        const size_t o = (((size_t)s0 * nr + m) * ntimes + t) * nc + c;
+        if (JK) JK[o] = -2.0 * aK[r];
+        if (JS) JS[o] = -2.0 * aS[r];
+    }
+}
+
+int launch_sens_p1(hipStream_t st, const lt_grid& cells, const double* kappa, const double* S, int ns, int nr,
+                   int nk, int t, int ntimes, size_t N, const double* X, const double* zs, const double* wq,
+                   double* JK, double* JS) {
+    const int ncz = cells.ndim == 3 ? cells.n[2] : 1;
+    const int nc = cells.n[0] * cells.n[1] * ncz;
+    dim3 grid((unsigned)((nc + kB - 1) / kB), (unsigned)ns, (unsigned)((nr + kSensM - 1) / kSensM));
+    k_sens_p1<<<grid, kB, 0, st>>>(cells.n[0], cells.n[1], ncz, cells.h[0], cells.h[1],
+                                   cells.ndim == 3 ? cells.h[2] : 1.0, kappa, S, ns, nr, nk, t, ntimes, N, X, zs,
+                                   wq, JK, JS);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
 int launch_sens(hipStream_t st, LevelView<double> L, const double* kappa, const double* mS, int ns, int nr, int nk,
                 int t, int ntimes, const double* X, const double* zs, const double* wq, double* JK, double* JS) {
     // 8 cells x (4 sources x 4 receivers per thread) when one block's 32 threads per cell cover
