@@ -93,12 +93,14 @@ def _parse():
     ap.add_argument("--no-tune", action="store_true", help="keep the default smoother tile shapes")
     ap.add_argument("--groups", type=int, default=2,
                     help="solve the sources as this many concurrent groups, one handle and stream each")
-    ap.add_argument("--workload", choices=["C5J", "C2", "C3", "C5", "EXACT", "THT"], default="C5J",
+    ap.add_argument("--workload", choices=["C5J", "C2", "C3", "C5", "EXACT", "THT", "BLOCK"], default="C5J",
                     help="C5J (default): the six Jacobian-assembly problems in one lt_adjoint_batch call; "
                          "C2: the 256x256 heads workload; C3: sensitivities (lt_adjoint) of the "
                          "64x64x32 workload; C5: the six grids' heads in one lt_solve_batch call; "
                          "EXACT: the single-well test with the exact shift-and-invert preconditioner; "
-                         "THT: the geostatistical inversion of the tomography case")
+                         "THT: the geostatistical inversion of the tomography case; BLOCK: block flexible "
+                         "GMRES (lt_shifted_solve_block) on the 256x256 workload's Jacobian right-hand sides "
+                         "and contour shifts, blocks of 1, 4 and 8")
     ap.add_argument("--tht-iters", type=int, default=6, help="THT: Gauss-Newton iterations per inversion")
     ap.add_argument("--tht-precond", choices=["exact", "gmg"], default="exact",
                     help="THT: preconditioner of the forward and adjoint solves (exact: the paper's "
@@ -258,6 +260,8 @@ def main():
         return main_exact(args)
     if args.workload == "THT":
         return main_tht(args)
+    if args.workload == "BLOCK":
+        return main_block(args)
     if args.workload == "C5":
         return main_batch(args)
     if args.workload == "C3":
@@ -799,6 +803,108 @@ def main_batch(args):
     print(json.dumps(out), flush=True)
     for h in hs:
         h.close()
+
+
+def main_block(args):
+    """Block flexible GMRES for shifted systems (lt_shifted_solve_block) on the 256x256 heads
+    workload: its 8 wells and 16 receivers (the Jacobian's 24 right-hand sides, unit point
+    sources) at the 20 contour shifts of its first two times, tol 1e-8 per shift, blocks of 1, 4 and 8
+    columns; the exact shift-and-invert preconditioner (the paper's two-shift schedule) and FP64
+    multigrid (the shift of largest real part, then the largest imaginary part alone)."""
+    import workloads as wl
+    from oracle.contour import talbot_nodes
+    p = wl.make_problem(WORKLOAD)
+    pts = np.vstack([p.sources, p.receivers])
+    R = pts.shape[0]
+    z = np.concatenate([talbot_nodes(p.nz_contour, t)[0] for t in p.times[:2]])
+    nk = z.size
+    zr, zi = z[np.argmax(z.real)], z[np.argmax(np.abs(z.imag))]
+    taus = {"exact": [z[np.argmin(z.real)]] * 3 + [zr] * 2, "gmg": [zr, complex(0.0, zi.imag)]}
+    tol = 1e-8
+    cpu, sample = None, None
+    if not args.no_cpu_baseline:
+        # the oracle's block algorithm (SuperLU preconditioner solves) on the first block of 4
+        # columns at the shifts of the first time
+        from oracle.block import block_flexible_shifted
+        from oracle.fv import assemble
+        K, m = assemble(p.n, p.h, p.kappa, p.S, bc=p.bc, sy=p.sy)
+        N = int(np.prod(p.n[:p.ndim]))
+        B = np.zeros((N, 4))
+        B[_cells_of(p, pts[:4]), np.arange(4)] = 1.0
+        zs = z[:p.nz_contour // 2]
+        t0 = time.perf_counter()
+        orc = block_flexible_shifted(K, m, B, taus["exact"], zs, tol=tol, maxit=60)
+        dt = time.perf_counter() - t0
+        sample = (zs, orc["x"])
+        cpu = {"value": 4 * zs.size / dt, "unit": "shifted solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"block FGMRES-Sh of the oracle, first block of 4 columns x the first time's "
+                         f"{zs.size} shifts, exact preconditioner ({orc['iters']} steps, {dt:.1f} s)"}
+        print(f"[bench] oracle sample: {cpu['value']:.2f} solves/s", file=sys.stderr, flush=True)
+    import torch
+    from paper_1409_2556_amd import binding as lt
+    torch.cuda.set_device(0)
+    h, _ = _handle(lt, p, False, R)
+    # right-hand sides: unit vectors at the cells holding the wells and receivers (plain indexing)
+    cells = _cells_of(p, pts)
+    b = torch.zeros((R, 2, h.N), dtype=torch.float64, device="cuda")
+    b[torch.arange(R, device="cuda"), 0, torch.tensor(cells, device="cuda")] = 1.0
+    x = torch.empty((nk, R, 2, h.N), dtype=torch.float64, device="cuda")
+    res = {}
+    for pre in ("exact", "gmg"):
+        for blk in (1, 4, 8):
+            o = lt.make_opts(tol=tol, maxit=60, precond=lt.LT_PRECOND_EXACT if pre == "exact" else lt.LT_PRECOND_GMG)
+            for _ in range(args.warmup):
+                lt.lt_shifted_solve_block(h, z, b, blk, taus[pre], o, x=x)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, st = lt.lt_shifted_solve_block(h, z, b, blk, taus[pre], o, x=x)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+            r = {"ms_per_step": dt * 1e3, "solves_per_s": R * nk / dt, "rc": st["rc"], "steps_max": st["iters_max"],
+                 "steps_mean": float(np.mean(st["iters_per_rhs"])),
+                 "precond_applications": int(np.sum(st["iters_per_rhs"])), "vcycles": st["vcycles"],
+                 "true_relres_max": st["true_relres_max"]}
+            if sample is not None and pre == "exact" and blk == 4:
+                got = x[:sample[0].size, :4].cpu().numpy()
+                got = got[:, :, 0] + 1j * got[:, :, 1]
+                r["rel_err_vs_oracle_sample"] = float(max(
+                    np.abs(got[k, c] - sample[1][k][:, c]).max() / np.abs(sample[1][k][:, c]).max()
+                    for k in range(sample[0].size) for c in range(4)))
+            res[f"{pre}_block{blk}"] = r
+            print(f"[bench] BLOCK {pre} p {blk}: {r}", file=sys.stderr, flush=True)
+    head = res["exact_block4"]
+    valid = head["rc"] == 0 and head["true_relres_max"] <= tol and \
+        head.get("rel_err_vs_oracle_sample", 0.0) <= 1e-6
+    out = {
+        "metric": "shifted solves/sec (RHS\u00d7shift, true residual 1e-8): block flexible GMRES",
+        "value": R * nk / (head["ms_per_step"] * 1e-3) if valid else 0.0,
+        "unit": "shifted solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"256x256 heads workload's {R} Jacobian right-hand sides (8 wells, 16 receivers; "
+                               f"unit vectors at their cells) x {nk} contour shifts (first 2 times, 20-node Talbot), "
+                               "lt_shifted_solve_block, exact preconditioner, blocks of 4", "tol": tol},
+        "variants": res,
+        "block4_vs_single_exact": res["exact_block1"]["ms_per_step"] / head["ms_per_step"],
+        "block4_vs_single_gmg": res["gmg_block1"]["ms_per_step"] / res["gmg_block4"]["ms_per_step"],
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
+def _cells_of(p, pts):
+    """Index of the cell holding each point (x fastest)."""
+    d = p.ndim
+    idx = np.zeros(len(pts), dtype=np.int64)
+    stride = 1
+    for a in range(d):
+        i = np.clip(np.floor(pts[:, a] / p.h[a]).astype(np.int64), 0, p.n[a] - 1)
+        idx += i * stride
+        stride *= p.n[a]
+    return idx
 
 
 def _exact_problem(wl, var=1.6, n=(128, 128), t=0.3, wells=None):

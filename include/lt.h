@@ -342,6 +342,35 @@ int lt_adjoint(lt_handle* h, const lt_sources* src, const lt_points* receivers,
                const double* times, int ntimes, const lt_contour* contour, const lt_opts* opts,
                double* dlnK, double* dlnS, lt_stats* stats);
 
+/* Block flexible GMRES for shifted systems (the block approach Section 6
+ * proposes for many right-hand sides; Algorithm 1 of Section 3 with block
+ * vectors): x_k = (K + z_k M)^{-1} b for every shift z_k and every column of
+ * b, the columns taken in blocks of `block` consecutive right-hand sides that
+ * share one basis.  Step j applies the preconditioner of tau_j =
+ * taus[(j - 1) % ntau] to every column of the block's newest basis block
+ * (LT_PRECOND_EXACT: the factorisation of K + tau_j M; LT_PRECOND_GMG: FP64
+ * V-cycles until each residual is below tol / 100), orthogonalises M U_j
+ * against the block basis by classical Gram-Schmidt, twice, and takes the QR
+ * of the remainder by modified Gram-Schmidt; each (block, shift) then updates
+ * its block least-squares problem by Givens rotations.  A shift of a block
+ * stops when every column meets weights[k] ||r|| <= tol ||b||.
+ *   shifts   host [nshift][2] (re, im), 1..1024; weights host [nshift] or NULL
+ *   taus     host [ntau][2]; GMG needs Re(tau) >= 0
+ *   b        device [nvec][2][N], every column nonzero; nvec <= 1000
+ *   block    1..16, dividing nvec
+ *   x        device [nshift][nvec][2][N] (written; must not overlap b)
+ * opts: tol, maxit, precond (GMG or EXACT), nu1, nu2, inner_max (GMG: at most
+ * 8 inner_max V-cycles per step); other fields are ignored.  The steps are
+ * capped at 32768 / (16 block^2) - 1 (127 for blocks of 4, 31 for 8), where one
+ * (block, shift)'s least-squares columns fill 32 KB of LDS.  Workspace: about
+ * (2 maxit + 2) nvec 16 N bytes on the handle.  The status follows the FP64
+ * true residuals (stats.true_relres, [nvec][nshift]): LT_WNOTCONV if a
+ * weighted one exceeds tol.  stats.iters_per_rhs gets each column's block's
+ * steps.  LT_EINVAL for bad sizes, a zero column or negative weights. */
+int lt_shifted_solve_block(lt_handle* h, int nshift, const double* shifts, const double* weights, int ntau,
+                           const double* taus, int nvec, int block, const double* b, const lt_opts* opts,
+                           double* x, lt_stats* stats);
+
 /* ---- batches of problems ----------------------------------------------
  * Every shift of every right-hand side of several problems, possibly on
  * grids of different shapes and dimensions, solved in one call: each item

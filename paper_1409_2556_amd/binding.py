@@ -129,6 +129,9 @@ _lib.lt_geostat_invert.argtypes = [C.c_void_p, C.c_void_p, _vp, C.c_void_p, _vp,
 _lib.lt_geostat_invert.restype = C.c_int
 _lib.lt_shift_invert.argtypes = [_h, C.c_double, C.c_double, C.c_int, _vp, _vp]
 _lib.lt_shift_invert.restype = C.c_int
+_lib.lt_shifted_solve_block.argtypes = [_h, C.c_int, _dp, _dp, C.c_int, _dp, C.c_int, C.c_int, _vp,
+                                        C.POINTER(lt_opts), _vp, C.POINTER(lt_stats)]
+_lib.lt_shifted_solve_block.restype = C.c_int
 _lib.lt_krylov_basis.argtypes = [_h, C.c_int, C.c_int, _dp, _dp, _dp, C.POINTER(C.c_int)]
 _lib.lt_krylov_basis.restype = C.c_int
 _lib.lt_level_shape.argtypes = [_h, C.c_int, C.POINTER(C.c_int)]
@@ -476,6 +479,29 @@ def lt_shift_invert(handle: Handle, tau, b, x, nvec):
                                        _dev_f64(x, "x")))
 
 
+def lt_shifted_solve_block(handle: Handle, shifts, b, block, taus, opts: lt_opts | None = None, weights=None,
+                           x=None):
+    """x[k] = (K + shifts[k] M)^{-1} b for every column of b ([nvec, 2, N] float64 CUDA tensor), by
+    block flexible GMRES over blocks of `block` columns (preconditioner shifts `taus`, cyclic).
+    Returns (x [nshift, nvec, 2, N], stats dict)."""
+    import torch
+    z = np.asarray(shifts, dtype=np.complex128).ravel()
+    t = np.asarray(taus, dtype=np.complex128).ravel()
+    zz = np.ascontiguousarray(np.stack([z.real, z.imag], axis=1))
+    tt = np.ascontiguousarray(np.stack([t.real, t.imag], axis=1))
+    nvec = int(b.shape[0])
+    if x is None:
+        x = torch.empty((z.size, nvec, 2, handle.N), dtype=torch.float64, device="cuda")
+    w = None if weights is None else np.ascontiguousarray(np.asarray(weights, dtype=np.float64).ravel())
+    o = opts if opts is not None else lt_opts_default()
+    st, it, tr = _stats(nvec, z.size)
+    rc = _check(_lib.lt_shifted_solve_block(handle.ptr, z.size, zz.ctypes.data_as(_dp),
+                                            None if w is None else w.ctypes.data_as(_dp), t.size,
+                                            tt.ctypes.data_as(_dp), nvec, int(block), _dev_f64(b, "b"),
+                                            C.byref(o), _dev_f64(x, "x"), C.byref(st)))
+    return x, _stats_dict(st, it, tr, rc, nvec, z.size)
+
+
 def lt_cov_apply(handle: Handle, var, length, v, out, nvec):
     """out = Q v for nvec float64 CUDA vectors [nvec][N] (exponential covariance, lengths per axis)."""
     ln = np.ascontiguousarray(np.broadcast_to(np.asarray(length, dtype=np.float64), (3,)).copy())
@@ -565,7 +591,7 @@ _ABI_NAMES = ["lt_opts_default", "lt_setup", "lt_setup_p1", "lt_solve", "lt_adjo
               "lt_unet_nparams", "lt_unet_get_params", "lt_unet_set_params", "lt_unet_apply",
               "lt_unet_train_step", "lt_unet_grad", "lt_unet_attach", "lt_unet_destroy", "lt_precond_solve",
               "lt_solve_batch", "lt_adjoint_batch", "lt_autotune", "lt_set_tiles", "lt_tile_shape",
-              "lt_krylov_basis"]
+              "lt_krylov_basis", "lt_shifted_solve_block"]
 
 
 # ---------------------------------------------------------------- learned preconditioner

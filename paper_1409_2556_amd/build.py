@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "liblt.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["mg.hip", "mg_fused.hip", "krylov.hip", "unet.hip", "api.hip", "plan.cpp", "batch.cpp",
-           "tune.hip", "noalloc.hip", "exact.hip", "geostat.hip"]
+           "tune.hip", "noalloc.hip", "exact.hip", "geostat.hip", "block.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     # packed FP32 instructions are kept out of the device code

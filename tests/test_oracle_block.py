@@ -26,7 +26,7 @@ def _problem(n=(20, 18), nsrc=4, seed=7):
     K, m = assemble(p.n, p.h, p.kappa, p.S)
     rng = np.random.default_rng(seed)
     pts = np.column_stack([rng.uniform(0.1, 0.9, nsrc), rng.uniform(0.1, 0.9, nsrc), np.zeros(nsrc)])
-    B = point_weights(p.n, p.h, pts).toarray().T
+    B = point_weights(p.n, p.h, pts).toarray().T  # wells as the oracle discretises them
     z, _ = talbot_nodes(16, 0.3 * T_D)
     return K, m, B, z
 
