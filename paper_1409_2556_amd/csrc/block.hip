@@ -51,61 +51,109 @@ __device__ inline double block_sum(double v, double* red) {
     return s;
 }
 
-__device__ inline const double* vec(const double* base, int R, int p, size_t N2, int b, int i) {
-    return base + ((size_t)(i / p) * R + (size_t)b * p + i % p) * N2;
-}
-
-// C[b][i - i0][c] = V_{b,i}^* W_{b, c0 + c} for i in [i0, i0 + gridDim.x), c < nc; the same
-// added to Hacc[b hb + i hld + hcol + c] (complex).
-__global__ __launch_bounds__(kBT) void k_bdots(const double* __restrict__ V, int R, int p, int N, int i0,
-                                                 const double* __restrict__ W, int c0, int nc,
-                                                 double* __restrict__ C, int ci, double* __restrict__ Hacc,
-                                                 size_t hb, int hld, int hcol) {
-    __shared__ double red[kBT / 64];
-    const int i = i0 + blockIdx.x, b = blockIdx.y;
+// Dots V_{b,i}^* W_{b, c0 + c} for i in [i0, i0 + ni), c < nc, in two passes.  First, each
+// workgroup takes 256 grid points of one block, holds the W columns there in registers and
+// streams every basis vector once: part[b][i][c][chunk].  Then k_bdots_fin sums the chunks into
+// C[b][i][c0 + c] and adds them to Hacc[b hb + (i0 + i) hld + hcol + c] (complex).
+__global__ __launch_bounds__(kBT) void k_bdots_part(const double* __restrict__ V, int R, int p, int N, int i0,
+                                                      int ni, const double* __restrict__ W, int c0, int nc,
+                                                      double* __restrict__ part, int nchunk) {
+    __shared__ double red[kBT / 64][2 * kBlockMax];
+    const int chunk = blockIdx.x, b = blockIdx.y;
+    const int n = chunk * kBT + threadIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool in = n < N;
     const size_t N2 = 2 * (size_t)N;
-    const double* q = vec(V, R, p, N2, b, i);
-    double ar[kBlockMax], ai[kBlockMax];
+    double wr[kBlockMax], wi[kBlockMax];
 #pragma unroll
-    for (int c = 0; c < kBlockMax; ++c) ar[c] = ai[c] = 0.0;
-    for (int n = threadIdx.x; n < N; n += kBT) {
-        const double qr = q[n], qi = q[n + N];
+    for (int c = 0; c < kBlockMax; ++c) {
+        wr[c] = wi[c] = 0.0;
+        if (c < nc && in) {
+            const double* w = W + ((size_t)b * p + c0 + c) * N2;
+            wr[c] = w[n];
+            wi[c] = w[n + N];
+        }
+    }
+    int sl = i0 / p, cc = i0 % p;  // slot and column of basis index i0 + i
+    for (int i = 0; i < ni; ++i) {
+        const double* q = V + ((size_t)sl * R + (size_t)b * p + cc) * N2;
+        if (++cc == p) {
+            cc = 0;
+            ++sl;
+        }
+        const double qr = in ? q[n] : 0.0, qi = in ? q[n + N] : 0.0;
 #pragma unroll
         for (int c = 0; c < kBlockMax; ++c) {
             if (c < nc) {
-                const double* w = W + ((size_t)b * p + c0 + c) * N2;
-                const double wr = w[n], wi = w[n + N];
-                ar[c] += qr * wr + qi * wi;
-                ai[c] += qr * wi - qi * wr;
+                const double sr = wave_sum(qr * wr[c] + qi * wi[c]);
+                const double si = wave_sum(qr * wi[c] - qi * wr[c]);
+                if (lane == 0) {
+                    red[wv][2 * c] = sr;
+                    red[wv][2 * c + 1] = si;
+                }
             }
         }
+        __syncthreads();
+        if (threadIdx.x < 2 * nc) {
+            double s = 0.0;
+            for (int q2 = 0; q2 < kBT / 64; ++q2) s += red[q2][threadIdx.x];
+            const int c = threadIdx.x >> 1, im = threadIdx.x & 1;
+            part[2 * ((((size_t)b * ni + i) * kBlockMax + c) * nchunk + chunk) + im] = s;
+        }
+        __syncthreads();
     }
-#pragma unroll
-    for (int c = 0; c < kBlockMax; ++c) {
-        if (c >= nc) break;  // nc is uniform over the workgroup
-        const double sr = block_sum(ar[c], red);
-        const double si = block_sum(ai[c], red);
+}
+
+__global__ __launch_bounds__(kBT) void k_bdots_fin(const double* __restrict__ part, int ni, int nchunk, int p,
+                                                     int i0, int c0, int nc, double* __restrict__ C, int ci,
+                                                     double* __restrict__ Hacc, size_t hb, int hld, int hcol) {
+    __shared__ double red[kBT / 64];
+    const int i = blockIdx.x, b = blockIdx.y;
+    for (int c = 0; c < nc; ++c) {
+        const double* pp = part + 2 * ((((size_t)b * ni + i) * kBlockMax + c) * nchunk);
+        double sr = 0.0, si = 0.0;
+        for (int k = threadIdx.x; k < nchunk; k += kBT) {
+            sr += pp[2 * k];
+            si += pp[2 * k + 1];
+        }
+        sr = block_sum(sr, red);
+        si = block_sum(si, red);
         if (threadIdx.x == 0) {
-            double* o = C + 2 * (((size_t)b * ci + blockIdx.x) * p + c0 + c);
+            double* o = C + 2 * (((size_t)b * ci + i) * p + c0 + c);
             o[0] = sr;
             o[1] = si;
-            double* hh = Hacc + 2 * ((size_t)b * hb + (size_t)i * hld + hcol + c);
+            double* hh = Hacc + 2 * ((size_t)b * hb + (size_t)(i0 + i) * hld + hcol + c);
             hh[0] += sr;
             hh[1] += si;
         }
     }
 }
 
-// W_{b, c0 + c} -= sum_{i < ni} V_{b, i0 + i} C[b][i][c0 + c]
+// W_{b, c0 + c} -= sum_{i < ni} V_{b, i0 + i} C[b][i][c0 + c]; the coefficients of the block
+// and the offsets of its basis vectors are staged in LDS (dynamic: ni nc complex, then ni
+// offsets), so the loop over the vectors unrolls and keeps several loads in flight
+// NCM: the column count rounded up to 1, 2 or 4 (the accumulators held in registers)
+template <int NCM>
 __global__ __launch_bounds__(kBT) void k_bupdate(const double* __restrict__ V, int R, int p, int N, int i0, int ni,
                                                    double* __restrict__ W, int c0, int nc,
                                                    const double* __restrict__ C, int ci) {
-    const int n = blockIdx.x * kBT + threadIdx.x, b = blockIdx.y;
-    if (n >= N) return;
+    extern __shared__ double cl[];  // [ni][nc][2], then [ni] offsets
+    size_t* off = reinterpret_cast<size_t*>(cl + 2 * (size_t)ni * nc);
+    const int b = blockIdx.y;
     const size_t N2 = 2 * (size_t)N;
-    double ar[kBlockMax], ai[kBlockMax];
+    for (int e = threadIdx.x; e < ni * nc; e += kBT) {
+        const int i = e / nc, c = e % nc;
+        const double* s = C + 2 * (((size_t)b * ci + i) * p + c0 + c);
+        cl[2 * e] = s[0];
+        cl[2 * e + 1] = s[1];
+    }
+    for (int i = threadIdx.x; i < ni; i += kBT)
+        off[i] = ((size_t)((i0 + i) / p) * R + (size_t)b * p + (i0 + i) % p) * N2;
+    __syncthreads();
+    const int n = blockIdx.x * kBT + threadIdx.x;
+    if (n >= N) return;
+    double ar[NCM], ai[NCM];
 #pragma unroll
-    for (int c = 0; c < kBlockMax; ++c) {
+    for (int c = 0; c < NCM; ++c) {
         ar[c] = ai[c] = 0.0;
         if (c < nc) {
             const double* w = W + ((size_t)b * p + c0 + c) * N2;
@@ -113,12 +161,13 @@ __global__ __launch_bounds__(kBT) void k_bupdate(const double* __restrict__ V, i
             ai[c] = w[n + N];
         }
     }
+#pragma unroll 4
     for (int i = 0; i < ni; ++i) {
-        const double* q = vec(V, R, p, N2, b, i0 + i);
+        const double* q = V + off[i];
         const double qr = q[n], qi = q[n + N];
-        const double* cc = C + 2 * (((size_t)b * ci + i) * p + c0);
+        const double* cc = cl + 2 * i * nc;
 #pragma unroll
-        for (int c = 0; c < kBlockMax; ++c) {
+        for (int c = 0; c < NCM; ++c) {
             if (c < nc) {
                 const double hr = cc[2 * c], hi = cc[2 * c + 1];
                 ar[c] -= qr * hr - qi * hi;
@@ -127,7 +176,7 @@ __global__ __launch_bounds__(kBT) void k_bupdate(const double* __restrict__ V, i
         }
     }
 #pragma unroll
-    for (int c = 0; c < kBlockMax; ++c) {
+    for (int c = 0; c < NCM; ++c) {
         if (c < nc) {
             double* w = W + ((size_t)b * p + c0 + c) * N2;
             w[n] = ar[c];
@@ -136,29 +185,23 @@ __global__ __launch_bounds__(kBT) void k_bupdate(const double* __restrict__ V, i
     }
 }
 
-// Column c of every block: nrm = ||W_{b,c}||, V_out = W / nrm (zero when the remainder has
-// lost rank: nrm <= 1e-14 of the block's largest column norm before orthogonalisation, scale),
-// Hd[b hb + hrow hld + hcol] = nrm.
-__global__ __launch_bounds__(kBT) void k_bnormalize(const double* __restrict__ W, int R, int p, int N, int c,
-                                                      double* __restrict__ Vout, const double* __restrict__ scale,
-                                                      double* __restrict__ Hd, size_t hb, int hld, int hrow, int hcol,
-                                                      int* __restrict__ brk) {
-    __shared__ double red[kBT / 64];
-    const int b = blockIdx.x;
-    const size_t N2 = 2 * (size_t)N;
-    const double* w = W + ((size_t)b * p + c) * N2;
-    double s = 0.0;
-    for (size_t n = threadIdx.x; n < N2; n += kBT) s += w[n] * w[n];
-    const double nrm = sqrt(block_sum(s, red));
+// Column c of every block scaled into Vout by 1 / nrm[b] (nrm from launch_norms), or zeroed
+// when the remainder has lost rank: nrm <= 1e-14 of the block's largest column norm before
+// orthogonalisation (scale); Hd[b hb + hrow hld + hcol] = nrm.
+__global__ __launch_bounds__(kBT) void k_bscale(const double* __restrict__ W, int R, int p, int N, int c,
+                                                  double* __restrict__ Vout, const double* __restrict__ nrm,
+                                                  const double* __restrict__ scale, double* __restrict__ Hd, size_t hb,
+                                                  int hld, int hrow, int hcol, int* __restrict__ brk) {
+    const int b = blockIdx.y;
+    const size_t N2 = 2 * (size_t)N, n = (size_t)blockIdx.x * kBT + threadIdx.x;
+    const double nr = nrm[b];
     double sc = 0.0;
     for (int q = 0; q < p; ++q) sc = fmax(sc, scale[b * p + q]);
-    const bool bad = !(nrm > 1e-14 * sc);
-    const double inv = bad ? 0.0 : 1.0 / nrm;
-    double* v = Vout + ((size_t)b * p + c) * N2;
-    for (size_t n = threadIdx.x; n < N2; n += kBT) v[n] = w[n] * inv;
-    if (threadIdx.x == 0) {
+    const bool bad = !(nr > 1e-14 * sc);
+    if (n < N2) Vout[((size_t)b * p + c) * N2 + n] = bad ? 0.0 : W[((size_t)b * p + c) * N2 + n] / nr;
+    if (n == 0) {
         double* hh = Hd + 2 * ((size_t)b * hb + (size_t)hrow * hld + hcol);
-        hh[0] = nrm;
+        hh[0] = nr;
         hh[1] = 0.0;
         if (bad) brk[b] = 1;
     }
@@ -376,8 +419,12 @@ __global__ __launch_bounds__(kBT) void k_bform_x(const double* __restrict__ U, i
     const int ni = jd[id] * p;
     const double* y = Y + 2 * (size_t)id * mx * p * p;
     double ar = 0.0, ai = 0.0;
-    for (int i = 0; i < ni; ++i) {
-        const double* u = vec(U, R, p, N2, b, i);
+    for (int i = 0, sl = 0, col = 0; i < ni; ++i) {
+        const double* u = U + ((size_t)sl * R + (size_t)b * p + col) * N2;
+        if (++col == p) {
+            col = 0;
+            ++sl;
+        }
         const double ur = u[n], ui = u[n + N];
         const double yr = y[2 * (i * p + c)], yi = y[2 * (i * p + c) + 1];
         ar += ur * yr - ui * yi;
@@ -407,6 +454,47 @@ __global__ __launch_bounds__(kBT) void k_bresid(const double* __restrict__ B, co
 }
 
 unsigned nblk(size_t n) { return (unsigned)((n + kBT - 1) / kBT); }
+
+// W_{b, c0 + c} -= sum_i V_{b, i0 + i} C[b][i][c0 + c] (dynamic LDS: coefficients, then offsets).
+// Wider blocks go in groups of four columns: eight or sixteen accumulators per thread spill.
+int launch_bupdate(hipStream_t st, const double* V, int R, int p, int nb, int N, int i0, int ni, double* W, int c0,
+                   int nc, const double* C, int ci) {
+    const dim3 g(nblk(N), nb);
+    for (int g0 = 0; g0 < nc; g0 += 4) {
+        const int m = std::min(4, nc - g0);
+        const size_t lds = (2 * sizeof(double) * m + sizeof(size_t)) * (size_t)ni;
+        if (m == 1)
+            k_bupdate<1><<<g, kBT, lds, st>>>(V, R, p, N, i0, ni, W, c0 + g0, m, C, ci);
+        else if (m == 2)
+            k_bupdate<2><<<g, kBT, lds, st>>>(V, R, p, N, i0, ni, W, c0 + g0, m, C, ci);
+        else
+            k_bupdate<4><<<g, kBT, lds, st>>>(V, R, p, N, i0, ni, W, c0 + g0, m, C, ci);
+        LT_HIP(hipGetLastError());
+    }
+    return 0;
+}
+
+// column c of every block normalised into the slot at Vout (norms by launch_norms over the
+// columns b p + c, then scaled over the whole grid)
+int launch_bnormalize(hipStream_t st, const double* W, int R, int p, int nb, int N, int c, double* Vout,
+                      const double* scale, double* Hd, size_t hb, int hld, int hrow, int hcol, int* brk,
+                      double* npart, double* nrm) {
+    const size_t N2 = 2 * (size_t)N;
+    LT_TRY(launch_norms(st, N, nb, (size_t)p * N2, W + (size_t)c * N2, npart, nrm, nullptr));
+    k_bscale<<<dim3(nblk(N2), nb), kBT, 0, st>>>(W, R, p, N, c, Vout, nrm, scale, Hd, hb, hld, hrow, hcol, brk);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_bdots(hipStream_t st, const double* V, int R, int p, int nb, int N, int i0, int ni, const double* W,
+                 int c0, int nc, double* part, double* C, int ci, double* Hacc, size_t hb, int hld, int hcol) {
+    const int nchunk = (int)nblk(N);
+    k_bdots_part<<<dim3(nchunk, nb), kBT, 0, st>>>(V, R, p, N, i0, ni, W, c0, nc, part, nchunk);
+    LT_HIP(hipGetLastError());
+    k_bdots_fin<<<dim3(ni, nb), kBT, 0, st>>>(part, ni, nchunk, p, i0, c0, nc, C, ci, Hacc, hb, hld, hcol);
+    LT_HIP(hipGetLastError());
+    return 0;
+}
 
 }  // namespace
 }  // namespace lt
@@ -465,21 +553,23 @@ int lt_shifted_solve_block(lt_handle* h, int nshift, const double* shifts, const
     double* rot = wsp<double>(h, "bk_rot", 3 * (size_t)nb * nk * hld * p, &rc);
     double* Y = wsp<double>(h, "bk_Y", 2 * (size_t)nb * nk * hld * p, &rc);
     double* res = wsp<double>(h, "bk_res", (size_t)nb * nk * p, &rc);
-    double* dev = wsp<double>(h, "bk_small", 2 * (size_t)nk + nk + 2 * (size_t)R + (size_t)nk * R, &rc);
+    double* dev = wsp<double>(h, "bk_small", 2 * (size_t)nk + nk + 2 * (size_t)R + (size_t)nk * R + nb, &rc);
     int* ints = wsp<int>(h, "bk_ints", 2 * (size_t)nb * nk + nb, &rc);
     const int nbr = reduce_blocks(N, R);
     double* part = wsp<double>(h, "bk_part", (size_t)R * nbr, &rc);
     double* rho = wsp<double>(h, "bk_rho", (size_t)R * N2, &rc);
     double* ecorr = wsp<double>(h, "bk_e", (size_t)R * N2, &rc);
     double* lo = h->cp3d ? wsp<double>(h, "bk_lo", (size_t)R * N2, &rc) : nullptr;
+    double* dpart = wsp<double>(h, "bk_dpart", 2 * (size_t)nb * grows * kBlockMax * nblk(N), &rc);
     if (!V || !U || !W || !C || !H || !R0 || !Rm || !g || !rot || !Y || !res || !dev || !ints || !part || !rho ||
-        !ecorr || (h->cp3d && !lo))
+        !ecorr || (h->cp3d && !lo) || !dpart)
         return rc ? rc : LT_ENOMEM;
     double* zs = dev;
     double* wk = zs + 2 * nk;
     double* bnorm = wk + nk;
     double* cnorm = bnorm + R;
     double* tres = cnorm + R;
+    double* bcn = tres + (size_t)nk * R;  // [nb] norms of one column per block
     int* jd = ints;
     int* conv = jd + nb * nk;
     int* brk = conv + nb * nk;
@@ -496,7 +586,6 @@ int lt_shifted_solve_block(lt_handle* h, int nshift, const double* shifts, const
     LT_HIP(hipMemsetAsync(ints, 0, (2 * (size_t)nb * nk + nb) * sizeof(int), st));
     LT_TRY(launch_norms(st, N, R, N2, b, part, bnorm, nullptr));
     LT_HIP(hipMemcpyAsync(W, b, (size_t)R * N2 * sizeof(double), hipMemcpyDeviceToDevice, st));
-    const dim3 gv(nblk(N), nb);
     {
         std::vector<double> hb0(R);
         LT_HIP(hipMemcpyAsync(hb0.data(), bnorm, R * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -511,13 +600,10 @@ int lt_shifted_solve_block(lt_handle* h, int nshift, const double* shifts, const
     // twice): R_0[b][row][c], rows and columns 0 .. p - 1
     for (int c = 0; c < p; ++c) {
         for (int pass = 0; c > 0 && pass < 2; ++pass) {
-            k_bdots<<<dim3(c, nb), kBT, 0, st>>>(V, R, p, N, 0, W, c, 1, C, grows, R0, (size_t)p * p, p, c);
-            LT_HIP(hipGetLastError());
-            k_bupdate<<<gv, kBT, 0, st>>>(V, R, p, N, 0, c, W, c, 1, C, grows);
-            LT_HIP(hipGetLastError());
+            LT_TRY(launch_bdots(st, V, R, p, nb, N, 0, c, W, c, 1, dpart, C, grows, R0, (size_t)p * p, p, c));
+            LT_TRY(launch_bupdate(st, V, R, p, nb, N, 0, c, W, c, 1, C, grows));
         }
-        k_bnormalize<<<nb, kBT, 0, st>>>(W, R, p, N, c, V, bnorm, R0, (size_t)p * p, p, c, c, brk);
-        LT_HIP(hipGetLastError());
+        LT_TRY(launch_bnormalize(st, W, R, p, nb, N, c, V, bnorm, R0, (size_t)p * p, p, c, c, brk, part, bcn));
     }
     k_binit_g<<<nb * nk, kBT, 0, st>>>(R0, p, nk, grows, g);
     LT_HIP(hipGetLastError());
@@ -568,23 +654,18 @@ int lt_shifted_solve_block(lt_handle* h, int nshift, const double* shifts, const
         LT_HIP(hipGetLastError());
         LT_TRY(launch_norms(st, N, R, N2, W, part, cnorm, nullptr));
         for (int pass = 0; pass < 2; ++pass) {
-            k_bdots<<<dim3(j * p, nb), kBT, 0, st>>>(V, R, p, N, 0, W, 0, p, C, grows, H, hb, hld, (j - 1) * p);
-            LT_HIP(hipGetLastError());
-            k_bupdate<<<gv, kBT, 0, st>>>(V, R, p, N, 0, j * p, W, 0, p, C, grows);
-            LT_HIP(hipGetLastError());
+            LT_TRY(launch_bdots(st, V, R, p, nb, N, 0, j * p, W, 0, p, dpart, C, grows, H, hb, hld, (j - 1) * p));
+            LT_TRY(launch_bupdate(st, V, R, p, nb, N, 0, j * p, W, 0, p, C, grows));
         }
         // V_{j+1} H_{j+1, j}: rows j p + c of columns (j - 1) p + c
         for (int c = 0; c < p; ++c) {
             for (int pass = 0; c > 0 && pass < 2; ++pass) {
-                k_bdots<<<dim3(c, nb), kBT, 0, st>>>(V, R, p, N, j * p, W, c, 1, C, grows, H, hb, hld,
-                                                     (j - 1) * p + c);
-                LT_HIP(hipGetLastError());
-                k_bupdate<<<gv, kBT, 0, st>>>(V, R, p, N, j * p, c, W, c, 1, C, grows);
-                LT_HIP(hipGetLastError());
+                LT_TRY(launch_bdots(st, V, R, p, nb, N, j * p, c, W, c, 1, dpart, C, grows, H, hb, hld,
+                                    (j - 1) * p + c));
+                LT_TRY(launch_bupdate(st, V, R, p, nb, N, j * p, c, W, c, 1, C, grows));
             }
-            k_bnormalize<<<nb, kBT, 0, st>>>(W, R, p, N, c, V + (size_t)j * R * N2, cnorm, H, hb, hld, j * p + c,
-                                             (j - 1) * p + c, brk);
-            LT_HIP(hipGetLastError());
+            LT_TRY(launch_bnormalize(st, W, R, p, nb, N, c, V + (size_t)j * R * N2, cnorm, H, hb, hld, j * p + c,
+                                     (j - 1) * p + c, brk, part, bcn));
         }
         k_bls<<<nb * nk, 64, ls_lds, st>>>(j, p, nk, mx, H, hb, hld, zs, tau.real(), tau.imag(), wk, bnorm, o.tol,
                                            brk, Rm, g, rot, jd, res, conv);
