@@ -51,26 +51,32 @@ __device__ inline double block_sum(double v, double* red) {
     return s;
 }
 
-// Dots V_{b,i}^* W_{b, c0 + c} for i in [i0, i0 + ni), c < nc, in two passes.  First, each
-// workgroup takes 256 grid points of one block, holds the W columns there in registers and
-// streams every basis vector once: part[b][i][c][chunk].  Then k_bdots_fin sums the chunks into
-// C[b][i][c0 + c] and adds them to Hacc[b hb + (i0 + i) hld + hcol + c] (complex).
+// Dots V_{b,i}^* W_{b, c0 + c} for i in [i0, i0 + ni), c < nc (at most four), in two passes.
+// First, each workgroup takes kDotE x 256 grid points of one block, holds the W columns there in
+// registers and streams every basis vector once: part[b][i][c][chunk] (one cross-wave reduction
+// per vector for kDotE x 256 points).  Then k_bdots_fin sums the chunks into C[b][i][c0 + c] and
+// adds them to Hacc[b hb + (i0 + i) hld + hcol + c] (complex).
+constexpr int kDotE = 4;
+template <int NCM>
 __global__ __launch_bounds__(kBT) void k_bdots_part(const double* __restrict__ V, int R, int p, int N, int i0,
                                                       int ni, const double* __restrict__ W, int c0, int nc,
                                                       double* __restrict__ part, int nchunk) {
-    __shared__ double red[kBT / 64][2 * kBlockMax];
-    const int chunk = blockIdx.x, b = blockIdx.y;
-    const int n = chunk * kBT + threadIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const bool in = n < N;
+    __shared__ double red[kBT / 64][2 * NCM];
+    const int chunk = blockIdx.x, b = blockIdx.y, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const size_t N2 = 2 * (size_t)N;
-    double wr[kBlockMax], wi[kBlockMax];
+    int nn[kDotE];
+    double wr[kDotE][NCM], wi[kDotE][NCM];
 #pragma unroll
-    for (int c = 0; c < kBlockMax; ++c) {
-        wr[c] = wi[c] = 0.0;
-        if (c < nc && in) {
-            const double* w = W + ((size_t)b * p + c0 + c) * N2;
-            wr[c] = w[n];
-            wi[c] = w[n + N];
+    for (int e = 0; e < kDotE; ++e) {
+        nn[e] = (chunk * kDotE + e) * kBT + threadIdx.x;
+#pragma unroll
+        for (int c = 0; c < NCM; ++c) {
+            wr[e][c] = wi[e][c] = 0.0;
+            if (c < nc && nn[e] < N) {
+                const double* w = W + ((size_t)b * p + c0 + c) * N2;
+                wr[e][c] = w[nn[e]];
+                wi[e][c] = w[nn[e] + N];
+            }
         }
     }
     int sl = i0 / p, cc = i0 % p;  // slot and column of basis index i0 + i
@@ -80,12 +86,23 @@ __global__ __launch_bounds__(kBT) void k_bdots_part(const double* __restrict__ V
             cc = 0;
             ++sl;
         }
-        const double qr = in ? q[n] : 0.0, qi = in ? q[n + N] : 0.0;
+        double qr[kDotE], qi[kDotE];
 #pragma unroll
-        for (int c = 0; c < kBlockMax; ++c) {
+        for (int e = 0; e < kDotE; ++e) {
+            qr[e] = nn[e] < N ? q[nn[e]] : 0.0;
+            qi[e] = nn[e] < N ? q[nn[e] + N] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < NCM; ++c) {
             if (c < nc) {
-                const double sr = wave_sum(qr * wr[c] + qi * wi[c]);
-                const double si = wave_sum(qr * wi[c] - qi * wr[c]);
+                double sr = 0.0, si = 0.0;
+#pragma unroll
+                for (int e = 0; e < kDotE; ++e) {
+                    sr += qr[e] * wr[e][c] + qi[e] * wi[e][c];
+                    si += qr[e] * wi[e][c] - qi[e] * wr[e][c];
+                }
+                sr = wave_sum(sr);
+                si = wave_sum(si);
                 if (lane == 0) {
                     red[wv][2 * c] = sr;
                     red[wv][2 * c + 1] = si;
@@ -488,11 +505,21 @@ int launch_bnormalize(hipStream_t st, const double* W, int R, int p, int nb, int
 
 int launch_bdots(hipStream_t st, const double* V, int R, int p, int nb, int N, int i0, int ni, const double* W,
                  int c0, int nc, double* part, double* C, int ci, double* Hacc, size_t hb, int hld, int hcol) {
-    const int nchunk = (int)nblk(N);
-    k_bdots_part<<<dim3(nchunk, nb), kBT, 0, st>>>(V, R, p, N, i0, ni, W, c0, nc, part, nchunk);
-    LT_HIP(hipGetLastError());
-    k_bdots_fin<<<dim3(ni, nb), kBT, 0, st>>>(part, ni, nchunk, p, i0, c0, nc, C, ci, Hacc, hb, hld, hcol);
-    LT_HIP(hipGetLastError());
+    const int nchunk = (int)((N + kDotE * kBT - 1) / (kDotE * kBT));
+    for (int g0 = 0; g0 < nc; g0 += 4) {  // four columns at a time: their W values stay in registers
+        const int m = std::min(4, nc - g0);
+        const dim3 g(nchunk, nb);
+        if (m == 1)
+            k_bdots_part<1><<<g, kBT, 0, st>>>(V, R, p, N, i0, ni, W, c0 + g0, m, part, nchunk);
+        else if (m == 2)
+            k_bdots_part<2><<<g, kBT, 0, st>>>(V, R, p, N, i0, ni, W, c0 + g0, m, part, nchunk);
+        else
+            k_bdots_part<4><<<g, kBT, 0, st>>>(V, R, p, N, i0, ni, W, c0 + g0, m, part, nchunk);
+        LT_HIP(hipGetLastError());
+        k_bdots_fin<<<dim3(ni, nb), kBT, 0, st>>>(part, ni, nchunk, p, i0, c0 + g0, m, C, ci, Hacc, hb, hld,
+                                                  hcol + g0);
+        LT_HIP(hipGetLastError());
+    }
     return 0;
 }
 
