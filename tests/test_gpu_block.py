@@ -10,6 +10,10 @@ oracle's block algorithm and direct solves.
 * Multigrid preconditioners (FP64 V-cycles to tol / 100), 2D and 3D: solutions against direct
   solves (1e-6) and FP64 true residuals within tol.
 * Weighted shifts; refusals (a block that does not divide nvec, a block of 17, a zero column).
+* The widest block (16 columns) at its step cap (7): LT_WNOTCONV, and the solutions are the
+  oracle's after the same 7 steps.
+* A P1 handle (lumped mass): multigrid block solves against direct solves of the oracle's
+  element assembly.
 """
 import numpy as np
 import pytest
@@ -149,4 +153,54 @@ def test_block_weights_and_refusals(lt):
     with pytest.raises(lt.LTError) as e:
         lt.lt_shifted_solve_block(hd, z, b0, 2, taus, o)
     assert e.value.code == lt.LT_EINVAL
+    hd.close()
+
+
+def test_widest_block_stops_at_its_step_cap(lt):
+    # 16 columns: one (block, shift)'s least-squares columns fill 32 KB of LDS after 7 steps; the
+    # call stops there, reports LT_WNOTCONV, and its solutions are the oracle's after 7 steps
+    p, K, m, B, hd, b = _setup(lt, nsrc=16)
+    z, _ = talbot_nodes(16, 0.3 * T_D)
+    taus = tau_schedule(z, 2)
+    announce("block 16 cap", p.n)
+    o = lt.make_opts(tol=1e-14, maxit=60, precond=lt.LT_PRECOND_EXACT)
+    x, st = lt.lt_shifted_solve_block(hd, z, b, 16, taus, o)
+    assert st["rc"] == lt.LT_WNOTCONV
+    assert st["iters_max"] == 7 and (st["iters_per_rhs"] == 7).all()
+    orc = block_flexible_shifted(K, m, B, taus, z, tol=1e-14, maxit=7)
+    got = _cplx(x)
+    err = max(np.abs(got[k, c] - orc["x"][k][:, c]).max() / np.abs(orc["x"][k][:, c]).max()
+              for k in range(z.size) for c in range(16))
+    print(f"[block 16] steps {st['iters_max']} true residual {st['true_relres_max']:.2e} err {err:.2e}", flush=True)
+    assert err <= 1e-8
+    hd.close()
+
+
+def test_block_on_p1_elements(lt):
+    # a P1 handle (lumped mass, interior vertices): FP64 multigrid, against direct solves of the
+    # oracle's element assembly
+    from oracle.p1 import assemble_p1
+    p = wl.make_problem("C2", n=(33, 25))
+    n, h = p.n[:2], p.h[:2]
+    K, m = assemble_p1(n, h, p.kappa, p.S)
+    hd = lt.lt_setup_p1(n, h, torch.tensor(p.kappa, dtype=torch.float64, device="cuda"),
+                        torch.tensor(p.S, dtype=torch.float64, device="cuda"))
+    assert hd.N == K.shape[0]
+    rng = np.random.default_rng(4)
+    B = np.zeros((hd.N, 4))
+    B[rng.choice(hd.N, size=4, replace=False), np.arange(4)] = 1.0
+    b = torch.zeros((4, 2, hd.N), dtype=torch.float64, device="cuda")
+    b[:, 0, :] = torch.tensor(B.T, dtype=torch.float64, device="cuda")
+    z, _ = talbot_nodes(16, p.times[3])
+    zr, zi = z[np.argmax(z.real)], z[np.argmax(np.abs(z.imag))]
+    announce("block p1", n)
+    x, st = lt.lt_shifted_solve_block(hd, z, b, 2, [zr, complex(0.0, zi.imag)],
+                                      lt.make_opts(tol=1e-8, maxit=100, precond=lt.LT_PRECOND_GMG))
+    got = _cplx(x)
+    ref = _direct(K, m, z, B)
+    err = max(np.abs(got[k, c] - ref[k][:, c]).max() / np.abs(ref[k][:, c]).max()
+              for k in range(z.size) for c in range(4))
+    print(f"[block p1] rc {st['rc']} steps {st['iters_max']} true residual {st['true_relres_max']:.2e} "
+          f"err {err:.2e}", flush=True)
+    assert st["rc"] == 0 and err <= 1e-6
     hd.close()
