@@ -102,3 +102,16 @@ def test_setup_rejects_grids_beyond_the_cell_limit_without_gpu(lib):
     # exactly 2^28 cells passes the size check and stops only at the missing device
     edge = lib.lt_grid(3, (C.c_int * 3)(1024, 1024, 256), (C.c_double * 3)(1.0, 1.0, 1.0))
     assert so.lt_setup(C.byref(edge), ptr, ptr, None, None, C.byref(out)) == lib.LT_EHIP
+
+
+def test_block_solver_checks_arguments_without_gpu(lib):
+    """lt_shifted_solve_block refuses a missing handle, shift list or right-hand side before any
+    device call."""
+    so = lib._lib
+    z = np.zeros(4)
+    zp = z.ctypes.data_as(lib._dp)
+    o = lib.lt_opts_default()
+    assert so.lt_shifted_solve_block(None, 2, zp, None, 1, zp, 4, 2, z.ctypes.data, C.byref(o),
+                                     z.ctypes.data, None) == lib.LT_EINVAL
+    assert "lt_shifted_solve_block" in lib.lt_last_error()
+    assert so.lt_shifted_solve_block(None, 0, None, None, 0, None, 0, 0, None, None, None, None) == lib.LT_EINVAL
