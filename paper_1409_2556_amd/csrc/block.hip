@@ -557,8 +557,22 @@ int lt_shifted_solve_block(lt_handle* h, int nshift, const double* shifts, const
             set_last_error("lt_shifted_solve_block: weights must be non-negative");
             return LT_EINVAL;
         }
+    for (int t = 0; t < ntau; ++t)
+        if (!std::isfinite(taus[2 * t]) || !std::isfinite(taus[2 * t + 1]) ||
+            (o.precond == LT_PRECOND_GMG && taus[2 * t] < 0.0)) {
+            set_last_error("lt_shifted_solve_block: taus must be finite, with Re(tau) >= 0 for multigrid");
+            return LT_EINVAL;
+        }
     const int p = block, R = nvec, nb = R / p, nk = nshift, N = h->N;
     const size_t N2 = 2 * (size_t)N;
+    {
+        const uintptr_t pb = (uintptr_t)b, px = (uintptr_t)x;
+        const size_t bb = (size_t)R * N2 * sizeof(double), xb = (size_t)nk * bb;
+        if (pb < px + xb && px < pb + bb) {
+            set_last_error("lt_shifted_solve_block: x overlaps b");
+            return LT_EINVAL;
+        }
+    }
     // the least squares keeps one (block, shift)'s rotated columns and right-hand side in LDS
     const int mx = std::min(o.maxit, kLdsBytes / (16 * p * p) - 1);
     if (mx < 1) {

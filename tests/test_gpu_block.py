@@ -9,7 +9,8 @@ oracle's block algorithm and direct solves.
   space), on the same problem.
 * Multigrid preconditioners (FP64 V-cycles to tol / 100), 2D and 3D: solutions against direct
   solves (1e-6) and FP64 true residuals within tol.
-* Weighted shifts; refusals (a block that does not divide nvec, a block of 17, a zero column).
+* Weighted shifts; refusals (a block that does not divide nvec, a block of 17, a zero column,
+  multigrid with a negative real preconditioner shift, x overlapping b).
 * The widest block (16 columns) at its step cap (7): LT_WNOTCONV, and the solutions are the
   oracle's after the same 7 steps.
 * A P1 handle (lumped mass): multigrid block solves against direct solves of the oracle's
@@ -148,6 +149,14 @@ def test_block_weights_and_refusals(lt):
         with pytest.raises(lt.LTError) as e:
             lt.lt_shifted_solve_block(hd, z, b, blk, taus, o)
         assert e.value.code == lt.LT_EINVAL
+    with pytest.raises(lt.LTError) as e:  # multigrid with a negative real preconditioner shift
+        lt.lt_shifted_solve_block(hd, z, b, 2, [complex(-1e4, 1e4)],
+                                  lt.make_opts(tol=1e-8, maxit=10, precond=lt.LT_PRECOND_GMG))
+    assert e.value.code == lt.LT_EINVAL
+    xo = torch.empty((z.size + 1, b.shape[0], 2, hd.N), dtype=torch.float64, device="cuda")
+    with pytest.raises(lt.LTError) as e:  # x overlapping b
+        lt.lt_shifted_solve_block(hd, z, xo[1], 2, taus, o, x=xo[1:])  # refused before b is read
+    assert e.value.code == lt.LT_EINVAL
     b0 = b.clone()
     b0[1].zero_()
     with pytest.raises(lt.LTError) as e:
