@@ -552,11 +552,16 @@ int lt_shifted_solve_block(lt_handle* h, int nshift, const double* shifts, const
         set_last_error("lt_shifted_solve_block: tol > 0, maxit >= 1, precond GMG or EXACT");
         return LT_EINVAL;
     }
-    for (int k = 0; k < nshift; ++k)
+    for (int k = 0; k < nshift; ++k) {
+        if (!std::isfinite(shifts[2 * k]) || !std::isfinite(shifts[2 * k + 1])) {
+            set_last_error("lt_shifted_solve_block: shifts must be finite");
+            return LT_EINVAL;
+        }
         if (weights && !(weights[k] >= 0.0)) {
             set_last_error("lt_shifted_solve_block: weights must be non-negative");
             return LT_EINVAL;
         }
+    }
     for (int t = 0; t < ntau; ++t)
         if (!std::isfinite(taus[2 * t]) || !std::isfinite(taus[2 * t + 1]) ||
             (o.precond == LT_PRECOND_GMG && taus[2 * t] < 0.0)) {
