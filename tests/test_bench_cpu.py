@@ -41,3 +41,22 @@ def test_water_table_and_tau_options():
     assert bench._boundary_config(q3)["sy"] == 1e-4
     same = bench._with_boundary(p2, argparse.Namespace(water_table=None, n_tau=None))
     assert same is p2 and bench._boundary_config(same) == {}
+
+
+def test_block_workload_cells_of_points():
+    """The block benchmark's right-hand sides are unit vectors at the cells holding the wells and
+    receivers: cell centres map to their own cell (x fastest), the far walls to the last cell."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import bench
+    import workloads as wl
+    p = wl.make_problem("C3", n=(8, 6, 4))
+    idx = [(1, 2, 3), (7, 0, 0), (0, 5, 2)]
+    pts = np.array([[(i + 0.5) * p.h[0], (j + 0.5) * p.h[1], (k + 0.5) * p.h[2]] for i, j, k in idx])
+    assert list(bench._cells_of(p, pts)) == [i + 8 * (j + 6 * k) for i, j, k in idx]
+    far = np.array([[8 * p.h[0], 6 * p.h[1], 4 * p.h[2]]])
+    assert list(bench._cells_of(p, far)) == [8 * 6 * 4 - 1]
+    p2 = wl.make_problem("C2")
+    w = np.vstack([p2.sources, p2.receivers])
+    c = bench._cells_of(p2, w)
+    assert len(set(c.tolist())) == len(w) and c.max() < 256 * 256
