@@ -56,7 +56,13 @@ def test_block_workload_cells_of_points():
     assert list(bench._cells_of(p, pts)) == [i + 8 * (j + 6 * k) for i, j, k in idx]
     far = np.array([[8 * p.h[0], 6 * p.h[1], 4 * p.h[2]]])
     assert list(bench._cells_of(p, far)) == [8 * 6 * 4 - 1]
+    # the 256x256 workload: its 8 wells sit at 8 of its 16 receivers, so the 24 columns hold 16
+    # distinct cells; in the benchmark's order (wells, then receivers) every block of 4 or 8 holds
+    # distinct cells, so no block starts rank deficient
     p2 = wl.make_problem("C2")
     w = np.vstack([p2.sources, p2.receivers])
     c = bench._cells_of(p2, w)
-    assert len(set(c.tolist())) == len(w) and c.max() < 256 * 256
+    assert len(set(c.tolist())) == 16 and c.max() < 256 * 256
+    for blk in (4, 8):
+        for b0 in range(0, len(c), blk):
+            assert len(set(c[b0:b0 + blk].tolist())) == blk
