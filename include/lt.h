@@ -366,7 +366,10 @@ int lt_adjoint(lt_handle* h, const lt_sources* src, const lt_points* receivers,
  * (2 maxit + 2) nvec 16 N bytes on the handle.  The status follows the FP64
  * true residuals (stats.true_relres, [nvec][nshift]): LT_WNOTCONV if a
  * weighted one exceeds tol.  stats.iters_per_rhs gets each column's block's
- * steps.  LT_EINVAL for bad sizes, non-finite shifts, a zero column, negative weights, a
+ * steps.  The columns of a block must be linearly independent: a block of
+ * lower rank (a column repeated, say) stops after its first step, and its
+ * true residuals report it.
+ * LT_EINVAL for bad sizes, non-finite shifts, a zero column, negative weights, a
  * negative Re(tau) with multigrid, or x overlapping b. */
 int lt_shifted_solve_block(lt_handle* h, int nshift, const double* shifts, const double* weights, int ntau,
                            const double* taus, int nvec, int block, const double* b, const lt_opts* opts,

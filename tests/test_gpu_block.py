@@ -15,6 +15,8 @@ oracle's block algorithm and direct solves.
   oracle's after the same 7 steps.
 * A P1 handle (lumped mass): multigrid block solves against direct solves of the oracle's
   element assembly.
+* A block with a repeated column stops after one step (LT_WNOTCONV, finite output); the other
+  block converges as before.
 """
 import numpy as np
 import pytest
@@ -212,4 +214,28 @@ def test_block_on_p1_elements(lt):
     print(f"[block p1] rc {st['rc']} steps {st['iters_max']} true residual {st['true_relres_max']:.2e} "
           f"err {err:.2e}", flush=True)
     assert st["rc"] == 0 and err <= 1e-6
+    hd.close()
+
+
+def test_block_with_a_repeated_column_stops_alone(lt):
+    # a block whose columns are linearly dependent (one column twice) loses rank at its first QR:
+    # that block stops after one step (LT_WNOTCONV from its true residuals, finite output); the
+    # other block is unaffected
+    p, K, m, B, hd, b = _setup(lt, nsrc=8)
+    b[5] = b[4]
+    B[:, 5] = B[:, 4]
+    z, _ = talbot_nodes(16, 0.3 * T_D)
+    taus = tau_schedule(z, 2)
+    announce("block repeated column", p.n)
+    x, st = lt.lt_shifted_solve_block(hd, z, b, 4, taus, lt.make_opts(tol=1e-10, maxit=60,
+                                                                      precond=lt.LT_PRECOND_EXACT))
+    got = _cplx(x)
+    print(f"[block repeated] rc {st['rc']} steps {list(st['iters_per_rhs'])}", flush=True)
+    assert st["rc"] == lt.LT_WNOTCONV
+    assert np.isfinite(got).all()
+    assert (st["iters_per_rhs"][4:] == 1).all() and (st["iters_per_rhs"][:4] > 1).all()
+    ref = _direct(K, m, z, B)
+    for k in range(z.size):
+        for c in range(4):
+            assert np.abs(got[k, c] - ref[k][:, c]).max() <= 1e-8 * np.abs(ref[k][:, c]).max()
     hd.close()
