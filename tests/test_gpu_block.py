@@ -4,7 +4,7 @@ oracle's block algorithm and direct solves.
 * Exact shift-and-invert preconditioners: the solutions of every shift and column against the
   oracle's block FGMRES-Sh (same blocks, same preconditioner shifts) element by element (1e-8 of
   each column's largest entry) and against direct solves; the steps agree with the oracle's
-  within one (the tolerance test sits on rounding); blocks of 1, 4 and 8 columns.
+  within one (the tolerance test sits on rounding); blocks of 1, 4 and 8 columns; and a 3D grid.
 * Blocks need fewer steps than single right-hand sides (the block space contains each single
   space), on the same problem.
 * Multigrid preconditioners (FP64 V-cycles to tol / 100), 2D and 3D: solutions against direct
@@ -238,4 +238,22 @@ def test_block_with_a_repeated_column_stops_alone(lt):
     for k in range(z.size):
         for c in range(4):
             assert np.abs(got[k, c] - ref[k][:, c]).max() <= 1e-8 * np.abs(ref[k][:, c]).max()
+    hd.close()
+
+
+def test_block_exact_3d_matches_oracle(lt):
+    # a 3D grid (the exact preconditioner's block-tridiagonal factorisation over planes)
+    p, K, m, B, hd, b = _setup(lt, "C3", n=(12, 10, 8), nsrc=4)
+    z, _ = talbot_nodes(16, p.times[0])
+    taus = tau_schedule(z, 2)
+    announce("block exact 3d", p.n)
+    x, st = lt.lt_shifted_solve_block(hd, z, b, 4, taus, lt.make_opts(tol=1e-10, maxit=60,
+                                                                      precond=lt.LT_PRECOND_EXACT))
+    assert st["rc"] == 0
+    orc = block_flexible_shifted(K, m, B, taus, z, tol=1e-10, maxit=60)
+    got = _cplx(x)
+    err = max(np.abs(got[k, c] - orc["x"][k][:, c]).max() / np.abs(orc["x"][k][:, c]).max()
+              for k in range(z.size) for c in range(4))
+    print(f"[block exact 3d] steps {st['iters_max']} oracle {orc['iters']} err {err:.2e}", flush=True)
+    assert abs(st["iters_max"] - orc["iters"]) <= 1 and err <= 1e-8
     hd.close()
