@@ -362,8 +362,9 @@ int lt_adjoint(lt_handle* h, const lt_sources* src, const lt_points* receivers,
  * opts: tol, maxit, precond (GMG or EXACT), nu1, nu2, inner_max (GMG: at most
  * 8 inner_max V-cycles per step); other fields are ignored.  The steps are
  * capped at 32768 / (16 block^2) - 1 (127 for blocks of 4, 31 for 8), where one
- * (block, shift)'s least-squares columns fill 32 KB of LDS.  Workspace: about
- * (2 maxit + 2) nvec 16 N bytes on the handle.  The status follows the FP64
+ * (block, shift)'s least-squares columns fill 32 KB of LDS.  Workspace on the
+ * handle, with m the capped steps: about (2 m + 5) nvec 16 N bytes of vectors,
+ * plus 16 (m block)^2 bytes of rotated least-squares columns per (block, shift).  The status follows the FP64
  * true residuals (stats.true_relres, [nvec][nshift]): LT_WNOTCONV if a
  * weighted one exceeds tol.  stats.iters_per_rhs gets each column's block's
  * steps.  The columns of a block must be linearly independent: a block of
