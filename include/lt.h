@@ -364,14 +364,14 @@ int lt_adjoint(lt_handle* h, const lt_sources* src, const lt_points* receivers,
  * capped at 32768 / (16 block^2) - 1 (127 for blocks of 4, 31 for 8), where one
  * (block, shift)'s least-squares columns fill 32 KB of LDS.  Workspace on the
  * handle, with m the capped steps: about (2 m + 5) nvec 16 N bytes of vectors,
- * plus 16 (m block)^2 bytes of rotated least-squares columns per (block, shift).  The status follows the FP64
- * true residuals (stats.true_relres, [nvec][nshift]): LT_WNOTCONV if a
- * weighted one exceeds tol.  stats.iters_per_rhs gets each column's block's
- * steps.  The columns of a block must be linearly independent: a block of
- * lower rank (a column repeated, say) stops after its first step, and its
- * true residuals report it.
- * LT_EINVAL for bad sizes, non-finite shifts, a zero column, negative weights, a
- * negative Re(tau) with multigrid, or x overlapping b. */
+ * plus 16 (m block)^2 bytes of rotated least-squares columns per (block, shift).
+ * The status follows the FP64 true residuals (stats.true_relres,
+ * [nvec][nshift]): LT_WNOTCONV if a weighted one exceeds tol.
+ * stats.iters_per_rhs gets each column's block's steps.  The columns of a
+ * block must be linearly independent: a block of lower rank (a column
+ * repeated, say) stops after its first step, and its true residuals report
+ * it.  LT_EINVAL for bad sizes, non-finite shifts, a zero column, negative
+ * weights, a negative Re(tau) with multigrid, or x overlapping b. */
 int lt_shifted_solve_block(lt_handle* h, int nshift, const double* shifts, const double* weights, int ntau,
                            const double* taus, int nvec, int block, const double* b, const lt_opts* opts,
                            double* x, lt_stats* stats);
