@@ -425,49 +425,56 @@ __global__ __launch_bounds__(kBT) void k_bsolve(int p, int nk, int mx, const dou
     }
 }
 
-// x[k][r] = sum_{i < jd p} U_{b, i} Y[b, k][i][c] (r = b p + c)
+// x[k][r] = sum_{i < jd p} U_{b, i} Y[b, k][i][c] (r = b p + c), kFormK shifts per thread, so
+// that each basis vector is read once for every kFormK shifts (each shift has its own steps)
+constexpr int kFormK = 8;
 __global__ __launch_bounds__(kBT) void k_bform_x(const double* __restrict__ U, int R, int p, int N, int nk, int mx,
                                                    const int* __restrict__ jd, const double* __restrict__ Y,
                                                    double* __restrict__ x) {
-    const int n = blockIdx.x * kBT + threadIdx.x, r = blockIdx.y, k = blockIdx.z;
+    const int n = blockIdx.x * kBT + threadIdx.x, r = blockIdx.y, k0 = blockIdx.z * kFormK;
     if (n >= N) return;
-    const int b = r / p, c = r % p, id = b * nk + k;
+    const int b = r / p, c = r % p;
     const size_t N2 = 2 * (size_t)N;
-    const int ni = jd[id] * p;
-    const double* y = Y + 2 * (size_t)id * mx * p * p;
-    double ar = 0.0, ai = 0.0;
-    for (int i = 0, sl = 0, col = 0; i < ni; ++i) {
+    int ni[kFormK];
+    int nmax = 0;
+#pragma unroll
+    for (int q = 0; q < kFormK; ++q) {
+        ni[q] = k0 + q < nk ? jd[b * nk + k0 + q] * p : 0;
+        nmax = max(nmax, ni[q]);
+    }
+    double ar[kFormK], ai[kFormK];
+#pragma unroll
+    for (int q = 0; q < kFormK; ++q) ar[q] = ai[q] = 0.0;
+    for (int i = 0, sl = 0, col = 0; i < nmax; ++i) {
         const double* u = U + ((size_t)sl * R + (size_t)b * p + col) * N2;
         if (++col == p) {
             col = 0;
             ++sl;
         }
         const double ur = u[n], ui = u[n + N];
-        const double yr = y[2 * (i * p + c)], yi = y[2 * (i * p + c) + 1];
-        ar += ur * yr - ui * yi;
-        ai += ur * yi + ui * yr;
+#pragma unroll
+        for (int q = 0; q < kFormK; ++q) {
+            if (i < ni[q]) {
+                const double* y = Y + 2 * ((size_t)(b * nk + k0 + q) * mx * p * p + (size_t)i * p + c);
+                ar[q] += ur * y[0] - ui * y[1];
+                ai[q] += ur * y[1] + ui * y[0];
+            }
+        }
     }
-    double* o = x + ((size_t)k * R + r) * N2;
-    o[n] = ar;
-    o[n + N] = ai;
+#pragma unroll
+    for (int q = 0; q < kFormK; ++q) {
+        if (k0 + q < nk) {
+            double* o = x + ((size_t)(k0 + q) * R + r) * N2;
+            o[n] = ar[q];
+            o[n + N] = ai[q];
+        }
+    }
 }
 
-// out[k R + r] = ||b_r - y_r|| / ||b_r|| (y = (K + z_k M) x_{k, r})
-__global__ __launch_bounds__(kBT) void k_bresid(const double* __restrict__ B, const double* __restrict__ Yv, int N,
-                                                  const double* __restrict__ bnorm, int R, int k,
-                                                  double* __restrict__ out) {
-    __shared__ double red[kBT / 64];
-    const int r = blockIdx.x;
-    const size_t N2 = 2 * (size_t)N;
-    const double* bb = B + r * N2;
-    const double* yy = Yv + r * N2;
-    double s = 0.0;
-    for (size_t n = threadIdx.x; n < N2; n += kBT) {
-        const double d = bb[n] - yy[n];
-        s += d * d;
-    }
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) out[(size_t)k * R + r] = sqrt(s) / bnorm[r];
+// Y = B - Y over R vectors (the residual of the operator's output Y)
+__global__ __launch_bounds__(kBT) void k_bdiff(const double* __restrict__ B, double* __restrict__ Yv, size_t n2) {
+    const size_t e = (size_t)blockIdx.x * kBT + threadIdx.x;
+    if (e < n2) Yv[e] = B[e] - Yv[e];
 }
 
 unsigned nblk(size_t n) { return (unsigned)((n + kBT - 1) / kBT); }
@@ -723,20 +730,25 @@ int lt_shifted_solve_block(lt_handle* h, int nshift, const double* shifts, const
     }
     k_bsolve<<<nb * nk, kBT, 2 * sizeof(double) * (size_t)mx * p * p, st>>>(p, nk, mx, Rm, g, jd, Y);
     LT_HIP(hipGetLastError());
-    k_bform_x<<<dim3(nblk(N), R, nk), kBT, 0, st>>>(U, R, p, N, nk, mx, jd, Y, x);
+    k_bform_x<<<dim3(nblk(N), R, (nk + kFormK - 1) / kFormK), kBT, 0, st>>>(U, R, p, N, nk, mx, jd, Y, x);
     LT_HIP(hipGetLastError());
-    // FP64 true residuals ||b - (K + z_k M) x_k|| / ||b|| (W holds the operator's output)
+    // FP64 true residuals ||b - (K + z_k M) x_k|| (W holds the operator's output, then the
+    // residual), divided by ||b|| below
     for (int k = 0; k < nk; ++k) {
         LT_TRY(apply_operator<double>(h, 0, cdouble(hz[2 * k], hz[2 * k + 1]), x + (size_t)k * R * N2, W, R,
                                       nullptr));
-        k_bresid<<<R, kBT, 0, st>>>(b, W, N, bnorm, R, k, tres);
+        k_bdiff<<<nblk((size_t)R * N2), kBT, 0, st>>>(b, W, (size_t)R * N2);
         LT_HIP(hipGetLastError());
+        LT_TRY(launch_norms(st, N, R, N2, W, part, tres + (size_t)k * R, nullptr));
     }
-    std::vector<double> htr((size_t)nk * R);
+    std::vector<double> htr((size_t)nk * R), hbn(R);
     std::vector<int> hjd((size_t)nb * nk);
     LT_HIP(hipMemcpyAsync(htr.data(), tres, htr.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    LT_HIP(hipMemcpyAsync(hbn.data(), bnorm, R * sizeof(double), hipMemcpyDeviceToHost, st));
     LT_HIP(hipMemcpyAsync(hjd.data(), jd, hjd.size() * sizeof(int), hipMemcpyDeviceToHost, st));
     LT_HIP(hipStreamSynchronize(st));
+    for (int k = 0; k < nk; ++k)
+        for (int r = 0; r < R; ++r) htr[(size_t)k * R + r] /= hbn[r];
     double worst = 0.0;
     for (int k = 0; k < nk; ++k)
         for (int r = 0; r < R; ++r) worst = std::max(worst, hw[k] * htr[(size_t)k * R + r]);
