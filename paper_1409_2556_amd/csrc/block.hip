@@ -52,11 +52,12 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 // Dots V_{b,i}^* W_{b, c0 + c} for i in [i0, i0 + ni), c < nc (at most four), in two passes.
-// First, each workgroup takes kDotE x 256 grid points of one block, holds the W columns there in
-// registers and streams every basis vector once: part[b][i][c][chunk] (one cross-wave reduction
+// First, each workgroup takes kDotE x 256 grid points of one block and kDotI of its basis vectors,
+// holds the W columns there in registers and streams those vectors once: part[b][i][c][chunk] (one cross-wave reduction
 // per vector for kDotE x 256 points).  Then k_bdots_fin sums the chunks into C[b][i][c0 + c] and
 // adds them to Hacc[b hb + (i0 + i) hld + hcol + c] (complex).
 constexpr int kDotE = 4;
+constexpr int kDotI = 8;  // basis vectors per workgroup (more workgroups for short grids)
 template <int NCM>
 __global__ __launch_bounds__(kBT) void k_bdots_part(const double* __restrict__ V, int R, int p, int N, int i0,
                                                       int ni, const double* __restrict__ W, int c0, int nc,
@@ -79,8 +80,10 @@ __global__ __launch_bounds__(kBT) void k_bdots_part(const double* __restrict__ V
             }
         }
     }
-    int sl = i0 / p, cc = i0 % p;  // slot and column of basis index i0 + i
-    for (int i = 0; i < ni; ++i) {
+    // this workgroup's basis vectors: i in [ia, ib) (blockIdx.z selects a group of kDotI)
+    const int ia = blockIdx.z * kDotI, ib = min(ni, ia + kDotI);
+    int sl = (i0 + ia) / p, cc = (i0 + ia) % p;  // slot and column of basis index i0 + i
+    for (int i = ia; i < ib; ++i) {
         const double* q = V + ((size_t)sl * R + (size_t)b * p + cc) * N2;
         if (++cc == p) {
             cc = 0;
@@ -515,7 +518,7 @@ int launch_bdots(hipStream_t st, const double* V, int R, int p, int nb, int N, i
     const int nchunk = (int)((N + kDotE * kBT - 1) / (kDotE * kBT));
     for (int g0 = 0; g0 < nc; g0 += 4) {  // four columns at a time: their W values stay in registers
         const int m = std::min(4, nc - g0);
-        const dim3 g(nchunk, nb);
+        const dim3 g(nchunk, nb, (ni + kDotI - 1) / kDotI);
         if (m == 1)
             k_bdots_part<1><<<g, kBT, 0, st>>>(V, R, p, N, i0, ni, W, c0 + g0, m, part, nchunk);
         else if (m == 2)
