@@ -348,8 +348,10 @@ int lt_adjoint(lt_handle* h, const lt_sources* src, const lt_points* receivers,
  * b, the columns taken in blocks of `block` consecutive right-hand sides that
  * share one basis.  Step j applies the preconditioner of tau_j =
  * taus[(j - 1) % ntau] to every column of the block's newest basis block
- * (LT_PRECOND_EXACT: the factorisation of K + tau_j M; LT_PRECOND_GMG: FP64
- * V-cycles until each residual is below tol / 100), orthogonalises M U_j
+ * (LT_PRECOND_EXACT: the factorisation of K + tau_j M; LT_PRECOND_GMG:
+ * V-cycles until each residual is below tol / 100, FP64 cycles, or with
+ * opts.precision LT_PREC_MIXED FP32 cycles on an FP32 copy of the FP64
+ * residual, corrections and residuals in FP64), orthogonalises M U_j
  * against the block basis by classical Gram-Schmidt, twice, and takes the QR
  * of the remainder by modified Gram-Schmidt; each (block, shift) then updates
  * its block least-squares problem by Givens rotations.  A shift of a block
@@ -359,8 +361,9 @@ int lt_adjoint(lt_handle* h, const lt_sources* src, const lt_points* receivers,
  *   b        device [nvec][2][N], every column nonzero; nvec <= 1000
  *   block    1..16, dividing nvec
  *   x        device [nshift][nvec][2][N] (written; must not overlap b)
- * opts: tol, maxit, precond (GMG or EXACT), nu1, nu2, inner_max (GMG: at most
- * 8 inner_max V-cycles per step); other fields are ignored.  The steps are
+ * opts: tol, maxit, precond (GMG or EXACT), precision (FP64 or MIXED), nu1,
+ * nu2, inner_max (GMG: at most 8 inner_max V-cycles per step); other fields
+ * are ignored.  The steps are
  * capped at 32768 / (16 block^2) - 1 (127 for blocks of 4, 31 for 8), where one
  * (block, shift)'s least-squares columns fill 32 KB of LDS.  Workspace on the
  * handle, with m the capped steps: about (2 m + 5) nvec 16 N bytes of vectors,

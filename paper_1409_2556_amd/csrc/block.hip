@@ -558,8 +558,9 @@ int lt_shifted_solve_block(lt_handle* h, int nshift, const double* shifts, const
     } else {
         lt_opts_default(&o);
     }
-    if (!(o.tol > 0.0) || o.maxit < 1 || (o.precond != LT_PRECOND_GMG && o.precond != LT_PRECOND_EXACT)) {
-        set_last_error("lt_shifted_solve_block: tol > 0, maxit >= 1, precond GMG or EXACT");
+    if (!(o.tol > 0.0) || o.maxit < 1 || (o.precond != LT_PRECOND_GMG && o.precond != LT_PRECOND_EXACT) ||
+        (o.precision != LT_PREC_FP64 && o.precision != LT_PREC_MIXED)) {
+        set_last_error("lt_shifted_solve_block: tol > 0, maxit >= 1, precond GMG or EXACT, precision FP64 or MIXED");
         return LT_EINVAL;
     }
     for (int k = 0; k < nshift; ++k) {
@@ -615,10 +616,13 @@ int lt_shifted_solve_block(lt_handle* h, int nshift, const double* shifts, const
     double* part = wsp<double>(h, "bk_part", (size_t)R * nbr, &rc);
     double* rho = wsp<double>(h, "bk_rho", (size_t)R * N2, &rc);
     double* ecorr = wsp<double>(h, "bk_e", (size_t)R * N2, &rc);
-    double* lo = h->cp3d ? wsp<double>(h, "bk_lo", (size_t)R * N2, &rc) : nullptr;
+    const bool mixed = o.precond == LT_PRECOND_GMG && o.precision == LT_PREC_MIXED;
+    double* lo = h->cp3d && !mixed ? wsp<double>(h, "bk_lo", (size_t)R * N2, &rc) : nullptr;
+    float* lo32 = mixed ? wsp<float>(h, "bk_lo32", (size_t)R * N2, &rc) : nullptr;
+    float* e32 = mixed ? wsp<float>(h, "bk_e32", (size_t)R * N2, &rc) : nullptr;
     double* dpart = wsp<double>(h, "bk_dpart", 2 * (size_t)nb * grows * kBlockMax * nblk(N), &rc);
     if (!V || !U || !W || !C || !H || !R0 || !Rm || !g || !rot || !Y || !res || !dev || !ints || !part || !rho ||
-        !ecorr || (h->cp3d && !lo) || !dpart)
+        !ecorr || (h->cp3d && !mixed && !lo) || (mixed && (!lo32 || !e32)) || !dpart)
         return rc ? rc : LT_ENOMEM;
     double* zs = dev;
     double* wk = zs + 2 * nk;
@@ -684,19 +688,30 @@ int lt_shifted_solve_block(lt_handle* h, int nshift, const double* shifts, const
             factor_ms += h->exact_factor_ms - m0;
             LT_TRY(exact_apply(h, F, R, Vj, N2, Uj, N2));
         } else {
-            // FP64 V-cycle iteration to tol / 100: the true residual gathers these inner residuals
-            // through the combination coefficients y, whose sum is of order ten here
+            // V-cycle iteration to tol / 100 (the true residual gathers these inner residuals
+            // through the combination coefficients y, whose sum is of order ten here): FP64
+            // cycles, or FP32 cycles on an FP32 copy of the FP64 residual (opts.precision MIXED;
+            // colour-planar on 3D grids), each correction added and the residual updated in FP64
             const LevelView<double> L0 = h->levels[0].v64();
             LT_HIP(hipMemcpyAsync(rho, Vj, (size_t)R * N2 * sizeof(double), hipMemcpyDeviceToDevice, st));
             if (lo) LT_TRY(convert_vectors_cp<double, double>(st, Vj, lo, R, N, h->grid.n[0], h->grid.n[1], 0));
+            if (mixed)
+                LT_TRY(convert_vectors_cp<double, float>(st, Vj, lo32, R, N, h->cp3d ? h->grid.n[0] : 0,
+                                                          h->grid.n[1], 0));
             LT_HIP(hipMemsetAsync(Uj, 0, (size_t)R * N2 * sizeof(double), st));
             std::vector<double> hn(R);
             const int maxc = std::max(o.inner_max, 1) * 8;
             bool ok = false;
             for (int cyc = 0; cyc < maxc && !ok; ++cyc) {
-                LT_TRY(mg_vcycle<double>(h, tau, o.nu1, o.nu2, R, nullptr, ecorr, lo ? lo : rho));
-                LT_TRY(launch_inner_update<double>(st, L0, tau, R, ecorr, Uj, N2, nullptr, rho, lo, part, nullptr,
-                                                   lo ? 1 : 0));
+                if (mixed) {
+                    LT_TRY(mg_vcycle<float>(h, tau, o.nu1, o.nu2, R, nullptr, e32, lo32));
+                    LT_TRY(launch_inner_update<float>(st, L0, tau, R, e32, Uj, N2, nullptr, rho, lo32, part, nullptr,
+                                                      h->cp3d ? 1 : 0));
+                } else {
+                    LT_TRY(mg_vcycle<double>(h, tau, o.nu1, o.nu2, R, nullptr, ecorr, lo ? lo : rho));
+                    LT_TRY(launch_inner_update<double>(st, L0, tau, R, ecorr, Uj, N2, nullptr, rho, lo, part,
+                                                       nullptr, lo ? 1 : 0));
+                }
                 LT_TRY(launch_norms(st, N, R, N2, rho, part, cnorm, nullptr));
                 LT_HIP(hipMemcpyAsync(hn.data(), cnorm, R * sizeof(double), hipMemcpyDeviceToHost, st));
                 LT_HIP(hipStreamSynchronize(st));

@@ -7,8 +7,8 @@ oracle's block algorithm and direct solves.
   within one (the tolerance test sits on rounding); blocks of 1, 4 and 8 columns; and a 3D grid.
 * Blocks need fewer steps than single right-hand sides (the block space contains each single
   space), on the same problem.
-* Multigrid preconditioners (FP64 V-cycles to tol / 100), 2D and 3D: solutions against direct
-  solves (1e-6) and FP64 true residuals within tol.
+* Multigrid preconditioners (V-cycles to tol / 100, FP64 or FP32 under FP64 refinement), 2D and
+  3D: solutions against direct solves (1e-6) and FP64 true residuals within tol.
 * Weighted shifts; refusals (a block that does not divide nvec, a block of 17, a zero column,
   multigrid with a negative real preconditioner shift, x overlapping b).
 * The widest block (16 columns) at its step cap (7): LT_WNOTCONV, and the solutions are the
@@ -105,7 +105,8 @@ def test_blocks_take_fewer_steps(lt):
 
 
 @pytest.mark.parametrize("case", ["2d", "3d"])
-def test_block_multigrid_matches_direct_solves(lt, case):
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_block_multigrid_matches_direct_solves(lt, case, prec):
     if case == "2d":
         p, K, m, B, hd, b = _setup(lt, "C2", n=(64, 48), nsrc=8)
     else:
@@ -116,15 +117,16 @@ def test_block_multigrid_matches_direct_solves(lt, case):
     zr = z[np.argmax(z.real)]
     zi = z[np.argmax(np.abs(z.imag))]
     taus = [zr, complex(0.0, zi.imag)]
-    announce("block gmg", case, p.n)
+    announce("block gmg", case, prec, p.n)
     tol = 1e-8
-    o = lt.make_opts(tol=tol, maxit=100, precond=lt.LT_PRECOND_GMG)
+    o = lt.make_opts(tol=tol, maxit=100, precond=lt.LT_PRECOND_GMG,
+                     precision=lt.LT_PREC_MIXED if prec == "mixed" else lt.LT_PREC_FP64)
     x, st = lt.lt_shifted_solve_block(hd, z, b, 4, taus, o)
     got = _cplx(x)
     ref = _direct(K, m, z, B)
     err = max(np.abs(got[k, c] - ref[k][:, c]).max() / np.abs(ref[k][:, c]).max()
               for k in range(z.size) for c in range(B.shape[1]))
-    print(f"[block gmg] {case}: rc {st['rc']} steps {st['iters_max']} vcycles {st['vcycles']} "
+    print(f"[block gmg] {case} {prec}: rc {st['rc']} steps {st['iters_max']} vcycles {st['vcycles']} "
           f"true residual {st['true_relres_max']:.2e} err {err:.2e}", flush=True)
     assert st["rc"] == 0
     assert st["true_relres_max"] <= tol
